@@ -1,0 +1,186 @@
+"""CPU oracle for TSDF integration (test infrastructure).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library never loads it: the GPU path and the
+oracle share no code.
+
+The oracle itself is plain C (``vbx_oracle.c``), compiled with gcc by
+:func:`build` and loaded here with ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vbx_oracle.c")
+_LIB_DIR = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_LIB_DIR, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+          "-mfpmath=sse", "-msse2", "-Wall", "-Wno-unused-function"]
+
+
+def build(extra_flags=(), out: Optional[str] = None) -> str:
+    """Compile the oracle with gcc; returns the path of the shared library."""
+    out = out or _LIB
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    cmd = ["gcc", *CFLAGS, *extra_flags, _SRC, "-o", out, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("voxel_size", ctypes.c_float), ("trunc", ctypes.c_float),
+                ("w_max", ctypes.c_float), ("max_range", ctypes.c_float),
+                ("z_min", ctypes.c_float), ("weighting", ctypes.c_int),
+                ("merge", ctypes.c_int), ("fp16", ctypes.c_int), ("dist", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("points", "valid", "invalid", "out_of_bounds", "rays", "touches", "voxels",
+                 "new_blocks")]
+
+
+_libs = {}
+
+
+def load(path: Optional[str] = None):
+    path = path or _LIB
+    if path in _libs:
+        return _libs[path]
+    if not os.path.exists(path):
+        if path != _LIB:
+            raise FileNotFoundError(path)
+        build()
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.orc_create.restype = ctypes.c_void_p
+    lib.orc_create.argtypes = [P(_Params)]
+    lib.orc_destroy.argtypes = [ctypes.c_void_p]
+    lib.orc_integrate.restype = ctypes.c_int
+    lib.orc_integrate.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p, P(_Stats)]
+    lib.orc_num_blocks.restype = ctypes.c_size_t
+    lib.orc_num_blocks.argtypes = [ctypes.c_void_p]
+    lib.orc_export.restype = ctypes.c_size_t
+    lib.orc_export.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_size_t]
+    lib.orc_last_touches.restype = ctypes.c_size_t
+    lib.orc_last_touches.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_size_t]
+    lib.orc_dda.restype = ctypes.c_int
+    lib.orc_dda.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    lib.orc_group_mean.restype = None
+    lib.orc_group_mean.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_float, ctypes.c_int, ctypes.c_void_p]
+    lib.orc_round_half.restype = ctypes.c_double
+    lib.orc_round_half.argtypes = [ctypes.c_double]
+    _libs[path] = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+WEIGHTING = {"const": 0, "quad": 1}
+MERGE = {"simple": 0, "grouped": 1}
+DIST = {"eq1": 0, "ray": 1}
+
+
+def weight_bits(weighting: str, z_min: float) -> int:
+    """Fractional bits of the fixed-point point weights in the grouped mean (0: weights are 1)."""
+    if weighting == "const":
+        return 0
+    zf = np.float32(z_min)
+    wmax = np.float32(1.0) / (zf * zf)
+    c = 0
+    while np.float32(2.0 ** c) < wmax:
+        c += 1
+    return 32 - c
+
+
+class OracleMap:
+    """One TSDF map integrated frame by frame on the CPU."""
+
+    def __init__(self, voxel_size: float, trunc: float, weighting: str = "const",
+                 merge: str = "simple", w_max: float = 1e4, max_range: float = 5.0,
+                 z_min: float = 0.1, storage: str = "f32", dist: str = "eq1",
+                 lib_path: Optional[str] = None):
+        self.lib = load(lib_path)
+        self.params = dict(voxel_size=voxel_size, trunc=trunc, weighting=weighting,
+                           merge=merge, w_max=w_max, max_range=max_range, z_min=z_min,
+                           storage=storage, dist=dist)
+        p = _Params(voxel_size, trunc, w_max, max_range, z_min, WEIGHTING[weighting],
+                    MERGE[merge], 1 if storage == "f16" else 0, DIST[dist])
+        self._h = self.lib.orc_create(ctypes.byref(p))
+
+    def close(self):
+        if self._h:
+            self.lib.orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def integrate(self, points: np.ndarray, pose: np.ndarray) -> dict:
+        pts = np.ascontiguousarray(points, dtype=np.float32).reshape(-1, 3)
+        ps = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
+        st = _Stats()
+        self.lib.orc_integrate(self._h, _ptr(pts), pts.shape[0], _ptr(ps), ctypes.byref(st))
+        return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
+
+    def num_blocks(self) -> int:
+        return int(self.lib.orc_num_blocks(self._h))
+
+    def export(self, with_mass: bool = True):
+        """(coords int32 [B,3] ascending, D f64 [B,4096] metres, W f64 [B,4096], mass f64 [B,4096])."""
+        nb = self.num_blocks()
+        coords = np.zeros((nb, 3), np.int32)
+        D = np.zeros((nb, 4096), np.float64)
+        W = np.zeros((nb, 4096), np.float64)
+        M = np.zeros((nb, 4096), np.float64) if with_mass else None
+        self.lib.orc_export(self._h, _ptr(coords), _ptr(D), _ptr(W),
+                            _ptr(M) if with_mass else None, nb)
+        return coords, D, W, M
+
+    def last_touches(self):
+        """Voxels touched by the last frame: (coords int32 [T,3], ray counts uint32 [T])."""
+        n = int(self.lib.orc_last_touches(self._h, None, None, 0))
+        coords = np.zeros((n, 3), np.int32)
+        counts = np.zeros(n, np.uint32)
+        self.lib.orc_last_touches(self._h, _ptr(coords), _ptr(counts), n)
+        return coords, counts
+
+
+def dda(A, B, lib_path: Optional[str] = None) -> np.ndarray:
+    """Voxels visited between voxel-space points A and B (float32), in visiting order."""
+    lib = load(lib_path)
+    a = np.ascontiguousarray(A, np.float32).reshape(3)
+    b = np.ascontiguousarray(B, np.float32).reshape(3)
+    n = lib.orc_dda(_ptr(a), _ptr(b), None, 0)
+    out = np.zeros((n, 3), np.int32)
+    lib.orc_dda(_ptr(a), _ptr(b), _ptr(out), n)
+    return out
+
+
+def group_mean(p32, w32, voxel_size: float, wbits: int, lib_path: Optional[str] = None):
+    """Binary32 ray end point of a group of points (grouped raycasting)."""
+    lib = load(lib_path)
+    p = np.ascontiguousarray(p32, np.float32).reshape(-1, 3)
+    w = np.ascontiguousarray(w32, np.float32).reshape(-1)
+    out = np.zeros(3, np.float32)
+    lib.orc_group_mean(_ptr(p), _ptr(w), p.shape[0], voxel_size, wbits, _ptr(out))
+    return out
+
+
+def round_half(x: float, lib_path: Optional[str] = None) -> float:
+    return float(load(lib_path).orc_round_half(float(x)))

@@ -1,0 +1,70 @@
+"""The CPU oracle against what the paper and plain mathematics fix (no GPU needed)."""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+from tests import pins
+
+
+@pytest.mark.parametrize("pin", pins.ALL_PINS, ids=lambda f: f.__name__)
+def test_pin(oracle_lib, pin):
+    pin()
+
+
+# Plausible mistakes planted in a copy of the oracle; each must be caught by a pin.
+MUTATIONS = {
+    "eq1_sign_flipped": ("double sgn = dot > 0.0f ? 1.0 : (dot < 0.0f ? -1.0 : 0.0);",
+                         "double sgn = dot > 0.0f ? -1.0 : (dot < 0.0f ? 1.0 : 0.0);"),
+    "tie_to_highest_axis": ("if (axis < 0 || tM[k] < tM[axis]) axis = k;",
+                            "if (axis < 0 || tM[k] <= tM[axis]) axis = k;"),
+    "dropoff_slope": ("return (d + delta) / (delta - eps);", "return (d + delta) / delta;"),
+    "no_weight_cap": ("vx->W = vx->W + vx->sw < wmax ? vx->W + vx->sw : wmax;",
+                      "vx->W = vx->W + vx->sw;"),
+    "merge_drops_old_weight": ("vx->D = (vx->W * vx->D + vx->swd) / (vx->W + vx->sw);",
+                               "vx->D = (vx->D + vx->swd) / (vx->W + vx->sw);"),
+    "rotation_transposed": ("q[k] = ((pose[4 * k] * x + pose[4 * k + 1] * y) + pose[4 * k + 2] * z) + pose[4 * k + 3];",
+                            "q[k] = ((pose[k] * x + pose[4 + k] * y) + pose[8 + k] * z) + pose[4 * k + 3];"),
+    "group_mean_unweighted": ("uint64_t om = wbits > 0 ? (uint64_t)rintf(ldexpf(w32[i], wbits)) : 1u;",
+                              "uint64_t om = 1u;"),
+    "no_band_behind_surface": ("float t1 = r + delta;", "float t1 = r;"),
+    "no_distance_clamp": ("double dc = d < -d64 ? -d64 : (d > d64 ? d64 : d);", "double dc = d;"),
+    "corner_not_centre": ("double x = ((double)g[k] + 0.5) * v64;\n                double f = ray->p64[k] - x;",
+                          "double x = ((double)g[k]) * v64;\n                double f = ray->p64[k] - x;"),
+    "weight_one_over_z": ("w64[nv] = P->weighting == 1 ? 1.0 / ((double)z * (double)z) : 1.0;",
+                          "w64[nv] = P->weighting == 1 ? 1.0 / (double)z : 1.0;"),
+    "group_weight_dropped": ("rays[nr].wgt = sw;", "rays[nr].wgt = w64[ki[lo].idx];"),
+    "half_rounding_truncates": ("double r = nearbyint(ax / ulp) * ulp;", "double r = floor(ax / ulp) * ulp;"),
+}
+
+FAST_FIRST = [pins.pin_head_on_plane, pins.pin_dropoff_values, pins.pin_running_average,
+              pins.pin_validity, pins.pin_identical_points, pins.pin_merged_singletons,
+              pins.pin_group_mean, pins.pin_round_half, pins.pin_weight_sums,
+              pins.pin_permutation, pins.pin_dda_dyadic, pins.pin_dda_random]
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(oracle_lib, name):
+    old, new = MUTATIONS[name]
+    src = open(oracle._SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    tmp = tempfile.mkdtemp(prefix="orc_mut_")
+    try:
+        path = os.path.join(tmp, "vbx_oracle.c")
+        with open(path, "w") as f:
+            f.write(src.replace(old, new))
+        lib = os.path.join(tmp, "liboracle_mut.so")
+        subprocess.run(["gcc", *oracle.CFLAGS, path, "-o", lib, "-lm"], check=True)
+        caught = []
+        for pin in FAST_FIRST:
+            try:
+                pin(lib)
+            except AssertionError:
+                caught.append(pin.__name__)
+                break
+        assert caught, f"planted mistake '{name}' passed every pin"
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
