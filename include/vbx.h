@@ -1,0 +1,197 @@
+/*
+ * vbx — TSDF integration into spatially hashed 16^3-voxel blocks on AMD MI355X
+ * (gfx950), after Oleynikova et al., "Voxblox: Incremental 3D Euclidean Signed
+ * Distance Fields for On-Board MAV Planning", Sec. III (voxel-hashed layers) and
+ * Sec. IV (TSDF construction: Eqs. 1-5, grouped raycasting).
+ *
+ * C ABI: plain pointers and sizes only.  "dev" pointers are device (HBM) memory
+ * of the current HIP device; "host" pointers are ordinary host memory.
+ *
+ * Conventions
+ *  - Every function returns a vbx_status: VBX_OK (0) or a negative error.  Out
+ *    parameters are written only on success.  No C++ exception crosses the ABI.
+ *  - Integration calls are stream-ordered and asynchronous: they enqueue work on
+ *    the map's HIP stream and return.  The caller keeps the point buffers alive
+ *    until the stream has passed the call (e.g. vbx_map_sync).
+ *  - Errors found on the device (block pool full) are sticky.  The call that hits
+ *    them leaves the map exactly as it was before the call; later integration
+ *    calls are skipped until vbx_map_reserve (or vbx_map_clear_error) is called.
+ *    vbx_map_sync returns the sticky error.
+ *  - The map owns its device memory (hash table, block pool, scratch).  Callers
+ *    own their input and output buffers.
+ *  - Voxel g (integer index, world position (g + 0.5) * voxel_size at its centre)
+ *    lives in block floor(g / 16), local index (g - 16*block) with x fastest:
+ *    l = lx + 16*ly + 256*lz.
+ */
+#ifndef VBX_H
+#define VBX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VBX_OK = 0,
+    VBX_ERR_INVALID_ARG = -1,      /* bad pointer, size or parameter */
+    VBX_ERR_OUT_OF_MEMORY = -2,    /* device or pinned host allocation failed */
+    VBX_ERR_POOL_FULL = -3,        /* block pool capacity exceeded; map unchanged by that call */
+    VBX_ERR_BUFFER_TOO_SMALL = -4, /* caller's output buffer (or touch record buffer) too small */
+    VBX_ERR_DEVICE = -5,           /* a HIP runtime call failed */
+    VBX_ERR_LIMIT = -6             /* request beyond a documented limit (points per frame, frames) */
+} vbx_status;
+
+/* Weighting of one observation: Eq. (2) constant w = 1, or Eq. (5) 1/z^2 with a
+ * linear drop-off behind the surface (epsilon = voxel_size, delta = trunc). */
+typedef enum { VBX_W_CONST = 0, VBX_W_QUAD = 1 } vbx_weighting;
+
+/* Raycasting every point, or grouped raycasting (Sec. IV-B): points that fall in
+ * one voxel are merged into one ray cast towards their weighted mean. */
+typedef enum { VBX_MERGE_NONE = 0, VBX_MERGE_GROUPED = 1 } vbx_merge;
+
+/* Storage of the per-voxel distance D and weight W: binary32 pairs (8 B/voxel)
+ * or binary16 pairs (4 B/voxel, D stored as D/trunc); arithmetic is binary32. */
+typedef enum { VBX_F32 = 0, VBX_F16 = 1 } vbx_storage;
+
+/* Distance of Eq. (1) (Euclidean norm with the sign of the projection on the
+ * ray) or the projective distance along the ray (Sec. I). */
+typedef enum { VBX_DIST_EQ1 = 0, VBX_DIST_ALONG_RAY = 1 } vbx_dist;
+
+enum {
+    VBX_FLAG_KEEP_TOUCHES = 1u   /* record the touched voxels and ray counts of the last call */
+};
+
+/* Limits */
+#define VBX_MAX_POINTS_PER_FRAME (1u << 24)
+#define VBX_MAX_FRAMES_PER_CALL 4096
+#define VBX_VOXEL_INDEX_LIMIT (1 << 18) /* |voxel index| < 2^18, |block index| < 2^14 */
+
+typedef struct {
+    float voxel_size;        /* v, metres, > 0 */
+    float trunc;             /* delta, metres, > 0 (the paper uses 4v; 3v is common) */
+    float w_max;             /* W_max of Eq. (4); <= 65504 for VBX_F16 */
+    float max_range;         /* points farther than this from the sensor are rejected */
+    float z_min;             /* VBX_W_QUAD: points with depth z < z_min are rejected; >= 1e-3 */
+    int32_t weighting;       /* vbx_weighting */
+    int32_t merge;           /* vbx_merge */
+    int32_t storage;         /* vbx_storage */
+    int32_t dist;            /* vbx_dist */
+    uint32_t block_capacity; /* blocks the pool holds; vbx_map_reserve grows it */
+    uint32_t flags;          /* VBX_FLAG_* */
+    void* stream;            /* hipStream_t to run on (NULL: the null stream) */
+} vbx_map_params;
+
+/* One depth or LiDAR frame. */
+typedef struct {
+    const float* points; /* dev [n][3] float32, sensor frame; non-finite marks an invalid point */
+    uint64_t n;          /* number of points, <= VBX_MAX_POINTS_PER_FRAME */
+    uint32_t width;      /* organised clouds: row length (n % width == 0); 0 = unorganised.
+                            Only a locality hint for grouping: results do not depend on it. */
+    uint32_t reserved;
+    float pose[12];      /* row-major 3x4 T_world_sensor; the sensor origin is its last column */
+} vbx_frame;
+
+typedef struct {
+    uint64_t points;        /* points submitted */
+    uint64_t valid;         /* points that passed the validity tests */
+    uint64_t invalid;       /* non-finite, zero range, beyond max_range, or z < z_min */
+    uint64_t out_of_bounds; /* rays whose band leaves the addressable voxel range */
+    uint64_t rays;          /* rays cast (points, or groups under VBX_MERGE_GROUPED) */
+    uint64_t touches;       /* ray-voxel visits (voxel updates) */
+    uint64_t voxels;        /* distinct (voxel, frame) pairs updated */
+    uint64_t new_blocks;    /* blocks allocated */
+    uint64_t blocks;        /* blocks in the map */
+    uint64_t calls;         /* integration calls that ran */
+} vbx_stats;
+
+typedef struct vbx_map vbx_map;
+
+/* Fills *p with defaults: w_max 1e4, max_range 5 m, z_min 0.1 m, constant
+ * weighting, no grouping, binary32 storage, Eq. (1), capacity 65536 blocks. */
+void vbx_default_params(vbx_map_params* p);
+
+/* Creates a map with the defaults above (Sec. III: a layer of blocks indexed by
+ * position through a hash table).  voxel_size and trunc in metres; weighting is
+ * a vbx_weighting. */
+int vbx_map_create(float voxel_size, float trunc, int weighting, vbx_map** out);
+
+/* Creates a map from explicit parameters.  Allocates the hash table (2x the
+ * capacity, power of two) and the block pool on the current device. */
+int vbx_map_create_ex(const vbx_map_params* params, vbx_map** out);
+
+/* Waits for the map's stream and frees everything the map owns.  NULL is a no-op. */
+void vbx_map_destroy(vbx_map* map);
+
+/* Sets the HIP stream later calls run on (hipStream_t, NULL = null stream). */
+int vbx_map_set_stream(vbx_map* map, void* stream);
+
+/* Integrates one frame (Sec. IV: raycast every valid point's truncation band,
+ * weight each observation by Eq. (2) or (5), merge into each voxel by Eqs. (3)-(4);
+ * grouped raycasting per Sec. IV-B when the map merges).  points_dev: dev [n][3]
+ * float32 in the sensor frame; pose: host [12] row-major T_world_sensor.
+ * All observations of one frame that reach a voxel are merged in one update. */
+int vbx_integrate(vbx_map* map, const float* points_dev, size_t n, const float pose[12]);
+
+/* Integrates F frames in order in one pipelined pass.  The result is bit-identical
+ * to F consecutive vbx_integrate calls.  points_dev: host array of F dev pointers;
+ * n: host [F]; poses: host [F][12]. */
+int vbx_integrate_batch(vbx_map* map, const float* const* points_dev, const size_t* n,
+                        const float* poses, int F);
+
+/* As vbx_integrate_batch, with per-frame organisation hints. */
+int vbx_integrate_frames(vbx_map* map, const vbx_frame* frames, int F);
+
+/* Integrates frames[i] into maps[i] for i < M (distinct maps on one device) in one
+ * pipelined pass on maps[0]'s stream, using maps[0]'s scratch memory.  Each map's
+ * result is bit-identical to integrating its frame alone. */
+int vbx_integrate_multi(vbx_map* const* maps, const vbx_frame* frames, int M);
+
+/* Blocks until the map's stream is idle; returns the sticky device error, if any. */
+int vbx_map_sync(vbx_map* map);
+
+/* Clears a sticky device error (the map content is unchanged). */
+int vbx_map_clear_error(vbx_map* map);
+
+/* Grows the block pool (and hash table) to hold at least block_capacity blocks,
+ * keeping every block, and clears a sticky VBX_ERR_POOL_FULL.  Synchronises. */
+int vbx_map_reserve(vbx_map* map, uint32_t block_capacity);
+
+/* Number of allocated blocks (synchronises). */
+int vbx_map_num_blocks(vbx_map* map, size_t* n_out);
+
+/* Exports every block in ascending (bx, by, bz) order (synchronises).
+ * coords: host [cap][3] int32 block indices or NULL; dw: host [cap][4096][2] float32
+ * (D in metres, W) or NULL.  With both NULL only *n_out is written.  Returns
+ * VBX_ERR_BUFFER_TOO_SMALL if cap is smaller than the block count. */
+int vbx_export_blocks(vbx_map* map, int32_t* coords, float* dw, size_t cap, size_t* n_out);
+
+/* Replaces the map content with n blocks (coords host [n][3], dw host [n][4096][2],
+ * D in metres) — the inverse of vbx_export_blocks (checkpoint / resume).  Values
+ * are rounded to the map's storage type.  Synchronises. */
+int vbx_import_blocks(vbx_map* map, const int32_t* coords, const float* dw, size_t n);
+
+/* Touched voxels of the last integration call (requires VBX_FLAG_KEEP_TOUCHES):
+ * coords host [cap][3] voxel indices and counts host [cap] (rays that visited the
+ * voxel, summed over the call's frames); unordered.  Synchronises.  NULL buffers:
+ * only *n_out is written. */
+int vbx_last_touches(vbx_map* map, int32_t* coords, uint32_t* counts, size_t cap, size_t* n_out);
+
+/* Cumulative statistics of the map (synchronises). */
+int vbx_map_stats(vbx_map* map, vbx_stats* out);
+
+/* Traversal primitive, for verification: for each i < n, the voxels visited between
+ * the voxel-space points A_dev[i] and B_dev[i] (dev [n][3] float32), in order,
+ * written to out_dev[i][cap][3] (int32), count to counts_dev[i] (may exceed cap;
+ * only cap are written).  Runs on the null stream and synchronises. */
+int vbx_debug_traverse(const float* A_dev, const float* B_dev, int n, int32_t* out_dev,
+                       int cap, int32_t* counts_dev);
+
+/* Human-readable name of a status code (static string). */
+const char* vbx_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VBX_H */

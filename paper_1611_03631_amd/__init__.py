@@ -1,0 +1,280 @@
+"""vbx: TSDF integration into hashed 16^3-voxel blocks on AMD MI355X.
+
+A thin ctypes binding over the C ABI of libvbx.so (include/vbx.h).  It only marshals
+arguments: every step of the integration runs in the library's HIP kernels.  PyTorch
+provides device memory and streams; torch is imported first so that the library shares
+torch's HIP runtime.
+
+If the library has not been built, or cannot be loaded, every entry point raises: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch  # noqa: F401  (shares its HIP runtime with libvbx)
+
+from .build import LIB as _LIB_PATH, build as build_library  # noqa: F401
+
+# ---------------------------------------------------------------------------
+# C structures (mirror include/vbx.h)
+# ---------------------------------------------------------------------------
+W_CONST, W_QUAD = 0, 1
+MERGE_NONE, MERGE_GROUPED = 0, 1
+F32, F16 = 0, 1
+DIST_EQ1, DIST_ALONG_RAY = 0, 1
+FLAG_KEEP_TOUCHES = 1
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "block pool full",
+          -4: "buffer too small", -5: "device error", -6: "limit exceeded"}
+ERR_POOL_FULL = -3
+
+
+class VbxError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"vbx: {what}: {STATUS.get(status, status)} ({status})")
+
+
+class MapParams(ctypes.Structure):
+    _fields_ = [("voxel_size", ctypes.c_float), ("trunc", ctypes.c_float),
+                ("w_max", ctypes.c_float), ("max_range", ctypes.c_float),
+                ("z_min", ctypes.c_float), ("weighting", ctypes.c_int32),
+                ("merge", ctypes.c_int32), ("storage", ctypes.c_int32), ("dist", ctypes.c_int32),
+                ("block_capacity", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("stream", ctypes.c_void_p)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_uint64), ("width", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("pose", ctypes.c_float * 12)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("points", "valid", "invalid", "out_of_bounds", "rays", "touches", "voxels",
+                 "new_blocks", "blocks", "calls")]
+
+
+EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_map_destroy",
+            "vbx_map_set_stream", "vbx_integrate", "vbx_integrate_batch", "vbx_integrate_frames",
+            "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
+            "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
+            "vbx_map_stats", "vbx_debug_traverse", "vbx_status_string"]
+
+_lib = None
+
+
+def lib(path: Optional[str] = None):
+    """Loads libvbx.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or _LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"vbx: {p} is not built; run paper_1611_03631_amd.build.build()")
+    L = ctypes.CDLL(p)
+    vp, sz, i32, u32, f32p = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p
+    L.vbx_default_params.argtypes = [ctypes.POINTER(MapParams)]
+    L.vbx_default_params.restype = None
+    L.vbx_map_create.argtypes = [ctypes.c_float, ctypes.c_float, i32, ctypes.POINTER(vp)]
+    L.vbx_map_create_ex.argtypes = [ctypes.POINTER(MapParams), ctypes.POINTER(vp)]
+    L.vbx_map_destroy.argtypes = [vp]
+    L.vbx_map_destroy.restype = None
+    L.vbx_map_set_stream.argtypes = [vp, vp]
+    L.vbx_integrate.argtypes = [vp, f32p, sz, f32p]
+    L.vbx_integrate_batch.argtypes = [vp, vp, vp, f32p, i32]
+    L.vbx_integrate_frames.argtypes = [vp, ctypes.POINTER(Frame), i32]
+    L.vbx_integrate_multi.argtypes = [vp, ctypes.POINTER(Frame), i32]
+    L.vbx_map_sync.argtypes = [vp]
+    L.vbx_map_clear_error.argtypes = [vp]
+    L.vbx_map_reserve.argtypes = [vp, u32]
+    L.vbx_map_num_blocks.argtypes = [vp, ctypes.POINTER(sz)]
+    L.vbx_export_blocks.argtypes = [vp, vp, vp, sz, ctypes.POINTER(sz)]
+    L.vbx_import_blocks.argtypes = [vp, vp, vp, sz]
+    L.vbx_last_touches.argtypes = [vp, vp, vp, sz, ctypes.POINTER(sz)]
+    L.vbx_map_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.vbx_debug_traverse.argtypes = [vp, vp, i32, vp, i32, vp]
+    L.vbx_status_string.argtypes = [i32]
+    L.vbx_status_string.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("vbx_default_params", "vbx_map_destroy", "vbx_status_string"):
+            getattr(L, name).restype = ctypes.c_int
+    if path is None:
+        _lib = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise VbxError(status, what)
+
+
+def _dev_points(points) -> Tuple[int, int]:
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise TypeError("points must be a device (cuda) torch tensor of shape [N, 3]")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 3:
+        raise TypeError("points must be float32 [N, 3]")
+    if not points.is_contiguous():
+        raise TypeError("points must be contiguous")
+    return points.data_ptr(), int(points.shape[0])
+
+
+def _pose12(pose) -> np.ndarray:
+    p = np.ascontiguousarray(np.asarray(pose, dtype=np.float32).reshape(12))
+    return p
+
+
+_WEIGHTING = {"const": W_CONST, "quad": W_QUAD}
+_MERGE = {"simple": MERGE_NONE, "none": MERGE_NONE, "grouped": MERGE_GROUPED}
+_STORAGE = {"f32": F32, "f16": F16}
+_DIST = {"eq1": DIST_EQ1, "ray": DIST_ALONG_RAY}
+
+
+class Map:
+    """A TSDF map on the current HIP device (wraps vbx_map)."""
+
+    def __init__(self, voxel_size: float, trunc: float, weighting: str = "const",
+                 merge: str = "simple", storage: str = "f32", w_max: float = 1e4,
+                 max_range: float = 5.0, z_min: float = 0.1, dist: str = "eq1",
+                 block_capacity: int = 65536, keep_touches: bool = False, stream=None):
+        L = lib()
+        p = MapParams()
+        L.vbx_default_params(ctypes.byref(p))
+        p.voxel_size, p.trunc, p.w_max = voxel_size, trunc, w_max
+        p.max_range, p.z_min = max_range, z_min
+        p.weighting, p.merge = _WEIGHTING[weighting], _MERGE[merge]
+        p.storage, p.dist = _STORAGE[storage], _DIST[dist]
+        p.block_capacity = block_capacity
+        p.flags = FLAG_KEEP_TOUCHES if keep_touches else 0
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        p.stream = s.cuda_stream
+        h = ctypes.c_void_p()
+        _check(L.vbx_map_create_ex(ctypes.byref(p), ctypes.byref(h)), "vbx_map_create_ex")
+        self._h = h
+        self.params = dict(voxel_size=voxel_size, trunc=trunc, weighting=weighting, merge=merge,
+                           storage=storage, w_max=w_max, max_range=max_range, z_min=z_min,
+                           dist=dist, block_capacity=block_capacity)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vbx_map_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- integration -------------------------------------------------------
+    def integrate(self, points, pose):
+        ptr, n = _dev_points(points)
+        pz = _pose12(pose)
+        _check(lib().vbx_integrate(self._h, ptr, n, pz.ctypes.data), "vbx_integrate")
+
+    def integrate_frames(self, frames: Sequence[Tuple]):
+        """frames: sequence of (points tensor [N,3], pose [3,4]) or (points, pose, width)."""
+        arr = make_frames(frames)
+        _check(lib().vbx_integrate_frames(self._h, arr, len(frames)), "vbx_integrate_frames")
+
+    def integrate_batch(self, points_list, poses):
+        F = len(points_list)
+        ptrs = (ctypes.c_void_p * F)()
+        ns = (ctypes.c_size_t * F)()
+        for i, pts in enumerate(points_list):
+            ptrs[i], ns[i] = _dev_points(pts)
+        P = np.ascontiguousarray(np.asarray(poses, dtype=np.float32).reshape(F, 12))
+        _check(lib().vbx_integrate_batch(self._h, ptrs, ns, P.ctypes.data, F), "vbx_integrate_batch")
+
+    # -- state ---------------------------------------------------------------
+    def sync(self) -> int:
+        """Waits for the map's stream; returns the sticky device status (0 = ok)."""
+        return int(lib().vbx_map_sync(self._h))
+
+    def clear_error(self):
+        _check(lib().vbx_map_clear_error(self._h), "vbx_map_clear_error")
+
+    def reserve(self, block_capacity: int):
+        _check(lib().vbx_map_reserve(self._h, block_capacity), "vbx_map_reserve")
+
+    def num_blocks(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().vbx_map_num_blocks(self._h, ctypes.byref(n)), "vbx_map_num_blocks")
+        return int(n.value)
+
+    def export(self):
+        """(coords int32 [B,3] ascending, dw float32 [B,4096,2] with D in metres and W)."""
+        L = lib()
+        n = ctypes.c_size_t()
+        _check(L.vbx_export_blocks(self._h, None, None, 0, ctypes.byref(n)), "vbx_export_blocks")
+        B = int(n.value)
+        coords = np.zeros((B, 3), np.int32)
+        dw = np.zeros((B, 4096, 2), np.float32)
+        _check(L.vbx_export_blocks(self._h, coords.ctypes.data, dw.ctypes.data, B, ctypes.byref(n)),
+               "vbx_export_blocks")
+        return coords, dw
+
+    def import_blocks(self, coords: np.ndarray, dw: np.ndarray):
+        c = np.ascontiguousarray(coords, np.int32).reshape(-1, 3)
+        d = np.ascontiguousarray(dw, np.float32).reshape(-1, 4096, 2)
+        _check(lib().vbx_import_blocks(self._h, c.ctypes.data, d.ctypes.data, c.shape[0]),
+               "vbx_import_blocks")
+
+    def last_touches(self):
+        """Voxels touched by the last call: (coords int32 [T,3], counts uint32 [T]), unordered."""
+        L = lib()
+        n = ctypes.c_size_t()
+        _check(L.vbx_last_touches(self._h, None, None, 0, ctypes.byref(n)), "vbx_last_touches")
+        T = int(n.value)
+        coords = np.zeros((T, 3), np.int32)
+        counts = np.zeros(T, np.uint32)
+        _check(L.vbx_last_touches(self._h, coords.ctypes.data, counts.ctypes.data, T,
+                                  ctypes.byref(n)), "vbx_last_touches")
+        return coords, counts
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().vbx_map_stats(self._h, ctypes.byref(s)), "vbx_map_stats")
+        return {n: int(getattr(s, n)) for n, _ in Stats._fields_}
+
+
+def make_frames(frames) -> ctypes.Array:
+    arr = (Frame * len(frames))()
+    for i, f in enumerate(frames):
+        pts, pose = f[0], f[1]
+        width = int(f[2]) if len(f) > 2 else 0
+        ptr, n = _dev_points(pts)
+        arr[i].points = ptr
+        arr[i].n = n
+        arr[i].width = width
+        pz = _pose12(pose)
+        for k in range(12):
+            arr[i].pose[k] = float(pz[k])
+    return arr
+
+
+def integrate_multi(maps: Sequence[Map], frames: Sequence[Tuple]):
+    """frames[i] (points, pose[, width]) into maps[i], one pass on maps[0]'s stream."""
+    M = len(maps)
+    hs = (ctypes.c_void_p * M)(*[m.handle for m in maps])
+    arr = make_frames(frames)
+    _check(lib().vbx_integrate_multi(hs, arr, M), "vbx_integrate_multi")
+
+
+def debug_traverse(A: torch.Tensor, B: torch.Tensor, cap: int = 128):
+    """Voxels visited from A[i] to B[i] (voxel units, device float32 [n,3])."""
+    n = A.shape[0]
+    out = torch.zeros((n, cap, 3), dtype=torch.int32, device=A.device)
+    counts = torch.zeros(n, dtype=torch.int32, device=A.device)
+    _check(lib().vbx_debug_traverse(A.data_ptr(), B.data_ptr(), n, out.data_ptr(), cap,
+                                    counts.data_ptr()), "vbx_debug_traverse")
+    return out, counts

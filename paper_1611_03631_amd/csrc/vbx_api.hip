@@ -1,0 +1,915 @@
+// C-ABI of the vbx TSDF integrator: map lifecycle, per-call scratch, the launch sequence of
+// one integration call, and the cold paths (export, import, statistics).
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/vbx.h"
+#include "vbx_host.h"
+#include "vbx_internal.h"
+
+using namespace vbx;
+
+namespace {
+
+#define VBX_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return VBX_ERR_DEVICE;   \
+    } while (0)
+
+size_t next_pow2(size_t x) {
+    size_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// A grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// Pinned staging for the per-call job and map tables, in a small ring so that a call never
+// overwrites a table whose copy to the device is still queued.
+struct Stage {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+
+struct Scratch {
+    DevBuf rays_p, rays_job, cross, sorted, tkeys, tval, tlist, t_key, t_slot, bins, off, partial,
+        gtable, occ, touch_key, touch_n, tables, jst, cs;
+    size_t ray_cap = 0, cross_cap = 0, tkey_cap = 0, tlist_cap = 0, bins_cap = 0, nparts = 0,
+           gcap = 0, touch_cap = 0, job_cap = 0, map_cap = 0;
+    Stage stage[4];
+    int stage_i = 0;
+    // host copy of the maps of the last call (for vbx_last_touches)
+    std::vector<vbx_map*> last_maps;
+    bool touches_valid = false;
+};
+
+}  // namespace
+
+struct vbx_map {
+    vbx_map_params P;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    MapState* st = nullptr;       // device
+    u64* hkeys = nullptr;         // device
+    int* hslots = nullptr;        // device
+    u32 hcap = 0;
+    void* pool = nullptr;         // device
+    u32 capacity = 0;
+    size_t voxel_bytes = 8;
+    int wbits = 0;
+    int kw = 0;
+    Scratch* scratch = nullptr;
+    Scratch* touch_src = nullptr; // scratch holding this map's last touches
+    int touch_idx = 0;
+};
+
+namespace {
+
+int dev_alloc(DevBuf& b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return VBX_OK;
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        b.p = nullptr;
+        return VBX_ERR_OUT_OF_MEMORY;
+    }
+    b.bytes = bytes;
+    return VBX_OK;
+}
+
+unsigned grid_for(size_t n, unsigned cap = 2048) {
+    size_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+int weight_bits(const vbx_map_params& P) {
+    if (P.weighting == VBX_W_CONST) return 0;
+    const float wmax = 1.0f / (P.z_min * P.z_min);
+    int c = 0;
+    while (std::ldexp(1.0f, c) < wmax) ++c;
+    return 32 - c;
+}
+
+// Fixed-point bits of the per-voxel weight sums: every (voxel, frame) sum stays below 2^62
+// for frames of up to 2^24 points with weights up to 2^(32 - wbits).
+int sum_bits(const vbx_map_params& P) {
+    const int c = P.weighting == VBX_W_CONST ? 0 : 32 - weight_bits(P);
+    return 38 - c;
+}
+
+int max_blocks_per_ray(const vbx_map_params& P) {
+    const double len = 2.0 * (double)P.trunc / (double)P.voxel_size + 2.0;   // band, voxel units
+    return 1 + 3 * ((int)std::floor(len / 16.0) + 1);
+}
+
+int max_voxels_per_ray(const vbx_map_params& P) {
+    return 3 * ((int)std::ceil(2.0 * (double)P.trunc / (double)P.voxel_size) + 2) + 1;
+}
+
+int validate_params(const vbx_map_params& P) {
+    if (!(P.voxel_size > 0.0f) || !std::isfinite(P.voxel_size)) return VBX_ERR_INVALID_ARG;
+    if (!(P.trunc > 0.0f) || !std::isfinite(P.trunc)) return VBX_ERR_INVALID_ARG;
+    if (!(P.w_max > 0.0f)) return VBX_ERR_INVALID_ARG;
+    if (!(P.max_range > 0.0f) || !std::isfinite(P.max_range)) return VBX_ERR_INVALID_ARG;
+    if (P.weighting != VBX_W_CONST && P.weighting != VBX_W_QUAD) return VBX_ERR_INVALID_ARG;
+    if (P.merge != VBX_MERGE_NONE && P.merge != VBX_MERGE_GROUPED) return VBX_ERR_INVALID_ARG;
+    if (P.storage != VBX_F32 && P.storage != VBX_F16) return VBX_ERR_INVALID_ARG;
+    if (P.dist != VBX_DIST_EQ1 && P.dist != VBX_DIST_ALONG_RAY) return VBX_ERR_INVALID_ARG;
+    if (P.weighting == VBX_W_QUAD && !(P.z_min >= 0.05f)) return VBX_ERR_INVALID_ARG;
+    if (P.storage == VBX_F16 && P.w_max > 65504.0f) return VBX_ERR_INVALID_ARG;
+    if (P.block_capacity == 0 || P.block_capacity > (1u << 29)) return VBX_ERR_INVALID_ARG;
+    if (2.0 * P.trunc / P.voxel_size > 28.0) return VBX_ERR_LIMIT;   // band of <= 28 voxels
+    return VBX_OK;
+}
+
+MapDesc make_desc(const vbx_map* m, int map_id, int job0, int njobs) {
+    const vbx_map_params& P = m->P;
+    MapDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.v = P.voxel_size;
+    d.iv = 1.0f / P.voxel_size;
+    d.delta = P.trunc;
+    d.inv_delta = 1.0f / P.trunc;
+    d.eps = P.voxel_size;
+    d.ramp = 1.0f / (P.trunc - P.voxel_size);
+    d.w_max = P.w_max;
+    d.rmax2 = P.max_range * P.max_range;
+    d.z_min = P.z_min;
+    d.wscale = std::ldexp(1.0f, m->kw);
+    d.inv_wscale = std::ldexp(1.0f, -m->kw);
+    d.weighting = P.weighting;
+    d.merge = P.merge;
+    d.storage = P.storage;
+    d.dist = P.dist;
+    d.wbits = m->wbits;
+    d.njobs = njobs;
+    d.job0 = job0;
+    d.map_id = map_id;
+    d.hkeys = m->hkeys;
+    d.hslots = m->hslots;
+    d.hmask = m->hcap - 1;
+    d.capacity = m->capacity;
+    d.pool = m->pool;
+    d.st = m->st;
+    return d;
+}
+
+int alloc_storage(vbx_map* m, u32 capacity) {
+    m->capacity = capacity;
+    m->hcap = (u32)next_pow2((size_t)capacity * 2);
+    if (hipMalloc(&m->hkeys, sizeof(u64) * m->hcap) != hipSuccess) return VBX_ERR_OUT_OF_MEMORY;
+    if (hipMalloc(&m->hslots, sizeof(int) * m->hcap) != hipSuccess) return VBX_ERR_OUT_OF_MEMORY;
+    if (hipMalloc(&m->pool, (size_t)capacity * 4096 * m->voxel_bytes) != hipSuccess)
+        return VBX_ERR_OUT_OF_MEMORY;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(m->hcap)), dim3(256), 0, m->stream, m->hkeys, kEmpty,
+                       (size_t)m->hcap);
+    return hipGetLastError() == hipSuccess ? VBX_OK : VBX_ERR_DEVICE;
+}
+
+void free_storage(vbx_map* m) {
+    if (m->hkeys) (void)hipFree(m->hkeys);
+    if (m->hslots) (void)hipFree(m->hslots);
+    if (m->pool) (void)hipFree(m->pool);
+    m->hkeys = nullptr;
+    m->hslots = nullptr;
+    m->pool = nullptr;
+}
+
+void free_scratch(Scratch* s) {
+    if (!s) return;
+    DevBuf* bufs[] = {&s->rays_p, &s->rays_job, &s->cross, &s->sorted, &s->tkeys, &s->tval,
+                      &s->tlist, &s->t_key, &s->t_slot, &s->bins, &s->off, &s->partial,
+                      &s->gtable, &s->occ, &s->touch_key, &s->touch_n, &s->tables, &s->jst, &s->cs};
+    for (DevBuf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    for (Stage& st : s->stage) {
+        if (st.host) (void)hipHostFree(st.host);
+        if (st.ev) (void)hipEventDestroy(st.ev);
+    }
+    delete s;
+}
+
+struct CallPlan {
+    size_t total_points = 0;
+    int JM = 1;
+    int max_blocks = 4;
+    int max_vox = 22;
+    bool grouped = false;
+    int storage = 0;
+    bool keep_touches = false;
+};
+
+// Grows the scratch of `lead` for a call; tables that must start cleared are cleared here.
+int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, size_t max_chunk_points,
+                   size_t sum_capacity) {
+    Scratch* s = lead->scratch;
+    hipStream_t st = lead->stream;
+    const size_t ray_cap = std::max<size_t>(plan.total_points, 1);
+    const size_t cross_cap = ray_cap * (size_t)plan.max_blocks;
+    if (cross_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
+    const size_t tlist_cap = std::min<size_t>(std::max<size_t>(sum_capacity + 4096, 4096), cross_cap + 4096);
+    const size_t tkey_cap = next_pow2(2 * tlist_cap);
+    const size_t bins_cap = tlist_cap * (size_t)plan.JM;
+    if (bins_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
+    const size_t nparts = (bins_cap + kScanChunkHost - 1) / kScanChunkHost;
+    const size_t gcap = plan.grouped ? next_pow2(std::max<size_t>(2 * max_chunk_points, 1024)) : 0;
+    const size_t touch_cap =
+        plan.keep_touches ? std::min<size_t>(ray_cap * (size_t)plan.max_vox, (size_t)1 << 26) : 0;
+
+    bool need_sync = false;
+    auto grow = [&](DevBuf& b, size_t bytes) -> int {
+        if (b.bytes >= bytes && b.p) return 0;
+        if (!need_sync) {
+            (void)hipStreamSynchronize(st);
+            need_sync = true;
+        }
+        return dev_alloc(b, bytes) == VBX_OK ? 1 : -1;
+    };
+    int r;
+#define GROW(buf, bytes)                          \
+    if ((r = grow(buf, bytes)) < 0) return VBX_ERR_OUT_OF_MEMORY;
+
+    GROW(s->rays_p, ray_cap * sizeof(float4));
+    GROW(s->rays_job, ray_cap * sizeof(u32));
+    GROW(s->cross, cross_cap * sizeof(uint2));
+    GROW(s->sorted, cross_cap * sizeof(u32));
+    if ((r = grow(s->tkeys, tkey_cap * sizeof(u64))) < 0) return VBX_ERR_OUT_OF_MEMORY;
+    if (r == 1 || s->tkey_cap != tkey_cap) {
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(tkey_cap)), dim3(256), 0, st, (u64*)s->tkeys.p,
+                           kEmpty, tkey_cap);
+    }
+    s->tkey_cap = tkey_cap;
+    GROW(s->tval, tkey_cap * sizeof(u32));
+    GROW(s->tlist, tlist_cap * sizeof(u32));
+    GROW(s->t_key, tlist_cap * sizeof(u64));
+    GROW(s->t_slot, tlist_cap * sizeof(int));
+    if ((r = grow(s->bins, (bins_cap + 1) * sizeof(u32))) < 0) return VBX_ERR_OUT_OF_MEMORY;
+    if (r == 1) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(bins_cap + 1)), dim3(256), 0, st, (u32*)s->bins.p, 0u, bins_cap + 1);
+    GROW(s->off, (bins_cap + 1) * sizeof(u32));
+    GROW(s->partial, (nparts + 1) * sizeof(u32));
+    if (plan.grouped && s->gcap < gcap) {
+        // grouping table: power-of-two capacity >= 2x the points of a chunk, cleared once;
+        // every use leaves it clean again
+        if ((r = grow(s->gtable, gcap * sizeof(GroupEntry))) < 0) return VBX_ERR_OUT_OF_MEMORY;
+        hipLaunchKernelGGL(k_clear_groups, dim3(grid_for(gcap)), dim3(256), 0, st, (GroupEntry*)s->gtable.p, gcap);
+        s->gcap = gcap;
+        GROW(s->occ, gcap / 2 * sizeof(u32));
+    }
+    if (plan.keep_touches) {
+        GROW(s->touch_key, touch_cap * sizeof(u64));
+        GROW(s->touch_n, touch_cap * sizeof(u32));
+        s->touch_cap = touch_cap;
+    }
+    const size_t tables_bytes = (size_t)nmaps * sizeof(MapDesc) + (size_t)njobs * sizeof(Job);
+    GROW(s->tables, tables_bytes);
+    if ((r = grow(s->jst, (size_t)njobs * sizeof(JobStat))) < 0) return VBX_ERR_OUT_OF_MEMORY;
+    if (r == 1) hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(s->jst.bytes / 8)), dim3(256), 0, st, (u64*)s->jst.p, 0ull, s->jst.bytes / 8);
+    if ((r = grow(s->cs, sizeof(CallState))) < 0) return VBX_ERR_OUT_OF_MEMORY;
+    if (r == 1) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, (u32*)s->cs.p, 0u, sizeof(CallState) / 4);
+#undef GROW
+    s->ray_cap = ray_cap;
+    s->cross_cap = cross_cap;
+    s->tlist_cap = tlist_cap;
+    s->bins_cap = bins_cap;
+    s->nparts = nparts;
+    // pinned staging
+    Stage& sg = s->stage[s->stage_i];
+    if (sg.used) (void)hipEventSynchronize(sg.ev);
+    if (sg.bytes < tables_bytes) {
+        if (sg.host) (void)hipHostFree(sg.host);
+        sg.host = nullptr;
+        if (hipHostMalloc(&sg.host, tables_bytes, hipHostMallocDefault) != hipSuccess) {
+            sg.host = nullptr;
+            sg.bytes = 0;
+            return VBX_ERR_OUT_OF_MEMORY;
+        }
+        sg.bytes = tables_bytes;
+    }
+    if (!sg.ev && hipEventCreateWithFlags(&sg.ev, hipEventDisableTiming) != hipSuccess) return VBX_ERR_DEVICE;
+    return VBX_OK;
+}
+
+int update_occupancy_grid() {
+    static int grid = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0, cus = 256, per = 2;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_update<0>), 256, 0) !=
+                hipSuccess || per < 1)
+            per = 1;
+        grid = cus * per;
+    });
+    return grid > 0 ? grid : 512;
+}
+
+// One integration call over `maps` (distinct maps sharing maps[0]'s scratch and stream) with
+// frames[i] belonging to maps[owner[i]]; frames of one map are in call order.
+int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
+             const std::vector<int>& owner) {
+    vbx_map* lead = maps[0];
+    hipStream_t st = lead->stream;
+    const int M = (int)maps.size();
+    const int F = (int)frames.size();
+    if (F == 0) return VBX_OK;
+    if (F > VBX_MAX_FRAMES_PER_CALL) return VBX_ERR_LIMIT;
+
+    // jobs grouped by map, frames of a map in call order
+    std::vector<std::vector<int>> per_map(M);
+    for (int i = 0; i < F; ++i) per_map[owner[i]].push_back(i);
+    CallPlan plan;
+    plan.grouped = false;
+    plan.storage = lead->P.storage;
+    size_t sum_capacity = 0;
+    for (int m = 0; m < M; ++m) {
+        const vbx_map_params& P = maps[m]->P;
+        if (P.storage != plan.storage) return VBX_ERR_INVALID_ARG;
+        if (P.merge != lead->P.merge) return VBX_ERR_INVALID_ARG;
+        plan.JM = std::max<int>(plan.JM, (int)per_map[m].size());
+        plan.max_blocks = std::max(plan.max_blocks, max_blocks_per_ray(P));
+        plan.max_vox = std::max(plan.max_vox, max_voxels_per_ray(P));
+        plan.keep_touches = plan.keep_touches || (P.flags & VBX_FLAG_KEEP_TOUCHES);
+        sum_capacity += maps[m]->capacity;
+    }
+    plan.grouped = lead->P.merge == VBX_MERGE_GROUPED;
+
+    std::vector<Job> jobs;
+    std::vector<MapDesc> descs;
+    jobs.reserve(F);
+    for (int m = 0; m < M; ++m) {
+        descs.push_back(make_desc(maps[m], m, (int)jobs.size(), (int)per_map[m].size()));
+        for (size_t k = 0; k < per_map[m].size(); ++k) {
+            const vbx_frame& fr = frames[per_map[m][k]];
+            Job j;
+            std::memset(&j, 0, sizeof j);
+            if (fr.n > VBX_MAX_POINTS_PER_FRAME) return VBX_ERR_LIMIT;
+            if (fr.n > 0 && !fr.points) return VBX_ERR_INVALID_ARG;
+            if (fr.width > 0 && fr.n % fr.width != 0) return VBX_ERR_INVALID_ARG;
+            for (int q = 0; q < 12; ++q)
+                if (!std::isfinite(fr.pose[q])) return VBX_ERR_INVALID_ARG;
+            j.pts = fr.points;
+            j.n = (u32)fr.n;
+            j.width = fr.width;
+            j.map = (u32)m;
+            j.jm = (u32)k;
+            std::memcpy(j.pose, fr.pose, sizeof j.pose);
+            jobs.push_back(j);
+            plan.total_points += fr.n;
+        }
+    }
+    const int J = (int)jobs.size();
+
+    // chunks: <= kChunkJobs frames and a bounded point count each (grouping table size)
+    const size_t chunk_points_cap = (size_t)1 << 22;
+    std::vector<std::pair<int, int>> chunks;   // [begin, end)
+    size_t max_chunk_points = 0;
+    {
+        int b = 0;
+        size_t pts = 0;
+        for (int i = 0; i < J; ++i) {
+            if (i > b && (i - b >= kChunkJobs || pts + jobs[i].n > chunk_points_cap)) {
+                chunks.push_back({b, i});
+                max_chunk_points = std::max(max_chunk_points, pts);
+                b = i;
+                pts = 0;
+            }
+            pts += jobs[i].n;
+        }
+        chunks.push_back({b, J});
+        max_chunk_points = std::max(max_chunk_points, pts);
+    }
+    // tiles, numbered per chunk
+    std::vector<u32> chunk_tiles(chunks.size(), 0);
+    for (size_t c = 0; c < chunks.size(); ++c) {
+        u32 t = 0;
+        for (int i = chunks[c].first; i < chunks[c].second; ++i) {
+            Job& j = jobs[i];
+            u32 nt;
+            if (!plan.grouped) {
+                nt = (j.n + kTileSimple - 1) / kTileSimple;
+            } else if (j.width > 0) {
+                const u32 rows = j.n / j.width;
+                nt = ((j.width + kTileGroupedW - 1) / kTileGroupedW) * ((rows + kTileGroupedH - 1) / kTileGroupedH);
+            } else {
+                nt = (j.n + kTileGrouped - 1) / kTileGrouped;
+            }
+            j.tile0 = t;
+            j.ntiles = nt;
+            t += nt;
+        }
+        chunk_tiles[c] = t;
+    }
+
+    // maps integrated on the lead's stream must be idle on their own streams
+    for (int m = 1; m < M; ++m)
+        if (maps[m]->stream != st) VBX_TRY(hipStreamSynchronize(maps[m]->stream));
+    int rc = ensure_scratch(lead, plan, J, M, max_chunk_points, sum_capacity);
+    if (rc != VBX_OK) return rc;
+    Scratch* s = lead->scratch;
+
+    // stage the map and job tables
+    Stage& sg = s->stage[s->stage_i];
+    s->stage_i = (s->stage_i + 1) % 4;
+    const size_t map_bytes = (size_t)M * sizeof(MapDesc);
+    std::memcpy(sg.host, descs.data(), map_bytes);
+    std::memcpy((char*)sg.host + map_bytes, jobs.data(), (size_t)J * sizeof(Job));
+    VBX_TRY(hipMemcpyAsync(s->tables.p, sg.host, map_bytes + (size_t)J * sizeof(Job), hipMemcpyHostToDevice, st));
+    VBX_TRY(hipEventRecord(sg.ev, st));
+    sg.used = true;
+    const MapDesc* d_maps = (const MapDesc*)s->tables.p;
+    const Job* d_jobs = (const Job*)((char*)s->tables.p + map_bytes);
+    CallState* cs = (CallState*)s->cs.p;
+    JobStat* jst = (JobStat*)s->jst.p;
+    float4* rays_p = (float4*)s->rays_p.p;
+    u32* rays_job = (u32*)s->rays_job.p;
+    const u32 ray_cap = (u32)s->ray_cap;
+
+    // points
+    for (size_t c = 0; c < chunks.size(); ++c) {
+        const int jb = chunks[c].first, je = chunks[c].second;
+        if (chunk_tiles[c] == 0) continue;
+        if (!plan.grouped) {
+            hipLaunchKernelGGL(k_points_simple, dim3(chunk_tiles[c]), dim3(256), 0, st, d_jobs + jb, je - jb, jb,
+                               d_maps, rays_p, rays_job, jst, cs, ray_cap);
+        } else {
+            hipLaunchKernelGGL(k_points_grouped, dim3(chunk_tiles[c]), dim3(256), 0, st, d_jobs + jb, je - jb, jb,
+                               d_maps, (GroupEntry*)s->gtable.p, (u32)(s->gcap - 1), (u32*)s->occ.p, jst, cs);
+            size_t pts = 0;
+            for (int i = jb; i < je; ++i) pts += jobs[i].n;
+            hipLaunchKernelGGL(k_groups_to_rays, dim3(grid_for(pts, 1024)), dim3(256), 0, st, d_jobs + jb, jb, d_maps,
+                               (GroupEntry*)s->gtable.p, (const u32*)s->occ.p, rays_p, rays_job, jst, cs, ray_cap);
+            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->occ_count, 0u);
+        }
+    }
+    const unsigned G = grid_for(plan.total_points, 2048);
+    hipLaunchKernelGGL(k_cross, dim3(G), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
+                       (const u32*)rays_job, (u64*)s->tkeys.p, (u32)(s->tkey_cap - 1), (u32*)s->tlist.p,
+                       (u32)s->tlist_cap, (uint2*)s->cross.p, (u32)s->cross_cap, jst, cs, ray_cap);
+    const unsigned GT = grid_for(s->tlist_cap, 1024);
+    hipLaunchKernelGGL(k_resolve, dim3(GT), dim3(256), 0, st, d_maps, (const u64*)s->tkeys.p, (u32*)s->tval.p,
+                       (const u32*)s->tlist.p, (u64*)s->t_key.p, (int*)s->t_slot.p, cs);
+    hipLaunchKernelGGL(k_commit, dim3(GT), dim3(256), 0, st, d_maps, (const u64*)s->t_key.p, (int*)s->t_slot.p, cs);
+    const u32 JM = (u32)plan.JM;
+    hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, d_jobs, (const uint2*)s->cross.p,
+                       (const u32*)s->tval.p, (const u32*)rays_job, (u32*)s->bins.p, JM, cs);
+    const unsigned NP = (unsigned)std::max<size_t>(s->nparts, 1);
+    hipLaunchKernelGGL(k_scan_sums, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, JM, (u32*)s->partial.p,
+                       (const CallState*)cs);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, (u32*)s->partial.p, (u32)NP, (u32*)s->off.p, JM,
+                       (const CallState*)cs);
+    hipLaunchKernelGGL(k_scan_final, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, (const u32*)s->partial.p,
+                       (u32*)s->off.p, JM, (const CallState*)cs);
+    hipLaunchKernelGGL(k_scatter, dim3(G), dim3(256), 0, st, d_jobs, (const uint2*)s->cross.p, (const u32*)s->tval.p,
+                       (const u32*)rays_job, (u32*)s->bins.p, (const u32*)s->off.p, JM, (u32*)s->sorted.p, cs);
+    if (plan.keep_touches) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->touch_count, 0u);
+    const int GU = update_occupancy_grid();
+    if (plan.storage == VBX_F32) {
+        hipLaunchKernelGGL(k_update<0>, dim3(GU), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
+                           (const u64*)s->t_key.p, (const int*)s->t_slot.p, (const u32*)s->off.p,
+                           (const u32*)s->sorted.p, JM, (u64*)s->touch_key.p, (u32*)s->touch_n.p,
+                           (u32)s->touch_cap, plan.keep_touches ? 1 : 0, jst, cs);
+    } else {
+        hipLaunchKernelGGL(k_update<1>, dim3(GU), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
+                           (const u64*)s->t_key.p, (const int*)s->t_slot.p, (const u32*)s->off.p,
+                           (const u32*)s->sorted.p, JM, (u64*)s->touch_key.p, (u32*)s->touch_n.p,
+                           (u32)s->touch_cap, plan.keep_touches ? 1 : 0, jst, cs);
+    }
+    hipLaunchKernelGGL(k_cleanup, dim3(grid_for(s->tkey_cap, 1024)), dim3(256), 0, st, (u64*)s->tkeys.p,
+                       (u32)s->tkey_cap, (const u32*)s->tlist.p, (u32)s->tlist_cap, (const CallState*)cs);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, d_jobs, J, d_maps, M, jst, cs);
+    if (hipGetLastError() != hipSuccess) return VBX_ERR_DEVICE;
+    if (plan.keep_touches) {
+        s->last_maps = maps;
+        s->touches_valid = true;
+        for (int m = 0; m < M; ++m) {
+            maps[m]->touch_src = s;
+            maps[m]->touch_idx = m;
+        }
+    }
+    return VBX_OK;
+}
+
+int read_state(vbx_map* m, MapState* out) {
+    VBX_TRY(hipStreamSynchronize(m->stream));
+    VBX_TRY(hipMemcpy(out, m->st, sizeof(MapState), hipMemcpyDeviceToHost));
+    return VBX_OK;
+}
+
+// Host-side insertion with the device's probe order (linear probing from mix64(key)).
+void host_insert(std::vector<u64>& keys, std::vector<int>& slots, u64 key, int slot) {
+    const u32 mask = (u32)keys.size() - 1;
+    u32 h = (u32)mix64(key) & mask;
+    while (keys[h] != kEmpty && keys[h] != key) h = (h + 1) & mask;
+    keys[h] = key;
+    slots[h] = slot;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void vbx_default_params(vbx_map_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->voxel_size = 0.1f;
+    p->trunc = 0.3f;
+    p->w_max = 1e4f;
+    p->max_range = 5.0f;
+    p->z_min = 0.1f;
+    p->weighting = VBX_W_CONST;
+    p->merge = VBX_MERGE_NONE;
+    p->storage = VBX_F32;
+    p->dist = VBX_DIST_EQ1;
+    p->block_capacity = 65536;
+    p->flags = 0;
+    p->stream = nullptr;
+}
+
+int vbx_map_create_ex(const vbx_map_params* params, vbx_map** out) {
+    if (!params || !out) return VBX_ERR_INVALID_ARG;
+    int rc = validate_params(*params);
+    if (rc != VBX_OK) return rc;
+    vbx_map* m = new (std::nothrow) vbx_map();
+    if (!m) return VBX_ERR_OUT_OF_MEMORY;
+    m->P = *params;
+    (void)hipGetDevice(&m->device);
+    m->stream = (hipStream_t)params->stream;
+    m->voxel_bytes = params->storage == VBX_F16 ? 4 : 8;
+    m->wbits = weight_bits(m->P);
+    m->kw = sum_bits(m->P);
+    m->scratch = new (std::nothrow) Scratch();
+    if (!m->scratch || hipMalloc(&m->st, sizeof(MapState)) != hipSuccess) {
+        delete m->scratch;
+        delete m;
+        return VBX_ERR_OUT_OF_MEMORY;
+    }
+    MapState zero;
+    std::memset(&zero, 0, sizeof zero);
+    if (hipMemcpy(m->st, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess ||
+        (rc = alloc_storage(m, params->block_capacity)) != VBX_OK ||
+        hipStreamSynchronize(m->stream) != hipSuccess) {
+        free_storage(m);
+        (void)hipFree(m->st);
+        free_scratch(m->scratch);
+        delete m;
+        return rc != VBX_OK ? rc : VBX_ERR_DEVICE;
+    }
+    *out = m;
+    return VBX_OK;
+}
+
+int vbx_map_create(float voxel_size, float trunc, int weighting, vbx_map** out) {
+    vbx_map_params p;
+    vbx_default_params(&p);
+    p.voxel_size = voxel_size;
+    p.trunc = trunc;
+    p.weighting = weighting;
+    return vbx_map_create_ex(&p, out);
+}
+
+void vbx_map_destroy(vbx_map* m) {
+    if (!m) return;
+    (void)hipStreamSynchronize(m->stream);
+    free_storage(m);
+    (void)hipFree(m->st);
+    free_scratch(m->scratch);
+    delete m;
+}
+
+int vbx_map_set_stream(vbx_map* m, void* stream) {
+    if (!m) return VBX_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(m->stream);
+    m->stream = (hipStream_t)stream;
+    m->P.stream = stream;
+    return VBX_OK;
+}
+
+int vbx_integrate_frames(vbx_map* m, const vbx_frame* frames, int F) {
+    if (!m || F < 0 || (F > 0 && !frames)) return VBX_ERR_INVALID_ARG;
+    std::vector<vbx_map*> maps{m};
+    std::vector<vbx_frame> fr(frames, frames + F);
+    std::vector<int> owner(F, 0);
+    return run_call(maps, fr, owner);
+}
+
+int vbx_integrate(vbx_map* m, const float* points_dev, size_t n, const float pose[12]) {
+    if (!m || !pose || (n > 0 && !points_dev)) return VBX_ERR_INVALID_ARG;
+    vbx_frame f;
+    std::memset(&f, 0, sizeof f);
+    f.points = points_dev;
+    f.n = n;
+    std::memcpy(f.pose, pose, sizeof f.pose);
+    return vbx_integrate_frames(m, &f, 1);
+}
+
+int vbx_integrate_batch(vbx_map* m, const float* const* points_dev, const size_t* n,
+                        const float* poses, int F) {
+    if (!m || F < 0 || (F > 0 && (!points_dev || !n || !poses))) return VBX_ERR_INVALID_ARG;
+    std::vector<vbx_frame> fr(F);
+    for (int i = 0; i < F; ++i) {
+        std::memset(&fr[i], 0, sizeof fr[i]);
+        fr[i].points = points_dev[i];
+        fr[i].n = n[i];
+        std::memcpy(fr[i].pose, poses + 12 * i, sizeof fr[i].pose);
+    }
+    return vbx_integrate_frames(m, fr.data(), F);
+}
+
+int vbx_integrate_multi(vbx_map* const* maps, const vbx_frame* frames, int M) {
+    if (!maps || !frames || M <= 0) return VBX_ERR_INVALID_ARG;
+    if (M > 127) return VBX_ERR_LIMIT;
+    std::vector<vbx_map*> mv(maps, maps + M);
+    for (int i = 0; i < M; ++i) {
+        if (!mv[i]) return VBX_ERR_INVALID_ARG;
+        for (int j = 0; j < i; ++j)
+            if (mv[j] == mv[i]) return VBX_ERR_INVALID_ARG;
+    }
+    std::vector<vbx_frame> fr(frames, frames + M);
+    std::vector<int> owner(M);
+    for (int i = 0; i < M; ++i) owner[i] = i;
+    return run_call(mv, fr, owner);
+}
+
+int vbx_map_sync(vbx_map* m) {
+    if (!m) return VBX_ERR_INVALID_ARG;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    return s.error;
+}
+
+int vbx_map_clear_error(vbx_map* m) {
+    if (!m) return VBX_ERR_INVALID_ARG;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    s.error = 0;
+    VBX_TRY(hipMemcpy(m->st, &s, sizeof s, hipMemcpyHostToDevice));
+    return VBX_OK;
+}
+
+int vbx_map_num_blocks(vbx_map* m, size_t* n_out) {
+    if (!m || !n_out) return VBX_ERR_INVALID_ARG;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    *n_out = s.block_count;
+    return VBX_OK;
+}
+
+int vbx_map_reserve(vbx_map* m, uint32_t block_capacity) {
+    if (!m || block_capacity == 0 || block_capacity > (1u << 29)) return VBX_ERR_INVALID_ARG;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    if (block_capacity <= m->capacity) {
+        if (s.error == VBX_ERR_POOL_FULL) return vbx_map_clear_error(m);
+        return VBX_OK;
+    }
+    // copy the old hash to the host, allocate the bigger storage, move the pool, rehash
+    std::vector<u64> okeys(m->hcap);
+    std::vector<int> oslots(m->hcap);
+    VBX_TRY(hipMemcpy(okeys.data(), m->hkeys, sizeof(u64) * m->hcap, hipMemcpyDeviceToHost));
+    VBX_TRY(hipMemcpy(oslots.data(), m->hslots, sizeof(int) * m->hcap, hipMemcpyDeviceToHost));
+    u64* old_keys = m->hkeys;
+    int* old_slots = m->hslots;
+    void* old_pool = m->pool;
+    const u32 old_cap = m->capacity;
+    m->hkeys = nullptr;
+    m->hslots = nullptr;
+    m->pool = nullptr;
+    rc = alloc_storage(m, block_capacity);
+    if (rc != VBX_OK) {
+        free_storage(m);
+        m->hkeys = old_keys;
+        m->hslots = old_slots;
+        m->pool = old_pool;
+        m->capacity = old_cap;
+        m->hcap = (u32)okeys.size();
+        return rc;
+    }
+    VBX_TRY(hipMemcpyAsync(m->pool, old_pool, (size_t)s.block_count * 4096 * m->voxel_bytes,
+                           hipMemcpyDeviceToDevice, m->stream));
+    std::vector<u64> nkeys(m->hcap, kEmpty);
+    std::vector<int> nslots(m->hcap, 0);
+    for (size_t i = 0; i < okeys.size(); ++i)
+        if (okeys[i] != kEmpty) host_insert(nkeys, nslots, okeys[i], oslots[i]);
+    VBX_TRY(hipStreamSynchronize(m->stream));
+    VBX_TRY(hipMemcpy(m->hkeys, nkeys.data(), sizeof(u64) * m->hcap, hipMemcpyHostToDevice));
+    VBX_TRY(hipMemcpy(m->hslots, nslots.data(), sizeof(int) * m->hcap, hipMemcpyHostToDevice));
+    (void)hipFree(old_keys);
+    (void)hipFree(old_slots);
+    (void)hipFree(old_pool);
+    m->P.block_capacity = block_capacity;
+    if (s.error == VBX_ERR_POOL_FULL) {
+        s.error = 0;
+        VBX_TRY(hipMemcpy(m->st, &s, sizeof s, hipMemcpyHostToDevice));
+    }
+    return VBX_OK;
+}
+
+int vbx_export_blocks(vbx_map* m, int32_t* coords, float* dw, size_t cap, size_t* n_out) {
+    if (!m || !n_out) return VBX_ERR_INVALID_ARG;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    const size_t nb = s.block_count;
+    if (!coords && !dw) {
+        *n_out = nb;
+        return VBX_OK;
+    }
+    if (cap < nb) return VBX_ERR_BUFFER_TOO_SMALL;
+    std::vector<u64> keys(m->hcap);
+    std::vector<int> slots(m->hcap);
+    VBX_TRY(hipMemcpy(keys.data(), m->hkeys, sizeof(u64) * m->hcap, hipMemcpyDeviceToHost));
+    VBX_TRY(hipMemcpy(slots.data(), m->hslots, sizeof(int) * m->hcap, hipMemcpyDeviceToHost));
+    std::vector<std::pair<u64, int>> blocks;
+    blocks.reserve(nb);
+    for (size_t i = 0; i < keys.size(); ++i)
+        if (keys[i] != kEmpty) blocks.push_back({keys[i], slots[i]});
+    if (blocks.size() != nb) return VBX_ERR_DEVICE;
+    std::sort(blocks.begin(), blocks.end());
+    std::vector<unsigned char> pool;
+    if (dw) {
+        pool.resize(nb * 4096 * m->voxel_bytes);
+        if (nb) VBX_TRY(hipMemcpy(pool.data(), m->pool, pool.size(), hipMemcpyDeviceToHost));
+    }
+    for (size_t b = 0; b < nb; ++b) {
+        if (coords) {
+            int bx, by, bz;
+            unpack_block(blocks[b].first, bx, by, bz);
+            coords[3 * b] = bx;
+            coords[3 * b + 1] = by;
+            coords[3 * b + 2] = bz;
+        }
+        if (dw) {
+            const size_t slot = (size_t)blocks[b].second;
+            for (int l = 0; l < 4096; ++l) {
+                float Dn, W;
+                if (m->P.storage == VBX_F32) {
+                    const float* v = (const float*)pool.data() + 2 * (slot * 4096 + l);
+                    Dn = v[0];
+                    W = v[1];
+                } else {
+                    const uint32_t raw = ((const uint32_t*)pool.data())[slot * 4096 + l];
+                    Dn = __half2float(__ushort_as_half((unsigned short)(raw & 0xFFFF)));
+                    W = __half2float(__ushort_as_half((unsigned short)(raw >> 16)));
+                }
+                dw[2 * (b * 4096 + l)] = Dn * m->P.trunc;
+                dw[2 * (b * 4096 + l) + 1] = W;
+            }
+        }
+    }
+    *n_out = nb;
+    return VBX_OK;
+}
+
+int vbx_import_blocks(vbx_map* m, const int32_t* coords, const float* dw, size_t n) {
+    if (!m || (n > 0 && (!coords || !dw))) return VBX_ERR_INVALID_ARG;
+    if (n > m->capacity) return VBX_ERR_POOL_FULL;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    std::vector<u64> keys(m->hcap, kEmpty);
+    std::vector<int> slots(m->hcap, 0);
+    std::vector<unsigned char> pool(n * 4096 * m->voxel_bytes);
+    for (size_t b = 0; b < n; ++b) {
+        const int bx = coords[3 * b], by = coords[3 * b + 1], bz = coords[3 * b + 2];
+        const int lim = kVoxLimit / 16;
+        if (bx < -lim || bx >= lim || by < -lim || by >= lim || bz < -lim || bz >= lim) return VBX_ERR_INVALID_ARG;
+        host_insert(keys, slots, pack_block(bx, by, bz), (int)b);
+        for (int l = 0; l < 4096; ++l) {
+            const float Dn = dw[2 * (b * 4096 + l)] / m->P.trunc;
+            const float W = dw[2 * (b * 4096 + l) + 1];
+            if (m->P.storage == VBX_F32) {
+                float* v = (float*)pool.data() + 2 * (b * 4096 + l);
+                v[0] = Dn;
+                v[1] = W;
+            } else {
+                const uint32_t d = __half_as_ushort(__float2half_rn(Dn));
+                const uint32_t w = __half_as_ushort(__float2half_rn(W));
+                ((uint32_t*)pool.data())[b * 4096 + l] = d | (w << 16);
+            }
+        }
+    }
+    VBX_TRY(hipMemcpy(m->hkeys, keys.data(), sizeof(u64) * m->hcap, hipMemcpyHostToDevice));
+    VBX_TRY(hipMemcpy(m->hslots, slots.data(), sizeof(int) * m->hcap, hipMemcpyHostToDevice));
+    if (n) VBX_TRY(hipMemcpy(m->pool, pool.data(), pool.size(), hipMemcpyHostToDevice));
+    s.block_count = (u32)n;
+    s.new_count = 0;
+    s.error = 0;
+    VBX_TRY(hipMemcpy(m->st, &s, sizeof s, hipMemcpyHostToDevice));
+    return VBX_OK;
+}
+
+int vbx_last_touches(vbx_map* m, int32_t* coords, uint32_t* counts, size_t cap, size_t* n_out) {
+    if (!m || !n_out) return VBX_ERR_INVALID_ARG;
+    if (!(m->P.flags & VBX_FLAG_KEEP_TOUCHES) || !m->touch_src) return VBX_ERR_INVALID_ARG;
+    Scratch* s = m->touch_src;
+    vbx_map* lead = s->last_maps.empty() ? m : s->last_maps[0];
+    VBX_TRY(hipStreamSynchronize(lead->stream));
+    CallState cs;
+    VBX_TRY(hipMemcpy(&cs, s->cs.p, sizeof cs, hipMemcpyDeviceToHost));
+    const size_t total = cs.touch_count;
+    if (total > s->touch_cap) return VBX_ERR_BUFFER_TOO_SMALL;
+    std::vector<u64> keys(total);
+    std::vector<u32> n(total);
+    if (total) {
+        VBX_TRY(hipMemcpy(keys.data(), s->touch_key.p, total * sizeof(u64), hipMemcpyDeviceToHost));
+        VBX_TRY(hipMemcpy(n.data(), s->touch_n.p, total * sizeof(u32), hipMemcpyDeviceToHost));
+    }
+    size_t cnt = 0;
+    for (size_t i = 0; i < total; ++i)
+        if ((int)(keys[i] >> 57) == m->touch_idx) ++cnt;
+    if (!coords && !counts) {
+        *n_out = cnt;
+        return VBX_OK;
+    }
+    if (cap < cnt) return VBX_ERR_BUFFER_TOO_SMALL;
+    size_t j = 0;
+    for (size_t i = 0; i < total; ++i) {
+        if ((int)(keys[i] >> 57) != m->touch_idx) continue;
+        int gx, gy, gz;
+        unpack_voxel(keys[i] & ((1ull << 57) - 1), gx, gy, gz);
+        if (coords) {
+            coords[3 * j] = gx;
+            coords[3 * j + 1] = gy;
+            coords[3 * j + 2] = gz;
+        }
+        if (counts) counts[j] = n[i];
+        ++j;
+    }
+    *n_out = cnt;
+    return VBX_OK;
+}
+
+int vbx_map_stats(vbx_map* m, vbx_stats* out) {
+    if (!m || !out) return VBX_ERR_INVALID_ARG;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    out->points = s.points;
+    out->valid = s.valid;
+    out->invalid = s.invalid;
+    out->out_of_bounds = s.oob;
+    out->rays = s.rays;
+    out->touches = s.touches;
+    out->voxels = s.voxels;
+    out->new_blocks = s.new_blocks;
+    out->blocks = s.block_count;
+    out->calls = s.calls;
+    return VBX_OK;
+}
+
+int vbx_debug_traverse(const float* A_dev, const float* B_dev, int n, int32_t* out_dev, int cap,
+                       int32_t* counts_dev) {
+    if (n < 0 || cap < 0 || (n > 0 && (!A_dev || !B_dev || !counts_dev || (cap > 0 && !out_dev))))
+        return VBX_ERR_INVALID_ARG;
+    if (n == 0) return VBX_OK;
+    hipLaunchKernelGGL(k_debug_traverse, dim3((n + 255) / 256), dim3(256), 0, nullptr, A_dev, B_dev, n,
+                       (int*)out_dev, cap, (int*)counts_dev);
+    VBX_TRY(hipGetLastError());
+    VBX_TRY(hipStreamSynchronize(nullptr));
+    return VBX_OK;
+}
+
+const char* vbx_status_string(int status) {
+    switch (status) {
+        case VBX_OK: return "ok";
+        case VBX_ERR_INVALID_ARG: return "invalid argument";
+        case VBX_ERR_OUT_OF_MEMORY: return "out of memory";
+        case VBX_ERR_POOL_FULL: return "block pool full";
+        case VBX_ERR_BUFFER_TOO_SMALL: return "buffer too small";
+        case VBX_ERR_DEVICE: return "device error";
+        case VBX_ERR_LIMIT: return "limit exceeded";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

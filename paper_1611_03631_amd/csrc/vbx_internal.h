@@ -1,0 +1,278 @@
+// Internal structures and device helpers of the vbx TSDF integrator (gfx950).
+//
+// Everything here is compiled without floating-point contraction: the traversal,
+// validity tests, the sign of the Eq. (1) distance and the grouped-raycasting
+// mean are binary32/binary64 operations in a fixed order, so that the voxels a
+// ray visits are reproducible bit-for-bit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace vbx {
+
+typedef unsigned long long u64;
+typedef long long i64;
+typedef unsigned int u32;
+
+constexpr u64 kEmpty = ~0ull;
+constexpr int kVoxLimit = 1 << 18;     // |voxel index| < 2^18
+constexpr int kBlockBias = 1 << 14;    // block indices packed as 15-bit biased fields
+constexpr int kTileSimple = 1024;      // points per workgroup, per-point raycasting
+constexpr int kTileGroupedW = 32;      // 2-D tile of an organised cloud (grouped)
+constexpr int kTileGroupedH = 16;
+constexpr int kTileGrouped = kTileGroupedW * kTileGroupedH;  // 512 points
+constexpr int kGroupSlots = 1024;      // LDS hash slots per grouped tile (load <= 0.5)
+constexpr int kChunkJobs = 127;        // frames per grouping table fill (7-bit tag, 127 reserved)
+constexpr int kMaxStepsPerRay = 96;    // guard only; real bands need 3*(2*delta/v + 2) + 1
+
+// Per-map parameters and device pointers for one call (copied to the device per call).
+struct MapDesc {
+    float v, iv, delta, inv_delta;  // voxel size, 1/v (binary32), truncation, 1/delta
+    float eps, ramp, w_max, rmax2;  // Eq. (5) epsilon = v, 1/(delta-eps), W_max, max_range^2
+    float z_min, wscale, inv_wscale, pad0;  // weight fixed-point scale 2^kw and 2^-kw
+    int weighting, merge, storage, dist;
+    int wbits;                      // grouped-mean weight bits (0: unit weights)
+    int njobs, job0;                // this map's frames in the call: jobs [job0, job0+njobs)
+    int map_id;
+    u64* hkeys;                     // block hash: keys (kEmpty = free)
+    int* hslots;                    //             pool slot per key
+    u32 hmask;                      // hash capacity - 1
+    u32 capacity;                   // pool capacity in blocks
+    void* pool;                     // [capacity][4096] float2 (F32) or u32 half pairs (F16)
+    struct MapState* st;
+};
+
+// Device-resident counters of a map.
+struct MapState {
+    u32 block_count;   // committed blocks (pool slots [0, block_count) are in use)
+    u32 new_count;     // blocks pending in the current call
+    int error;         // sticky vbx_status of the device side
+    u32 pad;
+    u64 points, valid, invalid, oob, rays, touches, voxels, new_blocks, calls;
+};
+
+// One frame of a call.
+struct Job {
+    const float* pts;
+    u32 n, width;     // points; organised row length (0: unorganised)
+    u32 map;          // index into the call's MapDesc array
+    u32 jm;           // frame index within its map for this call
+    u32 tile0;        // first tile of this job in the current launch
+    u32 ntiles;
+    float pose[12];
+};
+
+// Counters of one call (device).
+struct CallState {
+    u32 ray_count;
+    u32 cross_count;
+    u32 t_count;
+    u32 occ_count;     // grouping table: occupied entries
+    u32 work_next;     // persistent work counter of the update kernel
+    u32 touch_count;
+    int error;         // call-wide error (scratch overflow)
+    u32 pad;
+};
+
+// Grouping table entry (64 bytes): exact integer sums of one (frame, voxel) group.
+struct GroupEntry {
+    u64 key;       // (job_in_chunk << 57) | voxel key
+    u64 so;        // sum of fixed-point point weights
+    u64 sq[3];     // low 64 bits of sum(weight * Q_k)
+    u32 sqhi[3];   // high bits
+    u32 n;         // points
+    u32 idx;       // index of the point when the group has one point
+    u32 pad;
+};
+
+__host__ __device__ inline u64 mix64(u64 x) {
+    x ^= x >> 33; x *= 0xff51afd7ed558ccdULL;
+    x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ULL;
+    x ^= x >> 33;
+    return x;
+}
+
+__host__ __device__ inline u64 pack_block(int bx, int by, int bz) {
+    return ((u64)(u32)(bx + kBlockBias) << 30) | ((u64)(u32)(by + kBlockBias) << 15) |
+           (u64)(u32)(bz + kBlockBias);
+}
+__host__ __device__ inline void unpack_block(u64 k, int& bx, int& by, int& bz) {
+    bx = (int)((k >> 30) & 0x7FFF) - kBlockBias;
+    by = (int)((k >> 15) & 0x7FFF) - kBlockBias;
+    bz = (int)(k & 0x7FFF) - kBlockBias;
+}
+__host__ __device__ inline u64 block_key_of(int gx, int gy, int gz) {
+    return pack_block(gx >> 4, gy >> 4, gz >> 4);   // arithmetic shift = floor division by 16
+}
+__host__ __device__ inline u32 local_of(int gx, int gy, int gz) {
+    return (u32)(gx & 15) | ((u32)(gy & 15) << 4) | ((u32)(gz & 15) << 8);
+}
+__host__ __device__ inline u64 voxel_key_of(int gx, int gy, int gz) {
+    return (block_key_of(gx, gy, gz) << 12) | local_of(gx, gy, gz);
+}
+__host__ __device__ inline void unpack_voxel(u64 k, int& gx, int& gy, int& gz) {
+    int bx, by, bz;
+    unpack_block(k >> 12, bx, by, bz);
+    gx = 16 * bx + (int)(k & 15);
+    gy = 16 * by + (int)((k >> 4) & 15);
+    gz = 16 * bz + (int)((k >> 8) & 15);
+}
+
+// ---------------------------------------------------------------------------
+// Point validity and pose transform (binary32, fixed order)
+// ---------------------------------------------------------------------------
+// Returns true and the world point q when the sensor-frame point is valid:
+// finite, 0 < |p|^2 <= max_range^2, depth z >= z_min under quadratic weighting,
+// and the world point's voxel index inside the addressable range.
+__device__ inline int classify_point(const MapDesc& M, const float* pose, float x, float y,
+                                     float z, float q[3]) {
+    // 0 = invalid, 1 = valid, 2 = out of bounds
+    if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z))) return 0;
+    float rho2 = (x * x + y * y) + z * z;
+    if (!(rho2 > 0.0f && rho2 <= M.rmax2)) return 0;
+    if (M.weighting == 1 && !(z >= M.z_min)) return 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        q[k] = ((pose[4 * k] * x + pose[4 * k + 1] * y) + pose[4 * k + 2] * z) + pose[4 * k + 3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float f = q[k] * M.iv;
+        if (!(f >= -(float)kVoxLimit && f < (float)kVoxLimit)) return 2;
+    }
+    return 1;
+}
+
+// ---------------------------------------------------------------------------
+// Ray set-up and traversal of the truncation band (binary32, fixed order)
+// ---------------------------------------------------------------------------
+struct Walk {
+    int g[3];        // current voxel
+    int n[3];        // steps left per axis
+    int step[3];
+    float tM[3], tD[3];
+    int left;        // total steps left
+};
+
+// Segment of the ray s->p inside the band [max(r - delta, 0), r + delta]; returns
+// false (out of bounds) when r == 0 or an end lies outside the voxel range.
+__device__ inline bool walk_setup(const MapDesc& M, const float p[3], const float s[3],
+                                  float e[3], float& r, Walk& w) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = p[k] - s[k];
+    r = __builtin_sqrtf((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
+    if (r == 0.0f) return false;
+    float t0 = r - M.delta;
+    if (t0 < 0.0f) t0 = 0.0f;
+    float t1 = r + M.delta;
+    float A[3], B[3];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float u = e[k] / r;
+        float a = s[k] + u * t0;
+        float b = s[k] + u * t1;
+        A[k] = a * M.iv;
+        B[k] = b * M.iv;
+        ok = ok && (A[k] >= -(float)kVoxLimit && A[k] < (float)kVoxLimit &&
+                    B[k] >= -(float)kVoxLimit && B[k] < (float)kVoxLimit);
+    }
+    if (!ok) return false;
+    w.left = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        int ga = (int)__builtin_floorf(A[k]);
+        int gb = (int)__builtin_floorf(B[k]);
+        w.g[k] = ga;
+        w.n[k] = gb > ga ? gb - ga : ga - gb;
+        w.step[k] = gb > ga ? 1 : (gb < ga ? -1 : 0);
+        w.tM[k] = __builtin_inff();
+        w.tD[k] = __builtin_inff();
+        if (w.n[k] > 0) {
+            float delta = B[k] - A[k];
+            float bound = (float)(ga + (w.step[k] > 0 ? 1 : 0));
+            w.tD[k] = 1.0f / __builtin_fabsf(delta);
+            w.tM[k] = (bound - A[k]) / delta;
+        }
+        w.left += w.n[k];
+    }
+    return true;
+}
+
+// Traversal from voxel-space end points directly (verification entry point).
+__device__ inline void walk_setup_vox(const float A[3], const float B[3], Walk& w) {
+    w.left = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        int ga = (int)__builtin_floorf(A[k]);
+        int gb = (int)__builtin_floorf(B[k]);
+        w.g[k] = ga;
+        w.n[k] = gb > ga ? gb - ga : ga - gb;
+        w.step[k] = gb > ga ? 1 : (gb < ga ? -1 : 0);
+        w.tM[k] = __builtin_inff();
+        w.tD[k] = __builtin_inff();
+        if (w.n[k] > 0) {
+            float delta = B[k] - A[k];
+            float bound = (float)(ga + (w.step[k] > 0 ? 1 : 0));
+            w.tD[k] = 1.0f / __builtin_fabsf(delta);
+            w.tM[k] = (bound - A[k]) / delta;
+        }
+        w.left += w.n[k];
+    }
+}
+
+// One step: among axes with steps left, the smallest crossing parameter; ties go
+// to the lowest axis.
+// (Constant indices only, so the walk state stays in registers.)
+__device__ inline void walk_step(Walk& w) {
+    int axis = -1;
+    float best = 0.0f;
+    if (w.n[0] > 0) { axis = 0; best = w.tM[0]; }
+    if (w.n[1] > 0 && (axis < 0 || w.tM[1] < best)) { axis = 1; best = w.tM[1]; }
+    if (w.n[2] > 0 && (axis < 0 || w.tM[2] < best)) { axis = 2; }
+    // an axis is always found: the caller only steps while w.left > 0
+    if (axis == 0) {
+        w.g[0] += w.step[0]; w.n[0] -= 1; w.tM[0] = w.tM[0] + w.tD[0];
+    } else if (axis == 1) {
+        w.g[1] += w.step[1]; w.n[1] -= 1; w.tM[1] = w.tM[1] + w.tD[1];
+    } else {
+        w.g[2] += w.step[2]; w.n[2] -= 1; w.tM[2] = w.tM[2] + w.tD[2];
+    }
+    w.left -= 1;
+}
+
+// ---------------------------------------------------------------------------
+// Observation of a voxel by a ray: Eq. (1) distance, Eq. (2)/(5) weight
+// ---------------------------------------------------------------------------
+struct Obs {
+    float w;     // weight
+    float e;     // clamped distance / delta, in [-1, 1]
+};
+
+__device__ inline Obs observe(const MapDesc& M, const float p[3], const float e[3], float r,
+                              float wgt, int gx, int gy, int gz) {
+    float f0 = p[0] - ((float)gx + 0.5f) * M.v;
+    float f1 = p[1] - ((float)gy + 0.5f) * M.v;
+    float f2 = p[2] - ((float)gz + 0.5f) * M.v;
+    float dot = (f0 * e[0] + f1 * e[1]) + f2 * e[2];
+    float d;
+    if (M.dist == 0) {
+        float mag = __builtin_sqrtf((f0 * f0 + f1 * f1) + f2 * f2);
+        d = dot > 0.0f ? mag : (dot < 0.0f ? -mag : 0.0f);
+    } else {
+        d = dot / r;
+    }
+    Obs o;
+    float fdrop = 1.0f;
+    if (M.weighting == 1)
+        fdrop = d > -M.eps ? 1.0f : (d > -M.delta ? (d + M.delta) * M.ramp : 0.0f);
+    o.w = wgt * fdrop;
+    float dc = d < -M.delta ? -M.delta : (d > M.delta ? M.delta : d);
+    o.e = dc * M.inv_delta;
+    if (o.e > 1.0f) o.e = 1.0f;
+    if (o.e < -1.0f) o.e = -1.0f;
+    return o;
+}
+
+}  // namespace vbx

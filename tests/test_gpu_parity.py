@@ -1,0 +1,197 @@
+"""GPU path (through the C ABI) against the CPU oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from tests.common import (compare_export, compare_touches, gpu_map, log, oracle_map)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vbx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1611_03631_amd as vbx
+    vbx.lib()
+    return vbx
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def run_both(vbx, params, frames, batch=False, **over):
+    """Integrate frames [(points, pose[, width])] on the GPU and in the oracle."""
+    g = gpu_map(vbx, params, **over)
+    o = oracle_map(params, **over)
+    if batch:
+        g.integrate_frames([(dev(f[0]), f[1]) + tuple(f[2:]) for f in frames])
+    for f in frames:
+        if not batch:
+            g.integrate(dev(f[0]), f[1])
+        o.integrate(f[0], f[1])
+    assert g.sync() == 0
+    return g, o
+
+
+# ---------------------------------------------------------------------------
+# traversal primitive
+# ---------------------------------------------------------------------------
+def test_traversal_bit_exact(vbx):
+    import oracle
+    rng = np.random.default_rng(21)
+    A = rng.uniform(-40, 40, size=(4000, 3)).astype(np.float32)
+    B = (A + rng.uniform(-9, 9, size=(4000, 3))).astype(np.float32)
+    # dyadic segments with exact face and edge ties
+    Ad = (rng.integers(-64, 64, size=(1000, 3)) / 16.0).astype(np.float32)
+    Bd = (Ad + rng.choice([-2.0, -1.0, -0.5, 0.0, 0.5, 1.0, 2.0, 4.0], size=(1000, 3))).astype(np.float32)
+    Ac = np.floor(Ad) + np.float32(0.5)
+    Bc = (Ac + rng.choice([-2.0, 2.0], size=(1000, 3))).astype(np.float32)
+    A = np.concatenate([A, Ad, Ac.astype(np.float32)])
+    B = np.concatenate([B, Bd, Bc])
+    log(f"traversal: {A.shape[0]} segments")
+    out, counts = vbx.debug_traverse(dev(A), dev(B), cap=64)
+    out, counts = out.cpu().numpy(), counts.cpu().numpy()
+    for i in range(A.shape[0]):
+        ref = oracle.dda(A[i], B[i])
+        assert counts[i] == ref.shape[0], i
+        assert np.array_equal(out[i, :counts[i]], ref), i
+
+
+# ---------------------------------------------------------------------------
+# single frames, every mode
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("weighting,merge,dist", [("const", "simple", "eq1"), ("quad", "simple", "eq1"),
+                                                  ("const", "grouped", "eq1"), ("quad", "grouped", "eq1"),
+                                                  ("quad", "grouped", "ray")])
+def test_c1_room_frame(vbx, weighting, merge, dist):
+    import synth
+    w = synth.config1()
+    params = dict(w.params, weighting=weighting, merge=merge, dist=dist)
+    log(f"c1 160x120 {weighting} {merge} {dist}")
+    g, o = run_both(vbx, params, [(w.frame(0), w.poses[0])])
+    n = compare_touches(g.last_touches(), o.last_touches())
+    res = compare_export(g.export(), o.export(), params)
+    st = g.stats()
+    assert st["touches"] == sum(o.last_touches()[1]) and st["voxels"] == n
+    log(f"  ok: {res}")
+
+
+def test_c1_stats_match_oracle(vbx):
+    import synth
+    w = synth.config1()
+    params = dict(w.params)
+    pts = w.frame(0).copy()
+    pts[::17] = np.nan                       # invalid points
+    pts[5::23] *= 3.0                        # beyond max range
+    g = gpu_map(vbx, params)
+    o = oracle_map(params)
+    g.integrate(dev(pts), w.poses[0])
+    ost = o.integrate(pts, w.poses[0])
+    assert g.sync() == 0
+    st = g.stats()
+    for k_g, k_o in [("points", "points"), ("valid", "valid"), ("invalid", "invalid"),
+                     ("out_of_bounds", "out_of_bounds"), ("rays", "rays"), ("touches", "touches"),
+                     ("voxels", "voxels"), ("new_blocks", "new_blocks")]:
+        assert st[k_g] == ost[k_o], (k_g, st[k_g], ost[k_o])
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_room_sequence_grouped(vbx, storage):
+    """Several 320x240 frames of the furnished room (grouped, 1/z^2), frame by frame."""
+    import synth
+    poses, frame = synth.room_sequence(320, 240, 6, seed=synth.SEED_BASE + 11)
+    params = dict(voxel_size=0.05, trunc=0.15, max_range=5.0, weighting="quad", merge="grouped",
+                  storage=storage)
+    frames = [(frame(k), poses[k]) for k in range(6)]
+    log(f"room 320x240 x6 grouped {storage}")
+    g, o = run_both(vbx, params, frames)
+    compare_touches(g.last_touches(), o.last_touches())
+    res = compare_export(g.export(), o.export(), params, storage=storage)
+    log(f"  ok: {res}")
+
+
+def test_lidar_sweeps_simple(vbx):
+    import synth
+    w = synth.config3(n_sweeps=3, n_az=512)
+    params = dict(w.params)
+    frames = [(w.frame(k), w.poses[k]) for k in range(3)]
+    log("lidar 64x512 x3 simple const")
+    g, o = run_both(vbx, params, frames)
+    compare_touches(g.last_touches(), o.last_touches())
+    res = compare_export(g.export(), o.export(), params)
+    log(f"  ok: {res}")
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+def test_empty_and_invalid_frames(vbx):
+    params = dict(voxel_size=0.1, trunc=0.3, weighting="quad", merge="grouped")
+    g = gpu_map(vbx, params)
+    pose = np.eye(3, 4, dtype=np.float32)
+    g.integrate(dev(np.zeros((0, 3))), pose)
+    g.integrate(dev(np.full((1000, 3), np.nan)), pose)
+    assert g.sync() == 0
+    assert g.num_blocks() == 0
+    st = g.stats()
+    assert st["invalid"] == 1000 and st["rays"] == 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 511, 513, 1023, 1025, 4097])
+@pytest.mark.parametrize("merge", ["simple", "grouped"])
+def test_ragged_sizes(vbx, n, merge):
+    rng = np.random.default_rng(n)
+    pts = np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(0.5, 3, n)], 1)
+    pose = np.eye(3, 4, dtype=np.float32)
+    pose[:, 3] = [0.01, 0.02, 0.03]
+    params = dict(voxel_size=0.1, trunc=0.3, weighting="quad", merge=merge)
+    g, o = run_both(vbx, params, [(pts.astype(np.float32), pose)])
+    compare_touches(g.last_touches(), o.last_touches())
+    compare_export(g.export(), o.export(), params)
+
+
+def test_organised_hint_does_not_change_result(vbx):
+    import synth
+    poses, frame = synth.room_sequence(160, 120, 2, seed=synth.SEED_BASE + 12)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped")
+    a = gpu_map(vbx, params)
+    b = gpu_map(vbx, params)
+    a.integrate_frames([(dev(frame(k)), poses[k], 160) for k in range(2)])
+    b.integrate_frames([(dev(frame(k)), poses[k], 0) for k in range(2)])
+    assert a.sync() == 0 and b.sync() == 0
+    ca, da = a.export()
+    cb, db = b.export()
+    assert np.array_equal(ca, cb) and np.array_equal(da, db)
+
+
+def test_permutation_bit_identical(vbx):
+    import synth
+    w = synth.config1()
+    pts = w.frame(0)
+    perm = np.random.default_rng(3).permutation(pts.shape[0])
+    for merge in ("simple", "grouped"):
+        params = dict(w.params, weighting="quad", merge=merge)
+        a = gpu_map(vbx, params)
+        b = gpu_map(vbx, params)
+        a.integrate(dev(pts), w.poses[0])
+        b.integrate(dev(pts[perm]), w.poses[0])
+        assert a.sync() == 0 and b.sync() == 0
+        ca, da = a.export()
+        cb, db = b.export()
+        assert np.array_equal(ca, cb) and np.array_equal(da, db), merge
+
+
+def test_repeat_runs_bit_identical(vbx):
+    import synth
+    poses, frame = synth.room_sequence(320, 240, 3, seed=synth.SEED_BASE + 13)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped")
+    outs = []
+    for _ in range(2):
+        g = gpu_map(vbx, params)
+        g.integrate_frames([(dev(frame(k)), poses[k], 320) for k in range(3)])
+        assert g.sync() == 0
+        outs.append(g.export())
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
