@@ -73,7 +73,7 @@ typedef struct {
     float trunc;             /* delta, metres, > 0 (the paper uses 4v; 3v is common) */
     float w_max;             /* W_max of Eq. (4); <= 65504 for VBX_F16 */
     float max_range;         /* points farther than this from the sensor are rejected */
-    float z_min;             /* VBX_W_QUAD: points with depth z < z_min are rejected; >= 1e-3 */
+    float z_min;             /* VBX_W_QUAD: points with depth z < z_min are rejected; >= 0.05 */
     int32_t weighting;       /* vbx_weighting */
     int32_t merge;           /* vbx_merge */
     int32_t storage;         /* vbx_storage */
@@ -97,10 +97,11 @@ typedef struct {
     uint64_t points;        /* points submitted */
     uint64_t valid;         /* points that passed the validity tests */
     uint64_t invalid;       /* non-finite, zero range, beyond max_range, or z < z_min */
-    uint64_t out_of_bounds; /* rays whose band leaves the addressable voxel range */
+    uint64_t out_of_bounds; /* points or ray bands outside the addressable voxel range */
     uint64_t rays;          /* rays cast (points, or groups under VBX_MERGE_GROUPED) */
     uint64_t touches;       /* ray-voxel visits (voxel updates) */
     uint64_t voxels;        /* distinct (voxel, frame) pairs updated */
+    uint64_t cells;         /* distinct voxels updated per call, summed over calls */
     uint64_t new_blocks;    /* blocks allocated */
     uint64_t blocks;        /* blocks in the map */
     uint64_t calls;         /* integration calls that ran */
@@ -187,6 +188,26 @@ int vbx_map_stats(vbx_map* map, vbx_stats* out);
  * only cap are written).  Runs on the null stream and synchronises. */
 int vbx_debug_traverse(const float* A_dev, const float* B_dev, int n, int32_t* out_dev,
                        int cap, int32_t* counts_dev);
+
+/* Removes every block and restarts the statistics (stream-ordered, asynchronous).  The
+ * pool keeps its capacity; the next call allocates blocks from the start again. */
+int vbx_map_clear(vbx_map* map);
+
+/* Per-stage timing of integration calls.  While enabled, every call records HIP events on
+ * the map's stream around each pipeline stage (points, groups, cross, resolve, commit,
+ * bins, scan, scatter, update, finish); vbx_map_profile_read synchronises and returns the
+ * summed milliseconds and launch counts per stage since the last reset. */
+#define VBX_PROFILE_STAGES 10
+typedef struct {
+    double ms[VBX_PROFILE_STAGES];
+    uint64_t launches[VBX_PROFILE_STAGES];
+} vbx_profile;
+
+int vbx_map_profile(vbx_map* map, int enable);
+int vbx_map_profile_read(vbx_map* map, vbx_profile* out, int reset);
+
+/* Name of profile stage i (static string), NULL when out of range. */
+const char* vbx_profile_stage_name(int stage);
 
 /* Human-readable name of a status code (static string). */
 const char* vbx_status_string(int status);

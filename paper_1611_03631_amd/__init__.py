@@ -56,14 +56,21 @@ class Frame(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("points", "valid", "invalid", "out_of_bounds", "rays", "touches", "voxels",
-                 "new_blocks", "blocks", "calls")]
+                 "cells", "new_blocks", "blocks", "calls")]
 
 
 EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_map_destroy",
             "vbx_map_set_stream", "vbx_integrate", "vbx_integrate_batch", "vbx_integrate_frames",
             "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
-            "vbx_map_stats", "vbx_debug_traverse", "vbx_status_string"]
+            "vbx_map_stats", "vbx_debug_traverse", "vbx_status_string", "vbx_map_clear",
+            "vbx_map_profile", "vbx_map_profile_read", "vbx_profile_stage_name"]
+
+PROFILE_STAGES = 10
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * PROFILE_STAGES), ("launches", ctypes.c_uint64 * PROFILE_STAGES)]
 
 _lib = None
 
@@ -100,8 +107,14 @@ def lib(path: Optional[str] = None):
     L.vbx_debug_traverse.argtypes = [vp, vp, i32, vp, i32, vp]
     L.vbx_status_string.argtypes = [i32]
     L.vbx_status_string.restype = ctypes.c_char_p
+    L.vbx_map_clear.argtypes = [vp]
+    L.vbx_map_profile.argtypes = [vp, i32]
+    L.vbx_map_profile_read.argtypes = [vp, ctypes.POINTER(Profile), i32]
+    L.vbx_profile_stage_name.argtypes = [i32]
+    L.vbx_profile_stage_name.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("vbx_default_params", "vbx_map_destroy", "vbx_status_string"):
+        if name not in ("vbx_default_params", "vbx_map_destroy", "vbx_status_string",
+                        "vbx_profile_stage_name"):
             getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -240,6 +253,22 @@ class Map:
         _check(L.vbx_last_touches(self._h, coords.ctypes.data, counts.ctypes.data, T,
                                   ctypes.byref(n)), "vbx_last_touches")
         return coords, counts
+
+    def clear(self):
+        """Removes every block (stream-ordered)."""
+        _check(lib().vbx_map_clear(self._h), "vbx_map_clear")
+
+    def profile(self, enable: bool = True):
+        _check(lib().vbx_map_profile(self._h, 1 if enable else 0), "vbx_map_profile")
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{stage: (milliseconds, launches)} summed since the last reset (synchronises)."""
+        L = lib()
+        p = Profile()
+        _check(L.vbx_map_profile_read(self._h, ctypes.byref(p), 1 if reset else 0),
+               "vbx_map_profile_read")
+        return {L.vbx_profile_stage_name(i).decode(): (p.ms[i], int(p.launches[i]))
+                for i in range(PROFILE_STAGES)}
 
     def stats(self) -> dict:
         s = Stats()

@@ -61,8 +61,34 @@ struct Scratch {
 
 }  // namespace
 
+// Per-stage event timing of a map's calls.
+struct Profiler {
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    bool on = false;
+    std::vector<hipEvent_t> spare;
+    std::vector<Rec> pending;
+    double ms[VBX_PROFILE_STAGES] = {};
+    uint64_t launches[VBX_PROFILE_STAGES] = {};
+    hipEvent_t take() {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+enum { ST_POINTS, ST_GROUPS, ST_CROSS, ST_RESOLVE, ST_COMMIT, ST_BINS, ST_SCAN, ST_SCATTER, ST_UPDATE, ST_FINISH };
+
 struct vbx_map {
     vbx_map_params P;
+    Profiler prof;
     int device = 0;
     hipStream_t stream = nullptr;
     MapState* st = nullptr;       // device
@@ -326,6 +352,27 @@ int update_occupancy_grid() {
     return grid > 0 ? grid : 512;
 }
 
+// Records the start / end of a stage on the stream when profiling is on.
+struct StageTimer {
+    vbx_map* m;
+    hipStream_t st;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageTimer(vbx_map* m_, hipStream_t s_, int stage_) : m(m_), st(s_), stage(stage_) {
+        if (m->prof.on && (a = m->prof.take())) (void)hipEventRecord(a, st);
+    }
+    ~StageTimer() {
+        if (!a) return;
+        hipEvent_t b = m->prof.take();
+        if (!b) {
+            m->prof.spare.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, st);
+        m->prof.pending.push_back({stage, a, b});
+    }
+};
+
 // One integration call over `maps` (distinct maps sharing maps[0]'s scratch and stream) with
 // frames[i] belonging to maps[owner[i]]; frames of one map are in call order.
 int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
@@ -452,11 +499,16 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
         const int jb = chunks[c].first, je = chunks[c].second;
         if (chunk_tiles[c] == 0) continue;
         if (!plan.grouped) {
+            StageTimer tm(lead, st, ST_POINTS);
             hipLaunchKernelGGL(k_points_simple, dim3(chunk_tiles[c]), dim3(256), 0, st, d_jobs + jb, je - jb, jb,
                                d_maps, rays_p, rays_job, jst, cs, ray_cap);
         } else {
+            {
+            StageTimer tm(lead, st, ST_POINTS);
             hipLaunchKernelGGL(k_points_grouped, dim3(chunk_tiles[c]), dim3(256), 0, st, d_jobs + jb, je - jb, jb,
                                d_maps, (GroupEntry*)s->gtable.p, (u32)(s->gcap - 1), (u32*)s->occ.p, jst, cs);
+            }
+            StageTimer tm(lead, st, ST_GROUPS);
             size_t pts = 0;
             for (int i = jb; i < je; ++i) pts += jobs[i].n;
             hipLaunchKernelGGL(k_groups_to_rays, dim3(grid_for(pts, 1024)), dim3(256), 0, st, d_jobs + jb, jb, d_maps,
@@ -465,27 +517,47 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
         }
     }
     const unsigned G = grid_for(plan.total_points, 2048);
+    {
+    StageTimer tm(lead, st, ST_CROSS);
     hipLaunchKernelGGL(k_cross, dim3(G), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
                        (const u32*)rays_job, (u64*)s->tkeys.p, (u32)(s->tkey_cap - 1), (u32*)s->tlist.p,
                        (u32)s->tlist_cap, (uint2*)s->cross.p, (u32)s->cross_cap, jst, cs, ray_cap);
+    }
     const unsigned GT = grid_for(s->tlist_cap, 1024);
+    {
+    StageTimer tm(lead, st, ST_RESOLVE);
     hipLaunchKernelGGL(k_resolve, dim3(GT), dim3(256), 0, st, d_maps, (const u64*)s->tkeys.p, (u32*)s->tval.p,
                        (const u32*)s->tlist.p, (u64*)s->t_key.p, (int*)s->t_slot.p, cs);
+    }
+    {
+    StageTimer tm(lead, st, ST_COMMIT);
     hipLaunchKernelGGL(k_commit, dim3(GT), dim3(256), 0, st, d_maps, (const u64*)s->t_key.p, (int*)s->t_slot.p, cs);
+    }
     const u32 JM = (u32)plan.JM;
+    {
+    StageTimer tm(lead, st, ST_BINS);
     hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, d_jobs, (const uint2*)s->cross.p,
                        (const u32*)s->tval.p, (const u32*)rays_job, (u32*)s->bins.p, JM, cs);
+    }
     const unsigned NP = (unsigned)std::max<size_t>(s->nparts, 1);
+    {
+    StageTimer tm(lead, st, ST_SCAN);
     hipLaunchKernelGGL(k_scan_sums, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, JM, (u32*)s->partial.p,
                        (const CallState*)cs);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, (u32*)s->partial.p, (u32)NP, (u32*)s->off.p, JM,
                        (const CallState*)cs);
     hipLaunchKernelGGL(k_scan_final, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, (const u32*)s->partial.p,
                        (u32*)s->off.p, JM, (const CallState*)cs);
+    }
+    {
+    StageTimer tm(lead, st, ST_SCATTER);
     hipLaunchKernelGGL(k_scatter, dim3(G), dim3(256), 0, st, d_jobs, (const uint2*)s->cross.p, (const u32*)s->tval.p,
                        (const u32*)rays_job, (u32*)s->bins.p, (const u32*)s->off.p, JM, (u32*)s->sorted.p, cs);
+    }
     if (plan.keep_touches) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->touch_count, 0u);
     const int GU = update_occupancy_grid();
+    {
+    StageTimer tm(lead, st, ST_UPDATE);
     if (plan.storage == VBX_F32) {
         hipLaunchKernelGGL(k_update<0>, dim3(GU), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
                            (const u64*)s->t_key.p, (const int*)s->t_slot.p, (const u32*)s->off.p,
@@ -497,9 +569,13 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
                            (const u32*)s->sorted.p, JM, (u64*)s->touch_key.p, (u32*)s->touch_n.p,
                            (u32)s->touch_cap, plan.keep_touches ? 1 : 0, jst, cs);
     }
+    }
+    {
+    StageTimer tm(lead, st, ST_FINISH);
     hipLaunchKernelGGL(k_cleanup, dim3(grid_for(s->tkey_cap, 1024)), dim3(256), 0, st, (u64*)s->tkeys.p,
                        (u32)s->tkey_cap, (const u32*)s->tlist.p, (u32)s->tlist_cap, (const CallState*)cs);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, d_jobs, J, d_maps, M, jst, cs);
+    }
     if (hipGetLastError() != hipSuccess) return VBX_ERR_DEVICE;
     if (plan.keep_touches) {
         s->last_maps = maps;
@@ -596,6 +672,11 @@ int vbx_map_create(float voxel_size, float trunc, int weighting, vbx_map** out) 
 void vbx_map_destroy(vbx_map* m) {
     if (!m) return;
     (void)hipStreamSynchronize(m->stream);
+    for (auto& r : m->prof.pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : m->prof.spare) (void)hipEventDestroy(e);
     free_storage(m);
     (void)hipFree(m->st);
     free_scratch(m->scratch);
@@ -781,7 +862,7 @@ int vbx_export_blocks(vbx_map* m, int32_t* coords, float* dw, size_t cap, size_t
                     Dn = __half2float(__ushort_as_half((unsigned short)(raw & 0xFFFF)));
                     W = __half2float(__ushort_as_half((unsigned short)(raw >> 16)));
                 }
-                dw[2 * (b * 4096 + l)] = Dn * m->P.trunc;
+                dw[2 * (b * 4096 + l)] = m->P.storage == VBX_F32 ? Dn : Dn * m->P.trunc;
                 dw[2 * (b * 4096 + l) + 1] = W;
             }
         }
@@ -805,14 +886,14 @@ int vbx_import_blocks(vbx_map* m, const int32_t* coords, const float* dw, size_t
         if (bx < -lim || bx >= lim || by < -lim || by >= lim || bz < -lim || bz >= lim) return VBX_ERR_INVALID_ARG;
         host_insert(keys, slots, pack_block(bx, by, bz), (int)b);
         for (int l = 0; l < 4096; ++l) {
-            const float Dn = dw[2 * (b * 4096 + l)] / m->P.trunc;
+            const float D = dw[2 * (b * 4096 + l)];
             const float W = dw[2 * (b * 4096 + l) + 1];
             if (m->P.storage == VBX_F32) {
                 float* v = (float*)pool.data() + 2 * (b * 4096 + l);
-                v[0] = Dn;
+                v[0] = D;
                 v[1] = W;
             } else {
-                const uint32_t d = __half_as_ushort(__float2half_rn(Dn));
+                const uint32_t d = __half_as_ushort(__float2half_rn(D / m->P.trunc));
                 const uint32_t w = __half_as_ushort(__float2half_rn(W));
                 ((uint32_t*)pool.data())[b * 4096 + l] = d | (w << 16);
             }
@@ -881,6 +962,7 @@ int vbx_map_stats(vbx_map* m, vbx_stats* out) {
     out->rays = s.rays;
     out->touches = s.touches;
     out->voxels = s.voxels;
+    out->cells = s.cells;
     out->new_blocks = s.new_blocks;
     out->blocks = s.block_count;
     out->calls = s.calls;
@@ -897,6 +979,51 @@ int vbx_debug_traverse(const float* A_dev, const float* B_dev, int n, int32_t* o
     VBX_TRY(hipGetLastError());
     VBX_TRY(hipStreamSynchronize(nullptr));
     return VBX_OK;
+}
+
+int vbx_map_clear(vbx_map* m) {
+    if (!m) return VBX_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(m->hcap)), dim3(256), 0, m->stream, m->hkeys, kEmpty,
+                       (size_t)m->hcap);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, m->stream, (u32*)m->st, 0u,
+                       sizeof(MapState) / 4);
+    VBX_TRY(hipGetLastError());
+    return VBX_OK;
+}
+
+int vbx_map_profile(vbx_map* m, int enable) {
+    if (!m) return VBX_ERR_INVALID_ARG;
+    m->prof.on = enable != 0;
+    return VBX_OK;
+}
+
+int vbx_map_profile_read(vbx_map* m, vbx_profile* out, int reset) {
+    if (!m || !out) return VBX_ERR_INVALID_ARG;
+    VBX_TRY(hipStreamSynchronize(m->stream));
+    for (const Profiler::Rec& r : m->prof.pending) {
+        float ms = 0.0f;
+        VBX_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        m->prof.ms[r.stage] += ms;
+        m->prof.launches[r.stage] += 1;
+        m->prof.spare.push_back(r.a);
+        m->prof.spare.push_back(r.b);
+    }
+    m->prof.pending.clear();
+    for (int i = 0; i < VBX_PROFILE_STAGES; ++i) {
+        out->ms[i] = m->prof.ms[i];
+        out->launches[i] = m->prof.launches[i];
+        if (reset) {
+            m->prof.ms[i] = 0.0;
+            m->prof.launches[i] = 0;
+        }
+    }
+    return VBX_OK;
+}
+
+const char* vbx_profile_stage_name(int stage) {
+    static const char* names[VBX_PROFILE_STAGES] = {"points", "groups", "cross", "resolve", "commit",
+                                                    "bins", "scan", "scatter", "update", "finish"};
+    return stage >= 0 && stage < VBX_PROFILE_STAGES ? names[stage] : nullptr;
 }
 
 const char* vbx_status_string(int status) {

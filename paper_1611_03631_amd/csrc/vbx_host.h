@@ -9,7 +9,7 @@ namespace vbx {
 
 // Per-frame counters of one call (device, zeroed after every call).
 struct JobStat {
-    u64 valid, invalid, oob_pts, oob_rays, rays, touches, voxels, pad;
+    u64 valid, invalid, oob_pts, oob_rays, rays, touches, voxels, cells;
 };
 
 // Kernels (defined in vbx_kernels.hip).

@@ -40,7 +40,7 @@ struct MapDesc {
     int* hslots;                    //             pool slot per key
     u32 hmask;                      // hash capacity - 1
     u32 capacity;                   // pool capacity in blocks
-    void* pool;                     // [capacity][4096] float2 (F32) or u32 half pairs (F16)
+    void* pool;                     // [capacity][4096] float2 (F32: D metres, W) or u32 half pairs (F16: D/delta, W)
     struct MapState* st;
 };
 
@@ -50,7 +50,7 @@ struct MapState {
     u32 new_count;     // blocks pending in the current call
     int error;         // sticky vbx_status of the device side
     u32 pad;
-    u64 points, valid, invalid, oob, rays, touches, voxels, new_blocks, calls;
+    u64 points, valid, invalid, oob, rays, touches, voxels, cells, new_blocks, calls;
 };
 
 // One frame of a call.

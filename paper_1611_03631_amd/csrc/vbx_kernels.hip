@@ -707,13 +707,13 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
     __shared__ u64 a_d[4096];    // sum of fixed-point weight * distance/delta (two's complement)
     __shared__ u32 a_n[4096];    // rays
     __shared__ u32 s_t;
-    __shared__ u32 s_stat[2];
+    __shared__ u32 s_stat[3];
     __shared__ u32 s_tbase;
     __shared__ u32 lds8[4];
     for (int i = threadIdx.x; i < 4096; i += 256) { a_w[i] = 0; a_d[i] = 0; a_n[i] = 0; }
     const u32 nt = cs->error ? 0u : cs->t_count;
     for (;;) {
-        if (threadIdx.x == 0) { s_t = atomicAdd(&cs->work_next, 1u); s_stat[0] = 0; s_stat[1] = 0; }
+        if (threadIdx.x == 0) { s_t = atomicAdd(&cs->work_next, 1u); s_stat[0] = 0; s_stat[1] = 0; s_stat[2] = 0; }
         __syncthreads();
         const u32 t = s_t;
         if (t >= nt) break;
@@ -778,7 +778,10 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
                     const u64 sw_fx = a_w[l];
                     if (sw_fx) {
                         const float sw = (float)sw_fx * M.inv_wscale;
-                        const float swd = (float)(i64)a_d[l] * M.inv_wscale;
+                        // sums are in units of delta; binary32 storage keeps D in metres,
+                        // binary16 storage keeps D / delta
+                        float swd = (float)(i64)a_d[l] * M.inv_wscale;
+                        if (STORAGE == 0) swd = swd * M.delta;
                         float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
                         float Wn = W[j] + sw;
                         if (Wn > M.w_max) Wn = M.w_max;
@@ -799,7 +802,14 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
         }
 #pragma unroll
         for (int j = 0; j < 16; ++j) store_voxel<STORAGE>(pool, vbase + threadIdx.x + 256 * j, D[j], W[j]);
-        if (stat_vox) { atomicAdd(&s_stat[0], stat_vox); atomicAdd(&s_stat[1], stat_touch); }
+        if (stat_vox) {
+            u32 cells = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) cells += ntot[j] ? 1u : 0u;
+            atomicAdd(&s_stat[0], stat_vox);
+            atomicAdd(&s_stat[1], stat_touch);
+            atomicAdd(&s_stat[2], cells);
+        }
         if (keep_touches) {
             u32 mine = 0;
 #pragma unroll
@@ -826,6 +836,7 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
         if (threadIdx.x == 0 && s_stat[0]) {
             atomicAdd(&jst[M.job0].voxels, (u64)s_stat[0]);
             atomicAdd(&jst[M.job0].touches, (u64)s_stat[1]);
+            atomicAdd(&jst[M.job0].cells, (u64)s_stat[2]);
         }
         __syncthreads();
     }
@@ -876,6 +887,7 @@ __global__ __launch_bounds__(1024) void k_finish(const Job* __restrict__ jobs, i
                     st->rays += s.rays - s.oob_rays;
                     st->touches += s.touches;
                     st->voxels += s.voxels;
+                    st->cells += s.cells;
                 }
             }
             if (cs->error != 0 && st->error == 0) st->error = cs->error;
@@ -891,7 +903,7 @@ __global__ __launch_bounds__(1024) void k_finish(const Job* __restrict__ jobs, i
     __syncthreads();
     for (int j = threadIdx.x; j < njobs; j += blockDim.x) {
         JobStat z;
-        z.valid = z.invalid = z.oob_pts = z.oob_rays = z.rays = z.touches = z.voxels = z.pad = 0;
+        z.valid = z.invalid = z.oob_pts = z.oob_rays = z.rays = z.touches = z.voxels = z.cells = 0;
         jst[j] = z;
     }
 }

@@ -1,0 +1,178 @@
+"""API-level guarantees of the GPU library, checked on the GPU through the C ABI."""
+import numpy as np
+import pytest
+
+from tests.common import compare_export, compare_touches, gpu_map, log, oracle_map
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vbx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1611_03631_amd as vbx
+    vbx.lib()
+    return vbx
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def same_export(a, b):
+    ca, da = a.export()
+    cb, db = b.export()
+    return np.array_equal(ca, cb) and np.array_equal(da, db)
+
+
+def room(w, h, n, seed):
+    import synth
+    poses, frame = synth.room_sequence(w, h, n, seed=synth.SEED_BASE + seed)
+    return [(frame(k), poses[k]) for k in range(n)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("merge", ["simple", "grouped"])
+def test_batch_equals_sequential(vbx, storage, merge):
+    frames = room(320, 240, 5, 21)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge=merge, storage=storage,
+                  w_max=2000.0)     # low cap so that saturation happens inside the batch
+    seq = gpu_map(vbx, params)
+    bat = gpu_map(vbx, params)
+    bat2 = gpu_map(vbx, params)
+    for p, pose in frames:
+        seq.integrate(dev(p), pose)
+    bat.integrate_frames([(dev(p), pose, 320) for p, pose in frames])
+    bat2.integrate_batch([dev(p) for p, _ in frames], np.stack([q for _, q in frames]))
+    assert seq.sync() == 0 and bat.sync() == 0 and bat2.sync() == 0
+    assert same_export(seq, bat) and same_export(seq, bat2)
+    o = oracle_map(params)
+    for p, pose in frames:
+        o.integrate(p, pose)
+    compare_export(bat.export(), o.export(), params, storage=storage)
+
+
+def test_multi_equals_alone(vbx):
+    import synth
+    specs = [(160, 120, 0.02), (320, 240, 0.05), (640, 480, 0.10), (320, 240, 0.02), (160, 120, 0.10)]
+    alone, multi, frames = [], [], []
+    for i, (w, h, v) in enumerate(specs):
+        poses, frame = synth.room_sequence(w, h, 2, seed=synth.SEED_BASE + 100 + i, phase=0.3 * i)
+        params = dict(voxel_size=v, trunc=3 * v, weighting="quad", merge="grouped", block_capacity=8192)
+        frames.append([(frame(k), poses[k], w) for k in range(2)])
+        alone.append(gpu_map(vbx, params))
+        multi.append(gpu_map(vbx, params))
+    for k in range(2):
+        for i in range(len(specs)):
+            p, pose, wd = frames[i][k]
+            alone[i].integrate_frames([(dev(p), pose, wd)])
+        vbx.integrate_multi(multi, [(dev(frames[i][k][0]), frames[i][k][1], frames[i][k][2])
+                                    for i in range(len(specs))])
+    for a, b in zip(alone, multi):
+        assert a.sync() == 0 and b.sync() == 0
+        assert same_export(a, b)
+        ta, tb = a.last_touches(), b.last_touches()
+        assert sorted(zip(map(tuple, ta[0].tolist()), ta[1].tolist())) == \
+            sorted(zip(map(tuple, tb[0].tolist()), tb[1].tolist()))
+
+
+def test_pool_full_leaves_map_unchanged_then_reserve(vbx):
+    frames = room(160, 120, 2, 31)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped", block_capacity=64)
+    g = gpu_map(vbx, params)
+    g.integrate(dev(frames[0][0][:200]), frames[0][1])        # a few blocks only
+    assert g.sync() == 0
+    before = g.export()
+    nb = before[0].shape[0]
+    assert 0 < nb < 64
+    g.integrate(dev(frames[1][0]), frames[1][1])               # needs more than 64 blocks
+    assert g.sync() == vbx.ERR_POOL_FULL
+    after = g.export()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    g.integrate(dev(frames[0][0][:200]), frames[0][1])          # skipped while the error is set
+    assert g.sync() == vbx.ERR_POOL_FULL
+    assert np.array_equal(g.export()[1], before[1])
+    g.reserve(4096)
+    assert g.sync() == 0
+    assert np.array_equal(g.export()[1], before[1])
+    g.integrate(dev(frames[1][0]), frames[1][1])
+    assert g.sync() == 0
+    o = oracle_map(params)
+    o.integrate(frames[0][0][:200], frames[0][1])
+    o.integrate(frames[1][0], frames[1][1])
+    compare_export(g.export(), o.export(), params)
+
+
+def test_export_import_roundtrip(vbx):
+    frames = room(320, 240, 4, 41)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped")
+    a = gpu_map(vbx, params)
+    for p, pose in frames[:3]:
+        a.integrate(dev(p), pose)
+    coords, dw = a.export()
+    b = gpu_map(vbx, params)
+    b.import_blocks(coords, dw)
+    assert same_export(a, b)
+    a.integrate(dev(frames[3][0]), frames[3][1])
+    b.integrate(dev(frames[3][0]), frames[3][1])
+    assert a.sync() == 0 and b.sync() == 0
+    assert same_export(a, b)
+
+
+def test_clear_and_reserve(vbx):
+    frames = room(160, 120, 3, 51)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped", block_capacity=2048)
+    a = gpu_map(vbx, params)
+    for p, pose in frames:
+        a.integrate(dev(p), pose)
+    a.clear()
+    for p, pose in frames[:2]:
+        a.integrate(dev(p), pose)
+    a.reserve(6000)
+    a.integrate(dev(frames[2][0]), frames[2][1])
+    fresh = gpu_map(vbx, dict(params, block_capacity=8192))
+    for p, pose in frames:
+        fresh.integrate(dev(p), pose)
+    assert a.sync() == 0 and fresh.sync() == 0
+    assert same_export(a, fresh)
+    assert a.stats()["calls"] == 3
+
+
+def test_profile_records_every_stage(vbx):
+    frames = room(160, 120, 2, 61)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped")
+    a = gpu_map(vbx, params)
+    a.profile(True)
+    a.integrate_frames([(dev(p), pose, 160) for p, pose in frames])
+    prof = a.profile_read()
+    for stage in ("points", "groups", "cross", "resolve", "commit", "bins", "scan", "scatter",
+                  "update", "finish"):
+        assert prof[stage][1] >= 1 and prof[stage][0] > 0, stage
+
+
+def test_full_sequence_640x480x100_bench_configuration(vbx):
+    """The benchmark workload at full size, in the launch configuration the benchmark times
+    (one call over all 100 organised frames), against the oracle integrating frame by frame."""
+    from concurrent.futures import ThreadPoolExecutor
+    import synth
+    w = synth.config2(n_frames=100)
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        frames = list(ex.map(w.frame, range(100)))
+    P = dict(w.params)
+    log("c2 640x480x100 grouped quad f32: GPU")
+    host = np.stack(frames)
+    d = dev(host)
+    g = gpu_map(vbx, dict(P, block_capacity=16384, keep_touches=False))
+    g.integrate_frames([(d[k], w.poses[k], 640) for k in range(100)])
+    assert g.sync() == 0
+    log("c2: oracle")
+    o = oracle_map(P)
+    for k in range(100):
+        o.integrate(frames[k], w.poses[k])
+    res = compare_export(g.export(), o.export(), P)
+    log(f"  ok: {res}")
+    st = g.stats()
+    assert st["points"] == 100 * 640 * 480
