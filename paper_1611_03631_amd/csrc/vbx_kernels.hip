@@ -198,6 +198,8 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     __shared__ u64 s_sq[3][kGroupSlots];
     __shared__ u32 s_n[kGroupSlots];
     __shared__ u32 s_idx[kGroupSlots];
+    __shared__ u32 s_new[kTileGrouped];   // table entries this tile created
+    __shared__ u32 s_nnew, s_occ_base;
     __shared__ u32 s_cnt[3];
     const int jloc = job_of_tile(jobs, njobs, blockIdx.x);
     const int jid = job_base + jloc;
@@ -207,6 +209,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         s_key[i] = kEmpty; s_so[i] = 0; s_sq[0][i] = 0; s_sq[1][i] = 0; s_sq[2][i] = 0; s_n[i] = 0;
     }
     if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_nnew = 0;
     __syncthreads();
 
     const u32 tile = blockIdx.x - J.tile0;
@@ -255,7 +258,8 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     if (n_oob) atomicAdd(&s_cnt[2], n_oob);
     __syncthreads();
 
-    // merge the tile's partial groups into the global table of this chunk of frames
+    // merge the tile's partial groups into the global table of this chunk of frames; new
+    // table entries are listed in LDS and appended to the occupied list with one atomic
     const u64 tag = (u64)jloc << 57;
     for (int s = threadIdx.x; s < kGroupSlots; s += 256) {
         const u64 key = s_key[s];
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         u32 h = (u32)mix64(gk) & tmask;
         for (;;) {
             u64 old = atomicCAS(&table[h].key, kEmpty, gk);
-            if (old == kEmpty) { occ[atomicAdd(&cs->occ_count, 1u)] = h; break; }
+            if (old == kEmpty) { s_new[atomicAdd(&s_nnew, 1u)] = h; break; }
             if (old == gk) break;
             h = (h + 1) & tmask;
         }
@@ -280,6 +284,10 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         atomicAdd(&E->n, n);
         if (n == 1) E->idx = s_idx[s];
     }
+    __syncthreads();
+    if (threadIdx.x == 0) s_occ_base = s_nnew ? atomicAdd(&cs->occ_count, s_nnew) : 0u;
+    __syncthreads();
+    for (u32 k = threadIdx.x; k < s_nnew; k += 256) occ[s_occ_base + k] = s_new[k];
     if (threadIdx.x == 0) {
         if (s_cnt[0]) atomicAdd(&jst[jid].valid, (u64)s_cnt[0]);
         if (s_cnt[1]) atomicAdd(&jst[jid].invalid, (u64)s_cnt[1]);
@@ -383,6 +391,26 @@ __device__ inline u32 tset_insert(u64* tkeys, u32 tmask, u64 key, u32* tlist, u3
     return 0xFFFFFFFFu;
 }
 
+// Per workgroup of 256 rays, in three phases separated by barriers:
+//  1. walk every ray, count its block crossings and enter the block keys in an LDS set;
+//  2. insert each distinct block of the workgroup once into the per-call block set;
+//  3. walk again and write the crossings at a range reserved with one global atomic.
+constexpr int kCrossSlots = 2048;   // LDS block-key set (at most 256 rays x 7 blocks)
+
+__device__ inline u32 lds_set_insert(u64* keys, u64 key) {
+    u32 h = (u32)mix64(key) & (kCrossSlots - 1);
+    for (;;) {
+        const u64 old = atomicCAS(&keys[h], kEmpty, key);
+        if (old == kEmpty || old == key) return h;
+        h = (h + 1) & (kCrossSlots - 1);
+    }
+}
+__device__ inline u32 lds_set_find(const u64* keys, u64 key) {
+    u32 h = (u32)mix64(key) & (kCrossSlots - 1);
+    while (keys[h] != key) h = (h + 1) & (kCrossSlots - 1);
+    return h;
+}
+
 __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                                                const MapDesc* __restrict__ maps,
                                                const float4* __restrict__ rays_p,
@@ -392,41 +420,84 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                                                uint2* __restrict__ cross, u32 cross_cap,
                                                JobStat* __restrict__ jst,
                                                CallState* __restrict__ cs, u32 ray_cap) {
+    __shared__ u64 s_key[kCrossSlots];
+    __shared__ u32 s_h[kCrossSlots];
+    __shared__ u32 lds8[4];
+    __shared__ u32 s_base;
     const u32 nrays = cs->ray_count < ray_cap ? cs->ray_count : ray_cap;
     for (u32 base = blockIdx.x * 256u; base < nrays; base += gridDim.x * 256u) {
+        for (int i = threadIdx.x; i < kCrossSlots; i += 256) s_key[i] = kEmpty;
+        __syncthreads();
         const u32 i = base + threadIdx.x;
-        bool oob = false;
+        bool ok = false;
         u32 jid = 0;
+        float p[3] = {0.f, 0.f, 0.f}, s[3] = {0.f, 0.f, 0.f};
+        u64 mapbits = 0;
+        const MapDesc* Mp = maps;
         if (i < nrays) {
             jid = rays_job[i];
             const Job& J = jobs[jid];
-            const MapDesc& M = maps[J.map];
+            Mp = &maps[J.map];
             const float4 rp = rays_p[i];
-            const float p[3] = {rp.x, rp.y, rp.z};
-            const float s[3] = {J.pose[3], J.pose[7], J.pose[11]};
+            p[0] = rp.x; p[1] = rp.y; p[2] = rp.z;
+            s[0] = J.pose[3]; s[1] = J.pose[7]; s[2] = J.pose[11];
+            mapbits = (u64)Mp->map_id << 45;
             float e[3], r;
             Walk w;
-            if (!walk_setup(M, p, s, e, r, w)) {
-                oob = true;
-            } else {
-                const u64 mapbits = (u64)M.map_id << 45;
-                u64 cur = kEmpty;
-                for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
-                    const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
-                    if (bk != cur) {
-                        cur = bk;
-                        const u32 h = tset_insert(tkeys, tmask, mapbits | bk, tlist, tlist_cap, cs);
-                        if (h != 0xFFFFFFFFu) {
-                            const u32 c = atomicAdd(&cs->cross_count, 1u);
-                            if (c < cross_cap) cross[c] = make_uint2(h, i); else cs->error = -4;
-                        }
-                    }
-                    if (w.left == 0) break;
-                    walk_step(w);
+            ok = walk_setup(*Mp, p, s, e, r, w);
+        }
+        // phase 1
+        u32 ncross = 0;
+        if (ok) {
+            float e[3], r;
+            Walk w;
+            walk_setup(*Mp, p, s, e, r, w);
+            u64 cur = kEmpty;
+            for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
+                const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
+                if (bk != cur) {
+                    cur = bk;
+                    lds_set_insert(s_key, mapbits | bk);
+                    ncross++;
                 }
+                if (w.left == 0) break;
+                walk_step(w);
+            }
+        }
+        u32 tot;
+        const u32 incl = block_scan_256(ncross, lds8, &tot);
+        if (threadIdx.x == 0) {
+            const u32 b0 = atomicAdd(&cs->cross_count, tot);
+            if ((u64)b0 + tot > cross_cap) cs->error = -4;
+            s_base = b0;
+        }
+        // phase 2
+        for (int k = threadIdx.x; k < kCrossSlots; k += 256) {
+            const u64 key = s_key[k];
+            if (key != kEmpty) s_h[k] = tset_insert(tkeys, tmask, key, tlist, tlist_cap, cs);
+        }
+        __syncthreads();
+        // phase 3
+        if (ok) {
+            u32 pos = s_base + incl - ncross;
+            float e[3], r;
+            Walk w;
+            walk_setup(*Mp, p, s, e, r, w);
+            u64 cur = kEmpty;
+            for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
+                const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
+                if (bk != cur) {
+                    cur = bk;
+                    const u32 h = s_h[lds_set_find(s_key, mapbits | bk)];
+                    if (pos < cross_cap && h != 0xFFFFFFFFu) cross[pos] = make_uint2(h, i);
+                    pos++;
+                }
+                if (w.left == 0) break;
+                walk_step(w);
             }
         }
         // out-of-bounds rays per frame (rare); rays were counted when created
+        const bool oob = i < nrays && !ok;
         u64 pending = __ballot(oob);
         const int lane = lane_id();
         while (pending) {
@@ -436,6 +507,7 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
             if (lane == leader) atomicAdd(&jst[k].oob_rays, (u64)__popcll(grp));
             pending &= ~grp;
         }
+        __syncthreads();
     }
 }
 
@@ -657,11 +729,34 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ jobs,
                                                  u32 JM, u32* __restrict__ sorted,
                                                  CallState* __restrict__ cs) {
     const u32 nc = cs->error ? 0u : cs->cross_count;
-    for (u32 i = blockIdx.x * 256u + threadIdx.x; i < nc; i += gridDim.x * 256u) {
-        const uint2 c = cross[i];
-        const u32 b = tval[c.x] * JM + jobs[rays_job[c.y]].jm;
-        const u32 pos = off[b] + atomicSub(&bins[b], 1u) - 1u;
-        sorted[pos] = c.y;
+    const int lane = lane_id();
+    for (u32 base = blockIdx.x * 256u; base < nc; base += gridDim.x * 256u) {
+        const u32 i = base + threadIdx.x;
+        const bool act = i < nc;
+        u32 b = 0, ray = 0;
+        if (act) {
+            const uint2 c = cross[i];
+            ray = c.y;
+            b = tval[c.x] * JM + jobs[rays_job[ray]].jm;
+        }
+        // lanes sharing a bin take consecutive positions reserved by one atomic
+        u64 pending = __ballot(act);
+        u32 pos = 0;
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const u32 kb = __shfl(b, leader);
+            const bool mine = ((pending >> lane) & 1ull) && b == kb;
+            const u64 grp = __ballot(mine);
+            u32 old = 0;
+            if (lane == leader) old = atomicSub(&bins[kb], (u32)__popcll(grp));
+            old = __shfl(old, leader);
+            if (mine) {
+                const u32 rank = (u32)__popcll(grp & ((1ull << lane) - 1ull));
+                pos = off[kb] + old - 1u - rank;
+            }
+            pending &= ~grp;
+        }
+        if (act) sorted[pos] = ray;
     }
 }
 
