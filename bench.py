@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="wall-clock budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch tuning instead of timing the candidates first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -110,6 +112,12 @@ def main():
         rc = L.vbx_integrate_frames(m.handle, frames_arr, F)
         if rc != 0:
             raise vbx.VbxError(rc, "vbx_integrate_frames")
+
+    # ---------------------------------------------------------------- tuning (untimed)
+    tune = None
+    if not args.no_autotune:
+        tune = m.autotune(batch)
+        tune["ms"] = [round(x, 4) for x in tune["ms"]]
 
     # ---------------------------------------------------------------- warm-up
     for _ in range(args.warmup):
@@ -216,6 +224,8 @@ def main():
         "whole_step_algorithmic_GBps": round(whole, 1),
         "stage_ms_per_step": stages,
         "wall_s": round(wall_s, 3),
+        "tuning": m.tuning(),
+        "autotune": tune,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "input_generation_s": round(gen_s, 1),

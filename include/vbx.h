@@ -209,6 +209,24 @@ int vbx_map_profile_read(vbx_map* map, vbx_profile* out, int reset);
 /* Name of profile stage i (static string), NULL when out of range. */
 const char* vbx_profile_stage_name(int stage);
 
+/* Launch tuning of a map's calls.  Results never depend on it. */
+#define VBX_TUNING_CANDIDATES 3
+typedef struct {
+    int32_t update_split;   /* z-slabs per block in the update stage: 1, 2 or 4 (default 2) */
+    int32_t reserved[7];
+} vbx_tuning;
+
+int vbx_map_get_tuning(vbx_map* map, vbx_tuning* out);
+int vbx_map_set_tuning(vbx_map* map, const vbx_tuning* tuning);
+
+/* Autotuner: times the integration of frames[0..F) under every candidate tuning on a
+ * scratch map with the same parameters (the map itself is not modified), keeps the fastest
+ * in the map and writes it to *best (may be NULL).  ms_out (may be NULL, at least
+ * VBX_TUNING_CANDIDATES entries) receives each candidate's mean time per call.
+ * Synchronises. */
+int vbx_map_autotune(vbx_map* map, const vbx_frame* frames, int F, vbx_tuning* best,
+                     double* ms_out);
+
 /* Human-readable name of a status code (static string). */
 const char* vbx_status_string(int status);
 

@@ -64,7 +64,14 @@ EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_ma
             "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
             "vbx_map_stats", "vbx_debug_traverse", "vbx_status_string", "vbx_map_clear",
-            "vbx_map_profile", "vbx_map_profile_read", "vbx_profile_stage_name"]
+            "vbx_map_profile", "vbx_map_profile_read", "vbx_profile_stage_name",
+            "vbx_map_get_tuning", "vbx_map_set_tuning", "vbx_map_autotune"]
+
+TUNING_CANDIDATES = 3
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("update_split", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 PROFILE_STAGES = 10
 
@@ -110,6 +117,9 @@ def lib(path: Optional[str] = None):
     L.vbx_map_clear.argtypes = [vp]
     L.vbx_map_profile.argtypes = [vp, i32]
     L.vbx_map_profile_read.argtypes = [vp, ctypes.POINTER(Profile), i32]
+    L.vbx_map_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.vbx_map_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.vbx_map_autotune.argtypes = [vp, ctypes.POINTER(Frame), i32, ctypes.POINTER(Tuning), vp]
     L.vbx_profile_stage_name.argtypes = [i32]
     L.vbx_profile_stage_name.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -269,6 +279,26 @@ class Map:
                "vbx_map_profile_read")
         return {L.vbx_profile_stage_name(i).decode(): (p.ms[i], int(p.launches[i]))
                 for i in range(PROFILE_STAGES)}
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().vbx_map_get_tuning(self._h, ctypes.byref(t)), "vbx_map_get_tuning")
+        return {"update_split": int(t.update_split)}
+
+    def set_tuning(self, update_split: int):
+        t = Tuning()
+        t.update_split = update_split
+        _check(lib().vbx_map_set_tuning(self._h, ctypes.byref(t)), "vbx_map_set_tuning")
+
+    def autotune(self, frames) -> dict:
+        """Times every candidate tuning on a scratch map and keeps the fastest.
+        Returns {"best": tuning dict, "ms": [per-candidate ms]}."""
+        arr = make_frames(frames)
+        best = Tuning()
+        ms = (ctypes.c_double * TUNING_CANDIDATES)()
+        _check(lib().vbx_map_autotune(self._h, arr, len(frames), ctypes.byref(best), ms),
+               "vbx_map_autotune")
+        return {"best": {"update_split": int(best.update_split)}, "ms": list(ms)}
 
     def stats(self) -> dict:
         s = Stats()

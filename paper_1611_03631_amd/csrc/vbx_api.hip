@@ -103,6 +103,7 @@ struct vbx_map {
     Scratch* scratch = nullptr;
     Scratch* touch_src = nullptr; // scratch holding this map's last touches
     int touch_idx = 0;
+    int update_split = 2;         // z-slabs per block in the update kernel (1, 2 or 4)
 };
 
 namespace {
@@ -280,7 +281,7 @@ int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, si
     GROW(s->rays_p, ray_cap * sizeof(float4));
     GROW(s->rays_job, ray_cap * sizeof(u32));
     GROW(s->cross, cross_cap * sizeof(uint2));
-    GROW(s->sorted, cross_cap * sizeof(u32));
+    GROW(s->sorted, cross_cap * sizeof(float4));
     if ((r = grow(s->tkeys, tkey_cap * sizeof(u64))) < 0) return VBX_ERR_OUT_OF_MEMORY;
     if (r == 1 || s->tkey_cap != tkey_cap) {
         hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(tkey_cap)), dim3(256), 0, st, (u64*)s->tkeys.p,
@@ -337,19 +338,43 @@ int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, si
     return VBX_OK;
 }
 
-int update_occupancy_grid() {
+// Persistent grid of an update-kernel variant: one workgroup per slot the chip can hold.
+template <int STORAGE, int SPLIT>
+int update_grid() {
     static int grid = 0;
     static std::once_flag once;
     std::call_once(once, [] {
-        int dev = 0, cus = 256, per = 2;
+        int dev = 0, cus = 256, per = 1;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_update<0>), 256, 0) !=
-                hipSuccess || per < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per, reinterpret_cast<const void*>(&k_update<STORAGE, SPLIT>), 256, 0) != hipSuccess ||
+            per < 1)
             per = 1;
         grid = cus * per;
     });
-    return grid > 0 ? grid : 512;
+    return grid > 0 ? grid : 256;
+}
+
+template <int STORAGE, int SPLIT>
+void launch_update_t(hipStream_t st, const Job* jobs, const MapDesc* maps, const u64* t_key,
+                     const int* t_slot, const u32* off, const float4* sorted, u32 JM, u64* touch_key,
+                     u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
+    hipLaunchKernelGGL((k_update<STORAGE, SPLIT>), dim3(update_grid<STORAGE, SPLIT>()), dim3(256), 0, st,
+                       jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep,
+                       jst, cs);
+}
+
+void launch_update(int storage, int split, hipStream_t st, const Job* jobs, const MapDesc* maps,
+                   const u64* t_key, const int* t_slot, const u32* off, const float4* sorted, u32 JM,
+                   u64* touch_key, u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
+#define VBX_UPD(S, P) launch_update_t<S, P>(st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep, jst, cs)
+    if (storage == VBX_F32) {
+        if (split == 1) VBX_UPD(0, 1); else if (split == 4) VBX_UPD(0, 4); else VBX_UPD(0, 2);
+    } else {
+        if (split == 1) VBX_UPD(1, 1); else if (split == 4) VBX_UPD(1, 4); else VBX_UPD(1, 2);
+    }
+#undef VBX_UPD
 }
 
 // Records the start / end of a stage on the stream when profiling is on.
@@ -552,23 +577,16 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     {
     StageTimer tm(lead, st, ST_SCATTER);
     hipLaunchKernelGGL(k_scatter, dim3(G), dim3(256), 0, st, d_jobs, (const uint2*)s->cross.p, (const u32*)s->tval.p,
-                       (const u32*)rays_job, (u32*)s->bins.p, (const u32*)s->off.p, JM, (u32*)s->sorted.p, cs);
+                       (const u32*)rays_job, (u32*)s->bins.p, (const u32*)s->off.p, JM, (const float4*)rays_p,
+                       (float4*)s->sorted.p, cs);
     }
     if (plan.keep_touches) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->touch_count, 0u);
-    const int GU = update_occupancy_grid();
     {
     StageTimer tm(lead, st, ST_UPDATE);
-    if (plan.storage == VBX_F32) {
-        hipLaunchKernelGGL(k_update<0>, dim3(GU), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
-                           (const u64*)s->t_key.p, (const int*)s->t_slot.p, (const u32*)s->off.p,
-                           (const u32*)s->sorted.p, JM, (u64*)s->touch_key.p, (u32*)s->touch_n.p,
-                           (u32)s->touch_cap, plan.keep_touches ? 1 : 0, jst, cs);
-    } else {
-        hipLaunchKernelGGL(k_update<1>, dim3(GU), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
-                           (const u64*)s->t_key.p, (const int*)s->t_slot.p, (const u32*)s->off.p,
-                           (const u32*)s->sorted.p, JM, (u64*)s->touch_key.p, (u32*)s->touch_n.p,
-                           (u32)s->touch_cap, plan.keep_touches ? 1 : 0, jst, cs);
-    }
+    launch_update(plan.storage, lead->update_split, st, d_jobs, d_maps, (const u64*)s->t_key.p,
+                  (const int*)s->t_slot.p, (const u32*)s->off.p, (const float4*)s->sorted.p, JM,
+                  (u64*)s->touch_key.p, (u32*)s->touch_n.p, (u32)s->touch_cap, plan.keep_touches ? 1 : 0,
+                  jst, cs);
     }
     {
     StageTimer tm(lead, st, ST_FINISH);
@@ -640,6 +658,10 @@ int vbx_map_create_ex(const vbx_map_params* params, vbx_map** out) {
     m->wbits = weight_bits(m->P);
     m->kw = sum_bits(m->P);
     m->scratch = new (std::nothrow) Scratch();
+    if (const char* e = std::getenv("VBX_UPDATE_SPLIT")) {
+        const int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4) m->update_split = v;
+    }
     if (!m->scratch || hipMalloc(&m->st, sizeof(MapState)) != hipSuccess) {
         delete m->scratch;
         delete m;
@@ -1024,6 +1046,63 @@ const char* vbx_profile_stage_name(int stage) {
     static const char* names[VBX_PROFILE_STAGES] = {"points", "groups", "cross", "resolve", "commit",
                                                     "bins", "scan", "scatter", "update", "finish"};
     return stage >= 0 && stage < VBX_PROFILE_STAGES ? names[stage] : nullptr;
+}
+
+int vbx_map_get_tuning(vbx_map* m, vbx_tuning* out) {
+    if (!m || !out) return VBX_ERR_INVALID_ARG;
+    std::memset(out, 0, sizeof *out);
+    out->update_split = m->update_split;
+    return VBX_OK;
+}
+
+int vbx_map_set_tuning(vbx_map* m, const vbx_tuning* t) {
+    if (!m || !t) return VBX_ERR_INVALID_ARG;
+    if (t->update_split != 1 && t->update_split != 2 && t->update_split != 4) return VBX_ERR_INVALID_ARG;
+    m->update_split = t->update_split;
+    return VBX_OK;
+}
+
+int vbx_map_autotune(vbx_map* m, const vbx_frame* frames, int F, vbx_tuning* best, double* ms_out) {
+    if (!m || F <= 0 || !frames) return VBX_ERR_INVALID_ARG;
+    static const int splits[VBX_TUNING_CANDIDATES] = {1, 2, 4};
+    vbx_map_params p = m->P;
+    p.flags &= ~(uint32_t)VBX_FLAG_KEEP_TOUCHES;
+    vbx_map* tmp = nullptr;
+    int rc = vbx_map_create_ex(&p, &tmp);
+    if (rc != VBX_OK) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        vbx_map_destroy(tmp);
+        return VBX_ERR_DEVICE;
+    }
+    double best_ms = 1e300;
+    int best_split = m->update_split;
+    const int reps = 3;
+    for (int c = 0; c < VBX_TUNING_CANDIDATES && rc == VBX_OK; ++c) {
+        tmp->update_split = splits[c];
+        // one untimed pass (scratch growth, first-touch), then the timed passes
+        if ((rc = vbx_map_clear(tmp)) != VBX_OK || (rc = vbx_integrate_frames(tmp, frames, F)) != VBX_OK) break;
+        (void)hipEventRecord(e0, tmp->stream);
+        for (int r = 0; r < reps && rc == VBX_OK; ++r) {
+            if ((rc = vbx_map_clear(tmp)) == VBX_OK) rc = vbx_integrate_frames(tmp, frames, F);
+        }
+        (void)hipEventRecord(e1, tmp->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = VBX_ERR_DEVICE; break; }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double per = (double)ms / reps;
+        if (ms_out) ms_out[c] = per;
+        MapState s;
+        if (read_state(tmp, &s) != VBX_OK || s.error != 0) { rc = s.error ? s.error : VBX_ERR_DEVICE; break; }
+        if (per < best_ms) { best_ms = per; best_split = splits[c]; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    vbx_map_destroy(tmp);
+    if (rc != VBX_OK) return rc;
+    m->update_split = best_split;
+    if (best) vbx_map_get_tuning(m, best);
+    return VBX_OK;
 }
 
 const char* vbx_status_string(int status) {

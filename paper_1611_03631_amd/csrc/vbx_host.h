@@ -39,12 +39,12 @@ __global__ void k_scan_partials(u32* partial, u32 nparts, u32* off, u32 JM, cons
 __global__ void k_scan_final(const u32* bins, const u32* partial, u32* off, u32 JM,
                              const CallState* cs);
 __global__ void k_scatter(const Job* jobs, const uint2* cross, const u32* tval,
-                          const u32* rays_job, u32* bins, const u32* off, u32 JM, u32* sorted,
-                          CallState* cs);
-template <int STORAGE>
-__global__ void k_update(const Job* jobs, const MapDesc* maps, const float4* rays_p,
-                         const u64* t_key, const int* t_slot, const u32* off, const u32* sorted,
-                         u32 JM, u64* touch_key, u32* touch_n, u32 touch_cap, int keep_touches,
+                          const u32* rays_job, u32* bins, const u32* off, u32 JM,
+                          const float4* rays_p, float4* sorted, CallState* cs);
+template <int STORAGE, int SPLIT>
+__global__ void k_update(const Job* jobs, const MapDesc* maps, const u64* t_key,
+                         const int* t_slot, const u32* off, const float4* sorted, u32 JM,
+                         u64* touch_key, u32* touch_n, u32 touch_cap, int keep_touches,
                          JobStat* jst, CallState* cs);
 __global__ void k_cleanup(u64* tkeys, u32 tkey_cap, const u32* tlist, u32 tlist_cap,
                           const CallState* cs);

@@ -23,7 +23,7 @@ constexpr int kTileSimple = 1024;      // points per workgroup, per-point raycas
 constexpr int kTileGroupedW = 32;      // 2-D tile of an organised cloud (grouped)
 constexpr int kTileGroupedH = 16;
 constexpr int kTileGrouped = kTileGroupedW * kTileGroupedH;  // 512 points
-constexpr int kGroupSlots = 1024;      // LDS hash slots per grouped tile (load <= 0.5)
+constexpr int kGroupSlots = 512;       // LDS hash slots per grouped tile (>= its points)
 constexpr int kChunkJobs = 127;        // frames per grouping table fill (7-bit tag, 127 reserved)
 constexpr int kMaxStepsPerRay = 96;    // guard only; real bands need 3*(2*delta/v + 2) + 1
 

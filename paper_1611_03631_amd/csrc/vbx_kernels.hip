@@ -87,14 +87,17 @@ __global__ void k_clear_groups(GroupEntry* t, size_t n) {
 }
 __global__ void k_set_u32(u32* p, u32 v) { *p = v; }
 
-// Job of a tile: the last job whose first tile is <= tile.
+// Job of a tile: the last job whose first tile is <= tile (first tiles are non-decreasing),
+// found with one round of loads and a vote.  Every lane of the wave must call it.
 __device__ inline int job_of_tile(const Job* jobs, int njobs, u32 tile) {
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    const int lane = lane_id();
+    int cnt = 0;
+    for (int b = 0; b < njobs; b += 64) {
+        const int j = b + lane;
+        const bool le = j < njobs && jobs[j].tile0 <= tile;
+        cnt += (int)__popcll(__ballot(le));
     }
-    return lo;
+    return cnt - 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -719,14 +722,16 @@ __global__ __launch_bounds__(256) void k_scan_final(const u32* __restrict__ bins
     }
 }
 
-// Places each crossing's ray at its bin position.  Counts are decremented back to zero,
+// Copies each crossing's ray (end point, weight) to its bin position, so that the update
+// kernel reads every (block, frame) bin contiguously.  Counts are decremented back to zero,
 // leaving the bins clean for the next call.
 __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ jobs,
                                                  const uint2* __restrict__ cross,
                                                  const u32* __restrict__ tval,
                                                  const u32* __restrict__ rays_job,
                                                  u32* __restrict__ bins, const u32* __restrict__ off,
-                                                 u32 JM, u32* __restrict__ sorted,
+                                                 u32 JM, const float4* __restrict__ rays_p,
+                                                 float4* __restrict__ sorted,
                                                  CallState* __restrict__ cs) {
     const u32 nc = cs->error ? 0u : cs->cross_count;
     const int lane = lane_id();
@@ -756,7 +761,7 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ jobs,
             }
             pending &= ~grp;
         }
-        if (act) sorted[pos] = ray;
+        if (act) sorted[pos] = rays_p[ray];
     }
 }
 
@@ -785,33 +790,44 @@ __device__ inline void store_voxel(void* pool, size_t idx, float D, float W) {
     }
 }
 
-template <int STORAGE>
+constexpr int kOffWindow = 256;   // frames whose bin offsets are staged in LDS at a time
+
+// Work item u = t * SPLIT + q: slab q (local z in [q*16/SPLIT, (q+1)*16/SPLIT)) of touched block t.
+// Slabs of one block are independent (different voxels) and replay the same rays, so a
+// block's frames run in parallel across SPLIT workgroups with 1/SPLIT of the LDS each.
+template <int STORAGE, int SPLIT>
 __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
                                                 const MapDesc* __restrict__ maps,
-                                                const float4* __restrict__ rays_p,
                                                 const u64* __restrict__ t_key,
                                                 const int* __restrict__ t_slot,
                                                 const u32* __restrict__ off,
-                                                const u32* __restrict__ sorted, u32 JM,
+                                                const float4* __restrict__ sorted, u32 JM,
                                                 u64* __restrict__ touch_key,
                                                 u32* __restrict__ touch_n, u32 touch_cap,
                                                 int keep_touches,
                                                 JobStat* __restrict__ jst,
                                                 CallState* __restrict__ cs) {
-    __shared__ u64 a_w[4096];    // sum of fixed-point weights
-    __shared__ u64 a_d[4096];    // sum of fixed-point weight * distance/delta (two's complement)
-    __shared__ u32 a_n[4096];    // rays
+    constexpr int VOX = 4096 / SPLIT;      // voxels of one slab
+    constexpr int VPT = VOX / 256;         // voxels per thread
+    constexpr int ZS = 16 / SPLIT;         // slab thickness
+    __shared__ u64 a_w[VOX];    // sum of fixed-point weights
+    __shared__ u64 a_d[VOX];    // sum of fixed-point weight * distance/delta (two's complement)
+    __shared__ u32 a_n[VOX];    // rays
+    __shared__ u32 s_off[kOffWindow + 1];
     __shared__ u32 s_t;
     __shared__ u32 s_stat[3];
     __shared__ u32 s_tbase;
     __shared__ u32 lds8[4];
-    for (int i = threadIdx.x; i < 4096; i += 256) { a_w[i] = 0; a_d[i] = 0; a_n[i] = 0; }
-    const u32 nt = cs->error ? 0u : cs->t_count;
+    for (int i = threadIdx.x; i < VOX; i += 256) { a_w[i] = 0; a_d[i] = 0; a_n[i] = 0; }
+    const u32 nt = cs->error ? 0u : cs->t_count * (u32)SPLIT;
     for (;;) {
         if (threadIdx.x == 0) { s_t = atomicAdd(&cs->work_next, 1u); s_stat[0] = 0; s_stat[1] = 0; s_stat[2] = 0; }
         __syncthreads();
-        const u32 t = s_t;
-        if (t >= nt) break;
+        const u32 u = s_t;
+        if (u >= nt) break;
+        const u32 t = u / (u32)SPLIT;
+        const int q = (int)(u % (u32)SPLIT);
+        const int lbase = q * VOX;
         const u64 tk = t_key[t];
         const MapDesc& M = maps[(u32)(tk >> 45)];
         if (M.st->error != 0) { __syncthreads(); continue; }
@@ -821,86 +837,112 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
         const bool is_new = (ts & 0x40000000) != 0;
         const size_t slot = (size_t)(ts & 0x3FFFFFFF);
         void* pool = M.pool;
-        const size_t vbase = slot * 4096;
-        float D[16], W[16];
-        u32 ntot[16];
+        const size_t vbase = slot * 4096 + (size_t)lbase;
+        float D[VPT], W[VPT];
+        u32 ntot[VPT];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
+        for (int j = 0; j < VPT; ++j) {
             ntot[j] = 0;
             if (is_new) { D[j] = 0.0f; W[j] = 0.0f; }
             else load_voxel<STORAGE>(pool, vbase + threadIdx.x + 256 * j, D[j], W[j]);
         }
-        const int ox = 16 * bx, oy = 16 * by, oz = 16 * bz;
+        const int ox = 16 * bx, oy = 16 * by, oz = 16 * bz + q * ZS;
         u32 stat_vox = 0, stat_touch = 0;
-        for (int jm = 0; jm < M.njobs; ++jm) {
-            const u32 b = t * JM + (u32)jm;
-            const u32 lo = off[b], hi = off[b + 1];
-            if (lo == hi) continue;
-            const Job& J = jobs[M.job0 + jm];
-            const float s[3] = {J.pose[3], J.pose[7], J.pose[11]};
-            for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
-                const float4 rp = rays_p[sorted[e]];
-                const float p[3] = {rp.x, rp.y, rp.z};
-                float ev[3], r;
-                Walk w;
-                walk_setup(M, p, s, ev, r, w);
-                bool inside = false;
-                for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
-                    const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
-                    if ((u32)lx < 16u && (u32)ly < 16u && (u32)lz < 16u) {
-                        inside = true;
-                        const Obs o = observe(M, p, ev, r, rp.w, w.g[0], w.g[1], w.g[2]);
-                        const u32 l = (u32)lx | ((u32)ly << 4) | ((u32)lz << 8);
-                        const u64 fw = (u64)__builtin_rintf(o.w * M.wscale);
-                        const i64 fd = (i64)__builtin_rintf(o.w * o.e * M.wscale);
-                        if (fw) atomicAdd(&a_w[l], fw);
-                        if (fd) atomicAdd(&a_d[l], (u64)fd);
-                        atomicAdd(&a_n[l], 1u);
-                    } else if (inside) {
-                        break;   // the walk is monotone per axis: it never re-enters the block
-                    }
-                    if (w.left == 0) break;
-                    walk_step(w);
-                }
-            }
+        for (int w0 = 0; w0 < M.njobs; w0 += kOffWindow) {
+            const int wn = M.njobs - w0 < kOffWindow ? M.njobs - w0 : kOffWindow;
+            for (int k = threadIdx.x; k <= wn; k += 256) s_off[k] = off[t * JM + (u32)(w0 + k)];
             __syncthreads();
-            // Eqs. (3)-(4), once per voxel for this frame
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int l = threadIdx.x + 256 * j;
-                const u32 c = a_n[l];
-                if (c) {
-                    const u64 sw_fx = a_w[l];
-                    if (sw_fx) {
-                        const float sw = (float)sw_fx * M.inv_wscale;
-                        // sums are in units of delta; binary32 storage keeps D in metres,
-                        // binary16 storage keeps D / delta
-                        float swd = (float)(i64)a_d[l] * M.inv_wscale;
-                        if (STORAGE == 0) swd = swd * M.delta;
-                        float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
-                        float Wn = W[j] + sw;
-                        if (Wn > M.w_max) Wn = M.w_max;
-                        if (STORAGE == 1) {
-                            Dn = __half2float(__float2half_rn(Dn));
-                            Wn = __half2float(__float2half_rn(Wn));
-                        }
-                        D[j] = Dn;
-                        W[j] = Wn;
-                    }
-                    ntot[j] += c;
-                    stat_vox += 1;
-                    stat_touch += c;
-                    a_w[l] = 0; a_d[l] = 0; a_n[l] = 0;
+            // frames of the window in order; the first ray of every thread for the next frame
+            // that has rays is loaded while the current frame is processed
+            int jm = 0;
+            while (jm < wn && s_off[jm] == s_off[jm + 1]) ++jm;
+            float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+            bool has_nxt = false;
+            if (jm < wn) {
+                const u32 e = s_off[jm] + threadIdx.x;
+                has_nxt = e < s_off[jm + 1];
+                if (has_nxt) nxt = sorted[e];
+            }
+            while (jm < wn) {
+                int jn = jm + 1;
+                while (jn < wn && s_off[jn] == s_off[jn + 1]) ++jn;
+                const float4 cur = nxt;
+                const bool has_cur = has_nxt;
+                const u32 lo = s_off[jm], hi = s_off[jm + 1];
+                if (jn < wn) {
+                    const u32 e = s_off[jn] + threadIdx.x;
+                    has_nxt = e < s_off[jn + 1];
+                    if (has_nxt) nxt = sorted[e];
                 }
+                const Job& J = jobs[M.job0 + w0 + jm];
+                const float s[3] = {J.pose[3], J.pose[7], J.pose[11]};
+                for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
+                    const float4 rp = e == lo + threadIdx.x ? cur : sorted[e];
+                    (void)has_cur;
+                    const float p[3] = {rp.x, rp.y, rp.z};
+                    float ev[3], r;
+                    Walk w;
+                    walk_setup(M, p, s, ev, r, w);
+                    bool inside = false;
+                    for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
+                        const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
+                        if ((u32)lx < 16u && (u32)ly < 16u && (u32)lz < (u32)ZS) {
+                            inside = true;
+                            const Obs o = observe(M, p, ev, r, rp.w, w.g[0], w.g[1], w.g[2]);
+                            const u32 l = (u32)lx | ((u32)ly << 4) | ((u32)lz << 8);
+                            const u64 fw = (u64)__builtin_rintf(o.w * M.wscale);
+                            const i64 fd = (i64)__builtin_rintf(o.w * o.e * M.wscale);
+                            if (fw) atomicAdd(&a_w[l], fw);
+                            if (fd) atomicAdd(&a_d[l], (u64)fd);
+                            atomicAdd(&a_n[l], 1u);
+                        } else if (inside) {
+                            break;   // the walk is monotone per axis: it never re-enters the slab
+                        }
+                        if (w.left == 0) break;
+                        walk_step(w);
+                    }
+                }
+                __syncthreads();
+                // Eqs. (3)-(4), once per voxel for this frame
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) {
+                    const int l = threadIdx.x + 256 * j;
+                    const u32 c = a_n[l];
+                    if (c) {
+                        const u64 sw_fx = a_w[l];
+                        if (sw_fx) {
+                            const float sw = (float)sw_fx * M.inv_wscale;
+                            // sums are in units of delta; binary32 storage keeps D in metres,
+                            // binary16 storage keeps D / delta
+                            float swd = (float)(i64)a_d[l] * M.inv_wscale;
+                            if (STORAGE == 0) swd = swd * M.delta;
+                            float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
+                            float Wn = W[j] + sw;
+                            if (Wn > M.w_max) Wn = M.w_max;
+                            if (STORAGE == 1) {
+                                Dn = __half2float(__float2half_rn(Dn));
+                                Wn = __half2float(__float2half_rn(Wn));
+                            }
+                            D[j] = Dn;
+                            W[j] = Wn;
+                        }
+                        ntot[j] += c;
+                        stat_vox += 1;
+                        stat_touch += c;
+                        a_w[l] = 0; a_d[l] = 0; a_n[l] = 0;
+                    }
+                }
+                __syncthreads();
+                jm = jn;
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int j = 0; j < 16; ++j) store_voxel<STORAGE>(pool, vbase + threadIdx.x + 256 * j, D[j], W[j]);
+        for (int j = 0; j < VPT; ++j) store_voxel<STORAGE>(pool, vbase + threadIdx.x + 256 * j, D[j], W[j]);
         if (stat_vox) {
             u32 cells = 0;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) cells += ntot[j] ? 1u : 0u;
+            for (int j = 0; j < VPT; ++j) cells += ntot[j] ? 1u : 0u;
             atomicAdd(&s_stat[0], stat_vox);
             atomicAdd(&s_stat[1], stat_touch);
             atomicAdd(&s_stat[2], cells);
@@ -908,14 +950,14 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
         if (keep_touches) {
             u32 mine = 0;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) mine += ntot[j] ? 1u : 0u;
+            for (int j = 0; j < VPT; ++j) mine += ntot[j] ? 1u : 0u;
             u32 tot;
             const u32 incl = block_scan_256(mine, lds8, &tot);
             if (threadIdx.x == 0) s_tbase = atomicAdd(&cs->touch_count, tot);
             __syncthreads();
             u32 pos = s_tbase + incl - mine;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int j = 0; j < VPT; ++j) {
                 if (ntot[j]) {
                     const int l = threadIdx.x + 256 * j;
                     if (pos < touch_cap) {
@@ -937,12 +979,24 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
     }
 }
 
-template __global__ void k_update<0>(const Job*, const MapDesc*, const float4*, const u64*,
-                                     const int*, const u32*, const u32*, u32, u64*, u32*, u32, int,
-                                     JobStat*, CallState*);
-template __global__ void k_update<1>(const Job*, const MapDesc*, const float4*, const u64*,
-                                     const int*, const u32*, const u32*, u32, u64*, u32*, u32, int,
-                                     JobStat*, CallState*);
+template __global__ void k_update<0, 1>(const Job*, const MapDesc*, const u64*, const int*,
+                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                         JobStat*, CallState*);
+template __global__ void k_update<0, 2>(const Job*, const MapDesc*, const u64*, const int*,
+                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                         JobStat*, CallState*);
+template __global__ void k_update<0, 4>(const Job*, const MapDesc*, const u64*, const int*,
+                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                         JobStat*, CallState*);
+template __global__ void k_update<1, 1>(const Job*, const MapDesc*, const u64*, const int*,
+                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                         JobStat*, CallState*);
+template __global__ void k_update<1, 2>(const Job*, const MapDesc*, const u64*, const int*,
+                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                         JobStat*, CallState*);
+template __global__ void k_update<1, 4>(const Job*, const MapDesc*, const u64*, const int*,
+                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                         JobStat*, CallState*);
 
 // ---------------------------------------------------------------------------
 // finish: commit block counts, fold statistics, clean per-call tables

@@ -176,3 +176,25 @@ def test_full_sequence_640x480x100_bench_configuration(vbx):
     log(f"  ok: {res}")
     st = g.stats()
     assert st["points"] == 100 * 640 * 480
+
+
+def test_tuning_never_changes_results_and_autotune_leaves_map(vbx):
+    frames = room(320, 240, 3, 71)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped")
+    outs = []
+    for split in (1, 2, 4):
+        g = gpu_map(vbx, params)
+        g.set_tuning(split)
+        g.integrate_frames([(dev(p), pose, 320) for p, pose in frames])
+        assert g.sync() == 0
+        outs.append(g.export())
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+    g = gpu_map(vbx, params)
+    g.integrate(dev(frames[0][0]), frames[0][1])
+    before = g.export()
+    res = g.autotune([(dev(p), pose, 320) for p, pose in frames])
+    assert res["best"]["update_split"] in (1, 2, 4) and all(x > 0 for x in res["ms"])
+    after = g.export()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    assert g.tuning() == res["best"]
