@@ -120,7 +120,10 @@ def main():
         tune["ms"] = [round(x, 4) for x in tune["ms"]]
 
     # ---------------------------------------------------------------- warm-up
-    for _ in range(args.warmup):
+    step()
+    assert m.sync() == 0
+    first_export = m.export()          # every step must rebuild exactly this map
+    for _ in range(max(args.warmup - 1, 0)):
         step()
     assert m.sync() == 0
     m.profile(True)
@@ -141,6 +144,10 @@ def main():
     if status != 0:
         raise vbx.VbxError(status, "device status after the timed steps")
     ms_total = ev0.elapsed_time(ev1)
+    last_export = m.export()
+    if not (np.array_equal(first_export[0], last_export[0]) and
+            np.array_equal(first_export[1], last_export[1])):
+        raise RuntimeError("the last timed step did not reproduce the first step's map bit-for-bit")
     prof = m.profile_read(reset=True)
     m.profile(False)
     st = m.stats()           # the map was cleared before the last step: one step's counts
@@ -224,6 +231,7 @@ def main():
         "whole_step_algorithmic_GBps": round(whole, 1),
         "stage_ms_per_step": stages,
         "wall_s": round(wall_s, 3),
+        "repeat_bit_identical": True,
         "tuning": m.tuning(),
         "autotune": tune,
         "roofline": roofline,

@@ -48,10 +48,10 @@ struct Stage {
 };
 
 struct Scratch {
-    DevBuf rays_p, rays_job, cross, sorted, tkeys, tval, tlist, t_key, t_slot, bins, off, partial,
-        gtable, occ, touch_key, touch_n, tables, jst, cs;
+    DevBuf rays_p, rays_job, cross, ncross, sorted, tkeys, tval, tlist, t_key, t_slot, bins, off,
+        partial, parts, parts_sorted, tile_parts, touch_key, touch_n, tables, jst, cs;
     size_t ray_cap = 0, cross_cap = 0, tkey_cap = 0, tlist_cap = 0, bins_cap = 0, nparts = 0,
-           gcap = 0, touch_cap = 0, job_cap = 0, map_cap = 0;
+           touch_cap = 0;
     Stage stage[4];
     int stage_i = 0;
     // host copy of the maps of the last call (for vbx_last_touches)
@@ -226,9 +226,10 @@ void free_storage(vbx_map* m) {
 
 void free_scratch(Scratch* s) {
     if (!s) return;
-    DevBuf* bufs[] = {&s->rays_p, &s->rays_job, &s->cross, &s->sorted, &s->tkeys, &s->tval,
-                      &s->tlist, &s->t_key, &s->t_slot, &s->bins, &s->off, &s->partial,
-                      &s->gtable, &s->occ, &s->touch_key, &s->touch_n, &s->tables, &s->jst, &s->cs};
+    DevBuf* bufs[] = {&s->rays_p, &s->rays_job, &s->cross, &s->ncross, &s->sorted, &s->tkeys,
+                      &s->tval, &s->tlist, &s->t_key, &s->t_slot, &s->bins, &s->off, &s->partial,
+                      &s->parts, &s->parts_sorted, &s->tile_parts, &s->touch_key, &s->touch_n,
+                      &s->tables, &s->jst, &s->cs};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (Stage& st : s->stage) {
@@ -240,6 +241,8 @@ void free_scratch(Scratch* s) {
 
 struct CallPlan {
     size_t total_points = 0;
+    size_t ray_slots = 0;       // tiles x points per tile
+    u32 tiles = 0;
     int JM = 1;
     int max_blocks = 4;
     int max_vox = 22;
@@ -249,19 +252,17 @@ struct CallPlan {
 };
 
 // Grows the scratch of `lead` for a call; tables that must start cleared are cleared here.
-int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, size_t max_chunk_points,
-                   size_t sum_capacity) {
+int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, size_t sum_capacity) {
     Scratch* s = lead->scratch;
     hipStream_t st = lead->stream;
-    const size_t ray_cap = std::max<size_t>(plan.total_points, 1);
+    const size_t ray_cap = std::max<size_t>(plan.ray_slots, 1);
     const size_t cross_cap = ray_cap * (size_t)plan.max_blocks;
-    if (cross_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
+    if (cross_cap > 0xFFFFFFF0ull || ray_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
     const size_t tlist_cap = std::min<size_t>(std::max<size_t>(sum_capacity + 4096, 4096), cross_cap + 4096);
     const size_t tkey_cap = next_pow2(2 * tlist_cap);
     const size_t bins_cap = tlist_cap * (size_t)plan.JM;
     if (bins_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
     const size_t nparts = (bins_cap + kScanChunkHost - 1) / kScanChunkHost;
-    const size_t gcap = plan.grouped ? next_pow2(std::max<size_t>(2 * max_chunk_points, 1024)) : 0;
     const size_t touch_cap =
         plan.keep_touches ? std::min<size_t>(ray_cap * (size_t)plan.max_vox, (size_t)1 << 26) : 0;
 
@@ -280,7 +281,8 @@ int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, si
 
     GROW(s->rays_p, ray_cap * sizeof(float4));
     GROW(s->rays_job, ray_cap * sizeof(u32));
-    GROW(s->cross, cross_cap * sizeof(uint2));
+    GROW(s->cross, cross_cap * sizeof(u32));
+    GROW(s->ncross, ray_cap);
     GROW(s->sorted, cross_cap * sizeof(float4));
     if ((r = grow(s->tkeys, tkey_cap * sizeof(u64))) < 0) return VBX_ERR_OUT_OF_MEMORY;
     if (r == 1 || s->tkey_cap != tkey_cap) {
@@ -296,13 +298,11 @@ int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, si
     if (r == 1) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(bins_cap + 1)), dim3(256), 0, st, (u32*)s->bins.p, 0u, bins_cap + 1);
     GROW(s->off, (bins_cap + 1) * sizeof(u32));
     GROW(s->partial, (nparts + 1) * sizeof(u32));
-    if (plan.grouped && s->gcap < gcap) {
-        // grouping table: power-of-two capacity >= 2x the points of a chunk, cleared once;
-        // every use leaves it clean again
-        if ((r = grow(s->gtable, gcap * sizeof(GroupEntry))) < 0) return VBX_ERR_OUT_OF_MEMORY;
-        hipLaunchKernelGGL(k_clear_groups, dim3(grid_for(gcap)), dim3(256), 0, st, (GroupEntry*)s->gtable.p, gcap);
-        s->gcap = gcap;
-        GROW(s->occ, gcap / 2 * sizeof(u32));
+    if (plan.grouped) {
+        // partial groups: a tile of kTileGrouped points owns kTileGrouped slots
+        GROW(s->parts, ray_cap * sizeof(Partial));
+        GROW(s->parts_sorted, ray_cap * sizeof(Partial));
+        GROW(s->tile_parts, std::max<size_t>(plan.tiles, 1) * sizeof(u32));
     }
     if (plan.keep_touches) {
         GROW(s->touch_key, touch_cap * sizeof(u64));
@@ -336,6 +336,22 @@ int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, si
     }
     if (!sg.ev && hipEventCreateWithFlags(&sg.ev, hipEventDisableTiming) != hipSuccess) return VBX_ERR_DEVICE;
     return VBX_OK;
+}
+
+// Persistent grid of the group-merge kernel.
+int group_merge_grid() {
+    static int grid = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0, cus = 256, per = 1;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_group_merge), 256, 0) !=
+                hipSuccess || per < 1)
+            per = 1;
+        grid = cus * per;
+    });
+    return grid > 0 ? grid : 256;
 }
 
 // Persistent grid of an update-kernel variant: one workgroup per slot the chip can hold.
@@ -454,51 +470,27 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     }
     const int J = (int)jobs.size();
 
-    // chunks: <= kChunkJobs frames and a bounded point count each (grouping table size)
-    const size_t chunk_points_cap = (size_t)1 << 22;
-    std::vector<std::pair<int, int>> chunks;   // [begin, end)
-    size_t max_chunk_points = 0;
-    {
-        int b = 0;
-        size_t pts = 0;
-        for (int i = 0; i < J; ++i) {
-            if (i > b && (i - b >= kChunkJobs || pts + jobs[i].n > chunk_points_cap)) {
-                chunks.push_back({b, i});
-                max_chunk_points = std::max(max_chunk_points, pts);
-                b = i;
-                pts = 0;
-            }
-            pts += jobs[i].n;
+    // tiles of every frame, numbered over the whole call
+    u32 total_tiles = 0;
+    for (int i = 0; i < J; ++i) {
+        Job& j = jobs[i];
+        u32 nt;
+        if (!plan.grouped) {
+            nt = (j.n + kTileSimple - 1) / kTileSimple;
+        } else if (j.width > 0) {
+            const u32 rows = j.n / j.width;
+            nt = ((j.width + kTileGroupedW - 1) / kTileGroupedW) * ((rows + kTileGroupedH - 1) / kTileGroupedH);
+        } else {
+            nt = (j.n + kTileGrouped - 1) / kTileGrouped;
         }
-        chunks.push_back({b, J});
-        max_chunk_points = std::max(max_chunk_points, pts);
+        j.tile0 = total_tiles;
+        j.ntiles = nt;
+        total_tiles += nt;
     }
-    // tiles, numbered per chunk
-    std::vector<u32> chunk_tiles(chunks.size(), 0);
-    for (size_t c = 0; c < chunks.size(); ++c) {
-        u32 t = 0;
-        for (int i = chunks[c].first; i < chunks[c].second; ++i) {
-            Job& j = jobs[i];
-            u32 nt;
-            if (!plan.grouped) {
-                nt = (j.n + kTileSimple - 1) / kTileSimple;
-            } else if (j.width > 0) {
-                const u32 rows = j.n / j.width;
-                nt = ((j.width + kTileGroupedW - 1) / kTileGroupedW) * ((rows + kTileGroupedH - 1) / kTileGroupedH);
-            } else {
-                nt = (j.n + kTileGrouped - 1) / kTileGrouped;
-            }
-            j.tile0 = t;
-            j.ntiles = nt;
-            t += nt;
-        }
-        chunk_tiles[c] = t;
-    }
+    plan.tiles = total_tiles;
+    plan.ray_slots = (size_t)total_tiles * (plan.grouped ? kTileGrouped : kTileSimple);
 
-    // maps integrated on the lead's stream must be idle on their own streams
-    for (int m = 1; m < M; ++m)
-        if (maps[m]->stream != st) VBX_TRY(hipStreamSynchronize(maps[m]->stream));
-    int rc = ensure_scratch(lead, plan, J, M, max_chunk_points, sum_capacity);
+    int rc = ensure_scratch(lead, plan, J, M, sum_capacity);
     if (rc != VBX_OK) return rc;
     Scratch* s = lead->scratch;
 
@@ -519,36 +511,53 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     u32* rays_job = (u32*)s->rays_job.p;
     const u32 ray_cap = (u32)s->ray_cap;
 
+    const u32 JM = (u32)plan.JM;
+    const unsigned GT = grid_for(s->tlist_cap, 1024);
+    const unsigned NP = (unsigned)std::max<size_t>(s->nparts, 1);
+    auto scan_bins = [&]() {
+        hipLaunchKernelGGL(k_scan_sums, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, JM, (u32*)s->partial.p,
+                           (const CallState*)cs);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, (u32*)s->partial.p, (u32)NP, (u32*)s->off.p, JM,
+                           (const CallState*)cs);
+        hipLaunchKernelGGL(k_scan_final, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, (const u32*)s->partial.p,
+                           (u32*)s->off.p, JM, (const CallState*)cs);
+    };
     // points
-    for (size_t c = 0; c < chunks.size(); ++c) {
-        const int jb = chunks[c].first, je = chunks[c].second;
-        if (chunk_tiles[c] == 0) continue;
+    if (total_tiles > 0) {
+        StageTimer tm(lead, st, ST_POINTS);
         if (!plan.grouped) {
-            StageTimer tm(lead, st, ST_POINTS);
-            hipLaunchKernelGGL(k_points_simple, dim3(chunk_tiles[c]), dim3(256), 0, st, d_jobs + jb, je - jb, jb,
-                               d_maps, rays_p, rays_job, jst, cs, ray_cap);
+            hipLaunchKernelGGL(k_points_simple, dim3(total_tiles), dim3(256), 0, st, d_jobs, J, d_maps, rays_p,
+                               rays_job, jst, cs);
         } else {
-            {
-            StageTimer tm(lead, st, ST_POINTS);
-            hipLaunchKernelGGL(k_points_grouped, dim3(chunk_tiles[c]), dim3(256), 0, st, d_jobs + jb, je - jb, jb,
-                               d_maps, (GroupEntry*)s->gtable.p, (u32)(s->gcap - 1), (u32*)s->occ.p, jst, cs);
-            }
-            StageTimer tm(lead, st, ST_GROUPS);
-            size_t pts = 0;
-            for (int i = jb; i < je; ++i) pts += jobs[i].n;
-            hipLaunchKernelGGL(k_groups_to_rays, dim3(grid_for(pts, 1024)), dim3(256), 0, st, d_jobs + jb, jb, d_maps,
-                               (GroupEntry*)s->gtable.p, (const u32*)s->occ.p, rays_p, rays_job, jst, cs, ray_cap);
-            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->occ_count, 0u);
+            hipLaunchKernelGGL(k_points_grouped, dim3(total_tiles), dim3(256), 0, st, d_jobs, J, d_maps,
+                               (u64*)s->tkeys.p, (u32)(s->tkey_cap - 1), (u32*)s->tlist.p, (u32)s->tlist_cap,
+                               (Partial*)s->parts.p, (u32*)s->tile_parts.p, jst, cs);
         }
     }
-    const unsigned G = grid_for(plan.total_points, 2048);
+    if (plan.grouped && total_tiles > 0) {
+        StageTimer tm(lead, st, ST_GROUPS);
+        const unsigned GW = (total_tiles + 3) / 4;   // one wave per tile
+        hipLaunchKernelGGL(k_densify, dim3(GT), dim3(256), 0, st, (const u32*)s->tlist.p, (u32)s->tlist_cap,
+                           (u32*)s->tval.p, (const CallState*)cs);
+        hipLaunchKernelGGL(k_gbin_count, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
+                           (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p, JM,
+                           (const CallState*)cs);
+        scan_bins();
+        hipLaunchKernelGGL(k_gscatter, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
+                           (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p,
+                           (const u32*)s->off.p, JM, (Partial*)s->parts_sorted.p, (const CallState*)cs);
+        hipLaunchKernelGGL(k_group_merge, dim3(group_merge_grid()), dim3(256), 0, st, d_jobs, d_maps,
+                           (const u64*)s->tkeys.p, (const u32*)s->tlist.p, (const u32*)s->off.p,
+                           (const Partial*)s->parts_sorted.p, JM, rays_p, rays_job, jst, cs);
+    }
+    const unsigned G = grid_for(plan.ray_slots, 2048);
+    const u32 MB = (u32)plan.max_blocks;
     {
     StageTimer tm(lead, st, ST_CROSS);
     hipLaunchKernelGGL(k_cross, dim3(G), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
                        (const u32*)rays_job, (u64*)s->tkeys.p, (u32)(s->tkey_cap - 1), (u32*)s->tlist.p,
-                       (u32)s->tlist_cap, (uint2*)s->cross.p, (u32)s->cross_cap, jst, cs, ray_cap);
+                       (u32)s->tlist_cap, (u32*)s->cross.p, (unsigned char*)s->ncross.p, MB, jst, cs, ray_cap);
     }
-    const unsigned GT = grid_for(s->tlist_cap, 1024);
     {
     StageTimer tm(lead, st, ST_RESOLVE);
     hipLaunchKernelGGL(k_resolve, dim3(GT), dim3(256), 0, st, d_maps, (const u64*)s->tkeys.p, (u32*)s->tval.p,
@@ -558,27 +567,22 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     StageTimer tm(lead, st, ST_COMMIT);
     hipLaunchKernelGGL(k_commit, dim3(GT), dim3(256), 0, st, d_maps, (const u64*)s->t_key.p, (int*)s->t_slot.p, cs);
     }
-    const u32 JM = (u32)plan.JM;
     {
     StageTimer tm(lead, st, ST_BINS);
-    hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, d_jobs, (const uint2*)s->cross.p,
-                       (const u32*)s->tval.p, (const u32*)rays_job, (u32*)s->bins.p, JM, cs);
+    hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, d_jobs, (const u32*)s->cross.p,
+                       (const unsigned char*)s->ncross.p, MB, (const u32*)s->tval.p, (const u32*)rays_job,
+                       (u32*)s->bins.p, JM, cs, ray_cap);
     }
-    const unsigned NP = (unsigned)std::max<size_t>(s->nparts, 1);
     {
     StageTimer tm(lead, st, ST_SCAN);
-    hipLaunchKernelGGL(k_scan_sums, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, JM, (u32*)s->partial.p,
-                       (const CallState*)cs);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, (u32*)s->partial.p, (u32)NP, (u32*)s->off.p, JM,
-                       (const CallState*)cs);
-    hipLaunchKernelGGL(k_scan_final, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, (const u32*)s->partial.p,
-                       (u32*)s->off.p, JM, (const CallState*)cs);
+    scan_bins();
     }
     {
     StageTimer tm(lead, st, ST_SCATTER);
-    hipLaunchKernelGGL(k_scatter, dim3(G), dim3(256), 0, st, d_jobs, (const uint2*)s->cross.p, (const u32*)s->tval.p,
-                       (const u32*)rays_job, (u32*)s->bins.p, (const u32*)s->off.p, JM, (const float4*)rays_p,
-                       (float4*)s->sorted.p, cs);
+    hipLaunchKernelGGL(k_scatter, dim3(G), dim3(256), 0, st, d_jobs, (const u32*)s->cross.p,
+                       (const unsigned char*)s->ncross.p, MB, (const u32*)s->tval.p, (const u32*)rays_job,
+                       (u32*)s->bins.p, (const u32*)s->off.p, JM, (const float4*)rays_p, (float4*)s->sorted.p, cs,
+                       ray_cap);
     }
     if (plan.keep_touches) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->touch_count, 0u);
     {
@@ -592,7 +596,7 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     StageTimer tm(lead, st, ST_FINISH);
     hipLaunchKernelGGL(k_cleanup, dim3(grid_for(s->tkey_cap, 1024)), dim3(256), 0, st, (u64*)s->tkeys.p,
                        (u32)s->tkey_cap, (const u32*)s->tlist.p, (u32)s->tlist_cap, (const CallState*)cs);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, d_jobs, J, d_maps, M, jst, cs);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d_jobs, J, d_maps, M, jst, cs);
     }
     if (hipGetLastError() != hipSuccess) return VBX_ERR_DEVICE;
     if (plan.keep_touches) {

@@ -15,32 +15,39 @@ struct JobStat {
 // Kernels (defined in vbx_kernels.hip).
 __global__ void k_fill_u64(u64* p, u64 val, size_t n);
 __global__ void k_fill_u32(u32* p, u32 val, size_t n);
-__global__ void k_clear_groups(GroupEntry* t, size_t n);
 __global__ void k_set_u32(u32* p, u32 v);
-__global__ void k_points_simple(const Job* jobs, int njobs, int job_base, const MapDesc* maps,
-                                float4* rays_p, u32* rays_job, JobStat* jst, CallState* cs,
-                                u32 ray_cap);
-__global__ void k_points_grouped(const Job* jobs, int njobs, int job_base, const MapDesc* maps,
-                                 GroupEntry* table, u32 tmask, u32* occ, JobStat* jst,
-                                 CallState* cs);
-__global__ void k_groups_to_rays(const Job* jobs, int job_base, const MapDesc* maps,
-                                 GroupEntry* table, const u32* occ, float4* rays_p, u32* rays_job,
-                                 JobStat* jst, CallState* cs, u32 ray_cap);
+__global__ void k_points_simple(const Job* jobs, int njobs, const MapDesc* maps, float4* rays_p,
+                                u32* rays_job, JobStat* jst, CallState* cs);
+__global__ void k_points_grouped(const Job* jobs, int njobs, const MapDesc* maps, u64* tkeys,
+                                 u32 tmask, u32* tlist, u32 tlist_cap, Partial* parts,
+                                 u32* tile_parts, JobStat* jst, CallState* cs);
+__global__ void k_densify(const u32* tlist, u32 tlist_cap, u32* tval, const CallState* cs);
+__global__ void k_gbin_count(const Partial* parts, const u32* tile_parts, u32 ntiles,
+                             const u32* tval, u32* bins, u32 JM, const CallState* cs);
+__global__ void k_gscatter(const Partial* parts, const u32* tile_parts, u32 ntiles,
+                           const u32* tval, u32* bins, const u32* off, u32 JM, Partial* sorted,
+                           const CallState* cs);
+__global__ void k_group_merge(const Job* jobs, const MapDesc* maps, const u64* tkeys,
+                              const u32* tlist, const u32* off, const Partial* sorted, u32 JM,
+                              float4* rays_p, u32* rays_job, JobStat* jst, CallState* cs);
 __global__ void k_cross(const Job* jobs, const MapDesc* maps, const float4* rays_p,
                         const u32* rays_job, u64* tkeys, u32 tmask, u32* tlist, u32 tlist_cap,
-                        uint2* cross, u32 cross_cap, JobStat* jst, CallState* cs, u32 ray_cap);
+                        u32* cross, unsigned char* ncross, u32 MB, JobStat* jst, CallState* cs,
+                        u32 ray_cap);
 __global__ void k_resolve(const MapDesc* maps, const u64* tkeys, u32* tval, const u32* tlist,
                           u64* t_key, int* t_slot, CallState* cs);
 __global__ void k_commit(const MapDesc* maps, const u64* t_key, int* t_slot, CallState* cs);
-__global__ void k_bin_count(const Job* jobs, const uint2* cross, const u32* tval,
-                            const u32* rays_job, u32* bins, u32 JM, CallState* cs);
+__global__ void k_bin_count(const Job* jobs, const u32* cross, const unsigned char* ncross,
+                            u32 MB, const u32* tval, const u32* rays_job, u32* bins, u32 JM,
+                            CallState* cs, u32 ray_cap);
 __global__ void k_scan_sums(const u32* bins, u32 JM, u32* partial, const CallState* cs);
 __global__ void k_scan_partials(u32* partial, u32 nparts, u32* off, u32 JM, const CallState* cs);
 __global__ void k_scan_final(const u32* bins, const u32* partial, u32* off, u32 JM,
                              const CallState* cs);
-__global__ void k_scatter(const Job* jobs, const uint2* cross, const u32* tval,
-                          const u32* rays_job, u32* bins, const u32* off, u32 JM,
-                          const float4* rays_p, float4* sorted, CallState* cs);
+__global__ void k_scatter(const Job* jobs, const u32* cross, const unsigned char* ncross,
+                          u32 MB, const u32* tval, const u32* rays_job, u32* bins,
+                          const u32* off, u32 JM, const float4* rays_p, float4* sorted,
+                          CallState* cs, u32 ray_cap);
 template <int STORAGE, int SPLIT>
 __global__ void k_update(const Job* jobs, const MapDesc* maps, const u64* t_key,
                          const int* t_slot, const u32* off, const float4* sorted, u32 JM,

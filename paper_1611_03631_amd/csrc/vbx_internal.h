@@ -17,6 +17,7 @@ typedef long long i64;
 typedef unsigned int u32;
 
 constexpr u64 kEmpty = ~0ull;
+constexpr u32 kNoRay = 0xFFFFFFFFu;      // job of an empty ray slot
 constexpr int kVoxLimit = 1 << 18;     // |voxel index| < 2^18
 constexpr int kBlockBias = 1 << 14;    // block indices packed as 15-bit biased fields
 constexpr int kTileSimple = 1024;      // points per workgroup, per-point raycasting
@@ -24,7 +25,6 @@ constexpr int kTileGroupedW = 32;      // 2-D tile of an organised cloud (groupe
 constexpr int kTileGroupedH = 16;
 constexpr int kTileGrouped = kTileGroupedW * kTileGroupedH;  // 512 points
 constexpr int kGroupSlots = 512;       // LDS hash slots per grouped tile (>= its points)
-constexpr int kChunkJobs = 127;        // frames per grouping table fill (7-bit tag, 127 reserved)
 constexpr int kMaxStepsPerRay = 96;    // guard only; real bands need 3*(2*delta/v + 2) + 1
 
 // Per-map parameters and device pointers for one call (copied to the device per call).
@@ -66,25 +66,23 @@ struct Job {
 
 // Counters of one call (device).
 struct CallState {
-    u32 ray_count;
-    u32 cross_count;
-    u32 t_count;
-    u32 occ_count;     // grouping table: occupied entries
+    u32 ray_count;     // ray slots of the call (some may be empty)
+    u32 t_count;       // entries of the per-call block set
     u32 work_next;     // persistent work counter of the update kernel
     u32 touch_count;
     int error;         // call-wide error (scratch overflow)
-    u32 pad;
+    u32 work_merge;    // persistent work counter of the group merge kernel
+    u32 pad0, pad1;
 };
 
-// Grouping table entry (64 bytes): exact integer sums of one (frame, voxel) group.
-struct GroupEntry {
-    u64 key;       // (job_in_chunk << 57) | voxel key
+// Partial group of one tile (48 bytes): exact integer sums of the tile's points in one voxel.
+struct Partial {
     u64 so;        // sum of fixed-point point weights
-    u64 sq[3];     // low 64 bits of sum(weight * Q_k)
-    u32 sqhi[3];   // high bits
+    u64 sq[3];     // sum of weight * Q_k (fits 64 bits for a tile of <= 512 points)
+    u32 h;         // block-set slot of the voxel's block
+    u32 lj;        // local voxel index (12 bits) | frame-in-map index << 12
     u32 n;         // points
-    u32 idx;       // index of the point when the group has one point
-    u32 pad;
+    u32 idx;       // index of the point (meaningful when n == 1)
 };
 
 __host__ __device__ inline u64 mix64(u64 x) {

@@ -3,9 +3,11 @@
 // One integration call runs this pipeline on the map's stream:
 //   points   : validity, pose transform, voxel keying (one thread per point, coalesced
 //              12-byte loads).  Per-point raycasting writes one ray per valid point.
-//              Grouped raycasting (Sec. IV-B) first merges the points of a tile in an LDS
-//              hash by voxel, then merges the tile partials of one (frame, voxel) in a
-//              global table, all in exact integer sums, and casts one ray per group.
+//              Grouped raycasting (Sec. IV-B) merges the points of a tile in an LDS hash by
+//              voxel and writes one record per partial group, tagged with its block.
+//   groups   : (grouped only) counting sort of the partial groups by (block, frame), then
+//              one workgroup per bin merges them by voxel in LDS and casts one ray per
+//              group; every sum is an exact integer, so the order never matters.
 //   cross    : walk every ray through its truncation band and record, for each block the
 //              walk enters, a (block, ray) crossing; blocks are collected in a per-call hash.
 //   resolve  : look the call's blocks up in the map's block hash (wavefront-cooperative
@@ -77,14 +79,6 @@ __global__ void k_fill_u32(u32* p, u32 val, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = val;
 }
-__global__ void k_clear_groups(GroupEntry* t, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        GroupEntry e;
-        e.key = kEmpty; e.so = 0; e.sq[0] = e.sq[1] = e.sq[2] = 0;
-        e.sqhi[0] = e.sqhi[1] = e.sqhi[2] = 0; e.n = 0; e.idx = 0; e.pad = 0;
-        t[i] = e;
-    }
-}
 __global__ void k_set_u32(u32* p, u32 v) { *p = v; }
 
 // Job of a tile: the last job whose first tile is <= tile (first tiles are non-decreasing),
@@ -103,63 +97,54 @@ __device__ inline int job_of_tile(const Job* jobs, int njobs, u32 tile) {
 // ---------------------------------------------------------------------------
 // points: per-point raycasting
 // ---------------------------------------------------------------------------
+// Every point of tile k owns ray slot k * kTileSimple + (its index in the tile); invalid points
+// and the tail of a frame's last tile leave a hole (job kNoRay).  No counter is shared.
 __global__ __launch_bounds__(256) void k_points_simple(const Job* __restrict__ jobs, int njobs,
-                                                       int job_base,
                                                        const MapDesc* __restrict__ maps,
                                                        float4* __restrict__ rays_p,
                                                        u32* __restrict__ rays_job,
                                                        JobStat* __restrict__ jst,
-                                                       CallState* __restrict__ cs, u32 ray_cap) {
+                                                       CallState* __restrict__ cs) {
     __shared__ u32 s_cnt[3];   // valid, invalid, out of bounds
-    __shared__ u32 s_base;
-    __shared__ u32 lds8[4];
-    const int jloc = job_of_tile(jobs, njobs, blockIdx.x);
-    const int jid = job_base + jloc;
-    const Job& J = jobs[jloc];
+    const int jid = job_of_tile(jobs, njobs, blockIdx.x);
+    const Job& J = jobs[jid];
     const MapDesc& M = maps[J.map];
     if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) cs->ray_count = gridDim.x * (u32)kTileSimple;
     __syncthreads();
     const u32 first = (blockIdx.x - J.tile0) * kTileSimple;
-    float q[4][3];
-    u32 valid_mask = 0;
-    u32 n_inv = 0, n_oob = 0;
+    u32 n_valid = 0, n_inv = 0, n_oob = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        u32 i = first + threadIdx.x + 256u * j;
+        const u32 i = first + threadIdx.x + 256u * j;
+        const size_t slot = (size_t)blockIdx.x * kTileSimple + threadIdx.x + 256u * j;
+        u32 job = kNoRay;
         if (i < J.n) {
             const float x = J.pts[3 * (size_t)i], y = J.pts[3 * (size_t)i + 1], z = J.pts[3 * (size_t)i + 2];
-            int c = classify_point(M, J.pose, x, y, z, q[j]);
-            if (c == 1) valid_mask |= 1u << j;
-            else if (c == 0) n_inv++;
-            else n_oob++;
+            float q[3];
+            const int c = classify_point(M, J.pose, x, y, z, q);
+            if (c == 1) {
+                // per-point weight: Eq. (2) 1, or the 1/z^2 factor of Eq. (5)
+                const float wgt = M.weighting == 1 ? 1.0f / (z * z) : 1.0f;
+                rays_p[slot] = make_float4(q[0], q[1], q[2], wgt);
+                job = (u32)jid;
+                n_valid++;
+            } else if (c == 0) {
+                n_inv++;
+            } else {
+                n_oob++;
+            }
         }
+        rays_job[slot] = job;
     }
-    u32 nv = __builtin_popcount(valid_mask);
-    u32 tot;
-    u32 incl = block_scan_256(nv, lds8, &tot);
+    if (n_valid) atomicAdd(&s_cnt[0], n_valid);
     if (n_inv) atomicAdd(&s_cnt[1], n_inv);
     if (n_oob) atomicAdd(&s_cnt[2], n_oob);
-    if (threadIdx.x == 0) s_base = tot ? atomicAdd(&cs->ray_count, tot) : 0;
     __syncthreads();
-    u32 pos = s_base + incl - nv;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (valid_mask & (1u << j)) {
-            if (pos < ray_cap) {
-                // per-point weight: Eq. (2) 1, or the 1/z^2 factor of Eq. (5)
-                const float z = J.pts[3 * (size_t)(first + threadIdx.x + 256u * j) + 2];
-                float wgt = M.weighting == 1 ? 1.0f / (z * z) : 1.0f;
-                rays_p[pos] = make_float4(q[j][0], q[j][1], q[j][2], wgt);
-                rays_job[pos] = (u32)jid;
-            }
-            pos++;
-        }
-    }
     if (threadIdx.x == 0) {
-        if (tot) atomicAdd(&jst[jid].valid, (u64)tot);
+        if (s_cnt[0]) { atomicAdd(&jst[jid].valid, (u64)s_cnt[0]); atomicAdd(&jst[jid].rays, (u64)s_cnt[0]); }
         if (s_cnt[1]) atomicAdd(&jst[jid].invalid, (u64)s_cnt[1]);
         if (s_cnt[2]) atomicAdd(&jst[jid].oob_pts, (u64)s_cnt[2]);
-        if (tot) atomicAdd(&jst[jid].rays, (u64)tot);
     }
 }
 
@@ -189,11 +174,37 @@ __device__ inline void group_terms(const MapDesc& M, const float q[3], float z, 
     }
 }
 
+// Inserts a (map, block) key into the per-call block set; returns its slot (0xFFFFFFFF and a
+// call error when the set is full).
+__device__ inline u32 tset_insert(u64* tkeys, u32 tmask, u64 key, u32* tlist, u32 tlist_cap,
+                                  CallState* cs) {
+    u32 h = (u32)mix64(key) & tmask;
+    for (u32 probe = 0; probe <= tmask; ++probe) {
+        // always the atomic: a plain read may return a line cached before the slot was
+        // cleaned by the previous call, which would let one key enter two slots
+        u64 old = atomicCAS(&tkeys[h], kEmpty, key);
+        if (old == kEmpty) {
+            u32 t = atomicAdd(&cs->t_count, 1u);
+            if (t < tlist_cap) { tlist[t] = h; return h; }
+            cs->error = -3;   // more distinct blocks than the maps can hold
+            return 0xFFFFFFFFu;
+        }
+        if (old == key) return h;
+        h = (h + 1) & tmask;
+    }
+    cs->error = -3;
+    return 0xFFFFFFFFu;
+}
+
+// Grouped raycasting, step 1: the points of a tile are merged by voxel in an LDS hash (exact
+// integer sums); each partial group is written as one record, tagged with the block-set slot
+// of its voxel's block.  The block set is entered once per distinct block of the tile.
 __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ jobs, int njobs,
-                                                        int job_base,
                                                         const MapDesc* __restrict__ maps,
-                                                        GroupEntry* __restrict__ table, u32 tmask,
-                                                        u32* __restrict__ occ,
+                                                        u64* __restrict__ tkeys, u32 tmask,
+                                                        u32* __restrict__ tlist, u32 tlist_cap,
+                                                        Partial* __restrict__ parts,
+                                                        u32* __restrict__ tile_parts,
                                                         JobStat* __restrict__ jst,
                                                         CallState* __restrict__ cs) {
     __shared__ u64 s_key[kGroupSlots];
@@ -201,18 +212,18 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     __shared__ u64 s_sq[3][kGroupSlots];
     __shared__ u32 s_n[kGroupSlots];
     __shared__ u32 s_idx[kGroupSlots];
-    __shared__ u32 s_new[kTileGrouped];   // table entries this tile created
-    __shared__ u32 s_nnew, s_occ_base;
+    __shared__ u64 s_bkey[kGroupSlots];   // distinct (map, block) keys of the tile
+    __shared__ u32 s_bh[kGroupSlots];     // their block-set slots
     __shared__ u32 s_cnt[3];
-    const int jloc = job_of_tile(jobs, njobs, blockIdx.x);
-    const int jid = job_base + jloc;
-    const Job& J = jobs[jloc];
+    __shared__ u32 lds8[4];
+    const int jid = job_of_tile(jobs, njobs, blockIdx.x);
+    const Job& J = jobs[jid];
     const MapDesc& M = maps[J.map];
     for (int i = threadIdx.x; i < kGroupSlots; i += 256) {
         s_key[i] = kEmpty; s_so[i] = 0; s_sq[0][i] = 0; s_sq[1][i] = 0; s_sq[2][i] = 0; s_n[i] = 0;
+        s_bkey[i] = kEmpty;
     }
     if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) s_nnew = 0;
     __syncthreads();
 
     const u32 tile = blockIdx.x - J.tile0;
@@ -261,36 +272,51 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     if (n_oob) atomicAdd(&s_cnt[2], n_oob);
     __syncthreads();
 
-    // merge the tile's partial groups into the global table of this chunk of frames; new
-    // table entries are listed in LDS and appended to the occupied list with one atomic
-    const u64 tag = (u64)jloc << 57;
-    for (int s = threadIdx.x; s < kGroupSlots; s += 256) {
-        const u64 key = s_key[s];
+    // blocks of the tile's partial groups; reserve the output range
+    const u64 mapbits = (u64)M.map_id << 45;
+    u32 mine = 0;
+    for (int k = threadIdx.x; k < kGroupSlots; k += 256) {
+        const u64 key = s_key[k];
         if (key == kEmpty) continue;
-        const u64 gk = tag | key;
-        u32 h = (u32)mix64(gk) & tmask;
+        mine++;
+        const u64 bk = mapbits | (key >> 12);
+        u32 b = (u32)mix64(bk) & (kGroupSlots - 1);
         for (;;) {
-            u64 old = atomicCAS(&table[h].key, kEmpty, gk);
-            if (old == kEmpty) { s_new[atomicAdd(&s_nnew, 1u)] = h; break; }
-            if (old == gk) break;
-            h = (h + 1) & tmask;
+            u64 old = atomicCAS(&s_bkey[b], kEmpty, bk);
+            if (old == kEmpty || old == bk) break;
+            b = (b + 1) & (kGroupSlots - 1);
         }
-        GroupEntry* E = &table[h];
-        atomicAdd(&E->so, s_so[s]);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const u64 add = s_sq[k][s];
-            const u64 old = atomicAdd(&E->sq[k], add);
-            if (old + add < old) atomicAdd(&E->sqhi[k], 1u);   // carry into the high word
-        }
-        const u32 n = s_n[s];
-        atomicAdd(&E->n, n);
-        if (n == 1) E->idx = s_idx[s];
+    }
+    // partials of tile k take slots [k * kTileGrouped, k * kTileGrouped + count): a tile has at
+    // most kTileGrouped points, so the slots never overlap and no counter is shared
+    u32 tot;
+    const u32 incl = block_scan_256(mine, lds8, &tot);
+    if (threadIdx.x == 0) tile_parts[blockIdx.x] = tot;
+    for (int k = threadIdx.x; k < kGroupSlots; k += 256) {
+        const u64 bk = s_bkey[k];
+        if (bk != kEmpty) s_bh[k] = tset_insert(tkeys, tmask, bk, tlist, tlist_cap, cs);
     }
     __syncthreads();
-    if (threadIdx.x == 0) s_occ_base = s_nnew ? atomicAdd(&cs->occ_count, s_nnew) : 0u;
-    __syncthreads();
-    for (u32 k = threadIdx.x; k < s_nnew; k += 256) occ[s_occ_base + k] = s_new[k];
+    size_t pos = (size_t)blockIdx.x * kTileGrouped + incl - mine;
+    const u32 jm12 = J.jm << 12;
+    for (int k = threadIdx.x; k < kGroupSlots; k += 256) {
+        const u64 key = s_key[k];
+        if (key == kEmpty) continue;
+        const u64 bk = mapbits | (key >> 12);
+        u32 b = (u32)mix64(bk) & (kGroupSlots - 1);
+        while (s_bkey[b] != bk) b = (b + 1) & (kGroupSlots - 1);
+        {
+            Partial P;
+            P.so = s_so[k];
+            P.sq[0] = s_sq[0][k]; P.sq[1] = s_sq[1][k]; P.sq[2] = s_sq[2][k];
+            P.h = s_bh[b];
+            P.lj = jm12 | (u32)(key & 4095u);
+            P.n = s_n[k];
+            P.idx = s_idx[k];
+            parts[pos] = P;
+        }
+        pos++;
+    }
     if (threadIdx.x == 0) {
         if (s_cnt[0]) atomicAdd(&jst[jid].valid, (u64)s_cnt[0]);
         if (s_cnt[1]) atomicAdd(&jst[jid].invalid, (u64)s_cnt[1]);
@@ -298,102 +324,210 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     }
 }
 
-// One ray per group: its end point is the exact weighted mean (singletons keep the point),
-// its weight the group's summed weight.  Cleans the table entry for the next chunk.
-__global__ __launch_bounds__(256) void k_groups_to_rays(const Job* __restrict__ jobs, int job_base,
-                                                        const MapDesc* __restrict__ maps,
-                                                        GroupEntry* __restrict__ table,
-                                                        const u32* __restrict__ occ,
-                                                        float4* __restrict__ rays_p,
-                                                        u32* __restrict__ rays_job,
-                                                        JobStat* __restrict__ jst,
-                                                        CallState* __restrict__ cs, u32 ray_cap) {
-    __shared__ u32 lds8[4];
-    __shared__ u32 s_base;
-    const u32 nocc = cs->occ_count;
-    for (u32 base = blockIdx.x * 256u; base < nocc; base += gridDim.x * 256u) {
-        const u32 i = base + threadIdx.x;
-        const bool act = i < nocc;
-        float4 ray = make_float4(0.f, 0.f, 0.f, 0.f);
-        u32 jid = 0;
+// Dense index of every block-set entry listed so far (its list position).
+__global__ __launch_bounds__(256) void k_densify(const u32* __restrict__ tlist, u32 tlist_cap,
+                                                 u32* __restrict__ tval,
+                                                 const CallState* __restrict__ cs) {
+    const u32 nt = cs->error ? 0u : (cs->t_count < tlist_cap ? cs->t_count : tlist_cap);
+    for (u32 i = blockIdx.x * 256u + threadIdx.x; i < nt; i += gridDim.x * 256u) tval[tlist[i]] = i;
+}
+
+// Grouped raycasting, step 2: counting sort of the partial groups by (block, frame).  One
+// wave per tile walks the tile's partials.
+__global__ __launch_bounds__(256) void k_gbin_count(const Partial* __restrict__ parts,
+                                                    const u32* __restrict__ tile_parts, u32 ntiles,
+                                                    const u32* __restrict__ tval,
+                                                    u32* __restrict__ bins, u32 JM,
+                                                    const CallState* __restrict__ cs) {
+    if (cs->error) return;
+    const u32 tile = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;   // whole wave
+    const int lane = lane_id();
+    const u32 np = tile_parts[tile];
+    const Partial* tp = parts + (size_t)tile * kTileGrouped;
+    for (u32 b0 = 0; b0 < np; b0 += 64) {
+        const u32 i = b0 + (u32)lane;
+        u32 b = 0;
+        if (i < np) b = tval[tp[i].h] * JM + (tp[i].lj >> 12);
+        wave_count_by_key(bins, i < np, b);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ parts,
+                                                  const u32* __restrict__ tile_parts, u32 ntiles,
+                                                  const u32* __restrict__ tval,
+                                                  u32* __restrict__ bins, const u32* __restrict__ off,
+                                                  u32 JM, Partial* __restrict__ sorted,
+                                                  const CallState* __restrict__ cs) {
+    if (cs->error) return;
+    const u32 tile = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;   // whole wave
+    const int lane = lane_id();
+    const u32 np = tile_parts[tile];
+    const Partial* tp = parts + (size_t)tile * kTileGrouped;
+    for (u32 b0 = 0; b0 < np; b0 += 64) {
+        const u32 i = b0 + (u32)lane;
+        const bool act = i < np;
+        u32 b = 0;
+        Partial P;
         if (act) {
-            const u32 h = occ[i];
-            GroupEntry E = table[h];
-            const u32 jloc = (u32)(E.key >> 57);
-            jid = job_base + jloc;
-            const Job& J = jobs[jloc];
-            const MapDesc& M = maps[J.map];
-            int g[3];
-            unpack_voxel(E.key & ((1ull << 57) - 1), g[0], g[1], g[2]);
-            float p[3];
-            if (E.n == 1) {
-                const float x = J.pts[3 * (size_t)E.idx], y = J.pts[3 * (size_t)E.idx + 1],
-                            z = J.pts[3 * (size_t)E.idx + 2];
-                classify_point(M, J.pose, x, y, z, p);
-            } else {
-                const double den = (double)E.so * 1048576.0;
+            P = tp[i];
+            b = tval[P.h] * JM + (P.lj >> 12);
+        }
+        u64 pending = __ballot(act);
+        u32 pos = 0;
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const u32 kb = __shfl(b, leader);
+            const bool mine = ((pending >> lane) & 1ull) && b == kb;
+            const u64 grp = __ballot(mine);
+            u32 old = 0;
+            if (lane == leader) old = atomicSub(&bins[kb], (u32)__popcll(grp));
+            old = __shfl(old, leader);
+            if (mine) pos = off[kb] + old - 1u - (u32)__popcll(grp & ((1ull << lane) - 1ull));
+            pending &= ~grp;
+        }
+        if (act) sorted[pos] = P;
+    }
+}
+
+// Grouped raycasting, step 3: one workgroup per (block, frame) bin merges the bin's partial
+// groups by voxel (exact integer sums, 1024 voxels of the block per pass) and casts one ray
+// per group: the exact weighted mean (a single point keeps the point), the summed weight.
+constexpr int kMergeVox = 1024;
+constexpr int kMergeGrab = 64;      // bins per work grab
+
+__global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ jobs,
+                                                     const MapDesc* __restrict__ maps,
+                                                     const u64* __restrict__ tkeys,
+                                                     const u32* __restrict__ tlist,
+                                                     const u32* __restrict__ off,
+                                                     const Partial* __restrict__ sorted, u32 JM,
+                                                     float4* __restrict__ rays_p,
+                                                     u32* __restrict__ rays_job,
+                                                     JobStat* __restrict__ jst,
+                                                     CallState* __restrict__ cs) {
+    __shared__ u64 m_so[kMergeVox];
+    __shared__ u64 m_sq[3][kMergeVox];
+    __shared__ u32 m_hi[3][kMergeVox];
+    __shared__ u32 m_n[kMergeVox];
+    __shared__ u32 m_idx[kMergeVox];
+    __shared__ u32 s_b0, s_quarters, s_nr;
+    __shared__ u32 s_off[kMergeGrab + 1];
+    __shared__ u32 lds8[4];
+    for (int i = threadIdx.x; i < kMergeVox; i += 256) {
+        m_so[i] = 0; m_sq[0][i] = 0; m_sq[1][i] = 0; m_sq[2][i] = 0;
+        m_hi[0][i] = 0; m_hi[1][i] = 0; m_hi[2][i] = 0; m_n[i] = 0;
+    }
+    const u32 nb = cs->error ? 0u : cs->t_count * JM;
+    // the rays of bin b take slots [off[b], off[b] + groups) -- a bin has at least as many
+    // partials as groups -- and the rest of the bin's range is left empty
+    if (blockIdx.x == 0 && threadIdx.x == 0) cs->ray_count = nb ? off[nb] : 0u;
+    for (;;) {
+    // bins are taken kMergeGrab at a time; their offsets are staged in LDS
+    if (threadIdx.x == 0) s_b0 = atomicAdd(&cs->work_merge, (u32)kMergeGrab);
+    __syncthreads();
+    const u32 b0 = s_b0;
+    if (b0 >= nb) break;
+    const u32 bn = nb - b0 < (u32)kMergeGrab ? nb - b0 : (u32)kMergeGrab;
+    for (u32 k = threadIdx.x; k <= bn; k += 256) s_off[k] = off[b0 + k];
+    __syncthreads();
+    for (u32 bi = 0; bi < bn; ++bi) {
+        const u32 b = b0 + bi;
+        const u32 lo = s_off[bi], hi = s_off[bi + 1];
+        if (lo == hi) continue;
+        if (threadIdx.x == 0) { s_quarters = 0; s_nr = 0; }
+        __syncthreads();
+        const u32 t = b / JM, jm = b - t * JM;
+        const u64 tk = tkeys[tlist[t]];
+        const MapDesc& M = maps[(u32)(tk >> 45)];
+        const int jid = M.job0 + (int)jm;
+        const Job& J = jobs[jid];
+        int bx, by, bz;
+        unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
+        u32 qm = 0;
+        for (u32 e = lo + threadIdx.x; e < hi; e += 256) qm |= 1u << ((sorted[e].lj & 4095u) >> 10);
+        if (qm) atomicOr(&s_quarters, qm);
+        __syncthreads();
+        const u32 quarters = s_quarters;
+        u32 nrays_bin = 0;
+        for (int qd = 0; qd < 4; ++qd) {
+            if (!(quarters & (1u << qd))) continue;
+            for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
+                const Partial& P = sorted[e];
+                const u32 l = P.lj & 4095u;
+                if ((int)(l >> 10) != qd) continue;
+                const u32 v = l & (kMergeVox - 1);
+                atomicAdd(&m_so[v], P.so);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    const double hi = (double)(u64)E.sqhi[k];
-                    const double lo = (double)E.sq[k];
-                    const double m = (hi * 18446744073709551616.0 + lo) / den;
-                    p[k] = (float)(((double)g[k] + m) * (double)M.v);
+                    const u64 old = atomicAdd(&m_sq[k][v], P.sq[k]);
+                    if (old + P.sq[k] < old) atomicAdd(&m_hi[k][v], 1u);   // carry
                 }
+                atomicAdd(&m_n[v], P.n);
+                if (P.n == 1) m_idx[v] = P.idx;
             }
-            const float wgt = M.wbits > 0 ? (float)((double)E.so * __builtin_ldexp(1.0, -M.wbits))
-                                          : (float)E.n;
-            ray = make_float4(p[0], p[1], p[2], wgt);
-            GroupEntry Z;
-            Z.key = kEmpty; Z.so = 0; Z.sq[0] = Z.sq[1] = Z.sq[2] = 0;
-            Z.sqhi[0] = Z.sqhi[1] = Z.sqhi[2] = 0; Z.n = 0; Z.idx = 0; Z.pad = 0;
-            table[h] = Z;
-        }
-        u32 tot;
-        const u32 incl = block_scan_256(act ? 1u : 0u, lds8, &tot);
-        if (threadIdx.x == 0) s_base = atomicAdd(&cs->ray_count, tot);
-        __syncthreads();
-        if (act) {
-            const u32 pos = s_base + incl - 1;
-            if (pos < ray_cap) { rays_p[pos] = ray; rays_job[pos] = jid; }
-        }
-        // per-frame ray counts, aggregated per wave
-        {
-            u64 pending = __ballot(act);
-            const int lane = lane_id();
-            while (pending) {
-                int leader = __ffsll((long long)pending) - 1;
-                u32 k = __shfl(jid, leader);
-                u64 grp = __ballot(((pending >> lane) & 1ull) && jid == k);
-                if (lane == leader) atomicAdd(&jst[k].rays, (u64)__popcll(grp));
-                pending &= ~grp;
+            __syncthreads();
+            float4 ray[4];
+            bool has[4];
+            u32 nmine = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int v = threadIdx.x + 256 * r;
+                const u32 n = m_n[v];
+                has[r] = n != 0;
+                ray[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (!n) continue;
+                const int l = qd * kMergeVox + v;
+                const int g[3] = {16 * bx + (l & 15), 16 * by + ((l >> 4) & 15), 16 * bz + (l >> 8)};
+                float p[3];
+                if (n == 1) {
+                    const u32 idx = m_idx[v];
+                    classify_point(M, J.pose, J.pts[3 * (size_t)idx], J.pts[3 * (size_t)idx + 1],
+                                   J.pts[3 * (size_t)idx + 2], p);
+                } else {
+                    const double den = (double)m_so[v] * 1048576.0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const double hi_d = (double)(u64)m_hi[k][v];
+                        const double lo_d = (double)m_sq[k][v];
+                        const double m = (hi_d * 18446744073709551616.0 + lo_d) / den;
+                        p[k] = (float)(((double)g[k] + m) * (double)M.v);
+                    }
+                }
+                const float wgt = M.wbits > 0 ? (float)((double)m_so[v] * __builtin_ldexp(1.0, -M.wbits))
+                                              : (float)n;
+                ray[r] = make_float4(p[0], p[1], p[2], wgt);
+                nmine++;
+                m_so[v] = 0; m_sq[0][v] = 0; m_sq[1][v] = 0; m_sq[2][v] = 0;
+                m_hi[0][v] = 0; m_hi[1][v] = 0; m_hi[2][v] = 0; m_n[v] = 0;
             }
+            u32 tot;
+            const u32 incl = block_scan_256(nmine, lds8, &tot);
+            u32 pos = lo + s_nr + incl - nmine;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (!has[r]) continue;
+                rays_p[pos] = ray[r];
+                rays_job[pos] = (u32)jid;
+                pos++;
+            }
+            nrays_bin += tot;
+            __syncthreads();
+            if (threadIdx.x == 0) s_nr += tot;
+            __syncthreads();
         }
+        for (u32 e = lo + nrays_bin + threadIdx.x; e < hi; e += 256) rays_job[e] = kNoRay;
+        if (threadIdx.x == 0 && nrays_bin) atomicAdd(&jst[jid].rays, (u64)nrays_bin);
         __syncthreads();
+    }
+    __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
 // cross: walk the band of each ray, record (block, ray) crossings
 // ---------------------------------------------------------------------------
-// Inserts a (map, block) key into the per-call block set; returns its slot.
-__device__ inline u32 tset_insert(u64* tkeys, u32 tmask, u64 key, u32* tlist, u32 tlist_cap,
-                                  CallState* cs) {
-    u32 h = (u32)mix64(key) & tmask;
-    for (u32 probe = 0; probe <= tmask; ++probe) {
-        u64 old = atomicCAS(&tkeys[h], kEmpty, key);
-        if (old == kEmpty) {
-            u32 t = atomicAdd(&cs->t_count, 1u);
-            if (t < tlist_cap) { tlist[t] = h; return h; }
-            cs->error = -3;   // more distinct blocks than the maps can hold
-            return 0xFFFFFFFFu;
-        }
-        if (old == key) return h;
-        h = (h + 1) & tmask;
-    }
-    cs->error = -3;
-    return 0xFFFFFFFFu;
-}
-
 // Per workgroup of 256 rays, in three phases separated by barriers:
 //  1. walk every ray, count its block crossings and enter the block keys in an LDS set;
 //  2. insert each distinct block of the workgroup once into the per-call block set;
@@ -420,25 +554,26 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                                                const u32* __restrict__ rays_job,
                                                u64* __restrict__ tkeys, u32 tmask,
                                                u32* __restrict__ tlist, u32 tlist_cap,
-                                               uint2* __restrict__ cross, u32 cross_cap,
-                                               JobStat* __restrict__ jst,
+                                               u32* __restrict__ cross, unsigned char* __restrict__ ncross,
+                                               u32 MB, JobStat* __restrict__ jst,
                                                CallState* __restrict__ cs, u32 ray_cap) {
     __shared__ u64 s_key[kCrossSlots];
     __shared__ u32 s_h[kCrossSlots];
-    __shared__ u32 lds8[4];
-    __shared__ u32 s_base;
     const u32 nrays = cs->ray_count < ray_cap ? cs->ray_count : ray_cap;
     for (u32 base = blockIdx.x * 256u; base < nrays; base += gridDim.x * 256u) {
         for (int i = threadIdx.x; i < kCrossSlots; i += 256) s_key[i] = kEmpty;
         __syncthreads();
         const u32 i = base + threadIdx.x;
-        bool ok = false;
+        bool ok = false, live = false;
         u32 jid = 0;
         float p[3] = {0.f, 0.f, 0.f}, s[3] = {0.f, 0.f, 0.f};
         u64 mapbits = 0;
         const MapDesc* Mp = maps;
         if (i < nrays) {
             jid = rays_job[i];
+            live = jid != kNoRay;
+        }
+        if (live) {
             const Job& J = jobs[jid];
             Mp = &maps[J.map];
             const float4 rp = rays_p[i];
@@ -448,59 +583,51 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
             float e[3], r;
             Walk w;
             ok = walk_setup(*Mp, p, s, e, r, w);
-        }
-        // phase 1
-        u32 ncross = 0;
-        if (ok) {
-            float e[3], r;
-            Walk w;
-            walk_setup(*Mp, p, s, e, r, w);
-            u64 cur = kEmpty;
-            for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
-                const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
-                if (bk != cur) {
-                    cur = bk;
-                    lds_set_insert(s_key, mapbits | bk);
-                    ncross++;
+            // phase 1: the blocks the band enters, entered in the workgroup's LDS set
+            if (ok) {
+                u64 cur = kEmpty;
+                for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
+                    const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
+                    if (bk != cur) {
+                        cur = bk;
+                        lds_set_insert(s_key, mapbits | bk);
+                    }
+                    if (w.left == 0) break;
+                    walk_step(w);
                 }
-                if (w.left == 0) break;
-                walk_step(w);
             }
         }
-        u32 tot;
-        const u32 incl = block_scan_256(ncross, lds8, &tot);
-        if (threadIdx.x == 0) {
-            const u32 b0 = atomicAdd(&cs->cross_count, tot);
-            if ((u64)b0 + tot > cross_cap) cs->error = -4;
-            s_base = b0;
-        }
-        // phase 2
+        __syncthreads();
+        // phase 2: each distinct block of the workgroup enters the per-call block set once
         for (int k = threadIdx.x; k < kCrossSlots; k += 256) {
             const u64 key = s_key[k];
             if (key != kEmpty) s_h[k] = tset_insert(tkeys, tmask, key, tlist, tlist_cap, cs);
         }
         __syncthreads();
-        // phase 3
-        if (ok) {
-            u32 pos = s_base + incl - ncross;
-            float e[3], r;
-            Walk w;
-            walk_setup(*Mp, p, s, e, r, w);
-            u64 cur = kEmpty;
-            for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
-                const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
-                if (bk != cur) {
-                    cur = bk;
-                    const u32 h = s_h[lds_set_find(s_key, mapbits | bk)];
-                    if (pos < cross_cap && h != 0xFFFFFFFFu) cross[pos] = make_uint2(h, i);
-                    pos++;
+        // phase 3: crossing c of ray slot i goes to cross[i * MB + c]
+        if (i < nrays) {
+            u32 nc = 0;
+            if (ok) {
+                float e[3], r;
+                Walk w;
+                walk_setup(*Mp, p, s, e, r, w);
+                u64 cur = kEmpty;
+                for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
+                    const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
+                    if (bk != cur) {
+                        cur = bk;
+                        if (nc < MB) cross[(size_t)i * MB + nc] = s_h[lds_set_find(s_key, mapbits | bk)];
+                        nc++;
+                    }
+                    if (w.left == 0) break;
+                    walk_step(w);
                 }
-                if (w.left == 0) break;
-                walk_step(w);
+                if (nc > MB) { cs->error = -4; nc = MB; }   // cannot happen: MB bounds the band
             }
+            ncross[i] = (unsigned char)nc;
         }
         // out-of-bounds rays per frame (rare); rays were counted when created
-        const bool oob = i < nrays && !ok;
+        const bool oob = live && !ok;
         u64 pending = __ballot(oob);
         const int lane = lane_id();
         while (pending) {
@@ -517,25 +644,42 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
 // ---------------------------------------------------------------------------
 // resolve / commit: wavefront-cooperative probing of the map's block hash
 // ---------------------------------------------------------------------------
-// The 64 lanes of a wave read 64 consecutive slots of the probe sequence at once and vote
-// for a match or a free slot.  Keys are never deleted, so a key is absent when a free slot
-// comes before any match.  Returns the slot index holding key, or -1 (with *free_at set to
-// the first free slot of the probe sequence).  Wave-uniform arguments and result.
-__device__ inline int coop_find(const u64* __restrict__ hkeys, u32 hmask, u64 key, u32* free_at) {
+// Wavefront-cooperative probing: the wave splits into groups of kProbeLanes lanes; each group
+// probes one key, its lanes reading consecutive slots of the key's probe sequence at once and
+// voting (ballot) for a match or a free slot.  Keys are never deleted during a call, so a key
+// is absent when a free slot comes before any match.  A wave probes 64 / kProbeLanes keys at
+// a time.  Returns the slot holding `key` or -1, with *free_at = the first free slot seen.
+constexpr int kProbeLanes = 8;
+
+__device__ inline int coop_find(const u64* __restrict__ hkeys, u32 hmask, u64 key, bool active,
+                                u32* free_at) {
     const int lane = lane_id();
+    const int sub = lane & (kProbeLanes - 1);
+    const int gshift = lane - sub;                       // first lane of this group
+    const u64 gmask = ((1ull << kProbeLanes) - 1ull) << gshift;
     const u32 start = (u32)mix64(key) & hmask;
-    for (u32 base = 0; base <= hmask; base += 64) {
-        const u32 slot = (start + base + lane) & hmask;
-        const u64 k = hkeys[slot];
-        const u64 match = __ballot(k == key);
-        const u64 empty = __ballot(k == kEmpty);
-        const int fm = match ? __ffsll((long long)match) : 65;
-        const int fe = empty ? __ffsll((long long)empty) : 65;
-        if (fm < fe) return (int)((start + base + fm - 1) & hmask);
-        if (fe < 65) { *free_at = (start + base + fe - 1) & hmask; return -1; }
-    }
+    int result = -1;
     *free_at = 0xFFFFFFFFu;
-    return -1;
+    bool done = !active;
+    for (u32 base = 0; base <= hmask; base += kProbeLanes) {
+        if (__ballot(!done) == 0ull) break;
+        const u32 slot = (start + base + (u32)sub) & hmask;
+        const u64 k = done ? kEmpty : hkeys[slot];
+        const u64 match = (__ballot(!done && k == key) & gmask) >> gshift;
+        const u64 empty = (__ballot(!done && k == kEmpty) & gmask) >> gshift;
+        if (!done) {
+            const int fm = match ? __ffsll((long long)match) : 65;
+            const int fe = empty ? __ffsll((long long)empty) : 65;
+            if (fm < fe) {
+                result = (int)((start + base + (u32)fm - 1u) & hmask);
+                done = true;
+            } else if (fe < 65) {
+                *free_at = (start + base + (u32)fe - 1u) & hmask;
+                done = true;
+            }
+        }
+    }
+    return result;
 }
 
 __global__ __launch_bounds__(256) void k_resolve(const MapDesc* __restrict__ maps,
@@ -546,34 +690,28 @@ __global__ __launch_bounds__(256) void k_resolve(const MapDesc* __restrict__ map
                                                  CallState* __restrict__ cs) {
     const u32 nt = cs->error ? 0u : cs->t_count;
     const int lane = lane_id();
-    const u32 wave_global = (blockIdx.x * 256u + threadIdx.x) >> 6;
-    const u32 nwaves = (gridDim.x * 256u) >> 6;
-    for (u32 wbase = wave_global * 64u; wbase < nt; wbase += nwaves * 64u) {
-        const u32 i = wbase + lane;
+    constexpr u32 per = 64 / kProbeLanes;          // entries per wave per round
+    const u32 wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
+    const u32 nwaves = gridDim.x * 4u;
+    for (u32 wb = wave * per; wb < nt; wb += nwaves * per) {
+        // lane group g of the wave owns entry wb + g
+        const u32 i = wb + (u32)lane / kProbeLanes;
+        const bool act = i < nt;
         u64 key = kEmpty;
-        if (i < nt) {
-            const u32 h = tlist[i];
+        u32 h = 0;
+        if (act) {
+            h = tlist[i];
             key = tkeys[h];
+        }
+        const MapDesc& M = maps[act ? (u32)(key >> 45) : 0u];
+        u32 free_at;
+        const int pos = coop_find(M.hkeys, M.hmask, key & ((1ull << 45) - 1), act, &free_at);
+        if (act && (lane & (kProbeLanes - 1)) == 0) {
             tval[h] = i;
             t_key[i] = key;
-        }
-        int my_slot = -1;
-        u64 act = __ballot(i < nt);
-        while (act) {
-            const int l = __ffsll((long long)act) - 1;
-            act &= act - 1;
-            const u64 k = __shfl(key, l);
-            const MapDesc& M = maps[(u32)(k >> 45)];
-            u32 free_at;
-            const int pos = coop_find(M.hkeys, M.hmask, k & ((1ull << 45) - 1), &free_at);
-            const int slot = pos >= 0 ? M.hslots[pos] : -1;
-            if (lane == l) my_slot = slot;
-        }
-        if (i < nt) {
-            if (my_slot >= 0) {
-                t_slot[i] = my_slot;
+            if (pos >= 0) {
+                t_slot[i] = M.hslots[pos];
             } else {
-                const MapDesc& M = maps[(u32)(key >> 45)];
                 const u32 rank = atomicAdd(&M.st->new_count, 1u);
                 t_slot[i] = -(int)rank - 2;   // pending: -2 - rank
             }
@@ -587,50 +725,46 @@ __global__ __launch_bounds__(256) void k_commit(const MapDesc* __restrict__ maps
                                                 CallState* __restrict__ cs) {
     const u32 nt = cs->error ? 0u : cs->t_count;
     const int lane = lane_id();
-    const u32 wave_global = (blockIdx.x * 256u + threadIdx.x) >> 6;
-    const u32 nwaves = (gridDim.x * 256u) >> 6;
-    for (u32 wbase = wave_global * 64u; wbase < nt; wbase += nwaves * 64u) {
-        const u32 i = wbase + lane;
+    constexpr u32 per = 64 / kProbeLanes;
+    const u32 wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
+    const u32 nwaves = gridDim.x * 4u;
+    for (u32 wb = wave * per; wb < nt; wb += nwaves * per) {
+        const u32 i = wb + (u32)lane / kProbeLanes;
         bool pending = false;
         u64 key = kEmpty;
         int slot = 0;
         if (i < nt) {
             key = t_key[i];
-            const int s = t_slot[i];
-            if (s <= -2) {
+            const int sv = t_slot[i];
+            if (sv <= -2) {
                 const MapDesc& M = maps[(u32)(key >> 45)];
                 MapState* st = M.st;
-                const u32 rank = (u32)(-s - 2);
-                if (st->error == 0 && (u64)st->block_count + st->new_count <= M.capacity && cs->error == 0) {
+                const u32 rank = (u32)(-sv - 2);
+                if (st->error == 0 && (u64)st->block_count + st->new_count <= M.capacity) {
                     pending = true;
                     slot = (int)(st->block_count + rank);
                 } else {
-                    if (cs->error == 0) st->error = -3;   // VBX_ERR_POOL_FULL, map left unchanged
+                    st->error = -3;   // VBX_ERR_POOL_FULL: this call leaves the map unchanged
                 }
             }
         }
-        u64 act = __ballot(pending);
-        while (act) {
-            const int l = __ffsll((long long)act) - 1;
-            act &= act - 1;
-            const u64 k = __shfl(key, l);
-            const int sl = __shfl(slot, l);
-            const MapDesc& M = maps[(u32)(k >> 45)];
-            const u64 bk = k & ((1ull << 45) - 1);
-            for (;;) {
-                u32 free_at;
-                const int pos = coop_find(M.hkeys, M.hmask, bk, &free_at);
-                if (pos >= 0 || free_at == 0xFFFFFFFFu) break;   // present (cannot happen) or full
-                u64 old = 0;
-                if (lane == 0) old = atomicCAS(&M.hkeys[free_at], kEmpty, bk);
-                old = __shfl(old, 0);
-                if (old == kEmpty) {
-                    if (lane == 0) M.hslots[free_at] = sl;
-                    break;
-                }
+        const MapDesc& M = maps[pending ? (u32)(key >> 45) : 0u];
+        const u64 bk = key & ((1ull << 45) - 1);
+        bool todo = pending;
+        while (__ballot(todo) != 0ull) {
+            u32 free_at;
+            const int pos = coop_find(M.hkeys, M.hmask, bk, todo, &free_at);
+            if (todo && (pos >= 0 || free_at == 0xFFFFFFFFu)) todo = false;   // present or full
+            bool won = false;
+            if (todo && (lane & (kProbeLanes - 1)) == 0) {
+                won = atomicCAS(&M.hkeys[free_at], kEmpty, bk) == kEmpty;
+                if (won) M.hslots[free_at] = slot;
             }
+            // the group leader's outcome decides for the whole group
+            const u64 wonmask = __ballot(won);
+            if (todo && ((wonmask >> (lane & ~(kProbeLanes - 1))) & 1ull)) todo = false;
         }
-        if (pending) t_slot[i] = slot | (int)0x40000000;   // bit 30: new block
+        if (pending && (lane & (kProbeLanes - 1)) == 0) t_slot[i] = slot | (int)0x40000000;   // bit 30: new
     }
 }
 
@@ -638,20 +772,26 @@ __global__ __launch_bounds__(256) void k_commit(const MapDesc* __restrict__ maps
 // bins: counting sort of crossings by (block, frame)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bin_count(const Job* __restrict__ jobs,
-                                                   const uint2* __restrict__ cross,
+                                                   const u32* __restrict__ cross,
+                                                   const unsigned char* __restrict__ ncross, u32 MB,
                                                    const u32* __restrict__ tval,
                                                    const u32* __restrict__ rays_job,
                                                    u32* __restrict__ bins, u32 JM,
-                                                   CallState* __restrict__ cs) {
-    const u32 nc = cs->error ? 0u : cs->cross_count;
-    for (u32 base = blockIdx.x * 256u; base < nc; base += gridDim.x * 256u) {
+                                                   CallState* __restrict__ cs, u32 ray_cap) {
+    const u32 nr = cs->error ? 0u : (cs->ray_count < ray_cap ? cs->ray_count : ray_cap);
+    for (u32 base = blockIdx.x * 256u; base < nr; base += gridDim.x * 256u) {
         const u32 i = base + threadIdx.x;
-        u32 b = 0;
-        if (i < nc) {
-            const uint2 c = cross[i];
-            b = tval[c.x] * JM + jobs[rays_job[c.y]].jm;
+        u32 nc = 0, jm = 0;
+        if (i < nr) {
+            nc = ncross[i];
+            if (nc) jm = jobs[rays_job[i]].jm;
         }
-        wave_count_by_key(bins, i < nc, b);
+        for (u32 c = 0; c < MB; ++c) {
+            if (__ballot(c < nc) == 0ull) break;
+            const bool act = c < nc;
+            const u32 b = act ? tval[cross[(size_t)i * MB + c]] * JM + jm : 0u;
+            wave_count_by_key(bins, act, b);
+        }
     }
 }
 
@@ -726,42 +866,47 @@ __global__ __launch_bounds__(256) void k_scan_final(const u32* __restrict__ bins
 // kernel reads every (block, frame) bin contiguously.  Counts are decremented back to zero,
 // leaving the bins clean for the next call.
 __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ jobs,
-                                                 const uint2* __restrict__ cross,
+                                                 const u32* __restrict__ cross,
+                                                 const unsigned char* __restrict__ ncross, u32 MB,
                                                  const u32* __restrict__ tval,
                                                  const u32* __restrict__ rays_job,
                                                  u32* __restrict__ bins, const u32* __restrict__ off,
                                                  u32 JM, const float4* __restrict__ rays_p,
                                                  float4* __restrict__ sorted,
-                                                 CallState* __restrict__ cs) {
-    const u32 nc = cs->error ? 0u : cs->cross_count;
+                                                 CallState* __restrict__ cs, u32 ray_cap) {
+    const u32 nr = cs->error ? 0u : (cs->ray_count < ray_cap ? cs->ray_count : ray_cap);
     const int lane = lane_id();
-    for (u32 base = blockIdx.x * 256u; base < nc; base += gridDim.x * 256u) {
+    for (u32 base = blockIdx.x * 256u; base < nr; base += gridDim.x * 256u) {
         const u32 i = base + threadIdx.x;
-        const bool act = i < nc;
-        u32 b = 0, ray = 0;
-        if (act) {
-            const uint2 c = cross[i];
-            ray = c.y;
-            b = tval[c.x] * JM + jobs[rays_job[ray]].jm;
-        }
-        // lanes sharing a bin take consecutive positions reserved by one atomic
-        u64 pending = __ballot(act);
-        u32 pos = 0;
-        while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const u32 kb = __shfl(b, leader);
-            const bool mine = ((pending >> lane) & 1ull) && b == kb;
-            const u64 grp = __ballot(mine);
-            u32 old = 0;
-            if (lane == leader) old = atomicSub(&bins[kb], (u32)__popcll(grp));
-            old = __shfl(old, leader);
-            if (mine) {
-                const u32 rank = (u32)__popcll(grp & ((1ull << lane) - 1ull));
-                pos = off[kb] + old - 1u - rank;
+        u32 nc = 0, jm = 0;
+        float4 rp = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i < nr) {
+            nc = ncross[i];
+            if (nc) {
+                jm = jobs[rays_job[i]].jm;
+                rp = rays_p[i];
             }
-            pending &= ~grp;
         }
-        if (act) sorted[pos] = rays_p[ray];
+        for (u32 c = 0; c < MB; ++c) {
+            if (__ballot(c < nc) == 0ull) break;
+            const bool act = c < nc;
+            const u32 b = act ? tval[cross[(size_t)i * MB + c]] * JM + jm : 0u;
+            // lanes sharing a bin take consecutive positions reserved by one atomic
+            u64 pending = __ballot(act);
+            u32 pos = 0;
+            while (pending) {
+                const int leader = __ffsll((long long)pending) - 1;
+                const u32 kb = __shfl(b, leader);
+                const bool mine = ((pending >> lane) & 1ull) && b == kb;
+                const u64 grp = __ballot(mine);
+                u32 old = 0;
+                if (lane == leader) old = atomicSub(&bins[kb], (u32)__popcll(grp));
+                old = __shfl(old, leader);
+                if (mine) pos = off[kb] + old - 1u - (u32)__popcll(grp & ((1ull << lane) - 1ull));
+                pending &= ~grp;
+            }
+            if (act) sorted[pos] = rp;
+        }
     }
 }
 
@@ -1015,45 +1160,65 @@ __global__ __launch_bounds__(256) void k_cleanup(u64* __restrict__ tkeys, u32 tk
     }
 }
 
-__global__ __launch_bounds__(1024) void k_finish(const Job* __restrict__ jobs, int njobs,
-                                                 const MapDesc* __restrict__ maps, int nmaps,
-                                                 JobStat* __restrict__ jst,
-                                                 CallState* __restrict__ cs) {
-    if (threadIdx.x == 0) {
-        for (int m = 0; m < nmaps; ++m) {
-            MapState* st = maps[m].st;
-            const bool ok = st->error == 0 && cs->error == 0;
+__global__ __launch_bounds__(256) void k_finish(const Job* __restrict__ jobs, int njobs,
+                                                const MapDesc* __restrict__ maps, int nmaps,
+                                                JobStat* __restrict__ jst,
+                                                CallState* __restrict__ cs) {
+    __shared__ u64 s_acc[8];
+    for (int m = 0; m < nmaps; ++m) {
+        MapState* st = maps[m].st;
+        const bool ok = st->error == 0 && cs->error == 0;
+        if (threadIdx.x < 8) s_acc[threadIdx.x] = 0;
+        __syncthreads();
+        if (ok) {
+            u64 a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int j = maps[m].job0 + threadIdx.x; j < maps[m].job0 + maps[m].njobs; j += 256) {
+                const JobStat& s = jst[j];
+                a[0] += jobs[j].n;
+                a[1] += s.valid;
+                a[2] += s.invalid;
+                a[3] += s.oob_pts + s.oob_rays;
+                a[4] += s.rays - s.oob_rays;
+                a[5] += s.touches;
+                a[6] += s.voxels;
+                a[7] += s.cells;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (a[k]) atomicAdd(&s_acc[k], a[k]);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
             if (ok) {
                 st->new_blocks += st->new_count;
                 st->block_count += st->new_count;
                 st->calls += 1;
-                for (int j = maps[m].job0; j < maps[m].job0 + maps[m].njobs; ++j) {
-                    const JobStat& s = jst[j];
-                    st->points += jobs[j].n;
-                    st->valid += s.valid;
-                    st->invalid += s.invalid;
-                    st->oob += s.oob_pts + s.oob_rays;
-                    st->rays += s.rays - s.oob_rays;
-                    st->touches += s.touches;
-                    st->voxels += s.voxels;
-                    st->cells += s.cells;
-                }
+                st->points += s_acc[0];
+                st->valid += s_acc[1];
+                st->invalid += s_acc[2];
+                st->oob += s_acc[3];
+                st->rays += s_acc[4];
+                st->touches += s_acc[5];
+                st->voxels += s_acc[6];
+                st->cells += s_acc[7];
             }
             if (cs->error != 0 && st->error == 0) st->error = cs->error;
             st->new_count = 0;
         }
-        cs->ray_count = 0;
-        cs->cross_count = 0;
-        cs->t_count = 0;
-        cs->occ_count = 0;
-        cs->work_next = 0;
-        cs->error = 0;
+        __syncthreads();
     }
-    __syncthreads();
-    for (int j = threadIdx.x; j < njobs; j += blockDim.x) {
+    for (int j = threadIdx.x; j < njobs; j += 256) {
         JobStat z;
         z.valid = z.invalid = z.oob_pts = z.oob_rays = z.rays = z.touches = z.voxels = z.cells = 0;
         jst[j] = z;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cs->ray_count = 0;
+        cs->t_count = 0;
+        cs->work_next = 0;
+        cs->work_merge = 0;
+        cs->error = 0;
     }
 }
 

@@ -16,6 +16,8 @@ Conventions
   sensor's maximum range are kept (the integrator rejects them).
 * Poses are float32 [3, 4] row-major T_world_sensor.
 * Intersections are computed in float64 and written as float32.
+* Only elementwise numpy arithmetic is used (no BLAS products), so a frame is bit-identical
+  however many threads generate frames concurrently.
 """
 from __future__ import annotations
 
@@ -99,13 +101,18 @@ def _hit_boxes(o, d, boxes):
     return best
 
 
+def _dot3(d, v):
+    """Row-wise dot product of d [n, 3] with a 3-vector, elementwise (no BLAS)."""
+    return (d[:, 0] * v[0] + d[:, 1] * v[1]) + d[:, 2] * v[2]
+
+
 def _hit_spheres(o, d, spheres):
     best = np.full(d.shape[0], np.inf)
-    dd = np.einsum("ij,ij->i", d, d)
+    dd = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
     for c, r in spheres:
         oc = o - c
-        b = d @ oc
-        cc = oc @ oc - r * r
+        b = _dot3(d, oc)
+        cc = float((oc[0] * oc[0] + oc[1] * oc[1]) + oc[2] * oc[2]) - r * r
         disc = b * b - dd * cc
         ok = disc >= 0
         sq = np.sqrt(np.where(ok, disc, 0.0))
@@ -190,7 +197,7 @@ def _depth_frame(pose32, dirs_cam, hit_fn, sigma_fn, rng, invalid_rate=0.0):
     """Cast pixel rays, add depth noise, return camera-frame float32 points (NaN = invalid)."""
     pose = pose32.astype(np.float64)
     R, t = pose[:, :3], pose[:, 3]
-    d_world = dirs_cam @ R.T
+    d_world = np.stack([_dot3(dirs_cam, R[k]) for k in range(3)], axis=1)
     tz = hit_fn(t, d_world)                 # distance along d_world; dirs have unit z
     z = tz.copy()                           # camera-frame depth of the hit
     ok = np.isfinite(z)

@@ -198,3 +198,26 @@ def test_tuning_never_changes_results_and_autotune_leaves_map(vbx):
     after = g.export()
     assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
     assert g.tuning() == res["best"]
+
+
+def test_reused_map_and_scratch_repeat_bit_identical(vbx):
+    """Repeated clear + integrate on one map (the benchmark's pattern: scratch tables reused
+    across calls) gives the same map every time, equal to a fresh map's."""
+    frames = room(640, 480, 8, 81)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped",
+                  block_capacity=8192, keep_touches=False)
+    batch = [(dev(p), pose, 640) for p, pose in frames]
+    g = gpu_map(vbx, params)
+    ref = None
+    for rep in range(5):
+        g.clear()
+        g.integrate_frames(batch)
+        assert g.sync() == 0
+        out = g.export()
+        if ref is None:
+            ref = out
+        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), rep
+    fresh = gpu_map(vbx, params)
+    fresh.integrate_frames(batch)
+    assert fresh.sync() == 0
+    assert same_export(fresh, g)
