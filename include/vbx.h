@@ -210,10 +210,12 @@ int vbx_map_profile_read(vbx_map* map, vbx_profile* out, int reset);
 const char* vbx_profile_stage_name(int stage);
 
 /* Launch tuning of a map's calls.  Results never depend on it. */
-#define VBX_TUNING_CANDIDATES 3
+#define VBX_TUNING_CANDIDATES 5
 typedef struct {
-    int32_t update_split;   /* z-slabs per block in the update stage: 1, 2 or 4 (default 2) */
-    int32_t reserved[7];
+    int32_t update_split;   /* z-slabs per block in the update stage (default 2) */
+    int32_t update_threads; /* threads per update workgroup (default 256); the candidates are
+                               (split, threads) = (1,256) (2,256) (4,256) (4,64) (8,64) */
+    int32_t reserved[6];
 } vbx_tuning;
 
 int vbx_map_get_tuning(vbx_map* map, vbx_tuning* out);

@@ -67,11 +67,12 @@ EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_ma
             "vbx_map_profile", "vbx_map_profile_read", "vbx_profile_stage_name",
             "vbx_map_get_tuning", "vbx_map_set_tuning", "vbx_map_autotune"]
 
-TUNING_CANDIDATES = 3
+TUNING_CANDIDATES = 5
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("update_split", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("update_split", ctypes.c_int32), ("update_threads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 PROFILE_STAGES = 10
 
@@ -283,11 +284,12 @@ class Map:
     def tuning(self) -> dict:
         t = Tuning()
         _check(lib().vbx_map_get_tuning(self._h, ctypes.byref(t)), "vbx_map_get_tuning")
-        return {"update_split": int(t.update_split)}
+        return {"update_split": int(t.update_split), "update_threads": int(t.update_threads)}
 
-    def set_tuning(self, update_split: int):
+    def set_tuning(self, update_split: int, update_threads: int = 256):
         t = Tuning()
         t.update_split = update_split
+        t.update_threads = update_threads
         _check(lib().vbx_map_set_tuning(self._h, ctypes.byref(t)), "vbx_map_set_tuning")
 
     def autotune(self, frames) -> dict:
@@ -298,7 +300,8 @@ class Map:
         ms = (ctypes.c_double * TUNING_CANDIDATES)()
         _check(lib().vbx_map_autotune(self._h, arr, len(frames), ctypes.byref(best), ms),
                "vbx_map_autotune")
-        return {"best": {"update_split": int(best.update_split)}, "ms": list(ms)}
+        return {"best": {"update_split": int(best.update_split),
+                         "update_threads": int(best.update_threads)}, "ms": list(ms)}
 
     def stats(self) -> dict:
         s = Stats()

@@ -49,7 +49,7 @@ struct Stage {
 
 struct Scratch {
     DevBuf rays_p, rays_job, cross, ncross, sorted, tkeys, tval, tlist, t_key, t_slot, bins, off,
-        partial, parts, parts_sorted, tile_parts, touch_key, touch_n, tables, jst, cs;
+        partial, parts, parts_sorted, tile_parts, chunk_first, touch_key, touch_n, tables, jst, cs;
     size_t ray_cap = 0, cross_cap = 0, tkey_cap = 0, tlist_cap = 0, bins_cap = 0, nparts = 0,
            touch_cap = 0;
     Stage stage[4];
@@ -103,7 +103,7 @@ struct vbx_map {
     Scratch* scratch = nullptr;
     Scratch* touch_src = nullptr; // scratch holding this map's last touches
     int touch_idx = 0;
-    int update_split = 2;         // z-slabs per block in the update kernel (1, 2 or 4)
+    int update_variant = 1;       // index into kUpdateVariants
 };
 
 namespace {
@@ -228,7 +228,7 @@ void free_scratch(Scratch* s) {
     if (!s) return;
     DevBuf* bufs[] = {&s->rays_p, &s->rays_job, &s->cross, &s->ncross, &s->sorted, &s->tkeys,
                       &s->tval, &s->tlist, &s->t_key, &s->t_slot, &s->bins, &s->off, &s->partial,
-                      &s->parts, &s->parts_sorted, &s->tile_parts, &s->touch_key, &s->touch_n,
+                      &s->parts, &s->parts_sorted, &s->tile_parts, &s->chunk_first, &s->touch_key, &s->touch_n,
                       &s->tables, &s->jst, &s->cs};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -303,6 +303,7 @@ int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, si
         GROW(s->parts, ray_cap * sizeof(Partial));
         GROW(s->parts_sorted, ray_cap * sizeof(Partial));
         GROW(s->tile_parts, std::max<size_t>(plan.tiles, 1) * sizeof(u32));
+        GROW(s->chunk_first, (ray_cap / 512 + 2) * sizeof(u32));
     }
     if (plan.keep_touches) {
         GROW(s->touch_key, touch_cap * sizeof(u64));
@@ -355,7 +356,7 @@ int group_merge_grid() {
 }
 
 // Persistent grid of an update-kernel variant: one workgroup per slot the chip can hold.
-template <int STORAGE, int SPLIT>
+template <int STORAGE, int SPLIT, int NT>
 int update_grid() {
     static int grid = 0;
     static std::once_flag once;
@@ -364,7 +365,7 @@ int update_grid() {
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per, reinterpret_cast<const void*>(&k_update<STORAGE, SPLIT>), 256, 0) != hipSuccess ||
+                &per, reinterpret_cast<const void*>(&k_update<STORAGE, SPLIT, NT>), NT, 0) != hipSuccess ||
             per < 1)
             per = 1;
         grid = cus * per;
@@ -372,24 +373,40 @@ int update_grid() {
     return grid > 0 ? grid : 256;
 }
 
-template <int STORAGE, int SPLIT>
+template <int STORAGE, int SPLIT, int NT>
 void launch_update_t(hipStream_t st, const Job* jobs, const MapDesc* maps, const u64* t_key,
                      const int* t_slot, const u32* off, const float4* sorted, u32 JM, u64* touch_key,
                      u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
-    hipLaunchKernelGGL((k_update<STORAGE, SPLIT>), dim3(update_grid<STORAGE, SPLIT>()), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_update<STORAGE, SPLIT, NT>), dim3(update_grid<STORAGE, SPLIT, NT>()), dim3(NT), 0, st,
                        jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep,
                        jst, cs);
 }
 
-void launch_update(int storage, int split, hipStream_t st, const Job* jobs, const MapDesc* maps,
+// Update-kernel variants: z-slabs per block and threads per workgroup.
+struct UpdateVariant {
+    int split, threads;
+};
+constexpr UpdateVariant kUpdateVariants[] = {{1, 256}, {2, 256}, {4, 256}, {4, 64}, {8, 64}};
+constexpr int kNumUpdateVariants = sizeof(kUpdateVariants) / sizeof(kUpdateVariants[0]);
+
+void launch_update(int storage, int variant, hipStream_t st, const Job* jobs, const MapDesc* maps,
                    const u64* t_key, const int* t_slot, const u32* off, const float4* sorted, u32 JM,
                    u64* touch_key, u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
-#define VBX_UPD(S, P) launch_update_t<S, P>(st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep, jst, cs)
-    if (storage == VBX_F32) {
-        if (split == 1) VBX_UPD(0, 1); else if (split == 4) VBX_UPD(0, 4); else VBX_UPD(0, 2);
-    } else {
-        if (split == 1) VBX_UPD(1, 1); else if (split == 4) VBX_UPD(1, 4); else VBX_UPD(1, 2);
+#define VBX_UPD(S, P, T) launch_update_t<S, P, T>(st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep, jst, cs)
+#define VBX_UPD_ALL(S)                 \
+    switch (variant) {                 \
+        case 0: VBX_UPD(S, 1, 256); break; \
+        case 2: VBX_UPD(S, 4, 256); break; \
+        case 3: VBX_UPD(S, 4, 64); break;  \
+        case 4: VBX_UPD(S, 8, 64); break;  \
+        default: VBX_UPD(S, 2, 256); break; \
     }
+    if (storage == VBX_F32) {
+        VBX_UPD_ALL(0)
+    } else {
+        VBX_UPD_ALL(1)
+    }
+#undef VBX_UPD_ALL
 #undef VBX_UPD
 }
 
@@ -546,9 +563,12 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
         hipLaunchKernelGGL(k_gscatter, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
                            (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p,
                            (const u32*)s->off.p, JM, (Partial*)s->parts_sorted.p, (const CallState*)cs);
+        hipLaunchKernelGGL(k_chunk_first, dim3(grid_for(s->bins_cap + 1, 1024)), dim3(256), 0, st,
+                           (const u32*)s->off.p, JM, (u32*)s->chunk_first.p, (const CallState*)cs);
         hipLaunchKernelGGL(k_group_merge, dim3(group_merge_grid()), dim3(256), 0, st, d_jobs, d_maps,
                            (const u64*)s->tkeys.p, (const u32*)s->tlist.p, (const u32*)s->off.p,
-                           (const Partial*)s->parts_sorted.p, JM, rays_p, rays_job, jst, cs);
+                           (const u32*)s->chunk_first.p, (const Partial*)s->parts_sorted.p, JM, rays_p,
+                           rays_job, jst, cs);
     }
     const unsigned G = grid_for(plan.ray_slots, 2048);
     const u32 MB = (u32)plan.max_blocks;
@@ -587,7 +607,7 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     if (plan.keep_touches) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->touch_count, 0u);
     {
     StageTimer tm(lead, st, ST_UPDATE);
-    launch_update(plan.storage, lead->update_split, st, d_jobs, d_maps, (const u64*)s->t_key.p,
+    launch_update(plan.storage, lead->update_variant, st, d_jobs, d_maps, (const u64*)s->t_key.p,
                   (const int*)s->t_slot.p, (const u32*)s->off.p, (const float4*)s->sorted.p, JM,
                   (u64*)s->touch_key.p, (u32*)s->touch_n.p, (u32)s->touch_cap, plan.keep_touches ? 1 : 0,
                   jst, cs);
@@ -662,9 +682,9 @@ int vbx_map_create_ex(const vbx_map_params* params, vbx_map** out) {
     m->wbits = weight_bits(m->P);
     m->kw = sum_bits(m->P);
     m->scratch = new (std::nothrow) Scratch();
-    if (const char* e = std::getenv("VBX_UPDATE_SPLIT")) {
+    if (const char* e = std::getenv("VBX_UPDATE_VARIANT")) {
         const int v = std::atoi(e);
-        if (v == 1 || v == 2 || v == 4) m->update_split = v;
+        if (v >= 0 && v < kNumUpdateVariants) m->update_variant = v;
     }
     if (!m->scratch || hipMalloc(&m->st, sizeof(MapState)) != hipSuccess) {
         delete m->scratch;
@@ -1055,20 +1075,24 @@ const char* vbx_profile_stage_name(int stage) {
 int vbx_map_get_tuning(vbx_map* m, vbx_tuning* out) {
     if (!m || !out) return VBX_ERR_INVALID_ARG;
     std::memset(out, 0, sizeof *out);
-    out->update_split = m->update_split;
+    out->update_split = kUpdateVariants[m->update_variant].split;
+    out->update_threads = kUpdateVariants[m->update_variant].threads;
     return VBX_OK;
 }
 
 int vbx_map_set_tuning(vbx_map* m, const vbx_tuning* t) {
     if (!m || !t) return VBX_ERR_INVALID_ARG;
-    if (t->update_split != 1 && t->update_split != 2 && t->update_split != 4) return VBX_ERR_INVALID_ARG;
-    m->update_split = t->update_split;
-    return VBX_OK;
+    for (int v = 0; v < kNumUpdateVariants; ++v) {
+        if (kUpdateVariants[v].split == t->update_split && kUpdateVariants[v].threads == t->update_threads) {
+            m->update_variant = v;
+            return VBX_OK;
+        }
+    }
+    return VBX_ERR_INVALID_ARG;
 }
 
 int vbx_map_autotune(vbx_map* m, const vbx_frame* frames, int F, vbx_tuning* best, double* ms_out) {
     if (!m || F <= 0 || !frames) return VBX_ERR_INVALID_ARG;
-    static const int splits[VBX_TUNING_CANDIDATES] = {1, 2, 4};
     vbx_map_params p = m->P;
     p.flags &= ~(uint32_t)VBX_FLAG_KEEP_TOUCHES;
     vbx_map* tmp = nullptr;
@@ -1080,11 +1104,11 @@ int vbx_map_autotune(vbx_map* m, const vbx_frame* frames, int F, vbx_tuning* bes
         return VBX_ERR_DEVICE;
     }
     double best_ms = 1e300;
-    int best_split = m->update_split;
+    int best_v = m->update_variant;
     const int reps = 3;
-    for (int c = 0; c < VBX_TUNING_CANDIDATES && rc == VBX_OK; ++c) {
-        tmp->update_split = splits[c];
-        // one untimed pass (scratch growth, first-touch), then the timed passes
+    for (int c = 0; c < kNumUpdateVariants && rc == VBX_OK; ++c) {
+        tmp->update_variant = c;
+        // one untimed pass (scratch growth, first touch), then the timed passes
         if ((rc = vbx_map_clear(tmp)) != VBX_OK || (rc = vbx_integrate_frames(tmp, frames, F)) != VBX_OK) break;
         (void)hipEventRecord(e0, tmp->stream);
         for (int r = 0; r < reps && rc == VBX_OK; ++r) {
@@ -1098,13 +1122,13 @@ int vbx_map_autotune(vbx_map* m, const vbx_frame* frames, int F, vbx_tuning* bes
         if (ms_out) ms_out[c] = per;
         MapState s;
         if (read_state(tmp, &s) != VBX_OK || s.error != 0) { rc = s.error ? s.error : VBX_ERR_DEVICE; break; }
-        if (per < best_ms) { best_ms = per; best_split = splits[c]; }
+        if (per < best_ms) { best_ms = per; best_v = c; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     vbx_map_destroy(tmp);
     if (rc != VBX_OK) return rc;
-    m->update_split = best_split;
+    m->update_variant = best_v;
     if (best) vbx_map_get_tuning(m, best);
     return VBX_OK;
 }

@@ -27,9 +27,11 @@ __global__ void k_gbin_count(const Partial* parts, const u32* tile_parts, u32 nt
 __global__ void k_gscatter(const Partial* parts, const u32* tile_parts, u32 ntiles,
                            const u32* tval, u32* bins, const u32* off, u32 JM, Partial* sorted,
                            const CallState* cs);
+__global__ void k_chunk_first(const u32* off, u32 JM, u32* chunk_first, const CallState* cs);
 __global__ void k_group_merge(const Job* jobs, const MapDesc* maps, const u64* tkeys,
-                              const u32* tlist, const u32* off, const Partial* sorted, u32 JM,
-                              float4* rays_p, u32* rays_job, JobStat* jst, CallState* cs);
+                              const u32* tlist, const u32* off, const u32* chunk_first,
+                              const Partial* sorted, u32 JM, float4* rays_p, u32* rays_job,
+                              JobStat* jst, CallState* cs);
 __global__ void k_cross(const Job* jobs, const MapDesc* maps, const float4* rays_p,
                         const u32* rays_job, u64* tkeys, u32 tmask, u32* tlist, u32 tlist_cap,
                         u32* cross, unsigned char* ncross, u32 MB, JobStat* jst, CallState* cs,
@@ -48,7 +50,7 @@ __global__ void k_scatter(const Job* jobs, const u32* cross, const unsigned char
                           u32 MB, const u32* tval, const u32* rays_job, u32* bins,
                           const u32* off, u32 JM, const float4* rays_p, float4* sorted,
                           CallState* cs, u32 ray_cap);
-template <int STORAGE, int SPLIT>
+template <int STORAGE, int SPLIT, int NT>
 __global__ void k_update(const Job* jobs, const MapDesc* maps, const u64* t_key,
                          const int* t_slot, const u32* off, const float4* sorted, u32 JM,
                          u64* touch_key, u32* touch_n, u32 touch_cap, int keep_touches,

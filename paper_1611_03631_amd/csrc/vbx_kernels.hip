@@ -71,6 +71,21 @@ __device__ inline u32 block_scan_256(u32 x, u32* lds8, u32* tot) {
     return v + add;
 }
 
+// Inclusive prefix sum over a workgroup of NT threads (NT a multiple of 64, at most 256).
+template <int NT>
+__device__ inline u32 block_scan(u32 x, u32* lds8, u32* tot) {
+    if (NT == 256) return block_scan_256(x, lds8, tot);
+    const int lane = lane_id();
+    u32 v = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        u32 y = __shfl_up(v, o);
+        if (lane >= o) v += y;
+    }
+    *tot = __shfl(v, 63);
+    return v;
+}
+
 __global__ void k_fill_u64(u64* p, u64 val, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = val;
@@ -391,137 +406,233 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
     }
 }
 
-// Grouped raycasting, step 3: one workgroup per (block, frame) bin merges the bin's partial
-// groups by voxel (exact integer sums, 1024 voxels of the block per pass) and casts one ray
-// per group: the exact weighted mean (a single point keeps the point), the summed weight.
-constexpr int kMergeVox = 1024;
-constexpr int kMergeGrab = 64;      // bins per work grab
+// Grouped raycasting, step 3: merging the partial groups of each (block, frame) bin by
+// voxel and casting one ray per group -- the exact weighted mean (a group of one point keeps
+// the point) with the group's summed weight.
+//
+// Work is cut into chunks of kMergeSpan consecutive sorted partials; a chunk owns the bins
+// whose first partial falls in it.  Consecutive bins of a chunk are merged together in one
+// LDS hash keyed by (bin in batch, local voxel) while they hold at most kMergeBatch partials;
+// a bin larger than that is merged alone over a dense voxel table, kMergeVox voxels per pass.
+// The rays of bin b take slots [off[b], off[b] + groups) and the rest of its range is marked
+// empty, so no counter is shared between workgroups.
+constexpr int kMergeVox = 1024;     // LDS table entries (hash slots or dense voxels)
+constexpr int kMergeSpan = 512;     // partials per work chunk
+constexpr int kMergeBatch = 640;    // partials merged in one hash pass (load <= 0.625)
+
+// chunk_first[c] = first bin whose first partial lies at or after c * kMergeSpan.
+__global__ __launch_bounds__(256) void k_chunk_first(const u32* __restrict__ off, u32 JM,
+                                                     u32* __restrict__ chunk_first,
+                                                     const CallState* __restrict__ cs) {
+    const u32 nb = cs->error ? 0u : cs->t_count * JM;
+    for (u32 b = blockIdx.x * 256u + threadIdx.x; b <= nb; b += gridDim.x * 256u) {
+        // chunks whose start c * kMergeSpan lies in (off[b - 1], off[b]]
+        const u32 hi = off[b];
+        const u32 c_lo = b == 0 ? 0u : off[b - 1] / kMergeSpan + 1u;
+        const u32 c_hi = hi / kMergeSpan;
+        for (u32 c = c_lo; c <= c_hi; ++c) chunk_first[c] = b;
+    }
+}
+
+__device__ inline void group_ray(const MapDesc& M, const Job& J, int bx, int by, int bz, u32 l,
+                                 u32 n, u64 so, const u64* sq, const u32* hi, u32 idx, float4& ray) {
+    const int g[3] = {16 * bx + (int)(l & 15), 16 * by + (int)((l >> 4) & 15), 16 * bz + (int)(l >> 8)};
+    float p[3];
+    if (n == 1) {
+        classify_point(M, J.pose, J.pts[3 * (size_t)idx], J.pts[3 * (size_t)idx + 1],
+                       J.pts[3 * (size_t)idx + 2], p);
+    } else {
+        const double den = (double)so * 1048576.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double m = ((double)(u64)hi[k] * 18446744073709551616.0 + (double)sq[k]) / den;
+            p[k] = (float)(((double)g[k] + m) * (double)M.v);
+        }
+    }
+    const float wgt = M.wbits > 0 ? (float)((double)so * __builtin_ldexp(1.0, -M.wbits)) : (float)n;
+    ray = make_float4(p[0], p[1], p[2], wgt);
+}
 
 __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ jobs,
                                                      const MapDesc* __restrict__ maps,
                                                      const u64* __restrict__ tkeys,
                                                      const u32* __restrict__ tlist,
                                                      const u32* __restrict__ off,
+                                                     const u32* __restrict__ chunk_first,
                                                      const Partial* __restrict__ sorted, u32 JM,
                                                      float4* __restrict__ rays_p,
                                                      u32* __restrict__ rays_job,
                                                      JobStat* __restrict__ jst,
                                                      CallState* __restrict__ cs) {
+    __shared__ u32 m_key[kMergeVox];   // hash: (bin in batch << 12 | local) + 1, 0 = free
     __shared__ u64 m_so[kMergeVox];
     __shared__ u64 m_sq[3][kMergeVox];
     __shared__ u32 m_hi[3][kMergeVox];
     __shared__ u32 m_n[kMergeVox];
     __shared__ u32 m_idx[kMergeVox];
-    __shared__ u32 s_b0, s_quarters, s_nr;
-    __shared__ u32 s_off[kMergeGrab + 1];
+    __shared__ u32 s_nr[kMergeBatch];  // rays emitted per bin of the batch
+    __shared__ u32 s_off[kMergeBatch + 2];
+    __shared__ u32 s_quarters;
     __shared__ u32 lds8[4];
     for (int i = threadIdx.x; i < kMergeVox; i += 256) {
-        m_so[i] = 0; m_sq[0][i] = 0; m_sq[1][i] = 0; m_sq[2][i] = 0;
+        m_key[i] = 0; m_so[i] = 0; m_sq[0][i] = 0; m_sq[1][i] = 0; m_sq[2][i] = 0;
         m_hi[0][i] = 0; m_hi[1][i] = 0; m_hi[2][i] = 0; m_n[i] = 0;
     }
     const u32 nb = cs->error ? 0u : cs->t_count * JM;
-    // the rays of bin b take slots [off[b], off[b] + groups) -- a bin has at least as many
-    // partials as groups -- and the rest of the bin's range is left empty
-    if (blockIdx.x == 0 && threadIdx.x == 0) cs->ray_count = nb ? off[nb] : 0u;
-    for (;;) {
-    // bins are taken kMergeGrab at a time; their offsets are staged in LDS
-    if (threadIdx.x == 0) s_b0 = atomicAdd(&cs->work_merge, (u32)kMergeGrab);
+    const u32 total = nb ? off[nb] : 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) cs->ray_count = total;
+    const u32 nchunks = (total + kMergeSpan - 1) / kMergeSpan;
     __syncthreads();
-    const u32 b0 = s_b0;
-    if (b0 >= nb) break;
-    const u32 bn = nb - b0 < (u32)kMergeGrab ? nb - b0 : (u32)kMergeGrab;
-    for (u32 k = threadIdx.x; k <= bn; k += 256) s_off[k] = off[b0 + k];
-    __syncthreads();
-    for (u32 bi = 0; bi < bn; ++bi) {
-        const u32 b = b0 + bi;
-        const u32 lo = s_off[bi], hi = s_off[bi + 1];
-        if (lo == hi) continue;
-        if (threadIdx.x == 0) { s_quarters = 0; s_nr = 0; }
-        __syncthreads();
-        const u32 t = b / JM, jm = b - t * JM;
-        const u64 tk = tkeys[tlist[t]];
-        const MapDesc& M = maps[(u32)(tk >> 45)];
-        const int jid = M.job0 + (int)jm;
-        const Job& J = jobs[jid];
-        int bx, by, bz;
-        unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
-        u32 qm = 0;
-        for (u32 e = lo + threadIdx.x; e < hi; e += 256) qm |= 1u << ((sorted[e].lj & 4095u) >> 10);
-        if (qm) atomicOr(&s_quarters, qm);
-        __syncthreads();
-        const u32 quarters = s_quarters;
-        u32 nrays_bin = 0;
-        for (int qd = 0; qd < 4; ++qd) {
-            if (!(quarters & (1u << qd))) continue;
-            for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
+    for (u32 c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const u32 bs = chunk_first[c];
+        const u32 be = c + 1 < nchunks ? chunk_first[c + 1] : nb;
+        // bins [bs, be) in batches; a batch is a run of bins with at most kMergeBatch partials
+        u32 b = bs;
+        while (b < be) {
+            // stage the offsets of up to kMergeBatch bins
+            const u32 wn = be - b < (u32)kMergeBatch ? be - b : (u32)kMergeBatch;
+            for (u32 k = threadIdx.x; k <= wn; k += 256) s_off[k] = off[b + k];
+            __syncthreads();
+            const u32 base = s_off[0];
+            u32 nbat = 0;
+            while (nbat < wn && s_off[nbat + 1] - base <= (u32)kMergeBatch) ++nbat;
+            if (nbat == 0) {
+                // ---- a bin too large for one hash pass: dense passes over its voxels
+                const u32 lo = s_off[0], hi = s_off[1];
+                const u32 t = b / JM, jm = b - t * JM;
+                const u64 tk = tkeys[tlist[t]];
+                const MapDesc& M = maps[(u32)(tk >> 45)];
+                const int jid = M.job0 + (int)jm;
+                const Job& J = jobs[jid];
+                int bx, by, bz;
+                unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
+                if (threadIdx.x == 0) s_quarters = 0;
+                __syncthreads();
+                u32 qm = 0;
+                for (u32 e = lo + threadIdx.x; e < hi; e += 256) qm |= 1u << ((sorted[e].lj & 4095u) >> 10);
+                if (qm) atomicOr(&s_quarters, qm);
+                __syncthreads();
+                const u32 quarters = s_quarters;
+                u32 nrays = 0;
+                for (int qd = 0; qd < 4; ++qd) {
+                    if (!(quarters & (1u << qd))) continue;
+                    for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
+                        const Partial& P = sorted[e];
+                        const u32 l = P.lj & 4095u;
+                        if ((int)(l >> 10) != qd) continue;
+                        const u32 v = l & (kMergeVox - 1);
+                        atomicAdd(&m_so[v], P.so);
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            const u64 old = atomicAdd(&m_sq[k][v], P.sq[k]);
+                            if (old + P.sq[k] < old) atomicAdd(&m_hi[k][v], 1u);   // carry
+                        }
+                        atomicAdd(&m_n[v], P.n);
+                        if (P.n == 1) m_idx[v] = P.idx;
+                    }
+                    __syncthreads();
+                    float4 ray[4];
+                    bool has[4];
+                    u32 nmine = 0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int v = threadIdx.x + 256 * r;
+                        const u32 n = m_n[v];
+                        has[r] = n != 0;
+                        ray[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (!n) continue;
+                        const u64 sq[3] = {m_sq[0][v], m_sq[1][v], m_sq[2][v]};
+                        const u32 hw[3] = {m_hi[0][v], m_hi[1][v], m_hi[2][v]};
+                        group_ray(M, J, bx, by, bz, (u32)(qd * kMergeVox + v), n, m_so[v], sq, hw, m_idx[v], ray[r]);
+                        nmine++;
+                        m_so[v] = 0; m_sq[0][v] = 0; m_sq[1][v] = 0; m_sq[2][v] = 0;
+                        m_hi[0][v] = 0; m_hi[1][v] = 0; m_hi[2][v] = 0; m_n[v] = 0;
+                    }
+                    u32 tot;
+                    const u32 incl = block_scan_256(nmine, lds8, &tot);
+                    u32 pos = lo + nrays + incl - nmine;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        if (!has[r]) continue;
+                        rays_p[pos] = ray[r];
+                        rays_job[pos] = (u32)jid;
+                        pos++;
+                    }
+                    nrays += tot;
+                    __syncthreads();
+                }
+                for (u32 e = lo + nrays + threadIdx.x; e < hi; e += 256) rays_job[e] = kNoRay;
+                if (threadIdx.x == 0 && nrays) atomicAdd(&jst[jid].rays, (u64)nrays);
+                __syncthreads();
+                b += 1;
+                continue;
+            }
+            // ---- hash merge of bins [b, b + nbat)
+            const u32 pend = s_off[nbat];
+            for (u32 k = threadIdx.x; k < nbat; k += 256) s_nr[k] = 0;
+            __syncthreads();
+            for (u32 e = base + threadIdx.x; e < pend; e += 256) {
                 const Partial& P = sorted[e];
-                const u32 l = P.lj & 4095u;
-                if ((int)(l >> 10) != qd) continue;
-                const u32 v = l & (kMergeVox - 1);
-                atomicAdd(&m_so[v], P.so);
+                // bin of partial e: the last staged bin whose start is <= e
+                u32 lo_i = 0, hi_i = nbat - 1;
+                while (lo_i < hi_i) {
+                    const u32 mid = (lo_i + hi_i + 1) >> 1;
+                    if (s_off[mid] <= e) lo_i = mid; else hi_i = mid - 1;
+                }
+                const u32 key = ((lo_i << 12) | (P.lj & 4095u)) + 1u;
+                u32 h = (u32)mix64(key) & (kMergeVox - 1);
+                for (;;) {
+                    const u32 old = atomicCAS(&m_key[h], 0u, key);
+                    if (old == 0u || old == key) break;
+                    h = (h + 1) & (kMergeVox - 1);
+                }
+                atomicAdd(&m_so[h], P.so);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    const u64 old = atomicAdd(&m_sq[k][v], P.sq[k]);
-                    if (old + P.sq[k] < old) atomicAdd(&m_hi[k][v], 1u);   // carry
+                    const u64 old = atomicAdd(&m_sq[k][h], P.sq[k]);
+                    if (old + P.sq[k] < old) atomicAdd(&m_hi[k][h], 1u);   // carry
                 }
-                atomicAdd(&m_n[v], P.n);
-                if (P.n == 1) m_idx[v] = P.idx;
+                atomicAdd(&m_n[h], P.n);
+                if (P.n == 1) m_idx[h] = P.idx;
             }
             __syncthreads();
-            float4 ray[4];
-            bool has[4];
-            u32 nmine = 0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int v = threadIdx.x + 256 * r;
-                const u32 n = m_n[v];
-                has[r] = n != 0;
-                ray[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (!n) continue;
-                const int l = qd * kMergeVox + v;
-                const int g[3] = {16 * bx + (l & 15), 16 * by + ((l >> 4) & 15), 16 * bz + (l >> 8)};
-                float p[3];
-                if (n == 1) {
-                    const u32 idx = m_idx[v];
-                    classify_point(M, J.pose, J.pts[3 * (size_t)idx], J.pts[3 * (size_t)idx + 1],
-                                   J.pts[3 * (size_t)idx + 2], p);
-                } else {
-                    const double den = (double)m_so[v] * 1048576.0;
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const double hi_d = (double)(u64)m_hi[k][v];
-                        const double lo_d = (double)m_sq[k][v];
-                        const double m = (hi_d * 18446744073709551616.0 + lo_d) / den;
-                        p[k] = (float)(((double)g[k] + m) * (double)M.v);
-                    }
-                }
-                const float wgt = M.wbits > 0 ? (float)((double)m_so[v] * __builtin_ldexp(1.0, -M.wbits))
-                                              : (float)n;
-                ray[r] = make_float4(p[0], p[1], p[2], wgt);
-                nmine++;
-                m_so[v] = 0; m_sq[0][v] = 0; m_sq[1][v] = 0; m_sq[2][v] = 0;
-                m_hi[0][v] = 0; m_hi[1][v] = 0; m_hi[2][v] = 0; m_n[v] = 0;
-            }
-            u32 tot;
-            const u32 incl = block_scan_256(nmine, lds8, &tot);
-            u32 pos = lo + s_nr + incl - nmine;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (!has[r]) continue;
-                rays_p[pos] = ray[r];
+            for (int h = threadIdx.x; h < kMergeVox; h += 256) {
+                const u32 key = m_key[h];
+                if (!key) continue;
+                const u32 bi = (key - 1u) >> 12, l = (key - 1u) & 4095u;
+                const u32 bb = b + bi;
+                const u32 t = bb / JM, jm = bb - t * JM;
+                const u64 tk = tkeys[tlist[t]];
+                const MapDesc& M = maps[(u32)(tk >> 45)];
+                const int jid = M.job0 + (int)jm;
+                const Job& J = jobs[jid];
+                int bx, by, bz;
+                unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
+                const u64 sq[3] = {m_sq[0][h], m_sq[1][h], m_sq[2][h]};
+                const u32 hw[3] = {m_hi[0][h], m_hi[1][h], m_hi[2][h]};
+                float4 ray;
+                group_ray(M, J, bx, by, bz, l, m_n[h], m_so[h], sq, hw, m_idx[h], ray);
+                const u32 pos = s_off[bi] + atomicAdd(&s_nr[bi], 1u);
+                rays_p[pos] = ray;
                 rays_job[pos] = (u32)jid;
-                pos++;
+                m_key[h] = 0; m_so[h] = 0; m_sq[0][h] = 0; m_sq[1][h] = 0; m_sq[2][h] = 0;
+                m_hi[0][h] = 0; m_hi[1][h] = 0; m_hi[2][h] = 0; m_n[h] = 0;
             }
-            nrays_bin += tot;
             __syncthreads();
-            if (threadIdx.x == 0) s_nr += tot;
+            // empty slots of each bin, and per-frame ray counts
+            for (u32 k = 0; k < nbat; ++k) {
+                const u32 nr = s_nr[k];
+                for (u32 e = s_off[k] + nr + threadIdx.x; e < s_off[k + 1]; e += 256) rays_job[e] = kNoRay;
+                if (threadIdx.x == 0 && nr) {
+                    const u32 bb = b + k;
+                    const u32 t = bb / JM;
+                    const MapDesc& M = maps[(u32)(tkeys[tlist[t]] >> 45)];
+                    atomicAdd(&jst[M.job0 + (bb - t * JM)].rays, (u64)nr);
+                }
+            }
             __syncthreads();
+            b += nbat;
         }
-        for (u32 e = lo + nrays_bin + threadIdx.x; e < hi; e += 256) rays_job[e] = kNoRay;
-        if (threadIdx.x == 0 && nrays_bin) atomicAdd(&jst[jid].rays, (u64)nrays_bin);
-        __syncthreads();
-    }
-    __syncthreads();
     }
 }
 
@@ -940,8 +1051,8 @@ constexpr int kOffWindow = 256;   // frames whose bin offsets are staged in LDS 
 // Work item u = t * SPLIT + q: slab q (local z in [q*16/SPLIT, (q+1)*16/SPLIT)) of touched block t.
 // Slabs of one block are independent (different voxels) and replay the same rays, so a
 // block's frames run in parallel across SPLIT workgroups with 1/SPLIT of the LDS each.
-template <int STORAGE, int SPLIT>
-__global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
+template <int STORAGE, int SPLIT, int NT>
+__global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                                 const MapDesc* __restrict__ maps,
                                                 const u64* __restrict__ t_key,
                                                 const int* __restrict__ t_slot,
@@ -953,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
                                                 JobStat* __restrict__ jst,
                                                 CallState* __restrict__ cs) {
     constexpr int VOX = 4096 / SPLIT;      // voxels of one slab
-    constexpr int VPT = VOX / 256;         // voxels per thread
+    constexpr int VPT = VOX / NT;          // voxels per thread
     constexpr int ZS = 16 / SPLIT;         // slab thickness
     __shared__ u64 a_w[VOX];    // sum of fixed-point weights
     __shared__ u64 a_d[VOX];    // sum of fixed-point weight * distance/delta (two's complement)
@@ -963,7 +1074,7 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
     __shared__ u32 s_stat[3];
     __shared__ u32 s_tbase;
     __shared__ u32 lds8[4];
-    for (int i = threadIdx.x; i < VOX; i += 256) { a_w[i] = 0; a_d[i] = 0; a_n[i] = 0; }
+    for (int i = threadIdx.x; i < VOX; i += NT) { a_w[i] = 0; a_d[i] = 0; a_n[i] = 0; }
     const u32 nt = cs->error ? 0u : cs->t_count * (u32)SPLIT;
     for (;;) {
         if (threadIdx.x == 0) { s_t = atomicAdd(&cs->work_next, 1u); s_stat[0] = 0; s_stat[1] = 0; s_stat[2] = 0; }
@@ -989,45 +1100,47 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
         for (int j = 0; j < VPT; ++j) {
             ntot[j] = 0;
             if (is_new) { D[j] = 0.0f; W[j] = 0.0f; }
-            else load_voxel<STORAGE>(pool, vbase + threadIdx.x + 256 * j, D[j], W[j]);
+            else load_voxel<STORAGE>(pool, vbase + threadIdx.x + NT * j, D[j], W[j]);
         }
         const int ox = 16 * bx, oy = 16 * by, oz = 16 * bz + q * ZS;
         u32 stat_vox = 0, stat_touch = 0;
         for (int w0 = 0; w0 < M.njobs; w0 += kOffWindow) {
             const int wn = M.njobs - w0 < kOffWindow ? M.njobs - w0 : kOffWindow;
-            for (int k = threadIdx.x; k <= wn; k += 256) s_off[k] = off[t * JM + (u32)(w0 + k)];
+            for (int k = threadIdx.x; k <= wn; k += NT) s_off[k] = off[t * JM + (u32)(w0 + k)];
             __syncthreads();
             // frames of the window in order; the first ray of every thread for the next frame
             // that has rays is loaded while the current frame is processed
             int jm = 0;
             while (jm < wn && s_off[jm] == s_off[jm + 1]) ++jm;
             float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
-            bool has_nxt = false;
             if (jm < wn) {
                 const u32 e = s_off[jm] + threadIdx.x;
-                has_nxt = e < s_off[jm + 1];
-                if (has_nxt) nxt = sorted[e];
+                if (e < s_off[jm + 1]) nxt = sorted[e];
             }
             while (jm < wn) {
                 int jn = jm + 1;
                 while (jn < wn && s_off[jn] == s_off[jn + 1]) ++jn;
                 const float4 cur = nxt;
-                const bool has_cur = has_nxt;
                 const u32 lo = s_off[jm], hi = s_off[jm + 1];
                 if (jn < wn) {
                     const u32 e = s_off[jn] + threadIdx.x;
-                    has_nxt = e < s_off[jn + 1];
-                    if (has_nxt) nxt = sorted[e];
+                    if (e < s_off[jn + 1]) nxt = sorted[e];
                 }
                 const Job& J = jobs[M.job0 + w0 + jm];
                 const float s[3] = {J.pose[3], J.pose[7], J.pose[11]};
-                for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
+                for (u32 e = lo + threadIdx.x; e < hi; e += NT) {
                     const float4 rp = e == lo + threadIdx.x ? cur : sorted[e];
-                    (void)has_cur;
                     const float p[3] = {rp.x, rp.y, rp.z};
                     float ev[3], r;
                     Walk w;
                     walk_setup(M, p, s, ev, r, w);
+                    if (SPLIT > 1) {
+                        // the walk's z indices lie between its end voxels: skip bands that miss the slab
+                        const int z_end = w.g[2] + w.step[2] * w.n[2];
+                        const int zlo = w.g[2] < z_end ? w.g[2] : z_end;
+                        const int zhi = w.g[2] < z_end ? z_end : w.g[2];
+                        if (zhi < oz || zlo >= oz + ZS) continue;
+                    }
                     bool inside = false;
                     for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
                         const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
@@ -1051,7 +1164,7 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
                 // Eqs. (3)-(4), once per voxel for this frame
 #pragma unroll
                 for (int j = 0; j < VPT; ++j) {
-                    const int l = threadIdx.x + 256 * j;
+                    const int l = threadIdx.x + NT * j;
                     const u32 c = a_n[l];
                     if (c) {
                         const u64 sw_fx = a_w[l];
@@ -1083,7 +1196,7 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
             __syncthreads();
         }
 #pragma unroll
-        for (int j = 0; j < VPT; ++j) store_voxel<STORAGE>(pool, vbase + threadIdx.x + 256 * j, D[j], W[j]);
+        for (int j = 0; j < VPT; ++j) store_voxel<STORAGE>(pool, vbase + threadIdx.x + NT * j, D[j], W[j]);
         if (stat_vox) {
             u32 cells = 0;
 #pragma unroll
@@ -1097,14 +1210,14 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
 #pragma unroll
             for (int j = 0; j < VPT; ++j) mine += ntot[j] ? 1u : 0u;
             u32 tot;
-            const u32 incl = block_scan_256(mine, lds8, &tot);
+            const u32 incl = block_scan<NT>(mine, lds8, &tot);
             if (threadIdx.x == 0) s_tbase = atomicAdd(&cs->touch_count, tot);
             __syncthreads();
             u32 pos = s_tbase + incl - mine;
 #pragma unroll
             for (int j = 0; j < VPT; ++j) {
                 if (ntot[j]) {
-                    const int l = threadIdx.x + 256 * j;
+                    const int l = threadIdx.x + NT * j;
                     if (pos < touch_cap) {
                         touch_key[pos] = ((u64)(M.map_id) << 57) |
                                          voxel_key_of(ox + (l & 15), oy + ((l >> 4) & 15), oz + (l >> 8));
@@ -1124,24 +1237,36 @@ __global__ __launch_bounds__(256) void k_update(const Job* __restrict__ jobs,
     }
 }
 
-template __global__ void k_update<0, 1>(const Job*, const MapDesc*, const u64*, const int*,
-                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                         JobStat*, CallState*);
-template __global__ void k_update<0, 2>(const Job*, const MapDesc*, const u64*, const int*,
-                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                         JobStat*, CallState*);
-template __global__ void k_update<0, 4>(const Job*, const MapDesc*, const u64*, const int*,
-                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                         JobStat*, CallState*);
-template __global__ void k_update<1, 1>(const Job*, const MapDesc*, const u64*, const int*,
-                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                         JobStat*, CallState*);
-template __global__ void k_update<1, 2>(const Job*, const MapDesc*, const u64*, const int*,
-                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                         JobStat*, CallState*);
-template __global__ void k_update<1, 4>(const Job*, const MapDesc*, const u64*, const int*,
-                                         const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                         JobStat*, CallState*);
+template __global__ void k_update<0, 1, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                              JobStat*, CallState*);
+template __global__ void k_update<0, 2, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                              JobStat*, CallState*);
+template __global__ void k_update<0, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                              JobStat*, CallState*);
+template __global__ void k_update<0, 4, 64>(const Job*, const MapDesc*, const u64*, const int*,
+                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                              JobStat*, CallState*);
+template __global__ void k_update<0, 8, 64>(const Job*, const MapDesc*, const u64*, const int*,
+                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                              JobStat*, CallState*);
+template __global__ void k_update<1, 1, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                              JobStat*, CallState*);
+template __global__ void k_update<1, 2, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                              JobStat*, CallState*);
+template __global__ void k_update<1, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                              JobStat*, CallState*);
+template __global__ void k_update<1, 4, 64>(const Job*, const MapDesc*, const u64*, const int*,
+                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                              JobStat*, CallState*);
+template __global__ void k_update<1, 8, 64>(const Job*, const MapDesc*, const u64*, const int*,
+                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                              JobStat*, CallState*);
 
 // ---------------------------------------------------------------------------
 // finish: commit block counts, fold statistics, clean per-call tables
