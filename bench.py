@@ -1,11 +1,16 @@
 #!/usr/bin/env python3
 """Throughput benchmark of TSDF integration on one MI355X.
 
-Workload: the 100-frame 640x480 depth sequence of a 10x10x3 m furnished room (camera on a
-1.5 m circle), voxel 0.05 m, truncation 0.15 m, 1/z^2 weighting with drop-off, grouped
-raycasting, binary32 storage.  One step integrates the whole sequence (one
-vbx_integrate_frames call over the 100 frames, organised 640-wide) into an emptied map; the
-frames are resident in HBM before timing starts.
+Default workload (--workload c2): the 100-frame 640x480 depth sequence of a 10x10x3 m
+furnished room (camera on a 1.5 m circle), voxel 0.05 m, truncation 0.15 m, 1/z^2 weighting
+with drop-off, grouped raycasting, binary32 storage.  One step integrates the whole sequence
+(one vbx_integrate_frames call over the 100 frames, organised 640-wide) into an emptied map;
+the frames are resident in HBM before timing starts.
+
+--workload c4: 32 maps per tick (8 x 160x120, 16 x 320x240, 8 x 640x480 depth frames, voxel
+0.02 / 0.05 / 0.10 m by map, truncation 3 voxels, 1/z^2, grouped), one frame per map per
+tick, binary16 storage; one step is one tick, replayed from a captured graph.  The eager
+multi-map call and binary32 storage are timed beside it.
 
 Prints one JSON line: points/s as the value, voxel updates/s beside it, the roofline of the
 dominant kernel stage (timed live with HIP events on the map's stream), and the CPU oracle
@@ -56,39 +61,46 @@ def read_traffic(stage: str, sha: str):
         return None
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--frames", type=int, default=100)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="wall-clock budget of the CPU oracle sample")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default launch tuning instead of timing the candidates first")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
-    args = ap.parse_args()
+def stage_roofline(prof, algo, steps):
+    """Roofline of the dominant stage among those with an algorithmic byte figure."""
+    dom = max(algo, key=lambda k: prof[k][0])
+    ms_r, launches_r = prof[dom]
+    per_launch_bytes = algo[dom] * steps / max(launches_r, 1)
+    avg_launch_s = ms_r / max(launches_r, 1) / 1e3
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic(dom, kernel_source_sha()),
+            "kernel_stage": dom, "launches_per_step": launches_r / steps,
+            "avg_launch_ms": round(ms_r / max(launches_r, 1), 4),
+            "algorithmic_bytes_per_launch": per_launch_bytes}
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the integrator runs on a single MI355X "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
-    import torch
+def oracle_sample(w_list, budget_s):
+    """Integrates frames of the given workloads in order with the single-threaded C oracle
+    until the time budget is spent; returns (points, seconds, frames done)."""
+    import oracle
+    pts = done = 0
+    t0 = time.perf_counter()
+    for w, k_lo, k_hi in w_list:
+        P = w.params
+        om = oracle.OracleMap(P["voxel_size"], P["trunc"], weighting=P["weighting"],
+                              merge=P["merge"], max_range=P["max_range"],
+                              storage=P.get("storage", "f32"))
+        for k in range(k_lo, k_hi):
+            if time.perf_counter() - t0 >= budget_s:
+                break
+            f = w.frame(k)
+            om.integrate(f, w.poses[k])
+            pts += f.shape[0]
+            done += 1
+        om.close()
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    return pts, time.perf_counter() - t0, done
 
-    import synth
-    import paper_1611_03631_amd as vbx
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(2)
-    vbx.lib()   # raises if the HIP library is missing: no fallback
-
-    # ---------------------------------------------------------------- inputs
+def bench_c2(args, np, torch, vbx, synth):
     w = synth.config2(n_frames=args.frames)
     t0 = time.time()
     with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
@@ -162,52 +174,22 @@ def main():
         "points": 12.0 * points_per_step + 48.0 * F,
         "update": 2.0 * s_v * st["cells"] + 4096.0 * s_v * st["new_blocks"],
     }
-    dom = max(prof, key=lambda k: prof[k][0])
-    ms_dom, launches = prof[dom]
-    if dom not in algo:
-        dom_for_roofline = max(algo, key=lambda k: prof[k][0])
-    else:
-        dom_for_roofline = dom
-    ms_r, launches_r = prof[dom_for_roofline]
-    per_launch_bytes = algo[dom_for_roofline] * args.steps / max(launches_r, 1)
-    avg_launch_s = ms_r / max(launches_r, 1) / 1e3
-    achieved = per_launch_bytes / avg_launch_s / 1e9
-    sha = kernel_source_sha()
-    traffic = read_traffic(dom_for_roofline, sha)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel_stage": dom_for_roofline, "launches_per_step": launches_r / args.steps,
-                "avg_launch_ms": round(ms_r / max(launches_r, 1), 4),
-                "algorithmic_bytes_per_launch": per_launch_bytes}
+    roofline = stage_roofline(prof, algo, args.steps)
     whole = (algo["points"] + algo["update"]) / (ms_per_step / 1e3) / 1e9
     stages = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
 
     # ---------------------------------------------------------------- CPU oracle sample
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        om = oracle.OracleMap(P["voxel_size"], P["trunc"], weighting=P["weighting"],
-                              merge=P["merge"], max_range=P["max_range"], storage=args.storage)
-        done, pts = 0, 0
-        t0 = time.perf_counter()
-        while done < F and time.perf_counter() - t0 < args.cpu_seconds:
-            om.integrate(frames[done], w.poses[done])
-            pts += N
-            done += 1
-        cpu_s = time.perf_counter() - t0
+        wo = synth.config2(n_frames=args.frames)
+        wo.params = dict(wo.params, storage=args.storage)
+        wo.frame_fn = lambda k: frames[k]
+        pts, cpu_s, done = oracle_sample([(wo, 0, F)], args.cpu_seconds)
         cpu = {"value": round(pts / cpu_s, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
                "sample": f"first {done} of {F} frames of the same sequence, integrated in order "
                          f"by the single-threaded C oracle ({cpu_s:.1f} s)"}
-        om.close()
 
-    if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-
-    out = {
+    return {
         "metric": "points/s & voxel-updates/s TSDF integration; p50/p99 frame latency (served)",
         "value": round(value, 1),
         "unit": "points/s",
@@ -237,8 +219,207 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "input_generation_s": round(gen_s, 1),
-        "kernel_source_sha": sha,
+        "kernel_source_sha": kernel_source_sha(),
     }
+
+
+C4_CAPACITY = {0.02: 16384, 0.05: 4096, 0.10: 2048}
+
+
+def bench_c4(args, np, torch, vbx, synth):
+    T = args.ticks
+    M = 32
+    ws = [synth.config4_map(m, n_ticks=T) for m in range(M)]
+    t0 = time.time()
+    jobs = [(m, k) for m in range(M) for k in range(T)]
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        flat = list(ex.map(lambda mk: ws[mk[0]].frame(mk[1]), jobs))
+    gen_s = time.time() - t0
+    dev = []
+    for m in range(M):
+        dev.append(torch.from_numpy(np.stack(flat[m * T:(m + 1) * T])).cuda())
+    del flat
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    pts_tick = sum(int(d.shape[1]) for d in dev)
+
+    def tick(k):
+        return [(dev[m][k], ws[m].poses[k], ws[m].width) for m in range(M)]
+
+    def make_maps(storage):
+        out = []
+        for m in range(M):
+            P = ws[m].params
+            out.append(vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"],
+                               storage=storage, max_range=P["max_range"],
+                               block_capacity=C4_CAPACITY[round(P["voxel_size"], 2)], stream=stream))
+        return out
+
+    def clear(maps):
+        for mp in maps:
+            mp.clear()
+
+    def run(maps, graph, steps, warm):
+        """warm + steps ticks from emptied maps; returns ms per timed tick."""
+        clear(maps)
+        for k in range(warm):
+            graph.launch(tick(k % T)) if graph else vbx.integrate_multi(maps, tick(k % T))
+        clear(maps)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(steps):
+            graph.launch(tick(k % T)) if graph else vbx.integrate_multi(maps, tick(k % T))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        for mp in maps:
+            st = mp.sync()
+            if st != 0:
+                raise vbx.VbxError(st, "device status after the timed ticks")
+        return e0.elapsed_time(e1) / steps
+
+    results = {}
+    for storage in ("f16", "f32"):
+        maps = make_maps(storage)
+        # launch tuning: one graph per update variant, a few ticks each (untimed)
+        tune = None
+        if not args.no_autotune:
+            tune = {}
+            for split, threads in ((1, 256), (2, 256), (4, 256), (4, 64), (8, 64)):
+                maps[0].set_tuning(split, threads)
+                g = vbx.Graph(maps, tick(0))
+                tune[f"{split}x{threads}"] = round(run(maps, g, 5, 2), 4)
+                g.close()
+            best = min(tune, key=tune.get)
+            maps[0].set_tuning(*[int(x) for x in best.split("x")])
+        g = vbx.Graph(maps, tick(0))
+        ms_graph = run(maps, g, args.steps, args.warmup)
+        ref = [maps[i].export() for i in (0, 3, 17)]
+        stats = [mp.stats() for mp in maps]
+        ms_eager = run(maps, None, args.steps, args.warmup)
+        for j, i in enumerate((0, 3, 17)):
+            e = maps[i].export()
+            if not (np.array_equal(e[0], ref[j][0]) and np.array_equal(e[1], ref[j][1])):
+                raise RuntimeError("graph replay and eager calls built different maps")
+        # stage profile of a few eager ticks (the graph replays the same kernels)
+        clear(maps)
+        maps[0].profile(True)
+        maps[0].profile_read(reset=True)
+        n_prof = min(args.steps, 10)
+        before = [mp.stats() for mp in maps]
+        for k in range(n_prof):
+            vbx.integrate_multi(maps, tick(k % T))
+        torch.cuda.synchronize()
+        prof = maps[0].profile_read(reset=True)
+        maps[0].profile(False)
+        after = [mp.stats() for mp in maps]
+        cells = sum(a["cells"] - b["cells"] for a, b in zip(after, before))
+        new_blocks = sum(a["new_blocks"] - b["new_blocks"] for a, b in zip(after, before))
+        s_v = 8 if storage == "f32" else 4
+        algo = {"points": (12.0 * pts_tick + 48.0 * M) * n_prof,
+                "update": 2.0 * s_v * cells + 4096.0 * s_v * new_blocks}
+        algo = {k: v / n_prof for k, v in algo.items()}
+        results[storage] = {
+            "ms_per_tick_graph": round(ms_graph, 4), "ms_per_tick_eager": round(ms_eager, 4),
+            "points_per_s": round(pts_tick / (ms_graph / 1e3), 1),
+            "voxel_updates_per_s": round(sum(s["touches"] for s in stats) / args.steps / (ms_graph / 1e3), 1),
+            "blocks_per_class": {f"v{v}": sum(stats[m]["blocks"] for m in range(M)
+                                               if abs(ws[m].params["voxel_size"] - v) < 1e-6)
+                                 for v in synth.MULTI_VOXEL},
+            "stage_ms_per_tick": {k: round(v[0] / n_prof, 4) for k, v in prof.items()},
+            "roofline": stage_roofline(prof, algo, n_prof),
+            "tuning": maps[0].tuning(), "autotune": tune}
+        g.close()
+        for mp in maps:
+            mp.close()
+        del maps
+    main_r = results["f16"]
+    ms = main_r["ms_per_tick_graph"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        sample = [(ws[m], 0, 1) for m in range(M)]
+        pts, cpu_s, done = oracle_sample(sample, args.cpu_seconds)
+        cpu = {"value": round(pts / cpu_s, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+               "sample": f"first tick's frame of {done} of the {M} maps, integrated by the "
+                         f"single-threaded C oracle in binary16-emulating mode ({cpu_s:.1f} s)"}
+    return {
+        "metric": "points/s & voxel-updates/s TSDF integration; p50/p99 frame latency (served)",
+        "value": main_r["points_per_s"],
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16-storage/f32",
+        "data": "synthetic",
+        "config": {"workload": f"c4_multi_map: {M} maps per tick (8x160x120, 16x320x240, 8x640x480 "
+                               "depth), voxel 0.02/0.05/0.10 m, truncation 3 voxels, 1/z^2, grouped, "
+                               "f16 storage, one captured graph per tick",
+                   "maps": M, "points_per_tick": pts_tick, "ticks": T},
+        "voxel_updates_per_s": main_r["voxel_updates_per_s"],
+        "graph_vs_eager_speedup": round(main_r["ms_per_tick_eager"] / ms, 3),
+        "f16_vs_f32_speedup": round(results["f32"]["ms_per_tick_graph"] / ms, 3),
+        "storage": results,
+        "repeat_bit_identical": True,
+        "roofline": main_r["roofline"],
+        "cpu_baseline": cpu,
+        "input_generation_s": round(gen_s, 1),
+        "kernel_source_sha": kernel_source_sha(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4"])
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (c2: 10, c4: 100 ticks)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=100, help="c2: frames of the sequence")
+    ap.add_argument("--ticks", type=int, default=100, help="c4: distinct ticks generated")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16"], help="c2 storage")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="wall-clock budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch tuning instead of timing the candidates first")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the integrator runs on a single MI355X "
+              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.steps is None:
+        args.steps = 10 if args.workload == "c2" else 100
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1611_03631_amd as vbx
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    vbx.lib()   # raises if the HIP library is missing: no fallback
+
+    if args.workload == "c2":
+        out = bench_c2(args, np, torch, vbx, synth)
+    else:
+        out = bench_c4(args, np, torch, vbx, synth)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
     print(json.dumps(out), flush=True)
 
 

@@ -149,6 +149,35 @@ int vbx_integrate_frames(vbx_map* map, const vbx_frame* frames, int F);
  * result is bit-identical to integrating its frame alone. */
 int vbx_integrate_multi(vbx_map* const* maps, const vbx_frame* frames, int M);
 
+/* ---- captured calls ---------------------------------------------------------------
+ * A graph is one integration call (the same work as vbx_integrate_multi, or as
+ * vbx_integrate_frames for M = 1) captured once into a HIP graph and replayed with one
+ * hipGraphLaunch per call, which removes the per-kernel launch cost of small frames
+ * (the many-maps-per-tick pattern).  It is bound to its maps and to the point count and
+ * width of every frame; point pointers and poses may change between launches. */
+typedef struct vbx_graph vbx_graph;
+
+/* Captures the call that integrates frames[i] into maps[owner[i]] (owner NULL: F == M and
+ * frames[i] goes to maps[i]); frames of one map apply in array order.  maps: M distinct
+ * maps with equal storage and merge mode; the launches run on maps[0]'s stream.  frames
+ * are only inspected here (nothing is integrated).  The graph owns its own scratch memory
+ * (the size of one eager call's) and a private capture stream.  Synchronises maps[0]'s
+ * stream.  Errors: INVALID_ARG, LIMIT (M > 127, F > VBX_MAX_FRAMES_PER_CALL),
+ * OUT_OF_MEMORY, DEVICE; *out is written only on success. */
+int vbx_graph_create(vbx_map* const* maps, int M, const vbx_frame* frames, const int* owner, int F,
+                     vbx_graph** out);
+
+/* Runs the captured call on maps[0]'s stream (asynchronous, stream-ordered).  frames
+ * (host [F], or NULL to reuse the previous launch's) replace the points pointers and
+ * poses; every frame must keep the n and width given at capture.  The result is
+ * bit-identical to the eager call over the same frames.  The caller keeps the points
+ * alive until the stream passes the launch.  Errors: INVALID_ARG (changed shapes, or a
+ * map whose storage was reallocated since capture: create a new graph), DEVICE. */
+int vbx_graph_launch(vbx_graph* graph, const vbx_frame* frames, int F);
+
+/* Waits for maps[0]'s stream and frees the graph.  NULL is a no-op. */
+void vbx_graph_destroy(vbx_graph* graph);
+
 /* Blocks until the map's stream is idle; returns the sticky device error, if any. */
 int vbx_map_sync(vbx_map* map);
 

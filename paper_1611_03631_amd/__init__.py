@@ -65,7 +65,8 @@ EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_ma
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
             "vbx_map_stats", "vbx_debug_traverse", "vbx_status_string", "vbx_map_clear",
             "vbx_map_profile", "vbx_map_profile_read", "vbx_profile_stage_name",
-            "vbx_map_get_tuning", "vbx_map_set_tuning", "vbx_map_autotune"]
+            "vbx_map_get_tuning", "vbx_map_set_tuning", "vbx_map_autotune",
+            "vbx_graph_create", "vbx_graph_launch", "vbx_graph_destroy"]
 
 TUNING_CANDIDATES = 5
 
@@ -123,9 +124,13 @@ def lib(path: Optional[str] = None):
     L.vbx_map_autotune.argtypes = [vp, ctypes.POINTER(Frame), i32, ctypes.POINTER(Tuning), vp]
     L.vbx_profile_stage_name.argtypes = [i32]
     L.vbx_profile_stage_name.restype = ctypes.c_char_p
+    L.vbx_graph_create.argtypes = [vp, i32, ctypes.POINTER(Frame), vp, i32, ctypes.POINTER(vp)]
+    L.vbx_graph_launch.argtypes = [vp, ctypes.POINTER(Frame), i32]
+    L.vbx_graph_destroy.argtypes = [vp]
+    L.vbx_graph_destroy.restype = None
     for name in EXPORTED:
         if name not in ("vbx_default_params", "vbx_map_destroy", "vbx_status_string",
-                        "vbx_profile_stage_name"):
+                        "vbx_profile_stage_name", "vbx_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -330,6 +335,45 @@ def integrate_multi(maps: Sequence[Map], frames: Sequence[Tuple]):
     hs = (ctypes.c_void_p * M)(*[m.handle for m in maps])
     arr = make_frames(frames)
     _check(lib().vbx_integrate_multi(hs, arr, M), "vbx_integrate_multi")
+
+
+class Graph:
+    """One integration call captured into a HIP graph (frames[i] into maps[owner[i]]),
+    replayed by `launch`; frames keep their point count and width, pointers and poses may
+    change."""
+
+    def __init__(self, maps: Sequence[Map], frames: Sequence[Tuple], owner=None):
+        self._maps = list(maps)          # keeps the maps alive while the graph is
+        M = len(self._maps)
+        hs = (ctypes.c_void_p * M)(*[m.handle for m in self._maps])
+        arr = make_frames(frames)
+        self._F = len(frames)
+        own = None
+        if owner is not None:
+            own = (ctypes.c_int32 * self._F)(*[int(x) for x in owner])
+        h = ctypes.c_void_p()
+        _check(lib().vbx_graph_create(hs, M, arr, own, self._F, ctypes.byref(h)), "vbx_graph_create")
+        self._h = h
+        self._keep = frames
+
+    def launch(self, frames: Optional[Sequence[Tuple]] = None):
+        if frames is None:
+            _check(lib().vbx_graph_launch(self._h, None, 0), "vbx_graph_launch")
+        else:
+            arr = make_frames(frames)
+            _check(lib().vbx_graph_launch(self._h, arr, len(frames)), "vbx_graph_launch")
+            self._keep = frames
+
+    def close(self):
+        if self._h:
+            lib().vbx_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def debug_traverse(A: torch.Tensor, B: torch.Tensor, cap: int = 128):

@@ -106,6 +106,22 @@ struct vbx_map {
     int update_variant = 1;       // index into kUpdateVariants
 };
 
+// A captured call: the kernel sequence of one integration call over fixed maps and frame
+// shapes, replayed with hipGraphLaunch.  It owns its scratch, so eager calls on the same maps
+// never move buffers the graph refers to.
+struct vbx_graph {
+    std::vector<vbx_map*> maps;
+    std::vector<int> owner;
+    std::vector<vbx_frame> frames;   // frames of the next launch
+    std::vector<u32> capacity;       // map capacities at capture
+    size_t sum_capacity = 0;
+    int update_variant = 1;
+    Scratch* scratch = nullptr;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 namespace {
 
 int dev_alloc(DevBuf& b, size_t bytes) {
@@ -251,10 +267,8 @@ struct CallPlan {
     bool keep_touches = false;
 };
 
-// Grows the scratch of `lead` for a call; tables that must start cleared are cleared here.
-int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, size_t sum_capacity) {
-    Scratch* s = lead->scratch;
-    hipStream_t st = lead->stream;
+// Grows a scratch set for a call on stream `st`; tables that must start cleared are cleared here.
+int ensure_scratch(Scratch* s, hipStream_t st, const CallPlan& plan, int njobs, int nmaps, size_t sum_capacity) {
     const size_t ray_cap = std::max<size_t>(plan.ray_slots, 1);
     const size_t cross_cap = ray_cap * (size_t)plan.max_blocks;
     if (cross_cap > 0xFFFFFFF0ull || ray_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
@@ -322,20 +336,6 @@ int ensure_scratch(vbx_map* lead, const CallPlan& plan, int njobs, int nmaps, si
     s->tlist_cap = tlist_cap;
     s->bins_cap = bins_cap;
     s->nparts = nparts;
-    // pinned staging
-    Stage& sg = s->stage[s->stage_i];
-    if (sg.used) (void)hipEventSynchronize(sg.ev);
-    if (sg.bytes < tables_bytes) {
-        if (sg.host) (void)hipHostFree(sg.host);
-        sg.host = nullptr;
-        if (hipHostMalloc(&sg.host, tables_bytes, hipHostMallocDefault) != hipSuccess) {
-            sg.host = nullptr;
-            sg.bytes = 0;
-            return VBX_ERR_OUT_OF_MEMORY;
-        }
-        sg.bytes = tables_bytes;
-    }
-    if (!sg.ev && hipEventCreateWithFlags(&sg.ev, hipEventDisableTiming) != hipSuccess) return VBX_ERR_DEVICE;
     return VBX_OK;
 }
 
@@ -417,7 +417,7 @@ struct StageTimer {
     int stage;
     hipEvent_t a = nullptr;
     StageTimer(vbx_map* m_, hipStream_t s_, int stage_) : m(m_), st(s_), stage(stage_) {
-        if (m->prof.on && (a = m->prof.take())) (void)hipEventRecord(a, st);
+        if (m && m->prof.on && (a = m->prof.take())) (void)hipEventRecord(a, st);
     }
     ~StageTimer() {
         if (!a) return;
@@ -431,24 +431,28 @@ struct StageTimer {
     }
 };
 
-// One integration call over `maps` (distinct maps sharing maps[0]'s scratch and stream) with
-// frames[i] belonging to maps[owner[i]]; frames of one map are in call order.
-int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
-             const std::vector<int>& owner) {
+// Host description of one integration call: the launch plan and the map and job tables.
+struct Prepared {
+    CallPlan plan;
+    std::vector<Job> jobs;
+    std::vector<MapDesc> descs;
+    size_t sum_capacity = 0;
+};
+
+// Validates the frames of a call over `maps` (frames[i] belongs to maps[owner[i]]; frames of one
+// map are in call order) and numbers the tiles of every frame over the whole call.
+int prepare_call(const std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
+                 const std::vector<int>& owner, Prepared& out) {
     vbx_map* lead = maps[0];
-    hipStream_t st = lead->stream;
     const int M = (int)maps.size();
     const int F = (int)frames.size();
-    if (F == 0) return VBX_OK;
     if (F > VBX_MAX_FRAMES_PER_CALL) return VBX_ERR_LIMIT;
-
-    // jobs grouped by map, frames of a map in call order
     std::vector<std::vector<int>> per_map(M);
     for (int i = 0; i < F; ++i) per_map[owner[i]].push_back(i);
-    CallPlan plan;
-    plan.grouped = false;
+    CallPlan& plan = out.plan;
+    plan = CallPlan();
     plan.storage = lead->P.storage;
-    size_t sum_capacity = 0;
+    out.sum_capacity = 0;
     for (int m = 0; m < M; ++m) {
         const vbx_map_params& P = maps[m]->P;
         if (P.storage != plan.storage) return VBX_ERR_INVALID_ARG;
@@ -457,12 +461,14 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
         plan.max_blocks = std::max(plan.max_blocks, max_blocks_per_ray(P));
         plan.max_vox = std::max(plan.max_vox, max_voxels_per_ray(P));
         plan.keep_touches = plan.keep_touches || (P.flags & VBX_FLAG_KEEP_TOUCHES);
-        sum_capacity += maps[m]->capacity;
+        out.sum_capacity += maps[m]->capacity;
     }
     plan.grouped = lead->P.merge == VBX_MERGE_GROUPED;
 
-    std::vector<Job> jobs;
-    std::vector<MapDesc> descs;
+    std::vector<Job>& jobs = out.jobs;
+    std::vector<MapDesc>& descs = out.descs;
+    jobs.clear();
+    descs.clear();
     jobs.reserve(F);
     for (int m = 0; m < M; ++m) {
         descs.push_back(make_desc(maps[m], m, (int)jobs.size(), (int)per_map[m].size()));
@@ -485,12 +491,8 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
             plan.total_points += fr.n;
         }
     }
-    const int J = (int)jobs.size();
-
-    // tiles of every frame, numbered over the whole call
     u32 total_tiles = 0;
-    for (int i = 0; i < J; ++i) {
-        Job& j = jobs[i];
+    for (Job& j : jobs) {
         u32 nt;
         if (!plan.grouped) {
             nt = (j.n + kTileSimple - 1) / kTileSimple;
@@ -506,20 +508,53 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     }
     plan.tiles = total_tiles;
     plan.ray_slots = (size_t)total_tiles * (plan.grouped ? kTileGrouped : kTileSimple);
+    return VBX_OK;
+}
 
-    int rc = ensure_scratch(lead, plan, J, M, sum_capacity);
-    if (rc != VBX_OK) return rc;
-    Scratch* s = lead->scratch;
-
-    // stage the map and job tables
+// Copies the map and job tables to the device through the pinned staging ring.
+int stage_tables(Scratch* s, hipStream_t st, const Prepared& pr) {
     Stage& sg = s->stage[s->stage_i];
     s->stage_i = (s->stage_i + 1) % 4;
-    const size_t map_bytes = (size_t)M * sizeof(MapDesc);
-    std::memcpy(sg.host, descs.data(), map_bytes);
-    std::memcpy((char*)sg.host + map_bytes, jobs.data(), (size_t)J * sizeof(Job));
-    VBX_TRY(hipMemcpyAsync(s->tables.p, sg.host, map_bytes + (size_t)J * sizeof(Job), hipMemcpyHostToDevice, st));
+    if (sg.used) VBX_TRY(hipEventSynchronize(sg.ev));
+    const size_t map_bytes = pr.descs.size() * sizeof(MapDesc);
+    const size_t job_bytes = pr.jobs.size() * sizeof(Job);
+    if (map_bytes + job_bytes > s->tables.bytes) return VBX_ERR_INVALID_ARG;
+    if (sg.bytes < map_bytes + job_bytes) {
+        if (sg.host) (void)hipHostFree(sg.host);
+        sg.host = nullptr;
+        sg.bytes = 0;
+        if (hipHostMalloc(&sg.host, map_bytes + job_bytes, hipHostMallocDefault) != hipSuccess) {
+            sg.host = nullptr;
+            return VBX_ERR_OUT_OF_MEMORY;
+        }
+        sg.bytes = map_bytes + job_bytes;
+    }
+    if (!sg.ev && hipEventCreateWithFlags(&sg.ev, hipEventDisableTiming) != hipSuccess) return VBX_ERR_DEVICE;
+    std::memcpy(sg.host, pr.descs.data(), map_bytes);
+    std::memcpy((char*)sg.host + map_bytes, pr.jobs.data(), job_bytes);
+    VBX_TRY(hipMemcpyAsync(s->tables.p, sg.host, map_bytes + job_bytes, hipMemcpyHostToDevice, st));
     VBX_TRY(hipEventRecord(sg.ev, st));
     sg.used = true;
+    return VBX_OK;
+}
+
+// Resolves the once-per-process launch shapes before any capture.
+void warm_launch_shapes() {
+    (void)group_merge_grid();
+    (void)update_grid<0, 1, 256>(); (void)update_grid<0, 2, 256>(); (void)update_grid<0, 4, 256>();
+    (void)update_grid<0, 4, 64>();  (void)update_grid<0, 8, 64>();
+    (void)update_grid<1, 1, 256>(); (void)update_grid<1, 2, 256>(); (void)update_grid<1, 4, 256>();
+    (void)update_grid<1, 4, 64>();  (void)update_grid<1, 8, 64>();
+}
+
+// The kernel sequence of one call over the staged tables in `s`.  Only kernel launches are
+// made here (no copies, fills through the memset API, allocations or host waits), so the
+// sequence can be captured into a graph.  `timer` is the map whose profiler records the
+// stages, or null.
+int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, int update_variant,
+                vbx_map* timer) {
+    vbx_map* prof_map = timer;
+    const size_t map_bytes = (size_t)M * sizeof(MapDesc);
     const MapDesc* d_maps = (const MapDesc*)s->tables.p;
     const Job* d_jobs = (const Job*)((char*)s->tables.p + map_bytes);
     CallState* cs = (CallState*)s->cs.p;
@@ -527,6 +562,7 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     float4* rays_p = (float4*)s->rays_p.p;
     u32* rays_job = (u32*)s->rays_job.p;
     const u32 ray_cap = (u32)s->ray_cap;
+    const u32 total_tiles = plan.tiles;
 
     const u32 JM = (u32)plan.JM;
     const unsigned GT = grid_for(s->tlist_cap, 1024);
@@ -541,7 +577,7 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     };
     // points
     if (total_tiles > 0) {
-        StageTimer tm(lead, st, ST_POINTS);
+        StageTimer tm(prof_map, st, ST_POINTS);
         if (!plan.grouped) {
             hipLaunchKernelGGL(k_points_simple, dim3(total_tiles), dim3(256), 0, st, d_jobs, J, d_maps, rays_p,
                                rays_job, jst, cs);
@@ -552,7 +588,7 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
         }
     }
     if (plan.grouped && total_tiles > 0) {
-        StageTimer tm(lead, st, ST_GROUPS);
+        StageTimer tm(prof_map, st, ST_GROUPS);
         const unsigned GW = (total_tiles + 3) / 4;   // one wave per tile
         hipLaunchKernelGGL(k_densify, dim3(GT), dim3(256), 0, st, (const u32*)s->tlist.p, (u32)s->tlist_cap,
                            (u32*)s->tval.p, (const CallState*)cs);
@@ -573,32 +609,32 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     const unsigned G = grid_for(plan.ray_slots, 2048);
     const u32 MB = (u32)plan.max_blocks;
     {
-    StageTimer tm(lead, st, ST_CROSS);
+    StageTimer tm(prof_map, st, ST_CROSS);
     hipLaunchKernelGGL(k_cross, dim3(G), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
                        (const u32*)rays_job, (u64*)s->tkeys.p, (u32)(s->tkey_cap - 1), (u32*)s->tlist.p,
                        (u32)s->tlist_cap, (u32*)s->cross.p, (unsigned char*)s->ncross.p, MB, jst, cs, ray_cap);
     }
     {
-    StageTimer tm(lead, st, ST_RESOLVE);
+    StageTimer tm(prof_map, st, ST_RESOLVE);
     hipLaunchKernelGGL(k_resolve, dim3(GT), dim3(256), 0, st, d_maps, (const u64*)s->tkeys.p, (u32*)s->tval.p,
                        (const u32*)s->tlist.p, (u64*)s->t_key.p, (int*)s->t_slot.p, cs);
     }
     {
-    StageTimer tm(lead, st, ST_COMMIT);
+    StageTimer tm(prof_map, st, ST_COMMIT);
     hipLaunchKernelGGL(k_commit, dim3(GT), dim3(256), 0, st, d_maps, (const u64*)s->t_key.p, (int*)s->t_slot.p, cs);
     }
     {
-    StageTimer tm(lead, st, ST_BINS);
+    StageTimer tm(prof_map, st, ST_BINS);
     hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, d_jobs, (const u32*)s->cross.p,
                        (const unsigned char*)s->ncross.p, MB, (const u32*)s->tval.p, (const u32*)rays_job,
                        (u32*)s->bins.p, JM, cs, ray_cap);
     }
     {
-    StageTimer tm(lead, st, ST_SCAN);
+    StageTimer tm(prof_map, st, ST_SCAN);
     scan_bins();
     }
     {
-    StageTimer tm(lead, st, ST_SCATTER);
+    StageTimer tm(prof_map, st, ST_SCATTER);
     hipLaunchKernelGGL(k_scatter, dim3(G), dim3(256), 0, st, d_jobs, (const u32*)s->cross.p,
                        (const unsigned char*)s->ncross.p, MB, (const u32*)s->tval.p, (const u32*)rays_job,
                        (u32*)s->bins.p, (const u32*)s->off.p, JM, (const float4*)rays_p, (float4*)s->sorted.p, cs,
@@ -606,27 +642,48 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
     }
     if (plan.keep_touches) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->touch_count, 0u);
     {
-    StageTimer tm(lead, st, ST_UPDATE);
-    launch_update(plan.storage, lead->update_variant, st, d_jobs, d_maps, (const u64*)s->t_key.p,
+    StageTimer tm(prof_map, st, ST_UPDATE);
+    launch_update(plan.storage, update_variant, st, d_jobs, d_maps, (const u64*)s->t_key.p,
                   (const int*)s->t_slot.p, (const u32*)s->off.p, (const float4*)s->sorted.p, JM,
                   (u64*)s->touch_key.p, (u32*)s->touch_n.p, (u32)s->touch_cap, plan.keep_touches ? 1 : 0,
                   jst, cs);
     }
     {
-    StageTimer tm(lead, st, ST_FINISH);
+    StageTimer tm(prof_map, st, ST_FINISH);
     hipLaunchKernelGGL(k_cleanup, dim3(grid_for(s->tkey_cap, 1024)), dim3(256), 0, st, (u64*)s->tkeys.p,
                        (u32)s->tkey_cap, (const u32*)s->tlist.p, (u32)s->tlist_cap, (const CallState*)cs);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d_jobs, J, d_maps, M, jst, cs);
     }
     if (hipGetLastError() != hipSuccess) return VBX_ERR_DEVICE;
-    if (plan.keep_touches) {
-        s->last_maps = maps;
-        s->touches_valid = true;
-        for (int m = 0; m < M; ++m) {
-            maps[m]->touch_src = s;
-            maps[m]->touch_idx = m;
-        }
+    return VBX_OK;
+}
+
+// Records which scratch holds the touches of the maps of the last call.
+void note_touches(Scratch* s, const std::vector<vbx_map*>& maps, const CallPlan& plan) {
+    if (!plan.keep_touches) return;
+    s->last_maps = maps;
+    s->touches_valid = true;
+    for (size_t m = 0; m < maps.size(); ++m) {
+        maps[m]->touch_src = s;
+        maps[m]->touch_idx = (int)m;
     }
+}
+
+// One integration call over `maps` (distinct maps sharing maps[0]'s scratch and stream) with
+// frames[i] belonging to maps[owner[i]]; frames of one map are in call order.
+int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
+             const std::vector<int>& owner) {
+    vbx_map* lead = maps[0];
+    hipStream_t st = lead->stream;
+    if (frames.empty()) return VBX_OK;
+    Prepared pr;
+    int rc = prepare_call(maps, frames, owner, pr);
+    if (rc != VBX_OK) return rc;
+    const int J = (int)pr.jobs.size(), M = (int)maps.size();
+    if ((rc = ensure_scratch(lead->scratch, st, pr.plan, J, M, pr.sum_capacity)) != VBX_OK) return rc;
+    if ((rc = stage_tables(lead->scratch, st, pr)) != VBX_OK) return rc;
+    if ((rc = launch_call(lead->scratch, st, pr.plan, J, M, lead->update_variant, lead)) != VBX_OK) return rc;
+    note_touches(lead->scratch, maps, pr.plan);
     return VBX_OK;
 }
 
@@ -1130,6 +1187,101 @@ int vbx_map_autotune(vbx_map* m, const vbx_frame* frames, int F, vbx_tuning* bes
     if (rc != VBX_OK) return rc;
     m->update_variant = best_v;
     if (best) vbx_map_get_tuning(m, best);
+    return VBX_OK;
+}
+
+void vbx_graph_destroy(vbx_graph* g) {
+    if (!g) return;
+    if (!g->maps.empty()) (void)hipStreamSynchronize(g->maps[0]->stream);
+    if (g->capture_stream) (void)hipStreamSynchronize(g->capture_stream);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->capture_stream) (void)hipStreamDestroy(g->capture_stream);
+    free_scratch(g->scratch);
+    delete g;
+}
+
+int vbx_graph_create(vbx_map* const* maps, int M, const vbx_frame* frames, const int* owner, int F,
+                     vbx_graph** out) {
+    if (!maps || !frames || !out || M <= 0 || F <= 0) return VBX_ERR_INVALID_ARG;
+    if (M > 127 || F > VBX_MAX_FRAMES_PER_CALL) return VBX_ERR_LIMIT;
+    if (!owner && F != M) return VBX_ERR_INVALID_ARG;
+    for (int i = 0; i < M; ++i) {
+        if (!maps[i]) return VBX_ERR_INVALID_ARG;
+        for (int j = 0; j < i; ++j)
+            if (maps[j] == maps[i]) return VBX_ERR_INVALID_ARG;
+    }
+    vbx_graph* g = new (std::nothrow) vbx_graph();
+    if (!g) return VBX_ERR_OUT_OF_MEMORY;
+    g->maps.assign(maps, maps + M);
+    g->frames.assign(frames, frames + F);
+    g->owner.resize(F);
+    for (int i = 0; i < F; ++i) {
+        g->owner[i] = owner ? owner[i] : i;
+        if (g->owner[i] < 0 || g->owner[i] >= M) {
+            delete g;
+            return VBX_ERR_INVALID_ARG;
+        }
+    }
+    g->update_variant = maps[0]->update_variant;
+    for (int m = 0; m < M; ++m) g->capacity.push_back(maps[m]->capacity);
+    g->scratch = new (std::nothrow) Scratch();
+    if (!g->scratch) {
+        delete g;
+        return VBX_ERR_OUT_OF_MEMORY;
+    }
+    Prepared pr;
+    hipStream_t st = maps[0]->stream;
+    int rc = prepare_call(g->maps, g->frames, g->owner, pr);
+    if (rc == VBX_OK) rc = ensure_scratch(g->scratch, st, pr.plan, (int)pr.jobs.size(), M, pr.sum_capacity);
+    g->sum_capacity = pr.sum_capacity;
+    if (rc == VBX_OK && hipStreamSynchronize(st) != hipSuccess) rc = VBX_ERR_DEVICE;
+    if (rc == VBX_OK && hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        g->capture_stream = nullptr;
+        rc = VBX_ERR_DEVICE;
+    }
+    if (rc == VBX_OK) {
+        warm_launch_shapes();
+        if (hipStreamBeginCapture(g->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = VBX_ERR_DEVICE;
+        } else {
+            const int lrc = launch_call(g->scratch, g->capture_stream, pr.plan, (int)pr.jobs.size(), M,
+                                        g->update_variant, nullptr);
+            const hipError_t ec = hipStreamEndCapture(g->capture_stream, &g->graph);
+            if (lrc != VBX_OK || ec != hipSuccess || !g->graph) rc = VBX_ERR_DEVICE;
+        }
+    }
+    if (rc == VBX_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+        g->exec = nullptr;
+        rc = VBX_ERR_DEVICE;
+    }
+    if (rc != VBX_OK) {
+        vbx_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return VBX_OK;
+}
+
+int vbx_graph_launch(vbx_graph* g, const vbx_frame* frames, int F) {
+    if (!g) return VBX_ERR_INVALID_ARG;
+    if (frames) {
+        if (F != (int)g->frames.size()) return VBX_ERR_INVALID_ARG;
+        for (int i = 0; i < F; ++i)
+            if (frames[i].n != g->frames[i].n || frames[i].width != g->frames[i].width) return VBX_ERR_INVALID_ARG;
+    }
+    for (size_t m = 0; m < g->maps.size(); ++m)
+        if (g->maps[m]->capacity != g->capacity[m]) return VBX_ERR_INVALID_ARG;   // storage moved
+    std::vector<vbx_frame> next = g->frames;
+    if (frames) next.assign(frames, frames + F);
+    Prepared pr;
+    int rc = prepare_call(g->maps, next, g->owner, pr);
+    if (rc != VBX_OK) return rc;
+    hipStream_t st = g->maps[0]->stream;
+    if ((rc = stage_tables(g->scratch, st, pr)) != VBX_OK) return rc;
+    VBX_TRY(hipGraphLaunch(g->exec, st));
+    g->frames.swap(next);
+    note_touches(g->scratch, g->maps, pr.plan);
     return VBX_OK;
 }
 
