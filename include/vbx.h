@@ -258,6 +258,77 @@ int vbx_map_set_tuning(vbx_map* map, const vbx_tuning* tuning);
 int vbx_map_autotune(vbx_map* map, const vbx_frame* frames, int F, vbx_tuning* best,
                      double* ms_out);
 
+/* ---- map server ---------------------------------------------------------------------
+ * Many maps (one per robot or sensor) served from one device: integration requests
+ * arrive one frame at a time, each for one map; the server batches whatever has arrived
+ * into the next call ("tick", the vbx_integrate_multi pass, several frames per map
+ * allowed) while the previous tick still runs, so batches form continuously.  Requests
+ * of one map are applied in submission order, and a map served in the mix ends
+ * bit-identical to the same frames integrated into it alone, in that order.  Every map
+ * stays resident in device memory; admission charges each map's storage (hash table and
+ * block pool) against a byte budget.  Two host threads run the server: one forms and
+ * launches ticks, one waits for them and completes requests. */
+typedef struct vbx_server vbx_server;
+
+typedef struct {
+    uint64_t budget_bytes;         /* device memory all maps' storage may take (> 0) */
+    uint32_t max_frames_per_tick;  /* frames per tick (0: 256; at most VBX_MAX_FRAMES_PER_CALL) */
+    uint64_t max_points_per_tick;  /* points per tick (0: 2^24); a larger frame runs alone */
+    int32_t max_inflight;          /* ticks queued on the device at once, 1..3 (0: 2) */
+    int32_t grow;                  /* nonzero: a map whose pool fills is doubled within the
+                                      budget (vbx_map_reserve) and its turned-away requests
+                                      run again; zero: they fail with VBX_ERR_POOL_FULL */
+    void* stream;                  /* hipStream_t of the ticks; NULL: the server creates a
+                                      stream ordered after null-stream work */
+} vbx_server_params;
+
+typedef struct {
+    uint64_t submitted, completed, failed;   /* requests */
+    uint64_t ticks, frames, points, replays; /* frames launched, points completed, requests rerun */
+    uint32_t maps, rejected_maps;
+    uint64_t budget_bytes, used_bytes;
+    double p50_ms, p99_ms, max_ms, mean_ms;  /* arrival -> completion, completed requests */
+    double points_per_s;                     /* completed points / (last completion - first arrival) */
+    double mean_frames_per_tick;
+} vbx_server_summary;
+
+/* Seconds on the server's clock (monotonic); arrival times are given on it. */
+double vbx_server_clock(void);
+
+/* Starts a server on the current device.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+int vbx_server_create(const vbx_server_params* params, vbx_server** out);
+
+/* Admits a map (its stream is the server's; params->block_capacity is its initial pool).
+ * Returns VBX_ERR_OUT_OF_MEMORY, and counts a rejection, when its storage does not fit in
+ * what is left of the budget.  *map_id (0, 1, ...) is written on success. */
+int vbx_server_add_map(vbx_server* server, const vbx_map_params* params, int* map_id);
+
+/* Queues one frame for map_id.  frame->points (device) must stay valid and unchanged
+ * until the request completes.  t_arrival: vbx_server_clock() time the request arrived
+ * (<= 0: now); latency is measured from it.  *ticket (may be NULL) identifies it.
+ * Returns at once; errors (INVALID_ARG, LIMIT) mean nothing was queued. */
+int vbx_server_submit(vbx_server* server, int map_id, const vbx_frame* frame, double t_arrival,
+                      uint64_t* ticket);
+
+/* Blocks until the request completes; writes its status (VBX_OK or the error its map
+ * reported) and completion time (server clock). */
+int vbx_server_wait(vbx_server* server, uint64_t ticket, int* status, double* t_done);
+
+/* Blocks until every queued request has completed. */
+int vbx_server_drain(vbx_server* server);
+
+/* Counters and latency percentiles since the start or the last reset. */
+int vbx_server_stats(vbx_server* server, vbx_server_summary* out);
+
+/* Drains, then restarts the counters and latency record (maps keep their contents). */
+int vbx_server_reset_stats(vbx_server* server);
+
+/* The map behind map_id (owned by the server; NULL if unknown).  Drain before reading it. */
+vbx_map* vbx_server_map(vbx_server* server, int map_id);
+
+/* Drains, stops the threads and frees the server and its maps.  NULL is a no-op. */
+void vbx_server_destroy(vbx_server* server);
+
 /* Human-readable name of a status code (static string). */
 const char* vbx_status_string(int status);
 

@@ -30,7 +30,7 @@ FLAG_KEEP_TOUCHES = 1
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "block pool full",
           -4: "buffer too small", -5: "device error", -6: "limit exceeded"}
-ERR_POOL_FULL = -3
+ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_POOL_FULL = -1, -2, -3
 
 
 class VbxError(RuntimeError):
@@ -66,9 +66,28 @@ EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_ma
             "vbx_map_stats", "vbx_debug_traverse", "vbx_status_string", "vbx_map_clear",
             "vbx_map_profile", "vbx_map_profile_read", "vbx_profile_stage_name",
             "vbx_map_get_tuning", "vbx_map_set_tuning", "vbx_map_autotune",
-            "vbx_graph_create", "vbx_graph_launch", "vbx_graph_destroy"]
+            "vbx_graph_create", "vbx_graph_launch", "vbx_graph_destroy",
+            "vbx_server_clock", "vbx_server_create", "vbx_server_add_map", "vbx_server_submit",
+            "vbx_server_wait", "vbx_server_drain", "vbx_server_stats", "vbx_server_reset_stats",
+            "vbx_server_map", "vbx_server_destroy"]
 
 TUNING_CANDIDATES = 5
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_frames_per_tick", ctypes.c_uint32),
+                ("max_points_per_tick", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
+                ("grow", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class ServerSummary(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("ticks", ctypes.c_uint64), ("frames", ctypes.c_uint64),
+                ("points", ctypes.c_uint64), ("replays", ctypes.c_uint64), ("maps", ctypes.c_uint32),
+                ("rejected_maps", ctypes.c_uint32), ("budget_bytes", ctypes.c_uint64),
+                ("used_bytes", ctypes.c_uint64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("points_per_s", ctypes.c_double), ("mean_frames_per_tick", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -128,9 +147,24 @@ def lib(path: Optional[str] = None):
     L.vbx_graph_launch.argtypes = [vp, ctypes.POINTER(Frame), i32]
     L.vbx_graph_destroy.argtypes = [vp]
     L.vbx_graph_destroy.restype = None
+    L.vbx_server_clock.argtypes = []
+    L.vbx_server_clock.restype = ctypes.c_double
+    L.vbx_server_create.argtypes = [ctypes.POINTER(ServerParams), ctypes.POINTER(vp)]
+    L.vbx_server_add_map.argtypes = [vp, ctypes.POINTER(MapParams), ctypes.POINTER(i32)]
+    L.vbx_server_submit.argtypes = [vp, i32, ctypes.POINTER(Frame), ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    L.vbx_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    L.vbx_server_drain.argtypes = [vp]
+    L.vbx_server_stats.argtypes = [vp, ctypes.POINTER(ServerSummary)]
+    L.vbx_server_reset_stats.argtypes = [vp]
+    L.vbx_server_map.argtypes = [vp, i32]
+    L.vbx_server_map.restype = vp
+    L.vbx_server_destroy.argtypes = [vp]
+    L.vbx_server_destroy.restype = None
     for name in EXPORTED:
         if name not in ("vbx_default_params", "vbx_map_destroy", "vbx_status_string",
-                        "vbx_profile_stage_name", "vbx_graph_destroy"):
+                        "vbx_profile_stage_name", "vbx_graph_destroy", "vbx_server_clock",
+                        "vbx_server_map", "vbx_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -163,6 +197,22 @@ _STORAGE = {"f32": F32, "f16": F16}
 _DIST = {"eq1": DIST_EQ1, "ray": DIST_ALONG_RAY}
 
 
+def map_params(voxel_size: float, trunc: float, weighting: str = "const", merge: str = "simple",
+               storage: str = "f32", w_max: float = 1e4, max_range: float = 5.0, z_min: float = 0.1,
+               dist: str = "eq1", block_capacity: int = 65536, keep_touches: bool = False,
+               stream_handle: int = 0) -> MapParams:
+    p = MapParams()
+    lib().vbx_default_params(ctypes.byref(p))
+    p.voxel_size, p.trunc, p.w_max = voxel_size, trunc, w_max
+    p.max_range, p.z_min = max_range, z_min
+    p.weighting, p.merge = _WEIGHTING[weighting], _MERGE[merge]
+    p.storage, p.dist = _STORAGE[storage], _DIST[dist]
+    p.block_capacity = block_capacity
+    p.flags = FLAG_KEEP_TOUCHES if keep_touches else 0
+    p.stream = stream_handle
+    return p
+
+
 class Map:
     """A TSDF map on the current HIP device (wraps vbx_map)."""
 
@@ -171,23 +221,28 @@ class Map:
                  max_range: float = 5.0, z_min: float = 0.1, dist: str = "eq1",
                  block_capacity: int = 65536, keep_touches: bool = False, stream=None):
         L = lib()
-        p = MapParams()
-        L.vbx_default_params(ctypes.byref(p))
-        p.voxel_size, p.trunc, p.w_max = voxel_size, trunc, w_max
-        p.max_range, p.z_min = max_range, z_min
-        p.weighting, p.merge = _WEIGHTING[weighting], _MERGE[merge]
-        p.storage, p.dist = _STORAGE[storage], _DIST[dist]
-        p.block_capacity = block_capacity
-        p.flags = FLAG_KEEP_TOUCHES if keep_touches else 0
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
-        p.stream = s.cuda_stream
+        p = map_params(voxel_size, trunc, weighting, merge, storage, w_max, max_range, z_min, dist,
+                       block_capacity, keep_touches, s.cuda_stream)
         h = ctypes.c_void_p()
         _check(L.vbx_map_create_ex(ctypes.byref(p), ctypes.byref(h)), "vbx_map_create_ex")
         self._h = h
+        self._owned = True
         self.params = dict(voxel_size=voxel_size, trunc=trunc, weighting=weighting, merge=merge,
                            storage=storage, w_max=w_max, max_range=max_range, z_min=z_min,
                            dist=dist, block_capacity=block_capacity)
+
+    @classmethod
+    def _borrowed(cls, handle, params: dict, owner):
+        """A view of a map another object owns (a server's)."""
+        m = cls.__new__(cls)
+        m._h = ctypes.c_void_p(handle)
+        m._owned = False
+        m._owner = owner
+        m.params = dict(params)
+        m.stream = None
+        return m
 
     @property
     def handle(self):
@@ -195,7 +250,8 @@ class Map:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().vbx_map_destroy(self._h)
+            if getattr(self, "_owned", True):
+                lib().vbx_map_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -368,6 +424,92 @@ class Graph:
         if self._h:
             lib().vbx_graph_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching map server (wraps vbx_server): frames are submitted one request at
+    a time and batched into ticks on the device as they arrive."""
+
+    def __init__(self, budget_bytes: int, max_frames_per_tick: int = 0, max_points_per_tick: int = 0,
+                 max_inflight: int = 0, grow: bool = True, stream=None):
+        p = ServerParams()
+        p.budget_bytes = int(budget_bytes)
+        p.max_frames_per_tick = max_frames_per_tick
+        p.max_points_per_tick = max_points_per_tick
+        p.max_inflight = max_inflight
+        p.grow = 1 if grow else 0
+        p.stream = stream.cuda_stream if stream is not None else None
+        h = ctypes.c_void_p()
+        _check(lib().vbx_server_create(ctypes.byref(p), ctypes.byref(h)), "vbx_server_create")
+        self._h = h
+        self._params = {}
+        self._keep = {}        # points of requests not known to be finished
+        self._frame = Frame()
+
+    @staticmethod
+    def clock() -> float:
+        return float(lib().vbx_server_clock())
+
+    def add_map(self, **kw) -> int:
+        """Admits a map (keyword arguments as for Map); raises VbxError(OUT_OF_MEMORY) when
+        the budget cannot hold it."""
+        p = map_params(**kw)
+        mid = ctypes.c_int32()
+        _check(lib().vbx_server_add_map(self._h, ctypes.byref(p), ctypes.byref(mid)), "vbx_server_add_map")
+        self._params[int(mid.value)] = kw
+        return int(mid.value)
+
+    def submit(self, map_id: int, points, pose, width: int = 0, t_arrival: float = 0.0) -> int:
+        f = self._frame
+        ptr, n = _dev_points(points)
+        f.points, f.n, f.width = ptr, n, width
+        pz = _pose12(pose)
+        for k in range(12):
+            f.pose[k] = float(pz[k])
+        t = ctypes.c_uint64()
+        _check(lib().vbx_server_submit(self._h, map_id, ctypes.byref(f), float(t_arrival), ctypes.byref(t)),
+               "vbx_server_submit")
+        self._keep[int(t.value)] = points
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        """(status, completion time) of a request; blocks until it completes."""
+        st = ctypes.c_int32()
+        td = ctypes.c_double()
+        _check(lib().vbx_server_wait(self._h, ticket, ctypes.byref(st), ctypes.byref(td)), "vbx_server_wait")
+        self._keep.pop(ticket, None)
+        return int(st.value), float(td.value)
+
+    def drain(self):
+        _check(lib().vbx_server_drain(self._h), "vbx_server_drain")
+        self._keep.clear()
+
+    def stats(self) -> dict:
+        s = ServerSummary()
+        _check(lib().vbx_server_stats(self._h, ctypes.byref(s)), "vbx_server_stats")
+        return {name: getattr(s, name) for name, _ in ServerSummary._fields_}
+
+    def reset_stats(self):
+        _check(lib().vbx_server_reset_stats(self._h), "vbx_server_reset_stats")
+        self._keep.clear()
+
+    def map(self, map_id: int) -> Map:
+        h = lib().vbx_server_map(self._h, map_id)
+        if not h:
+            raise VbxError(ERR_INVALID_ARG, "vbx_server_map")
+        return Map._borrowed(h, self._params.get(map_id, {}), self)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vbx_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

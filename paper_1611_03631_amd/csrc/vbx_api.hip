@@ -4,7 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -15,6 +19,7 @@
 #include "../../include/vbx.h"
 #include "vbx_host.h"
 #include "vbx_internal.h"
+#include "vbx_sched.h"
 
 using namespace vbx;
 
@@ -669,22 +674,34 @@ void note_touches(Scratch* s, const std::vector<vbx_map*>& maps, const CallPlan&
     }
 }
 
-// One integration call over `maps` (distinct maps sharing maps[0]'s scratch and stream) with
-// frames[i] belonging to maps[owner[i]]; frames of one map are in call order.
-int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
-             const std::vector<int>& owner) {
-    vbx_map* lead = maps[0];
-    hipStream_t st = lead->stream;
+// One integration call over `maps` (distinct maps) with frames[i] belonging to
+// maps[owner[i]]; frames of one map are in call order.  Runs on stream `st` with scratch `s`.
+int run_call_on(Scratch* s, hipStream_t st, std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
+                const std::vector<int>& owner, int update_variant, vbx_map* timer) {
     if (frames.empty()) return VBX_OK;
     Prepared pr;
     int rc = prepare_call(maps, frames, owner, pr);
     if (rc != VBX_OK) return rc;
     const int J = (int)pr.jobs.size(), M = (int)maps.size();
-    if ((rc = ensure_scratch(lead->scratch, st, pr.plan, J, M, pr.sum_capacity)) != VBX_OK) return rc;
-    if ((rc = stage_tables(lead->scratch, st, pr)) != VBX_OK) return rc;
-    if ((rc = launch_call(lead->scratch, st, pr.plan, J, M, lead->update_variant, lead)) != VBX_OK) return rc;
-    note_touches(lead->scratch, maps, pr.plan);
+    if ((rc = ensure_scratch(s, st, pr.plan, J, M, pr.sum_capacity)) != VBX_OK) return rc;
+    if ((rc = stage_tables(s, st, pr)) != VBX_OK) return rc;
+    if ((rc = launch_call(s, st, pr.plan, J, M, update_variant, timer)) != VBX_OK) return rc;
+    note_touches(s, maps, pr.plan);
     return VBX_OK;
+}
+
+// A call on maps[0]'s scratch and stream.
+int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
+             const std::vector<int>& owner) {
+    vbx_map* lead = maps[0];
+    return run_call_on(lead->scratch, lead->stream, maps, frames, owner, lead->update_variant, lead);
+}
+
+// Device memory a map of `capacity` blocks holds (hash table, block pool, state).
+uint64_t map_storage_bytes(const vbx_map_params& P, uint64_t capacity) {
+    const uint64_t hcap = next_pow2((size_t)capacity * 2);
+    const uint64_t vb = P.storage == VBX_F16 ? 4 : 8;
+    return hcap * (sizeof(u64) + sizeof(int)) + capacity * 4096 * vb + sizeof(MapState);
 }
 
 int read_state(vbx_map* m, MapState* out) {
@@ -700,6 +717,195 @@ void host_insert(std::vector<u64>& keys, std::vector<int>& slots, u64 key, int s
     while (keys[h] != kEmpty && keys[h] != key) h = (h + 1) & mask;
     keys[h] = key;
     slots[h] = slot;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Map server: integration requests of many maps batched into ticks as they arrive
+// ===========================================================================
+namespace {
+
+double server_clock() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr int kServerSlots = 4;          // status slots; more than the ticks ever in flight
+constexpr int kServerMaxMapsPerTick = 127;
+
+struct ServerEntry {
+    vbx_sched::Request req;
+    vbx_frame frame;
+};
+
+struct TickRec {
+    std::vector<vbx_sched::Request*> reqs;
+    std::vector<int> owner;              // map of each request within the call
+    hipEvent_t ev = nullptr;
+    int slot = 0;
+    int launch_status = VBX_OK;          // a call that could not be launched
+};
+
+}  // namespace
+
+struct vbx_server {
+    vbx_server_params P;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Scratch* scratch = nullptr;
+    vbx_sched::Planner planner{0};
+    std::vector<vbx_map*> maps;
+    std::deque<ServerEntry> entries;     // by ticket - 1
+    std::mutex mu;
+    std::condition_variable cv_engine, cv_complete, cv_done;
+    std::deque<TickRec> inflight;
+    std::vector<hipEvent_t> spare_events;
+    int* status_dev = nullptr;           // [kServerSlots][128]
+    int* status_host = nullptr;          // pinned mirror
+    int next_slot = 0;
+    std::thread engine, completer;
+    bool stop = false;
+    // statistics
+    uint64_t submitted = 0, finished = 0, failed = 0, ticks = 0, frames = 0, points = 0, replays = 0;
+    uint32_t rejected_maps = 0;
+    double first_arrival = 1e300, last_done = 0.0;
+    std::vector<double> latency;         // seconds, completed requests
+};
+
+namespace {
+
+// Finished requests enter the statistics; caller holds the lock.
+void server_account(vbx_server* S, const std::vector<vbx_sched::Request*>& fin) {
+    for (vbx_sched::Request* r : fin) {
+        S->finished++;
+        if (r->status != VBX_OK) {
+            S->failed++;
+            continue;
+        }
+        S->points += r->points;
+        S->latency.push_back(r->t_done - r->t_arrival);
+        S->first_arrival = std::min(S->first_arrival, r->t_arrival);
+        S->last_done = std::max(S->last_done, r->t_done);
+    }
+}
+
+// A map whose pool filled: grow it within the budget and queue its turned-away requests
+// again; if it cannot grow, clear its error and run them again one at a time, so that only
+// a request that overflows the pool on its own fails.  Called with the lock held (released
+// around the device calls); the map has no tick in flight.
+void server_recover(vbx_server* S, int id, std::unique_lock<std::mutex>& lk) {
+    vbx_map* m = S->maps[(size_t)id];
+    const size_t n_replay = S->planner.map(id).replay.size();
+    const uint64_t cap = m->capacity;
+    const uint64_t ncap = cap * 2;
+    const uint64_t extra = map_storage_bytes(m->P, ncap) - map_storage_bytes(m->P, cap);
+    const bool charged = n_replay > 0 && S->P.grow && ncap <= (1u << 29) && S->planner.grow(id, extra);
+    lk.unlock();
+    int rc = charged ? vbx_map_reserve(m, (uint32_t)ncap) : VBX_ERR_POOL_FULL;
+    if (rc != VBX_OK) (void)vbx_map_clear_error(m);   // the map is as it was before the full call
+    lk.lock();
+    if (charged && rc != VBX_OK) S->planner.release(id, extra);
+    S->replays += n_replay;
+    S->planner.requeue(id, rc != VBX_OK);
+}
+
+void server_engine(vbx_server* S) {
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv_engine.wait(lk, [&] {
+            return S->stop || ((int)S->inflight.size() < S->P.max_inflight &&
+                               (S->planner.has_work() || !S->planner.recoverable().empty()));
+        });
+        if (S->stop) break;
+        const std::vector<int> rec = S->planner.recoverable();
+        if (!rec.empty()) {
+            server_recover(S, rec[0], lk);
+            continue;
+        }
+        std::vector<vbx_sched::Request*> tick = S->planner.next_tick(
+            S->P.max_frames_per_tick, S->P.max_points_per_tick, kServerMaxMapsPerTick);
+        if (tick.empty()) {
+            // not expected (has_work promises a request); never spin holding the lock
+            S->cv_engine.wait_for(lk, std::chrono::milliseconds(1));
+            continue;
+        }
+        // maps of the call in order of first appearance
+        std::vector<vbx_map*> cm;
+        std::vector<int> ids, owner;
+        std::vector<vbx_frame> fr;
+        for (const vbx_sched::Request* r : tick) {
+            size_t j = 0;
+            while (j < ids.size() && ids[j] != r->map) ++j;
+            if (j == ids.size()) {
+                ids.push_back(r->map);
+                cm.push_back(S->maps[(size_t)r->map]);
+            }
+            owner.push_back((int)j);
+            fr.push_back(S->entries[(size_t)(r->ticket - 1)].frame);
+        }
+        hipEvent_t ev = nullptr;
+        if (!S->spare_events.empty()) {
+            ev = S->spare_events.back();
+            S->spare_events.pop_back();
+        }
+        const int slot = S->next_slot;
+        S->next_slot = (slot + 1) % kServerSlots;
+        lk.unlock();
+        if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+        int rc = run_call_on(S->scratch, S->stream, cm, fr, owner, cm[0]->update_variant, nullptr);
+        if (rc == VBX_OK) {
+            hipLaunchKernelGGL(k_map_status, dim3(1), dim3(128), 0, S->stream, (const MapDesc*)S->scratch->tables.p,
+                               (int)cm.size(), S->status_dev + 128 * slot);
+            if (hipMemcpyAsync(S->status_host + 128 * slot, S->status_dev + 128 * slot, sizeof(int) * cm.size(),
+                               hipMemcpyDeviceToHost, S->stream) != hipSuccess)
+                rc = VBX_ERR_DEVICE;
+        }
+        if (!ev || hipEventRecord(ev, S->stream) != hipSuccess) rc = VBX_ERR_DEVICE;
+        lk.lock();
+        TickRec t;
+        t.reqs = std::move(tick);
+        t.owner = std::move(owner);
+        t.ev = ev;
+        t.slot = slot;
+        t.launch_status = rc;
+        S->ticks++;
+        S->frames += t.reqs.size();
+        S->inflight.push_back(std::move(t));
+        S->cv_complete.notify_one();
+    }
+}
+
+void server_completer(vbx_server* S) {
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv_complete.wait(lk, [&] { return S->stop || !S->inflight.empty(); });
+        if (S->inflight.empty()) {
+            if (S->stop) break;
+            continue;
+        }
+        hipEvent_t ev = S->inflight.front().ev;
+        lk.unlock();
+        const hipError_t e = ev ? hipEventSynchronize(ev) : hipErrorInvalidValue;
+        const double now = server_clock();
+        lk.lock();
+        TickRec t = std::move(S->inflight.front());
+        S->inflight.pop_front();
+        std::vector<int> st(t.reqs.size());
+        for (size_t i = 0; i < t.reqs.size(); ++i) {
+            if (t.launch_status != VBX_OK) st[i] = t.launch_status;
+            else if (e != hipSuccess) st[i] = VBX_ERR_DEVICE;
+            else st[i] = S->status_host[128 * t.slot + t.owner[i]];
+        }
+        std::vector<vbx_sched::Request*> fin;
+        S->planner.complete(t.reqs, st, now, &fin);
+        server_account(S, fin);
+        if (ev) S->spare_events.push_back(ev);
+        S->cv_engine.notify_one();
+        S->cv_done.notify_all();
+    }
 }
 
 }  // namespace
@@ -1283,6 +1489,199 @@ int vbx_graph_launch(vbx_graph* g, const vbx_frame* frames, int F) {
     g->frames.swap(next);
     note_touches(g->scratch, g->maps, pr.plan);
     return VBX_OK;
+}
+
+double vbx_server_clock(void) { return server_clock(); }
+
+int vbx_server_create(const vbx_server_params* params, vbx_server** out) {
+    if (!params || !out || params->budget_bytes == 0) return VBX_ERR_INVALID_ARG;
+    if (params->max_inflight < 0 || params->max_inflight >= kServerSlots) return VBX_ERR_INVALID_ARG;
+    vbx_server* S = new (std::nothrow) vbx_server();
+    if (!S) return VBX_ERR_OUT_OF_MEMORY;
+    S->P = *params;
+    if (S->P.max_frames_per_tick == 0 || S->P.max_frames_per_tick > VBX_MAX_FRAMES_PER_CALL)
+        S->P.max_frames_per_tick = 256;
+    if (S->P.max_points_per_tick == 0) S->P.max_points_per_tick = (uint64_t)1 << 24;
+    if (S->P.max_inflight == 0) S->P.max_inflight = 2;
+    S->planner = vbx_sched::Planner(params->budget_bytes);
+    (void)hipGetDevice(&S->device);
+    int rc = VBX_OK;
+    if (params->stream) {
+        S->stream = (hipStream_t)params->stream;
+    } else if (hipStreamCreate(&S->stream) == hipSuccess) {   // orders after null-stream uploads
+        S->own_stream = true;
+    } else {
+        rc = VBX_ERR_DEVICE;
+    }
+    S->scratch = new (std::nothrow) Scratch();
+    if (rc == VBX_OK && !S->scratch) rc = VBX_ERR_OUT_OF_MEMORY;
+    if (rc == VBX_OK && hipMalloc(&S->status_dev, sizeof(int) * 128 * kServerSlots) != hipSuccess) {
+        S->status_dev = nullptr;
+        rc = VBX_ERR_OUT_OF_MEMORY;
+    }
+    if (rc == VBX_OK && hipHostMalloc(&S->status_host, sizeof(int) * 128 * kServerSlots, hipHostMallocDefault) !=
+                            hipSuccess) {
+        S->status_host = nullptr;
+        rc = VBX_ERR_OUT_OF_MEMORY;
+    }
+    if (rc != VBX_OK) {
+        if (S->status_dev) (void)hipFree(S->status_dev);
+        if (S->own_stream) (void)hipStreamDestroy(S->stream);
+        free_scratch(S->scratch);
+        delete S;
+        return rc;
+    }
+    warm_launch_shapes();
+    S->engine = std::thread(server_engine, S);
+    S->completer = std::thread(server_completer, S);
+    *out = S;
+    return VBX_OK;
+}
+
+int vbx_server_add_map(vbx_server* S, const vbx_map_params* params, int* map_id) {
+    if (!S || !params || !map_id) return VBX_ERR_INVALID_ARG;
+    int rc = validate_params(*params);
+    if (rc != VBX_OK) return rc;
+    vbx_map_params p = *params;
+    p.stream = S->stream;
+    const uint64_t bytes = map_storage_bytes(p, p.block_capacity);
+    int id = -1;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (!S->planner.admit(bytes, &id)) {
+            S->rejected_maps++;
+            return VBX_ERR_OUT_OF_MEMORY;
+        }
+        S->maps.push_back(nullptr);
+    }
+    vbx_map* m = nullptr;
+    rc = vbx_map_create_ex(&p, &m);
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (rc != VBX_OK) {
+        // the budget stays charged to a slot that never receives requests
+        S->rejected_maps++;
+        return rc;
+    }
+    S->maps[(size_t)id] = m;
+    *map_id = id;
+    return VBX_OK;
+}
+
+int vbx_server_submit(vbx_server* S, int map_id, const vbx_frame* frame, double t_arrival, uint64_t* ticket) {
+    if (!S || !frame) return VBX_ERR_INVALID_ARG;
+    if (frame->n > VBX_MAX_POINTS_PER_FRAME) return VBX_ERR_LIMIT;
+    if ((frame->n > 0 && !frame->points) || (frame->width > 0 && frame->n % frame->width != 0))
+        return VBX_ERR_INVALID_ARG;
+    for (int q = 0; q < 12; ++q)
+        if (!std::isfinite(frame->pose[q])) return VBX_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (map_id < 0 || map_id >= (int)S->maps.size() || !S->maps[(size_t)map_id]) return VBX_ERR_INVALID_ARG;
+    S->entries.emplace_back();
+    ServerEntry& e = S->entries.back();
+    e.frame = *frame;
+    e.req.ticket = S->entries.size();
+    e.req.map = map_id;
+    e.req.points = frame->n;
+    e.req.t_arrival = t_arrival > 0.0 ? t_arrival : server_clock();
+    S->planner.submit(&e.req);
+    S->submitted++;
+    if (ticket) *ticket = e.req.ticket;
+    S->cv_engine.notify_one();
+    return VBX_OK;
+}
+
+int vbx_server_wait(vbx_server* S, uint64_t ticket, int* status, double* t_done) {
+    if (!S) return VBX_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (ticket == 0 || ticket > S->entries.size()) return VBX_ERR_INVALID_ARG;
+    vbx_sched::Request& r = S->entries[(size_t)(ticket - 1)].req;
+    S->cv_done.wait(lk, [&] { return r.state == 2; });
+    if (status) *status = r.status;
+    if (t_done) *t_done = r.t_done;
+    return VBX_OK;
+}
+
+int vbx_server_drain(vbx_server* S) {
+    if (!S) return VBX_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->finished == S->submitted; });
+    return VBX_OK;
+}
+
+int vbx_server_stats(vbx_server* S, vbx_server_summary* out) {
+    if (!S || !out) return VBX_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    std::memset(out, 0, sizeof *out);
+    out->submitted = S->submitted;
+    out->completed = S->finished - S->failed;
+    out->failed = S->failed;
+    out->ticks = S->ticks;
+    out->frames = S->frames;
+    out->points = S->points;
+    out->replays = S->replays;
+    out->maps = (uint32_t)S->planner.num_maps();
+    out->rejected_maps = S->rejected_maps;
+    out->budget_bytes = S->planner.budget();
+    out->used_bytes = S->planner.used();
+    out->mean_frames_per_tick = S->ticks ? (double)S->frames / (double)S->ticks : 0.0;
+    std::vector<double> lat = S->latency;
+    if (!lat.empty()) {
+        std::sort(lat.begin(), lat.end());
+        auto pct = [&](double q) {
+            const size_t i = (size_t)std::min<double>((double)lat.size() - 1, std::ceil(q * (double)lat.size()) - 1);
+            return lat[i] * 1e3;
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        out->max_ms = lat.back() * 1e3;
+        double sum = 0.0;
+        for (double x : lat) sum += x;
+        out->mean_ms = sum / (double)lat.size() * 1e3;
+        if (S->last_done > S->first_arrival)
+            out->points_per_s = (double)S->points / (S->last_done - S->first_arrival);
+    }
+    return VBX_OK;
+}
+
+int vbx_server_reset_stats(vbx_server* S) {
+    if (!S) return VBX_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->finished == S->submitted; });
+    S->submitted = S->finished = S->failed = S->ticks = S->frames = S->points = S->replays = 0;
+    S->first_arrival = 1e300;
+    S->last_done = 0.0;
+    S->latency.clear();
+    return VBX_OK;
+}
+
+vbx_map* vbx_server_map(vbx_server* S, int map_id) {
+    if (!S) return nullptr;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (map_id < 0 || map_id >= (int)S->maps.size()) return nullptr;
+    return S->maps[(size_t)map_id];
+}
+
+void vbx_server_destroy(vbx_server* S) {
+    if (!S) return;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv_done.wait(lk, [&] { return S->finished == S->submitted; });
+        S->stop = true;
+    }
+    S->cv_engine.notify_all();
+    S->cv_complete.notify_all();
+    if (S->engine.joinable()) S->engine.join();
+    if (S->completer.joinable()) S->completer.join();
+    (void)hipStreamSynchronize(S->stream);
+    for (vbx_map* m : S->maps) vbx_map_destroy(m);
+    for (hipEvent_t e : S->spare_events) (void)hipEventDestroy(e);
+    for (TickRec& t : S->inflight)
+        if (t.ev) (void)hipEventDestroy(t.ev);
+    free_scratch(S->scratch);
+    if (S->status_dev) (void)hipFree(S->status_dev);
+    if (S->status_host) (void)hipHostFree(S->status_host);
+    if (S->own_stream) (void)hipStreamDestroy(S->stream);
+    delete S;
 }
 
 const char* vbx_status_string(int status) {

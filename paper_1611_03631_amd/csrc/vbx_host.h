@@ -16,6 +16,7 @@ struct JobStat {
 __global__ void k_fill_u64(u64* p, u64 val, size_t n);
 __global__ void k_fill_u32(u32* p, u32 val, size_t n);
 __global__ void k_set_u32(u32* p, u32 v);
+__global__ void k_map_status(const MapDesc* maps, int nmaps, int* out);
 __global__ void k_points_simple(const Job* jobs, int njobs, const MapDesc* maps, float4* rays_p,
                                 u32* rays_job, JobStat* jst, CallState* cs);
 __global__ void k_points_grouped(const Job* jobs, int njobs, const MapDesc* maps, u64* tkeys,

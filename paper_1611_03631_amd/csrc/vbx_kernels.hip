@@ -96,6 +96,11 @@ __global__ void k_fill_u32(u32* p, u32 val, size_t n) {
 }
 __global__ void k_set_u32(u32* p, u32 v) { *p = v; }
 
+// Status each map of a call was left in (maps of the staged table, in table order).
+__global__ void k_map_status(const MapDesc* __restrict__ maps, int nmaps, int* __restrict__ out) {
+    for (int m = threadIdx.x; m < nmaps; m += blockDim.x) out[m] = maps[m].st->error;
+}
+
 // Job of a tile: the last job whose first tile is <= tile (first tiles are non-decreasing),
 // found with one round of loads and a vote.  Every lane of the wave must call it.
 __device__ inline int job_of_tile(const Job* jobs, int njobs, u32 tile) {
