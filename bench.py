@@ -12,6 +12,10 @@ the frames are resident in HBM before timing starts.
 tick, binary16 storage; one step is one tick, replayed from a captured graph.  The eager
 multi-map call and binary32 storage are timed beside it.
 
+--workload c3: 50 sweeps of a 64x2048 LiDAR along a street (voxel 0.20 m, range 60 m, constant
+weight, per-point raycasting), batched in one call; the same sweeps streamed one call each from
+a 4096-block pool that the host doubles whenever a sweep finds it full.
+
 --workload c5: 64 robots (the four sensor classes above plus a 64x2048 LiDAR) send frames
 as Poisson streams of 5-30 Hz each; a 10 s seeded trace is replayed in real time through
 the map server, which batches whatever has arrived into each tick.  Reports served points/s
@@ -183,6 +187,51 @@ def bench_c2(args, np, torch, vbx, synth):
     whole = (algo["points"] + algo["update"]) / (ms_per_step / 1e3) / 1e9
     stages = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
 
+    # ---------------------------------------------------------------- forms compared on this GPU
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    forms = {}
+    if not args.no_forms:
+        plain = vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"],
+                        storage="f32", max_range=P["max_range"], block_capacity=16384, stream=stream)
+        pose_ptrs = [np.ascontiguousarray(w.poses[k], np.float32).reshape(12) for k in range(F)]
+
+        def per_frame():      # one vbx_integrate call per frame, binary32 storage
+            L.vbx_map_clear(plain.handle)
+            for k in range(F):
+                rc = L.vbx_integrate(plain.handle, dev[k].data_ptr(), N, pose_ptrs[k].ctypes.data)
+                if rc != 0:
+                    raise vbx.VbxError(rc, "vbx_integrate")
+        forms["plain_per_frame_f32_ms"] = round(timed(per_frame, 3), 4)
+        half = vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"],
+                       storage="f16", max_range=P["max_range"], block_capacity=16384, stream=stream)
+        half.set_tuning(**m.tuning())
+        harr = vbx.make_frames(batch)
+
+        def batched_half():
+            L.vbx_map_clear(half.handle)
+            rc = L.vbx_integrate_frames(half.handle, harr, F)
+            if rc != 0:
+                raise vbx.VbxError(rc, "vbx_integrate_frames")
+        forms["batched_f16_ms"] = round(timed(batched_half, 5), 4)
+        forms["batched_f32_ms"] = round(ms_per_step, 4)
+        forms["batched_f16_vs_plain_per_frame_f32"] = round(forms["plain_per_frame_f32_ms"] /
+                                                            forms["batched_f16_ms"], 3)
+        if plain.sync() != 0 or half.sync() != 0:
+            raise RuntimeError("device status after the compared forms")
+        plain.close()
+        half.close()
+
     # ---------------------------------------------------------------- CPU oracle sample
     cpu = None
     if not args.no_cpu_baseline:
@@ -217,6 +266,7 @@ def bench_c2(args, np, torch, vbx, synth):
         "blocks": st["blocks"],
         "whole_step_algorithmic_GBps": round(whole, 1),
         "stage_ms_per_step": stages,
+        "forms_ms_per_step": forms,
         "wall_s": round(wall_s, 3),
         "repeat_bit_identical": True,
         "tuning": m.tuning(),
@@ -371,6 +421,132 @@ def bench_c4(args, np, torch, vbx, synth):
         "storage": results,
         "repeat_bit_identical": True,
         "roofline": main_r["roofline"],
+        "cpu_baseline": cpu,
+        "input_generation_s": round(gen_s, 1),
+        "kernel_source_sha": kernel_source_sha(),
+    }
+
+
+def bench_c3(args, np, torch, vbx, synth):
+    """50 LiDAR sweeps along a street: batched into one call, and streamed sweep by sweep from
+    a small pool that the host grows (vbx_map_reserve) whenever it fills."""
+    S = 50
+    w = synth.config3(n_sweeps=S)
+    t0 = time.time()
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        frames = list(ex.map(w.frame, range(S)))
+    gen_s = time.time() - t0
+    dev = torch.from_numpy(np.stack(frames)).cuda()
+    torch.cuda.synchronize()
+    P = w.params
+    stream = torch.cuda.current_stream()
+    N = int(dev.shape[1])
+    batch = [(dev[k], w.poses[k], w.width) for k in range(S)]
+    L = vbx.lib()
+
+    # streamed: one call per sweep, pool doubled by the host when a sweep finds it full
+    m = vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"], storage="f32",
+                max_range=P["max_range"], block_capacity=4096, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    rehash = 0
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for k in range(S):
+        m.integrate_frames([batch[k]])
+        if m.sync() == vbx.ERR_POOL_FULL:         # the map is as it was before the sweep
+            cap = m.params["block_capacity"] * 2
+            while True:
+                m.reserve(cap)
+                m.params["block_capacity"] = cap
+                rehash += 1
+                m.integrate_frames([batch[k]])
+                if m.sync() != vbx.ERR_POOL_FULL:
+                    break
+                cap *= 2
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stream_wall = time.perf_counter() - t_wall
+    stream_ms = e0.elapsed_time(e1)
+    st_stream = m.stats()
+    ref = m.export()
+    cap = m.params["block_capacity"]
+    m.close()
+
+    # batched: the whole sequence in one call into a pool of the final size
+    b = vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"], storage="f32",
+                max_range=P["max_range"], block_capacity=cap, stream=stream)
+    arr = vbx.make_frames(batch)
+
+    def step():
+        L.vbx_map_clear(b.handle)
+        rc = L.vbx_integrate_frames(b.handle, arr, S)
+        if rc != 0:
+            raise vbx.VbxError(rc, "vbx_integrate_frames")
+    tune = None
+    if not args.no_autotune:
+        tune = b.autotune(batch)
+        tune["ms"] = [round(x, 4) for x in tune["ms"]]
+    for _ in range(max(args.warmup, 1)):
+        step()
+    if b.sync() != 0:
+        raise RuntimeError("device status after warm-up")
+    out_b = b.export()
+    if not (np.array_equal(out_b[0], ref[0]) and np.array_equal(out_b[1], ref[1])):
+        raise RuntimeError("batched sweeps and streamed sweeps built different maps")
+    b.profile(True)
+    b.profile_read(reset=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    if b.sync() != 0:
+        raise RuntimeError("device status after the timed steps")
+    ms = e0.elapsed_time(e1) / args.steps
+    prof = b.profile_read(reset=True)
+    b.profile(False)
+    st = b.stats()
+    tuning = b.tuning()
+    b.close()
+    algo = {"points": 12.0 * S * N + 48.0 * S,
+            "update": 2.0 * 8 * st["cells"] + 4096.0 * 8 * st["new_blocks"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        w.frame_fn = lambda k: frames[k]
+        pts, cpu_s, done = oracle_sample([(w, 0, S)], args.cpu_seconds)
+        cpu = {"value": round(pts / cpu_s, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {done} of {S} sweeps in order by the single-threaded C oracle ({cpu_s:.1f} s)"}
+    return {
+        "metric": "points/s & voxel-updates/s TSDF integration; p50/p99 frame latency (served)",
+        "value": round(S * N / (ms / 1e3), 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {S} sweeps of a 64x2048 LiDAR along a street, voxel 0.20 m, "
+                               "truncation 0.60 m, range 60 m, constant weight, per-point raycasting, f32",
+                   "sweeps": S, "points_per_sweep": N},
+        "voxel_updates_per_s": round(st["touches"] / (ms / 1e3), 1),
+        "blocks": st["blocks"],
+        "blocks_allocated_per_s": round(st["new_blocks"] / (ms / 1e3), 1),
+        "streamed": {"ms_total": round(stream_ms, 3), "wall_s": round(stream_wall, 3),
+                     "rehashes": rehash, "initial_capacity": 4096, "final_capacity": cap,
+                     "points_per_s": round(S * N / (stream_ms / 1e3), 1),
+                     "blocks": st_stream["blocks"]},
+        "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
+        "repeat_bit_identical": True,
+        "tuning": tuning,
+        "autotune": tune,
+        "roofline": stage_roofline(prof, algo, args.steps),
         "cpu_baseline": cpu,
         "input_generation_s": round(gen_s, 1),
         "kernel_source_sha": kernel_source_sha(),
@@ -533,9 +709,11 @@ def bench_c5(args, np, torch, vbx, synth):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--no-forms", action="store_true",
+                    help="c2: skip timing the plain per-frame f32 and batched f16 forms")
     ap.add_argument("--duration", type=float, default=10.0, help="c5: trace length in seconds")
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (c2: 10, c4: 100 ticks)")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (c2, c3: 10; c4: 100 ticks)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=100, help="c2: frames of the sequence")
     ap.add_argument("--ticks", type=int, default=100, help="c4: distinct ticks generated")
@@ -554,7 +732,7 @@ def main():
               "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.steps is None:
-        args.steps = 10 if args.workload == "c2" else 100
+        args.steps = 100 if args.workload == "c4" else 10
 
     import numpy as np
     import torch
@@ -569,6 +747,8 @@ def main():
 
     if args.workload == "c2":
         out = bench_c2(args, np, torch, vbx, synth)
+    elif args.workload == "c3":
+        out = bench_c3(args, np, torch, vbx, synth)
     elif args.workload == "c4":
         out = bench_c4(args, np, torch, vbx, synth)
     else:
