@@ -341,13 +341,14 @@ def bench_c4(args, np, torch, vbx, synth):
         tune = None
         if not args.no_autotune:
             tune = {}
-            for split, threads in ((1, 256), (2, 256), (4, 256), (4, 64), (8, 64)):
-                maps[0].set_tuning(split, threads)
+            for split, columns, threads in vbx.TUNING_LIST:
+                maps[0].set_tuning(split, threads, columns)
                 g = vbx.Graph(maps, tick(0))
-                tune[f"{split}x{threads}"] = round(run(maps, g, 5, 2), 4)
+                tune[f"{split}{'c' if columns else 'z'}x{threads}"] = round(run(maps, g, 5, 2), 4)
                 g.close()
             best = min(tune, key=tune.get)
-            maps[0].set_tuning(*[int(x) for x in best.split("x")])
+            sc, th = best.split("x")
+            maps[0].set_tuning(int(sc[:-1]), int(th), 1 if sc[-1] == "c" else 0)
         g = vbx.Graph(maps, tick(0))
         ms_graph = run(maps, g, args.steps, args.warmup)
         ref = [maps[i].export() for i in (0, 3, 17)]

@@ -239,12 +239,15 @@ int vbx_map_profile_read(vbx_map* map, vbx_profile* out, int reset);
 const char* vbx_profile_stage_name(int stage);
 
 /* Launch tuning of a map's calls.  Results never depend on it. */
-#define VBX_TUNING_CANDIDATES 5
+#define VBX_TUNING_CANDIDATES 10
 typedef struct {
-    int32_t update_split;   /* z-slabs per block in the update stage (default 2) */
-    int32_t update_threads; /* threads per update workgroup (default 256); the candidates are
-                               (split, threads) = (1,256) (2,256) (4,256) (4,64) (8,64) */
-    int32_t reserved[6];
+    int32_t update_split;   /* regions each block is cut into for the update stage (default 2) */
+    int32_t update_threads; /* threads per update workgroup (default 256) */
+    int32_t update_columns; /* 0: z-slabs; 1: columns cut across x and y.  The candidates are
+                               (split, columns, threads) = (1,0,256) (2,0,256) (4,0,256)
+                               (2,1,256) (4,1,256) (8,1,256) (1,0,1024) (2,0,1024) (4,0,1024)
+                               (2,0,512) */
+    int32_t reserved[5];
 } vbx_tuning;
 
 int vbx_map_get_tuning(vbx_map* map, vbx_tuning* out);

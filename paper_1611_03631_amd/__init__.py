@@ -71,7 +71,10 @@ EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_ma
             "vbx_server_wait", "vbx_server_drain", "vbx_server_stats", "vbx_server_reset_stats",
             "vbx_server_map", "vbx_server_destroy"]
 
-TUNING_CANDIDATES = 5
+TUNING_CANDIDATES = 10
+# (update_split, update_columns, update_threads) of each candidate, in vbx_map_autotune's order
+TUNING_LIST = [(1, 0, 256), (2, 0, 256), (4, 0, 256), (2, 1, 256), (4, 1, 256), (8, 1, 256),
+               (1, 0, 1024), (2, 0, 1024), (4, 0, 1024), (2, 0, 512)]
 
 
 class ServerParams(ctypes.Structure):
@@ -92,7 +95,7 @@ class ServerSummary(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("update_split", ctypes.c_int32), ("update_threads", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("update_columns", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 PROFILE_STAGES = 10
 
@@ -345,12 +348,14 @@ class Map:
     def tuning(self) -> dict:
         t = Tuning()
         _check(lib().vbx_map_get_tuning(self._h, ctypes.byref(t)), "vbx_map_get_tuning")
-        return {"update_split": int(t.update_split), "update_threads": int(t.update_threads)}
+        return {"update_split": int(t.update_split), "update_threads": int(t.update_threads),
+                "update_columns": int(t.update_columns)}
 
-    def set_tuning(self, update_split: int, update_threads: int = 256):
+    def set_tuning(self, update_split: int, update_threads: int = 256, update_columns: int = 0):
         t = Tuning()
         t.update_split = update_split
         t.update_threads = update_threads
+        t.update_columns = update_columns
         _check(lib().vbx_map_set_tuning(self._h, ctypes.byref(t)), "vbx_map_set_tuning")
 
     def autotune(self, frames) -> dict:
@@ -361,8 +366,8 @@ class Map:
         ms = (ctypes.c_double * TUNING_CANDIDATES)()
         _check(lib().vbx_map_autotune(self._h, arr, len(frames), ctypes.byref(best), ms),
                "vbx_map_autotune")
-        return {"best": {"update_split": int(best.update_split),
-                         "update_threads": int(best.update_threads)}, "ms": list(ms)}
+        return {"best": {"update_split": int(best.update_split), "update_threads": int(best.update_threads),
+                         "update_columns": int(best.update_columns)}, "ms": list(ms)}
 
     def stats(self) -> dict:
         s = Stats()

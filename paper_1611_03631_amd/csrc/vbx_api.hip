@@ -361,7 +361,7 @@ int group_merge_grid() {
 }
 
 // Persistent grid of an update-kernel variant: one workgroup per slot the chip can hold.
-template <int STORAGE, int SPLIT, int NT>
+template <int STORAGE, int RX, int RY, int RZ, int NT>
 int update_grid() {
     static int grid = 0;
     static std::once_flag once;
@@ -370,7 +370,7 @@ int update_grid() {
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per, reinterpret_cast<const void*>(&k_update<STORAGE, SPLIT, NT>), NT, 0) != hipSuccess ||
+                &per, reinterpret_cast<const void*>(&k_update<STORAGE, RX, RY, RZ, NT>), NT, 0) != hipSuccess ||
             per < 1)
             per = 1;
         grid = cus * per;
@@ -378,41 +378,66 @@ int update_grid() {
     return grid > 0 ? grid : 256;
 }
 
-template <int STORAGE, int SPLIT, int NT>
+template <int STORAGE, int RX, int RY, int RZ, int NT>
 void launch_update_t(hipStream_t st, const Job* jobs, const MapDesc* maps, const u64* t_key,
                      const int* t_slot, const u32* off, const float4* sorted, u32 JM, u64* touch_key,
                      u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
-    hipLaunchKernelGGL((k_update<STORAGE, SPLIT, NT>), dim3(update_grid<STORAGE, SPLIT, NT>()), dim3(NT), 0, st,
-                       jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep,
-                       jst, cs);
+    hipLaunchKernelGGL((k_update<STORAGE, RX, RY, RZ, NT>), dim3(update_grid<STORAGE, RX, RY, RZ, NT>()), dim3(NT),
+                       0, st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep, jst,
+                       cs);
 }
 
-// Update-kernel variants: z-slabs per block and threads per workgroup.
+// Update-kernel variants: how a block is cut into regions, and the workgroup size.  Larger
+// workgroups put more waves on the rays of one block (its frames fold in sequence, so a
+// heavily observed block is a long chain for one workgroup).
 struct UpdateVariant {
-    int split, threads;
+    int split;     // regions per block
+    int columns;   // 0: z-slabs; 1: columns cut across x and y
+    int threads;   // workgroup size
 };
-constexpr UpdateVariant kUpdateVariants[] = {{1, 256}, {2, 256}, {4, 256}, {4, 64}, {8, 64}};
+constexpr UpdateVariant kUpdateVariants[] = {{1, 0, 256}, {2, 0, 256}, {4, 0, 256}, {2, 1, 256}, {4, 1, 256},
+                                             {8, 1, 256}, {1, 0, 1024}, {2, 0, 1024}, {4, 0, 1024}, {2, 0, 512}};
 constexpr int kNumUpdateVariants = sizeof(kUpdateVariants) / sizeof(kUpdateVariants[0]);
+static_assert(kNumUpdateVariants == VBX_TUNING_CANDIDATES, "tuning candidates");
+
+template <int STORAGE>
+void launch_update_s(int variant, hipStream_t st, const Job* jobs, const MapDesc* maps, const u64* t_key,
+                     const int* t_slot, const u32* off, const float4* sorted, u32 JM, u64* touch_key,
+                     u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
+#define VBX_UPD(X, Y, Z, T) launch_update_t<STORAGE, X, Y, Z, T>(st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep, jst, cs)
+    switch (variant) {
+        case 0: VBX_UPD(16, 16, 16, 256); break;
+        case 2: VBX_UPD(16, 16, 4, 256); break;
+        case 3: VBX_UPD(8, 16, 16, 256); break;
+        case 4: VBX_UPD(8, 8, 16, 256); break;
+        case 5: VBX_UPD(4, 8, 16, 256); break;
+        case 6: VBX_UPD(16, 16, 16, 1024); break;
+        case 7: VBX_UPD(16, 16, 8, 1024); break;
+        case 8: VBX_UPD(16, 16, 4, 1024); break;
+        case 9: VBX_UPD(16, 16, 8, 512); break;
+        default: VBX_UPD(16, 16, 8, 256); break;
+    }
+#undef VBX_UPD
+}
+
+template <int STORAGE>
+void warm_update_grids() {
+    (void)update_grid<STORAGE, 16, 16, 16, 256>(); (void)update_grid<STORAGE, 16, 16, 8, 256>();
+    (void)update_grid<STORAGE, 16, 16, 4, 256>();  (void)update_grid<STORAGE, 8, 16, 16, 256>();
+    (void)update_grid<STORAGE, 8, 8, 16, 256>();   (void)update_grid<STORAGE, 4, 8, 16, 256>();
+    (void)update_grid<STORAGE, 16, 16, 16, 1024>(); (void)update_grid<STORAGE, 16, 16, 8, 1024>();
+    (void)update_grid<STORAGE, 16, 16, 4, 1024>();  (void)update_grid<STORAGE, 16, 16, 8, 512>();
+}
 
 void launch_update(int storage, int variant, hipStream_t st, const Job* jobs, const MapDesc* maps,
                    const u64* t_key, const int* t_slot, const u32* off, const float4* sorted, u32 JM,
                    u64* touch_key, u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
-#define VBX_UPD(S, P, T) launch_update_t<S, P, T>(st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep, jst, cs)
-#define VBX_UPD_ALL(S)                 \
-    switch (variant) {                 \
-        case 0: VBX_UPD(S, 1, 256); break; \
-        case 2: VBX_UPD(S, 4, 256); break; \
-        case 3: VBX_UPD(S, 4, 64); break;  \
-        case 4: VBX_UPD(S, 8, 64); break;  \
-        default: VBX_UPD(S, 2, 256); break; \
-    }
-    if (storage == VBX_F32) {
-        VBX_UPD_ALL(0)
-    } else {
-        VBX_UPD_ALL(1)
-    }
-#undef VBX_UPD_ALL
-#undef VBX_UPD
+    if (storage == VBX_F32)
+        launch_update_s<0>(variant, st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap,
+                           keep, jst, cs);
+    else
+        launch_update_s<1>(variant, st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap,
+                           keep, jst, cs);
 }
 
 // Records the start / end of a stage on the stream when profiling is on.
@@ -546,10 +571,8 @@ int stage_tables(Scratch* s, hipStream_t st, const Prepared& pr) {
 // Resolves the once-per-process launch shapes before any capture.
 void warm_launch_shapes() {
     (void)group_merge_grid();
-    (void)update_grid<0, 1, 256>(); (void)update_grid<0, 2, 256>(); (void)update_grid<0, 4, 256>();
-    (void)update_grid<0, 4, 64>();  (void)update_grid<0, 8, 64>();
-    (void)update_grid<1, 1, 256>(); (void)update_grid<1, 2, 256>(); (void)update_grid<1, 4, 256>();
-    (void)update_grid<1, 4, 64>();  (void)update_grid<1, 8, 64>();
+    warm_update_grids<0>();
+    warm_update_grids<1>();
 }
 
 // The kernel sequence of one call over the staged tables in `s`.  Only kernel launches are
@@ -1340,13 +1363,15 @@ int vbx_map_get_tuning(vbx_map* m, vbx_tuning* out) {
     std::memset(out, 0, sizeof *out);
     out->update_split = kUpdateVariants[m->update_variant].split;
     out->update_threads = kUpdateVariants[m->update_variant].threads;
+    out->update_columns = kUpdateVariants[m->update_variant].columns;
     return VBX_OK;
 }
 
 int vbx_map_set_tuning(vbx_map* m, const vbx_tuning* t) {
     if (!m || !t) return VBX_ERR_INVALID_ARG;
     for (int v = 0; v < kNumUpdateVariants; ++v) {
-        if (kUpdateVariants[v].split == t->update_split && kUpdateVariants[v].threads == t->update_threads) {
+        if (kUpdateVariants[v].split == t->update_split && kUpdateVariants[v].threads == t->update_threads &&
+            kUpdateVariants[v].columns == (t->update_columns != 0)) {
             m->update_variant = v;
             return VBX_OK;
         }

@@ -51,7 +51,7 @@ __global__ void k_scatter(const Job* jobs, const u32* cross, const unsigned char
                           u32 MB, const u32* tval, const u32* rays_job, u32* bins,
                           const u32* off, u32 JM, const float4* rays_p, float4* sorted,
                           CallState* cs, u32 ray_cap);
-template <int STORAGE, int SPLIT, int NT>
+template <int STORAGE, int RX, int RY, int RZ, int NT>
 __global__ void k_update(const Job* jobs, const MapDesc* maps, const u64* t_key,
                          const int* t_slot, const u32* off, const float4* sorted, u32 JM,
                          u64* touch_key, u32* touch_n, u32 touch_cap, int keep_touches,

@@ -256,7 +256,9 @@ __device__ inline Obs observe(const MapDesc& M, const float p[3], const float e[
     float dot = (f0 * e[0] + f1 * e[1]) + f2 * e[2];
     float d;
     if (M.dist == 0) {
-        float mag = __builtin_sqrtf((f0 * f0 + f1 * f1) + f2 * f2);
+        // hardware square root (1 ulp): the magnitude only sets D's value, its sign comes
+        // from the dot product
+        float mag = __builtin_amdgcn_sqrtf((f0 * f0 + f1 * f1) + f2 * f2);
         d = dot > 0.0f ? mag : (dot < 0.0f ? -mag : 0.0f);
     } else {
         d = dot / r;

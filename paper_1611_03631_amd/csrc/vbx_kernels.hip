@@ -71,19 +71,34 @@ __device__ inline u32 block_scan_256(u32 x, u32* lds8, u32* tot) {
     return v + add;
 }
 
-// Inclusive prefix sum over a workgroup of NT threads (NT a multiple of 64, at most 256).
+// Inclusive prefix sum over a workgroup of NT threads (NT a multiple of 64, at most 1024);
+// lds needs NT / 64 entries.  Returns the inclusive value, the total in *tot.
 template <int NT>
-__device__ inline u32 block_scan(u32 x, u32* lds8, u32* tot) {
-    if (NT == 256) return block_scan_256(x, lds8, tot);
-    const int lane = lane_id();
+__device__ inline u32 block_scan(u32 x, u32* lds, u32* tot) {
+    constexpr int NW = NT / 64;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
     u32 v = x;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         u32 y = __shfl_up(v, o);
         if (lane >= o) v += y;
     }
-    *tot = __shfl(v, 63);
-    return v;
+    if (NW == 1) {
+        *tot = __shfl(v, 63);
+        return v;
+    }
+    if (lane == 63) lds[wave] = v;
+    __syncthreads();
+    u32 add = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        u32 s = lds[w];
+        if (w < wave) add += s;
+        total += s;
+    }
+    __syncthreads();
+    *tot = total;
+    return v + add;
 }
 
 __global__ void k_fill_u64(u64* p, u64 val, size_t n) {
@@ -127,8 +142,8 @@ __global__ __launch_bounds__(256) void k_points_simple(const Job* __restrict__ j
                                                        CallState* __restrict__ cs) {
     __shared__ u32 s_cnt[3];   // valid, invalid, out of bounds
     const int jid = job_of_tile(jobs, njobs, blockIdx.x);
-    const Job& J = jobs[jid];
-    const MapDesc& M = maps[J.map];
+    const Job J = jobs[jid];          // by value: kept in registers across the LDS atomics
+    const MapDesc M = maps[J.map];
     if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) cs->ray_count = gridDim.x * (u32)kTileSimple;
     __syncthreads();
@@ -237,8 +252,8 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     __shared__ u32 s_cnt[3];
     __shared__ u32 lds8[4];
     const int jid = job_of_tile(jobs, njobs, blockIdx.x);
-    const Job& J = jobs[jid];
-    const MapDesc& M = maps[J.map];
+    const Job J = jobs[jid];          // by value: kept in registers across the LDS atomics
+    const MapDesc M = maps[J.map];
     for (int i = threadIdx.x; i < kGroupSlots; i += 256) {
         s_key[i] = kEmpty; s_so[i] = 0; s_sq[0][i] = 0; s_sq[1][i] = 0; s_sq[2][i] = 0; s_n[i] = 0;
         s_bkey[i] = kEmpty;
@@ -1053,10 +1068,12 @@ __device__ inline void store_voxel(void* pool, size_t idx, float D, float W) {
 
 constexpr int kOffWindow = 256;   // frames whose bin offsets are staged in LDS at a time
 
-// Work item u = t * SPLIT + q: slab q (local z in [q*16/SPLIT, (q+1)*16/SPLIT)) of touched block t.
-// Slabs of one block are independent (different voxels) and replay the same rays, so a
-// block's frames run in parallel across SPLIT workgroups with 1/SPLIT of the LDS each.
-template <int STORAGE, int SPLIT, int NT>
+// Work item u = t * NREG + q: region q of touched block t, a box of RX x RY x RZ voxels
+// (regions tile the block, x fastest).  Regions of one block are independent (different
+// voxels) and replay the same rays, each ray walked in full but observed only inside the
+// region, so a block's frames run in parallel across NREG workgroups with 1/NREG of the LDS
+// each.  z-slabs divide the rays of walls, x/y columns those of floors and walls alike.
+template <int STORAGE, int RX, int RY, int RZ, int NT>
 __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                                 const MapDesc* __restrict__ maps,
                                                 const u64* __restrict__ t_key,
@@ -1068,9 +1085,11 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                                 int keep_touches,
                                                 JobStat* __restrict__ jst,
                                                 CallState* __restrict__ cs) {
-    constexpr int VOX = 4096 / SPLIT;      // voxels of one slab
+    constexpr int VOX = RX * RY * RZ;      // voxels of one region
     constexpr int VPT = VOX / NT;          // voxels per thread
-    constexpr int ZS = 16 / SPLIT;         // slab thickness
+    constexpr int NRX = 16 / RX, NRY = 16 / RY, NRZ = 16 / RZ;
+    constexpr int NREG = NRX * NRY * NRZ;  // regions per block
+    static_assert(VPT * NT == VOX && VPT >= 1, "region size must be a multiple of the workgroup");
     __shared__ u64 a_w[VOX];    // sum of fixed-point weights
     __shared__ u64 a_d[VOX];    // sum of fixed-point weight * distance/delta (two's complement)
     __shared__ u32 a_n[VOX];    // rays
@@ -1078,19 +1097,21 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
     __shared__ u32 s_t;
     __shared__ u32 s_stat[3];
     __shared__ u32 s_tbase;
-    __shared__ u32 lds8[4];
+    __shared__ u32 lds8[NT / 64];
     for (int i = threadIdx.x; i < VOX; i += NT) { a_w[i] = 0; a_d[i] = 0; a_n[i] = 0; }
-    const u32 nt = cs->error ? 0u : cs->t_count * (u32)SPLIT;
+    const u32 nt = cs->error ? 0u : cs->t_count * (u32)NREG;
     for (;;) {
         if (threadIdx.x == 0) { s_t = atomicAdd(&cs->work_next, 1u); s_stat[0] = 0; s_stat[1] = 0; s_stat[2] = 0; }
         __syncthreads();
         const u32 u = s_t;
         if (u >= nt) break;
-        const u32 t = u / (u32)SPLIT;
-        const int q = (int)(u % (u32)SPLIT);
-        const int lbase = q * VOX;
+        const u32 t = u / (u32)NREG;
+        const int q = (int)(u % (u32)NREG);
+        const int qx = q % NRX, qy = (q / NRX) % NRY, qz = q / (NRX * NRY);
         const u64 tk = t_key[t];
-        const MapDesc& M = maps[(u32)(tk >> 45)];
+        // by value: the walk loop then reads the map constants from registers instead of
+        // reloading them after every LDS atomic
+        const MapDesc M = maps[(u32)(tk >> 45)];
         if (M.st->error != 0) { __syncthreads(); continue; }
         int bx, by, bz;
         unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
@@ -1098,16 +1119,18 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
         const bool is_new = (ts & 0x40000000) != 0;
         const size_t slot = (size_t)(ts & 0x3FFFFFFF);
         void* pool = M.pool;
-        const size_t vbase = slot * 4096 + (size_t)lbase;
+        // voxel i of the region (i = threadIdx.x + NT * j) is block voxel pool_index(i)
+        const size_t vbase = slot * 4096 + (size_t)(qx * RX + 16 * (qy * RY) + 256 * (qz * RZ));
+        auto block_local = [](int i) { return (i % RX) + 16 * ((i / RX) % RY) + 256 * (i / (RX * RY)); };
         float D[VPT], W[VPT];
         u32 ntot[VPT];
 #pragma unroll
         for (int j = 0; j < VPT; ++j) {
             ntot[j] = 0;
             if (is_new) { D[j] = 0.0f; W[j] = 0.0f; }
-            else load_voxel<STORAGE>(pool, vbase + threadIdx.x + NT * j, D[j], W[j]);
+            else load_voxel<STORAGE>(pool, vbase + block_local(threadIdx.x + NT * j), D[j], W[j]);
         }
-        const int ox = 16 * bx, oy = 16 * by, oz = 16 * bz + q * ZS;
+        const int ox = 16 * bx + qx * RX, oy = 16 * by + qy * RY, oz = 16 * bz + qz * RZ;
         u32 stat_vox = 0, stat_touch = 0;
         for (int w0 = 0; w0 < M.njobs; w0 += kOffWindow) {
             const int wn = M.njobs - w0 < kOffWindow ? M.njobs - w0 : kOffWindow;
@@ -1133,33 +1156,45 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                 }
                 const Job& J = jobs[M.job0 + w0 + jm];
                 const float s[3] = {J.pose[3], J.pose[7], J.pose[11]};
+                float4 rp = cur;
                 for (u32 e = lo + threadIdx.x; e < hi; e += NT) {
-                    const float4 rp = e == lo + threadIdx.x ? cur : sorted[e];
+                    // the next ray's load is in flight while this one is walked
+                    float4 rn = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (e + NT < hi) rn = sorted[e + NT];
                     const float p[3] = {rp.x, rp.y, rp.z};
+                    const float wgt = rp.w;
+                    rp = rn;
                     float ev[3], r;
                     Walk w;
                     walk_setup(M, p, s, ev, r, w);
-                    if (SPLIT > 1) {
-                        // the walk's z indices lie between its end voxels: skip bands that miss the slab
-                        const int z_end = w.g[2] + w.step[2] * w.n[2];
-                        const int zlo = w.g[2] < z_end ? w.g[2] : z_end;
-                        const int zhi = w.g[2] < z_end ? z_end : w.g[2];
-                        if (zhi < oz || zlo >= oz + ZS) continue;
+                    if (NREG > 1) {
+                        // every walk index lies between its end voxels: skip bands that miss the region
+                        const int o3[3] = {ox, oy, oz};
+                        const int r3[3] = {RX, RY, RZ};
+                        bool miss = false;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const int g_end = w.g[a] + w.step[a] * w.n[a];
+                            const int glo = w.g[a] < g_end ? w.g[a] : g_end;
+                            const int ghi = w.g[a] < g_end ? g_end : w.g[a];
+                            miss = miss || ghi < o3[a] || glo >= o3[a] + r3[a];
+                        }
+                        if (miss) continue;
                     }
                     bool inside = false;
                     for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
                         const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
-                        if ((u32)lx < 16u && (u32)ly < 16u && (u32)lz < (u32)ZS) {
+                        if ((u32)lx < (u32)RX && (u32)ly < (u32)RY && (u32)lz < (u32)RZ) {
                             inside = true;
-                            const Obs o = observe(M, p, ev, r, rp.w, w.g[0], w.g[1], w.g[2]);
-                            const u32 l = (u32)lx | ((u32)ly << 4) | ((u32)lz << 8);
+                            const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
+                            const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
                             const u64 fw = (u64)__builtin_rintf(o.w * M.wscale);
                             const i64 fd = (i64)__builtin_rintf(o.w * o.e * M.wscale);
                             if (fw) atomicAdd(&a_w[l], fw);
                             if (fd) atomicAdd(&a_d[l], (u64)fd);
                             atomicAdd(&a_n[l], 1u);
                         } else if (inside) {
-                            break;   // the walk is monotone per axis: it never re-enters the slab
+                            break;   // the walk is monotone per axis: it never re-enters the region
                         }
                         if (w.left == 0) break;
                         walk_step(w);
@@ -1201,7 +1236,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
             __syncthreads();
         }
 #pragma unroll
-        for (int j = 0; j < VPT; ++j) store_voxel<STORAGE>(pool, vbase + threadIdx.x + NT * j, D[j], W[j]);
+        for (int j = 0; j < VPT; ++j) store_voxel<STORAGE>(pool, vbase + block_local(threadIdx.x + NT * j), D[j], W[j]);
         if (stat_vox) {
             u32 cells = 0;
 #pragma unroll
@@ -1225,7 +1260,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                     const int l = threadIdx.x + NT * j;
                     if (pos < touch_cap) {
                         touch_key[pos] = ((u64)(M.map_id) << 57) |
-                                         voxel_key_of(ox + (l & 15), oy + ((l >> 4) & 15), oz + (l >> 8));
+                                         voxel_key_of(ox + l % RX, oy + (l / RX) % RY, oz + l / (RX * RY));
                         touch_n[pos] = ntot[j];
                     }
                     pos++;
@@ -1242,36 +1277,66 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
     }
 }
 
-template __global__ void k_update<0, 1, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                              JobStat*, CallState*);
-template __global__ void k_update<0, 2, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                              JobStat*, CallState*);
-template __global__ void k_update<0, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                              JobStat*, CallState*);
-template __global__ void k_update<0, 4, 64>(const Job*, const MapDesc*, const u64*, const int*,
-                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                              JobStat*, CallState*);
-template __global__ void k_update<0, 8, 64>(const Job*, const MapDesc*, const u64*, const int*,
-                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                              JobStat*, CallState*);
-template __global__ void k_update<1, 1, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                              JobStat*, CallState*);
-template __global__ void k_update<1, 2, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                              JobStat*, CallState*);
-template __global__ void k_update<1, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                              JobStat*, CallState*);
-template __global__ void k_update<1, 4, 64>(const Job*, const MapDesc*, const u64*, const int*,
-                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                              JobStat*, CallState*);
-template __global__ void k_update<1, 8, 64>(const Job*, const MapDesc*, const u64*, const int*,
-                                              const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                              JobStat*, CallState*);
+template __global__ void k_update<0, 16, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<0, 16, 16, 8, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<0, 16, 16, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<0, 8, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<0, 8, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<0, 4, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<0, 16, 16, 16, 1024>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<0, 16, 16, 8, 1024>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<0, 16, 16, 4, 1024>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<0, 16, 16, 8, 512>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<1, 16, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<1, 16, 16, 8, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<1, 16, 16, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<1, 8, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<1, 8, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<1, 4, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<1, 16, 16, 16, 1024>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<1, 16, 16, 8, 1024>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<1, 16, 16, 4, 1024>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
+template __global__ void k_update<1, 16, 16, 8, 512>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
+                                                        JobStat*, CallState*);
 
 // ---------------------------------------------------------------------------
 // finish: commit block counts, fold statistics, clean per-call tables

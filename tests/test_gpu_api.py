@@ -182,9 +182,9 @@ def test_tuning_never_changes_results_and_autotune_leaves_map(vbx):
     frames = room(320, 240, 3, 71)
     params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped")
     outs = []
-    for split, threads in ((1, 256), (2, 256), (4, 256), (4, 64), (8, 64)):
+    for split, columns, threads in vbx.TUNING_LIST:
         g = gpu_map(vbx, params)
-        g.set_tuning(split, threads)
+        g.set_tuning(split, threads, columns)
         g.integrate_frames([(dev(p), pose, 320) for p, pose in frames])
         assert g.sync() == 0
         outs.append(g.export())
@@ -194,7 +194,9 @@ def test_tuning_never_changes_results_and_autotune_leaves_map(vbx):
     g.integrate(dev(frames[0][0]), frames[0][1])
     before = g.export()
     res = g.autotune([(dev(p), pose, 320) for p, pose in frames])
-    assert res["best"]["update_split"] in (1, 2, 4, 8) and all(x > 0 for x in res["ms"])
+    best = res["best"]
+    assert (best["update_split"], best["update_columns"], best["update_threads"]) in vbx.TUNING_LIST
+    assert len(res["ms"]) == len(vbx.TUNING_LIST) and all(x > 0 for x in res["ms"])
     after = g.export()
     assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
     assert g.tuning() == res["best"]
