@@ -514,8 +514,17 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
             for (u32 k = threadIdx.x; k <= wn; k += 256) s_off[k] = off[b + k];
             __syncthreads();
             const u32 base = s_off[0];
+            // bins [b, b + nbat) hold at most kMergeBatch partials: nbat is the largest n <= wn
+            // with s_off[n] - base <= kMergeBatch (offsets are non-decreasing)
             u32 nbat = 0;
-            while (nbat < wn && s_off[nbat + 1] - base <= (u32)kMergeBatch) ++nbat;
+            {
+                u32 lo_n = 0, hi_n = wn;
+                while (lo_n < hi_n) {
+                    const u32 mid = (lo_n + hi_n + 1) >> 1;
+                    if (s_off[mid] - base <= (u32)kMergeBatch) lo_n = mid; else hi_n = mid - 1;
+                }
+                nbat = lo_n;
+            }
             if (nbat == 0) {
                 // ---- a bin too large for one hash pass: dense passes over its voxels
                 const u32 lo = s_off[0], hi = s_off[1];
@@ -639,11 +648,11 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 m_hi[0][h] = 0; m_hi[1][h] = 0; m_hi[2][h] = 0; m_n[h] = 0;
             }
             __syncthreads();
-            // empty slots of each bin, and per-frame ray counts
-            for (u32 k = 0; k < nbat; ++k) {
+            // empty slots of each bin, and per-frame ray counts (one thread per bin)
+            for (u32 k = threadIdx.x; k < nbat; k += 256) {
                 const u32 nr = s_nr[k];
-                for (u32 e = s_off[k] + nr + threadIdx.x; e < s_off[k + 1]; e += 256) rays_job[e] = kNoRay;
-                if (threadIdx.x == 0 && nr) {
+                for (u32 e = s_off[k] + nr; e < s_off[k + 1]; ++e) rays_job[e] = kNoRay;
+                if (nr) {
                     const u32 bb = b + k;
                     const u32 t = bb / JM;
                     const MapDesc& M = maps[(u32)(tkeys[tlist[t]] >> 45)];
