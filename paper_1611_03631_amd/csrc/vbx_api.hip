@@ -322,7 +322,7 @@ int ensure_scratch(Scratch* s, hipStream_t st, const CallPlan& plan, int njobs, 
         GROW(s->parts, ray_cap * sizeof(Partial));
         GROW(s->parts_sorted, ray_cap * sizeof(Partial));
         GROW(s->tile_parts, std::max<size_t>(plan.tiles, 1) * sizeof(u32));
-        GROW(s->chunk_first, (ray_cap / 512 + 2) * sizeof(u32));
+        GROW(s->chunk_first, (ray_cap / kMergeSpan + 2) * sizeof(u32));
     }
     if (plan.keep_touches) {
         GROW(s->touch_key, touch_cap * sizeof(u64));

@@ -436,9 +436,11 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
 // a bin larger than that is merged alone over a dense voxel table, kMergeVox voxels per pass.
 // The rays of bin b take slots [off[b], off[b] + groups) and the rest of its range is marked
 // empty, so no counter is shared between workgroups.
-constexpr int kMergeVox = 1024;     // LDS table entries (hash slots or dense voxels)
-constexpr int kMergeSpan = 512;     // partials per work chunk
-constexpr int kMergeBatch = 640;    // partials merged in one hash pass (load <= 0.625)
+constexpr int kMergeVox = 2 * kMergeSpan;        // LDS table entries (hash slots or dense voxels)
+constexpr int kMergeBatch = kMergeSpan * 5 / 4;  // partials merged in one hash pass (load <= 0.625)
+constexpr int kMergePasses = 4096 / kMergeVox;   // dense passes over a block
+constexpr int kMergePerThread = kMergeVox / 256;
+static_assert(kMergePasses * kMergeVox == 4096 && kMergePerThread * 256 == kMergeVox, "merge table");
 
 // chunk_first[c] = first bin whose first partial lies at or after c * kMergeSpan.
 __global__ __launch_bounds__(256) void k_chunk_first(const u32* __restrict__ off, u32 JM,
@@ -538,17 +540,17 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 if (threadIdx.x == 0) s_quarters = 0;
                 __syncthreads();
                 u32 qm = 0;
-                for (u32 e = lo + threadIdx.x; e < hi; e += 256) qm |= 1u << ((sorted[e].lj & 4095u) >> 10);
+                for (u32 e = lo + threadIdx.x; e < hi; e += 256) qm |= 1u << ((sorted[e].lj & 4095u) / kMergeVox);
                 if (qm) atomicOr(&s_quarters, qm);
                 __syncthreads();
                 const u32 quarters = s_quarters;
                 u32 nrays = 0;
-                for (int qd = 0; qd < 4; ++qd) {
+                for (int qd = 0; qd < kMergePasses; ++qd) {
                     if (!(quarters & (1u << qd))) continue;
                     for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
                         const Partial& P = sorted[e];
                         const u32 l = P.lj & 4095u;
-                        if ((int)(l >> 10) != qd) continue;
+                        if ((int)(l / kMergeVox) != qd) continue;
                         const u32 v = l & (kMergeVox - 1);
                         atomicAdd(&m_so[v], P.so);
 #pragma unroll
@@ -560,11 +562,11 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                         if (P.n == 1) m_idx[v] = P.idx;
                     }
                     __syncthreads();
-                    float4 ray[4];
-                    bool has[4];
+                    float4 ray[kMergePerThread];
+                    bool has[kMergePerThread];
                     u32 nmine = 0;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
+                    for (int r = 0; r < kMergePerThread; ++r) {
                         const int v = threadIdx.x + 256 * r;
                         const u32 n = m_n[v];
                         has[r] = n != 0;
@@ -581,7 +583,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                     const u32 incl = block_scan_256(nmine, lds8, &tot);
                     u32 pos = lo + nrays + incl - nmine;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
+                    for (int r = 0; r < kMergePerThread; ++r) {
                         if (!has[r]) continue;
                         rays_p[pos] = ray[r];
                         rays_job[pos] = (u32)jid;
