@@ -270,6 +270,7 @@ struct CallPlan {
     bool grouped = false;
     int storage = 0;
     bool keep_touches = false;
+    u32 tiles_per_job = 0;      // every job has this many tiles and there is one map (else 0)
 };
 
 // Grows a scratch set for a call on stream `st`; tables that must start cleared are cleared here.
@@ -538,6 +539,12 @@ int prepare_call(const std::vector<vbx_map*>& maps, const std::vector<vbx_frame>
     }
     plan.tiles = total_tiles;
     plan.ray_slots = (size_t)total_tiles * (plan.grouped ? kTileGrouped : kTileSimple);
+    plan.tiles_per_job = 0;
+    if (M == 1 && !jobs.empty() && jobs[0].ntiles > 0) {
+        bool uniform = true;
+        for (const Job& j : jobs) uniform = uniform && j.ntiles == jobs[0].ntiles;
+        if (uniform) plan.tiles_per_job = jobs[0].ntiles;
+    }
     return VBX_OK;
 }
 
@@ -612,7 +619,7 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
         } else {
             hipLaunchKernelGGL(k_points_grouped, dim3(total_tiles), dim3(256), 0, st, d_jobs, J, d_maps,
                                (u64*)s->tkeys.p, (u32)(s->tkey_cap - 1), (u32*)s->tlist.p, (u32)s->tlist_cap,
-                               (Partial*)s->parts.p, (u32*)s->tile_parts.p, jst, cs);
+                               (Partial*)s->parts.p, (u32*)s->tile_parts.p, plan.tiles_per_job, jst, cs);
         }
     }
     if (plan.grouped && total_tiles > 0) {

@@ -19,9 +19,9 @@ __global__ void k_set_u32(u32* p, u32 v);
 __global__ void k_map_status(const MapDesc* maps, int nmaps, int* out);
 __global__ void k_points_simple(const Job* jobs, int njobs, const MapDesc* maps, float4* rays_p,
                                 u32* rays_job, JobStat* jst, CallState* cs);
-__global__ void k_points_grouped(const Job* jobs, int njobs, const MapDesc* maps, u64* tkeys,
-                                 u32 tmask, u32* tlist, u32 tlist_cap, Partial* parts,
-                                 u32* tile_parts, JobStat* jst, CallState* cs);
+__global__ void k_points_grouped(const Job* jobs, int njobs, const MapDesc* maps, u64* tkeys, u32 tmask,
+                                 u32* tlist, u32 tlist_cap, Partial* parts, u32* tile_parts, u32 tiles_per_job,
+                                 JobStat* jst, CallState* cs);
 __global__ void k_densify(const u32* tlist, u32 tlist_cap, u32* tval, const CallState* cs);
 __global__ void k_gbin_count(const Partial* parts, const u32* tile_parts, u32 ntiles,
                              const u32* tval, u32* bins, u32 JM, const CallState* cs);

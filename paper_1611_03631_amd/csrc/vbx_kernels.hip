@@ -129,6 +129,21 @@ __device__ inline int job_of_tile(const Job* jobs, int njobs, u32 tile) {
     return cnt - 1;
 }
 
+// Value of the lane N below (row_shr) or above (row_shl) within the lane's row of 16 lanes
+// (DPP, a VALU operand modifier; 0 where that lane lies outside the row).
+template <int N>
+__device__ inline u32 row_shr(u32 v) {
+    return (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + N, 0xF, 0xF, true);
+}
+template <int N>
+__device__ inline u64 row_shr64(u64 v) {
+    return (u64)row_shr<N>((u32)v) | ((u64)row_shr<N>((u32)(v >> 32)) << 32);
+}
+template <int N>
+__device__ inline u32 row_shl(u32 v) {
+    return (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + N, 0xF, 0xF, true);
+}
+
 // ---------------------------------------------------------------------------
 // points: per-point raycasting
 // ---------------------------------------------------------------------------
@@ -239,7 +254,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                                                         u64* __restrict__ tkeys, u32 tmask,
                                                         u32* __restrict__ tlist, u32 tlist_cap,
                                                         Partial* __restrict__ parts,
-                                                        u32* __restrict__ tile_parts,
+                                                        u32* __restrict__ tile_parts, u32 tiles_per_job,
                                                         JobStat* __restrict__ jst,
                                                         CallState* __restrict__ cs) {
     __shared__ u64 s_key[kGroupSlots];
@@ -251,9 +266,11 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     __shared__ u32 s_bh[kGroupSlots];     // their block-set slots
     __shared__ u32 s_cnt[3];
     __shared__ u32 lds8[4];
-    const int jid = job_of_tile(jobs, njobs, blockIdx.x);
+    // when every frame has the same number of tiles (and there is one map), the job and map
+    // follow without a dependent load
+    const int jid = tiles_per_job ? (int)(blockIdx.x / tiles_per_job) : job_of_tile(jobs, njobs, blockIdx.x);
     const Job J = jobs[jid];          // by value: kept in registers across the LDS atomics
-    const MapDesc M = maps[J.map];
+    const MapDesc M = maps[tiles_per_job ? 0u : J.map];
     for (int i = threadIdx.x; i < kGroupSlots; i += 256) {
         s_key[i] = kEmpty; s_so[i] = 0; s_sq[0][i] = 0; s_sq[1][i] = 0; s_sq[2][i] = 0; s_n[i] = 0;
         s_bkey[i] = kEmpty;
@@ -262,6 +279,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     __syncthreads();
 
     const u32 tile = blockIdx.x - J.tile0;
+    const int lane = lane_id(), r16 = lane & 15;
     u32 n_valid = 0, n_inv = 0, n_oob = 0;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -278,29 +296,67 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
             i = tile * kTileGrouped + threadIdx.x + 256u * j;
             in = i < J.n;
         }
-        if (!in) continue;
-        const float x = J.pts[3 * (size_t)i], y = J.pts[3 * (size_t)i + 1], z = J.pts[3 * (size_t)i + 2];
-        float q[3];
-        int c = classify_point(M, J.pose, x, y, z, q);
-        if (c != 1) { if (c == 0) n_inv++; else n_oob++; continue; }
-        n_valid++;
-        int g[3];
-        u32 Q[3];
-        u64 om;
-        group_terms(M, q, z, g, Q, om);
-        const u64 key = voxel_key_of(g[0], g[1], g[2]);
-        u32 h = (u32)mix64(key) & (kGroupSlots - 1);
-        for (;;) {
-            u64 old = atomicCAS(&s_key[h], kEmpty, key);
-            if (old == kEmpty || old == key) break;
-            h = (h + 1) & (kGroupSlots - 1);
+        // this lane's contribution; a lane without a valid point gets a key no point has
+        u64 key = kEmpty - 1 - (u64)lane;
+        u64 so = 0, sq0 = 0, sq1 = 0, sq2 = 0;
+        u32 cnt = 0;
+        if (in) {
+            const float x = J.pts[3 * (size_t)i], y = J.pts[3 * (size_t)i + 1], z = J.pts[3 * (size_t)i + 2];
+            float q[3];
+            const int c = classify_point(M, J.pose, x, y, z, q);
+            if (c == 1) {
+                n_valid++;
+                int g[3];
+                u32 Q[3];
+                u64 om;
+                group_terms(M, q, z, g, Q, om);
+                key = voxel_key_of(g[0], g[1], g[2]);
+                so = om;
+                sq0 = om * Q[0];
+                sq1 = om * Q[1];
+                sq2 = om * Q[2];
+                cnt = 1;
+            } else if (c == 0) {
+                n_inv++;
+            } else {
+                n_oob++;
+            }
         }
-        atomicAdd(&s_so[h], om);
-        atomicAdd(&s_sq[0][h], om * Q[0]);
-        atomicAdd(&s_sq[1][h], om * Q[1]);
-        atomicAdd(&s_sq[2][h], om * Q[2]);
-        atomicAdd(&s_n[h], 1u);
-        s_idx[h] = i;
+        // Neighbouring pixels mostly share a voxel: runs of equal keys within each row of 16
+        // lanes are summed first (segmented scan over DPP row shifts; integer sums, exact), so
+        // only the last lane of a run enters the tile's LDS hash.
+        // cross-lane reads run with every lane active (never inside a short-circuit condition)
+        const u64 prev_key = row_shr64<1>(key);
+        const bool head0 = r16 == 0 || prev_key != key;
+        bool head = head0;
+#define VBX_SEG_STEP(N)                                                                        \
+        {                                                                                      \
+            const u64 a_so = row_shr64<N>(so), a0 = row_shr64<N>(sq0), a1 = row_shr64<N>(sq1),  \
+                      a2 = row_shr64<N>(sq2);                                                  \
+            const u32 a_n = row_shr<N>(cnt), a_h = row_shr<N>((u32)head);                      \
+            if (r16 >= N && !head) {                                                           \
+                so += a_so; sq0 += a0; sq1 += a1; sq2 += a2; cnt += a_n;                       \
+            }                                                                                  \
+            if (r16 >= N) head = head || a_h != 0;                                             \
+        }
+        VBX_SEG_STEP(1) VBX_SEG_STEP(2) VBX_SEG_STEP(4) VBX_SEG_STEP(8)
+#undef VBX_SEG_STEP
+        const u32 next_head = row_shl<1>((u32)head0);
+        const bool tail = r16 == 15 || next_head != 0;
+        if (tail && cnt > 0) {
+            u32 h = (u32)mix64(key) & (kGroupSlots - 1);
+            for (;;) {
+                u64 old = atomicCAS(&s_key[h], kEmpty, key);
+                if (old == kEmpty || old == key) break;
+                h = (h + 1) & (kGroupSlots - 1);
+            }
+            atomicAdd(&s_so[h], so);
+            atomicAdd(&s_sq[0][h], sq0);
+            atomicAdd(&s_sq[1][h], sq1);
+            atomicAdd(&s_sq[2][h], sq2);
+            atomicAdd(&s_n[h], cnt);
+            s_idx[h] = i;     // read only when the group has a single point: then it is this one
+        }
     }
     if (n_valid) atomicAdd(&s_cnt[0], n_valid);
     if (n_inv) atomicAdd(&s_cnt[1], n_inv);
