@@ -6,6 +6,8 @@
 // ray visits are reproducible bit-for-bit.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <cstring>
 #include <stdint.h>
 
 #pragma clang fp contract(off)
@@ -79,12 +81,31 @@ struct CallState {
 // Partial group of one tile (48 bytes): exact integer sums of the tile's points in one voxel.
 struct Partial {
     u64 so;        // sum of fixed-point point weights
-    u64 sq[3];     // sum of weight * Q_k (fits 64 bits for a tile of <= 512 points)
+    u64 sq[3];     // n > 1: sums of weight * Q_k (fit 64 bits for a tile of <= 512 points);
+                   // n == 1: the point itself and its Q_k, packed by pack_single
     u32 h;         // block-set slot of the voxel's block
     u32 lj;        // local voxel index (12 bits) | frame-in-map index << 12
     u32 n;         // points
-    u32 idx;       // index of the point (meaningful when n == 1)
+    u32 pad;
 };
+
+// A one-point partial group carries the point (binary32 world coordinates) and its grid
+// fractions Q_k instead of the sums, which follow from them (sum = weight * Q_k).  A group
+// that stays a single point casts its ray to exactly that point.
+__host__ __device__ inline void pack_single(const float p[3], const u32 Q[3], u64 sq[3]) {
+    u32 b[3];
+    for (int k = 0; k < 3; ++k) std::memcpy(&b[k], &p[k], 4);
+    sq[0] = (u64)b[0] | ((u64)b[1] << 32);
+    sq[1] = (u64)b[2] | ((u64)Q[0] << 32);
+    sq[2] = (u64)Q[1] | ((u64)Q[2] << 32);
+}
+__host__ __device__ inline void unpack_single(const u64 sq[3], float p[3], u32 Q[3]) {
+    const u32 b[3] = {(u32)sq[0], (u32)(sq[0] >> 32), (u32)sq[1]};
+    for (int k = 0; k < 3; ++k) std::memcpy(&p[k], &b[k], 4);
+    Q[0] = (u32)(sq[1] >> 32);
+    Q[1] = (u32)sq[2];
+    Q[2] = (u32)(sq[2] >> 32);
+}
 
 __host__ __device__ inline u64 mix64(u64 x) {
     x ^= x >> 33; x *= 0xff51afd7ed558ccdULL;

@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     __shared__ u64 s_so[kGroupSlots];
     __shared__ u64 s_sq[3][kGroupSlots];
     __shared__ u32 s_n[kGroupSlots];
-    __shared__ u32 s_idx[kGroupSlots];
+    __shared__ u32 s_idx[kGroupSlots];      // the point of a one-point group
     __shared__ u64 s_bkey[kGroupSlots];   // distinct (map, block) keys of the tile
     __shared__ u32 s_bh[kGroupSlots];     // their block-set slots
     __shared__ u32 s_cnt[3];
@@ -363,6 +363,20 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     if (n_oob) atomicAdd(&s_cnt[2], n_oob);
     __syncthreads();
 
+    // one-point groups carry their point: load it now so that the load overlaps the block
+    // phase (slot k = threadIdx.x + 256 r is this thread's in the output loop too)
+    float sx[2] = {0.f, 0.f}, sy[2] = {0.f, 0.f}, sz[2] = {0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int k = threadIdx.x + 256 * r;
+        if (s_key[k] != kEmpty && s_n[k] == 1) {
+            const size_t i1 = s_idx[k];
+            sx[r] = J.pts[3 * i1];
+            sy[r] = J.pts[3 * i1 + 1];
+            sz[r] = J.pts[3 * i1 + 2];
+        }
+    }
+
     // blocks of the tile's partial groups; reserve the output range
     const u64 mapbits = (u64)M.map_id << 45;
     u32 mine = 0;
@@ -390,7 +404,10 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     __syncthreads();
     size_t pos = (size_t)blockIdx.x * kTileGrouped + incl - mine;
     const u32 jm12 = J.jm << 12;
-    for (int k = threadIdx.x; k < kGroupSlots; k += 256) {
+    static_assert(kGroupSlots == 512, "two output slots per thread");
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int k = threadIdx.x + 256 * r;
         const u64 key = s_key[k];
         if (key == kEmpty) continue;
         const u64 bk = mapbits | (key >> 12);
@@ -399,11 +416,22 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         {
             Partial P;
             P.so = s_so[k];
-            P.sq[0] = s_sq[0][k]; P.sq[1] = s_sq[1][k]; P.sq[2] = s_sq[2][k];
+            P.n = s_n[k];
+            if (P.n == 1) {
+                // the same transform and Q_k as when the point was grouped
+                float p1[3];
+                (void)classify_point(M, J.pose, sx[r], sy[r], sz[r], p1);
+                int g1[3];
+                u32 Q1[3];
+                u64 om1;
+                group_terms(M, p1, 1.0f, g1, Q1, om1);
+                pack_single(p1, Q1, P.sq);
+            } else {
+                P.sq[0] = s_sq[0][k]; P.sq[1] = s_sq[1][k]; P.sq[2] = s_sq[2][k];
+            }
             P.h = s_bh[b];
             P.lj = jm12 | (u32)(key & 4095u);
-            P.n = s_n[k];
-            P.idx = s_idx[k];
+            P.pad = 0;
             parts[pos] = P;
         }
         pos++;
@@ -512,13 +540,14 @@ __global__ __launch_bounds__(256) void k_chunk_first(const u32* __restrict__ off
     }
 }
 
-__device__ inline void group_ray(const MapDesc& M, const Job& J, int bx, int by, int bz, u32 l,
-                                 u32 n, u64 so, const u64* sq, const u32* hi, u32 idx, float4& ray) {
+// Ray of a merged group: towards its single point, else towards the exact weighted mean,
+// carrying the group's summed weight.
+__device__ inline void group_ray(const MapDesc& M, int bx, int by, int bz, u32 l, u32 n, u64 so,
+                                 const u64* sq, const u32* hi, const float* p1, float4& ray) {
     const int g[3] = {16 * bx + (int)(l & 15), 16 * by + (int)((l >> 4) & 15), 16 * bz + (int)(l >> 8)};
     float p[3];
     if (n == 1) {
-        classify_point(M, J.pose, J.pts[3 * (size_t)idx], J.pts[3 * (size_t)idx + 1],
-                       J.pts[3 * (size_t)idx + 2], p);
+        p[0] = p1[0]; p[1] = p1[1]; p[2] = p1[2];
     } else {
         const double den = (double)so * 1048576.0;
 #pragma unroll
@@ -529,6 +558,28 @@ __device__ inline void group_ray(const MapDesc& M, const Job& J, int bx, int by,
     }
     const float wgt = M.wbits > 0 ? (float)((double)so * __builtin_ldexp(1.0, -M.wbits)) : (float)n;
     ray = make_float4(p[0], p[1], p[2], wgt);
+}
+
+// Sums a partial group into merge slot v: a one-point partial contributes weight * Q_k.
+__device__ inline void merge_partial(const Partial& P, u32 v, u64* m_so, u64 (*m_sq)[kMergeVox],
+                                     u32 (*m_hi)[kMergeVox], u32* m_n, float (*m_p)[kMergeVox]) {
+    u64 add[3] = {P.sq[0], P.sq[1], P.sq[2]};
+    if (P.n == 1) {
+        float p1[3];
+        u32 Q[3];
+        unpack_single(P.sq, p1, Q);
+        add[0] = P.so * Q[0];
+        add[1] = P.so * Q[1];
+        add[2] = P.so * Q[2];
+        m_p[0][v] = p1[0]; m_p[1][v] = p1[1]; m_p[2][v] = p1[2];   // read only if the group stays single
+    }
+    atomicAdd(&m_so[v], P.so);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const u64 old = atomicAdd(&m_sq[k][v], add[k]);
+        if (old + add[k] < old) atomicAdd(&m_hi[k][v], 1u);   // carry
+    }
+    atomicAdd(&m_n[v], P.n);
 }
 
 __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ jobs,
@@ -547,7 +598,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
     __shared__ u64 m_sq[3][kMergeVox];
     __shared__ u32 m_hi[3][kMergeVox];
     __shared__ u32 m_n[kMergeVox];
-    __shared__ u32 m_idx[kMergeVox];
+    __shared__ float m_p[3][kMergeVox];   // the point of a one-point group
     __shared__ u32 s_nr[kMergeBatch];  // rays emitted per bin of the batch
     __shared__ u32 s_off[kMergeBatch + 2];
     __shared__ u32 s_quarters;
@@ -590,7 +641,6 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 const u64 tk = tkeys[tlist[t]];
                 const MapDesc& M = maps[(u32)(tk >> 45)];
                 const int jid = M.job0 + (int)jm;
-                const Job& J = jobs[jid];
                 int bx, by, bz;
                 unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
                 if (threadIdx.x == 0) s_quarters = 0;
@@ -608,14 +658,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                         const u32 l = P.lj & 4095u;
                         if ((int)(l / kMergeVox) != qd) continue;
                         const u32 v = l & (kMergeVox - 1);
-                        atomicAdd(&m_so[v], P.so);
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            const u64 old = atomicAdd(&m_sq[k][v], P.sq[k]);
-                            if (old + P.sq[k] < old) atomicAdd(&m_hi[k][v], 1u);   // carry
-                        }
-                        atomicAdd(&m_n[v], P.n);
-                        if (P.n == 1) m_idx[v] = P.idx;
+                        merge_partial(P, v, m_so, m_sq, m_hi, m_n, m_p);
                     }
                     __syncthreads();
                     float4 ray[kMergePerThread];
@@ -630,7 +673,8 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                         if (!n) continue;
                         const u64 sq[3] = {m_sq[0][v], m_sq[1][v], m_sq[2][v]};
                         const u32 hw[3] = {m_hi[0][v], m_hi[1][v], m_hi[2][v]};
-                        group_ray(M, J, bx, by, bz, (u32)(qd * kMergeVox + v), n, m_so[v], sq, hw, m_idx[v], ray[r]);
+                        const float p1[3] = {m_p[0][v], m_p[1][v], m_p[2][v]};
+                        group_ray(M, bx, by, bz, (u32)(qd * kMergeVox + v), n, m_so[v], sq, hw, p1, ray[r]);
                         nmine++;
                         m_so[v] = 0; m_sq[0][v] = 0; m_sq[1][v] = 0; m_sq[2][v] = 0;
                         m_hi[0][v] = 0; m_hi[1][v] = 0; m_hi[2][v] = 0; m_n[v] = 0;
@@ -673,14 +717,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                     if (old == 0u || old == key) break;
                     h = (h + 1) & (kMergeVox - 1);
                 }
-                atomicAdd(&m_so[h], P.so);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const u64 old = atomicAdd(&m_sq[k][h], P.sq[k]);
-                    if (old + P.sq[k] < old) atomicAdd(&m_hi[k][h], 1u);   // carry
-                }
-                atomicAdd(&m_n[h], P.n);
-                if (P.n == 1) m_idx[h] = P.idx;
+                merge_partial(P, h, m_so, m_sq, m_hi, m_n, m_p);
             }
             __syncthreads();
             for (int h = threadIdx.x; h < kMergeVox; h += 256) {
@@ -692,13 +729,13 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 const u64 tk = tkeys[tlist[t]];
                 const MapDesc& M = maps[(u32)(tk >> 45)];
                 const int jid = M.job0 + (int)jm;
-                const Job& J = jobs[jid];
                 int bx, by, bz;
                 unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
                 const u64 sq[3] = {m_sq[0][h], m_sq[1][h], m_sq[2][h]};
                 const u32 hw[3] = {m_hi[0][h], m_hi[1][h], m_hi[2][h]};
+                const float p1[3] = {m_p[0][h], m_p[1][h], m_p[2][h]};
                 float4 ray;
-                group_ray(M, J, bx, by, bz, l, m_n[h], m_so[h], sq, hw, m_idx[h], ray);
+                group_ray(M, bx, by, bz, l, m_n[h], m_so[h], sq, hw, p1, ray);
                 const u32 pos = s_off[bi] + atomicAdd(&s_nr[bi], 1u);
                 rays_p[pos] = ray;
                 rays_job[pos] = (u32)jid;
