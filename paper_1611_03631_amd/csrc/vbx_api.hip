@@ -687,7 +687,8 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     StageTimer tm(prof_map, st, ST_FINISH);
     hipLaunchKernelGGL(k_cleanup, dim3(grid_for(s->tkey_cap, 1024)), dim3(256), 0, st, (u64*)s->tkeys.p,
                        (u32)s->tkey_cap, (const u32*)s->tlist.p, (u32)s->tlist_cap, (const CallState*)cs);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d_jobs, J, d_maps, M, jst, cs);
+    hipLaunchKernelGGL(k_finish, dim3(M), dim3(256), 0, st, d_jobs, d_maps, M, jst, (const CallState*)cs);
+    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(64), 0, st, cs);
     }
     if (hipGetLastError() != hipSuccess) return VBX_ERR_DEVICE;
     return VBX_OK;

@@ -58,8 +58,8 @@ __global__ void k_update(const Job* jobs, const MapDesc* maps, const u64* t_key,
                          JobStat* jst, CallState* cs);
 __global__ void k_cleanup(u64* tkeys, u32 tkey_cap, const u32* tlist, u32 tlist_cap,
                           const CallState* cs);
-__global__ void k_finish(const Job* jobs, int njobs, const MapDesc* maps, int nmaps, JobStat* jst,
-                         CallState* cs);
+__global__ void k_finish(const Job* jobs, const MapDesc* maps, int nmaps, JobStat* jst, const CallState* cs);
+__global__ void k_reset_call(CallState* cs);
 __global__ void k_debug_traverse(const float* A, const float* B, int n, int* out, int cap,
                                  int* counts);
 

@@ -1459,59 +1459,64 @@ __global__ __launch_bounds__(256) void k_cleanup(u64* __restrict__ tkeys, u32 tk
     }
 }
 
-__global__ __launch_bounds__(256) void k_finish(const Job* __restrict__ jobs, int njobs,
+// Per map (one workgroup each): folds the call's per-frame statistics into the map, commits
+// its new blocks and clears its frames' statistics.
+__global__ __launch_bounds__(256) void k_finish(const Job* __restrict__ jobs,
                                                 const MapDesc* __restrict__ maps, int nmaps,
                                                 JobStat* __restrict__ jst,
-                                                CallState* __restrict__ cs) {
+                                                const CallState* __restrict__ cs) {
     __shared__ u64 s_acc[8];
-    for (int m = 0; m < nmaps; ++m) {
-        MapState* st = maps[m].st;
-        const bool ok = st->error == 0 && cs->error == 0;
-        if (threadIdx.x < 8) s_acc[threadIdx.x] = 0;
-        __syncthreads();
-        if (ok) {
-            u64 a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (int j = maps[m].job0 + threadIdx.x; j < maps[m].job0 + maps[m].njobs; j += 256) {
-                const JobStat& s = jst[j];
-                a[0] += jobs[j].n;
-                a[1] += s.valid;
-                a[2] += s.invalid;
-                a[3] += s.oob_pts + s.oob_rays;
-                a[4] += s.rays - s.oob_rays;
-                a[5] += s.touches;
-                a[6] += s.voxels;
-                a[7] += s.cells;
-            }
+    const int m = blockIdx.x;
+    if (m >= nmaps) return;   // whole workgroup
+    MapState* st = maps[m].st;
+    const bool ok = st->error == 0 && cs->error == 0;
+    if (threadIdx.x < 8) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    const int j0 = maps[m].job0, j1 = maps[m].job0 + maps[m].njobs;
+    if (ok) {
+        u64 a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int j = j0 + threadIdx.x; j < j1; j += 256) {
+            const JobStat& s = jst[j];
+            a[0] += jobs[j].n;
+            a[1] += s.valid;
+            a[2] += s.invalid;
+            a[3] += s.oob_pts + s.oob_rays;
+            a[4] += s.rays - s.oob_rays;
+            a[5] += s.touches;
+            a[6] += s.voxels;
+            a[7] += s.cells;
+        }
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (a[k]) atomicAdd(&s_acc[k], a[k]);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (ok) {
-                st->new_blocks += st->new_count;
-                st->block_count += st->new_count;
-                st->calls += 1;
-                st->points += s_acc[0];
-                st->valid += s_acc[1];
-                st->invalid += s_acc[2];
-                st->oob += s_acc[3];
-                st->rays += s_acc[4];
-                st->touches += s_acc[5];
-                st->voxels += s_acc[6];
-                st->cells += s_acc[7];
-            }
-            if (cs->error != 0 && st->error == 0) st->error = cs->error;
-            st->new_count = 0;
-        }
-        __syncthreads();
+        for (int k = 0; k < 8; ++k)
+            if (a[k]) atomicAdd(&s_acc[k], a[k]);
     }
-    for (int j = threadIdx.x; j < njobs; j += 256) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (ok) {
+            st->new_blocks += st->new_count;
+            st->block_count += st->new_count;
+            st->calls += 1;
+            st->points += s_acc[0];
+            st->valid += s_acc[1];
+            st->invalid += s_acc[2];
+            st->oob += s_acc[3];
+            st->rays += s_acc[4];
+            st->touches += s_acc[5];
+            st->voxels += s_acc[6];
+            st->cells += s_acc[7];
+        }
+        if (cs->error != 0 && st->error == 0) st->error = cs->error;
+        st->new_count = 0;
+    }
+    for (int j = j0 + threadIdx.x; j < j1; j += 256) {
         JobStat z;
         z.valid = z.invalid = z.oob_pts = z.oob_rays = z.rays = z.touches = z.voxels = z.cells = 0;
         jst[j] = z;
     }
-    __syncthreads();
+}
+
+// After k_finish: the call's counters start from zero for the next call.
+__global__ void k_reset_call(CallState* __restrict__ cs) {
     if (threadIdx.x == 0) {
         cs->ray_count = 0;
         cs->t_count = 0;
