@@ -241,8 +241,8 @@ const char* vbx_profile_stage_name(int stage);
 /* Launch tuning of a map's calls.  Results never depend on it. */
 #define VBX_TUNING_CANDIDATES 10
 typedef struct {
-    int32_t update_split;   /* regions each block is cut into for the update stage (default 2) */
-    int32_t update_threads; /* threads per update workgroup (default 256) */
+    int32_t update_split;   /* regions each block is cut into for the update stage (default 1) */
+    int32_t update_threads; /* threads per update workgroup (default 1024) */
     int32_t update_columns; /* 0: z-slabs; 1: columns cut across x and y.  The candidates are
                                (split, columns, threads) = (1,0,256) (2,0,256) (4,0,256)
                                (2,1,256) (4,1,256) (8,1,256) (1,0,1024) (2,0,1024) (4,0,1024)

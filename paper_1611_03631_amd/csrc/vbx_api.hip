@@ -108,7 +108,7 @@ struct vbx_map {
     Scratch* scratch = nullptr;
     Scratch* touch_src = nullptr; // scratch holding this map's last touches
     int touch_idx = 0;
-    int update_variant = 1;       // index into kUpdateVariants
+    int update_variant = 6;       // index into kUpdateVariants (whole block, 1024 threads)
 };
 
 // A captured call: the kernel sequence of one integration call over fixed maps and frame
