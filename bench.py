@@ -14,7 +14,7 @@ multi-map call and binary32 storage are timed beside it.
 
 --workload c3: 50 sweeps of a 64x2048 LiDAR along a street (voxel 0.20 m, range 60 m, constant
 weight, per-point raycasting), batched in one call; the same sweeps streamed one call each from
-a 4096-block pool that the host doubles whenever a sweep finds it full.
+a 256-block pool that the host doubles whenever a sweep finds it full.
 
 --workload c5: 64 robots (the four sensor classes above plus a 64x2048 LiDAR) send frames
 as Poisson streams of 5-30 Hz each; a 10 s seeded trace is replayed in real time through
@@ -428,6 +428,9 @@ def bench_c4(args, np, torch, vbx, synth):
     }
 
 
+C3_INITIAL_CAPACITY = 256   # blocks: the streamed sweeps grow the pool several times
+
+
 def bench_c3(args, np, torch, vbx, synth):
     """50 LiDAR sweeps along a street: batched into one call, and streamed sweep by sweep from
     a small pool that the host grows (vbx_map_reserve) whenever it fills."""
@@ -447,7 +450,7 @@ def bench_c3(args, np, torch, vbx, synth):
 
     # streamed: one call per sweep, pool doubled by the host when a sweep finds it full
     m = vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"], storage="f32",
-                max_range=P["max_range"], block_capacity=4096, stream=stream)
+                max_range=P["max_range"], block_capacity=C3_INITIAL_CAPACITY, stream=stream)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -540,7 +543,7 @@ def bench_c3(args, np, torch, vbx, synth):
         "blocks": st["blocks"],
         "blocks_allocated_per_s": round(st["new_blocks"] / (ms / 1e3), 1),
         "streamed": {"ms_total": round(stream_ms, 3), "wall_s": round(stream_wall, 3),
-                     "rehashes": rehash, "initial_capacity": 4096, "final_capacity": cap,
+                     "rehashes": rehash, "initial_capacity": C3_INITIAL_CAPACITY, "final_capacity": cap,
                      "points_per_s": round(S * N / (stream_ms / 1e3), 1),
                      "blocks": st_stream["blocks"]},
         "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},

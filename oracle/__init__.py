@@ -70,6 +70,8 @@ def load(path: Optional[str] = None):
     lib.orc_num_blocks.argtypes = [ctypes.c_void_p]
     lib.orc_export.restype = ctypes.c_size_t
     lib.orc_export.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_size_t]
+    lib.orc_export_ramp.restype = ctypes.c_size_t
+    lib.orc_export_ramp.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     lib.orc_last_touches.restype = ctypes.c_size_t
     lib.orc_last_touches.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_size_t]
@@ -142,15 +144,20 @@ class OracleMap:
         return int(self.lib.orc_num_blocks(self._h))
 
     def export(self, with_mass: bool = True):
-        """(coords int32 [B,3] ascending, D f64 [B,4096] metres, W f64 [B,4096], mass f64 [B,4096])."""
+        """(coords int32 [B,3] ascending, D f64 [B,4096] metres, W f64 [B,4096], mass f64 [B,4096],
+        ramp f64 [B,4096]).  mass: the summed weight of every ray that saw the voxel; ramp: that of
+        the rays that saw it on the Eq. (5) drop-off ramp (comparison diagnostics)."""
         nb = self.num_blocks()
         coords = np.zeros((nb, 3), np.int32)
         D = np.zeros((nb, 4096), np.float64)
         W = np.zeros((nb, 4096), np.float64)
         M = np.zeros((nb, 4096), np.float64) if with_mass else None
+        R = np.zeros((nb, 4096), np.float64) if with_mass else None
         self.lib.orc_export(self._h, _ptr(coords), _ptr(D), _ptr(W),
                             _ptr(M) if with_mass else None, nb)
-        return coords, D, W, M
+        if with_mass:
+            self.lib.orc_export_ramp(self._h, _ptr(R), nb)
+        return coords, D, W, M, R
 
     def last_touches(self):
         """Voxels touched by the last frame: (coords int32 [T,3], ray counts uint32 [T])."""

@@ -78,6 +78,8 @@ typedef struct {
 /* ------------------------------------------------------------------ */
 typedef struct {
     double D, W, mass;      /* running distance (in units of delta), weight, sum of ray weights */
+    double ramp;            /* sum of the weights of rays seen on the Eq. (5) ramp (-delta < d <= -eps):
+                               a diagnostic for comparisons, never part of D or W */
     double sw, swd;         /* this frame's sums */
     uint32_t n;             /* this frame's ray count */
     uint32_t stamp;         /* frame in which sw, swd, n were last reset */
@@ -407,6 +409,7 @@ static void cast_ray(orc_map* m, const orc_ray* ray, const float s32[3], const d
         vx->swd += w * (dc / d64);
         vx->n += 1;
         vx->mass += ray->wgt;
+        if (P->weighting == 1 && d > -d64 && d <= -eps) vx->ramp += ray->wgt;
         st->touches++;
     }
 }
@@ -568,6 +571,31 @@ size_t orc_export(const orc_map* m, int32_t* coords, double* D, double* W, doubl
             if (D) D[o] = vx ? vx->D * d64 : 0.0;
             if (W) W[o] = vx ? vx->W : 0.0;
             if (mass) mass[o] = vx ? vx->mass : 0.0;
+        }
+    }
+    free(keys);
+    return nb;
+}
+
+/*
+ * Per voxel, in orc_export's order: the summed weight of the rays that saw the voxel on the
+ * Eq. (5) ramp.  D's sensitivity to distance rounding grows with it (the ramp weights move
+ * with the distance).  Returns the number of blocks.
+ */
+size_t orc_export_ramp(const orc_map* m, double* ramp, size_t cap) {
+    size_t nb = m->blocks.size;
+    uint64_t* keys = (uint64_t*)malloc((nb + 1) * sizeof(uint64_t));
+    size_t j = 0;
+    for (size_t i = 0; i < m->blocks.cap; ++i)
+        if (m->blocks.keys[i]) keys[j++] = m->blocks.keys[i] - 1;
+    qsort(keys, nb, sizeof(uint64_t), cmp_u64);
+    for (size_t b = 0; b < nb && b < cap; ++b) {
+        int32_t bc[3];
+        unpack3(keys[b], &bc[0], &bc[1], &bc[2]);
+        for (int l = 0; l < 4096; ++l) {
+            int32_t g0 = 16 * bc[0] + (l & 15), g1 = 16 * bc[1] + ((l >> 4) & 15), g2 = 16 * bc[2] + (l >> 8);
+            const orc_voxel* vx = (const orc_voxel*)table_get((orc_table*)&m->vox, pack3(g0, g1, g2), 0, NULL);
+            ramp[b * 4096 + (size_t)l] = vx ? vx->ramp : 0.0;
         }
     }
     free(keys);

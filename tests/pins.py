@@ -183,7 +183,7 @@ def head_on_expectation(Z, axis, sign, weighting, frames, pose):
 
 
 def _export_dict(m):
-    coords, D, W, _ = m.export()
+    coords, D, W = m.export()[:3]
     res = {}
     for b in range(coords.shape[0]):
         for l in np.nonzero(W[b] > 0)[0]:
@@ -360,8 +360,8 @@ def pin_merged_singletons(lib_path=None, seed=8):
         sa = a.integrate(pts, pose)
         sb = b.integrate(pts, pose)
         assert sa["rays"] == sb["rays"] == pts.shape[0]
-        ca, Da, Wa, _ = a.export()
-        cb, Db, Wb, _ = b.export()
+        ca, Da, Wa = a.export()[:3]
+        cb, Db, Wb = b.export()[:3]
         assert np.array_equal(ca, cb) and np.array_equal(Wa, Wb) and np.array_equal(Da, Db)
         a.close(); b.close()
 
@@ -456,8 +456,8 @@ def pin_permutation(lib_path=None, seed=9):
         b = oracle.OracleMap(0.1, 0.3, weighting="quad", merge=merge, lib_path=lib_path)
         a.integrate(pts, w.poses[0])
         b.integrate(pts[perm], w.poses[0])
-        ca, Da, Wa, _ = a.export()
-        cb, Db, Wb, _ = b.export()
+        ca, Da, Wa = a.export()[:3]
+        cb, Db, Wb = b.export()[:3]
         assert np.array_equal(ca, cb)
         assert np.array_equal(Wa > 0, Wb > 0)
         ta, tb = a.last_touches(), b.last_touches()

@@ -29,7 +29,7 @@ def d_error(gpu_export, orc_export, v):
     least 1e-3 of the voxel's summed ray weights (outside the last 1/1000 of the drop-off ramp,
     where a 1e-7 m change of the binary32 distance moves the weight by a large relative amount)."""
     coords, dw = gpu_export
-    oc, oD, oW, oM = orc_export
+    oc, oD, oW, oM = orc_export[:4]
     assert np.array_equal(coords, oc)
     sel = (oW > 0) & (oW >= 1e-3 * oM)
     err = np.abs(dw[:, :, 0].astype(np.float64) - oD)[sel] / v
