@@ -27,7 +27,6 @@ constexpr int kTileSimple = 1024;      // points per workgroup, per-point raycas
 constexpr int kTileGroupedW = 32;      // 2-D tile of an organised cloud (grouped)
 constexpr int kTileGroupedH = 16;
 constexpr int kTileGrouped = kTileGroupedW * kTileGroupedH;  // 512 points
-constexpr int kGroupSlots = 512;       // LDS hash slots per grouped tile (>= its points)
 constexpr int kMaxStepsPerRay = 96;    // guard only; real bands need 3*(2*delta/v + 2) + 1
 
 // Per-map parameters and device pointers for one call (copied to the device per call).

@@ -246,9 +246,17 @@ __device__ inline u32 tset_insert(u64* tkeys, u32 tmask, u64 key, u32* tlist, u3
     return 0xFFFFFFFFu;
 }
 
-// Grouped raycasting, step 1: the points of a tile are merged by voxel in an LDS hash (exact
-// integer sums); each partial group is written as one record, tagged with the block-set slot
-// of its voxel's block.  The block set is entered once per distinct block of the tile.
+// Grouped raycasting, step 1: the points of a tile are merged by voxel (exact integer sums);
+// each partial group is written as one record, tagged with the block-set slot of its voxel's
+// block.  The block set is entered once per distinct block of the tile.
+//
+// The tile's voxel table has kTileHash slots, so that eight workgroups fit a CU.  A tile can
+// have more distinct voxels than that (up to its 512 points); a run of points that finds the
+// table full becomes a partial group of its own, which is exact because partial groups are
+// merged again across tiles.  A tile still writes at most kTileGrouped records.
+constexpr int kTileHash = 256;     // voxel table slots per tile (one per thread)
+constexpr int kTileBlocks = 128;   // distinct-block table slots per tile
+
 __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ jobs, int njobs,
                                                         const MapDesc* __restrict__ maps,
                                                         u64* __restrict__ tkeys, u32 tmask,
@@ -257,13 +265,14 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                                                         u32* __restrict__ tile_parts, u32 tiles_per_job,
                                                         JobStat* __restrict__ jst,
                                                         CallState* __restrict__ cs) {
-    __shared__ u64 s_key[kGroupSlots];
-    __shared__ u64 s_so[kGroupSlots];
-    __shared__ u64 s_sq[3][kGroupSlots];
-    __shared__ u32 s_n[kGroupSlots];
-    __shared__ u32 s_idx[kGroupSlots];      // the point of a one-point group
-    __shared__ u64 s_bkey[kGroupSlots];   // distinct (map, block) keys of the tile
-    __shared__ u32 s_bh[kGroupSlots];     // their block-set slots
+    static_assert(kTileHash == 256, "one voxel slot per thread");
+    __shared__ u64 s_key[kTileHash];
+    __shared__ u64 s_so[kTileHash];
+    __shared__ u64 s_sq[3][kTileHash];
+    __shared__ u32 s_n[kTileHash];
+    __shared__ u32 s_idx[kTileHash];        // the point of a one-point group
+    __shared__ u64 s_bkey[kTileBlocks];     // distinct (map, block) keys of the tile
+    __shared__ u32 s_bh[kTileBlocks];       // their block-set slots
     __shared__ u32 s_cnt[3];
     __shared__ u32 lds8[4];
     // when every frame has the same number of tiles (and there is one map), the job and map
@@ -271,16 +280,20 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     const int jid = tiles_per_job ? (int)(blockIdx.x / tiles_per_job) : job_of_tile(jobs, njobs, blockIdx.x);
     const Job J = jobs[jid];          // by value: kept in registers across the LDS atomics
     const MapDesc M = maps[tiles_per_job ? 0u : J.map];
-    for (int i = threadIdx.x; i < kGroupSlots; i += 256) {
-        s_key[i] = kEmpty; s_so[i] = 0; s_sq[0][i] = 0; s_sq[1][i] = 0; s_sq[2][i] = 0; s_n[i] = 0;
-        s_bkey[i] = kEmpty;
-    }
+    s_key[threadIdx.x] = kEmpty; s_so[threadIdx.x] = 0;
+    s_sq[0][threadIdx.x] = 0; s_sq[1][threadIdx.x] = 0; s_sq[2][threadIdx.x] = 0; s_n[threadIdx.x] = 0;
+    if (threadIdx.x < kTileBlocks) s_bkey[threadIdx.x] = kEmpty;
     if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
     __syncthreads();
 
     const u32 tile = blockIdx.x - J.tile0;
     const int lane = lane_id(), r16 = lane & 15;
     u32 n_valid = 0, n_inv = 0, n_oob = 0;
+    // runs that found the voxel table full: kept here and written as records of their own
+    bool o_has[2] = {false, false};
+    u64 o_key[2] = {0, 0}, o_so[2] = {0, 0}, o_sq[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    u32 o_n[2] = {0, 0};
+    float o_p[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         u32 i;
@@ -300,6 +313,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         u64 key = kEmpty - 1 - (u64)lane;
         u64 so = 0, sq0 = 0, sq1 = 0, sq2 = 0;
         u32 cnt = 0;
+        float pw[3] = {0.f, 0.f, 0.f};
         if (in) {
             const float x = J.pts[3 * (size_t)i], y = J.pts[3 * (size_t)i + 1], z = J.pts[3 * (size_t)i + 2];
             float q[3];
@@ -316,6 +330,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                 sq1 = om * Q[1];
                 sq2 = om * Q[2];
                 cnt = 1;
+                pw[0] = q[0]; pw[1] = q[1]; pw[2] = q[2];
             } else if (c == 0) {
                 n_inv++;
             } else {
@@ -324,7 +339,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         }
         // Neighbouring pixels mostly share a voxel: runs of equal keys within each row of 16
         // lanes are summed first (segmented scan over DPP row shifts; integer sums, exact), so
-        // only the last lane of a run enters the tile's LDS hash.
+        // only the last lane of a run enters the tile's table.
         // cross-lane reads run with every lane active (never inside a short-circuit condition)
         const u64 prev_key = row_shr64<1>(key);
         const bool head0 = r16 == 0 || prev_key != key;
@@ -344,18 +359,26 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         const u32 next_head = row_shl<1>((u32)head0);
         const bool tail = r16 == 15 || next_head != 0;
         if (tail && cnt > 0) {
-            u32 h = (u32)mix64(key) & (kGroupSlots - 1);
-            for (;;) {
-                u64 old = atomicCAS(&s_key[h], kEmpty, key);
-                if (old == kEmpty || old == key) break;
-                h = (h + 1) & (kGroupSlots - 1);
+            u32 h = (u32)mix64(key) & (kTileHash - 1);
+            bool placed = false;
+            for (int probe = 0; probe < kTileHash; ++probe) {
+                const u64 old = atomicCAS(&s_key[h], kEmpty, key);
+                if (old == kEmpty || old == key) { placed = true; break; }
+                h = (h + 1) & (kTileHash - 1);
             }
-            atomicAdd(&s_so[h], so);
-            atomicAdd(&s_sq[0][h], sq0);
-            atomicAdd(&s_sq[1][h], sq1);
-            atomicAdd(&s_sq[2][h], sq2);
-            atomicAdd(&s_n[h], cnt);
-            s_idx[h] = i;     // read only when the group has a single point: then it is this one
+            if (placed) {
+                atomicAdd(&s_so[h], so);
+                atomicAdd(&s_sq[0][h], sq0);
+                atomicAdd(&s_sq[1][h], sq1);
+                atomicAdd(&s_sq[2][h], sq2);
+                atomicAdd(&s_n[h], cnt);
+                s_idx[h] = i;     // read only when the group has a single point: then it is this one
+            } else {
+                o_has[j] = true;
+                o_key[j] = key; o_so[j] = so; o_sq[j][0] = sq0; o_sq[j][1] = sq1; o_sq[j][2] = sq2;
+                o_n[j] = cnt;
+                o_p[j][0] = pw[0]; o_p[j][1] = pw[1]; o_p[j][2] = pw[2];
+            }
         }
     }
     if (n_valid) atomicAdd(&s_cnt[0], n_valid);
@@ -363,64 +386,71 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     if (n_oob) atomicAdd(&s_cnt[2], n_oob);
     __syncthreads();
 
-    // one-point groups carry their point: load it now so that the load overlaps the block
-    // phase (slot k = threadIdx.x + 256 r is this thread's in the output loop too)
-    float sx[2] = {0.f, 0.f}, sy[2] = {0.f, 0.f}, sz[2] = {0.f, 0.f};
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int k = threadIdx.x + 256 * r;
-        if (s_key[k] != kEmpty && s_n[k] == 1) {
-            const size_t i1 = s_idx[k];
-            sx[r] = J.pts[3 * i1];
-            sy[r] = J.pts[3 * i1 + 1];
-            sz[r] = J.pts[3 * i1 + 2];
-        }
+    // this thread's records: its table slot, then its overflow runs
+    const int k = threadIdx.x;
+    const u64 skey = s_key[k];
+    const bool has_slot = skey != kEmpty;
+    const u32 sn = has_slot ? s_n[k] : 0u;
+    // a one-point group carries its point: load it now, so that the load overlaps the block phase
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    if (has_slot && sn == 1) {
+        const size_t i1 = s_idx[k];
+        sx = J.pts[3 * i1];
+        sy = J.pts[3 * i1 + 1];
+        sz = J.pts[3 * i1 + 2];
     }
-
-    // blocks of the tile's partial groups; reserve the output range
     const u64 mapbits = (u64)M.map_id << 45;
+    // distinct blocks of the records; a block that finds the block table full resolves alone
+    u32 bh_rec[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};   // block table slot, or direct
+    bool direct[3] = {false, false, false};
+    u64 rec_bk[3] = {0, 0, 0};
+    bool rec_on[3] = {has_slot, o_has[0], o_has[1]};
+    rec_bk[0] = mapbits | (skey >> 12);
+    rec_bk[1] = mapbits | (o_key[0] >> 12);
+    rec_bk[2] = mapbits | (o_key[1] >> 12);
     u32 mine = 0;
-    for (int k = threadIdx.x; k < kGroupSlots; k += 256) {
-        const u64 key = s_key[k];
-        if (key == kEmpty) continue;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        if (!rec_on[r]) continue;
         mine++;
-        const u64 bk = mapbits | (key >> 12);
-        u32 b = (u32)mix64(bk) & (kGroupSlots - 1);
-        for (;;) {
-            u64 old = atomicCAS(&s_bkey[b], kEmpty, bk);
-            if (old == kEmpty || old == bk) break;
-            b = (b + 1) & (kGroupSlots - 1);
+        const u64 bk = rec_bk[r];
+        u32 b = (u32)mix64(bk) & (kTileBlocks - 1);
+        for (int probe = 0; probe < kTileBlocks; ++probe) {
+            const u64 old = atomicCAS(&s_bkey[b], kEmpty, bk);
+            if (old == kEmpty || old == bk) { bh_rec[r] = b; break; }
+            b = (b + 1) & (kTileBlocks - 1);
         }
+        direct[r] = bh_rec[r] == 0xFFFFFFFFu;
     }
     // partials of tile k take slots [k * kTileGrouped, k * kTileGrouped + count): a tile has at
     // most kTileGrouped points, so the slots never overlap and no counter is shared
     u32 tot;
     const u32 incl = block_scan_256(mine, lds8, &tot);
     if (threadIdx.x == 0) tile_parts[blockIdx.x] = tot;
-    for (int k = threadIdx.x; k < kGroupSlots; k += 256) {
-        const u64 bk = s_bkey[k];
-        if (bk != kEmpty) s_bh[k] = tset_insert(tkeys, tmask, bk, tlist, tlist_cap, cs);
+    if (threadIdx.x < kTileBlocks) {
+        const u64 bk = s_bkey[threadIdx.x];
+        if (bk != kEmpty) s_bh[threadIdx.x] = tset_insert(tkeys, tmask, bk, tlist, tlist_cap, cs);
     }
+    u32 hdirect[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        if (rec_on[r] && direct[r]) hdirect[r] = tset_insert(tkeys, tmask, rec_bk[r], tlist, tlist_cap, cs);
     __syncthreads();
     size_t pos = (size_t)blockIdx.x * kTileGrouped + incl - mine;
     const u32 jm12 = J.jm << 12;
-    static_assert(kGroupSlots == 512, "two output slots per thread");
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int k = threadIdx.x + 256 * r;
-        const u64 key = s_key[k];
-        if (key == kEmpty) continue;
-        const u64 bk = mapbits | (key >> 12);
-        u32 b = (u32)mix64(bk) & (kGroupSlots - 1);
-        while (s_bkey[b] != bk) b = (b + 1) & (kGroupSlots - 1);
-        {
-            Partial P;
+    for (int r = 0; r < 3; ++r) {
+        if (!rec_on[r]) continue;
+        Partial P;
+        u64 key;
+        if (r == 0) {
+            key = skey;
             P.so = s_so[k];
-            P.n = s_n[k];
-            if (P.n == 1) {
+            P.n = sn;
+            if (sn == 1) {
                 // the same transform and Q_k as when the point was grouped
                 float p1[3];
-                (void)classify_point(M, J.pose, sx[r], sy[r], sz[r], p1);
+                (void)classify_point(M, J.pose, sx, sy, sz, p1);
                 int g1[3];
                 u32 Q1[3];
                 u64 om1;
@@ -429,11 +459,25 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
             } else {
                 P.sq[0] = s_sq[0][k]; P.sq[1] = s_sq[1][k]; P.sq[2] = s_sq[2][k];
             }
-            P.h = s_bh[b];
-            P.lj = jm12 | (u32)(key & 4095u);
-            P.pad = 0;
-            parts[pos] = P;
+        } else {
+            const int j = r - 1;
+            key = o_key[j];
+            P.so = o_so[j];
+            P.n = o_n[j];
+            if (o_n[j] == 1) {
+                int g1[3];
+                u32 Q1[3];
+                u64 om1;
+                group_terms(M, o_p[j], 1.0f, g1, Q1, om1);
+                pack_single(o_p[j], Q1, P.sq);
+            } else {
+                P.sq[0] = o_sq[j][0]; P.sq[1] = o_sq[j][1]; P.sq[2] = o_sq[j][2];
+            }
         }
+        P.h = direct[r] ? hdirect[r] : s_bh[bh_rec[r]];
+        P.lj = jm12 | (u32)(key & 4095u);
+        P.pad = 0;
+        parts[pos] = P;
         pos++;
     }
     if (threadIdx.x == 0) {

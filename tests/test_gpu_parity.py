@@ -128,6 +128,35 @@ def test_lidar_sweeps_simple(vbx):
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("width", [0, 64])
+def test_grouped_tiles_with_more_voxels_than_their_table(vbx, width):
+    """Points scattered so that a 512-point tile spans more distinct voxels than the tile's
+    voxel table holds: the runs that find it full become partial groups of their own, which
+    the cross-tile merge must combine exactly (some identical neighbours make runs of two)."""
+    rng = np.random.default_rng(1611036310 + 77 + width)
+    n = 4096
+    pts = np.empty((n, 3), np.float32)
+    pts[:, :2] = rng.uniform(-2.0, 2.0, size=(n, 2))
+    pts[:, 2] = rng.uniform(1.0, 5.0, size=n)
+    pts[1::4] = pts[0::4]            # 384 distinct voxels per 512-point tile (table: 256)
+    pose = np.eye(3, 4, dtype=np.float32)
+    params = dict(voxel_size=0.02, trunc=0.06, weighting="quad", merge="grouped", max_range=10.0,
+                  block_capacity=65536)
+    frames = [(pts, pose, width)]
+    g, o = run_both(vbx, params, frames, batch=True)
+    compare_touches(g.last_touches(), o.last_touches())
+    res = compare_export(g.export(), o.export(), params)
+    st = g.stats()
+    log(f"scattered tiles (width {width}): rays {st['rays']}, {res}")
+    # identity pose: world = sensor coordinates; one group (ray) per distinct binary32 voxel key
+    iv = np.float32(1.0) / np.float32(0.02)
+    keys = np.floor(pts * iv).astype(np.int64)
+    assert st["rays"] == np.unique(keys, axis=0).shape[0]
+    if width == 0:   # every 512-point tile overflowed its 256-slot table
+        assert all(np.unique(keys[s:s + 512], axis=0).shape[0] > 256 for s in range(0, n, 512))
+
+
+
 def test_empty_and_invalid_frames(vbx):
     params = dict(voxel_size=0.1, trunc=0.3, weighting="quad", merge="grouped")
     g = gpu_map(vbx, params)
