@@ -53,7 +53,7 @@ struct Stage {
 };
 
 struct Scratch {
-    DevBuf rays_p, rays_job, cross, ncross, sorted, tkeys, tval, tlist, t_key, t_slot, bins, off,
+    DevBuf rays_p, rays_job, cross, ncross, sorted, tkeys, tval, tlist, t_key, t_slot, order, bins, off,
         partial, parts, parts_sorted, tile_parts, chunk_first, touch_key, touch_n, tables, jst, cs;
     size_t ray_cap = 0, cross_cap = 0, tkey_cap = 0, tlist_cap = 0, bins_cap = 0, nparts = 0,
            touch_cap = 0;
@@ -248,7 +248,7 @@ void free_storage(vbx_map* m) {
 void free_scratch(Scratch* s) {
     if (!s) return;
     DevBuf* bufs[] = {&s->rays_p, &s->rays_job, &s->cross, &s->ncross, &s->sorted, &s->tkeys,
-                      &s->tval, &s->tlist, &s->t_key, &s->t_slot, &s->bins, &s->off, &s->partial,
+                      &s->tval, &s->tlist, &s->t_key, &s->t_slot, &s->order, &s->bins, &s->off, &s->partial,
                       &s->parts, &s->parts_sorted, &s->tile_parts, &s->chunk_first, &s->touch_key, &s->touch_n,
                       &s->tables, &s->jst, &s->cs};
     for (DevBuf* b : bufs)
@@ -314,6 +314,7 @@ int ensure_scratch(Scratch* s, hipStream_t st, const CallPlan& plan, int njobs, 
     GROW(s->tlist, tlist_cap * sizeof(u32));
     GROW(s->t_key, tlist_cap * sizeof(u64));
     GROW(s->t_slot, tlist_cap * sizeof(int));
+    GROW(s->order, tlist_cap * sizeof(u32));
     if ((r = grow(s->bins, (bins_cap + 1) * sizeof(u32))) < 0) return VBX_ERR_OUT_OF_MEMORY;
     if (r == 1) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(bins_cap + 1)), dim3(256), 0, st, (u32*)s->bins.p, 0u, bins_cap + 1);
     GROW(s->off, (bins_cap + 1) * sizeof(u32));
@@ -381,11 +382,11 @@ int update_grid() {
 
 template <int STORAGE, int RX, int RY, int RZ, int NT>
 void launch_update_t(hipStream_t st, const Job* jobs, const MapDesc* maps, const u64* t_key,
-                     const int* t_slot, const u32* off, const float4* sorted, u32 JM, u64* touch_key,
-                     u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
+                     const int* t_slot, const u32* off, const u32* order, const float4* sorted, u32 JM,
+                     u64* touch_key, u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
     hipLaunchKernelGGL((k_update<STORAGE, RX, RY, RZ, NT>), dim3(update_grid<STORAGE, RX, RY, RZ, NT>()), dim3(NT),
-                       0, st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep, jst,
-                       cs);
+                       0, st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, touch_n, touch_cap,
+                       keep, jst, cs);
 }
 
 // Update-kernel variants: how a block is cut into regions, and the workgroup size.  Larger
@@ -403,9 +404,9 @@ static_assert(kNumUpdateVariants == VBX_TUNING_CANDIDATES, "tuning candidates");
 
 template <int STORAGE>
 void launch_update_s(int variant, hipStream_t st, const Job* jobs, const MapDesc* maps, const u64* t_key,
-                     const int* t_slot, const u32* off, const float4* sorted, u32 JM, u64* touch_key,
-                     u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
-#define VBX_UPD(X, Y, Z, T) launch_update_t<STORAGE, X, Y, Z, T>(st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap, keep, jst, cs)
+                     const int* t_slot, const u32* off, const u32* order, const float4* sorted, u32 JM,
+                     u64* touch_key, u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
+#define VBX_UPD(X, Y, Z, T) launch_update_t<STORAGE, X, Y, Z, T>(st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, touch_n, touch_cap, keep, jst, cs)
     switch (variant) {
         case 0: VBX_UPD(16, 16, 16, 256); break;
         case 2: VBX_UPD(16, 16, 4, 256); break;
@@ -431,14 +432,14 @@ void warm_update_grids() {
 }
 
 void launch_update(int storage, int variant, hipStream_t st, const Job* jobs, const MapDesc* maps,
-                   const u64* t_key, const int* t_slot, const u32* off, const float4* sorted, u32 JM,
-                   u64* touch_key, u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
+                   const u64* t_key, const int* t_slot, const u32* off, const u32* order, const float4* sorted,
+                   u32 JM, u64* touch_key, u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
     if (storage == VBX_F32)
-        launch_update_s<0>(variant, st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap,
-                           keep, jst, cs);
+        launch_update_s<0>(variant, st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, touch_n,
+                           touch_cap, keep, jst, cs);
     else
-        launch_update_s<1>(variant, st, jobs, maps, t_key, t_slot, off, sorted, JM, touch_key, touch_n, touch_cap,
-                           keep, jst, cs);
+        launch_update_s<1>(variant, st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, touch_n,
+                           touch_cap, keep, jst, cs);
 }
 
 // Records the start / end of a stage on the stream when profiling is on.
@@ -678,8 +679,11 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     if (plan.keep_touches) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->touch_count, 0u);
     {
     StageTimer tm(prof_map, st, ST_UPDATE);
+    hipLaunchKernelGGL(k_order_blocks, dim3(1), dim3(1024), 0, st, (const u32*)s->off.p, JM, (u32*)s->order.p,
+                       (const CallState*)cs);
     launch_update(plan.storage, update_variant, st, d_jobs, d_maps, (const u64*)s->t_key.p,
-                  (const int*)s->t_slot.p, (const u32*)s->off.p, (const float4*)s->sorted.p, JM,
+                  (const int*)s->t_slot.p, (const u32*)s->off.p, (const u32*)s->order.p,
+                  (const float4*)s->sorted.p, JM,
                   (u64*)s->touch_key.p, (u32*)s->touch_n.p, (u32)s->touch_cap, plan.keep_touches ? 1 : 0,
                   jst, cs);
     }

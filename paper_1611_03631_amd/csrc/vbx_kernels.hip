@@ -1216,6 +1216,34 @@ __device__ inline void store_voxel(void* pool, size_t idx, float D, float W) {
 
 constexpr int kOffWindow = 256;   // frames whose bin offsets are staged in LDS at a time
 
+// Order in which the update takes the call's blocks: heaviest first (log2 buckets of the rays
+// crossing the block over all frames of the call), so that the longest frame chains start at
+// once and the light blocks fill in behind them.  One workgroup; the order within a bucket is
+// free (each block is folded by one workgroup, so results do not depend on it).
+__global__ __launch_bounds__(1024) void k_order_blocks(const u32* __restrict__ off, u32 JM,
+                                                       u32* __restrict__ order,
+                                                       const CallState* __restrict__ cs) {
+    __shared__ u32 s_cnt[33];
+    __shared__ u32 s_base[33];
+    const u32 nt = cs->error ? 0u : cs->t_count;
+    if (threadIdx.x < 33) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (u32 t = threadIdx.x; t < nt; t += 1024) {
+        const u32 w = off[(t + 1) * JM] - off[t * JM];
+        atomicAdd(&s_cnt[w ? 32 - __clz(w) : 0], 1u);   // bucket: bit length of w
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 acc = 0;
+        for (int b = 32; b >= 0; --b) { s_base[b] = acc; acc += s_cnt[b]; }   // heaviest first
+    }
+    __syncthreads();
+    for (u32 t = threadIdx.x; t < nt; t += 1024) {
+        const u32 w = off[(t + 1) * JM] - off[t * JM];
+        order[atomicAdd(&s_base[w ? 32 - __clz(w) : 0], 1u)] = t;
+    }
+}
+
 // Work item u = t * NREG + q: region q of touched block t, a box of RX x RY x RZ voxels
 // (regions tile the block, x fastest).  Regions of one block are independent (different
 // voxels) and replay the same rays, each ray walked in full but observed only inside the
@@ -1227,6 +1255,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                                 const u64* __restrict__ t_key,
                                                 const int* __restrict__ t_slot,
                                                 const u32* __restrict__ off,
+                                                const u32* __restrict__ order,
                                                 const float4* __restrict__ sorted, u32 JM,
                                                 u64* __restrict__ touch_key,
                                                 u32* __restrict__ touch_n, u32 touch_cap,
@@ -1253,7 +1282,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
         __syncthreads();
         const u32 u = s_t;
         if (u >= nt) break;
-        const u32 t = u / (u32)NREG;
+        const u32 t = order[u / (u32)NREG];    // heaviest blocks first
         const int q = (int)(u % (u32)NREG);
         const int qx = q % NRX, qy = (q / NRX) % NRY, qz = q / (NRX * NRY);
         const u64 tk = t_key[t];
@@ -1426,65 +1455,65 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
 }
 
 template __global__ void k_update<0, 16, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<0, 16, 16, 8, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<0, 16, 16, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<0, 8, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<0, 8, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<0, 4, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<0, 16, 16, 16, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<0, 16, 16, 8, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<0, 16, 16, 4, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<0, 16, 16, 8, 512>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<1, 16, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<1, 16, 16, 8, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<1, 16, 16, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<1, 8, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<1, 8, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<1, 4, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<1, 16, 16, 16, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<1, 16, 16, 8, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<1, 16, 16, 4, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 template __global__ void k_update<1, 16, 16, 8, 512>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const float4*, u32, u64*, u32*, u32, int,
-                                                        JobStat*, CallState*);
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 
 // ---------------------------------------------------------------------------
 // finish: commit block counts, fold statistics, clean per-call tables
