@@ -645,7 +645,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
     __shared__ float m_p[3][kMergeVox];   // the point of a one-point group
     __shared__ u32 s_nr[kMergeBatch];  // rays emitted per bin of the batch
     __shared__ u32 s_off[kMergeBatch + 2];
-    __shared__ u32 s_quarters;
+    __shared__ u32 s_passes;
     __shared__ u32 lds8[4];
     for (int i = threadIdx.x; i < kMergeVox; i += 256) {
         m_key[i] = 0; m_so[i] = 0; m_sq[0][i] = 0; m_sq[1][i] = 0; m_sq[2][i] = 0;
@@ -687,16 +687,16 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 const int jid = M.job0 + (int)jm;
                 int bx, by, bz;
                 unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
-                if (threadIdx.x == 0) s_quarters = 0;
+                if (threadIdx.x == 0) s_passes = 0;
                 __syncthreads();
                 u32 qm = 0;
                 for (u32 e = lo + threadIdx.x; e < hi; e += 256) qm |= 1u << ((sorted[e].lj & 4095u) / kMergeVox);
-                if (qm) atomicOr(&s_quarters, qm);
+                if (qm) atomicOr(&s_passes, qm);
                 __syncthreads();
-                const u32 quarters = s_quarters;
+                const u32 passes = s_passes;
                 u32 nrays = 0;
                 for (int qd = 0; qd < kMergePasses; ++qd) {
-                    if (!(quarters & (1u << qd))) continue;
+                    if (!(passes & (1u << qd))) continue;
                     for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
                         const Partial& P = sorted[e];
                         const u32 l = P.lj & 4095u;
