@@ -129,15 +129,26 @@ __device__ inline int job_of_tile(const Job* jobs, int njobs, u32 tile) {
     return cnt - 1;
 }
 
+// A float in global memory: loads through it compile to global (not flat) loads, which
+// wait on the vector memory counter only.
+typedef __attribute__((address_space(1))) float gfloat;
+
 // Value of the lane N below (row_shr) or above (row_shl) within the lane's row of 16 lanes
 // (DPP, a VALU operand modifier; 0 where that lane lies outside the row).
 template <int N>
 __device__ inline u32 row_shr(u32 v) {
     return (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + N, 0xF, 0xF, true);
 }
+// The two halves are shifted separately and reassembled as one register pair (a bit cast,
+// not an OR of shifted halves, which the compiler would turn into two 64-bit adds).
+typedef u32 u32x2 __attribute__((ext_vector_type(2)));
 template <int N>
 __device__ inline u64 row_shr64(u64 v) {
-    return (u64)row_shr<N>((u32)v) | ((u64)row_shr<N>((u32)(v >> 32)) << 32);
+    const u32x2 h = __builtin_bit_cast(u32x2, v);
+    u32x2 r;
+    r.x = row_shr<N>(h.x);
+    r.y = row_shr<N>(h.y);
+    return __builtin_bit_cast(u64, r);
 }
 template <int N>
 __device__ inline u32 row_shl(u32 v) {
@@ -253,7 +264,9 @@ __device__ inline u32 tset_insert(u64* tkeys, u32 tmask, u64 key, u32* tlist, u3
 // The tile's voxel table has kTileHash slots, so that eight workgroups fit a CU.  A tile can
 // have more distinct voxels than that (up to its 512 points); a run of points that finds the
 // table full becomes a partial group of its own, which is exact because partial groups are
-// merged again across tiles.  A tile still writes at most kTileGrouped records.
+// merged again across tiles.  Table records fill the tile's record range from the front, such
+// runs fill it from the back; a tile has at most kTileGrouped runs, so the two never meet.
+// tile_parts holds (front count) | (back count) << 16.
 constexpr int kTileHash = 256;     // voxel table slots per tile (one per thread)
 constexpr int kTileBlocks = 128;   // distinct-block table slots per tile
 
@@ -273,7 +286,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     __shared__ u32 s_idx[kTileHash];        // the point of a one-point group
     __shared__ u64 s_bkey[kTileBlocks];     // distinct (map, block) keys of the tile
     __shared__ u32 s_bh[kTileBlocks];       // their block-set slots
-    __shared__ u32 s_cnt[3];
+    __shared__ u32 s_cnt[4];
     __shared__ u32 lds8[4];
     // when every frame has the same number of tiles (and there is one map), the job and map
     // follow without a dependent load
@@ -283,39 +296,47 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     s_key[threadIdx.x] = kEmpty; s_so[threadIdx.x] = 0;
     s_sq[0][threadIdx.x] = 0; s_sq[1][threadIdx.x] = 0; s_sq[2][threadIdx.x] = 0; s_n[threadIdx.x] = 0;
     if (threadIdx.x < kTileBlocks) s_bkey[threadIdx.x] = kEmpty;
-    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
     __syncthreads();
 
     const u32 tile = blockIdx.x - J.tile0;
     const int lane = lane_id(), r16 = lane & 15;
+    const u64 mapbits = (u64)M.map_id << 45;
+    const u32 jm12 = J.jm << 12;
+    Partial* const tparts = parts + (size_t)blockIdx.x * kTileGrouped;
     u32 n_valid = 0, n_inv = 0, n_oob = 0;
-    // runs that found the voxel table full: kept here and written as records of their own
-    bool o_has[2] = {false, false};
-    u64 o_key[2] = {0, 0}, o_so[2] = {0, 0}, o_sq[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    u32 o_n[2] = {0, 0};
-    float o_p[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    // both points of this thread are loaded before either is processed; a lane past the end
+    // of the frame loads its first point (a frame with a tile has one) and ignores it
+    u32 ii[2];
+    bool inn[2];
+    float px[2], py[2], pz[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        u32 i;
-        bool in;
         if (J.width > 0) {
             const u32 tiles_x = (J.width + kTileGroupedW - 1) / kTileGroupedW;
             const u32 ty = tile / tiles_x, tx = tile - ty * tiles_x;
             const u32 col = tx * kTileGroupedW + (threadIdx.x & 31);
             const u32 row = ty * kTileGroupedH + (threadIdx.x >> 5) + 8u * j;
-            in = col < J.width && (size_t)row * J.width + col < J.n;
-            i = row * J.width + col;
+            inn[j] = col < J.width && (size_t)row * J.width + col < J.n;
+            ii[j] = row * J.width + col;
         } else {
-            i = tile * kTileGrouped + threadIdx.x + 256u * j;
-            in = i < J.n;
+            ii[j] = tile * kTileGrouped + threadIdx.x + 256u * j;
+            inn[j] = ii[j] < J.n;
         }
+        const gfloat* src = (const gfloat*)J.pts + 3 * (size_t)(inn[j] ? ii[j] : 0u);
+        px[j] = src[0]; py[j] = src[1]; pz[j] = src[2];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const u32 i = ii[j];
+        const bool in = inn[j];
         // this lane's contribution; a lane without a valid point gets a key no point has
         u64 key = kEmpty - 1 - (u64)lane;
         u64 so = 0, sq0 = 0, sq1 = 0, sq2 = 0;
         u32 cnt = 0;
         float pw[3] = {0.f, 0.f, 0.f};
         if (in) {
-            const float x = J.pts[3 * (size_t)i], y = J.pts[3 * (size_t)i + 1], z = J.pts[3 * (size_t)i + 2];
+            const float x = px[j], y = py[j], z = pz[j];
             float q[3];
             const int c = classify_point(M, J.pose, x, y, z, q);
             if (c == 1) {
@@ -374,10 +395,24 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                 atomicAdd(&s_n[h], cnt);
                 s_idx[h] = i;     // read only when the group has a single point: then it is this one
             } else {
-                o_has[j] = true;
-                o_key[j] = key; o_so[j] = so; o_sq[j][0] = sq0; o_sq[j][1] = sq1; o_sq[j][2] = sq2;
-                o_n[j] = cnt;
-                o_p[j][0] = pw[0]; o_p[j][1] = pw[1]; o_p[j][2] = pw[2];
+                // the table is full: the run is written now, from the back of the tile's range,
+                // and enters the block set alone
+                Partial P;
+                P.so = so;
+                P.n = cnt;
+                if (cnt == 1) {
+                    int g1[3];
+                    u32 Q1[3];
+                    u64 om1;
+                    group_terms(M, pw, 1.0f, g1, Q1, om1);
+                    pack_single(pw, Q1, P.sq);
+                } else {
+                    P.sq[0] = sq0; P.sq[1] = sq1; P.sq[2] = sq2;
+                }
+                P.h = tset_insert(tkeys, tmask, mapbits | (key >> 12), tlist, tlist_cap, cs);
+                P.lj = jm12 | (u32)(key & 4095u);
+                P.pad = 0;
+                tparts[kTileGrouped - 1 - atomicAdd(&s_cnt[3], 1u)] = P;
             }
         }
     }
@@ -386,7 +421,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     if (n_oob) atomicAdd(&s_cnt[2], n_oob);
     __syncthreads();
 
-    // this thread's records: its table slot, then its overflow runs
+    // this thread's record: its table slot
     const int k = threadIdx.x;
     const u64 skey = s_key[k];
     const bool has_slot = skey != kEmpty;
@@ -394,91 +429,53 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     // a one-point group carries its point: load it now, so that the load overlaps the block phase
     float sx = 0.f, sy = 0.f, sz = 0.f;
     if (has_slot && sn == 1) {
-        const size_t i1 = s_idx[k];
-        sx = J.pts[3 * i1];
-        sy = J.pts[3 * i1 + 1];
-        sz = J.pts[3 * i1 + 2];
+        const gfloat* src = (const gfloat*)J.pts + 3 * (size_t)s_idx[k];
+        sx = src[0]; sy = src[1]; sz = src[2];
     }
-    const u64 mapbits = (u64)M.map_id << 45;
     // distinct blocks of the records; a block that finds the block table full resolves alone
-    u32 bh_rec[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};   // block table slot, or direct
-    bool direct[3] = {false, false, false};
-    u64 rec_bk[3] = {0, 0, 0};
-    bool rec_on[3] = {has_slot, o_has[0], o_has[1]};
-    rec_bk[0] = mapbits | (skey >> 12);
-    rec_bk[1] = mapbits | (o_key[0] >> 12);
-    rec_bk[2] = mapbits | (o_key[1] >> 12);
-    u32 mine = 0;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        if (!rec_on[r]) continue;
-        mine++;
-        const u64 bk = rec_bk[r];
+    const u64 bk = mapbits | (skey >> 12);
+    u32 bh = 0xFFFFFFFFu;   // block table slot
+    if (has_slot) {
         u32 b = (u32)mix64(bk) & (kTileBlocks - 1);
         for (int probe = 0; probe < kTileBlocks; ++probe) {
             const u64 old = atomicCAS(&s_bkey[b], kEmpty, bk);
-            if (old == kEmpty || old == bk) { bh_rec[r] = b; break; }
+            if (old == kEmpty || old == bk) { bh = b; break; }
             b = (b + 1) & (kTileBlocks - 1);
         }
-        direct[r] = bh_rec[r] == 0xFFFFFFFFu;
     }
-    // partials of tile k take slots [k * kTileGrouped, k * kTileGrouped + count): a tile has at
-    // most kTileGrouped points, so the slots never overlap and no counter is shared
+    const bool direct = has_slot && bh == 0xFFFFFFFFu;
+    // table records of tile k take slots [k * kTileGrouped, k * kTileGrouped + count): a tile has
+    // at most kTileGrouped points, so the slots never overlap and no counter is shared
     u32 tot;
+    const u32 mine = has_slot ? 1u : 0u;
     const u32 incl = block_scan_256(mine, lds8, &tot);
-    if (threadIdx.x == 0) tile_parts[blockIdx.x] = tot;
     if (threadIdx.x < kTileBlocks) {
-        const u64 bk = s_bkey[threadIdx.x];
-        if (bk != kEmpty) s_bh[threadIdx.x] = tset_insert(tkeys, tmask, bk, tlist, tlist_cap, cs);
+        const u64 tb = s_bkey[threadIdx.x];
+        if (tb != kEmpty) s_bh[threadIdx.x] = tset_insert(tkeys, tmask, tb, tlist, tlist_cap, cs);
     }
-    u32 hdirect[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-        if (rec_on[r] && direct[r]) hdirect[r] = tset_insert(tkeys, tmask, rec_bk[r], tlist, tlist_cap, cs);
+    const u32 hdirect = direct ? tset_insert(tkeys, tmask, bk, tlist, tlist_cap, cs) : 0xFFFFFFFFu;
     __syncthreads();
-    size_t pos = (size_t)blockIdx.x * kTileGrouped + incl - mine;
-    const u32 jm12 = J.jm << 12;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        if (!rec_on[r]) continue;
+    if (threadIdx.x == 0) tile_parts[blockIdx.x] = tot | (s_cnt[3] << 16);
+    if (has_slot) {
         Partial P;
-        u64 key;
-        if (r == 0) {
-            key = skey;
-            P.so = s_so[k];
-            P.n = sn;
-            if (sn == 1) {
-                // the same transform and Q_k as when the point was grouped
-                float p1[3];
-                (void)classify_point(M, J.pose, sx, sy, sz, p1);
-                int g1[3];
-                u32 Q1[3];
-                u64 om1;
-                group_terms(M, p1, 1.0f, g1, Q1, om1);
-                pack_single(p1, Q1, P.sq);
-            } else {
-                P.sq[0] = s_sq[0][k]; P.sq[1] = s_sq[1][k]; P.sq[2] = s_sq[2][k];
-            }
+        P.so = s_so[k];
+        P.n = sn;
+        if (sn == 1) {
+            // the same transform and Q_k as when the point was grouped
+            float p1[3];
+            (void)classify_point(M, J.pose, sx, sy, sz, p1);
+            int g1[3];
+            u32 Q1[3];
+            u64 om1;
+            group_terms(M, p1, 1.0f, g1, Q1, om1);
+            pack_single(p1, Q1, P.sq);
         } else {
-            const int j = r - 1;
-            key = o_key[j];
-            P.so = o_so[j];
-            P.n = o_n[j];
-            if (o_n[j] == 1) {
-                int g1[3];
-                u32 Q1[3];
-                u64 om1;
-                group_terms(M, o_p[j], 1.0f, g1, Q1, om1);
-                pack_single(o_p[j], Q1, P.sq);
-            } else {
-                P.sq[0] = o_sq[j][0]; P.sq[1] = o_sq[j][1]; P.sq[2] = o_sq[j][2];
-            }
+            P.sq[0] = s_sq[0][k]; P.sq[1] = s_sq[1][k]; P.sq[2] = s_sq[2][k];
         }
-        P.h = direct[r] ? hdirect[r] : s_bh[bh_rec[r]];
-        P.lj = jm12 | (u32)(key & 4095u);
+        P.h = direct ? hdirect : s_bh[bh];
+        P.lj = jm12 | (u32)(skey & 4095u);
         P.pad = 0;
-        parts[pos] = P;
-        pos++;
+        tparts[incl - 1] = P;
     }
     if (threadIdx.x == 0) {
         if (s_cnt[0]) atomicAdd(&jst[jid].valid, (u64)s_cnt[0]);
@@ -497,6 +494,12 @@ __global__ __launch_bounds__(256) void k_densify(const u32* __restrict__ tlist, 
 
 // Grouped raycasting, step 2: counting sort of the partial groups by (block, frame).  One
 // wave per tile walks the tile's partials.
+
+// Position of a tile's i-th record, i < np: nf records at the front of its range, the other
+// np - nf at the back.
+__device__ inline u32 tile_record(u32 i, u32 nf, u32 np) {
+    return i < nf ? i : (u32)kTileGrouped - np + i;
+}
 __global__ __launch_bounds__(256) void k_gbin_count(const Partial* __restrict__ parts,
                                                     const u32* __restrict__ tile_parts, u32 ntiles,
                                                     const u32* __restrict__ tval,
@@ -506,13 +509,13 @@ __global__ __launch_bounds__(256) void k_gbin_count(const Partial* __restrict__ 
     const u32 tile = blockIdx.x * 4u + (threadIdx.x >> 6);
     if (tile >= ntiles) return;   // whole wave
     const int lane = lane_id();
-    const u32 np = tile_parts[tile];
+    const u32 tp_n = tile_parts[tile], nf = tp_n & 0xFFFFu, np = nf + (tp_n >> 16);
     const Partial* tp = parts + (size_t)tile * kTileGrouped;
     for (u32 b0 = 0; b0 < np; b0 += 64) {
-        const u32 i = b0 + (u32)lane;
+        const u32 i = tile_record(b0 + (u32)lane, nf, np);
         u32 b = 0;
-        if (i < np) b = tval[tp[i].h] * JM + (tp[i].lj >> 12);
-        wave_count_by_key(bins, i < np, b);
+        if (b0 + (u32)lane < np) b = tval[tp[i].h] * JM + (tp[i].lj >> 12);
+        wave_count_by_key(bins, b0 + (u32)lane < np, b);
     }
 }
 
@@ -526,15 +529,14 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
     const u32 tile = blockIdx.x * 4u + (threadIdx.x >> 6);
     if (tile >= ntiles) return;   // whole wave
     const int lane = lane_id();
-    const u32 np = tile_parts[tile];
+    const u32 tp_n = tile_parts[tile], nf = tp_n & 0xFFFFu, np = nf + (tp_n >> 16);
     const Partial* tp = parts + (size_t)tile * kTileGrouped;
     for (u32 b0 = 0; b0 < np; b0 += 64) {
-        const u32 i = b0 + (u32)lane;
-        const bool act = i < np;
+        const bool act = b0 + (u32)lane < np;
         u32 b = 0;
         Partial P;
         if (act) {
-            P = tp[i];
+            P = tp[tile_record(b0 + (u32)lane, nf, np)];
             b = tval[P.h] * JM + (P.lj >> 12);
         }
         u64 pending = __ballot(act);
