@@ -71,6 +71,34 @@ __device__ inline u32 block_scan_256(u32 x, u32* lds8, u32* tot) {
     return v + add;
 }
 
+// Inclusive count of the flagged threads of a 256-thread workgroup (ballots; lds4 holds four
+// words); *tot = all flagged threads.
+__device__ inline u32 block_count_256(bool flag, u32* lds4, u32* tot) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const u64 b = __ballot(flag);
+    const u32 below = __builtin_amdgcn_mbcnt_hi((u32)(b >> 32), __builtin_amdgcn_mbcnt_lo((u32)b, 0u));
+    if (lane == 0) lds4[wave] = (u32)__popcll(b);
+    __syncthreads();
+    u32 add = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const u32 s = lds4[w];
+        if (w < wave) add += s;
+        total += s;
+    }
+    __syncthreads();
+    *tot = total;
+    return add + below + (flag ? 1u : 0u);
+}
+
+// Slot of a key in a small LDS table of 2^BITS slots: the top bits of a 32-bit multiplicative
+// hash of the key's two halves.
+template <int BITS>
+__device__ inline u32 lds_slot(u64 key) {
+    const u32 x = (u32)key ^ ((u32)(key >> 32) * 0x85EBCA6Bu);
+    return (x * 0x9E3779B1u) >> (32 - BITS);
+}
+
 // Inclusive prefix sum over a workgroup of NT threads (NT a multiple of 64, at most 1024);
 // lds needs NT / 64 entries.  Returns the inclusive value, the total in *tot.
 template <int NT>
@@ -304,7 +332,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     const u64 mapbits = (u64)M.map_id << 45;
     const u32 jm12 = J.jm << 12;
     Partial* const tparts = parts + (size_t)blockIdx.x * kTileGrouped;
-    u32 n_valid = 0, n_inv = 0, n_oob = 0;
+    u32 n_valid = 0, n_inv = 0, n_oob = 0;   // per wave (from ballots)
     // both points of this thread are loaded before either is processed; a lane past the end
     // of the frame loads its first point (a frame with a tile has one) and ignores it
     u32 ii[2];
@@ -333,54 +361,50 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         // this lane's contribution; a lane without a valid point gets a key no point has
         u64 key = kEmpty - 1 - (u64)lane;
         u64 so = 0, sq0 = 0, sq1 = 0, sq2 = 0;
-        u32 cnt = 0;
         float pw[3] = {0.f, 0.f, 0.f};
-        if (in) {
-            const float x = px[j], y = py[j], z = pz[j];
-            float q[3];
-            const int c = classify_point(M, J.pose, x, y, z, q);
-            if (c == 1) {
-                n_valid++;
-                int g[3];
-                u32 Q[3];
-                u64 om;
-                group_terms(M, q, z, g, Q, om);
-                key = voxel_key_of(g[0], g[1], g[2]);
-                so = om;
-                sq0 = om * Q[0];
-                sq1 = om * Q[1];
-                sq2 = om * Q[2];
-                cnt = 1;
-                pw[0] = q[0]; pw[1] = q[1]; pw[2] = q[2];
-            } else if (c == 0) {
-                n_inv++;
-            } else {
-                n_oob++;
-            }
+        int c = -1;
+        if (in) c = classify_point(M, J.pose, px[j], py[j], pz[j], pw);
+        if (c == 1) {
+            int g[3];
+            u32 Q[3];
+            u64 om;
+            group_terms(M, pw, pz[j], g, Q, om);
+            key = voxel_key_of(g[0], g[1], g[2]);
+            so = om;
+            sq0 = om * Q[0];
+            sq1 = om * Q[1];
+            sq2 = om * Q[2];
         }
+        n_valid += (u32)__popcll(__ballot(c == 1));
+        n_inv += (u32)__popcll(__ballot(c == 0));
+        n_oob += (u32)__popcll(__ballot(c == 2));
         // Neighbouring pixels mostly share a voxel: runs of equal keys within each row of 16
         // lanes are summed first (segmented scan over DPP row shifts; integer sums, exact), so
-        // only the last lane of a run enters the tile's table.
+        // only the last lane of a run enters the tile's table.  A run holds valid points only
+        // (every other lane has a key of its own); its first lane is a head, found by ballot,
+        // and at the step of shift N a lane adds the partial sum N lanes below when that lane
+        // lies in its run (its position in the run is at least N).
         // cross-lane reads run with every lane active (never inside a short-circuit condition)
         const u64 prev_key = row_shr64<1>(key);
         const bool head0 = r16 == 0 || prev_key != key;
-        bool head = head0;
+        const u64 heads = __ballot(head0);
+        const u64 upto = heads & ((2ull << lane) - 1ull);     // heads at or below this lane
+        const u32 runpos = (u32)lane - (u32)(63 - __clzll((long long)upto));
 #define VBX_SEG_STEP(N)                                                                        \
         {                                                                                      \
             const u64 a_so = row_shr64<N>(so), a0 = row_shr64<N>(sq0), a1 = row_shr64<N>(sq1),  \
                       a2 = row_shr64<N>(sq2);                                                  \
-            const u32 a_n = row_shr<N>(cnt), a_h = row_shr<N>((u32)head);                      \
-            if (r16 >= N && !head) {                                                           \
-                so += a_so; sq0 += a0; sq1 += a1; sq2 += a2; cnt += a_n;                       \
+            if (runpos >= N) {                                                                 \
+                so += a_so; sq0 += a0; sq1 += a1; sq2 += a2;                                   \
             }                                                                                  \
-            if (r16 >= N) head = head || a_h != 0;                                             \
         }
         VBX_SEG_STEP(1) VBX_SEG_STEP(2) VBX_SEG_STEP(4) VBX_SEG_STEP(8)
 #undef VBX_SEG_STEP
         const u32 next_head = row_shl<1>((u32)head0);
         const bool tail = r16 == 15 || next_head != 0;
-        if (tail && cnt > 0) {
-            u32 h = (u32)mix64(key) & (kTileHash - 1);
+        const u32 cnt = runpos + 1;   // points of the run, at its last lane
+        if (tail && c == 1) {
+            u32 h = lds_slot<8>(key);
             bool placed = false;
             for (int probe = 0; probe < kTileHash; ++probe) {
                 const u64 old = atomicCAS(&s_key[h], kEmpty, key);
@@ -416,9 +440,11 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
             }
         }
     }
-    if (n_valid) atomicAdd(&s_cnt[0], n_valid);
-    if (n_inv) atomicAdd(&s_cnt[1], n_inv);
-    if (n_oob) atomicAdd(&s_cnt[2], n_oob);
+    if (lane == 0) {
+        if (n_valid) atomicAdd(&s_cnt[0], n_valid);
+        if (n_inv) atomicAdd(&s_cnt[1], n_inv);
+        if (n_oob) atomicAdd(&s_cnt[2], n_oob);
+    }
     __syncthreads();
 
     // this thread's record: its table slot
@@ -436,7 +462,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     const u64 bk = mapbits | (skey >> 12);
     u32 bh = 0xFFFFFFFFu;   // block table slot
     if (has_slot) {
-        u32 b = (u32)mix64(bk) & (kTileBlocks - 1);
+        u32 b = lds_slot<7>(bk);
         for (int probe = 0; probe < kTileBlocks; ++probe) {
             const u64 old = atomicCAS(&s_bkey[b], kEmpty, bk);
             if (old == kEmpty || old == bk) { bh = b; break; }
@@ -447,8 +473,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     // table records of tile k take slots [k * kTileGrouped, k * kTileGrouped + count): a tile has
     // at most kTileGrouped points, so the slots never overlap and no counter is shared
     u32 tot;
-    const u32 mine = has_slot ? 1u : 0u;
-    const u32 incl = block_scan_256(mine, lds8, &tot);
+    const u32 incl = block_count_256(has_slot, lds8, &tot);
     if (threadIdx.x < kTileBlocks) {
         const u64 tb = s_bkey[threadIdx.x];
         if (tb != kEmpty) s_bh[threadIdx.x] = tset_insert(tkeys, tmask, tb, tlist, tlist_cap, cs);
