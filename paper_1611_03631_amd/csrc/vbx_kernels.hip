@@ -71,6 +71,18 @@ __device__ inline u32 block_scan_256(u32 x, u32* lds8, u32* tot) {
     return v + add;
 }
 
+// Sum and OR over the 64 lanes of a wave (every lane active).
+__device__ inline u32 wave_sum(u32 x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += (u32)__shfl_xor((int)x, o);
+    return x;
+}
+__device__ inline u32 wave_or(u32 x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= (u32)__shfl_xor((int)x, o);
+    return x;
+}
+
 // Inclusive count of the flagged threads of a 256-thread workgroup (ballots; lds4 holds four
 // words); *tot = all flagged threads.
 __device__ inline u32 block_count_256(bool flag, u32* lds4, u32* tot) {
@@ -208,27 +220,29 @@ __global__ __launch_bounds__(256) void k_points_simple(const Job* __restrict__ j
         const u32 i = first + threadIdx.x + 256u * j;
         const size_t slot = (size_t)blockIdx.x * kTileSimple + threadIdx.x + 256u * j;
         u32 job = kNoRay;
+        int c = -1;
         if (i < J.n) {
             const float x = J.pts[3 * (size_t)i], y = J.pts[3 * (size_t)i + 1], z = J.pts[3 * (size_t)i + 2];
             float q[3];
-            const int c = classify_point(M, J.pose, x, y, z, q);
+            c = classify_point(M, J.pose, x, y, z, q);
             if (c == 1) {
                 // per-point weight: Eq. (2) 1, or the 1/z^2 factor of Eq. (5)
                 const float wgt = M.weighting == 1 ? 1.0f / (z * z) : 1.0f;
                 rays_p[slot] = make_float4(q[0], q[1], q[2], wgt);
                 job = (u32)jid;
-                n_valid++;
-            } else if (c == 0) {
-                n_inv++;
-            } else {
-                n_oob++;
             }
         }
         rays_job[slot] = job;
+        // per wave, from ballots
+        n_valid += (u32)__popcll(__ballot(c == 1));
+        n_inv += (u32)__popcll(__ballot(c == 0));
+        n_oob += (u32)__popcll(__ballot(c == 2));
     }
-    if (n_valid) atomicAdd(&s_cnt[0], n_valid);
-    if (n_inv) atomicAdd(&s_cnt[1], n_inv);
-    if (n_oob) atomicAdd(&s_cnt[2], n_oob);
+    if (lane_id() == 0) {
+        if (n_valid) atomicAdd(&s_cnt[0], n_valid);
+        if (n_inv) atomicAdd(&s_cnt[1], n_inv);
+        if (n_oob) atomicAdd(&s_cnt[2], n_oob);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         if (s_cnt[0]) { atomicAdd(&jst[jid].valid, (u64)s_cnt[0]); atomicAdd(&jst[jid].rays, (u64)s_cnt[0]); }
@@ -718,7 +732,8 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 __syncthreads();
                 u32 qm = 0;
                 for (u32 e = lo + threadIdx.x; e < hi; e += 256) qm |= 1u << ((sorted[e].lj & 4095u) / kMergeVox);
-                if (qm) atomicOr(&s_passes, qm);
+                qm = wave_or(qm);
+                if (lane_id() == 0 && qm) atomicOr(&s_passes, qm);
                 __syncthreads();
                 const u32 passes = s_passes;
                 u32 nrays = 0;
@@ -1441,13 +1456,18 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
         }
 #pragma unroll
         for (int j = 0; j < VPT; ++j) store_voxel<STORAGE>(pool, vbase + block_local(threadIdx.x + NT * j), D[j], W[j]);
-        if (stat_vox) {
+        {
+            // summed over the wave first: one lane adds (an atomic on one address with a
+            // different value per lane is otherwise carried out lane by lane)
             u32 cells = 0;
 #pragma unroll
             for (int j = 0; j < VPT; ++j) cells += ntot[j] ? 1u : 0u;
-            atomicAdd(&s_stat[0], stat_vox);
-            atomicAdd(&s_stat[1], stat_touch);
-            atomicAdd(&s_stat[2], cells);
+            const u32 wv = wave_sum(stat_vox), wt = wave_sum(stat_touch), wc = wave_sum(cells);
+            if (lane_id() == 0 && wv) {
+                atomicAdd(&s_stat[0], wv);
+                atomicAdd(&s_stat[1], wt);
+                atomicAdd(&s_stat[2], wc);
+            }
         }
         if (keep_touches) {
             u32 mine = 0;
