@@ -245,18 +245,21 @@ __device__ inline void walk_setup_vox(const float A[3], const float B[3], Walk& 
 // to the lowest axis.
 // (Constant indices only, so the walk state stays in registers.)
 __device__ inline void walk_step(Walk& w) {
-    int axis = -1;
-    float best = 0.0f;
-    if (w.n[0] > 0) { axis = 0; best = w.tM[0]; }
-    if (w.n[1] > 0 && (axis < 0 || w.tM[1] < best)) { axis = 1; best = w.tM[1]; }
-    if (w.n[2] > 0 && (axis < 0 || w.tM[2] < best)) { axis = 2; }
+    // the axis with steps left whose next boundary comes first (ties: the lowest axis), chosen
+    // with selects rather than branches, so that the lanes of a wave never diverge here
+    const bool c0 = w.n[0] > 0, c1 = w.n[1] > 0, c2 = w.n[2] > 0;
+    const bool t1 = c1 && (!c0 || w.tM[1] < w.tM[0]);
+    const float best = t1 ? w.tM[1] : w.tM[0];
+    const bool t2 = c2 && ((!c0 && !t1) || w.tM[2] < best);
     // an axis is always found: the caller only steps while w.left > 0
-    if (axis == 0) {
-        w.g[0] += w.step[0]; w.n[0] -= 1; w.tM[0] = w.tM[0] + w.tD[0];
-    } else if (axis == 1) {
-        w.g[1] += w.step[1]; w.n[1] -= 1; w.tM[1] = w.tM[1] + w.tD[1];
-    } else {
-        w.g[2] += w.step[2]; w.n[2] -= 1; w.tM[2] = w.tM[2] + w.tD[2];
+    const int axis = t2 ? 2 : (t1 ? 1 : 0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const bool s = axis == k;
+        const float next = w.tM[k] + w.tD[k];
+        w.g[k] += s ? w.step[k] : 0;
+        w.n[k] -= s ? 1 : 0;
+        w.tM[k] = s ? next : w.tM[k];
     }
     w.left -= 1;
 }
@@ -286,8 +289,10 @@ __device__ inline Obs observe(const MapDesc& M, const float p[3], const float e[
     }
     Obs o;
     float fdrop = 1.0f;
-    if (M.weighting == 1)
-        fdrop = d > -M.eps ? 1.0f : (d > -M.delta ? (d + M.delta) * M.ramp : 0.0f);
+    if (M.weighting == 1) {
+        const float ramp = (d + M.delta) * M.ramp;   // selected below, not branched on
+        fdrop = d > -M.eps ? 1.0f : (d > -M.delta ? ramp : 0.0f);
+    }
     o.w = wgt * fdrop;
     float dc = d < -M.delta ? -M.delta : (d > M.delta ? M.delta : d);
     o.e = dc * M.inv_delta;

@@ -1409,8 +1409,10 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                             const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
                             const u64 fw = (u64)__builtin_rintf(o.w * M.wscale);
                             const i64 fd = (i64)__builtin_rintf(o.w * o.e * M.wscale);
-                            if (fw) atomicAdd(&a_w[l], fw);
-                            if (fd) atomicAdd(&a_d[l], (u64)fd);
+                            // issued unconditionally: a wave issues an LDS atomic once for
+                            // all its lanes, and adding zero is harmless
+                            atomicAdd(&a_w[l], fw);
+                            atomicAdd(&a_d[l], (u64)fd);
                             atomicAdd(&a_n[l], 1u);
                         } else if (inside) {
                             break;   // the walk is monotone per axis: it never re-enters the region
