@@ -856,18 +856,18 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
 constexpr int kCrossSlots = 2048;   // LDS block-key set (at most 256 rays x 7 blocks)
 
 __device__ inline u32 lds_set_insert(u64* keys, u64 key) {
-    u32 h = (u32)mix64(key) & (kCrossSlots - 1);
+    static_assert(kCrossSlots == 2048, "slot hash bits");
+    u32 h = lds_slot<11>(key);
     for (;;) {
         const u64 old = atomicCAS(&keys[h], kEmpty, key);
         if (old == kEmpty || old == key) return h;
         h = (h + 1) & (kCrossSlots - 1);
     }
 }
-__device__ inline u32 lds_set_find(const u64* keys, u64 key) {
-    u32 h = (u32)mix64(key) & (kCrossSlots - 1);
-    while (keys[h] != key) h = (h + 1) & (kCrossSlots - 1);
-    return h;
-}
+
+// A ray crosses at most 7 blocks (the band is at most 28 voxels long): the LDS set slots of
+// its blocks, 16 bits each, fit two 64-bit registers.
+constexpr u32 kCrossHeld = 8;
 
 __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                                                const MapDesc* __restrict__ maps,
@@ -889,6 +889,8 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
         u32 jid = 0;
         float p[3] = {0.f, 0.f, 0.f}, s[3] = {0.f, 0.f, 0.f};
         u64 mapbits = 0;
+        u64 held0 = 0, held1 = 0;   // LDS set slots of the crossed blocks, in crossing order
+        u32 nc = 0;
         const MapDesc* Mp = maps;
         if (i < nrays) {
             jid = rays_job[i];
@@ -911,7 +913,10 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                     const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
                     if (bk != cur) {
                         cur = bk;
-                        lds_set_insert(s_key, mapbits | bk);
+                        const u32 h = lds_set_insert(s_key, mapbits | bk);
+                        if (nc < 4) held0 |= (u64)h << (16 * nc);
+                        else if (nc < kCrossHeld) held1 |= (u64)h << (16 * (nc - 4));
+                        nc++;
                     }
                     if (w.left == 0) break;
                     walk_step(w);
@@ -927,24 +932,12 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
         __syncthreads();
         // phase 3: crossing c of ray slot i goes to cross[i * MB + c]
         if (i < nrays) {
-            u32 nc = 0;
-            if (ok) {
-                float e[3], r;
-                Walk w;
-                walk_setup(*Mp, p, s, e, r, w);
-                u64 cur = kEmpty;
-                for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
-                    const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
-                    if (bk != cur) {
-                        cur = bk;
-                        if (nc < MB) cross[(size_t)i * MB + nc] = s_h[lds_set_find(s_key, mapbits | bk)];
-                        nc++;
-                    }
-                    if (w.left == 0) break;
-                    walk_step(w);
-                }
-                if (nc > MB) { cs->error = -4; nc = MB; }   // cannot happen: MB bounds the band
+            if (nc > MB || nc > kCrossHeld) {   // cannot happen: MB bounds the band
+                cs->error = -4;
+                nc = 0;
             }
+            for (u32 c = 0; c < nc; ++c)
+                cross[(size_t)i * MB + c] = s_h[(u32)((c < 4 ? held0 : held1) >> (16 * (c & 3))) & 0xFFFFu];
             ncross[i] = (unsigned char)nc;
         }
         // out-of-bounds rays per frame (rare); rays were counted when created
