@@ -280,7 +280,8 @@ int ensure_scratch(Scratch* s, hipStream_t st, const CallPlan& plan, int njobs, 
     if (cross_cap > 0xFFFFFFF0ull || ray_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
     const size_t tlist_cap = std::min<size_t>(std::max<size_t>(sum_capacity + 4096, 4096), cross_cap + 4096);
     const size_t tkey_cap = next_pow2(2 * tlist_cap);
-    const size_t bins_cap = tlist_cap * (size_t)plan.JM;
+    // grouped calls sort partial groups into kGroupSubBins bins per (block, frame)
+    const size_t bins_cap = tlist_cap * (size_t)plan.JM * (plan.grouped ? (size_t)kGroupSubBins : 1u);
     if (bins_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
     const size_t nparts = (bins_cap + kScanChunkHost - 1) / kScanChunkHost;
     const size_t touch_cap =
@@ -603,14 +604,16 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     const u32 JM = (u32)plan.JM;
     const unsigned GT = grid_for(s->tlist_cap, 1024);
     const unsigned NP = (unsigned)std::max<size_t>(s->nparts, 1);
-    auto scan_bins = [&]() {
-        hipLaunchKernelGGL(k_scan_sums, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, JM, (u32*)s->partial.p,
-                           (const CallState*)cs);
-        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, (u32*)s->partial.p, (u32)NP, (u32*)s->off.p, JM,
-                           (const CallState*)cs);
+    // exclusive scan of the t_count * per_block bin counts
+    auto scan_bins = [&](u32 per_block) {
+        hipLaunchKernelGGL(k_scan_sums, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, per_block,
+                           (u32*)s->partial.p, (const CallState*)cs);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, (u32*)s->partial.p, (u32)NP, (u32*)s->off.p,
+                           per_block, (const CallState*)cs);
         hipLaunchKernelGGL(k_scan_final, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, (const u32*)s->partial.p,
-                           (u32*)s->off.p, JM, (const CallState*)cs);
+                           (u32*)s->off.p, per_block, (const CallState*)cs);
     };
+    const u32 JMS = JM * (u32)kGroupSubBins;   // partial-group sort bins per block
     // points
     if (total_tiles > 0) {
         StageTimer tm(prof_map, st, ST_POINTS);
@@ -631,15 +634,15 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
         hipLaunchKernelGGL(k_gbin_count, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
                            (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p, JM,
                            (const CallState*)cs);
-        scan_bins();
+        scan_bins(JMS);
         hipLaunchKernelGGL(k_gscatter, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
                            (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p,
                            (const u32*)s->off.p, JM, (Partial*)s->parts_sorted.p, (const CallState*)cs);
         hipLaunchKernelGGL(k_chunk_first, dim3(grid_for(s->bins_cap + 1, 1024)), dim3(256), 0, st,
-                           (const u32*)s->off.p, JM, (u32*)s->chunk_first.p, (const CallState*)cs);
+                           (const u32*)s->off.p, JMS, (u32*)s->chunk_first.p, (const CallState*)cs);
         hipLaunchKernelGGL(k_group_merge, dim3(group_merge_grid()), dim3(256), 0, st, d_jobs, d_maps,
                            (const u64*)s->tkeys.p, (const u32*)s->tlist.p, (const u32*)s->off.p,
-                           (const u32*)s->chunk_first.p, (const Partial*)s->parts_sorted.p, JM, rays_p,
+                           (const u32*)s->chunk_first.p, (const Partial*)s->parts_sorted.p, JMS, rays_p,
                            rays_job, jst, cs);
     }
     const unsigned G = grid_for(plan.ray_slots, 2048);
@@ -667,7 +670,7 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     }
     {
     StageTimer tm(prof_map, st, ST_SCAN);
-    scan_bins();
+    scan_bins(JM);
     }
     {
     StageTimer tm(prof_map, st, ST_SCATTER);

@@ -20,6 +20,9 @@ typedef unsigned int u32;
 
 constexpr u64 kEmpty = ~0ull;
 constexpr int kMergeSpan = 256;    // grouped raycasting: sorted partial groups per merge work chunk
+// Grouped raycasting sorts partial groups by (block, frame, eighth of the block's voxels): a
+// sort bin then spans at most 4096 / kGroupSubBins distinct voxels.
+constexpr int kGroupSubBins = 8;
 constexpr u32 kNoRay = 0xFFFFFFFFu;      // job of an empty ray slot
 constexpr int kVoxLimit = 1 << 18;     // |voxel index| < 2^18
 constexpr int kBlockBias = 1 << 14;    // block indices packed as 15-bit biased fields

@@ -534,6 +534,12 @@ __global__ __launch_bounds__(256) void k_densify(const u32* __restrict__ tlist, 
 // Grouped raycasting, step 2: counting sort of the partial groups by (block, frame).  One
 // wave per tile walks the tile's partials.
 
+// Sort bin of a partial group: (block t, frame, eighth of the block's voxels), JM frames per
+// block, so that a bin spans at most kMergeVox distinct voxels.
+__device__ inline u32 group_bin(u32 t, u32 lj, u32 JM) {
+    return (t * JM + (lj >> 12)) * (u32)kGroupSubBins + ((lj & 4095u) >> 9);
+}
+
 // Position of a tile's i-th record, i < np: nf records at the front of its range, the other
 // np - nf at the back.
 __device__ inline u32 tile_record(u32 i, u32 nf, u32 np) {
@@ -553,7 +559,7 @@ __global__ __launch_bounds__(256) void k_gbin_count(const Partial* __restrict__ 
     for (u32 b0 = 0; b0 < np; b0 += 64) {
         const u32 i = tile_record(b0 + (u32)lane, nf, np);
         u32 b = 0;
-        if (b0 + (u32)lane < np) b = tval[tp[i].h] * JM + (tp[i].lj >> 12);
+        if (b0 + (u32)lane < np) b = group_bin(tval[tp[i].h], tp[i].lj, JM);
         wave_count_by_key(bins, b0 + (u32)lane < np, b);
     }
 }
@@ -576,7 +582,7 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
         Partial P;
         if (act) {
             P = tp[tile_record(b0 + (u32)lane, nf, np)];
-            b = tval[P.h] * JM + (P.lj >> 12);
+            b = group_bin(tval[P.h], P.lj, JM);
         }
         u64 pending = __ballot(act);
         u32 pos = 0;
@@ -595,21 +601,21 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
     }
 }
 
-// Grouped raycasting, step 3: merging the partial groups of each (block, frame) bin by
-// voxel and casting one ray per group -- the exact weighted mean (a group of one point keeps
-// the point) with the group's summed weight.
+// Grouped raycasting, step 3: merging the partial groups of each sort bin (block, frame,
+// eighth of the block's voxels; JMS bins per block) by voxel and casting one ray per group --
+// the exact weighted mean (a group of one point keeps the point) with the group's summed weight.
 //
 // Work is cut into chunks of kMergeSpan consecutive sorted partials; a chunk owns the bins
 // whose first partial falls in it.  Consecutive bins of a chunk are merged together in one
 // LDS hash keyed by (bin in batch, local voxel) while they hold at most kMergeBatch partials;
-// a bin larger than that is merged alone over a dense voxel table, kMergeVox voxels per pass.
+// a bin larger than that is merged alone, in one pass over a dense table of its kMergeVox
+// voxels.
 // The rays of bin b take slots [off[b], off[b] + groups) and the rest of its range is marked
 // empty, so no counter is shared between workgroups.
 constexpr int kMergeVox = 2 * kMergeSpan;        // LDS table entries (hash slots or dense voxels)
 constexpr int kMergeBatch = kMergeSpan * 5 / 4;  // partials merged in one hash pass (load <= 0.625)
-constexpr int kMergePasses = 4096 / kMergeVox;   // dense passes over a block
 constexpr int kMergePerThread = kMergeVox / 256;
-static_assert(kMergePasses * kMergeVox == 4096 && kMergePerThread * 256 == kMergeVox, "merge table");
+static_assert(kGroupSubBins * kMergeVox == 4096 && kMergePerThread * 256 == kMergeVox, "merge table");
 
 // chunk_first[c] = first bin whose first partial lies at or after c * kMergeSpan.
 __global__ __launch_bounds__(256) void k_chunk_first(const u32* __restrict__ off, u32 JM,
@@ -673,7 +679,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                                                      const u32* __restrict__ tlist,
                                                      const u32* __restrict__ off,
                                                      const u32* __restrict__ chunk_first,
-                                                     const Partial* __restrict__ sorted, u32 JM,
+                                                     const Partial* __restrict__ sorted, u32 JMS,
                                                      float4* __restrict__ rays_p,
                                                      u32* __restrict__ rays_job,
                                                      JobStat* __restrict__ jst,
@@ -686,13 +692,12 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
     __shared__ float m_p[3][kMergeVox];   // the point of a one-point group
     __shared__ u32 s_nr[kMergeBatch];  // rays emitted per bin of the batch
     __shared__ u32 s_off[kMergeBatch + 2];
-    __shared__ u32 s_passes;
     __shared__ u32 lds8[4];
     for (int i = threadIdx.x; i < kMergeVox; i += 256) {
         m_key[i] = 0; m_so[i] = 0; m_sq[0][i] = 0; m_sq[1][i] = 0; m_sq[2][i] = 0;
         m_hi[0][i] = 0; m_hi[1][i] = 0; m_hi[2][i] = 0; m_n[i] = 0;
     }
-    const u32 nb = cs->error ? 0u : cs->t_count * JM;
+    const u32 nb = cs->error ? 0u : cs->t_count * JMS;
     const u32 total = nb ? off[nb] : 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) cs->ray_count = total;
     const u32 nchunks = (total + kMergeSpan - 1) / kMergeSpan;
@@ -720,63 +725,48 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 nbat = lo_n;
             }
             if (nbat == 0) {
-                // ---- a bin too large for one hash pass: dense passes over its voxels
+                // ---- a bin too large for one hash pass: its at most kMergeVox voxels (one
+                // eighth of the block) over a dense table
                 const u32 lo = s_off[0], hi = s_off[1];
-                const u32 t = b / JM, jm = b - t * JM;
+                const u32 t = b / JMS, rb = b - t * JMS;
+                const u32 jm = rb / (u32)kGroupSubBins, qd = rb % (u32)kGroupSubBins;
                 const u64 tk = tkeys[tlist[t]];
                 const MapDesc& M = maps[(u32)(tk >> 45)];
                 const int jid = M.job0 + (int)jm;
                 int bx, by, bz;
                 unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
-                if (threadIdx.x == 0) s_passes = 0;
+                for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
+                    const Partial& P = sorted[e];
+                    merge_partial(P, P.lj & (u32)(kMergeVox - 1), m_so, m_sq, m_hi, m_n, m_p);
+                }
                 __syncthreads();
-                u32 qm = 0;
-                for (u32 e = lo + threadIdx.x; e < hi; e += 256) qm |= 1u << ((sorted[e].lj & 4095u) / kMergeVox);
-                qm = wave_or(qm);
-                if (lane_id() == 0 && qm) atomicOr(&s_passes, qm);
-                __syncthreads();
-                const u32 passes = s_passes;
-                u32 nrays = 0;
-                for (int qd = 0; qd < kMergePasses; ++qd) {
-                    if (!(passes & (1u << qd))) continue;
-                    for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
-                        const Partial& P = sorted[e];
-                        const u32 l = P.lj & 4095u;
-                        if ((int)(l / kMergeVox) != qd) continue;
-                        const u32 v = l & (kMergeVox - 1);
-                        merge_partial(P, v, m_so, m_sq, m_hi, m_n, m_p);
-                    }
-                    __syncthreads();
-                    float4 ray[kMergePerThread];
-                    bool has[kMergePerThread];
-                    u32 nmine = 0;
+                float4 ray[kMergePerThread];
+                bool has[kMergePerThread];
+                u32 nmine = 0;
 #pragma unroll
-                    for (int r = 0; r < kMergePerThread; ++r) {
-                        const int v = threadIdx.x + 256 * r;
-                        const u32 n = m_n[v];
-                        has[r] = n != 0;
-                        ray[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-                        if (!n) continue;
-                        const u64 sq[3] = {m_sq[0][v], m_sq[1][v], m_sq[2][v]};
-                        const u32 hw[3] = {m_hi[0][v], m_hi[1][v], m_hi[2][v]};
-                        const float p1[3] = {m_p[0][v], m_p[1][v], m_p[2][v]};
-                        group_ray(M, bx, by, bz, (u32)(qd * kMergeVox + v), n, m_so[v], sq, hw, p1, ray[r]);
-                        nmine++;
-                        m_so[v] = 0; m_sq[0][v] = 0; m_sq[1][v] = 0; m_sq[2][v] = 0;
-                        m_hi[0][v] = 0; m_hi[1][v] = 0; m_hi[2][v] = 0; m_n[v] = 0;
-                    }
-                    u32 tot;
-                    const u32 incl = block_scan_256(nmine, lds8, &tot);
-                    u32 pos = lo + nrays + incl - nmine;
+                for (int r = 0; r < kMergePerThread; ++r) {
+                    const int v = threadIdx.x + 256 * r;
+                    const u32 n = m_n[v];
+                    has[r] = n != 0;
+                    ray[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (!n) continue;
+                    const u64 sq[3] = {m_sq[0][v], m_sq[1][v], m_sq[2][v]};
+                    const u32 hw[3] = {m_hi[0][v], m_hi[1][v], m_hi[2][v]};
+                    const float p1[3] = {m_p[0][v], m_p[1][v], m_p[2][v]};
+                    group_ray(M, bx, by, bz, qd * (u32)kMergeVox + (u32)v, n, m_so[v], sq, hw, p1, ray[r]);
+                    nmine++;
+                    m_so[v] = 0; m_sq[0][v] = 0; m_sq[1][v] = 0; m_sq[2][v] = 0;
+                    m_hi[0][v] = 0; m_hi[1][v] = 0; m_hi[2][v] = 0; m_n[v] = 0;
+                }
+                u32 nrays;
+                const u32 incl = block_scan_256(nmine, lds8, &nrays);
+                u32 pos = lo + incl - nmine;
 #pragma unroll
-                    for (int r = 0; r < kMergePerThread; ++r) {
-                        if (!has[r]) continue;
-                        rays_p[pos] = ray[r];
-                        rays_job[pos] = (u32)jid;
-                        pos++;
-                    }
-                    nrays += tot;
-                    __syncthreads();
+                for (int r = 0; r < kMergePerThread; ++r) {
+                    if (!has[r]) continue;
+                    rays_p[pos] = ray[r];
+                    rays_job[pos] = (u32)jid;
+                    pos++;
                 }
                 for (u32 e = lo + nrays + threadIdx.x; e < hi; e += 256) rays_job[e] = kNoRay;
                 if (threadIdx.x == 0 && nrays) atomicAdd(&jst[jid].rays, (u64)nrays);
@@ -811,7 +801,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 if (!key) continue;
                 const u32 bi = (key - 1u) >> 12, l = (key - 1u) & 4095u;
                 const u32 bb = b + bi;
-                const u32 t = bb / JM, jm = bb - t * JM;
+                const u32 t = bb / JMS, jm = (bb - t * JMS) / (u32)kGroupSubBins;
                 const u64 tk = tkeys[tlist[t]];
                 const MapDesc& M = maps[(u32)(tk >> 45)];
                 const int jid = M.job0 + (int)jm;
@@ -835,9 +825,9 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 for (u32 e = s_off[k] + nr; e < s_off[k + 1]; ++e) rays_job[e] = kNoRay;
                 if (nr) {
                     const u32 bb = b + k;
-                    const u32 t = bb / JM;
+                    const u32 t = bb / JMS;
                     const MapDesc& M = maps[(u32)(tkeys[tlist[t]] >> 45)];
-                    atomicAdd(&jst[M.job0 + (bb - t * JM)].rays, (u64)nr);
+                    atomicAdd(&jst[M.job0 + (bb - t * JMS) / (u32)kGroupSubBins].rays, (u64)nr);
                 }
             }
             __syncthreads();
