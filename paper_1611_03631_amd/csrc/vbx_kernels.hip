@@ -48,6 +48,32 @@ __device__ inline void wave_count_by_key(u32* base, bool active, u32 key) {
     }
 }
 
+// Counting-sort positions for the active lanes of a wave: lanes with equal keys take
+// consecutive positions below their bin's remaining count, reserved by one atomic per distinct
+// key.  The groups are found first (ballots only) and every group's atomic is then issued by
+// one instruction, so a wave waits for one atomic round trip rather than one per key.
+__device__ inline u32 wave_claim_by_key(u32* bins, const u32* off, bool active, u32 key) {
+    const int lane = lane_id();
+    u64 pending = __ballot(active);
+    u32 leader_of = 0, rank = 0, count = 0;
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const u32 kb = __shfl(key, leader);
+        const bool mine = ((pending >> lane) & 1ull) && key == kb;
+        const u64 grp = __ballot(mine);
+        if (mine) {
+            leader_of = (u32)leader;
+            rank = (u32)__popcll(grp & ((1ull << lane) - 1ull));
+        }
+        if (lane == leader) count = (u32)__popcll(grp);
+        pending &= ~grp;
+    }
+    u32 old = 0;
+    if (count) old = atomicSub(&bins[key], count);   // the leaders, together
+    const u32 base = (u32)__shfl((int)old, (int)leader_of);
+    return active ? off[key] + base - 1u - rank : 0u;
+}
+
 // Inclusive prefix sum over a 256-thread workgroup; returns the inclusive value, total in *tot.
 __device__ inline u32 block_scan_256(u32 x, u32* lds8, u32* tot) {
     const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -584,19 +610,7 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
             P = tp[tile_record(b0 + (u32)lane, nf, np)];
             b = group_bin(tval[P.h], P.lj, JM);
         }
-        u64 pending = __ballot(act);
-        u32 pos = 0;
-        while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const u32 kb = __shfl(b, leader);
-            const bool mine = ((pending >> lane) & 1ull) && b == kb;
-            const u64 grp = __ballot(mine);
-            u32 old = 0;
-            if (lane == leader) old = atomicSub(&bins[kb], (u32)__popcll(grp));
-            old = __shfl(old, leader);
-            if (mine) pos = off[kb] + old - 1u - (u32)__popcll(grp & ((1ull << lane) - 1ull));
-            pending &= ~grp;
-        }
+        const u32 pos = wave_claim_by_key(bins, off, act, b);
         if (act) sorted[pos] = P;
     }
 }
@@ -1179,7 +1193,6 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ jobs,
                                                  float4* __restrict__ sorted,
                                                  CallState* __restrict__ cs, u32 ray_cap) {
     const u32 nr = cs->error ? 0u : (cs->ray_count < ray_cap ? cs->ray_count : ray_cap);
-    const int lane = lane_id();
     for (u32 base = blockIdx.x * 256u; base < nr; base += gridDim.x * 256u) {
         const u32 i = base + threadIdx.x;
         u32 nc = 0, jm = 0;
@@ -1196,19 +1209,7 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ jobs,
             const bool act = c < nc;
             const u32 b = act ? tval[cross[(size_t)i * MB + c]] * JM + jm : 0u;
             // lanes sharing a bin take consecutive positions reserved by one atomic
-            u64 pending = __ballot(act);
-            u32 pos = 0;
-            while (pending) {
-                const int leader = __ffsll((long long)pending) - 1;
-                const u32 kb = __shfl(b, leader);
-                const bool mine = ((pending >> lane) & 1ull) && b == kb;
-                const u64 grp = __ballot(mine);
-                u32 old = 0;
-                if (lane == leader) old = atomicSub(&bins[kb], (u32)__popcll(grp));
-                old = __shfl(old, leader);
-                if (mine) pos = off[kb] + old - 1u - (u32)__popcll(grp & ((1ull << lane) - 1ull));
-                pending &= ~grp;
-            }
+            const u32 pos = wave_claim_by_key(bins, off, act, b);
             if (act) sorted[pos] = rp;
         }
     }
@@ -1343,21 +1344,25 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
             int jm = 0;
             while (jm < wn && s_off[jm] == s_off[jm + 1]) ++jm;
             float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+            float nxs[3] = {0.f, 0.f, 0.f};   // that frame's sensor origin, also loaded ahead
             if (jm < wn) {
                 const u32 e = s_off[jm] + threadIdx.x;
                 if (e < s_off[jm + 1]) nxt = sorted[e];
+                const Job& Jn = jobs[M.job0 + w0 + jm];
+                nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
             }
             while (jm < wn) {
                 int jn = jm + 1;
                 while (jn < wn && s_off[jn] == s_off[jn + 1]) ++jn;
                 const float4 cur = nxt;
+                const float s[3] = {nxs[0], nxs[1], nxs[2]};
                 const u32 lo = s_off[jm], hi = s_off[jm + 1];
                 if (jn < wn) {
                     const u32 e = s_off[jn] + threadIdx.x;
                     if (e < s_off[jn + 1]) nxt = sorted[e];
+                    const Job& Jn = jobs[M.job0 + w0 + jn];
+                    nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
                 }
-                const Job& J = jobs[M.job0 + w0 + jm];
-                const float s[3] = {J.pose[3], J.pose[7], J.pose[11]};
                 float4 rp = cur;
                 for (u32 e = lo + threadIdx.x; e < hi; e += NT) {
                     // the next ray's load is in flight while this one is walked
