@@ -563,7 +563,7 @@ __global__ __launch_bounds__(256) void k_densify(const u32* __restrict__ tlist, 
 // Sort bin of a partial group: (block t, frame, eighth of the block's voxels), JM frames per
 // block, so that a bin spans at most kMergeVox distinct voxels.
 __device__ inline u32 group_bin(u32 t, u32 lj, u32 JM) {
-    return (t * JM + (lj >> 12)) * (u32)kGroupSubBins + ((lj & 4095u) >> 9);
+    return (t * JM + (lj >> 12)) * (u32)kGroupSubBins + (lj & 4095u) / (4096u / (u32)kGroupSubBins);
 }
 
 // Position of a tile's i-th record, i < np: nf records at the front of its range, the other
