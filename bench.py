@@ -51,9 +51,10 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(stage: str, sha: str):
+def read_traffic(stage: str, sha: str, workload: str, tuning=None):
     """HBM bytes per launch of `stage` from committed rocprofv3 counter runs, if they were taken
-    on the current kernel sources (otherwise None)."""
+    on the current kernel sources, on this workload and (where the file names one) with the
+    same update variant (otherwise None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{stage}.txt")
     if not os.path.exists(path):
         return None
@@ -62,16 +63,23 @@ def read_traffic(stage: str, sha: str):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha") != sha:
+    if kv.get("source_sha") != sha or kv.get("workload") != workload:
         return None
+    if "update_tuning" in kv:
+        if tuning is None:
+            return None
+        if kv["update_tuning"] != f"{tuning['update_split']},{tuning['update_threads']},{tuning['update_columns']}":
+            return None
     try:
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def stage_roofline(prof, algo, steps):
-    """Roofline of the dominant stage among those with an algorithmic byte figure."""
+def stage_roofline(prof, algo, steps, workload, tuning=None):
+    """Roofline of the dominant stage among those with an algorithmic byte figure; `workload`
+    (and the update variant `tuning`) select the counter runs that may supply the measured
+    traffic."""
     dom = max(algo, key=lambda k: prof[k][0])
     ms_r, launches_r = prof[dom]
     per_launch_bytes = algo[dom] * steps / max(launches_r, 1)
@@ -79,7 +87,7 @@ def stage_roofline(prof, algo, steps):
     achieved = per_launch_bytes / avg_launch_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": read_traffic(dom, kernel_source_sha()),
+            "traffic": read_traffic(dom, kernel_source_sha(), workload, tuning),
             "kernel_stage": dom, "launches_per_step": launches_r / steps,
             "avg_launch_ms": round(ms_r / max(launches_r, 1), 4),
             "algorithmic_bytes_per_launch": per_launch_bytes}
@@ -183,7 +191,7 @@ def bench_c2(args, np, torch, vbx, synth):
         "points": 12.0 * points_per_step + 48.0 * F,
         "update": 2.0 * s_v * st["cells"] + 4096.0 * s_v * st["new_blocks"],
     }
-    roofline = stage_roofline(prof, algo, args.steps)
+    roofline = stage_roofline(prof, algo, args.steps, w.name, m.tuning())
     whole = (algo["points"] + algo["update"]) / (ms_per_step / 1e3) / 1e9
     stages = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
 
@@ -384,7 +392,7 @@ def bench_c4(args, np, torch, vbx, synth):
                                                if abs(ws[m].params["voxel_size"] - v) < 1e-6)
                                  for v in synth.MULTI_VOXEL},
             "stage_ms_per_tick": {k: round(v[0] / n_prof, 4) for k, v in prof.items()},
-            "roofline": stage_roofline(prof, algo, n_prof),
+            "roofline": stage_roofline(prof, algo, n_prof, f"c4_multi_map_{storage}", maps[0].tuning()),
             "tuning": maps[0].tuning(), "autotune": tune}
         g.close()
         for mp in maps:
@@ -550,7 +558,7 @@ def bench_c3(args, np, torch, vbx, synth):
         "repeat_bit_identical": True,
         "tuning": tuning,
         "autotune": tune,
-        "roofline": stage_roofline(prof, algo, args.steps),
+        "roofline": stage_roofline(prof, algo, args.steps, w.name, tuning),
         "cpu_baseline": cpu,
         "input_generation_s": round(gen_s, 1),
         "kernel_source_sha": kernel_source_sha(),
