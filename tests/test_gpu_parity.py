@@ -157,6 +157,40 @@ def test_grouped_tiles_with_more_voxels_than_their_table(vbx, width):
 
 
 
+def test_grouped_large_bins_merge_in_one_dense_pass(vbx):
+    """Every 512-point tile holds the same 256 voxels of one two-voxel z-slab of one block (two
+    points each), so that slab's sort bin gets 16 x 256 partial groups: far more than one LDS
+    hash batch, merged over the dense table of its 512 voxels.  A second frame, shifted by half
+    a voxel, makes each tile span two blocks and two slabs."""
+    rng = np.random.default_rng(1611036310 + 91)
+    v = 0.05
+    ij = np.stack(np.meshgrid(np.arange(16), np.arange(16), indexing="ij"), -1).reshape(-1, 2)
+    pts = np.empty((8192, 3), np.float32)
+    for t in range(16):                        # tile t: each of the 256 voxels twice
+        blk = np.concatenate([ij, ij])[rng.permutation(512)]
+        jit = rng.uniform(0.1, 0.9, size=(512, 3))
+        pts[512 * t:512 * (t + 1), 0] = (blk[:, 0] + jit[:, 0]) * v
+        pts[512 * t:512 * (t + 1), 1] = (blk[:, 1] + jit[:, 1]) * v
+        pts[512 * t:512 * (t + 1), 2] = (20 + jit[:, 2]) * v          # voxel z 20: block 1, local z 4
+    pose = np.eye(3, 4, dtype=np.float32)
+    pose2 = pose.copy()
+    pose2[:, 3] = [0.5 * v, 0.5 * v, 0.5 * v]
+    params = dict(voxel_size=v, trunc=3 * v, weighting="quad", merge="grouped", max_range=10.0)
+    frames = [(pts, pose), (pts, pose2)]      # one call each: touches compare the second frame
+    g, o = run_both(vbx, params, frames)
+    compare_touches(g.last_touches(), o.last_touches())
+    res = compare_export(g.export(), o.export(), params)
+    st = g.stats()
+    log(f"large bins: rays {st['rays']}, {res}")
+    # one ray per distinct binary32 voxel key of each frame (identity rotation: the world point
+    # is the sensor point plus the translation, in binary32 as on the device)
+    iv = np.float32(1.0) / np.float32(v)
+    groups = [np.unique(np.floor((pts + q[:, 3]).astype(np.float32) * iv), axis=0).shape[0]
+              for q in (pose, pose2)]
+    assert groups[0] == 256
+    assert st["rays"] == sum(groups)
+
+
 def test_empty_and_invalid_frames(vbx):
     params = dict(voxel_size=0.1, trunc=0.3, weighting="quad", merge="grouped")
     g = gpu_map(vbx, params)
