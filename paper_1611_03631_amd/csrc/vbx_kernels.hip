@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     __shared__ u64 s_so[kTileHash];
     __shared__ u64 s_sq[3][kTileHash];
     __shared__ u32 s_n[kTileHash];
-    __shared__ u32 s_idx[kTileHash];        // the point of a one-point group
+    __shared__ float s_pt[3][kTileHash];    // the world point of a one-point group
     __shared__ u64 s_bkey[kTileBlocks];     // distinct (map, block) keys of the tile
     __shared__ u32 s_bh[kTileBlocks];       // their block-set slots
     __shared__ u32 s_cnt[4];
@@ -396,7 +396,6 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const u32 i = ii[j];
         const bool in = inn[j];
         // this lane's contribution; a lane without a valid point gets a key no point has
         u64 key = kEmpty - 1 - (u64)lane;
@@ -457,7 +456,8 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                 atomicAdd(&s_sq[1][h], sq1);
                 atomicAdd(&s_sq[2][h], sq2);
                 atomicAdd(&s_n[h], cnt);
-                s_idx[h] = i;     // read only when the group has a single point: then it is this one
+                // read only when the group has a single point: then it is this one
+                s_pt[0][h] = pw[0]; s_pt[1][h] = pw[1]; s_pt[2][h] = pw[2];
             } else {
                 // the table is full: the run is written now, from the back of the tile's range,
                 // and enters the block set alone
@@ -492,12 +492,6 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     const u64 skey = s_key[k];
     const bool has_slot = skey != kEmpty;
     const u32 sn = has_slot ? s_n[k] : 0u;
-    // a one-point group carries its point: load it now, so that the load overlaps the block phase
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-    if (has_slot && sn == 1) {
-        const gfloat* src = (const gfloat*)J.pts + 3 * (size_t)s_idx[k];
-        sx = src[0]; sy = src[1]; sz = src[2];
-    }
     // distinct blocks of the records; a block that finds the block table full resolves alone
     const u64 bk = mapbits | (skey >> 12);
     u32 bh = 0xFFFFFFFFu;   // block table slot
@@ -526,9 +520,8 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         P.so = s_so[k];
         P.n = sn;
         if (sn == 1) {
-            // the same transform and Q_k as when the point was grouped
-            float p1[3];
-            (void)classify_point(M, J.pose, sx, sy, sz, p1);
+            // the world point as it was grouped, and its Q_k
+            const float p1[3] = {s_pt[0][k], s_pt[1][k], s_pt[2][k]};
             int g1[3];
             u32 Q1[3];
             u64 om1;
