@@ -305,13 +305,27 @@ __device__ inline void group_terms(const MapDesc& M, const float q[3], float z, 
 
 // Inserts a (map, block) key into the per-call block set; returns its slot (0xFFFFFFFF and a
 // call error when the set is full).
+template <bool CHECK_FIRST>
 __device__ inline u32 tset_insert(u64* tkeys, u32 tmask, u64 key, u32* tlist, u32 tlist_cap,
                                   CallState* cs) {
     u32 h = (u32)mix64(key) & tmask;
     for (u32 probe = 0; probe <= tmask; ++probe) {
-        // always the atomic: a plain read may return a line cached before the slot was
-        // cleaned by the previous call, which would let one key enter two slots
-        u64 old = atomicCAS(&tkeys[h], kEmpty, key);
+        // CHECK_FIRST: a key never leaves its slot during a call, so a slot already holding it
+        // needs no read-modify-write.  Where nearly every workgroup enters the same few blocks
+        // (those next to a sensor), this avoids compare-and-swaps on one address, which are
+        // carried out one after another; elsewhere the extra round trip costs more.  The check
+        // is a device-coherent atomic load: a plain read may return a line cached before the
+        // slot was cleaned by the previous call, which would let one key enter two slots.
+        u64 old;
+        if (CHECK_FIRST) {
+            old = __hip_atomic_load(&tkeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (old == key) return h;
+            if (old != kEmpty) {
+                h = (h + 1) & tmask;
+                continue;
+            }
+        }
+        old = atomicCAS(&tkeys[h], kEmpty, key);
         if (old == kEmpty) {
             u32 t = atomicAdd(&cs->t_count, 1u);
             if (t < tlist_cap) { tlist[t] = h; return h; }
@@ -473,7 +487,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                 } else {
                     P.sq[0] = sq0; P.sq[1] = sq1; P.sq[2] = sq2;
                 }
-                P.h = tset_insert(tkeys, tmask, mapbits | (key >> 12), tlist, tlist_cap, cs);
+                P.h = tset_insert<false>(tkeys, tmask, mapbits | (key >> 12), tlist, tlist_cap, cs);
                 P.lj = jm12 | (u32)(key & 4095u);
                 P.pad = 0;
                 tparts[kTileGrouped - 1 - atomicAdd(&s_cnt[3], 1u)] = P;
@@ -510,9 +524,9 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     const u32 incl = block_count_256(has_slot, lds8, &tot);
     if (threadIdx.x < kTileBlocks) {
         const u64 tb = s_bkey[threadIdx.x];
-        if (tb != kEmpty) s_bh[threadIdx.x] = tset_insert(tkeys, tmask, tb, tlist, tlist_cap, cs);
+        if (tb != kEmpty) s_bh[threadIdx.x] = tset_insert<false>(tkeys, tmask, tb, tlist, tlist_cap, cs);
     }
-    const u32 hdirect = direct ? tset_insert(tkeys, tmask, bk, tlist, tlist_cap, cs) : 0xFFFFFFFFu;
+    const u32 hdirect = direct ? tset_insert<false>(tkeys, tmask, bk, tlist, tlist_cap, cs) : 0xFFFFFFFFu;
     __syncthreads();
     if (threadIdx.x == 0) tile_parts[blockIdx.x] = tot | (s_cnt[3] << 16);
     if (has_slot) {
@@ -924,7 +938,7 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
         // phase 2: each distinct block of the workgroup enters the per-call block set once
         for (int k = threadIdx.x; k < kCrossSlots; k += 256) {
             const u64 key = s_key[k];
-            if (key != kEmpty) s_h[k] = tset_insert(tkeys, tmask, key, tlist, tlist_cap, cs);
+            if (key != kEmpty) s_h[k] = tset_insert<true>(tkeys, tmask, key, tlist, tlist_cap, cs);
         }
         __syncthreads();
         // phase 3: crossing c of ray slot i goes to cross[i * MB + c]
