@@ -93,6 +93,23 @@ def stage_roofline(prof, algo, steps, workload, tuning=None):
             "algorithmic_bytes_per_launch": per_launch_bytes}
 
 
+ALGO_STAGES = ("points", "update")   # stages with an algorithmic byte figure
+BREAKDOWN_STEPS = 3
+
+
+def stage_breakdown(m, step, candidates):
+    """Per-stage times of a few untimed steps with every stage profiled, and the slowest of
+    `candidates`.  Each profiled stage adds two event records per call, which cost the
+    stream several microseconds each, so the timed steps afterwards profile only that stage."""
+    m.profile(True)
+    m.profile_read(reset=True)
+    for _ in range(BREAKDOWN_STEPS):
+        step()
+    prof = m.profile_read(reset=True)
+    m.profile(False)
+    return prof, max(candidates, key=lambda k: prof[k][0])
+
+
 def oracle_sample(w_list, budget_s):
     """Integrates frames of the given workloads in order with the single-threaded C oracle
     until the time budget is spent; returns (points, seconds, frames done)."""
@@ -155,7 +172,8 @@ def bench_c2(args, np, torch, vbx, synth):
     for _ in range(max(args.warmup - 1, 0)):
         step()
     assert m.sync() == 0
-    m.profile(True)
+    prof_all, dom = stage_breakdown(m, step, ALGO_STAGES)
+    m.profile(True, stages=[dom])
     m.profile_read(reset=True)
 
     # ---------------------------------------------------------------- timed
@@ -177,7 +195,7 @@ def bench_c2(args, np, torch, vbx, synth):
     if not (np.array_equal(first_export[0], last_export[0]) and
             np.array_equal(first_export[1], last_export[1])):
         raise RuntimeError("the last timed step did not reproduce the first step's map bit-for-bit")
-    prof = m.profile_read(reset=True)
+    prof = m.profile_read(reset=True)    # the dominant stage only, timed live
     m.profile(False)
     st = m.stats()           # the map was cleared before the last step: one step's counts
     ms_per_step = ms_total / args.steps
@@ -193,7 +211,7 @@ def bench_c2(args, np, torch, vbx, synth):
     }
     roofline = stage_roofline(prof, algo, args.steps, w.name, m.tuning())
     whole = (algo["points"] + algo["update"]) / (ms_per_step / 1e3) / 1e9
-    stages = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
+    stages = {k: round(v[0] / BREAKDOWN_STEPS, 4) for k, v in prof_all.items()}
 
     # ---------------------------------------------------------------- forms compared on this GPU
     def timed(fn, reps):
@@ -507,7 +525,8 @@ def bench_c3(args, np, torch, vbx, synth):
     out_b = b.export()
     if not (np.array_equal(out_b[0], ref[0]) and np.array_equal(out_b[1], ref[1])):
         raise RuntimeError("batched sweeps and streamed sweeps built different maps")
-    b.profile(True)
+    prof_all, dom = stage_breakdown(b, step, ALGO_STAGES)
+    b.profile(True, stages=[dom])
     b.profile_read(reset=True)
     torch.cuda.synchronize()
     e0.record(stream)
@@ -554,7 +573,7 @@ def bench_c3(args, np, torch, vbx, synth):
                      "rehashes": rehash, "initial_capacity": C3_INITIAL_CAPACITY, "final_capacity": cap,
                      "points_per_s": round(S * N / (stream_ms / 1e3), 1),
                      "blocks": st_stream["blocks"]},
-        "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
+        "stage_ms_per_step": {k: round(v[0] / BREAKDOWN_STEPS, 4) for k, v in prof_all.items()},
         "repeat_bit_identical": True,
         "tuning": tuning,
         "autotune": tune,

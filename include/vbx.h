@@ -235,6 +235,12 @@ typedef struct {
 int vbx_map_profile(vbx_map* map, int enable);
 int vbx_map_profile_read(vbx_map* map, vbx_profile* out, int reset);
 
+/* Per-stage timing of only the stages in stage_mask (bit i: stage i; 0 disables timing).
+ * Every timed stage adds two event records to the stream, and each record costs the stream
+ * a few microseconds, so a caller timing whole calls profiles as few stages as it needs.
+ * INVALID_ARG for bits at or above VBX_PROFILE_STAGES. */
+int vbx_map_profile_stages(vbx_map* map, uint32_t stage_mask);
+
 /* Name of profile stage i (static string), NULL when out of range. */
 const char* vbx_profile_stage_name(int stage);
 

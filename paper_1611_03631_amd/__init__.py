@@ -64,7 +64,7 @@ EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_ma
             "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
             "vbx_map_stats", "vbx_debug_traverse", "vbx_status_string", "vbx_map_clear",
-            "vbx_map_profile", "vbx_map_profile_read", "vbx_profile_stage_name",
+            "vbx_map_profile", "vbx_map_profile_read", "vbx_map_profile_stages", "vbx_profile_stage_name",
             "vbx_map_get_tuning", "vbx_map_set_tuning", "vbx_map_autotune",
             "vbx_graph_create", "vbx_graph_launch", "vbx_graph_destroy",
             "vbx_server_clock", "vbx_server_create", "vbx_server_add_map", "vbx_server_submit",
@@ -140,6 +140,7 @@ def lib(path: Optional[str] = None):
     L.vbx_status_string.restype = ctypes.c_char_p
     L.vbx_map_clear.argtypes = [vp]
     L.vbx_map_profile.argtypes = [vp, i32]
+    L.vbx_map_profile_stages.argtypes = [vp, u32]
     L.vbx_map_profile_read.argtypes = [vp, ctypes.POINTER(Profile), i32]
     L.vbx_map_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.vbx_map_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
@@ -333,8 +334,18 @@ class Map:
         """Removes every block (stream-ordered)."""
         _check(lib().vbx_map_clear(self._h), "vbx_map_clear")
 
-    def profile(self, enable: bool = True):
-        _check(lib().vbx_map_profile(self._h, 1 if enable else 0), "vbx_map_profile")
+    def profile(self, enable: bool = True, stages=None):
+        """Per-stage event timing of this map's calls: every stage, none, or only the named
+        stages (each timed stage costs its calls two event records)."""
+        L = lib()
+        if stages is None:
+            _check(L.vbx_map_profile(self._h, 1 if enable else 0), "vbx_map_profile")
+            return
+        names = [L.vbx_profile_stage_name(i).decode() for i in range(PROFILE_STAGES)]
+        mask = 0
+        for st in stages:
+            mask |= 1 << names.index(st)
+        _check(L.vbx_map_profile_stages(self._h, mask if enable else 0), "vbx_map_profile_stages")
 
     def profile_read(self, reset: bool = True) -> dict:
         """{stage: (milliseconds, launches)} summed since the last reset (synchronises)."""

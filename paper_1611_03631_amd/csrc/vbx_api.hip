@@ -72,7 +72,7 @@ struct Profiler {
         int stage;
         hipEvent_t a, b;
     };
-    bool on = false;
+    u32 mask = 0;   // stages whose launches are timed (bit i: stage i)
     std::vector<hipEvent_t> spare;
     std::vector<Rec> pending;
     double ms[VBX_PROFILE_STAGES] = {};
@@ -450,7 +450,7 @@ struct StageTimer {
     int stage;
     hipEvent_t a = nullptr;
     StageTimer(vbx_map* m_, hipStream_t s_, int stage_) : m(m_), st(s_), stage(stage_) {
-        if (m && m->prof.on && (a = m->prof.take())) (void)hipEventRecord(a, st);
+        if (m && ((m->prof.mask >> stage) & 1u) && (a = m->prof.take())) (void)hipEventRecord(a, st);
     }
     ~StageTimer() {
         if (!a) return;
@@ -1340,7 +1340,13 @@ int vbx_map_clear(vbx_map* m) {
 
 int vbx_map_profile(vbx_map* m, int enable) {
     if (!m) return VBX_ERR_INVALID_ARG;
-    m->prof.on = enable != 0;
+    m->prof.mask = enable != 0 ? (1u << VBX_PROFILE_STAGES) - 1u : 0u;
+    return VBX_OK;
+}
+
+int vbx_map_profile_stages(vbx_map* m, uint32_t stage_mask) {
+    if (!m || (stage_mask >> VBX_PROFILE_STAGES) != 0) return VBX_ERR_INVALID_ARG;
+    m->prof.mask = stage_mask;
     return VBX_OK;
 }
 

@@ -153,6 +153,30 @@ def test_profile_records_every_stage(vbx):
         assert prof[stage][1] >= 1 and prof[stage][0] > 0, stage
 
 
+def test_profile_of_selected_stages_only(vbx):
+    """Timing only some stages records only those, leaves results unchanged, and a mask with a
+    bit past the last stage is refused."""
+    frames = room(160, 120, 2, 62)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped")
+    a = gpu_map(vbx, params)
+    b = gpu_map(vbx, params)
+    a.profile(True, stages=["update", "points"])
+    for m in (a, b):
+        m.integrate_frames([(dev(p), pose, 160) for p, pose in frames])
+    prof = a.profile_read()
+    for stage, (ms, launches) in prof.items():
+        if stage in ("update", "points"):
+            assert launches == 1 and ms > 0, stage
+        else:
+            assert launches == 0 and ms == 0.0, stage
+    assert same_export(a, b)
+    L = vbx.lib()
+    assert L.vbx_map_profile_stages(a.handle, 1 << vbx.PROFILE_STAGES) == vbx.ERR_INVALID_ARG
+    a.profile(False)
+    a.integrate_frames([(dev(p), pose, 160) for p, pose in frames])
+    assert all(v[1] == 0 for v in a.profile_read().values())
+
+
 def test_full_sequence_640x480x100_bench_configuration(vbx):
     """The benchmark workload at full size, in the launch configuration the benchmark times
     (one call over all 100 organised frames), against the oracle integrating frame by frame."""
