@@ -607,9 +607,7 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     // exclusive scan of the t_count * per_block bin counts
     auto scan_bins = [&](u32 per_block) {
         hipLaunchKernelGGL(k_scan_sums, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, per_block,
-                           (u32*)s->partial.p, (const CallState*)cs);
-        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, (u32*)s->partial.p, (u32)NP, (u32*)s->off.p,
-                           per_block, (const CallState*)cs);
+                           (u32*)s->partial.p, (u32*)s->off.p, cs);
         hipLaunchKernelGGL(k_scan_final, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, (const u32*)s->partial.p,
                            (u32*)s->off.p, per_block, (const CallState*)cs);
     };

@@ -43,8 +43,7 @@ __global__ void k_commit(const MapDesc* maps, const u64* t_key, int* t_slot, Cal
 __global__ void k_bin_count(const Job* jobs, const u32* cross, const unsigned char* ncross,
                             u32 MB, const u32* tval, const u32* rays_job, u32* bins, u32 JM,
                             CallState* cs, u32 ray_cap);
-__global__ void k_scan_sums(const u32* bins, u32 JM, u32* partial, const CallState* cs);
-__global__ void k_scan_partials(u32* partial, u32 nparts, u32* off, u32 JM, const CallState* cs);
+__global__ void k_scan_sums(const u32* bins, u32 JM, u32* partial, u32* off, CallState* cs);
 __global__ void k_scan_final(const u32* bins, const u32* partial, u32* off, u32 JM,
                              const CallState* cs);
 __global__ void k_scatter(const Job* jobs, const u32* cross, const unsigned char* ncross,

@@ -77,7 +77,8 @@ struct CallState {
     u32 touch_count;
     int error;         // call-wide error (scratch overflow)
     u32 work_merge;    // persistent work counter of the group merge kernel
-    u32 pad0, pad1;
+    u32 scan_done;     // workgroups of the current scan that have written their sum
+    u32 pad1;
 };
 
 // Partial group of one tile (48 bytes): exact integer sums of the tile's points in one voxel.

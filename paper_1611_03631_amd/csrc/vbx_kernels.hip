@@ -103,6 +103,11 @@ __device__ inline u32 wave_sum(u32 x) {
     for (int o = 32; o > 0; o >>= 1) x += (u32)__shfl_xor((int)x, o);
     return x;
 }
+__device__ inline u64 wave_sum64(u64 x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += (u64)__shfl_xor((long long)x, o);
+    return x;
+}
 __device__ inline u32 wave_or(u32 x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x |= (u32)__shfl_xor((int)x, o);
@@ -1123,31 +1128,41 @@ __global__ __launch_bounds__(256) void k_bin_count(const Job* __restrict__ jobs,
 // Exclusive scan of bins[0, n) with n = t_count * JM, in chunks of 4096 (16 per thread).
 constexpr int kScanChunk = 4096;
 
+// Sums of the scan chunks.  The grid is sized for the largest possible count; only the
+// workgroups of chunks that hold bins take part.  The last of them to finish (counted in
+// cs->scan_done, which it then clears for the next scan) turns the sums into exclusive chunk
+// offsets and writes the total at off[n]: no workgroup waits for another.
 __global__ __launch_bounds__(256) void k_scan_sums(const u32* __restrict__ bins, u32 JM,
-                                                   u32* __restrict__ partial,
-                                                   const CallState* __restrict__ cs) {
+                                                   u32* __restrict__ partial, u32* __restrict__ off,
+                                                   CallState* __restrict__ cs) {
     __shared__ u32 lds8[4];
+    __shared__ bool s_last;
     const u32 n = cs->error ? 0u : cs->t_count * JM;
+    const u32 nparts = gridDim.x;
+    const u32 used_all = (n + kScanChunk - 1) / kScanChunk;
+    const u32 used = used_all < nparts ? used_all : nparts;
+    if (blockIdx.x >= used) {   // whole workgroup
+        if (used == 0 && blockIdx.x == 0 && threadIdx.x == 0) off[n] = 0;
+        return;
+    }
     const u32 base = blockIdx.x * (u32)kScanChunk;
     u32 s = 0;
-    if (base < n) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const u32 i = base + threadIdx.x * 16u + j;
-            if (i < n) s += bins[i];
-        }
+    for (int j = 0; j < 16; ++j) {
+        const u32 i = base + threadIdx.x * 16u + j;
+        if (i < n) s += bins[i];
     }
     u32 tot;
     block_scan_256(s, lds8, &tot);
-    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(256) void k_scan_partials(u32* __restrict__ partial, u32 nparts,
-                                                       u32* __restrict__ off, u32 JM,
-                                                       const CallState* __restrict__ cs) {
-    __shared__ u32 lds8[4];
-    const u32 n = cs->error ? 0u : cs->t_count * JM;
-    const u32 used = (n + kScanChunk - 1) / kScanChunk;
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = tot;
+        __threadfence();   // the sum is visible device-wide before the count says so
+        s_last = atomicAdd(&cs->scan_done, 1u) == used - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;   // whole workgroup
+    __threadfence();       // every other workgroup's sum is visible from here on
+    if (threadIdx.x == 0) cs->scan_done = 0;
     u32 carry = 0;
     for (u32 b = 0; b < used && b < nparts; b += 256) {
         const u32 i = b + threadIdx.x;
@@ -1603,9 +1618,12 @@ __global__ __launch_bounds__(256) void k_finish(const Job* __restrict__ jobs,
             a[6] += s.voxels;
             a[7] += s.cells;
         }
+        // summed over the wave first (ok is the same for the whole workgroup): one lane adds
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (a[k]) atomicAdd(&s_acc[k], a[k]);
+        for (int k = 0; k < 8; ++k) {
+            const u64 t = wave_sum64(a[k]);
+            if (lane_id() == 0 && t) atomicAdd(&s_acc[k], t);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1639,6 +1657,7 @@ __global__ void k_reset_call(CallState* __restrict__ cs) {
         cs->t_count = 0;
         cs->work_next = 0;
         cs->work_merge = 0;
+        cs->scan_done = 0;
         cs->error = 0;
     }
 }
