@@ -317,7 +317,9 @@ int ensure_scratch(Scratch* s, hipStream_t st, const CallPlan& plan, int njobs, 
     GROW(s->t_slot, tlist_cap * sizeof(int));
     GROW(s->order, tlist_cap * sizeof(u32));
     if ((r = grow(s->bins, (bins_cap + 1) * sizeof(u32))) < 0) return VBX_ERR_OUT_OF_MEMORY;
-    if (r == 1) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(bins_cap + 1)), dim3(256), 0, st, (u32*)s->bins.p, 0u, bins_cap + 1);
+    if (r == 1)
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(bins_cap + 1)), dim3(256), 0, st, (u32*)s->bins.p, 0u,
+                           bins_cap + 1);
     GROW(s->off, (bins_cap + 1) * sizeof(u32));
     GROW(s->partial, (nparts + 1) * sizeof(u32));
     if (plan.grouped) {
@@ -335,7 +337,9 @@ int ensure_scratch(Scratch* s, hipStream_t st, const CallPlan& plan, int njobs, 
     const size_t tables_bytes = (size_t)nmaps * sizeof(MapDesc) + (size_t)njobs * sizeof(Job);
     GROW(s->tables, tables_bytes);
     if ((r = grow(s->jst, (size_t)njobs * sizeof(JobStat))) < 0) return VBX_ERR_OUT_OF_MEMORY;
-    if (r == 1) hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(s->jst.bytes / 8)), dim3(256), 0, st, (u64*)s->jst.p, 0ull, s->jst.bytes / 8);
+    if (r == 1)
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(s->jst.bytes / 8)), dim3(256), 0, st, (u64*)s->jst.p, 0ull,
+                           s->jst.bytes / 8);
     if ((r = grow(s->cs, sizeof(CallState))) < 0) return VBX_ERR_OUT_OF_MEMORY;
     if (r == 1) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, (u32*)s->cs.p, 0u, sizeof(CallState) / 4);
 #undef GROW
@@ -407,7 +411,9 @@ template <int STORAGE>
 void launch_update_s(int variant, hipStream_t st, const Job* jobs, const MapDesc* maps, const u64* t_key,
                      const int* t_slot, const u32* off, const u32* order, const float4* sorted, u32 JM,
                      u64* touch_key, u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
-#define VBX_UPD(X, Y, Z, T) launch_update_t<STORAGE, X, Y, Z, T>(st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, touch_n, touch_cap, keep, jst, cs)
+#define VBX_UPD(X, Y, Z, T)                                                                        \
+    launch_update_t<STORAGE, X, Y, Z, T>(st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, \
+                                         touch_n, touch_cap, keep, jst, cs)
     switch (variant) {
         case 0: VBX_UPD(16, 16, 16, 256); break;
         case 2: VBX_UPD(16, 16, 4, 256); break;
