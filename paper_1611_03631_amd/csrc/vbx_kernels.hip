@@ -1315,21 +1315,28 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
     constexpr int NRX = 16 / RX, NRY = 16 / RY, NRZ = 16 / RZ;
     constexpr int NREG = NRX * NRY * NRZ;  // regions per block
     static_assert(VPT * NT == VOX && VPT >= 1, "region size must be a multiple of the workgroup");
-    // Frames are taken two at a time: each half of the workgroup walks one frame into its own
-    // pair of sums, then every voxel folds the earlier frame and then the later one.  A voxel's
-    // ray count over the call (a_c) grows by 1 per ray of the earlier frame and by 2^16 per ray of
-    // the later one, which splits exactly while each frame has fewer than 2^16 rays in the block;
-    // a frame with more is walked alone.
-    __shared__ u64 a_w[2][VOX];   // sum of fixed-point weights, per frame of the pair
-    __shared__ u64 a_d[2][VOX];   // sum of fixed-point weight * distance/delta (two's complement)
+    // With 1024-thread workgroups (which the thread limit already keeps to two per CU, so the
+    // second set of sums costs no occupancy) frames are taken two at a time: each half of the
+    // workgroup walks one frame into its own sums, then every voxel folds the earlier frame and
+    // then the later one.  A voxel's ray count over the call (a_c) grows by 1 per ray of the
+    // earlier frame and by 2^16 per ray of the later one, which splits exactly while each frame
+    // has fewer than 2^16 rays in the block; a frame with more is walked alone.  Smaller
+    // workgroups walk one frame at a time.
+    constexpr int K = NT == 1024 ? 2 : 1;
+    __shared__ u64 a_w[K][VOX];   // sum of fixed-point weights, per frame of the step
+    __shared__ u64 a_d[K][VOX];   // sum of fixed-point weight * distance/delta (two's complement)
     __shared__ u32 a_c[VOX];      // rays over the call (see above)
     __shared__ u32 s_off[kOffWindow + 1];
     __shared__ u32 s_t;
     __shared__ u32 s_stat[3];
     __shared__ u32 s_tbase;
     __shared__ u32 lds8[NT / 64];
-    static_assert(NT % 128 == 0, "each half of the workgroup is whole waves");
-    for (int i = threadIdx.x; i < VOX; i += NT) { a_w[0][i] = 0; a_d[0][i] = 0; a_w[1][i] = 0; a_d[1][i] = 0; }
+    static_assert(NT % (64 * K) == 0, "each half of the workgroup is whole waves");
+    for (int i = threadIdx.x; i < VOX; i += NT) {
+        a_c[i] = 0;
+#pragma unroll
+        for (int h = 0; h < K; ++h) { a_w[h][i] = 0; a_d[h][i] = 0; }
+    }
     const u32 nt = cs->error ? 0u : cs->t_count * (u32)NREG;
     for (;;) {
         if (threadIdx.x == 0) { s_t = atomicAdd(&cs->work_next, 1u); s_stat[0] = 0; s_stat[1] = 0; s_stat[2] = 0; }
@@ -1358,151 +1365,267 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
 #pragma unroll
         for (int j = 0; j < VPT; ++j) {
             ntot[j] = 0;
-            last[j] = 0;
-            a_c[threadIdx.x + NT * j] = 0;
+            if constexpr (K == 2) {   // one frame at a time leaves the counts cleared by its folds
+                last[j] = 0;
+                a_c[threadIdx.x + NT * j] = 0;
+            }
             if (is_new) { D[j] = 0.0f; W[j] = 0.0f; }
             else load_voxel<STORAGE>(pool, vbase + block_local(threadIdx.x + NT * j), D[j], W[j]);
         }
         const int ox = 16 * bx + qx * RX, oy = 16 * by + qy * RY, oz = 16 * bz + qz * RZ;
         u32 stat_vox = 0, stat_touch = 0;
-        for (int w0 = 0; w0 < M.njobs; w0 += kOffWindow) {
-            const int wn = M.njobs - w0 < kOffWindow ? M.njobs - w0 : kOffWindow;
-            for (int k = threadIdx.x; k <= wn; k += NT) s_off[k] = off[t * JM + (u32)(w0 + k)];
-            __syncthreads();
-            // Step plan from the window's offsets (the same in every thread): the step's first
-            // frame jm, the next frame with rays jn, whether the two are walked together, and this
-            // thread's frame, position and stride in that frame's rays.
-            auto next_frame = [&](int j) {
-                while (j < wn && s_off[j] == s_off[j + 1]) ++j;
-                return j;
-            };
-            struct Step {
-                int jm, jn, fr;
-                bool pair;
-                u32 pos, stride, cadd;
-                int half;
-            };
-            auto plan = [&](int jm) {
-                Step S;
-                S.jm = jm;
-                S.jn = jm < wn ? next_frame(jm + 1) : wn;
-                S.pair = S.jn < wn && s_off[jm + 1] - s_off[jm] < 65536u && s_off[S.jn + 1] - s_off[S.jn] < 65536u;
-                S.half = S.pair && (int)threadIdx.x >= NT / 2 ? 1 : 0;
-                S.fr = S.half ? S.jn : jm;
-                S.pos = S.half ? threadIdx.x - NT / 2 : threadIdx.x;
-                S.stride = S.pair ? NT / 2 : NT;
-                S.cadd = S.half ? 65536u : 1u;
-                return S;
-            };
-            // the first ray and sensor origin of every thread for the next step are loaded while
-            // the current step is processed
-            Step S = plan(next_frame(0));
-            float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
-            float nxs[3] = {0.f, 0.f, 0.f};
-            if (S.jm < wn) {
-                const u32 e = s_off[S.fr] + S.pos;
-                if (e < s_off[S.fr + 1]) nxt = sorted[e];
-                const Job& Jn = jobs[M.job0 + w0 + S.fr];
-                nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
-            }
-            while (S.jm < wn) {
-                const Step Sn = plan(next_frame(S.pair ? S.jn + 1 : S.jn));
-                const float4 cur = nxt;
-                const float s[3] = {nxs[0], nxs[1], nxs[2]};
-                const u32 lo = s_off[S.fr], hi = s_off[S.fr + 1];
-                if (Sn.jm < wn) {
-                    const u32 e = s_off[Sn.fr] + Sn.pos;
-                    if (e < s_off[Sn.fr + 1]) nxt = sorted[e];
-                    const Job& Jn = jobs[M.job0 + w0 + Sn.fr];
+        if constexpr (K == 2) {
+            for (int w0 = 0; w0 < M.njobs; w0 += kOffWindow) {
+                const int wn = M.njobs - w0 < kOffWindow ? M.njobs - w0 : kOffWindow;
+                for (int k = threadIdx.x; k <= wn; k += NT) s_off[k] = off[t * JM + (u32)(w0 + k)];
+                __syncthreads();
+                // Step plan from the window's offsets (the same in every thread): the step's first
+                // frame jm, the next frame with rays jn, whether the two are walked together, and this
+                // thread's frame, position and stride in that frame's rays.
+                auto next_frame = [&](int j) {
+                    while (j < wn && s_off[j] == s_off[j + 1]) ++j;
+                    return j;
+                };
+                struct Step {
+                    int jm, jn, fr;
+                    bool pair;
+                    u32 pos, stride, cadd;
+                    int half;
+                };
+                auto plan = [&](int jm) {
+                    Step S;
+                    S.jm = jm;
+                    S.jn = jm < wn ? next_frame(jm + 1) : wn;
+                    S.pair = K == 2 && S.jn < wn && s_off[jm + 1] - s_off[jm] < 65536u &&
+                             s_off[S.jn + 1] - s_off[S.jn] < 65536u;
+                    S.half = S.pair && (int)threadIdx.x >= NT / 2 ? 1 : 0;
+                    S.fr = S.half ? S.jn : jm;
+                    S.pos = S.half ? threadIdx.x - NT / 2 : threadIdx.x;
+                    S.stride = S.pair ? NT / 2 : NT;
+                    S.cadd = S.half ? 65536u : 1u;
+                    return S;
+                };
+                // the first ray and sensor origin of every thread for the next step are loaded while
+                // the current step is processed
+                Step S = plan(next_frame(0));
+                float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+                float nxs[3] = {0.f, 0.f, 0.f};
+                if (S.jm < wn) {
+                    const u32 e = s_off[S.fr] + S.pos;
+                    if (e < s_off[S.fr + 1]) nxt = sorted[e];
+                    const Job& Jn = jobs[M.job0 + w0 + S.fr];
                     nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
                 }
-                u64* const sw_buf = a_w[S.half];
-                u64* const sd_buf = a_d[S.half];
-                float4 rp = cur;
-                for (u32 e = lo + S.pos; e < hi; e += S.stride) {
-                    // the next ray's load is in flight while this one is walked
-                    float4 rn = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (e + S.stride < hi) rn = sorted[e + S.stride];
-                    const float p[3] = {rp.x, rp.y, rp.z};
-                    const float wgt = rp.w;
-                    rp = rn;
-                    float ev[3], r;
-                    Walk w;
-                    walk_setup(M, p, s, ev, r, w);
-                    if (NREG > 1) {
-                        // every walk index lies between its end voxels: skip bands that miss the region
-                        const int o3[3] = {ox, oy, oz};
-                        const int r3[3] = {RX, RY, RZ};
-                        bool miss = false;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            const int g_end = w.g[a] + w.step[a] * w.n[a];
-                            const int glo = w.g[a] < g_end ? w.g[a] : g_end;
-                            const int ghi = w.g[a] < g_end ? g_end : w.g[a];
-                            miss = miss || ghi < o3[a] || glo >= o3[a] + r3[a];
-                        }
-                        if (miss) continue;
+                while (S.jm < wn) {
+                    const Step Sn = plan(next_frame(S.pair ? S.jn + 1 : S.jn));
+                    const float4 cur = nxt;
+                    const float s[3] = {nxs[0], nxs[1], nxs[2]};
+                    const u32 lo = s_off[S.fr], hi = s_off[S.fr + 1];
+                    if (Sn.jm < wn) {
+                        const u32 e = s_off[Sn.fr] + Sn.pos;
+                        if (e < s_off[Sn.fr + 1]) nxt = sorted[e];
+                        const Job& Jn = jobs[M.job0 + w0 + Sn.fr];
+                        nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
                     }
-                    bool inside = false;
-                    for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
-                        const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
-                        if ((u32)lx < (u32)RX && (u32)ly < (u32)RY && (u32)lz < (u32)RZ) {
-                            inside = true;
-                            const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
-                            const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
-                            const u64 fw = (u64)__builtin_rintf(o.w * M.wscale);
-                            const i64 fd = (i64)__builtin_rintf(o.w * o.e * M.wscale);
-                            // issued unconditionally: a wave issues an LDS atomic once for
-                            // all its lanes, and adding zero is harmless
-                            atomicAdd(&sw_buf[l], fw);
-                            atomicAdd(&sd_buf[l], (u64)fd);
-                            atomicAdd(&a_c[l], S.cadd);
-                        } else if (inside) {
-                            break;   // the walk is monotone per axis: it never re-enters the region
-                        }
-                        if (w.left == 0) break;
-                        walk_step(w);
-                    }
-                }
-                __syncthreads();
-                // Eqs. (3)-(4), once per voxel for each frame of the step, in frame order
-#pragma unroll
-                for (int j = 0; j < VPT; ++j) {
-                    const int l = threadIdx.x + NT * j;
-                    const u32 c = a_c[l];
-                    const u32 d = c - last[j];
-                    last[j] = c;
-                    const u32 dn[2] = {S.pair ? (d & 0xFFFFu) : d, S.pair ? (d >> 16) : 0u};
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        if (!dn[h]) continue;
-                        const u64 sw_fx = a_w[h][l];
-                        if (sw_fx) {
-                            const float sw = (float)sw_fx * M.inv_wscale;
-                            // sums are in units of delta; binary32 storage keeps D in metres,
-                            // binary16 storage keeps D / delta
-                            float swd = (float)(i64)a_d[h][l] * M.inv_wscale;
-                            if (STORAGE == 0) swd = swd * M.delta;
-                            float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
-                            float Wn = W[j] + sw;
-                            if (Wn > M.w_max) Wn = M.w_max;
-                            if (STORAGE == 1) {
-                                Dn = __half2float(__float2half_rn(Dn));
-                                Wn = __half2float(__float2half_rn(Wn));
+                    u64* const sw_buf = a_w[K == 2 ? S.half : 0];
+                    u64* const sd_buf = a_d[K == 2 ? S.half : 0];
+                    float4 rp = cur;
+                    for (u32 e = lo + S.pos; e < hi; e += S.stride) {
+                        // the next ray's load is in flight while this one is walked
+                        float4 rn = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (e + S.stride < hi) rn = sorted[e + S.stride];
+                        const float p[3] = {rp.x, rp.y, rp.z};
+                        const float wgt = rp.w;
+                        rp = rn;
+                        float ev[3], r;
+                        Walk w;
+                        walk_setup(M, p, s, ev, r, w);
+                        if (NREG > 1) {
+                            // every walk index lies between its end voxels: skip bands that miss the region
+                            const int o3[3] = {ox, oy, oz};
+                            const int r3[3] = {RX, RY, RZ};
+                            bool miss = false;
+    #pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const int g_end = w.g[a] + w.step[a] * w.n[a];
+                                const int glo = w.g[a] < g_end ? w.g[a] : g_end;
+                                const int ghi = w.g[a] < g_end ? g_end : w.g[a];
+                                miss = miss || ghi < o3[a] || glo >= o3[a] + r3[a];
                             }
-                            D[j] = Dn;
-                            W[j] = Wn;
+                            if (miss) continue;
                         }
-                        ntot[j] += dn[h];
-                        stat_vox += 1;
-                        stat_touch += dn[h];
-                        a_w[h][l] = 0; a_d[h][l] = 0;
+                        bool inside = false;
+                        for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
+                            const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
+                            if ((u32)lx < (u32)RX && (u32)ly < (u32)RY && (u32)lz < (u32)RZ) {
+                                inside = true;
+                                const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
+                                const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
+                                const u64 fw = (u64)__builtin_rintf(o.w * M.wscale);
+                                const i64 fd = (i64)__builtin_rintf(o.w * o.e * M.wscale);
+                                // issued unconditionally: a wave issues an LDS atomic once for
+                                // all its lanes, and adding zero is harmless
+                                atomicAdd(&sw_buf[l], fw);
+                                atomicAdd(&sd_buf[l], (u64)fd);
+                                atomicAdd(&a_c[l], S.cadd);
+                            } else if (inside) {
+                                break;   // the walk is monotone per axis: it never re-enters the region
+                            }
+                            if (w.left == 0) break;
+                            walk_step(w);
+                        }
                     }
+                    __syncthreads();
+                    // Eqs. (3)-(4), once per voxel for each frame of the step, in frame order
+    #pragma unroll
+                    for (int j = 0; j < VPT; ++j) {
+                        const int l = threadIdx.x + NT * j;
+                        const u32 c = a_c[l];
+                        const u32 d = c - last[j];
+                        last[j] = c;
+                        const u32 dn[2] = {S.pair ? (d & 0xFFFFu) : d, S.pair ? (d >> 16) : 0u};
+    #pragma unroll
+                        for (int h = 0; h < K; ++h) {
+                            if (!dn[h]) continue;
+                            const u64 sw_fx = a_w[h][l];
+                            if (sw_fx) {
+                                const float sw = (float)sw_fx * M.inv_wscale;
+                                // sums are in units of delta; binary32 storage keeps D in metres,
+                                // binary16 storage keeps D / delta
+                                float swd = (float)(i64)a_d[h][l] * M.inv_wscale;
+                                if (STORAGE == 0) swd = swd * M.delta;
+                                float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
+                                float Wn = W[j] + sw;
+                                if (Wn > M.w_max) Wn = M.w_max;
+                                if (STORAGE == 1) {
+                                    Dn = __half2float(__float2half_rn(Dn));
+                                    Wn = __half2float(__float2half_rn(Wn));
+                                }
+                                D[j] = Dn;
+                                W[j] = Wn;
+                            }
+                            ntot[j] += dn[h];
+                            stat_vox += 1;
+                            stat_touch += dn[h];
+                            a_w[h][l] = 0; a_d[h][l] = 0;
+                        }
+                    }
+                    __syncthreads();
+                    S = Sn;
                 }
                 __syncthreads();
-                S = Sn;
             }
-            __syncthreads();
+        } else {
+            // one frame at a time: a_c holds the frame's ray counts, cleared by the fold
+            for (int w0 = 0; w0 < M.njobs; w0 += kOffWindow) {
+                const int wn = M.njobs - w0 < kOffWindow ? M.njobs - w0 : kOffWindow;
+                for (int k = threadIdx.x; k <= wn; k += NT) s_off[k] = off[t * JM + (u32)(w0 + k)];
+                __syncthreads();
+                // frames of the window in order; the first ray of every thread for the next frame
+                // that has rays is loaded while the current frame is processed
+                int jm = 0;
+                while (jm < wn && s_off[jm] == s_off[jm + 1]) ++jm;
+                float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+                float nxs[3] = {0.f, 0.f, 0.f};   // that frame's sensor origin, also loaded ahead
+                if (jm < wn) {
+                    const u32 e = s_off[jm] + threadIdx.x;
+                    if (e < s_off[jm + 1]) nxt = sorted[e];
+                    const Job& Jn = jobs[M.job0 + w0 + jm];
+                    nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
+                }
+                while (jm < wn) {
+                    int jn = jm + 1;
+                    while (jn < wn && s_off[jn] == s_off[jn + 1]) ++jn;
+                    const float4 cur = nxt;
+                    const float s[3] = {nxs[0], nxs[1], nxs[2]};
+                    const u32 lo = s_off[jm], hi = s_off[jm + 1];
+                    if (jn < wn) {
+                        const u32 e = s_off[jn] + threadIdx.x;
+                        if (e < s_off[jn + 1]) nxt = sorted[e];
+                        const Job& Jn = jobs[M.job0 + w0 + jn];
+                        nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
+                    }
+                    float4 rp = cur;
+                    for (u32 e = lo + threadIdx.x; e < hi; e += NT) {
+                        // the next ray's load is in flight while this one is walked
+                        float4 rn = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (e + NT < hi) rn = sorted[e + NT];
+                        const float p[3] = {rp.x, rp.y, rp.z};
+                        const float wgt = rp.w;
+                        rp = rn;
+                        float ev[3], r;
+                        Walk w;
+                        walk_setup(M, p, s, ev, r, w);
+                        if (NREG > 1) {
+                            // every walk index lies between its end voxels: skip bands that miss the region
+                            const int o3[3] = {ox, oy, oz};
+                            const int r3[3] = {RX, RY, RZ};
+                            bool miss = false;
+    #pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const int g_end = w.g[a] + w.step[a] * w.n[a];
+                                const int glo = w.g[a] < g_end ? w.g[a] : g_end;
+                                const int ghi = w.g[a] < g_end ? g_end : w.g[a];
+                                miss = miss || ghi < o3[a] || glo >= o3[a] + r3[a];
+                            }
+                            if (miss) continue;
+                        }
+                        bool inside = false;
+                        for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
+                            const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
+                            if ((u32)lx < (u32)RX && (u32)ly < (u32)RY && (u32)lz < (u32)RZ) {
+                                inside = true;
+                                const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
+                                const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
+                                const u64 fw = (u64)__builtin_rintf(o.w * M.wscale);
+                                const i64 fd = (i64)__builtin_rintf(o.w * o.e * M.wscale);
+                                // issued unconditionally: a wave issues an LDS atomic once for
+                                // all its lanes, and adding zero is harmless
+                                atomicAdd(&a_w[0][l], fw);
+                                atomicAdd(&a_d[0][l], (u64)fd);
+                                atomicAdd(&a_c[l], 1u);
+                            } else if (inside) {
+                                break;   // the walk is monotone per axis: it never re-enters the region
+                            }
+                            if (w.left == 0) break;
+                            walk_step(w);
+                        }
+                    }
+                    __syncthreads();
+                    // Eqs. (3)-(4), once per voxel for this frame
+    #pragma unroll
+                    for (int j = 0; j < VPT; ++j) {
+                        const int l = threadIdx.x + NT * j;
+                        const u32 c = a_c[l];
+                        if (c) {
+                            const u64 sw_fx = a_w[0][l];
+                            if (sw_fx) {
+                                const float sw = (float)sw_fx * M.inv_wscale;
+                                // sums are in units of delta; binary32 storage keeps D in metres,
+                                // binary16 storage keeps D / delta
+                                float swd = (float)(i64)a_d[0][l] * M.inv_wscale;
+                                if (STORAGE == 0) swd = swd * M.delta;
+                                float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
+                                float Wn = W[j] + sw;
+                                if (Wn > M.w_max) Wn = M.w_max;
+                                if (STORAGE == 1) {
+                                    Dn = __half2float(__float2half_rn(Dn));
+                                    Wn = __half2float(__float2half_rn(Wn));
+                                }
+                                D[j] = Dn;
+                                W[j] = Wn;
+                            }
+                            ntot[j] += c;
+                            stat_vox += 1;
+                            stat_touch += c;
+                            a_w[0][l] = 0; a_d[0][l] = 0; a_c[l] = 0;
+                        }
+                    }
+                    __syncthreads();
+                    jm = jn;
+                }
+                __syncthreads();
+            }
         }
 #pragma unroll
         for (int j = 0; j < VPT; ++j) store_voxel<STORAGE>(pool, vbase + block_local(threadIdx.x + NT * j), D[j], W[j]);
