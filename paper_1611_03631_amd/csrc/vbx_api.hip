@@ -367,6 +367,22 @@ int group_merge_grid() {
     return grid > 0 ? grid : 256;
 }
 
+// Waves of the partial-group sort kernels that the chip holds at once.
+unsigned sort_resident_waves() {
+    static unsigned waves = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0, cus = 256, per = 1;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_gscatter), 256, 0) !=
+                hipSuccess || per < 1)
+            per = 1;
+        waves = (unsigned)cus * (unsigned)per * 4u;
+    });
+    return waves > 0 ? waves : 8192u;
+}
+
 // Persistent grid of an update-kernel variant: one workgroup per slot the chip can hold.
 template <int STORAGE, int RX, int RY, int RZ, int NT>
 int update_grid() {
@@ -586,6 +602,7 @@ int stage_tables(Scratch* s, hipStream_t st, const Prepared& pr) {
 // Resolves the once-per-process launch shapes before any capture.
 void warm_launch_shapes() {
     (void)group_merge_grid();
+    (void)sort_resident_waves();
     warm_update_grids<0>();
     warm_update_grids<1>();
 }
@@ -632,16 +649,18 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     }
     if (plan.grouped && total_tiles > 0) {
         StageTimer tm(prof_map, st, ST_GROUPS);
-        const unsigned GW = (total_tiles + 3) / 4;   // one wave per tile
+        // two tiles per wave once the paired waves still fill the chip twice over
+        const u32 tpw = total_tiles >= 4u * sort_resident_waves() ? 2u : 1u;
+        const unsigned GW = (total_tiles + 4 * tpw - 1) / (4 * tpw);
         hipLaunchKernelGGL(k_densify, dim3(GT), dim3(256), 0, st, (const u32*)s->tlist.p, (u32)s->tlist_cap,
                            (u32*)s->tval.p, (const CallState*)cs);
         hipLaunchKernelGGL(k_gbin_count, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
                            (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p, JM,
-                           (const CallState*)cs);
+                           tpw, (const CallState*)cs);
         scan_bins(JMS);
         hipLaunchKernelGGL(k_gscatter, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
                            (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p,
-                           (const u32*)s->off.p, JM, (Partial*)s->parts_sorted.p, (const CallState*)cs);
+                           (const u32*)s->off.p, JM, tpw, (Partial*)s->parts_sorted.p, (const CallState*)cs);
         hipLaunchKernelGGL(k_chunk_first, dim3(grid_for(s->bins_cap + 1, 1024)), dim3(256), 0, st,
                            (const u32*)s->off.p, JMS, (u32*)s->chunk_first.p, (const CallState*)cs);
         hipLaunchKernelGGL(k_group_merge, dim3(group_merge_grid()), dim3(256), 0, st, d_jobs, d_maps,
@@ -696,10 +715,10 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     }
     {
     StageTimer tm(prof_map, st, ST_FINISH);
-    hipLaunchKernelGGL(k_cleanup, dim3(grid_for(s->tkey_cap, 1024)), dim3(256), 0, st, (u64*)s->tkeys.p,
-                       (u32)s->tkey_cap, (const u32*)s->tlist.p, (u32)s->tlist_cap, (const CallState*)cs);
-    hipLaunchKernelGGL(k_finish, dim3(M), dim3(256), 0, st, d_jobs, d_maps, M, jst, (const CallState*)cs);
-    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(64), 0, st, cs);
+    // one workgroup per map, and few for the block-set cleanup: every workgroup adds to one
+    // completion counter, and such adds are carried out one after another
+    hipLaunchKernelGGL(k_finish_call, dim3(M + grid_for(s->tkey_cap, 32)), dim3(256), 0, st, d_jobs, d_maps, M,
+                       jst, (u64*)s->tkeys.p, (u32)s->tkey_cap, (const u32*)s->tlist.p, (u32)s->tlist_cap, cs);
     }
     if (hipGetLastError() != hipSuccess) return VBX_ERR_DEVICE;
     return VBX_OK;

@@ -24,10 +24,10 @@ __global__ void k_points_grouped(const Job* jobs, int njobs, const MapDesc* maps
                                  JobStat* jst, CallState* cs);
 __global__ void k_densify(const u32* tlist, u32 tlist_cap, u32* tval, const CallState* cs);
 __global__ void k_gbin_count(const Partial* parts, const u32* tile_parts, u32 ntiles,
-                             const u32* tval, u32* bins, u32 JM, const CallState* cs);
+                             const u32* tval, u32* bins, u32 JM, u32 tpw, const CallState* cs);
 __global__ void k_gscatter(const Partial* parts, const u32* tile_parts, u32 ntiles,
-                           const u32* tval, u32* bins, const u32* off, u32 JM, Partial* sorted,
-                           const CallState* cs);
+                           const u32* tval, u32* bins, const u32* off, u32 JM, u32 tpw,
+                           Partial* sorted, const CallState* cs);
 __global__ void k_chunk_first(const u32* off, u32 JM, u32* chunk_first, const CallState* cs);
 __global__ void k_group_merge(const Job* jobs, const MapDesc* maps, const u64* tkeys,
                               const u32* tlist, const u32* off, const u32* chunk_first,
@@ -55,10 +55,8 @@ __global__ void k_update(const Job* jobs, const MapDesc* maps, const u64* t_key,
                          const u32* off, const u32* order, const float4* sorted, u32 JM, u64* touch_key,
                          u32* touch_n, u32 touch_cap, int keep_touches, JobStat* jst, CallState* cs);
 __global__ void k_order_blocks(const u32* off, u32 JM, u32* order, const CallState* cs);
-__global__ void k_cleanup(u64* tkeys, u32 tkey_cap, const u32* tlist, u32 tlist_cap,
-                          const CallState* cs);
-__global__ void k_finish(const Job* jobs, const MapDesc* maps, int nmaps, JobStat* jst, const CallState* cs);
-__global__ void k_reset_call(CallState* cs);
+__global__ void k_finish_call(const Job* jobs, const MapDesc* maps, int nmaps, JobStat* jst, u64* tkeys,
+                              u32 tkey_cap, const u32* tlist, u32 tlist_cap, CallState* cs);
 __global__ void k_debug_traverse(const float* A, const float* B, int n, int* out, int cap,
                                  int* counts);
 

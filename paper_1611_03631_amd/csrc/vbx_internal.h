@@ -78,19 +78,24 @@ struct CallState {
     int error;         // call-wide error (scratch overflow)
     u32 work_merge;    // persistent work counter of the group merge kernel
     u32 scan_done;     // workgroups of the current scan that have written their sum
-    u32 pad1;
+    u32 finish_done;   // workgroups of the call's last kernel that are done
 };
 
-// Partial group of one tile (48 bytes): exact integer sums of the tile's points in one voxel.
+// Partial group of one tile (40 bytes): exact integer sums of the tile's points in one voxel.
+// The weight sum is below 2^48 (at most 512 points of fixed-point weight at most 2^32), so the
+// point count shares its word.
 struct Partial {
-    u64 so;        // sum of fixed-point point weights
+    u64 so_n;      // sum of fixed-point point weights | (points - 1) << 48
     u64 sq[3];     // n > 1: sums of weight * Q_k (fit 64 bits for a tile of <= 512 points);
                    // n == 1: the point itself and its Q_k, packed by pack_single
     u32 h;         // block-set slot of the voxel's block
     u32 lj;        // local voxel index (12 bits) | frame-in-map index << 12
-    u32 n;         // points
-    u32 pad;
 };
+static_assert(sizeof(Partial) == 40, "partial group record");
+constexpr u64 kSoMask = (1ull << 48) - 1;
+__host__ __device__ inline u64 partial_so_n(u64 so, u32 n) { return so | ((u64)(n - 1u) << 48); }
+__host__ __device__ inline u64 partial_so(u64 so_n) { return so_n & kSoMask; }
+__host__ __device__ inline u32 partial_n(u64 so_n) { return (u32)(so_n >> 48) + 1u; }
 
 // A one-point partial group carries the point (binary32 world coordinates) and its grid
 // fractions Q_k instead of the sums, which follow from them (sum = weight * Q_k).  A group

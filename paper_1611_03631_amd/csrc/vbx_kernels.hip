@@ -48,14 +48,12 @@ __device__ inline void wave_count_by_key(u32* base, bool active, u32 key) {
     }
 }
 
-// Counting-sort positions for the active lanes of a wave: lanes with equal keys take
-// consecutive positions below their bin's remaining count, reserved by one atomic per distinct
-// key.  The groups are found first (ballots only) and every group's atomic is then issued by
-// one instruction, so a wave waits for one atomic round trip rather than one per key.
-__device__ inline u32 wave_claim_by_key(u32* bins, const u32* off, bool active, u32 key) {
+// Groups the active lanes of a wave by key (ballots only): each lane learns its group's first
+// lane and its rank in the group, and that first lane the group's size.
+__device__ inline void wave_group_by_key(bool active, u32 key, u32& leader_of, u32& rank, u32& count) {
     const int lane = lane_id();
     u64 pending = __ballot(active);
-    u32 leader_of = 0, rank = 0, count = 0;
+    leader_of = 0; rank = 0; count = 0;
     while (pending) {
         const int leader = __ffsll((long long)pending) - 1;
         const u32 kb = __shfl(key, leader);
@@ -68,10 +66,34 @@ __device__ inline u32 wave_claim_by_key(u32* bins, const u32* off, bool active, 
         if (lane == leader) count = (u32)__popcll(grp);
         pending &= ~grp;
     }
+}
+
+// Counting-sort positions for the active lanes of a wave: lanes with equal keys take
+// consecutive positions below their bin's remaining count, reserved by one atomic per distinct
+// key.  The groups are found first (ballots only) and every group's atomic is then issued by
+// one instruction, so a wave waits for one atomic round trip rather than one per key.
+__device__ inline u32 wave_claim_by_key(u32* bins, const u32* off, bool active, u32 key) {
+    u32 leader_of, rank, count;
+    wave_group_by_key(active, key, leader_of, rank, count);
     u32 old = 0;
     if (count) old = atomicSub(&bins[key], count);   // the leaders, together
     const u32 base = (u32)__shfl((int)old, (int)leader_of);
     return active ? off[key] + base - 1u - rank : 0u;
+}
+
+// The same for two keys per lane, both sets of reservations in flight together.
+__device__ inline void wave_claim_by_key2(u32* bins, const u32* off, bool act0, u32 key0, bool act1,
+                                          u32 key1, u32& pos0, u32& pos1) {
+    u32 lead0, rank0, cnt0, lead1, rank1, cnt1;
+    wave_group_by_key(act0, key0, lead0, rank0, cnt0);
+    wave_group_by_key(act1, key1, lead1, rank1, cnt1);
+    u32 old0 = 0, old1 = 0;
+    if (cnt0) old0 = atomicSub(&bins[key0], cnt0);
+    if (cnt1) old1 = atomicSub(&bins[key1], cnt1);
+    const u32 base0 = (u32)__shfl((int)old0, (int)lead0);
+    const u32 base1 = (u32)__shfl((int)old1, (int)lead1);
+    pos0 = act0 ? off[key0] + base0 - 1u - rank0 : 0u;
+    pos1 = act1 ? off[key1] + base1 - 1u - rank1 : 0u;
 }
 
 // Inclusive prefix sum over a 256-thread workgroup; returns the inclusive value, total in *tot.
@@ -481,8 +503,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                 // the table is full: the run is written now, from the back of the tile's range,
                 // and enters the block set alone
                 Partial P;
-                P.so = so;
-                P.n = cnt;
+                P.so_n = partial_so_n(so, cnt);
                 if (cnt == 1) {
                     int g1[3];
                     u32 Q1[3];
@@ -494,7 +515,6 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                 }
                 P.h = tset_insert<false>(tkeys, tmask, mapbits | (key >> 12), tlist, tlist_cap, cs);
                 P.lj = jm12 | (u32)(key & 4095u);
-                P.pad = 0;
                 tparts[kTileGrouped - 1 - atomicAdd(&s_cnt[3], 1u)] = P;
             }
         }
@@ -536,8 +556,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     if (threadIdx.x == 0) tile_parts[blockIdx.x] = tot | (s_cnt[3] << 16);
     if (has_slot) {
         Partial P;
-        P.so = s_so[k];
-        P.n = sn;
+        P.so_n = partial_so_n(s_so[k], sn);
         if (sn == 1) {
             // the world point as it was grouped, and its Q_k
             const float p1[3] = {s_pt[0][k], s_pt[1][k], s_pt[2][k]};
@@ -551,7 +570,6 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         }
         P.h = direct ? hdirect : s_bh[bh];
         P.lj = jm12 | (u32)(skey & 4095u);
-        P.pad = 0;
         tparts[incl - 1] = P;
     }
     if (threadIdx.x == 0) {
@@ -570,7 +588,10 @@ __global__ __launch_bounds__(256) void k_densify(const u32* __restrict__ tlist, 
 }
 
 // Grouped raycasting, step 2: counting sort of the partial groups by (block, frame).  One
-// wave per tile walks the tile's partials.
+// wave takes tpw (1 or 2) consecutive tiles and walks their partials as one list (the first
+// tile's, then the second's), two records per lane at a time, so that the loads and atomics of
+// up to 128 records are in flight together.  Two tiles per wave pay where the tiles outnumber
+// the waves the chip holds; with fewer tiles, one per wave keeps more waves running.
 
 // Sort bin of a partial group: (block t, frame, eighth of the block's voxels), JM frames per
 // block, so that a bin spans at most kMergeVox distinct voxels.
@@ -583,22 +604,45 @@ __device__ inline u32 group_bin(u32 t, u32 lj, u32 JM) {
 __device__ inline u32 tile_record(u32 i, u32 nf, u32 np) {
     return i < nf ? i : (u32)kTileGrouped - np + i;
 }
+
+// The records of tile tile0 and, when tpw is 2 and it exists, of tile0 + 1, as one list.
+struct TilePair {
+    u32 tile0, nf0, np0, nf1, np1;
+    __device__ TilePair(const u32* tile_parts, u32 ntiles, u32 t0, u32 tpw) : tile0(t0) {
+        const u32 a = tile_parts[t0];
+        const u32 b = tpw == 2u && t0 + 1u < ntiles ? tile_parts[t0 + 1u] : 0u;
+        nf0 = a & 0xFFFFu; np0 = nf0 + (a >> 16);
+        nf1 = b & 0xFFFFu; np1 = nf1 + (b >> 16);
+    }
+    __device__ u32 count() const { return np0 + np1; }
+    // index in the partial array of record r < count()
+    __device__ size_t record(u32 r) const {
+        return r < np0 ? (size_t)tile0 * kTileGrouped + tile_record(r, nf0, np0)
+                       : (size_t)(tile0 + 1u) * kTileGrouped + tile_record(r - np0, nf1, np1);
+    }
+};
+
 __global__ __launch_bounds__(256) void k_gbin_count(const Partial* __restrict__ parts,
                                                     const u32* __restrict__ tile_parts, u32 ntiles,
                                                     const u32* __restrict__ tval,
-                                                    u32* __restrict__ bins, u32 JM,
+                                                    u32* __restrict__ bins, u32 JM, u32 tpw,
                                                     const CallState* __restrict__ cs) {
     if (cs->error) return;
-    const u32 tile = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (tile >= ntiles) return;   // whole wave
-    const int lane = lane_id();
-    const u32 tp_n = tile_parts[tile], nf = tp_n & 0xFFFFu, np = nf + (tp_n >> 16);
-    const Partial* tp = parts + (size_t)tile * kTileGrouped;
-    for (u32 b0 = 0; b0 < np; b0 += 64) {
-        const u32 i = tile_record(b0 + (u32)lane, nf, np);
-        u32 b = 0;
-        if (b0 + (u32)lane < np) b = group_bin(tval[tp[i].h], tp[i].lj, JM);
-        wave_count_by_key(bins, b0 + (u32)lane < np, b);
+    const u32 tile0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * tpw;
+    if (tile0 >= ntiles) return;   // whole wave
+    const u32 lane = (u32)lane_id();
+    const TilePair tp(tile_parts, ntiles, tile0, tpw);
+    const u32 np = tp.count();
+    for (u32 b0 = 0; b0 < np; b0 += 128) {
+        const u32 r0 = b0 + lane, r1 = r0 + 64u;
+        const bool a0 = r0 < np, a1 = r1 < np;
+        u32 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+        if (a0) { const Partial& P = parts[tp.record(r0)]; h0 = P.h; l0 = P.lj; }
+        if (a1) { const Partial& P = parts[tp.record(r1)]; h1 = P.h; l1 = P.lj; }
+        const u32 k0 = a0 ? group_bin(tval[h0], l0, JM) : 0u;
+        const u32 k1 = a1 ? group_bin(tval[h1], l1, JM) : 0u;
+        wave_count_by_key(bins, a0, k0);
+        wave_count_by_key(bins, a1, k1);
     }
 }
 
@@ -606,24 +650,26 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
                                                   const u32* __restrict__ tile_parts, u32 ntiles,
                                                   const u32* __restrict__ tval,
                                                   u32* __restrict__ bins, const u32* __restrict__ off,
-                                                  u32 JM, Partial* __restrict__ sorted,
+                                                  u32 JM, u32 tpw, Partial* __restrict__ sorted,
                                                   const CallState* __restrict__ cs) {
     if (cs->error) return;
-    const u32 tile = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (tile >= ntiles) return;   // whole wave
-    const int lane = lane_id();
-    const u32 tp_n = tile_parts[tile], nf = tp_n & 0xFFFFu, np = nf + (tp_n >> 16);
-    const Partial* tp = parts + (size_t)tile * kTileGrouped;
-    for (u32 b0 = 0; b0 < np; b0 += 64) {
-        const bool act = b0 + (u32)lane < np;
-        u32 b = 0;
-        Partial P;
-        if (act) {
-            P = tp[tile_record(b0 + (u32)lane, nf, np)];
-            b = group_bin(tval[P.h], P.lj, JM);
-        }
-        const u32 pos = wave_claim_by_key(bins, off, act, b);
-        if (act) sorted[pos] = P;
+    const u32 tile0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * tpw;
+    if (tile0 >= ntiles) return;   // whole wave
+    const u32 lane = (u32)lane_id();
+    const TilePair tp(tile_parts, ntiles, tile0, tpw);
+    const u32 np = tp.count();
+    for (u32 b0 = 0; b0 < np; b0 += 128) {
+        const u32 r0 = b0 + lane, r1 = r0 + 64u;
+        const bool a0 = r0 < np, a1 = r1 < np;
+        Partial P0, P1;
+        if (a0) P0 = parts[tp.record(r0)];
+        if (a1) P1 = parts[tp.record(r1)];
+        const u32 k0 = a0 ? group_bin(tval[P0.h], P0.lj, JM) : 0u;
+        const u32 k1 = a1 ? group_bin(tval[P1.h], P1.lj, JM) : 0u;
+        u32 pos0, pos1;
+        wave_claim_by_key2(bins, off, a0, k0, a1, k1, pos0, pos1);
+        if (a0) sorted[pos0] = P0;
+        if (a1) sorted[pos1] = P1;
     }
 }
 
@@ -681,22 +727,24 @@ __device__ inline void group_ray(const MapDesc& M, int bx, int by, int bz, u32 l
 __device__ inline void merge_partial(const Partial& P, u32 v, u64* m_so, u64 (*m_sq)[kMergeVox],
                                      u32 (*m_hi)[kMergeVox], u32* m_n, float (*m_p)[kMergeVox]) {
     u64 add[3] = {P.sq[0], P.sq[1], P.sq[2]};
-    if (P.n == 1) {
+    const u64 so = partial_so(P.so_n);
+    const u32 n = partial_n(P.so_n);
+    if (n == 1) {
         float p1[3];
         u32 Q[3];
         unpack_single(P.sq, p1, Q);
-        add[0] = P.so * Q[0];
-        add[1] = P.so * Q[1];
-        add[2] = P.so * Q[2];
+        add[0] = so * Q[0];
+        add[1] = so * Q[1];
+        add[2] = so * Q[2];
         m_p[0][v] = p1[0]; m_p[1][v] = p1[1]; m_p[2][v] = p1[2];   // read only if the group stays single
     }
-    atomicAdd(&m_so[v], P.so);
+    atomicAdd(&m_so[v], so);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const u64 old = atomicAdd(&m_sq[k][v], add[k]);
         if (old + add[k] < old) atomicAdd(&m_hi[k][v], 1u);   // carry
     }
-    atomicAdd(&m_n[v], P.n);
+    atomicAdd(&m_n[v], n);
 }
 
 __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ jobs,
@@ -1738,29 +1786,29 @@ template __global__ void k_update<1, 16, 16, 8, 512>(const Job*, const MapDesc*,
 // ---------------------------------------------------------------------------
 // finish: commit block counts, fold statistics, clean per-call tables
 // ---------------------------------------------------------------------------
+// The call's last kernel, in one launch: workgroups [0, nmaps) fold each map's statistics,
+// workgroups [nmaps, grid) free the per-call block set, and the workgroup that finishes last
+// (counted in cs->finish_done) resets the call's counters for the next call.
+
 // Frees the per-call block set: the listed slots, or the whole table after a failed call
-// (whose set may hold keys that never reached the list).
-__global__ __launch_bounds__(256) void k_cleanup(u64* __restrict__ tkeys, u32 tkey_cap,
-                                                 const u32* __restrict__ tlist, u32 tlist_cap,
-                                                 const CallState* __restrict__ cs) {
-    const u32 stride = gridDim.x * 256u;
+// (whose set may hold keys that never reached the list).  Workgroup wg of nwg.
+__device__ inline void cleanup_part(u32 wg, u32 nwg, u64* __restrict__ tkeys, u32 tkey_cap,
+                                    const u32* __restrict__ tlist, u32 tlist_cap,
+                                    const CallState* __restrict__ cs) {
+    const u32 stride = nwg * 256u;
     if (cs->error) {
-        for (u32 i = blockIdx.x * 256u + threadIdx.x; i < tkey_cap; i += stride) tkeys[i] = kEmpty;
+        for (u32 i = wg * 256u + threadIdx.x; i < tkey_cap; i += stride) tkeys[i] = kEmpty;
     } else {
         const u32 nt = cs->t_count < tlist_cap ? cs->t_count : tlist_cap;
-        for (u32 i = blockIdx.x * 256u + threadIdx.x; i < nt; i += stride) tkeys[tlist[i]] = kEmpty;
+        for (u32 i = wg * 256u + threadIdx.x; i < nt; i += stride) tkeys[tlist[i]] = kEmpty;
     }
 }
 
-// Per map (one workgroup each): folds the call's per-frame statistics into the map, commits
-// its new blocks and clears its frames' statistics.
-__global__ __launch_bounds__(256) void k_finish(const Job* __restrict__ jobs,
-                                                const MapDesc* __restrict__ maps, int nmaps,
-                                                JobStat* __restrict__ jst,
-                                                const CallState* __restrict__ cs) {
-    __shared__ u64 s_acc[8];
-    const int m = blockIdx.x;
-    if (m >= nmaps) return;   // whole workgroup
+// Map m (one workgroup): folds the call's per-frame statistics into the map, commits its new
+// blocks and clears its frames' statistics.
+__device__ inline void finish_map(int m, const Job* __restrict__ jobs, const MapDesc* __restrict__ maps,
+                                  JobStat* __restrict__ jst, const CallState* __restrict__ cs,
+                                  u64* s_acc) {
     MapState* st = maps[m].st;
     const bool ok = st->error == 0 && cs->error == 0;
     if (threadIdx.x < 8) s_acc[threadIdx.x] = 0;
@@ -1811,15 +1859,32 @@ __global__ __launch_bounds__(256) void k_finish(const Job* __restrict__ jobs,
     }
 }
 
-// After k_finish: the call's counters start from zero for the next call.
-__global__ void k_reset_call(CallState* __restrict__ cs) {
+__global__ __launch_bounds__(256) void k_finish_call(const Job* __restrict__ jobs,
+                                                     const MapDesc* __restrict__ maps, int nmaps,
+                                                     JobStat* __restrict__ jst, u64* __restrict__ tkeys,
+                                                     u32 tkey_cap, const u32* __restrict__ tlist,
+                                                     u32 tlist_cap, CallState* __restrict__ cs) {
+    __shared__ u64 s_acc[8];
+    __shared__ bool s_last;
+    if ((int)blockIdx.x < nmaps)
+        finish_map((int)blockIdx.x, jobs, maps, jst, cs, s_acc);
+    else
+        cleanup_part(blockIdx.x - (u32)nmaps, gridDim.x - (u32)nmaps, tkeys, tkey_cap, tlist, tlist_cap, cs);
+    __syncthreads();
     if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(&cs->finish_done, 1u) == gridDim.x - 1u;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
         cs->ray_count = 0;
         cs->t_count = 0;
         cs->work_next = 0;
         cs->work_merge = 0;
         cs->scan_done = 0;
         cs->error = 0;
+        cs->finish_done = 0;
     }
 }
 
