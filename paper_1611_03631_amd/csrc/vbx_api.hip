@@ -628,11 +628,11 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     const unsigned GT = grid_for(s->tlist_cap, 1024);
     const unsigned NP = (unsigned)std::max<size_t>(s->nparts, 1);
     // exclusive scan of the t_count * per_block bin counts
-    auto scan_bins = [&](u32 per_block) {
+    auto scan_bins = [&](u32 per_block, u32* chunk_first) {
         hipLaunchKernelGGL(k_scan_sums, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, per_block,
                            (u32*)s->partial.p, (u32*)s->off.p, cs);
         hipLaunchKernelGGL(k_scan_final, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, (const u32*)s->partial.p,
-                           (u32*)s->off.p, per_block, (const CallState*)cs);
+                           (u32*)s->off.p, per_block, chunk_first, (const CallState*)cs);
     };
     const u32 JMS = JM * (u32)kGroupSubBins;   // partial-group sort bins per block
     // points
@@ -657,12 +657,10 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
         hipLaunchKernelGGL(k_gbin_count, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
                            (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p, JM,
                            tpw, (const CallState*)cs);
-        scan_bins(JMS);
+        scan_bins(JMS, (u32*)s->chunk_first.p);
         hipLaunchKernelGGL(k_gscatter, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
                            (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p,
                            (const u32*)s->off.p, JM, tpw, (Partial*)s->parts_sorted.p, (const CallState*)cs);
-        hipLaunchKernelGGL(k_chunk_first, dim3(grid_for(s->bins_cap + 1, 1024)), dim3(256), 0, st,
-                           (const u32*)s->off.p, JMS, (u32*)s->chunk_first.p, (const CallState*)cs);
         hipLaunchKernelGGL(k_group_merge, dim3(group_merge_grid()), dim3(256), 0, st, d_jobs, d_maps,
                            (const u64*)s->tkeys.p, (const u32*)s->tlist.p, (const u32*)s->off.p,
                            (const u32*)s->chunk_first.p, (const Partial*)s->parts_sorted.p, JMS, rays_p,
@@ -693,7 +691,7 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     }
     {
     StageTimer tm(prof_map, st, ST_SCAN);
-    scan_bins(JM);
+    scan_bins(JM, nullptr);
     }
     {
     StageTimer tm(prof_map, st, ST_SCATTER);
@@ -1353,10 +1351,8 @@ int vbx_debug_traverse(const float* A_dev, const float* B_dev, int n, int32_t* o
 
 int vbx_map_clear(vbx_map* m) {
     if (!m) return VBX_ERR_INVALID_ARG;
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(m->hcap)), dim3(256), 0, m->stream, m->hkeys, kEmpty,
-                       (size_t)m->hcap);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, m->stream, (u32*)m->st, 0u,
-                       sizeof(MapState) / 4);
+    hipLaunchKernelGGL(k_map_clear, dim3(grid_for(m->hcap)), dim3(256), 0, m->stream, m->hkeys, (size_t)m->hcap,
+                       (u32*)m->st, (u32)(sizeof(MapState) / 4));
     VBX_TRY(hipGetLastError());
     return VBX_OK;
 }

@@ -16,6 +16,7 @@ struct JobStat {
 __global__ void k_fill_u64(u64* p, u64 val, size_t n);
 __global__ void k_fill_u32(u32* p, u32 val, size_t n);
 __global__ void k_set_u32(u32* p, u32 v);
+__global__ void k_map_clear(u64* hkeys, size_t hcap, u32* state, u32 state_words);
 __global__ void k_map_status(const MapDesc* maps, int nmaps, int* out);
 __global__ void k_points_simple(const Job* jobs, int njobs, const MapDesc* maps, float4* rays_p,
                                 u32* rays_job, JobStat* jst, CallState* cs);
@@ -28,7 +29,6 @@ __global__ void k_gbin_count(const Partial* parts, const u32* tile_parts, u32 nt
 __global__ void k_gscatter(const Partial* parts, const u32* tile_parts, u32 ntiles,
                            const u32* tval, u32* bins, const u32* off, u32 JM, u32 tpw,
                            Partial* sorted, const CallState* cs);
-__global__ void k_chunk_first(const u32* off, u32 JM, u32* chunk_first, const CallState* cs);
 __global__ void k_group_merge(const Job* jobs, const MapDesc* maps, const u64* tkeys,
                               const u32* tlist, const u32* off, const u32* chunk_first,
                               const Partial* sorted, u32 JM, float4* rays_p, u32* rays_job,
@@ -44,7 +44,7 @@ __global__ void k_bin_count(const Job* jobs, const u32* cross, const unsigned ch
                             u32 MB, const u32* tval, const u32* rays_job, u32* bins, u32 JM,
                             CallState* cs, u32 ray_cap);
 __global__ void k_scan_sums(const u32* bins, u32 JM, u32* partial, u32* off, CallState* cs);
-__global__ void k_scan_final(const u32* bins, const u32* partial, u32* off, u32 JM,
+__global__ void k_scan_final(const u32* bins, const u32* partial, u32* off, u32 JM, u32* chunk_first,
                              const CallState* cs);
 __global__ void k_scatter(const Job* jobs, const u32* cross, const unsigned char* ncross,
                           u32 MB, const u32* tval, const u32* rays_job, u32* bins,

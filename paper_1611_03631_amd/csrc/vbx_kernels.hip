@@ -81,19 +81,23 @@ __device__ inline u32 wave_claim_by_key(u32* bins, const u32* off, bool active, 
     return active ? off[key] + base - 1u - rank : 0u;
 }
 
-// The same for two keys per lane, both sets of reservations in flight together.
-__device__ inline void wave_claim_by_key2(u32* bins, const u32* off, bool act0, u32 key0, bool act1,
-                                          u32 key1, u32& pos0, u32& pos1) {
-    u32 lead0, rank0, cnt0, lead1, rank1, cnt1;
-    wave_group_by_key(act0, key0, lead0, rank0, cnt0);
-    wave_group_by_key(act1, key1, lead1, rank1, cnt1);
-    u32 old0 = 0, old1 = 0;
-    if (cnt0) old0 = atomicSub(&bins[key0], cnt0);
-    if (cnt1) old1 = atomicSub(&bins[key1], cnt1);
-    const u32 base0 = (u32)__shfl((int)old0, (int)lead0);
-    const u32 base1 = (u32)__shfl((int)old1, (int)lead1);
-    pos0 = act0 ? off[key0] + base0 - 1u - rank0 : 0u;
-    pos1 = act1 ? off[key1] + base1 - 1u - rank1 : 0u;
+// The same for N keys per lane, all N sets of reservations in flight together.
+template <int N>
+__device__ inline void wave_claim_by_keys(u32* bins, const u32* off, const bool (&act)[N],
+                                          const u32 (&key)[N], u32 (&pos)[N]) {
+    u32 lead[N], rank[N], cnt[N], old[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) wave_group_by_key(act[k], key[k], lead[k], rank[k], cnt[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        old[k] = 0;
+        if (cnt[k]) old[k] = atomicSub(&bins[key[k]], cnt[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const u32 base = (u32)__shfl((int)old[k], (int)lead[k]);
+        pos[k] = act[k] ? off[key[k]] + base - 1u - rank[k] : 0u;
+    }
 }
 
 // Inclusive prefix sum over a 256-thread workgroup; returns the inclusive value, total in *tot.
@@ -203,6 +207,13 @@ __global__ void k_fill_u32(u32* p, u32 val, size_t n) {
         p[i] = val;
 }
 __global__ void k_set_u32(u32* p, u32 v) { *p = v; }
+// Empties a map: every hash slot free, and (workgroup 0) its state words zero.
+__global__ void k_map_clear(u64* hkeys, size_t hcap, u32* state, u32 state_words) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < hcap; i += (size_t)gridDim.x * blockDim.x)
+        hkeys[i] = kEmpty;
+    if (blockIdx.x == 0)
+        for (u32 i = threadIdx.x; i < state_words; i += blockDim.x) state[i] = 0u;
+}
 
 // Status each map of a call was left in (maps of the staged table, in table order).
 __global__ void k_map_status(const MapDesc* __restrict__ maps, int nmaps, int* __restrict__ out) {
@@ -660,16 +671,16 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
     const u32 np = tp.count();
     for (u32 b0 = 0; b0 < np; b0 += 128) {
         const u32 r0 = b0 + lane, r1 = r0 + 64u;
-        const bool a0 = r0 < np, a1 = r1 < np;
+        const bool a[2] = {r0 < np, r1 < np};
         Partial P0, P1;
-        if (a0) P0 = parts[tp.record(r0)];
-        if (a1) P1 = parts[tp.record(r1)];
-        const u32 k0 = a0 ? group_bin(tval[P0.h], P0.lj, JM) : 0u;
-        const u32 k1 = a1 ? group_bin(tval[P1.h], P1.lj, JM) : 0u;
-        u32 pos0, pos1;
-        wave_claim_by_key2(bins, off, a0, k0, a1, k1, pos0, pos1);
-        if (a0) sorted[pos0] = P0;
-        if (a1) sorted[pos1] = P1;
+        if (a[0]) P0 = parts[tp.record(r0)];
+        if (a[1]) P1 = parts[tp.record(r1)];
+        const u32 k[2] = {a[0] ? group_bin(tval[P0.h], P0.lj, JM) : 0u,
+                          a[1] ? group_bin(tval[P1.h], P1.lj, JM) : 0u};
+        u32 pos[2];
+        wave_claim_by_keys<2>(bins, off, a, k, pos);
+        if (a[0]) sorted[pos[0]] = P0;
+        if (a[1]) sorted[pos[1]] = P1;
     }
 }
 
@@ -688,20 +699,6 @@ constexpr int kMergeVox = 2 * kMergeSpan;        // LDS table entries (hash slot
 constexpr int kMergeBatch = kMergeSpan * 5 / 4;  // partials merged in one hash pass (load <= 0.625)
 constexpr int kMergePerThread = kMergeVox / 256;
 static_assert(kGroupSubBins * kMergeVox == 4096 && kMergePerThread * 256 == kMergeVox, "merge table");
-
-// chunk_first[c] = first bin whose first partial lies at or after c * kMergeSpan.
-__global__ __launch_bounds__(256) void k_chunk_first(const u32* __restrict__ off, u32 JM,
-                                                     u32* __restrict__ chunk_first,
-                                                     const CallState* __restrict__ cs) {
-    const u32 nb = cs->error ? 0u : cs->t_count * JM;
-    for (u32 b = blockIdx.x * 256u + threadIdx.x; b <= nb; b += gridDim.x * 256u) {
-        // chunks whose start c * kMergeSpan lies in (off[b - 1], off[b]]
-        const u32 hi = off[b];
-        const u32 c_lo = b == 0 ? 0u : off[b - 1] / kMergeSpan + 1u;
-        const u32 c_hi = hi / kMergeSpan;
-        for (u32 c = c_lo; c <= c_hi; ++c) chunk_first[c] = b;
-    }
-}
 
 // Ray of a merged group: towards its single point, else towards the exact weighted mean,
 // carrying the group's summed weight.
@@ -1223,9 +1220,13 @@ __global__ __launch_bounds__(256) void k_scan_sums(const u32* __restrict__ bins,
     if (threadIdx.x == 0) off[n] = carry;
 }
 
+// With chunk_first (the partial-group sort), it also records the first bin of every merge chunk:
+// chunk_first[c] = the first bin whose first partial lies at or after c * kMergeSpan, i.e. bin
+// b for the chunks whose start lies in (off[b - 1], off[b]], and the end n for those up to off[n].
 __global__ __launch_bounds__(256) void k_scan_final(const u32* __restrict__ bins,
                                                     const u32* __restrict__ partial,
                                                     u32* __restrict__ off, u32 JM,
+                                                    u32* __restrict__ chunk_first,
                                                     const CallState* __restrict__ cs) {
     __shared__ u32 lds8[4];
     const u32 n = cs->error ? 0u : cs->t_count * JM;
@@ -1242,10 +1243,22 @@ __global__ __launch_bounds__(256) void k_scan_final(const u32* __restrict__ bins
     u32 tot;
     const u32 incl = block_scan_256(s, lds8, &tot);
     u32 run = partial[blockIdx.x] + incl - s;
+    const u32 i0 = base + threadIdx.x * 16u;
+    u32 prev = chunk_first && i0 > 0u && i0 < n ? run - bins[i0 - 1u] : 0u;   // off[i - 1]
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const u32 i = base + threadIdx.x * 16u + j;
-        if (i < n) off[i] = run;
+        const u32 i = i0 + j;
+        if (i < n) {
+            off[i] = run;
+            if (chunk_first) {
+                for (u32 c = i == 0u ? 0u : prev / kMergeSpan + 1u; c <= run / kMergeSpan; ++c)
+                    chunk_first[c] = i;
+                prev = run;
+                if (i + 1u == n)
+                    for (u32 c = prev / kMergeSpan + 1u; c <= (run + v[j]) / kMergeSpan; ++c)
+                        chunk_first[c] = n;
+            }
+        }
         run += v[j];
     }
 }
