@@ -763,6 +763,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
     __shared__ float m_p[3][kMergeVox];   // the point of a one-point group
     __shared__ u32 s_nr[kMergeBatch];  // rays emitted per bin of the batch
     __shared__ u32 s_off[kMergeBatch + 2];
+    __shared__ u64 s_tk[kMergeBatch];  // block-set key of each bin's block
     __shared__ u32 lds8[4];
     for (int i = threadIdx.x; i < kMergeVox; i += 256) {
         m_key[i] = 0; m_so[i] = 0; m_sq[0][i] = 0; m_sq[1][i] = 0; m_sq[2][i] = 0;
@@ -780,8 +781,12 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
         u32 b = bs;
         while (b < be) {
             // stage the offsets of up to kMergeBatch bins
+            // (and their blocks' keys, loaded alongside rather than after them)
             const u32 wn = be - b < (u32)kMergeBatch ? be - b : (u32)kMergeBatch;
-            for (u32 k = threadIdx.x; k <= wn; k += 256) s_off[k] = off[b + k];
+            for (u32 k = threadIdx.x; k <= wn; k += 256) {
+                s_off[k] = off[b + k];
+                if (k < wn) s_tk[k] = tkeys[tlist[(b + k) / JMS]];
+            }
             __syncthreads();
             const u32 base = s_off[0];
             // bins [b, b + nbat) hold at most kMergeBatch partials: nbat is the largest n <= wn
@@ -801,7 +806,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 const u32 lo = s_off[0], hi = s_off[1];
                 const u32 t = b / JMS, rb = b - t * JMS;
                 const u32 jm = rb / (u32)kGroupSubBins, qd = rb % (u32)kGroupSubBins;
-                const u64 tk = tkeys[tlist[t]];
+                const u64 tk = s_tk[0];
                 const MapDesc& M = maps[(u32)(tk >> 45)];
                 const int jid = M.job0 + (int)jm;
                 int bx, by, bz;
@@ -873,7 +878,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 const u32 bi = (key - 1u) >> 12, l = (key - 1u) & 4095u;
                 const u32 bb = b + bi;
                 const u32 t = bb / JMS, jm = (bb - t * JMS) / (u32)kGroupSubBins;
-                const u64 tk = tkeys[tlist[t]];
+                const u64 tk = s_tk[bi];
                 const MapDesc& M = maps[(u32)(tk >> 45)];
                 const int jid = M.job0 + (int)jm;
                 int bx, by, bz;
@@ -897,7 +902,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 if (nr) {
                     const u32 bb = b + k;
                     const u32 t = bb / JMS;
-                    const MapDesc& M = maps[(u32)(tkeys[tlist[t]] >> 45)];
+                    const MapDesc& M = maps[(u32)(s_tk[k] >> 45)];
                     atomicAdd(&jst[M.job0 + (bb - t * JMS) / (u32)kGroupSubBins].rays, (u64)nr);
                 }
             }
