@@ -202,6 +202,34 @@ def test_full_sequence_640x480x100_bench_configuration(vbx):
     assert st["points"] == 100 * 640 * 480
 
 
+def test_grouped_tile_pairs_with_an_odd_tile_count(vbx):
+    """A grouped call with more tiles than four times the waves the chip holds, so that the
+    partial-group sort walks two tiles per wave, and an odd tile count, so that the last wave
+    has one: 101 frames of 656x496 pixels (21 x 31 tiles each, the last tile column half
+    full), eleven distinct frames in turn, against the oracle integrating them one by one."""
+    import synth
+    w, h, n_distinct, n = 656, 496, 11, 101
+    tiles = ((w + 31) // 32) * ((h + 15) // 16) * n
+    assert tiles % 2 == 1 and tiles >= 4 * 256 * 32 * 2
+    poses, frame = synth.room_sequence(w, h, n_distinct, seed=synth.SEED_BASE + 91)
+    frames = [frame(k) for k in range(n_distinct)]
+    order = [k % n_distinct for k in range(n)]
+    P = dict(voxel_size=0.05, trunc=0.15, max_range=5.0, weighting="quad", merge="grouped",
+             block_capacity=16384, keep_touches=False)
+    log(f"{n} x {w}x{h} grouped ({tiles} tiles): GPU")
+    d = [dev(f) for f in frames]
+    g = gpu_map(vbx, P)
+    g.integrate_frames([(d[k], poses[k], w) for k in order])
+    assert g.sync() == 0
+    log("  oracle")
+    o = oracle_map(P)
+    for k in order:
+        o.integrate(frames[k], poses[k])
+    res = compare_export(g.export(), o.export(), P)
+    log(f"  ok: {res}")
+    assert g.stats()["points"] == n * w * h
+
+
 def test_tuning_never_changes_results_and_autotune_leaves_map(vbx):
     frames = room(320, 240, 3, 71)
     params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped")
