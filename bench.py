@@ -16,6 +16,10 @@ multi-map call and binary32 storage are timed beside it.
 weight, per-point raycasting), batched in one call; the same sweeps streamed one call each from
 a 256-block pool that the host doubles whenever a sweep finds it full.
 
+--workload accuracy: the accuracy evaluation (trilinear lookup of noise-free surface points in
+maps built at voxel sizes 0.05 / 0.10 / 0.20 m with constant and 1/z^2 weighting) and the
+rate of that distance query.
+
 --workload c5: 64 robots (the four sensor classes above plus a 64x2048 LiDAR) send frames
 as Poisson streams of 5-30 Hz each; a 10 s seeded trace is replayed in real time through
 the map server, which batches whatever has arrived into each tick.  Reports served points/s
@@ -737,10 +741,90 @@ def bench_c5(args, np, torch, vbx, synth):
     }
 
 
+def bench_accuracy(args, np, torch, vbx, synth):
+    """The accuracy evaluation of Sec. V-B on synthetic ground truth, and the query's speed.
+
+    A 40-frame 320x240 sequence of the furnished room (the C2 camera path and depth noise) is
+    integrated at voxel sizes 0.05, 0.10 and 0.20 m with truncation 4 v (as in that
+    evaluation), grouped raycasting, constant and 1/z^2 weighting.  The exact surface points
+    of the same frames (no noise, no dropouts) are then looked up by trilinear interpolation;
+    the error of a known point is |distance| capped at the truncation distance.  The value
+    reported is the query rate of the largest map on 2^24 such points, timed with HIP events
+    on the map's stream."""
+    F, Wd, Hd = 40, 320, 240
+    seed = synth.SEED_BASE + 1
+    poses, frame = synth.room_sequence(Wd, Hd, F, seed)
+    _, frame_gt = synth.room_sequence(Wd, Hd, F, seed, invalid_rate=0.0, noise_scale=0.0)
+    frames = [frame(k) for k in range(F)]
+    gt = []
+    for k in range(F):
+        P = frame_gt(k).astype(np.float64)
+        T = poses[k].astype(np.float64)
+        gt.append(P[np.all(np.isfinite(P), axis=1)] @ T[:, :3].T + T[:, 3])
+    gt = np.concatenate(gt).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    gt = gt[rng.choice(gt.shape[0], size=min(1 << 20, gt.shape[0]), replace=False)]
+    dev_frames = [torch.from_numpy(f).cuda() for f in frames]
+    q = torch.from_numpy(gt).cuda()
+    stream = torch.cuda.current_stream()
+    table = {}
+    big = None
+    for v in (0.05, 0.10, 0.20):
+        row = {}
+        for weighting in ("const", "quad"):
+            m = vbx.Map(v, 4 * v, weighting=weighting, merge="grouped", max_range=5.0,
+                        block_capacity=65536, stream=stream)
+            m.integrate_frames([(dev_frames[k], poses[k], Wd) for k in range(F)])
+            d = m.interpolate(q)
+            if m.sync() != 0:
+                raise vbx.VbxError(m.sync(), "accuracy map")
+            dist = d.cpu().numpy().astype(np.float64)
+            known = np.isfinite(dist)
+            err = np.minimum(np.abs(dist[known]), 4 * v)     # error capped at the truncation
+            row[weighting] = {"mean_m": round(float(err.mean()), 6),
+                              "rms_m": round(float(np.sqrt(np.mean(err * err))), 6),
+                              "known": int(known.sum()), "of": int(dist.size)}
+            if v == 0.05 and weighting == "quad":
+                big = m
+        table[f"v{v:.2f}"] = row
+    # query speed: 2^24 ground-truth points (the sample repeated) on the 0.05 m map
+    nq = 1 << 24
+    reps = (nq + q.shape[0] - 1) // q.shape[0]
+    qq = q.repeat(reps, 1)[:nq].contiguous()
+    for _ in range(args.warmup):
+        big.interpolate(qq)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        big.interpolate(qq)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    rate = nq / (ms * 1e-3)
+    algo = 12 + 4 + 8 * 8          # query in, distance out, eight corner voxels (binary32 D, W)
+    achieved = algo * nq / (ms * 1e-3) / 1e9
+    return {
+        "metric": "trilinear distance queries/s (accuracy evaluation)",
+        "value": round(rate, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"accuracy_room_{Wd}x{Hd}x{F}: voxel 0.05/0.10/0.20 m, truncation 4 v, "
+                               "grouped, const and 1/z^2 weighting; ground truth = noise-free surface "
+                               "points of the same frames", "queries_per_step": nq},
+        "accuracy": table,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(achieved / 8000.0, 4), "traffic": None,
+                     "kernel_stage": "interpolate", "algorithmic_bytes_per_query": algo},
+        "kernel_source_sha": kernel_source_sha(),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "accuracy"])
     ap.add_argument("--no-forms", action="store_true",
                     help="c2: skip timing the plain per-frame f32 and batched f16 forms")
     ap.add_argument("--duration", type=float, default=10.0, help="c5: trace length in seconds")
@@ -782,6 +866,8 @@ def main():
         out = bench_c3(args, np, torch, vbx, synth)
     elif args.workload == "c4":
         out = bench_c4(args, np, torch, vbx, synth)
+    elif args.workload == "accuracy":
+        out = bench_accuracy(args, np, torch, vbx, synth)
     else:
         out = bench_c5(args, np, torch, vbx, synth)
 

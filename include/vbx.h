@@ -211,6 +211,20 @@ int vbx_last_touches(vbx_map* map, int32_t* coords, uint32_t* counts, size_t cap
 /* Cumulative statistics of the map (synchronises). */
 int vbx_map_stats(vbx_map* map, vbx_stats* out);
 
+/* Distance at query points by trilinear interpolation of the map (the accuracy evaluation of
+ * Sec. V-B: ground-truth surface points are looked up in the field, and the interpolated
+ * distance is their error).  points_dev: device [n][3] float32, world frame (metres);
+ * dist_dev: device [n] float32, written with the distance in metres, or NaN where any of the
+ * eight voxels around the point (voxel centres at (i + 1/2) v) is unallocated or unobserved
+ * (W = 0) or the point lies outside the voxel index range.  The corner choice and fractions
+ * are binary32 (u = x * (1/v) - 1/2, corner floor(u), fraction u - floor(u)); the blend runs
+ * along x, then y, then z, in binary32.  Buffers stay owned by the caller and must not overlap.
+ * Stream-ordered on the map's stream and asynchronous (the result is ready after a later
+ * vbx_map_sync or a stream synchronisation).  n <= VBX_MAX_QUERY_POINTS, else VBX_ERR_LIMIT;
+ * VBX_ERR_INVALID_ARG for a NULL map, or NULL buffers with n > 0. */
+#define VBX_MAX_QUERY_POINTS (1u << 31)
+int vbx_map_interpolate(vbx_map* map, const float* points_dev, size_t n, float* dist_dev);
+
 /* Traversal primitive, for verification: for each i < n, the voxels visited between
  * the voxel-space points A_dev[i] and B_dev[i] (dev [n][3] float32), in order,
  * written to out_dev[i][cap][3] (int32), count to counts_dev[i] (may exceed cap;

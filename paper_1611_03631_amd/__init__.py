@@ -63,7 +63,8 @@ EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_ma
             "vbx_map_set_stream", "vbx_integrate", "vbx_integrate_batch", "vbx_integrate_frames",
             "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
-            "vbx_map_stats", "vbx_debug_traverse", "vbx_status_string", "vbx_map_clear",
+            "vbx_map_stats", "vbx_map_interpolate", "vbx_debug_traverse", "vbx_status_string",
+            "vbx_map_clear",
             "vbx_map_profile", "vbx_map_profile_read", "vbx_map_profile_stages", "vbx_profile_stage_name",
             "vbx_map_get_tuning", "vbx_map_set_tuning", "vbx_map_autotune",
             "vbx_graph_create", "vbx_graph_launch", "vbx_graph_destroy",
@@ -126,6 +127,7 @@ def lib(path: Optional[str] = None):
     L.vbx_integrate.argtypes = [vp, f32p, sz, f32p]
     L.vbx_integrate_batch.argtypes = [vp, vp, vp, f32p, i32]
     L.vbx_integrate_frames.argtypes = [vp, ctypes.POINTER(Frame), i32]
+    L.vbx_map_interpolate.argtypes = [vp, vp, sz, vp]
     L.vbx_integrate_multi.argtypes = [vp, ctypes.POINTER(Frame), i32]
     L.vbx_map_sync.argtypes = [vp]
     L.vbx_map_clear_error.argtypes = [vp]
@@ -269,6 +271,15 @@ class Map:
         ptr, n = _dev_points(points)
         pz = _pose12(pose)
         _check(lib().vbx_integrate(self._h, ptr, n, pz.ctypes.data), "vbx_integrate")
+
+    def interpolate(self, points):
+        """Distances at device points float32 [N, 3] by trilinear interpolation (device float32
+        [N], NaN where unknown); stream-ordered on the map's stream."""
+        ptr, n = _dev_points(points)
+        out = torch.empty(n, dtype=torch.float32, device=points.device)
+        _check(lib().vbx_map_interpolate(self._h, ptr, n, out.data_ptr() if n else None),
+               "vbx_map_interpolate")
+        return out
 
     def integrate_frames(self, frames: Sequence[Tuple]):
         """frames: sequence of (points tensor [N,3], pose [3,4]) or (points, pose, width)."""

@@ -1337,6 +1337,19 @@ int vbx_map_stats(vbx_map* m, vbx_stats* out) {
     return VBX_OK;
 }
 
+int vbx_map_interpolate(vbx_map* m, const float* points_dev, size_t n, float* dist_dev) {
+    if (!m || (n > 0 && (!points_dev || !dist_dev))) return VBX_ERR_INVALID_ARG;
+    if (n > (size_t)VBX_MAX_QUERY_POINTS) return VBX_ERR_LIMIT;
+    if (n == 0) return VBX_OK;
+    const MapDesc d = make_desc(m, 0, 0, 0);
+    const unsigned grid = grid_for(n, 8192);
+    if (m->P.storage == VBX_F32)
+        hipLaunchKernelGGL(k_interpolate<0>, dim3(grid), dim3(256), 0, m->stream, d, points_dev, (u32)n, dist_dev);
+    else
+        hipLaunchKernelGGL(k_interpolate<1>, dim3(grid), dim3(256), 0, m->stream, d, points_dev, (u32)n, dist_dev);
+    return hipGetLastError() == hipSuccess ? VBX_OK : VBX_ERR_DEVICE;
+}
+
 int vbx_debug_traverse(const float* A_dev, const float* B_dev, int n, int32_t* out_dev, int cap,
                        int32_t* counts_dev) {
     if (n < 0 || cap < 0 || (n > 0 && (!A_dev || !B_dev || !counts_dev || (cap > 0 && !out_dev))))

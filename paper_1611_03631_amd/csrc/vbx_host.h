@@ -57,6 +57,8 @@ __global__ void k_update(const Job* jobs, const MapDesc* maps, const u64* t_key,
 __global__ void k_order_blocks(const u32* off, u32 JM, u32* order, const CallState* cs);
 __global__ void k_finish_call(const Job* jobs, const MapDesc* maps, int nmaps, JobStat* jst, u64* tkeys,
                               u32 tkey_cap, const u32* tlist, u32 tlist_cap, CallState* cs);
+template <int STORAGE>
+__global__ void k_interpolate(const MapDesc M, const float* q, u32 n, float* out);
 __global__ void k_debug_traverse(const float* A, const float* B, int n, int* out, int cap,
                                  int* counts);
 

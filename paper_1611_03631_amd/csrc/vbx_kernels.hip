@@ -1907,6 +1907,78 @@ __global__ __launch_bounds__(256) void k_finish_call(const Job* __restrict__ job
 }
 
 // ---------------------------------------------------------------------------
+// query: trilinear interpolation of the distance field (the accuracy evaluation, Sec. V-B)
+// ---------------------------------------------------------------------------
+// Voxel (i, j, k) holds the field at its centre ((i, j, k) + 1/2) v.  A query point q takes the
+// eight voxels around it: u = q * (1/v) - 1/2 per axis (binary32, with the map's binary32
+// reciprocal of v), base corner floor(u), fractions f = u - floor(u); the distance is the
+// trilinear blend of the eight corner distances, along x, then y, then z (binary32).  It is
+// known only where all eight voxels are allocated and observed (W > 0); elsewhere the output is
+// NaN.  One thread per query; corners in the block of the previous corner reuse its lookup.
+
+// Pool slot of block key bk in the map's hash (linear probing from mix64), -1 if absent.
+__device__ inline int find_block(const MapDesc& M, u64 bk) {
+    u32 h = (u32)mix64(bk) & M.hmask;
+    for (u32 probe = 0; probe <= M.hmask; ++probe) {
+        const u64 k = M.hkeys[h];
+        if (k == bk) return M.hslots[h];
+        if (k == kEmpty) return -1;
+        h = (h + 1) & M.hmask;
+    }
+    return -1;
+}
+
+template <int STORAGE>
+__global__ __launch_bounds__(256) void k_interpolate(const MapDesc M, const float* __restrict__ q, u32 n,
+                                                     float* __restrict__ out) {
+    for (u32 i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+        int b[3];
+        float f[3];
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float u = q[3 * (size_t)i + k] * M.iv - 0.5f;
+            const float fl = __builtin_floorf(u);
+            ok = ok && fl >= -(float)kVoxLimit && fl < (float)(kVoxLimit - 1);   // false for NaN
+            b[k] = ok ? (int)fl : 0;
+            f[k] = u - fl;
+        }
+        float d[8];
+        u64 last = kEmpty;
+        int slot = -1;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            d[c] = 0.0f;
+            if (!ok) continue;
+            const int gx = b[0] + (c & 1), gy = b[1] + ((c >> 1) & 1), gz = b[2] + (c >> 2);
+            const u64 bk = block_key_of(gx, gy, gz);
+            if (bk != last) {
+                slot = find_block(M, bk);
+                last = bk;
+            }
+            if (slot < 0) {
+                ok = false;
+                continue;
+            }
+            float D, W;
+            load_voxel<STORAGE>(M.pool, (size_t)slot * 4096 + local_of(gx, gy, gz), D, W);
+            if (!(W > 0.0f)) ok = false;
+            d[c] = STORAGE == 0 ? D : D * M.delta;
+        }
+        const float gx = 1.0f - f[0], gy = 1.0f - f[1], gz = 1.0f - f[2];
+        const float c00 = d[0] * gx + d[1] * f[0];
+        const float c10 = d[2] * gx + d[3] * f[0];
+        const float c01 = d[4] * gx + d[5] * f[0];
+        const float c11 = d[6] * gx + d[7] * f[0];
+        const float c0 = c00 * gy + c10 * f[1];
+        const float c1 = c01 * gy + c11 * f[1];
+        out[i] = ok ? c0 * gz + c1 * f[2] : __builtin_nanf("");
+    }
+}
+template __global__ void k_interpolate<0>(const MapDesc, const float*, u32, float*);
+template __global__ void k_interpolate<1>(const MapDesc, const float*, u32, float*);
+
+// ---------------------------------------------------------------------------
 // verification: traversal of voxel-space segments
 // ---------------------------------------------------------------------------
 __global__ void k_debug_traverse(const float* __restrict__ A, const float* __restrict__ B, int n,

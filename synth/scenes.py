@@ -282,9 +282,11 @@ def _room_scene_c2(rng, clear=0.5):
 
 
 def room_sequence(width: int, height: int, n_frames: int, seed: int, phase: float = 0.0,
-                  invalid_rate: float = 0.05):
+                  invalid_rate: float = 0.05, noise_scale: float = 1.0):
     """Camera on a 1.5 m circle at 1.5 m height in a 10x10x3 m furnished room,
-    optical axis radially outward; returns (poses, frame_fn)."""
+    optical axis radially outward; returns (poses, frame_fn).  noise_scale multiplies the
+    depth noise (0 with invalid_rate 0: the exact surface points of the same scene and poses,
+    i.e. ground truth)."""
     rng = np.random.default_rng(seed)
     lo, hi, boxes, spheres = _room_scene_c2(rng)
     poses = []
@@ -302,7 +304,7 @@ def room_sequence(width: int, height: int, n_frames: int, seed: int, phase: floa
         return np.minimum(t, _hit_spheres(o, d, spheres))
 
     def sigma(z):
-        return 0.0012 + 0.0019 * (z - 0.4) ** 2
+        return noise_scale * (0.0012 + 0.0019 * (z - 0.4) ** 2)
 
     def frame(k):
         frng = np.random.default_rng([seed, 104729, k])
