@@ -52,3 +52,14 @@ def test_library_has_no_oracle_code(libpath):
     """The product library never contains the oracle's symbols."""
     out = open(libpath, "rb").read()
     assert b"orc_integrate" not in out and b"orc_dda" not in out
+
+
+def test_interpolate_rejects_bad_arguments_before_any_device_work(libpath):
+    """A NULL map, or NULL buffers with points to query, are refused on the host."""
+    lib = ctypes.CDLL(libpath)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.vbx_map_interpolate.argtypes = [vp, vp, sz, vp]
+    lib.vbx_map_interpolate.restype = ctypes.c_int
+    import paper_1611_03631_amd as vbx
+    assert lib.vbx_map_interpolate(None, None, 0, None) == vbx.ERR_INVALID_ARG
+    assert lib.vbx_map_interpolate(None, None, 5, None) == vbx.ERR_INVALID_ARG
