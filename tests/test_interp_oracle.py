@@ -100,3 +100,66 @@ def test_surface_error_caps_at_truncation():
     s = interp.surface_error(np.array([0.01, -0.02, np.nan, 5.0]), 0.1)
     assert s["known"] == 3 and s["total"] == 4
     assert abs(s["mean"] - (0.01 + 0.02 + 0.1) / 3) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Planted mistakes: each altered copy of the oracle must fail at least one pin above.
+# ---------------------------------------------------------------------------
+MISTAKES = [
+    ("transposed voxel index", "16 * int(g[1] & 15) + 256 * int(g[2] & 15)",
+     "256 * int(g[1] & 15) + 16 * int(g[2] & 15)"),
+    ("swapped lerp weights", "cx0 = d[:, :, 0] * (1.0 - f[0]) + d[:, :, 1] * f[0]",
+     "cx0 = d[:, :, 0] * f[0] + d[:, :, 1] * (1.0 - f[0])"),
+    ("fraction of the wrong axis", "cy0 = cx0[:, 0] * (1.0 - f[1]) + cx0[:, 1] * f[1]",
+     "cy0 = cx0[:, 0] * (1.0 - f[2]) + cx0[:, 1] * f[2]"),
+    ("no half-voxel shift", "u = pts[p] * iv - np.float32(0.5)", "u = pts[p] * iv"),
+    ("round instead of floor", "fl = np.floor(u)", "fl = np.round(u)"),
+    ("every corner in the base corner's block",
+     "blk = index.get((int(g[0] >> 4), int(g[1] >> 4), int(g[2] >> 4)))",
+     "blk = index.get((int(base[0] >> 4), int(base[1] >> 4), int(base[2] >> 4)))"),
+    ("unobserved corners accepted", "if not W[blk, loc] > 0:", "if False:"),
+    ("error not capped", "e = np.minimum(np.abs(dist[known]), trunc)", "e = np.abs(dist[known])"),
+]
+
+
+def _altered(old, new):
+    import oracle.interp as mod
+    src = open(mod.__file__).read()
+    assert src.count(old) == 1, old
+    ns = {"__name__": "altered_interp"}
+    exec(compile(src.replace(old, new), "altered_interp", "exec"), ns)
+
+    class M:
+        pass
+    m = M()
+    m.interpolate, m.surface_error = ns["interpolate"], ns["surface_error"]
+    return m
+
+
+def _pins_pass(mod):
+    global interp
+    saved = interp
+    interp = mod
+    try:
+        for check in (lambda: test_linear_field_is_reproduced_across_blocks_and_signs(0.05),
+                      lambda: test_linear_field_is_reproduced_across_blocks_and_signs(0.2),
+                      test_voxel_centres_return_the_voxel_value,
+                      test_missing_or_unobserved_corner_is_unknown,
+                      test_surface_error_caps_at_truncation):
+            try:
+                check()
+            except AssertionError:
+                return False
+        return True
+    finally:
+        interp = saved
+
+
+def test_pins_pass_on_the_oracle_itself():
+    import oracle.interp as mod
+    assert _pins_pass(mod)
+
+
+@pytest.mark.parametrize("name,old,new", MISTAKES, ids=[m[0] for m in MISTAKES])
+def test_planted_mistake_is_caught(name, old, new):
+    assert not _pins_pass(_altered(old, new)), f"no pin catches: {name}"
