@@ -38,7 +38,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("voxel_size", ctypes.c_float), ("trunc", ctypes.c_float),
                 ("w_max", ctypes.c_float), ("max_range", ctypes.c_float),
                 ("z_min", ctypes.c_float), ("weighting", ctypes.c_int),
-                ("merge", ctypes.c_int), ("fp16", ctypes.c_int), ("dist", ctypes.c_int)]
+                ("merge", ctypes.c_int), ("fp16", ctypes.c_int), ("dist", ctypes.c_int),
+                ("world64", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -113,13 +114,15 @@ class OracleMap:
     def __init__(self, voxel_size: float, trunc: float, weighting: str = "const",
                  merge: str = "simple", w_max: float = 1e4, max_range: float = 5.0,
                  z_min: float = 0.1, storage: str = "f32", dist: str = "eq1",
-                 lib_path: Optional[str] = None):
+                 world64: bool = False, lib_path: Optional[str] = None):
+        """world64: measure distances from the binary64 transform of each sensor point (and a
+        group's exact binary64 mean) instead of the binary32 ray end point."""
         self.lib = load(lib_path)
         self.params = dict(voxel_size=voxel_size, trunc=trunc, weighting=weighting,
                            merge=merge, w_max=w_max, max_range=max_range, z_min=z_min,
-                           storage=storage, dist=dist)
+                           storage=storage, dist=dist, world64=world64)
         p = _Params(voxel_size, trunc, w_max, max_range, z_min, WEIGHTING[weighting],
-                    MERGE[merge], 1 if storage == "f16" else 0, DIST[dist])
+                    MERGE[merge], 1 if storage == "f16" else 0, DIST[dist], 1 if world64 else 0)
         self._h = self.lib.orc_create(ctypes.byref(p))
 
     def close(self):

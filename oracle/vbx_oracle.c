@@ -18,7 +18,14 @@
  *    operation order written below.  These are the decisions the GPU kernel
  *    takes too, so both sides must take them in the same precision.
  *  - Values (the distances d, weights w, and the running D, W of Eqs. (3)-(4))
- *    are computed in binary64 from the binary32 inputs promoted exactly.
+ *    are computed in binary64.  The point p of Eq. (1) is the ray's end point
+ *    as the geometry tier fixes it (the binary32 world point, or the binary32
+ *    end point of a group's ray), promoted exactly: the voxels a ray visits and
+ *    the distances it reports are measured from one and the same point.  The
+ *    voxel centre is (g + 1/2) v with v the binary32 voxel size, exact in
+ *    binary64.  With world64 set, p is instead the binary64 transform of the
+ *    sensor point (and a group's exact binary64 weighted mean): that mode
+ *    measures how far binary32 world coordinates move the field.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math (x86-64 SSE: every
  * float operation is rounded to binary32).
@@ -65,6 +72,7 @@ typedef struct {
     int merge;         /* 0: raycast every point; 1: grouped raycasting */
     int fp16;          /* 1: round D/delta and W to binary16 after every frame */
     int dist;          /* 0: Eq. (1); 1: projective distance along the ray */
+    int world64;       /* 1: distances from the binary64 world point (see the header) */
 } orc_params;
 
 typedef struct {
@@ -256,7 +264,7 @@ int orc_dda(const float A[3], const float B[3], int32_t* out, int cap) {
 /* ------------------------------------------------------------------ */
 typedef struct {
     float p32[3];     /* ray end point used for traversal and the sign of Eq. (1) */
-    double p64[3];    /* ray end point used for distance values */
+    double p64[3];    /* ray end point used for distance values (binary64) */
     double wgt;       /* 1 or 1/z^2 for a point; the summed point weights for a group */
 } orc_ray;
 
@@ -467,7 +475,10 @@ int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], 
     size_t nr = 0;
     if (P->merge == 0) {
         for (size_t i = 0; i < nv; ++i) {
-            for (int k = 0; k < 3; ++k) { rays[nr].p32[k] = p32[3 * i + k]; rays[nr].p64[k] = p64[3 * i + k]; }
+            for (int k = 0; k < 3; ++k) {
+                rays[nr].p32[k] = p32[3 * i + k];
+                rays[nr].p64[k] = P->world64 ? p64[3 * i + k] : (double)p32[3 * i + k];
+            }
             rays[nr].wgt = w64[i];
             nr++;
         }
@@ -495,7 +506,10 @@ int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], 
                 for (int k = 0; k < 3; ++k) sp[k] += w64[i] * p64[3 * i + k];
             }
             orc_group_mean(gp, gw, cnt, v, wbits, rays[nr].p32);
-            for (int k = 0; k < 3; ++k) rays[nr].p64[k] = cnt == 1 ? p64[3 * ki[lo].idx + k] : sp[k] / sw;
+            for (int k = 0; k < 3; ++k) {
+                if (P->world64) rays[nr].p64[k] = cnt == 1 ? p64[3 * ki[lo].idx + k] : sp[k] / sw;
+                else rays[nr].p64[k] = (double)rays[nr].p32[k];
+            }
             rays[nr].wgt = sw;
             nr++;
             lo = hi;

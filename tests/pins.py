@@ -245,6 +245,174 @@ def pin_dropoff_values(lib_path=None):
             assert abs(got[g][0] - dv * V) <= 1e-12
 
 
+
+def _identity_pose():
+    T = np.zeros((3, 4), np.float32)
+    T[:, :3] = np.eye(3)
+    T[:, 3] = [0.0625 + 0.25, 0.0625 - 0.5, 0.0625 + 0.125]   # a voxel centre at v = 0.125
+    return T
+
+
+def _exact_dist(p, s, g, mode):
+    """Eq. (1) (mode "eq1") or the projective distance along the ray (mode "ray") of voxel g's
+    centre, from exact rational p, s; returns (d as float, exact dot product)."""
+    x = [(Fr(int(gk)) + Fr(1, 2)) * Fr(V) for gk in g]
+    f = [p[k] - x[k] for k in range(3)]
+    e = [p[k] - s[k] for k in range(3)]
+    dot = sum(f[k] * e[k] for k in range(3))
+    if mode == "ray":
+        return float(dot) / math.sqrt(float(sum(ek * ek for ek in e))), dot
+    mag = math.sqrt(float(sum(fk * fk for fk in f)))
+    return (mag if dot > 0 else (-mag if dot < 0 else 0.0)), dot
+
+
+def pin_along_ray_off_axis(lib_path=None):
+    """Oblique rays whose band passes beside voxel centres: under the projective reading (Sec. I,
+    the distance along the sensor ray) d = (p - x).(p - s) / |p - s|, under Eq. (1)
+    d = |p - x| sign((p - x).(p - s)); after one frame D = clamp(d, +-delta) and W = f(d) / z^2.
+    The inputs are dyadic, so p and s are exact and the ray length is irrational; the two
+    readings differ by a large fraction of a voxel on most of the band's voxels."""
+    pose = _identity_pose()
+    s = [Fr(float(c)) for c in pose[:, 3]]
+    differ = 0
+    for q in ([0.75, 0.5, 1.3125], [-0.625, 0.375, 1.0625], [0.3125, -0.8125, 0.875]):
+        q32 = np.array([q], np.float32)
+        p = [s[k] + Fr(q[k]) for k in range(3)]       # identity rotation: exact in binary32
+        om = 1.0 / (q[2] * q[2])
+        for mode in ("ray", "eq1"):
+            for weighting in ("const", "quad"):
+                m = oracle.OracleMap(V, DELTA, weighting=weighting, merge="simple", w_max=1e30,
+                                     max_range=10.0, dist=mode, lib_path=lib_path)
+                m.integrate(q32, pose)
+                tc, _ = m.last_touches()
+                got, _ = _export_dict(m)
+                checked = 0
+                for g in map(tuple, tc.tolist()):
+                    d, dot = _exact_dist(p, s, g, mode)
+                    if mode == "eq1" and abs(dot) < 1e-9:
+                        continue              # the sign is decided in binary32 there
+                    if weighting == "const" and mode == "ray":
+                        d1, _ = _exact_dist(p, s, g, "eq1")
+                        differ += abs(d1 - d) > 0.05 * V
+                    f = 1.0 if (weighting == "const" or d > -V) else (
+                        (d + DELTA) / (DELTA - V) if d > -DELTA else 0.0)
+                    w = f * (1.0 if weighting == "const" else om)
+                    if w == 0.0:
+                        assert g not in got, f"{mode}: weight behind -delta must be 0 at {g}"
+                        continue
+                    dc = max(-DELTA, min(DELTA, d))
+                    assert abs(got[g][0] - dc) <= 1e-12, f"{mode} D at {g}: {got[g][0]} vs {dc}"
+                    assert abs(got[g][1] - w) <= 1e-12 * w, f"{mode} W at {g}: {got[g][1]} vs {w}"
+                    checked += 1
+                assert checked >= 5
+                m.close()
+    assert differ >= 6, "geometry does not separate the two distance readings"
+
+
+def _f16(x):
+    """Binary16 rounding by numpy's conversion (round to nearest even)."""
+    return float(np.float16(x))
+
+
+def pin_binary16_sequence(lib_path=None):
+    """Binary16 storage: after every frame D / delta and W are rounded to binary16, W after the
+    Eq. (4) cap.  A head-on sequence worked in exact arithmetic with numpy's float16 rounding:
+    frames of repeated points (constant weighting, so each frame's sums are exact), W stalling at
+    2048 (2049 is not a binary16 number and rounds to even), D stalling where a frame moves it by
+    less than half a binary16 step, and W_max = 2999 (not a binary16 number) reached inside a frame,
+    where the cap comes first and the rounding then gives 3000."""
+    pose = _axis_pose(2, 1)
+    sz = Fr(float(pose[2, 3]))
+    wmax = 2999.0
+    m = oracle.OracleMap(V, DELTA, weighting="const", merge="simple", w_max=wmax,
+                         max_range=10.0, storage="f16", lib_path=lib_path)
+    frames = [(3, 1.3125), (1, 1.34375), (2, 1.28125), (2041, 1.3125), (1, 1.3125),
+              (1, 1.375), (1000, 1.25), (1, 1.3125)]
+    state = {}                    # voxel z index -> (D / delta, W) as stored (binary16 values)
+    ix, iy = math.floor(float(pose[0, 3]) / V), math.floor(float(pose[1, 3]) / V)
+    stalled_d = 0
+    for f, (n, Z) in enumerate(frames):
+        pz = sz + Fr(Z)
+        lo, hi = math.floor((pz - Fr(DELTA)) / Fr(V)), math.floor((pz + Fr(DELTA)) / Fr(V))
+        m.integrate(np.repeat(np.array([[0.0, 0.0, Z]], np.float32), n, axis=0), pose)
+        for gz in range(lo, hi + 1):
+            d = pz - (Fr(gz) + Fr(1, 2)) * Fr(V)
+            dc = max(Fr(-DELTA), min(Fr(DELTA), d))
+            D0, W0 = state.get(gz, (0.0, 0.0))
+            exact = (Fr(W0) * Fr(D0) + n * dc / Fr(DELTA)) / (Fr(W0) + n)
+            D1 = _f16(float(exact))
+            W1 = _f16(min(W0 + n, wmax))
+            if f == 5 and D1 == D0 and exact != Fr(D0):
+                stalled_d += 1
+            state[gz] = (D1, W1)
+        centre = state[math.floor(pz / Fr(V))]
+        if f == 5:
+            assert centre[1] == 2048.0, "W must stall at 2048 (2049 rounds to even)"
+        if f >= 6:
+            assert centre[1] == 3000.0, "W capped at 2999, then rounded to binary16"
+    assert stalled_d >= 1, "sequence does not exercise a stalled D"
+    got, _ = _export_dict(m)
+    for gz, (Dq, Wq) in state.items():
+        g = (ix, iy, gz)
+        assert got[g][1] == Wq, f"W at {g}: {got[g][1]} vs {Wq}"
+        assert got[g][0] == Dq * DELTA, f"D at {g}: {got[g][0] / DELTA} vs {Dq} (units of delta)"
+    m.close()
+
+    # 1/z^2 weights (not binary16 numbers) on the Eq. (5) ramp, one ray per frame
+    m = oracle.OracleMap(V, DELTA, weighting="quad", merge="simple", w_max=1e4,
+                         max_range=10.0, storage="f16", lib_path=lib_path)
+    state = {}
+    for Z in (1.25, 1.1875, 1.3125, 1.25, 1.21875):
+        pz = float(sz) + Z
+        m.integrate(np.array([[0.0, 0.0, Z]], np.float32), pose)
+        om = 1.0 / (Z * Z)
+        for gz in range(math.floor((pz - DELTA) / V), math.floor((pz + DELTA) / V) + 1):
+            d = pz - (gz + 0.5) * V
+            fd = 1.0 if d > -V else ((d + DELTA) / (DELTA - V) if d > -DELTA else 0.0)
+            w = om * fd
+            if w == 0.0:
+                continue
+            D0, W0 = state.get(gz, (0.0, 0.0))
+            dc = max(-DELTA, min(DELTA, d))
+            state[gz] = (_f16((W0 * D0 + w * (dc / DELTA)) / (W0 + w)), _f16(min(W0 + w, 1e4)))
+    got, _ = _export_dict(m)
+    for gz, (Dq, Wq) in state.items():
+        g = (ix, iy, gz)
+        assert got[g][1] == Wq and got[g][0] == Dq * DELTA, f"quad binary16 at {g}"
+    m.close()
+
+
+def pin_ramp_diagnostic(lib_path=None):
+    """The ramp diagnostic of the oracle's export: per voxel, the summed point weight 1/z^2 of the
+    rays that saw it on the Eq. (5) drop-off ramp, -delta < d <= -eps (on the head-on axis d is
+    the signed distance to the plane).  It takes no part in D or W."""
+    pose = _axis_pose(2, 1)
+    sz = float(pose[2, 3])
+    ix, iy = math.floor(float(pose[0, 3]) / V), math.floor(float(pose[1, 3]) / V)
+    m = oracle.OracleMap(V, DELTA, weighting="quad", merge="simple", w_max=1e30,
+                         max_range=10.0, lib_path=lib_path)
+    expect = {}
+    # end points at voxel centres (d = -eps and d = -delta exactly on the band) and between them
+    for n, Z in ((1, 1.0), (2, 1.0625), (1, 1.5), (3, 0.96875)):
+        m.integrate(np.repeat(np.array([[0.0, 0.0, Z]], np.float32), n, axis=0), pose)
+        pz = sz + Z
+        for gz in range(math.floor((pz - DELTA) / V), math.floor((pz + DELTA) / V) + 1):
+            d = pz - (gz + 0.5) * V
+            expect.setdefault(gz, 0.0)
+            if -DELTA < d <= -V:
+                expect[gz] += n / (Z * Z)
+    coords, D, W, mass, ramp = m.export()
+    seen = 0
+    for b in range(coords.shape[0]):
+        for l in range(4096):
+            g = (16 * coords[b, 0] + (l & 15), 16 * coords[b, 1] + ((l >> 4) & 15),
+                 16 * coords[b, 2] + (l >> 8))
+            r = expect.get(int(g[2]), 0.0) if (g[0], g[1]) == (ix, iy) else 0.0
+            assert abs(ramp[b, l] - r) <= 1e-12 * max(1.0, r), f"ramp weight at {g}: {ramp[b, l]} vs {r}"
+            seen += r > 0
+    assert seen >= 3
+    m.close()
+
 # --------------------------------------------------------------------------
 # accumulation: weight sums, counts and D against exact enumeration
 # --------------------------------------------------------------------------
@@ -252,6 +420,17 @@ def _rand_rays(rng, n, spread=0.6):
     pts = rng.uniform(-spread, spread, size=(n, 3))
     pts[:, 2] = rng.uniform(0.9, 1.6, size=n)
     return pts.astype(np.float32)
+
+
+def world_point32(pose, q):
+    """Binary32 world point ((R0 x + R1 y) + R2 z) + t of a sensor point, every operation rounded
+    to binary32 (numpy float32 scalars), in the order the geometry tier fixes."""
+    T = np.asarray(pose, np.float32).reshape(3, 4)
+    x, y, z = (np.float32(c) for c in np.asarray(q, np.float32).reshape(3))
+    out = np.zeros(3, np.float32)
+    for k in range(3):
+        out[k] = ((T[k, 0] * x + T[k, 1] * y) + T[k, 2] * z) + T[k, 3]
+    return out
 
 
 def pin_weight_sums(lib_path=None, seed=5):
@@ -268,12 +447,14 @@ def pin_weight_sums(lib_path=None, seed=5):
         m = oracle.OracleMap(v, delta, weighting=weighting, merge="simple", w_max=1e30,
                              max_range=5.0, z_min=0.1, lib_path=lib_path)
         m.integrate(pts, pose)
-        R = pose[:, :3].astype(np.float64)
         s = pose[:, 3].astype(np.float64)
         acc = {}
         skipped = 0
-        for q in pts.astype(np.float64):
-            p = R @ q + s
+        for q32 in pts:
+            # the world point is the binary32 transform (fixed order, no fused multiply-add);
+            # Eq. (1) is then evaluated exactly from it
+            p = world_point32(pose, q32).astype(np.float64)
+            q = q32.astype(np.float64)
             e = p - s
             r = np.linalg.norm(e)
             u = e / r
@@ -468,5 +649,6 @@ def pin_permutation(lib_path=None, seed=9):
 
 
 ALL_PINS = [pin_dda_dyadic, pin_dda_random, pin_head_on_plane, pin_dropoff_values,
+            pin_along_ray_off_axis, pin_binary16_sequence, pin_ramp_diagnostic,
             pin_weight_sums, pin_group_mean, pin_merged_singletons, pin_identical_points,
             pin_running_average, pin_validity, pin_round_half, pin_permutation]
