@@ -742,7 +742,7 @@ def bench_c5(args, np, torch, vbx, synth):
 
 
 def bench_accuracy(args, np, torch, vbx, synth):
-    """The accuracy evaluation of Sec. V-B on synthetic ground truth, and the query's speed.
+    """The accuracy evaluation of Sec. VI-A on synthetic ground truth, and the query's speed.
 
     A 40-frame 320x240 sequence of the furnished room (the C2 camera path and depth noise) is
     integrated at voxel sizes 0.05, 0.10 and 0.20 m with truncation 4 v (as in that

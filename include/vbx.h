@@ -51,9 +51,19 @@ typedef enum { VBX_W_CONST = 0, VBX_W_QUAD = 1 } vbx_weighting;
  * one voxel are merged into one ray cast towards their weighted mean. */
 typedef enum { VBX_MERGE_NONE = 0, VBX_MERGE_GROUPED = 1 } vbx_merge;
 
-/* Storage of the per-voxel distance D and weight W: binary32 pairs (8 B/voxel)
- * or binary16 pairs (4 B/voxel, D stored as D/trunc); arithmetic is binary32. */
-typedef enum { VBX_F32 = 0, VBX_F16 = 1 } vbx_storage;
+/* Storage of the per-voxel distance D and weight W of Eqs. (3)-(4); the arithmetic is
+ * binary32 in every mode, and the stored values are rounded (to nearest, ties to even) once
+ * per frame after the update.
+ *  VBX_F32: binary32 D (metres) and W, 8 B/voxel.
+ *  VBX_F16: binary16 D/trunc and W, 4 B/voxel.  Near |D| = trunc a binary16 D/trunc has
+ *           11 significant bits, so each frame's rounding moves D by up to 2^-12 trunc.
+ *  VBX_S16: D/trunc as a signed 16-bit fixed-point number (D/trunc = i / 32767, |i| <= 32767)
+ *           and W as binary16, 4 B/voxel: the same bytes, with a uniform distance step of
+ *           trunc / 32767 everywhere in the band.
+ * In both 16-bit modes a frame's update is lost once it is below half a storage step: W stops
+ * growing once the frame's summed weight is below half a binary16 ulp of W (W >= 2048 times
+ * that weight), and D stops moving once W_sum |d - D| / (W + W_sum) is below half a step. */
+typedef enum { VBX_F32 = 0, VBX_F16 = 1, VBX_S16 = 2 } vbx_storage;
 
 /* Distance of Eq. (1) (Euclidean norm with the sign of the projection on the
  * ray) or the projective distance along the ray (Sec. I). */
@@ -71,7 +81,7 @@ enum {
 typedef struct {
     float voxel_size;        /* v, metres, > 0 */
     float trunc;             /* delta, metres, > 0 (the paper uses 4v; 3v is common) */
-    float w_max;             /* W_max of Eq. (4); <= 65504 for VBX_F16 */
+    float w_max;             /* W_max of Eq. (4); <= 65504 for VBX_F16 and VBX_S16 */
     float max_range;         /* points farther than this from the sensor are rejected */
     float z_min;             /* VBX_W_QUAD: points with depth z < z_min are rejected; >= 0.05 */
     int32_t weighting;       /* vbx_weighting */
@@ -81,6 +91,17 @@ typedef struct {
     uint32_t block_capacity; /* blocks the pool holds; vbx_map_reserve grows it */
     uint32_t flags;          /* VBX_FLAG_* */
     void* stream;            /* hipStream_t to run on (NULL: the null stream) */
+    /* Allocator hook for the map's own device memory: the block hash table, the block pool
+     * and the map's device state (a map holds its layer of blocks, Sec. III).  alloc(bytes,
+     * alloc_ctx) returns device memory of the current device, aligned to 256 bytes, or NULL
+     * when it cannot (the call that needed it then fails with VBX_ERR_OUT_OF_MEMORY and
+     * leaves the map as it was); free(ptr, alloc_ctx) returns it.  Both NULL (the default):
+     * hipMalloc and hipFree.  Setting only one of them is VBX_ERR_INVALID_ARG.  The hooks are
+     * called from the thread that creates, grows or destroys the map, never from a stream.
+     * Per-call scratch memory is not the map's storage and always comes from hipMalloc. */
+    void* (*alloc)(size_t bytes, void* alloc_ctx);
+    void (*free)(void* ptr, void* alloc_ctx);
+    void* alloc_ctx;
 } vbx_map_params;
 
 /* One depth or LiDAR frame. */
@@ -135,8 +156,10 @@ int vbx_map_set_stream(vbx_map* map, void* stream);
  * All observations of one frame that reach a voxel are merged in one update. */
 int vbx_integrate(vbx_map* map, const float* points_dev, size_t n, const float pose[12]);
 
-/* Integrates F frames in order in one pipelined pass.  The result is bit-identical
- * to F consecutive vbx_integrate calls.  points_dev: host array of F dev pointers;
+/* Integrates F frames in order in one pipelined pass (Sec. IV: every frame's observations
+ * are merged by Eqs. (3)-(4) in frame order; the frames' rays are independent of the map, so
+ * their contributions are computed together and each voxel folds them in order).  The
+ * result is bit-identical to F consecutive vbx_integrate calls.  points_dev: host array of F dev pointers;
  * n: host [F]; poses: host [F][12]. */
 int vbx_integrate_batch(vbx_map* map, const float* const* points_dev, const size_t* n,
                         const float* poses, int F);
@@ -145,12 +168,14 @@ int vbx_integrate_batch(vbx_map* map, const float* const* points_dev, const size
 int vbx_integrate_frames(vbx_map* map, const vbx_frame* frames, int F);
 
 /* Integrates frames[i] into maps[i] for i < M (distinct maps on one device) in one
- * pipelined pass on maps[0]'s stream, using maps[0]'s scratch memory.  Each map's
+ * pipelined pass on maps[0]'s stream, using maps[0]'s scratch memory.  Each map is
+ * integrated as in vbx_integrate (Sec. IV); batching independent maps into one pass is this
+ * library's own pattern (the paper integrates one map).  Each map's
  * result is bit-identical to integrating its frame alone. */
 int vbx_integrate_multi(vbx_map* const* maps, const vbx_frame* frames, int M);
 
 /* ---- captured calls ---------------------------------------------------------------
- * A graph is one integration call (the same work as vbx_integrate_multi, or as
+ * This library's own pattern, not the paper's.  A graph is one integration call (the same work as vbx_integrate_multi, or as
  * vbx_integrate_frames for M = 1) captured once into a HIP graph and replayed with one
  * hipGraphLaunch per call, which removes the per-kernel launch cost of small frames
  * (the many-maps-per-tick pattern).  It is bound to its maps and to the point count and
@@ -191,14 +216,15 @@ int vbx_map_reserve(vbx_map* map, uint32_t block_capacity);
 /* Number of allocated blocks (synchronises). */
 int vbx_map_num_blocks(vbx_map* map, size_t* n_out);
 
-/* Exports every block in ascending (bx, by, bz) order (synchronises).
+/* Exports the map's layer of blocks (Sec. III: blocks of voxels indexed by their position
+ * through a hash table) in ascending (bx, by, bz) order (synchronises).
  * coords: host [cap][3] int32 block indices or NULL; dw: host [cap][4096][2] float32
  * (D in metres, W) or NULL.  With both NULL only *n_out is written.  Returns
  * VBX_ERR_BUFFER_TOO_SMALL if cap is smaller than the block count. */
 int vbx_export_blocks(vbx_map* map, int32_t* coords, float* dw, size_t cap, size_t* n_out);
 
-/* Replaces the map content with n blocks (coords host [n][3], dw host [n][4096][2],
- * D in metres) — the inverse of vbx_export_blocks (checkpoint / resume).  Values
+/* Replaces the map content with n blocks (Sec. III layer of blocks; coords host [n][3], dw
+ * host [n][4096][2], D in metres) — the inverse of vbx_export_blocks (checkpoint / resume).  Values
  * are rounded to the map's storage type.  Synchronises. */
 int vbx_import_blocks(vbx_map* map, const int32_t* coords, const float* dw, size_t n);
 
@@ -212,7 +238,7 @@ int vbx_last_touches(vbx_map* map, int32_t* coords, uint32_t* counts, size_t cap
 int vbx_map_stats(vbx_map* map, vbx_stats* out);
 
 /* Distance at query points by trilinear interpolation of the map (the accuracy evaluation of
- * Sec. V-B: ground-truth surface points are looked up in the field, and the interpolated
+ * Sec. VI-A: ground-truth surface points are looked up in the field, and the interpolated
  * distance is their error).  points_dev: device [n][3] float32, world frame (metres);
  * dist_dev: device [n] float32, written with the distance in metres, or NaN where any of the
  * eight voxels around the point (voxel centres at (i + 1/2) v) is unallocated or unobserved
@@ -282,7 +308,8 @@ int vbx_map_autotune(vbx_map* map, const vbx_frame* frames, int F, vbx_tuning* b
                      double* ms_out);
 
 /* ---- map server ---------------------------------------------------------------------
- * Many maps (one per robot or sensor) served from one device: integration requests
+ * This library's own serving pattern (the paper integrates one map on one CPU core); each
+ * frame is integrated as in vbx_integrate (Sec. IV).  Many maps (one per robot or sensor) served from one device: integration requests
  * arrive one frame at a time, each for one map; the server batches whatever has arrived
  * into the next call ("tick", the vbx_integrate_multi pass, several frames per map
  * allowed) while the previous tick still runs, so batches form continuously.  Requests

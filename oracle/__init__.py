@@ -83,6 +83,8 @@ def load(path: Optional[str] = None):
                                    ctypes.c_float, ctypes.c_int, ctypes.c_void_p]
     lib.orc_round_half.restype = ctypes.c_double
     lib.orc_round_half.argtypes = [ctypes.c_double]
+    lib.orc_round_s16.restype = ctypes.c_double
+    lib.orc_round_s16.argtypes = [ctypes.c_double]
     _libs[path] = lib
     return lib
 
@@ -94,6 +96,9 @@ def _ptr(a: np.ndarray):
 WEIGHTING = {"const": 0, "quad": 1}
 MERGE = {"simple": 0, "grouped": 1}
 DIST = {"eq1": 0, "ray": 1}
+# value storage emulated after every frame: none (binary64), binary16 D/delta and W, or D/delta
+# to the nearest multiple of 1/32767 with binary16 W
+STORAGE = {"f32": 0, "f16": 1, "s16": 2}
 
 
 def weight_bits(weighting: str, z_min: float) -> int:
@@ -122,7 +127,7 @@ class OracleMap:
                            merge=merge, w_max=w_max, max_range=max_range, z_min=z_min,
                            storage=storage, dist=dist, world64=world64)
         p = _Params(voxel_size, trunc, w_max, max_range, z_min, WEIGHTING[weighting],
-                    MERGE[merge], 1 if storage == "f16" else 0, DIST[dist], 1 if world64 else 0)
+                    MERGE[merge], STORAGE[storage], DIST[dist], 1 if world64 else 0)
         self._h = self.lib.orc_create(ctypes.byref(p))
 
     def close(self):
@@ -194,3 +199,7 @@ def group_mean(p32, w32, voxel_size: float, wbits: int, lib_path: Optional[str] 
 
 def round_half(x: float, lib_path: Optional[str] = None) -> float:
     return float(load(lib_path).orc_round_half(float(x)))
+
+
+def round_s16(x: float, lib_path: Optional[str] = None) -> float:
+    return float(load(lib_path).orc_round_s16(float(x)))

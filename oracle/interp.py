@@ -1,6 +1,6 @@
 """Oracle of the distance query by trilinear interpolation (test infrastructure).
 
-Only the test-suite may import this module; the product library never loads it.  It follows the accuracy evaluation of Sec. V-B: a ground-truth surface point is
+Only the test-suite may import this module; the product library never loads it.  It follows the accuracy evaluation of Sec. VI-A: a ground-truth surface point is
 looked up in the distance field by trilinear interpolation over the eight voxels around it,
 and the interpolated distance is that point's error.
 

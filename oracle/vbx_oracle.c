@@ -70,7 +70,9 @@ typedef struct {
     float z_min;       /* quadratic weighting: smallest accepted depth */
     int weighting;     /* 0: Eq. (2) constant; 1: Eq. (5) quadratic with drop-off */
     int merge;         /* 0: raycast every point; 1: grouped raycasting */
-    int fp16;          /* 1: round D/delta and W to binary16 after every frame */
+    int fp16;          /* 1: round D/delta and W to binary16 after every frame;
+                          2: round D/delta to the nearest multiple of 1/32767 (ties to even)
+                          and W to binary16 after every frame (16-bit fixed-point distance) */
     int dist;          /* 0: Eq. (1); 1: projective distance along the ray */
     int world64;       /* 1: distances from the binary64 world point (see the header) */
 } orc_params;
@@ -209,6 +211,15 @@ double orc_round_half(double x) {
     double r = nearbyint(ax / ulp) * ulp;
     if (r > 65504.0) r = 65504.0;
     return copysign(r, x);
+}
+
+/* Fixed-point distance storage: D/delta as i / 32767 with |i| <= 32767, i the nearest integer
+   to 32767 D/delta (ties to even). */
+double orc_round_s16(double x) {
+    double i = nearbyint(x * 32767.0);
+    if (i > 32767.0) i = 32767.0;
+    if (i < -32767.0) i = -32767.0;
+    return i / 32767.0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -538,7 +549,7 @@ int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], 
             vx->D = (vx->W * vx->D + vx->swd) / (vx->W + vx->sw);
             vx->W = vx->W + vx->sw < wmax ? vx->W + vx->sw : wmax;
             if (P->fp16) {
-                vx->D = orc_round_half(vx->D);
+                vx->D = P->fp16 == 2 ? orc_round_s16(vx->D) : orc_round_half(vx->D);
                 vx->W = orc_round_half(vx->W);
             }
         }

@@ -24,7 +24,7 @@ from .build import LIB as _LIB_PATH, build as build_library  # noqa: F401
 # ---------------------------------------------------------------------------
 W_CONST, W_QUAD = 0, 1
 MERGE_NONE, MERGE_GROUPED = 0, 1
-F32, F16 = 0, 1
+F32, F16, S16 = 0, 1, 2
 DIST_EQ1, DIST_ALONG_RAY = 0, 1
 FLAG_KEEP_TOUCHES = 1
 
@@ -39,13 +39,20 @@ class VbxError(RuntimeError):
         super().__init__(f"vbx: {what}: {STATUS.get(status, status)} ({status})")
 
 
+# Allocator hook of a map's own device memory: alloc(bytes, ctx) -> device pointer or NULL;
+# free(ptr, ctx).
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class MapParams(ctypes.Structure):
     _fields_ = [("voxel_size", ctypes.c_float), ("trunc", ctypes.c_float),
                 ("w_max", ctypes.c_float), ("max_range", ctypes.c_float),
                 ("z_min", ctypes.c_float), ("weighting", ctypes.c_int32),
                 ("merge", ctypes.c_int32), ("storage", ctypes.c_int32), ("dist", ctypes.c_int32),
                 ("block_capacity", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p)]
 
 
 class Frame(ctypes.Structure):
@@ -199,7 +206,7 @@ def _pose12(pose) -> np.ndarray:
 
 _WEIGHTING = {"const": W_CONST, "quad": W_QUAD}
 _MERGE = {"simple": MERGE_NONE, "none": MERGE_NONE, "grouped": MERGE_GROUPED}
-_STORAGE = {"f32": F32, "f16": F16}
+_STORAGE = {"f32": F32, "f16": F16, "s16": S16}
 _DIST = {"eq1": DIST_EQ1, "ray": DIST_ALONG_RAY}
 
 
@@ -225,12 +232,23 @@ class Map:
     def __init__(self, voxel_size: float, trunc: float, weighting: str = "const",
                  merge: str = "simple", storage: str = "f32", w_max: float = 1e4,
                  max_range: float = 5.0, z_min: float = 0.1, dist: str = "eq1",
-                 block_capacity: int = 65536, keep_touches: bool = False, stream=None):
+                 block_capacity: int = 65536, keep_touches: bool = False, stream=None,
+                 allocator=None):
+        """allocator: optional (alloc, free) pair of callables, alloc(nbytes) -> device address
+        (0 when it cannot) and free(address), used for the map's hash table, block pool and
+        device state instead of hipMalloc / hipFree."""
         L = lib()
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
         p = map_params(voxel_size, trunc, weighting, merge, storage, w_max, max_range, z_min, dist,
                        block_capacity, keep_touches, s.cuda_stream)
+        self._hooks = None
+        if allocator is not None:
+            a_py, f_py = allocator
+            # the ctypes thunks must outlive the map: kept on the object
+            self._hooks = (ALLOC_FN(lambda nbytes, ctx: a_py(int(nbytes)) or None),
+                           FREE_FN(lambda ptr, ctx: f_py(int(ptr)) if ptr else None))
+            p.alloc, p.free = self._hooks
         h = ctypes.c_void_p()
         _check(L.vbx_map_create_ex(ctypes.byref(p), ctypes.byref(h)), "vbx_map_create_ex")
         self._h = h

@@ -183,10 +183,11 @@ int validate_params(const vbx_map_params& P) {
     if (!(P.max_range > 0.0f) || !std::isfinite(P.max_range)) return VBX_ERR_INVALID_ARG;
     if (P.weighting != VBX_W_CONST && P.weighting != VBX_W_QUAD) return VBX_ERR_INVALID_ARG;
     if (P.merge != VBX_MERGE_NONE && P.merge != VBX_MERGE_GROUPED) return VBX_ERR_INVALID_ARG;
-    if (P.storage != VBX_F32 && P.storage != VBX_F16) return VBX_ERR_INVALID_ARG;
+    if (P.storage != VBX_F32 && P.storage != VBX_F16 && P.storage != VBX_S16) return VBX_ERR_INVALID_ARG;
     if (P.dist != VBX_DIST_EQ1 && P.dist != VBX_DIST_ALONG_RAY) return VBX_ERR_INVALID_ARG;
     if (P.weighting == VBX_W_QUAD && !(P.z_min >= 0.05f)) return VBX_ERR_INVALID_ARG;
-    if (P.storage == VBX_F16 && P.w_max > 65504.0f) return VBX_ERR_INVALID_ARG;
+    if (P.storage != VBX_F32 && P.w_max > 65504.0f) return VBX_ERR_INVALID_ARG;   // binary16 W
+    if ((P.alloc == nullptr) != (P.free == nullptr)) return VBX_ERR_INVALID_ARG;
     if (P.block_capacity == 0 || P.block_capacity > (1u << 29)) return VBX_ERR_INVALID_ARG;
     if (2.0 * P.trunc / P.voxel_size > 28.0) return VBX_ERR_LIMIT;   // band of <= 28 voxels
     return VBX_OK;
@@ -224,12 +225,33 @@ MapDesc make_desc(const vbx_map* m, int map_id, int job0, int njobs) {
     return d;
 }
 
+// The map's own device memory (hash table, block pool, device state): the caller's allocator
+// hook when the parameters carry one, else hipMalloc / hipFree.
+int map_alloc(const vbx_map* m, void** p, size_t bytes) {
+    *p = nullptr;
+    if (m->P.alloc) {
+        *p = m->P.alloc(bytes, m->P.alloc_ctx);
+        return *p ? VBX_OK : VBX_ERR_OUT_OF_MEMORY;
+    }
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return VBX_ERR_OUT_OF_MEMORY;
+    }
+    return VBX_OK;
+}
+
+void map_free(const vbx_map* m, void* p) {
+    if (!p) return;
+    if (m->P.free) m->P.free(p, m->P.alloc_ctx);
+    else (void)hipFree(p);
+}
+
 int alloc_storage(vbx_map* m, u32 capacity) {
     m->capacity = capacity;
     m->hcap = (u32)next_pow2((size_t)capacity * 2);
-    if (hipMalloc(&m->hkeys, sizeof(u64) * m->hcap) != hipSuccess) return VBX_ERR_OUT_OF_MEMORY;
-    if (hipMalloc(&m->hslots, sizeof(int) * m->hcap) != hipSuccess) return VBX_ERR_OUT_OF_MEMORY;
-    if (hipMalloc(&m->pool, (size_t)capacity * 4096 * m->voxel_bytes) != hipSuccess)
+    if (map_alloc(m, (void**)&m->hkeys, sizeof(u64) * m->hcap) != VBX_OK) return VBX_ERR_OUT_OF_MEMORY;
+    if (map_alloc(m, (void**)&m->hslots, sizeof(int) * m->hcap) != VBX_OK) return VBX_ERR_OUT_OF_MEMORY;
+    if (map_alloc(m, &m->pool, (size_t)capacity * 4096 * m->voxel_bytes) != VBX_OK)
         return VBX_ERR_OUT_OF_MEMORY;
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(m->hcap)), dim3(256), 0, m->stream, m->hkeys, kEmpty,
                        (size_t)m->hcap);
@@ -237,9 +259,9 @@ int alloc_storage(vbx_map* m, u32 capacity) {
 }
 
 void free_storage(vbx_map* m) {
-    if (m->hkeys) (void)hipFree(m->hkeys);
-    if (m->hslots) (void)hipFree(m->hslots);
-    if (m->pool) (void)hipFree(m->pool);
+    map_free(m, m->hkeys);
+    map_free(m, m->hslots);
+    map_free(m, m->pool);
     m->hkeys = nullptr;
     m->hslots = nullptr;
     m->pool = nullptr;
@@ -460,8 +482,11 @@ void launch_update(int storage, int variant, hipStream_t st, const Job* jobs, co
     if (storage == VBX_F32)
         launch_update_s<0>(variant, st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, touch_n,
                            touch_cap, keep, jst, cs);
-    else
+    else if (storage == VBX_F16)
         launch_update_s<1>(variant, st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, touch_n,
+                           touch_cap, keep, jst, cs);
+    else
+        launch_update_s<2>(variant, st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, touch_n,
                            touch_cap, keep, jst, cs);
 }
 
@@ -605,6 +630,7 @@ void warm_launch_shapes() {
     (void)sort_resident_waves();
     warm_update_grids<0>();
     warm_update_grids<1>();
+    warm_update_grids<2>();
 }
 
 // The kernel sequence of one call over the staged tables in `s`.  Only kernel launches are
@@ -759,7 +785,7 @@ int run_call(std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
 // Device memory a map of `capacity` blocks holds (hash table, block pool, state).
 uint64_t map_storage_bytes(const vbx_map_params& P, uint64_t capacity) {
     const uint64_t hcap = next_pow2((size_t)capacity * 2);
-    const uint64_t vb = P.storage == VBX_F16 ? 4 : 8;
+    const uint64_t vb = P.storage == VBX_F32 ? 8 : 4;
     return hcap * (sizeof(u64) + sizeof(int)) + capacity * 4096 * vb + sizeof(MapState);
 }
 
@@ -998,9 +1024,8 @@ int vbx_map_create_ex(const vbx_map_params* params, vbx_map** out) {
     vbx_map* m = new (std::nothrow) vbx_map();
     if (!m) return VBX_ERR_OUT_OF_MEMORY;
     m->P = *params;
-    (void)hipGetDevice(&m->device);
     m->stream = (hipStream_t)params->stream;
-    m->voxel_bytes = params->storage == VBX_F16 ? 4 : 8;
+    m->voxel_bytes = params->storage == VBX_F32 ? 8 : 4;
     m->wbits = weight_bits(m->P);
     m->kw = sum_bits(m->P);
     m->scratch = new (std::nothrow) Scratch();
@@ -1008,18 +1033,21 @@ int vbx_map_create_ex(const vbx_map_params* params, vbx_map** out) {
         const int v = std::atoi(e);
         if (v >= 0 && v < kNumUpdateVariants) m->update_variant = v;
     }
-    if (!m->scratch || hipMalloc(&m->st, sizeof(MapState)) != hipSuccess) {
+    // the map's first device allocation comes before any other device call, so a failing
+    // allocator hook ends the call without touching the device
+    if (!m->scratch || map_alloc(m, (void**)&m->st, sizeof(MapState)) != VBX_OK) {
         delete m->scratch;
         delete m;
         return VBX_ERR_OUT_OF_MEMORY;
     }
+    (void)hipGetDevice(&m->device);
     MapState zero;
     std::memset(&zero, 0, sizeof zero);
     if (hipMemcpy(m->st, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess ||
         (rc = alloc_storage(m, params->block_capacity)) != VBX_OK ||
         hipStreamSynchronize(m->stream) != hipSuccess) {
         free_storage(m);
-        (void)hipFree(m->st);
+        map_free(m, m->st);
         free_scratch(m->scratch);
         delete m;
         return rc != VBX_OK ? rc : VBX_ERR_DEVICE;
@@ -1046,7 +1074,7 @@ void vbx_map_destroy(vbx_map* m) {
     }
     for (hipEvent_t e : m->prof.spare) (void)hipEventDestroy(e);
     free_storage(m);
-    (void)hipFree(m->st);
+    map_free(m, m->st);
     free_scratch(m->scratch);
     delete m;
 }
@@ -1172,9 +1200,9 @@ int vbx_map_reserve(vbx_map* m, uint32_t block_capacity) {
     VBX_TRY(hipStreamSynchronize(m->stream));
     VBX_TRY(hipMemcpy(m->hkeys, nkeys.data(), sizeof(u64) * m->hcap, hipMemcpyHostToDevice));
     VBX_TRY(hipMemcpy(m->hslots, nslots.data(), sizeof(int) * m->hcap, hipMemcpyHostToDevice));
-    (void)hipFree(old_keys);
-    (void)hipFree(old_slots);
-    (void)hipFree(old_pool);
+    map_free(m, old_keys);
+    map_free(m, old_slots);
+    map_free(m, old_pool);
     m->P.block_capacity = block_capacity;
     if (s.error == VBX_ERR_POOL_FULL) {
         s.error = 0;
@@ -1227,7 +1255,8 @@ int vbx_export_blocks(vbx_map* m, int32_t* coords, float* dw, size_t cap, size_t
                     W = v[1];
                 } else {
                     const uint32_t raw = ((const uint32_t*)pool.data())[slot * 4096 + l];
-                    Dn = __half2float(__ushort_as_half((unsigned short)(raw & 0xFFFF)));
+                    const unsigned short dc = (unsigned short)(raw & 0xFFFF);
+                    Dn = m->P.storage == VBX_F16 ? __half2float(__ushort_as_half(dc)) : s16_decode(dc);
                     W = __half2float(__ushort_as_half((unsigned short)(raw >> 16)));
                 }
                 dw[2 * (b * 4096 + l)] = m->P.storage == VBX_F32 ? Dn : Dn * m->P.trunc;
@@ -1261,7 +1290,9 @@ int vbx_import_blocks(vbx_map* m, const int32_t* coords, const float* dw, size_t
                 v[0] = D;
                 v[1] = W;
             } else {
-                const uint32_t d = __half_as_ushort(__float2half_rn(D / m->P.trunc));
+                const float dn = D / m->P.trunc;
+                const uint32_t d = m->P.storage == VBX_F16 ? (uint32_t)__half_as_ushort(__float2half_rn(dn))
+                                                           : (uint32_t)s16_encode(dn);
                 const uint32_t w = __half_as_ushort(__float2half_rn(W));
                 ((uint32_t*)pool.data())[b * 4096 + l] = d | (w << 16);
             }
@@ -1345,8 +1376,10 @@ int vbx_map_interpolate(vbx_map* m, const float* points_dev, size_t n, float* di
     const unsigned grid = grid_for(n, 8192);
     if (m->P.storage == VBX_F32)
         hipLaunchKernelGGL(k_interpolate<0>, dim3(grid), dim3(256), 0, m->stream, d, points_dev, (u32)n, dist_dev);
-    else
+    else if (m->P.storage == VBX_F16)
         hipLaunchKernelGGL(k_interpolate<1>, dim3(grid), dim3(256), 0, m->stream, d, points_dev, (u32)n, dist_dev);
+    else
+        hipLaunchKernelGGL(k_interpolate<2>, dim3(grid), dim3(256), 0, m->stream, d, points_dev, (u32)n, dist_dev);
     return hipGetLastError() == hipSuccess ? VBX_OK : VBX_ERR_DEVICE;
 }
 

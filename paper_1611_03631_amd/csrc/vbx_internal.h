@@ -149,6 +149,19 @@ __host__ __device__ inline void unpack_voxel(u64 k, int& gx, int& gy, int& gz) {
 }
 
 // ---------------------------------------------------------------------------
+// 16-bit voxel storage
+// ---------------------------------------------------------------------------
+// Fixed-point distance code of the VBX_S16 storage: D/delta = i / 32767 with |i| <= 32767,
+// the nearest code to the binary32 value (ties to even).  |D/delta| <= 1 always holds for a
+// weighted mean of clamped distances; the clamp only absorbs binary32 rounding.
+__host__ __device__ inline unsigned short s16_encode(float dn) {
+    float x = dn * 32767.0f;
+    x = x > 32767.0f ? 32767.0f : (x < -32767.0f ? -32767.0f : x);
+    return (unsigned short)(short)(int)__builtin_rintf(x);
+}
+__host__ __device__ inline float s16_decode(unsigned short c) { return (float)(short)c / 32767.0f; }
+
+// ---------------------------------------------------------------------------
 // Point validity and pose transform (binary32, fixed order)
 // ---------------------------------------------------------------------------
 // Returns true and the world point q when the sensor-frame point is valid:
@@ -283,18 +296,26 @@ struct Obs {
 
 __device__ inline Obs observe(const MapDesc& M, const float p[3], const float e[3], float r,
                               float wgt, int gx, int gy, int gz) {
-    float f0 = p[0] - ((float)gx + 0.5f) * M.v;
-    float f1 = p[1] - ((float)gy + 0.5f) * M.v;
-    float f2 = p[2] - ((float)gz + 0.5f) * M.v;
-    float dot = (f0 * e[0] + f1 * e[1]) + f2 * e[2];
+    // Voxel centre c v, c = g + 1/2 (exact in binary32 for |g| < 2^18).  The rounded product
+    // x = fl(c v) decides the sign of Eq. (1) in binary32, in the same operation order on every
+    // side.  The distance value is measured from the exact centre instead: the product's
+    // remainder c v - x is a binary32 number (an fma gives it exactly), so p - c v is formed
+    // with two roundings relative to |p - c v| <= delta + v, not to the world coordinates.
+    const float c0 = (float)gx + 0.5f, c1 = (float)gy + 0.5f, c2 = (float)gz + 0.5f;
+    const float x0 = c0 * M.v, x1 = c1 * M.v, x2 = c2 * M.v;
+    const float f0 = p[0] - x0, f1 = p[1] - x1, f2 = p[2] - x2;
+    const float h0 = f0 - __builtin_fmaf(c0, M.v, -x0);
+    const float h1 = f1 - __builtin_fmaf(c1, M.v, -x1);
+    const float h2 = f2 - __builtin_fmaf(c2, M.v, -x2);
     float d;
     if (M.dist == 0) {
-        // hardware square root (1 ulp): the magnitude only sets D's value, its sign comes
-        // from the dot product
-        float mag = __builtin_amdgcn_sqrtf((f0 * f0 + f1 * f1) + f2 * f2);
+        const float dot = (f0 * e[0] + f1 * e[1]) + f2 * e[2];
+        // correctly rounded square root of the exact-centre offset
+        const float mag = __builtin_sqrtf((h0 * h0 + h1 * h1) + h2 * h2);
         d = dot > 0.0f ? mag : (dot < 0.0f ? -mag : 0.0f);
     } else {
-        d = dot / r;
+        // the projective distance is continuous in the offset: no binary32 sign decision
+        d = ((h0 * e[0] + h1 * e[1]) + h2 * e[2]) / r;
     }
     Obs o;
     float fdrop = 1.0f;

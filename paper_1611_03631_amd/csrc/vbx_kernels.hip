@@ -1312,8 +1312,11 @@ __device__ inline void load_voxel(const void* pool, size_t idx, float& D, float&
         const float2 dw = ((const float2*)pool)[idx];
         D = dw.x; W = dw.y;
     } else {
+        // 16-bit pairs: D / delta in the low half (binary16, or the fixed-point code), W
+        // (binary16) in the high half
         const u32 raw = ((const u32*)pool)[idx];
-        D = __half2float(__ushort_as_half((unsigned short)(raw & 0xFFFF)));
+        D = STORAGE == 1 ? __half2float(__ushort_as_half((unsigned short)(raw & 0xFFFF)))
+                         : s16_decode((unsigned short)(raw & 0xFFFF));
         W = __half2float(__ushort_as_half((unsigned short)(raw >> 16)));
     }
 }
@@ -1322,9 +1325,21 @@ __device__ inline void store_voxel(void* pool, size_t idx, float D, float W) {
     if (STORAGE == 0) {
         ((float2*)pool)[idx] = make_float2(D, W);
     } else {
-        const u32 d = __half_as_ushort(__float2half_rn(D));
+        const u32 d = STORAGE == 1 ? (u32)__half_as_ushort(__float2half_rn(D)) : (u32)s16_encode(D);
         const u32 w = __half_as_ushort(__float2half_rn(W));
         ((u32*)pool)[idx] = d | (w << 16);
+    }
+}
+
+// The stored value a binary32 result of Eqs. (3)-(4) becomes (rounded once per frame).
+template <int STORAGE>
+__device__ inline void round_to_storage(float& D, float& W) {
+    if (STORAGE == 1) {
+        D = __half2float(__float2half_rn(D));
+        W = __half2float(__float2half_rn(W));
+    } else if (STORAGE == 2) {
+        D = s16_decode(s16_encode(D));
+        W = __half2float(__float2half_rn(W));
     }
 }
 
@@ -1557,16 +1572,13 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                             if (sw_fx) {
                                 const float sw = (float)sw_fx * M.inv_wscale;
                                 // sums are in units of delta; binary32 storage keeps D in metres,
-                                // binary16 storage keeps D / delta
+                                // 16-bit storage keeps D / delta
                                 float swd = (float)(i64)a_d[h][l] * M.inv_wscale;
                                 if (STORAGE == 0) swd = swd * M.delta;
                                 float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
                                 float Wn = W[j] + sw;
                                 if (Wn > M.w_max) Wn = M.w_max;
-                                if (STORAGE == 1) {
-                                    Dn = __half2float(__float2half_rn(Dn));
-                                    Wn = __half2float(__float2half_rn(Wn));
-                                }
+                                round_to_storage<STORAGE>(Dn, Wn);
                                 D[j] = Dn;
                                 W[j] = Wn;
                             }
@@ -1668,16 +1680,13 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                             if (sw_fx) {
                                 const float sw = (float)sw_fx * M.inv_wscale;
                                 // sums are in units of delta; binary32 storage keeps D in metres,
-                                // binary16 storage keeps D / delta
+                                // 16-bit storage keeps D / delta
                                 float swd = (float)(i64)a_d[0][l] * M.inv_wscale;
                                 if (STORAGE == 0) swd = swd * M.delta;
                                 float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
                                 float Wn = W[j] + sw;
                                 if (Wn > M.w_max) Wn = M.w_max;
-                                if (STORAGE == 1) {
-                                    Dn = __half2float(__float2half_rn(Dn));
-                                    Wn = __half2float(__float2half_rn(Wn));
-                                }
+                                round_to_storage<STORAGE>(Dn, Wn);
                                 D[j] = Dn;
                                 W[j] = Wn;
                             }
@@ -1800,6 +1809,36 @@ template __global__ void k_update<1, 16, 16, 4, 1024>(const Job*, const MapDesc*
 template __global__ void k_update<1, 16, 16, 8, 512>(const Job*, const MapDesc*, const u64*, const int*,
                                                         const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
+template __global__ void k_update<2, 16, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
+template __global__ void k_update<2, 16, 16, 8, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
+template __global__ void k_update<2, 16, 16, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
+template __global__ void k_update<2, 8, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
+template __global__ void k_update<2, 8, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
+template __global__ void k_update<2, 4, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
+template __global__ void k_update<2, 16, 16, 16, 1024>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
+template __global__ void k_update<2, 16, 16, 8, 1024>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
+template __global__ void k_update<2, 16, 16, 4, 1024>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
+template __global__ void k_update<2, 16, 16, 8, 512>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+                                                        int, JobStat*, CallState*);
 
 // ---------------------------------------------------------------------------
 // finish: commit block counts, fold statistics, clean per-call tables
@@ -1907,7 +1946,7 @@ __global__ __launch_bounds__(256) void k_finish_call(const Job* __restrict__ job
 }
 
 // ---------------------------------------------------------------------------
-// query: trilinear interpolation of the distance field (the accuracy evaluation, Sec. V-B)
+// query: trilinear interpolation of the distance field (the accuracy evaluation, Sec. VI-A)
 // ---------------------------------------------------------------------------
 // Voxel (i, j, k) holds the field at its centre ((i, j, k) + 1/2) v.  A query point q takes the
 // eight voxels around it: u = q * (1/v) - 1/2 per axis (binary32, with the map's binary32
@@ -1977,6 +2016,7 @@ __global__ __launch_bounds__(256) void k_interpolate(const MapDesc M, const floa
 }
 template __global__ void k_interpolate<0>(const MapDesc, const float*, u32, float*);
 template __global__ void k_interpolate<1>(const MapDesc, const float*, u32, float*);
+template __global__ void k_interpolate<2>(const MapDesc, const float*, u32, float*);
 
 // ---------------------------------------------------------------------------
 // verification: traversal of voxel-space segments

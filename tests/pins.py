@@ -382,6 +382,67 @@ def pin_binary16_sequence(lib_path=None):
     m.close()
 
 
+def _s16(x):
+    """Nearest multiple of 1/32767 in [-1, 1], ties to even (Python's round is half-even on
+    fractions), as an exact fraction."""
+    i = round(Fr(x) * 32767)
+    return Fr(max(-32767, min(32767, i)), 32767)
+
+
+def pin_s16_sequence(lib_path=None):
+    """16-bit fixed-point distance storage: after every frame D / delta is rounded to the nearest
+    multiple of 1/32767 (ties to even) and W to binary16, W after the Eq. (4) cap.  The head-on
+    sequence of the binary16 pin, worked in exact rational arithmetic: W stalls at 2048 as in
+    binary16, D keeps moving where binary16 stalls (its step is 1/32767 of delta everywhere, where
+    binary16's is 2^-11 of delta near |D| = delta), D stalls where a frame moves it by less than
+    half a step, the clamped D = +-delta is exact, and W_max = 2999 is capped before rounding."""
+    pose = _axis_pose(2, 1)
+    sz = Fr(float(pose[2, 3]))
+    wmax = 2999.0
+    m = oracle.OracleMap(V, DELTA, weighting="const", merge="simple", w_max=wmax,
+                         max_range=10.0, storage="s16", lib_path=lib_path)
+    frames = [(3, 1.3125), (1, 1.34375), (2, 1.28125), (2041, 1.3125), (1, 1.3125),
+              (1, 1.375), (1, 1.34375), (1000, 1.25), (1, 1.3125)]
+    state = {}                 # voxel z index -> (D / delta exact fraction, W float) as stored
+    ix, iy = math.floor(float(pose[0, 3]) / V), math.floor(float(pose[1, 3]) / V)
+    moved_where_f16_stalls = stalled = 0
+    for f, (n, Z) in enumerate(frames):
+        pz = sz + Fr(Z)
+        lo, hi = math.floor((pz - Fr(DELTA)) / Fr(V)), math.floor((pz + Fr(DELTA)) / Fr(V))
+        m.integrate(np.repeat(np.array([[0.0, 0.0, Z]], np.float32), n, axis=0), pose)
+        for gz in range(lo, hi + 1):
+            d = pz - (Fr(gz) + Fr(1, 2)) * Fr(V)
+            dc = max(Fr(-DELTA), min(Fr(DELTA), d))
+            D0, W0 = state.get(gz, (Fr(0), 0.0))
+            exact = (Fr(W0) * D0 + n * dc / Fr(DELTA)) / (Fr(W0) + n)
+            D1 = _s16(exact)
+            W1 = _f16(min(W0 + n, wmax))
+            if f >= 5 and D1 != D0 and _f16(float(exact)) == _f16(float(D0)):
+                moved_where_f16_stalls += 1
+            if f >= 4 and D1 == D0 and exact != D0:
+                stalled += 1
+            state[gz] = (D1, W1)
+        centre = state[math.floor(pz / Fr(V))]
+        if f == 5:
+            assert centre[1] == 2048.0, "W must stall at 2048 (2049 rounds to even)"
+        if f >= 7:
+            assert centre[1] == 3000.0, "W capped at 2999, then rounded to binary16"
+    assert moved_where_f16_stalls >= 1, "sequence does not separate the two 16-bit forms"
+    assert stalled >= 1, "sequence does not exercise a stalled D"
+    assert any(Dq == 1 for Dq, _ in state.values()), "sequence has no clamped voxel"
+    got, _ = _export_dict(m)
+    for gz, (Dq, Wq) in state.items():
+        g = (ix, iy, gz)
+        assert got[g][1] == Wq, f"W at {g}: {got[g][1]} vs {Wq}"
+        expect = (int(Dq * 32767) / 32767.0) * DELTA     # the binary64 the oracle exports
+        assert got[g][0] == expect, f"D at {g}: {got[g][0] / DELTA} vs {Dq} (units of delta)"
+    m.close()
+    # rounding ties go to the even code, and the code saturates at +-32767
+    for i in (0, 1, 2, 32765, -7):
+        assert oracle.round_s16((i + 0.5) / 32767.0, lib_path) == (i + (i & 1)) / 32767.0, i
+    assert oracle.round_s16(1.00001, lib_path) == 1.0 and oracle.round_s16(-1.5, lib_path) == -1.0
+
+
 def pin_ramp_diagnostic(lib_path=None):
     """The ramp diagnostic of the oracle's export: per voxel, the summed point weight 1/z^2 of the
     rays that saw it on the Eq. (5) drop-off ramp, -delta < d <= -eps (on the head-on axis d is
@@ -649,6 +710,6 @@ def pin_permutation(lib_path=None, seed=9):
 
 
 ALL_PINS = [pin_dda_dyadic, pin_dda_random, pin_head_on_plane, pin_dropoff_values,
-            pin_along_ray_off_axis, pin_binary16_sequence, pin_ramp_diagnostic,
+            pin_along_ray_off_axis, pin_binary16_sequence, pin_s16_sequence, pin_ramp_diagnostic,
             pin_weight_sums, pin_group_mean, pin_merged_singletons, pin_identical_points,
             pin_running_average, pin_validity, pin_round_half, pin_permutation]

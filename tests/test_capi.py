@@ -63,3 +63,56 @@ def test_interpolate_rejects_bad_arguments_before_any_device_work(libpath):
     import paper_1611_03631_amd as vbx
     assert lib.vbx_map_interpolate(None, None, 0, None) == vbx.ERR_INVALID_ARG
     assert lib.vbx_map_interpolate(None, None, 5, None) == vbx.ERR_INVALID_ARG
+
+
+def _create_ex(libpath):
+    lib = ctypes.CDLL(libpath)
+    lib.vbx_map_create_ex.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.vbx_map_create_ex.restype = ctypes.c_int
+    lib.vbx_default_params.argtypes = [ctypes.c_void_p]
+    lib.vbx_default_params.restype = None
+    return lib
+
+
+def test_allocator_hook_returning_null_fails_create_cleanly(libpath):
+    """A map whose allocator hook returns NULL is not created: VBX_ERR_OUT_OF_MEMORY, the out
+    parameter untouched, and nothing handed to the free hook (the hook's allocation is the map's
+    first device request, so no device is needed to see this)."""
+    import paper_1611_03631_amd as vbx
+    lib = _create_ex(libpath)
+    asked, freed = [], []
+    alloc = vbx.ALLOC_FN(lambda n, ctx: asked.append((n, ctx)) or None)
+    free = vbx.FREE_FN(lambda ptr, ctx: freed.append(ptr))
+    p = vbx.MapParams()
+    lib.vbx_default_params(ctypes.byref(p))
+    p.alloc, p.free, p.alloc_ctx = alloc, free, 77
+    out = ctypes.c_void_p(1234)
+    assert lib.vbx_map_create_ex(ctypes.byref(p), ctypes.byref(out)) == vbx.ERR_OUT_OF_MEMORY
+    assert out.value == 1234
+    assert len(asked) == 1 and asked[0][1] == 77 and asked[0][0] > 0
+    assert freed == []
+
+
+def test_allocator_hook_needs_both_functions(libpath):
+    import paper_1611_03631_amd as vbx
+    lib = _create_ex(libpath)
+    p = vbx.MapParams()
+    lib.vbx_default_params(ctypes.byref(p))
+    alloc = vbx.ALLOC_FN(lambda n, ctx: None)
+    p.alloc = alloc
+    out = ctypes.c_void_p(None)
+    assert lib.vbx_map_create_ex(ctypes.byref(p), ctypes.byref(out)) == vbx.ERR_INVALID_ARG
+    assert out.value is None
+
+
+def test_storage_modes_are_validated(libpath):
+    """The 16-bit storages hold W as binary16: a W_max above 65504 is refused, as is an unknown
+    storage code."""
+    import paper_1611_03631_amd as vbx
+    lib = _create_ex(libpath)
+    for storage, w_max in ((vbx.F16, 7e4), (vbx.S16, 7e4), (3, 1e4)):
+        p = vbx.MapParams()
+        lib.vbx_default_params(ctypes.byref(p))
+        p.storage, p.w_max = storage, w_max
+        out = ctypes.c_void_p(None)
+        assert lib.vbx_map_create_ex(ctypes.byref(p), ctypes.byref(out)) == vbx.ERR_INVALID_ARG

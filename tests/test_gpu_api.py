@@ -34,7 +34,7 @@ def room(w, h, n, seed):
     return [(frame(k), poses[k]) for k in range(n)]
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "s16"])
 @pytest.mark.parametrize("merge", ["simple", "grouped"])
 def test_batch_equals_sequential(vbx, storage, merge):
     frames = room(320, 240, 5, 21)
@@ -275,3 +275,84 @@ def test_reused_map_and_scratch_repeat_bit_identical(vbx):
     fresh.integrate_frames(batch)
     assert fresh.sync() == 0
     assert same_export(fresh, g)
+
+
+class _TorchAllocator:
+    """Allocator hook backed by torch's caching allocator; fails on request when told to."""
+
+    def __init__(self):
+        self.live = {}
+        self.calls = 0
+        self.fail_from = None      # the call index from which every request fails
+
+    def alloc(self, n):
+        self.calls += 1
+        if self.fail_from is not None and self.calls >= self.fail_from:
+            return 0
+        p = torch.cuda.caching_allocator_alloc(n)
+        self.live[p] = n
+        return p
+
+    def free(self, p):
+        self.live.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+
+
+def test_allocator_hook_owns_the_map_storage(vbx):
+    """The hash table, block pool and device state come from the caller's allocator: the map
+    integrates, grows (the old storage handed back) and is destroyed with every block returned;
+    its result equals a default-allocated map's, bit for bit."""
+    frames = room(320, 240, 3, 51)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped",
+                  block_capacity=64, keep_touches=False)
+    A = _TorchAllocator()
+    kw = {k: v for k, v in params.items() if k != "keep_touches"}
+    hooked = vbx.Map(**kw, allocator=(A.alloc, A.free))
+    plain = gpu_map(vbx, params)
+    assert len(A.live) == 4                      # state, hash keys, hash slots, pool
+    for m in (hooked, plain):
+        m.integrate(dev(frames[0][0]), frames[0][1])
+        full = m.sync() == vbx.ERR_POOL_FULL
+        m.reserve(4096)
+        if full:
+            m.integrate(dev(frames[0][0]), frames[0][1])
+        for p, pose in frames[1:]:
+            m.integrate(dev(p), pose)
+        assert m.sync() == 0
+    assert same_export(hooked, plain)
+    assert len(A.live) == 4 and A.calls == 7     # the grown hash and pool replaced the old ones
+    hooked.close()
+    assert A.live == {}
+
+
+def test_allocator_hook_failure_leaves_no_leak_and_the_map_usable(vbx):
+    frames = room(160, 120, 2, 52)
+    params = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped", block_capacity=256)
+    # the pool (the fourth request) cannot be had: no map, and the three granted requests returned
+    A = _TorchAllocator()
+    A.fail_from = 4
+    with pytest.raises(vbx.VbxError) as err:
+        vbx.Map(**params, allocator=(A.alloc, A.free))
+    assert err.value.status == vbx.ERR_OUT_OF_MEMORY and A.live == {}
+    # growth that cannot be had: VBX_ERR_OUT_OF_MEMORY, and the map keeps its storage and content
+    B = _TorchAllocator()
+    m = vbx.Map(**params, allocator=(B.alloc, B.free))
+    m.integrate(dev(frames[0][0]), frames[0][1])
+    assert m.sync() == 0
+    before = m.export()
+    held = dict(B.live)
+    B.fail_from = B.calls + 2                    # the new hash keys succeed, the slots do not
+    with pytest.raises(vbx.VbxError) as err:
+        m.reserve(8192)
+    assert err.value.status == vbx.ERR_OUT_OF_MEMORY
+    assert B.live == held
+    after = m.export()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    m.integrate(dev(frames[1][0]), frames[1][1])
+    assert m.sync() == 0
+    o = oracle_map(params)
+    for p, pose in frames:
+        o.integrate(p, pose)
+    compare_export(m.export(), o.export(), params)
+    m.close()
+    assert B.live == {}

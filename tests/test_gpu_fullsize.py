@@ -63,7 +63,7 @@ def test_lidar_street_grouped(vbx):
     log(f"c3 grouped x10 ok: {res}")
 
 
-@pytest.mark.parametrize("storage", ["f16", "f32"])
+@pytest.mark.parametrize("storage", ["f16", "s16", "f32"])
 def test_32_map_tick_graph_replay_vs_oracle(vbx, storage):
     """Two ticks of the 32-map mix (8 x 160x120, 16 x 320x240, 8 x 640x480; voxel 0.02 / 0.05
     / 0.10 m), each tick one graph launch, every map against the oracle."""

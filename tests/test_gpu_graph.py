@@ -42,7 +42,7 @@ def tick_frames(n_ticks, seed):
     return out
 
 
-@pytest.mark.parametrize("merge,storage", [("grouped", "f32"), ("grouped", "f16"), ("simple", "f32")])
+@pytest.mark.parametrize("merge,storage", [("grouped", "f32"), ("grouped", "f16"), ("grouped", "s16"), ("simple", "f32")])
 def test_graph_replays_equal_eager_multi(vbx, merge, storage):
     T = 3
     frames = tick_frames(T, 300)

@@ -52,7 +52,8 @@ def queries(frames, v, seed):
 
 
 @pytest.mark.parametrize("storage,weighting,merge", [("f32", "quad", "grouped"),
-                                                     ("f16", "const", "simple")])
+                                                     ("f16", "const", "simple"),
+                                                     ("s16", "quad", "grouped")])
 def test_interpolation_matches_oracle_on_gpu_map(vbx, storage, weighting, merge):
     import synth
     from oracle import interp

@@ -98,7 +98,7 @@ def test_c1_stats_match_oracle(vbx):
         assert st[k_g] == ost[k_o], (k_g, st[k_g], ost[k_o])
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "s16"])
 def test_room_sequence_grouped(vbx, storage):
     """Several 320x240 frames of the furnished room (grouped, 1/z^2), frame by frame."""
     import synth

@@ -1,6 +1,13 @@
-"""Binary16 storage (D/delta and W stored as binary16, every sum and update in binary32):
-parity with the binary16-emulating oracle, and the storage error itself against the binary64
-oracle, per voxel-size class of the 32-map batched mix (10 ticks per map)."""
+"""16-bit voxel storage (4 bytes per voxel; every sum and update in binary32, the stored values
+rounded once per frame): parity with the oracle's mode that rounds to the same storage, and the
+storage error itself against the binary64 oracle over a 100-frame sequence, per voxel-size
+class of the 32-map batched mix.
+
+Two 16-bit forms share the layout (D / delta in the low half, binary16 W in the high half):
+"f16" stores D / delta as binary16, "s16" as a fixed-point number in steps of 1/32767.  A
+binary16 D / delta near +-1 has 11 significant bits, so every frame may move D by up to
+2^-12 delta = 7.3e-4 v (delta = 3v) and the rounding errors of a long sequence add up like a
+random walk; the fixed-point step is 32767 times finer than delta everywhere in the band."""
 import numpy as np
 import pytest
 
@@ -9,6 +16,13 @@ from tests.common import compare_export, gpu_map, log, oracle_map
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+T = 100                     # frames per map
+CHECKPOINTS = (10, 50, 100)  # frames after which the storage error is measured
+BAR = 2e-3                  # |D - D_64| / v for 16-bit storage
+# binary16 D / delta misses the bar: after 100 frames its largest error over the three classes
+# is 4.2e-3 to 4.7e-3 v (rms 4.5e-4 to 7.3e-4 v); this limit keeps a regression from passing
+F16_LIMIT = 6e-3
 
 
 @pytest.fixture(scope="module")
@@ -24,49 +38,49 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
 
 
-def d_error(gpu_export, orc_export, v):
-    """max and rms |D - D_oracle| / v over the voxels the parity bar compares: W_o > 0 and W_o at
-    least 1e-3 of the voxel's summed ray weights (outside the last 1/1000 of the drop-off ramp,
-    where a 1e-7 m change of the binary32 distance moves the weight by a large relative amount)."""
+def storage_error(gpu_export, e64, emul, v):
+    """max and rms |D - D_64| / v over the voxels the storage keeps as observed (the emulating
+    oracle's W > 0); also how many binary64-observed voxels the storage lost to W underflow."""
     coords, dw = gpu_export
-    oc, oD, oW, oM = orc_export[:4]
-    assert np.array_equal(coords, oc)
-    sel = (oW > 0) & (oW >= 1e-3 * oM)
-    err = np.abs(dw[:, :, 0].astype(np.float64) - oD)[sel] / v
-    return float(err.max()), float(np.sqrt(np.mean(err ** 2))), int(sel.sum())
+    assert np.array_equal(coords, e64[0])
+    sel = emul[2] > 0
+    err = np.abs(dw[:, :, 0].astype(np.float64) - e64[1])[sel] / v
+    lost = int(((e64[2] > 0) & ~sel).sum())
+    return float(err.max(initial=0.0)), float(np.sqrt(np.mean(err ** 2))), int(sel.sum()), lost
 
 
 @pytest.mark.parametrize("m", [0, 1, 2])      # voxel 0.02 / 0.05 / 0.10 m (map m of the mix)
-def test_f16_storage_error_per_class(vbx, m):
+def test_16bit_storage_error_per_class(vbx, m):
     import synth
-    T = 10
     w = synth.config4_map(m, n_ticks=T)
     P = dict(w.params, block_capacity=8192)
     v = float(np.float32(P["voxel_size"]))
-    frames = [(w.frame(k), w.poses[k]) for k in range(T)]
-    g16 = gpu_map(vbx, dict(P, storage="f16", keep_touches=False))
-    g32 = gpu_map(vbx, dict(P, storage="f32", keep_touches=False))
-    for p, pose in frames:
+    forms = ("f16", "s16", "f32")
+    g = {s: gpu_map(vbx, dict(P, storage=s, keep_touches=False)) for s in forms}
+    o = {s: oracle_map(P, storage=s) for s in forms}
+    worst = {"f16": 0.0, "s16": 0.0}
+    for k in range(T):
+        p, pose = w.frame(k), w.poses[k]
         d = dev(p)
-        g16.integrate_frames([(d, pose, w.width)])
-        g32.integrate_frames([(d, pose, w.width)])
-    assert g16.sync() == 0 and g32.sync() == 0
-    o16 = oracle_map(P, storage="f16")
-    o64 = oracle_map(P, storage="f32")
-    for p, pose in frames:
-        o16.integrate(p, pose)
-        o64.integrate(p, pose)
-    e16 = o16.export()
-    e64 = o64.export()
-    # parity: binary16 GPU against the binary16-emulating oracle, binary32 GPU against binary64
-    compare_export(g16.export(), e16, P, storage="f16")
-    compare_export(g32.export(), e64, P, storage="f32")
-    # the storage error itself: binary16 against the binary64 oracle
-    mx16, rms16, n = d_error(g16.export(), e64, v)
-    mx32, rms32, _ = d_error(g32.export(), e64, v)
-    log(f"map {m} {w.width}x{w.height} v={v:g}: {n} weighted voxels; |D16 - D64|/v max {mx16:.3e} "
-        f"rms {rms16:.3e}; |D32 - D64|/v max {mx32:.3e} rms {rms32:.3e}")
-    # binary16 keeps D/delta (|D/delta| <= 1) with an 11-bit significand: one rounding per frame
-    # is at most 2^-12 delta = 3 * 2^-12 v; ten frames of rounding stay well inside 10x that
-    assert mx16 <= 10 * 3 * 2.0 ** -12
-    assert mx32 <= 1e-4
+        for s in forms:
+            g[s].integrate_frames([(d, pose, w.width)])
+            o[s].integrate(p, pose)
+        if k + 1 in CHECKPOINTS:
+            for s in forms:
+                assert g[s].sync() == 0
+            ex = {s: o[s].export() for s in forms}
+            gx = {s: g[s].export() for s in forms}
+            # parity: each GPU storage against the oracle rounding to the same storage
+            for s in forms:
+                compare_export(gx[s], ex[s], P, storage=s)
+            # the storage error itself, against the binary64 oracle
+            line = []
+            for s in forms:
+                mx, rms, n, lost = storage_error(gx[s], ex["f32"], ex[s], v)
+                if s != "f32":
+                    worst[s] = max(worst[s], mx)
+                line.append(f"{s} max {mx:.3e} rms {rms:.3e} (lost {lost})")
+            log(f"map {m} {w.width}x{w.height} v={v:g} frame {k + 1}: {n} voxels; |D - D64|/v: "
+                + "; ".join(line))
+            assert worst["s16"] <= BAR, f"fixed-point 16-bit storage misses {BAR} v: {worst['s16']:.3e}"
+            assert worst["f16"] <= F16_LIMIT

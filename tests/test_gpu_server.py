@@ -1,12 +1,12 @@
 """The map server on the GPU: a map served in a mix of maps ends bit-identical to the same
-frames integrated into it alone, in submission order; full pools grow and replay; admission
-respects the budget."""
+frames integrated into it alone, in submission order, and matches the oracle integrating those
+frames in that order; full pools grow and replay; admission respects the budget."""
 import time
 
 import numpy as np
 import pytest
 
-from tests.common import gpu_map, log
+from tests.common import compare_export, gpu_map, log, oracle_map
 
 pytestmark = pytest.mark.gpu
 
@@ -36,12 +36,15 @@ ROBOTS = [(160, 120, 0.02), (320, 240, 0.05), (640, 480, 0.10), (320, 240, 0.02)
           (640, 480, 0.05)]
 
 
-def robot_frames(n, seed):
+def robot_frames(n, seed, host=None):
+    """Device frames per robot; host (a list, if given) receives the same frames on the host."""
     import synth
     out = []
     for i, (w, h, v) in enumerate(ROBOTS):
         poses, frame = synth.room_sequence(w, h, n, seed=synth.SEED_BASE + seed + i, phase=0.7 * i)
         out.append([(dev(frame(k)), poses[k], w) for k in range(n)])
+        if host is not None:
+            host.append([(frame(k), poses[k]) for k in range(n)])
     return out
 
 
@@ -50,10 +53,11 @@ def params_of(v, storage="f16", cap=4096):
                 block_capacity=cap)
 
 
-@pytest.mark.parametrize("storage", ["f16", "f32"])
+@pytest.mark.parametrize("storage", ["f16", "s16", "f32"])
 def test_mix_equals_alone(vbx, storage):
     n = 4
-    frames = robot_frames(n, 400)
+    host = []
+    frames = robot_frames(n, 400, host)
     torch.cuda.synchronize()
     srv = vbx.Server(budget_bytes=64 << 30)
     ids = [srv.add_map(**params_of(v, storage)) for (_, _, v) in ROBOTS]
@@ -88,6 +92,13 @@ def test_mix_equals_alone(vbx, storage):
             alone.integrate_frames([frames[i][k]])
         assert alone.sync() == 0
         assert same_export(alone, srv.map(ids[i])), f"robot {i}"
+        # the served map against the oracle, its frames in submission order (the oracle rounds
+        # to the same storage after every frame)
+        P = params_of(v, storage)
+        o = oracle_map(P)
+        for p, pose in host[i]:
+            o.integrate(p, pose)
+        compare_export(srv.map(ids[i]).export(), o.export(), P, storage=storage)
     srv.close()
 
 

@@ -42,13 +42,21 @@ MUTATIONS = {
     "along_ray_sign_flipped": ("dot += (ray->p64[k] - x) * es64[k];", "dot += (x - ray->p64[k]) * es64[k];"),
     "along_ray_binary32_length": ("d = dot / er;", "d = dot / (double)r;"),
     # where binary16 storage rounds: D / delta (not metres), W after the Eq. (4) cap
-    "binary16_rounds_metres": ("vx->D = orc_round_half(vx->D);",
-                               "vx->D = orc_round_half(vx->D * (double)P->trunc) / (double)P->trunc;"),
+    "binary16_rounds_metres": (": orc_round_half(vx->D);",
+                               ": orc_round_half(vx->D * (double)P->trunc) / (double)P->trunc;"),
     "binary16_rounds_w_before_cap": (
         "vx->W = vx->W + vx->sw < wmax ? vx->W + vx->sw : wmax;\n            if (P->fp16) {\n"
-        "                vx->D = orc_round_half(vx->D);\n                vx->W = orc_round_half(vx->W);\n            }",
+        "                vx->D = P->fp16 == 2 ? orc_round_s16(vx->D) : orc_round_half(vx->D);\n"
+        "                vx->W = orc_round_half(vx->W);\n            }",
         "vx->W = P->fp16 ? orc_round_half(vx->W + vx->sw) : vx->W + vx->sw;\n"
-        "            if (vx->W > wmax) vx->W = wmax;\n            if (P->fp16) vx->D = orc_round_half(vx->D);"),
+        "            if (vx->W > wmax) vx->W = wmax;\n"
+        "            if (P->fp16) vx->D = P->fp16 == 2 ? orc_round_s16(vx->D) : orc_round_half(vx->D);"),
+    # the 16-bit fixed-point distance: D / delta in steps of 1/32767, to nearest
+    "s16_rounds_metres": ("? orc_round_s16(vx->D) :",
+                          "? orc_round_s16(vx->D * (double)P->trunc) / (double)P->trunc :"),
+    "s16_truncates": ("double i = nearbyint(x * 32767.0);", "double i = trunc(x * 32767.0);"),
+    "s16_power_of_two_step": ("return i / 32767.0;", "return i / 32768.0;"),
+    "s16_stored_as_binary16": ("? orc_round_s16(vx->D) :", "? orc_round_half(vx->D) :"),
     # the Eq. (5) ramp diagnostic
     "ramp_counts_behind_band": ("if (P->weighting == 1 && d > -d64 && d <= -eps) vx->ramp += ray->wgt;",
                                 "if (P->weighting == 1 && d <= -eps) vx->ramp += ray->wgt;"),
@@ -56,7 +64,8 @@ MUTATIONS = {
 }
 
 FAST_FIRST = [pins.pin_head_on_plane, pins.pin_dropoff_values, pins.pin_running_average,
-              pins.pin_along_ray_off_axis, pins.pin_binary16_sequence, pins.pin_ramp_diagnostic,
+              pins.pin_along_ray_off_axis, pins.pin_binary16_sequence, pins.pin_s16_sequence,
+              pins.pin_ramp_diagnostic,
               pins.pin_validity, pins.pin_identical_points, pins.pin_merged_singletons,
               pins.pin_group_mean, pins.pin_round_half, pins.pin_weight_sums,
               pins.pin_permutation, pins.pin_dda_dyadic, pins.pin_dda_random]
