@@ -167,6 +167,23 @@ int vbx_integrate_batch(vbx_map* map, const float* const* points_dev, const size
 /* As vbx_integrate_batch, with per-frame organisation hints. */
 int vbx_integrate_frames(vbx_map* map, const vbx_frame* frames, int F);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): vbx_integrate_frames into one map, with the call's
+ * scratch memory (rays, partial groups, sort bins, block set, tables, counters) taken from a
+ * fixed region of VBX_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends.  The call makes no hipMalloc, hipFree or pinned host allocation: the
+ * frame and map tables travel in kernel launch arguments, and the region's counters and tables
+ * are cleared by fill kernels at the start of every call.  The result is bit-identical to
+ * vbx_integrate_frames on the same frames.  Returns VBX_ERR_LIMIT, with nothing launched, when
+ * the call needs more scratch than the region holds (one 640x480 frame under grouped raycasting
+ * into a map of 65536 blocks needs about 65 MB); VBX_ERR_INVALID_ARG when the map was created on
+ * another device than the current one.  Every call on a device shares that device's region and
+ * leaves its contents behind: calls that may overlap on one device (different streams without
+ * ordering between them) race, so order them on one stream.  Touch records are not kept (a
+ * following vbx_last_touches reports VBX_ERR_INVALID_ARG), and stage profiling does not apply. */
+#define VBX_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int vbx_integrate_frames_noalloc(vbx_map* map, const vbx_frame* frames, int F);
+
 /* Integrates frames[i] into maps[i] for i < M (distinct maps on one device) in one
  * pipelined pass on maps[0]'s stream, using maps[0]'s scratch memory.  Each map is
  * integrated as in vbx_integrate (Sec. IV); batching independent maps into one pass is this

@@ -30,7 +30,7 @@ FLAG_KEEP_TOUCHES = 1
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "block pool full",
           -4: "buffer too small", -5: "device error", -6: "limit exceeded"}
-ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_POOL_FULL = -1, -2, -3
+ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_POOL_FULL, ERR_LIMIT = -1, -2, -3, -6
 
 
 class VbxError(RuntimeError):
@@ -68,6 +68,7 @@ class Stats(ctypes.Structure):
 
 EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_map_destroy",
             "vbx_map_set_stream", "vbx_integrate", "vbx_integrate_batch", "vbx_integrate_frames",
+            "vbx_integrate_frames_noalloc",
             "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
             "vbx_map_stats", "vbx_map_interpolate", "vbx_debug_traverse", "vbx_status_string",
@@ -134,6 +135,7 @@ def lib(path: Optional[str] = None):
     L.vbx_integrate.argtypes = [vp, f32p, sz, f32p]
     L.vbx_integrate_batch.argtypes = [vp, vp, vp, f32p, i32]
     L.vbx_integrate_frames.argtypes = [vp, ctypes.POINTER(Frame), i32]
+    L.vbx_integrate_frames_noalloc.argtypes = [vp, ctypes.POINTER(Frame), i32]
     L.vbx_map_interpolate.argtypes = [vp, vp, sz, vp]
     L.vbx_integrate_multi.argtypes = [vp, ctypes.POINTER(Frame), i32]
     L.vbx_map_sync.argtypes = [vp]
@@ -303,6 +305,13 @@ class Map:
         """frames: sequence of (points tensor [N,3], pose [3,4]) or (points, pose, width)."""
         arr = make_frames(frames)
         _check(lib().vbx_integrate_frames(self._h, arr, len(frames)), "vbx_integrate_frames")
+
+    def integrate_frames_noalloc(self, frames: Sequence[Tuple]):
+        """As integrate_frames, with the call's scratch memory taken from the library's fixed
+        per-device region (no device allocation; calls overlapping on one device race)."""
+        arr = make_frames(frames)
+        _check(lib().vbx_integrate_frames_noalloc(self._h, arr, len(frames)),
+               "vbx_integrate_frames_noalloc")
 
     def integrate_batch(self, points_list, poses):
         F = len(points_list)

@@ -23,6 +23,11 @@
 
 using namespace vbx;
 
+// Scratch region of vbx_integrate_frames_noalloc: one copy per device, held for the life of the
+// process.  In host code this name only stands for the symbol: its device address comes from
+// hipGetSymbolAddress (NoAllocDevice below), and only that address is ever handed to a kernel.
+static __device__ __align__(256) unsigned char scratch[VBX_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 #define VBX_TRY(expr)                                  \
@@ -295,19 +300,76 @@ struct CallPlan {
     u32 tiles_per_job = 0;      // every job has this many tiles and there is one map (else 0)
 };
 
+// Element counts of a call's scratch buffers (host upper bounds: nothing is read back mid-call).
+struct ScratchSizes {
+    size_t ray_cap, cross_cap, tlist_cap, tkey_cap, bins_cap, nparts, touch_cap, tables_bytes;
+};
+
+int scratch_sizes(const CallPlan& plan, int njobs, int nmaps, size_t sum_capacity, ScratchSizes& z) {
+    z.ray_cap = std::max<size_t>(plan.ray_slots, 1);
+    z.cross_cap = z.ray_cap * (size_t)plan.max_blocks;
+    if (z.cross_cap > 0xFFFFFFF0ull || z.ray_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
+    z.tlist_cap = std::min<size_t>(std::max<size_t>(sum_capacity + 4096, 4096), z.cross_cap + 4096);
+    z.tkey_cap = next_pow2(2 * z.tlist_cap);
+    // grouped calls sort partial groups into kGroupSubBins bins per (block, frame)
+    z.bins_cap = z.tlist_cap * (size_t)plan.JM * (plan.grouped ? (size_t)kGroupSubBins : 1u);
+    if (z.bins_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
+    z.nparts = (z.bins_cap + kScanChunkHost - 1) / kScanChunkHost;
+    z.touch_cap = plan.keep_touches ? std::min<size_t>(z.ray_cap * (size_t)plan.max_vox, (size_t)1 << 26) : 0;
+    z.tables_bytes = (size_t)nmaps * sizeof(MapDesc) + (size_t)njobs * sizeof(Job);
+    return VBX_OK;
+}
+
+// Calls `f(buffer, bytes)` for every scratch buffer a call with sizes `z` uses, in one fixed order.
+template <class F>
+void for_each_scratch(Scratch* s, const CallPlan& plan, const ScratchSizes& z, int njobs, F&& f) {
+    f(s->rays_p, z.ray_cap * sizeof(float4));
+    f(s->rays_job, z.ray_cap * sizeof(u32));
+    f(s->cross, z.cross_cap * sizeof(u32));
+    f(s->ncross, z.ray_cap);
+    f(s->sorted, z.cross_cap * sizeof(float4));
+    f(s->tkeys, z.tkey_cap * sizeof(u64));
+    f(s->tval, z.tkey_cap * sizeof(u32));
+    f(s->tlist, z.tlist_cap * sizeof(u32));
+    f(s->t_key, z.tlist_cap * sizeof(u64));
+    f(s->t_slot, z.tlist_cap * sizeof(int));
+    f(s->order, z.tlist_cap * sizeof(u32));
+    f(s->bins, (z.bins_cap + 1) * sizeof(u32));
+    f(s->off, (z.bins_cap + 1) * sizeof(u32));
+    f(s->partial, (z.nparts + 1) * sizeof(u32));
+    if (plan.grouped) {
+        // partial groups: a tile of kTileGrouped points owns kTileGrouped slots
+        f(s->parts, z.ray_cap * sizeof(Partial));
+        f(s->parts_sorted, z.ray_cap * sizeof(Partial));
+        f(s->tile_parts, std::max<size_t>(plan.tiles, 1) * sizeof(u32));
+        f(s->chunk_first, (z.ray_cap / kMergeSpan + 2) * sizeof(u32));
+    }
+    if (plan.keep_touches) {
+        f(s->touch_key, z.touch_cap * sizeof(u64));
+        f(s->touch_n, z.touch_cap * sizeof(u32));
+    }
+    f(s->tables, z.tables_bytes);
+    f(s->jst, (size_t)njobs * sizeof(JobStat));
+    f(s->cs, sizeof(CallState));
+}
+
+void note_scratch_sizes(Scratch* s, const ScratchSizes& z) {
+    s->ray_cap = z.ray_cap;
+    s->cross_cap = z.cross_cap;
+    s->tlist_cap = z.tlist_cap;
+    s->bins_cap = z.bins_cap;
+    s->nparts = z.nparts;
+    s->tkey_cap = z.tkey_cap;
+    s->touch_cap = z.touch_cap;
+}
+
 // Grows a scratch set for a call on stream `st`; tables that must start cleared are cleared here.
 int ensure_scratch(Scratch* s, hipStream_t st, const CallPlan& plan, int njobs, int nmaps, size_t sum_capacity) {
-    const size_t ray_cap = std::max<size_t>(plan.ray_slots, 1);
-    const size_t cross_cap = ray_cap * (size_t)plan.max_blocks;
-    if (cross_cap > 0xFFFFFFF0ull || ray_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
-    const size_t tlist_cap = std::min<size_t>(std::max<size_t>(sum_capacity + 4096, 4096), cross_cap + 4096);
-    const size_t tkey_cap = next_pow2(2 * tlist_cap);
-    // grouped calls sort partial groups into kGroupSubBins bins per (block, frame)
-    const size_t bins_cap = tlist_cap * (size_t)plan.JM * (plan.grouped ? (size_t)kGroupSubBins : 1u);
-    if (bins_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
-    const size_t nparts = (bins_cap + kScanChunkHost - 1) / kScanChunkHost;
-    const size_t touch_cap =
-        plan.keep_touches ? std::min<size_t>(ray_cap * (size_t)plan.max_vox, (size_t)1 << 26) : 0;
+    ScratchSizes z;
+    int rc = scratch_sizes(plan, njobs, nmaps, sum_capacity, z);
+    if (rc != VBX_OK) return rc;
+    const size_t ray_cap = z.ray_cap, cross_cap = z.cross_cap, tlist_cap = z.tlist_cap, tkey_cap = z.tkey_cap,
+                 bins_cap = z.bins_cap, nparts = z.nparts, touch_cap = z.touch_cap;
 
     bool need_sync = false;
     auto grow = [&](DevBuf& b, size_t bytes) -> int {
@@ -490,6 +552,41 @@ void launch_update(int storage, int variant, hipStream_t st, const Job* jobs, co
                            touch_cap, keep, jst, cs);
 }
 
+// Lays a call's scratch buffers out in [base, base + cap), each aligned to 256 bytes.
+// VBX_ERR_LIMIT when they do not fit.
+int carve_scratch(Scratch* s, char* base, size_t cap, const CallPlan& plan, const ScratchSizes& z, int njobs) {
+    size_t off = 0;
+    bool fits = true;
+    for_each_scratch(s, plan, z, njobs, [&](DevBuf& b, size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        if (bytes == 0) bytes = 256;
+        if (!fits || bytes > cap || off > cap - bytes) {
+            fits = false;
+            return;
+        }
+        b.p = base + off;
+        b.bytes = bytes;
+        off += bytes;
+    });
+    if (!fits) return VBX_ERR_LIMIT;
+    note_scratch_sizes(s, z);
+    return VBX_OK;
+}
+
+// The region's state every call expects to find: an empty block set, zero sort bins, per-frame
+// and per-call counters.  Fill kernels only (no memset API).
+int clear_carved(Scratch* s, hipStream_t st, int njobs) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(s->tkey_cap)), dim3(256), 0, st, (u64*)s->tkeys.p, kEmpty,
+                       s->tkey_cap);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(s->bins_cap + 1)), dim3(256), 0, st, (u32*)s->bins.p, 0u,
+                       s->bins_cap + 1);
+    const size_t jst_words = (size_t)njobs * sizeof(JobStat) / 8;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(jst_words)), dim3(256), 0, st, (u64*)s->jst.p, 0ull, jst_words);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, (u32*)s->cs.p, 0u, sizeof(CallState) / 4);
+    return hipGetLastError() == hipSuccess ? VBX_OK : VBX_ERR_DEVICE;
+}
+
+
 // Records the start / end of a stage on the stream when profiling is on.
 struct StageTimer {
     vbx_map* m;
@@ -623,6 +720,40 @@ int stage_tables(Scratch* s, hipStream_t st, const Prepared& pr) {
     sg.used = true;
     return VBX_OK;
 }
+
+// Copies the map and job tables into s->tables through the arguments of word-copy launches.
+int put_tables(Scratch* s, hipStream_t st, const Prepared& pr) {
+    const size_t map_bytes = pr.descs.size() * sizeof(MapDesc);
+    const size_t job_bytes = pr.jobs.size() * sizeof(Job);
+    static_assert(sizeof(MapDesc) % 4 == 0 && sizeof(Job) % 4 == 0, "tables are whole words");
+    if (map_bytes + job_bytes > s->tables.bytes) return VBX_ERR_INVALID_ARG;
+    const unsigned char* src[2] = {(const unsigned char*)pr.descs.data(), (const unsigned char*)pr.jobs.data()};
+    const size_t len[2] = {map_bytes, job_bytes};
+    size_t dst_off = 0;
+    for (int part = 0; part < 2; ++part) {
+        for (size_t o = 0; o < len[part]; o += sizeof(TableChunk)) {
+            const size_t n = std::min(sizeof(TableChunk), len[part] - o);
+            TableChunk c;
+            std::memcpy(c.w, src[part] + o, n);
+            hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, st, c, (u32)(n / 4),
+                               (u32*)((char*)s->tables.p + dst_off));
+            dst_off += n;
+        }
+    }
+    return hipGetLastError() == hipSuccess ? VBX_OK : VBX_ERR_DEVICE;
+}
+
+// Per device: the region's device address (from hipGetSymbolAddress, with that device current,
+// once) and the host description of the buffers laid out in it.
+struct NoAllocDevice {
+    std::once_flag once;
+    hipError_t status = hipSuccess;
+    void* ptr = nullptr;
+    std::mutex lock;   // the host-side layout below is rewritten by every call
+    Scratch layout;
+};
+constexpr int kNoAllocDevices = 64;
+NoAllocDevice g_noalloc[kNoAllocDevices];
 
 // Resolves the once-per-process launch shapes before any capture.
 void warm_launch_shapes() {
@@ -1093,6 +1224,36 @@ int vbx_integrate_frames(vbx_map* m, const vbx_frame* frames, int F) {
     std::vector<vbx_frame> fr(frames, frames + F);
     std::vector<int> owner(F, 0);
     return run_call(maps, fr, owner);
+}
+
+int vbx_integrate_frames_noalloc(vbx_map* m, const vbx_frame* frames, int F) {
+    if (!m || F < 0 || (F > 0 && !frames)) return VBX_ERR_INVALID_ARG;
+    int dev = -1;
+    VBX_TRY(hipGetDevice(&dev));
+    if (dev != m->device || dev < 0 || dev >= kNoAllocDevices) return VBX_ERR_INVALID_ARG;
+    NoAllocDevice& D = g_noalloc[dev];
+    std::call_once(D.once, [&D] { D.status = hipGetSymbolAddress(&D.ptr, HIP_SYMBOL(scratch)); });
+    if (D.status != hipSuccess || !D.ptr) return VBX_ERR_DEVICE;
+    if (F == 0) return VBX_OK;
+    std::vector<vbx_map*> maps{m};
+    std::vector<vbx_frame> fr(frames, frames + F);
+    std::vector<int> owner(F, 0);
+    Prepared pr;
+    int rc = prepare_call(maps, fr, owner, pr);
+    if (rc != VBX_OK) return rc;
+    pr.plan.keep_touches = false;
+    const int J = (int)pr.jobs.size();
+    ScratchSizes z;
+    if ((rc = scratch_sizes(pr.plan, J, 1, pr.sum_capacity, z)) != VBX_OK) return rc;
+    std::lock_guard<std::mutex> g(D.lock);
+    Scratch* s = &D.layout;
+    if ((rc = carve_scratch(s, (char*)D.ptr, VBX_NOALLOC_SCRATCH_BYTES, pr.plan, z, J)) != VBX_OK) return rc;
+    hipStream_t st = m->stream;
+    if ((rc = clear_carved(s, st, J)) != VBX_OK) return rc;
+    if ((rc = put_tables(s, st, pr)) != VBX_OK) return rc;
+    if ((rc = launch_call(s, st, pr.plan, J, 1, m->update_variant, nullptr)) != VBX_OK) return rc;
+    m->touch_src = nullptr;   // no touch records for this call
+    return VBX_OK;
 }
 
 int vbx_integrate(vbx_map* m, const float* points_dev, size_t n, const float pose[12]) {

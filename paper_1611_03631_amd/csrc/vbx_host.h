@@ -15,7 +15,13 @@ struct JobStat {
 // Kernels (defined in vbx_kernels.hip).
 __global__ void k_fill_u64(u64* p, u64 val, size_t n);
 __global__ void k_fill_u32(u32* p, u32 val, size_t n);
+// Words of a host table passed by value in one launch's arguments.
+constexpr int kTableChunkWords = 256;
+struct TableChunk {
+    u32 w[kTableChunkWords];
+};
 __global__ void k_set_u32(u32* p, u32 v);
+__global__ void k_put_words(TableChunk c, u32 n, u32* dst);
 __global__ void k_map_clear(u64* hkeys, size_t hcap, u32* state, u32 state_words);
 __global__ void k_map_status(const MapDesc* maps, int nmaps, int* out);
 __global__ void k_points_simple(const Job* jobs, int njobs, const MapDesc* maps, float4* rays_p,

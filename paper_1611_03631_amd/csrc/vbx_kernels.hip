@@ -207,6 +207,12 @@ __global__ void k_fill_u32(u32* p, u32 val, size_t n) {
         p[i] = val;
 }
 __global__ void k_set_u32(u32* p, u32 v) { *p = v; }
+
+// Writes n <= kTableChunkWords words carried in the kernel's arguments to dst: host tables reach
+// the device in launch parameters, with no staging buffer.
+__global__ void k_put_words(TableChunk c, u32 n, u32* dst) {
+    for (u32 i = threadIdx.x; i < n; i += blockDim.x) dst[i] = c.w[i];
+}
 // Empties a map: every hash slot free, and (workgroup 0) its state words zero.
 __global__ void k_map_clear(u64* hkeys, size_t hcap, u32* state, u32 state_words) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < hcap; i += (size_t)gridDim.x * blockDim.x)
