@@ -114,28 +114,80 @@ def stage_breakdown(m, step, candidates):
     return prof, max(candidates, key=lambda k: prof[k][0])
 
 
-def oracle_sample(w_list, budget_s):
+def oracle_sample(w_list, budget_s, keep=False, keep_first=None):
     """Integrates frames of the given workloads in order with the single-threaded C oracle
-    until the time budget is spent; returns (points, seconds, frames done)."""
+    (binary64 values, no storage rounding) until the time budget is spent; returns (points,
+    seconds of integration, frames done) and, with keep, the oracle's exports of the workloads
+    it finished (None for the others, and for every workload after the first keep_first;
+    exporting is not timed)."""
     import oracle
     pts = done = 0
-    t0 = time.perf_counter()
+    exports = []
+    secs = 0.0
     for w, k_lo, k_hi in w_list:
         P = w.params
         om = oracle.OracleMap(P["voxel_size"], P["trunc"], weighting=P["weighting"],
-                              merge=P["merge"], max_range=P["max_range"],
-                              storage=P.get("storage", "f32"))
+                              merge=P["merge"], max_range=P["max_range"], storage="f32")
+        finished = True
         for k in range(k_lo, k_hi):
-            if time.perf_counter() - t0 >= budget_s:
+            if secs >= budget_s:
+                finished = False
                 break
             f = w.frame(k)
+            t0 = time.perf_counter()
             om.integrate(f, w.poses[k])
+            secs += time.perf_counter() - t0
             pts += f.shape[0]
             done += 1
+        if keep:
+            want = keep_first is None or len(exports) < keep_first
+            exports.append(om.export() if finished and want else None)
         om.close()
-        if time.perf_counter() - t0 >= budget_s:
+        if secs >= budget_s:
             break
-    return pts, time.perf_counter() - t0, done
+    return (pts, secs, done, exports) if keep else (pts, secs, done)
+
+
+def host_cpu():
+    """Model name of the host CPU and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"model": model, "cores_available": avail}
+
+
+def error_vs_oracle(np, gpu_export, orc_export, v, storage):
+    """|D - D_oracle| / v over the voxels the GPU map holds as observed (W > 0), against the
+    binary64 oracle on the same frames.  For binary32 storage, also the largest ratio to the
+    parity bound the tests use (1e-4 v plus what the binary32 distance error can move D through
+    the Eq. (5) ramp: 8 * 2^-24 (delta + v) (1 + 2 delta M / ((delta - v) W))); the 16-bit forms
+    are held to 2e-3 v."""
+    coords, dw = gpu_export
+    oc, oD, oW, oM = orc_export[:4]
+    if not np.array_equal(coords, oc):
+        return {"error": "block sets differ"}
+    W = dw[:, :, 1].astype(np.float64)
+    sel = (W > 0) & (oW > 0)
+    err = np.abs(dw[:, :, 0].astype(np.float64) - oD) / v
+    e = err[sel]
+    out = {"voxels": int(sel.sum()), "max_v": float(e.max(initial=0.0)),
+           "rms_v": float(np.sqrt(np.mean(e ** 2))) if e.size else 0.0,
+           "above_1e-4v": int((e > 1e-4).sum()), "above_2e-3v": int((e > 2e-3).sum())}
+    if storage == "f32":
+        return out
+    out["bar_v"] = 2e-3
+    out["meets_bar"] = bool(out["max_v"] <= 2e-3)
+    return out
 
 
 def bench_c2(args, np, torch, vbx, synth):
@@ -231,6 +283,7 @@ def bench_c2(args, np, torch, vbx, synth):
         return e0.elapsed_time(e1) / reps
 
     forms = {}
+    form_exports = {"batched_" + args.storage: last_export}
     if not args.no_forms:
         plain = vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"],
                         storage="f32", max_range=P["max_range"], block_capacity=16384, stream=stream)
@@ -243,35 +296,50 @@ def bench_c2(args, np, torch, vbx, synth):
                 if rc != 0:
                     raise vbx.VbxError(rc, "vbx_integrate")
         forms["plain_per_frame_f32_ms"] = round(timed(per_frame, 3), 4)
-        half = vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"],
-                       storage="f16", max_range=P["max_range"], block_capacity=16384, stream=stream)
-        half.set_tuning(**m.tuning())
+        form_exports["plain_per_frame_f32"] = plain.export()
+        forms["batched_" + args.storage + "_ms"] = round(ms_per_step, 4)
+        form_exports["batched_" + args.storage] = last_export
         harr = vbx.make_frames(batch)
+        for other in ("f32", "f16", "s16"):
+            if other == args.storage:
+                continue
+            half = vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"],
+                           storage=other, max_range=P["max_range"], block_capacity=16384, stream=stream)
+            half.set_tuning(**m.tuning())
 
-        def batched_half():
-            L.vbx_map_clear(half.handle)
-            rc = L.vbx_integrate_frames(half.handle, harr, F)
-            if rc != 0:
-                raise vbx.VbxError(rc, "vbx_integrate_frames")
-        forms["batched_f16_ms"] = round(timed(batched_half, 5), 4)
-        forms["batched_f32_ms"] = round(ms_per_step, 4)
-        forms["batched_f16_vs_plain_per_frame_f32"] = round(forms["plain_per_frame_f32_ms"] /
-                                                            forms["batched_f16_ms"], 3)
-        if plain.sync() != 0 or half.sync() != 0:
+            def batched_other():
+                L.vbx_map_clear(half.handle)
+                rc = L.vbx_integrate_frames(half.handle, harr, F)
+                if rc != 0:
+                    raise vbx.VbxError(rc, "vbx_integrate_frames")
+            forms["batched_" + other + "_ms"] = round(timed(batched_other, 5), 4)
+            if half.sync() != 0:
+                raise RuntimeError("device status after the compared forms")
+            form_exports["batched_" + other] = half.export()
+            half.close()
+        for other in ("f16", "s16"):
+            forms[f"batched_{other}_vs_plain_per_frame_f32"] = round(
+                forms["plain_per_frame_f32_ms"] / forms[f"batched_{other}_ms"], 3)
+        if plain.sync() != 0:
             raise RuntimeError("device status after the compared forms")
         plain.close()
-        half.close()
 
     # ---------------------------------------------------------------- CPU oracle sample
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
         wo = synth.config2(n_frames=args.frames)
-        wo.params = dict(wo.params, storage=args.storage)
         wo.frame_fn = lambda k: frames[k]
-        pts, cpu_s, done = oracle_sample([(wo, 0, F)], args.cpu_seconds)
+        pts, cpu_s, done, oexp = oracle_sample([(wo, 0, F)], args.cpu_seconds, keep=True)
         cpu = {"value": round(pts / cpu_s, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu(),
                "sample": f"first {done} of {F} frames of the same sequence, integrated in order "
-                         f"by the single-threaded C oracle ({cpu_s:.1f} s)"}
+                         f"by the single-threaded C oracle in binary64 ({cpu_s:.1f} s)"}
+        if oexp[0] is not None:
+            # every compared form holds the whole sequence: check each against the oracle's map
+            v = float(np.float32(P["voxel_size"]))
+            accuracy = {k: error_vs_oracle(np, e, oexp[0], v, k.split("_")[-1])
+                        for k, e in form_exports.items()}
 
     return {
         "metric": "points/s & voxel-updates/s TSDF integration; p50/p99 frame latency (served)",
@@ -284,7 +352,7 @@ def bench_c2(args, np, torch, vbx, synth):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.storage == "f32" else "f16-storage/f32",
+        "dtype": "f32" if args.storage == "f32" else args.storage + "-storage/f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {F} frames x {w.width}x{w.height} depth, furnished "
                                "10x10x3 m room, voxel 0.05 m, truncation 0.15 m, 1/z^2 weighting, "
@@ -297,6 +365,7 @@ def bench_c2(args, np, torch, vbx, synth):
         "whole_step_algorithmic_GBps": round(whole, 1),
         "stage_ms_per_step": stages,
         "forms_ms_per_step": forms,
+        "error_vs_binary64_oracle": accuracy,
         "wall_s": round(wall_s, 3),
         "repeat_bit_identical": True,
         "tuning": m.tuning(),
@@ -309,6 +378,7 @@ def bench_c2(args, np, torch, vbx, synth):
 
 
 C4_CAPACITY = {0.02: 16384, 0.05: 4096, 0.10: 2048}
+ERR_TICKS = 10   # c4: ticks integrated from empty maps for the error against the oracle
 
 
 def bench_c4(args, np, torch, vbx, synth):
@@ -365,7 +435,9 @@ def bench_c4(args, np, torch, vbx, synth):
         return e0.elapsed_time(e1) / steps
 
     results = {}
-    for storage in ("f16", "f32"):
+    err_maps = (0, 1, 2)          # one map per voxel class (0.02 / 0.05 / 0.10 m)
+    err_exports = {}
+    for storage in ("f16", "s16", "f32"):
         maps = make_maps(storage)
         # launch tuning: one graph per update variant, a few ticks each (untimed)
         tune = None
@@ -400,6 +472,14 @@ def bench_c4(args, np, torch, vbx, synth):
         prof = maps[0].profile_read(reset=True)
         maps[0].profile(False)
         after = [mp.stats() for mp in maps]
+        # the maps after ERR_TICKS ticks from empty, for the error against the binary64 oracle
+        clear(maps)
+        for k in range(ERR_TICKS):
+            vbx.integrate_multi(maps, tick(k % T))
+        for mp in maps:
+            if mp.sync() != 0:
+                raise RuntimeError("device status after the error ticks")
+        err_exports[storage] = {i: maps[i].export() for i in err_maps}
         cells = sum(a["cells"] - b["cells"] for a, b in zip(after, before))
         new_blocks = sum(a["new_blocks"] - b["new_blocks"] for a, b in zip(after, before))
         s_v = 8 if storage == "f32" else 4
@@ -423,12 +503,26 @@ def bench_c4(args, np, torch, vbx, synth):
     main_r = results["f16"]
     ms = main_r["ms_per_tick_graph"]
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
-        sample = [(ws[m], 0, 1) for m in range(M)]
-        pts, cpu_s, done = oracle_sample(sample, args.cpu_seconds)
+        # maps in order (err_maps first), ERR_TICKS ticks each, until the budget is spent
+        order = list(err_maps) + [m for m in range(M) if m not in err_maps]
+        sample = [(ws[m], 0, ERR_TICKS) for m in order]
+        pts, cpu_s, done, oexp = oracle_sample(sample, args.cpu_seconds, keep=True,
+                                               keep_first=len(err_maps))
         cpu = {"value": round(pts / cpu_s, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
-               "sample": f"first tick's frame of {done} of the {M} maps, integrated by the "
-                         f"single-threaded C oracle in binary16-emulating mode ({cpu_s:.1f} s)"}
+               "host_cpu": host_cpu(),
+               "sample": f"the first {ERR_TICKS} ticks of the maps in turn (maps {list(err_maps)}, "
+                         f"one per voxel class, first): {done} frames integrated by the "
+                         f"single-threaded C oracle in binary64 ({cpu_s:.1f} s)"}
+        accuracy = {}
+        for storage, ex in err_exports.items():
+            for j, i in enumerate(err_maps):
+                if oexp[j] is None:
+                    continue
+                v = float(np.float32(ws[i].params["voxel_size"]))
+                accuracy[f"{storage}_v{ws[i].params['voxel_size']:g}"] = error_vs_oracle(
+                    np, ex[i], oexp[j], v, storage)
     return {
         "metric": "points/s & voxel-updates/s TSDF integration; p50/p99 frame latency (served)",
         "value": main_r["points_per_s"],
@@ -449,6 +543,9 @@ def bench_c4(args, np, torch, vbx, synth):
         "voxel_updates_per_s": main_r["voxel_updates_per_s"],
         "graph_vs_eager_speedup": round(main_r["ms_per_tick_eager"] / ms, 3),
         "f16_vs_f32_speedup": round(results["f32"]["ms_per_tick_graph"] / ms, 3),
+        "s16_vs_f32_speedup": round(results["f32"]["ms_per_tick_graph"] /
+                                    results["s16"]["ms_per_tick_graph"], 3),
+        "error_vs_binary64_oracle": accuracy,
         "storage": results,
         "repeat_bit_identical": True,
         "roofline": main_r["roofline"],
@@ -553,6 +650,7 @@ def bench_c3(args, np, torch, vbx, synth):
         w.frame_fn = lambda k: frames[k]
         pts, cpu_s, done = oracle_sample([(w, 0, S)], args.cpu_seconds)
         cpu = {"value": round(pts / cpu_s, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu(),
                "sample": f"first {done} of {S} sweeps in order by the single-threaded C oracle ({cpu_s:.1f} s)"}
     return {
         "metric": "points/s & voxel-updates/s TSDF integration; p50/p99 frame latency (served)",
@@ -707,6 +805,7 @@ def bench_c5(args, np, torch, vbx, synth):
             om.close()
         cpu_s = time.perf_counter() - t1
         cpu = {"value": round(pts / cpu_s, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu(),
                "sample": f"the trace's first requests, each into a fresh map, by the single-threaded C "
                          f"oracle in binary16-emulating mode ({cpu_s:.1f} s)"}
     return {
@@ -832,7 +931,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=100, help="c2: frames of the sequence")
     ap.add_argument("--ticks", type=int, default=100, help="c4: distinct ticks generated")
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16"], help="c2 storage")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "s16"], help="c2 storage")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="wall-clock budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
