@@ -268,6 +268,59 @@ int vbx_map_stats(vbx_map* map, vbx_stats* out);
 #define VBX_MAX_QUERY_POINTS (1u << 31)
 int vbx_map_interpolate(vbx_map* map, const float* points_dev, size_t n, float* dist_dev);
 
+/* Writes n TSDF blocks into the map (Sec. III layer of blocks): coords host [n][3] block indices,
+ * dw host [n][4096][2] (D in metres, W), values rounded to the map's storage.  Blocks the map
+ * holds are overwritten in place (same pool slot); missing ones are allocated.  Every written
+ * block counts as changed for the next vbx_esdf_update.  VBX_ERR_POOL_FULL (map unchanged) when
+ * the new blocks do not fit; VBX_ERR_INVALID_ARG for indices outside the voxel range.
+ * Synchronises. */
+int vbx_write_blocks(vbx_map* map, const int32_t* coords, const float* dw, size_t n);
+
+/* ---- ESDF layer -----------------------------------------------------------------------
+ * The Euclidean signed distance field built from the TSDF (Sec. V-A, Algorithm 1): ESDF voxels
+ * co-located with the TSDF voxels.  TSDF voxels with |D| < gamma form the fixed band, which
+ * takes its values from the TSDF; the other observed voxels (W > 0) take the distance of the
+ * band along 26-neighbour paths (quasi-Euclidean steps v, sqrt(2) v, sqrt(3) v), up to d_max,
+ * on their own side of the surface.  Unknown voxels (W = 0) take no distance and pass none on.
+ * An update looks at the blocks integration (or vbx_write_blocks / vbx_import_blocks) changed
+ * since the last update: voxels whose band value rose, or that left the band, start a raise
+ * wave that resets the voxels whose distance came from them; new and changed band voxels and
+ * the raise wave's border start a lower wave.  The waves run level by level on the device
+ * (each level one launch over its frontier), raise first, then lower; the converged field does
+ * not depend on the processing order. */
+typedef struct {
+    float gamma;       /* fixed band radius (metres, > 0); the paper recommends one voxel */
+    float d_max;       /* largest distance the field holds (metres, >= gamma) */
+    uint32_t reserved[6];
+} vbx_esdf_params;
+
+typedef struct {
+    uint64_t updates;          /* vbx_esdf_update calls */
+    uint32_t dirty_blocks;     /* blocks looked at by the last update */
+    uint32_t raise_rounds;     /* levels of the last update's raise wave */
+    uint32_t lower_rounds;     /* levels of the last update's lower wave */
+    uint32_t reserved;
+    uint64_t voxels;           /* voxels the layer holds (allocated blocks * 4096) */
+} vbx_esdf_stats;
+
+/* Attaches an ESDF layer to the map (its memory comes from the map's allocator).  Every block
+ * the map holds counts as changed for the first update.  INVALID_ARG for bad parameters or a
+ * map that already has a layer. */
+int vbx_esdf_enable(vbx_map* map, const vbx_esdf_params* params);
+
+/* Propagates the TSDF changes since the last update into the ESDF layer (Algorithm 1).
+ * Synchronises (the host reads the frontier sizes between levels).  Returns the map's sticky
+ * error if it has one.  out (may be NULL) receives the layer's statistics. */
+int vbx_esdf_update(vbx_map* map, vbx_esdf_stats* out);
+
+/* Exports the ESDF layer block by block in ascending (bx, by, bz) order, the TSDF export's order
+ * (synchronises): coords host [cap][3] or NULL; d host [cap][4096] float32 signed distance
+ * (metres; 0 for unobserved voxels) or NULL; info host [cap][4096] uint8 or NULL: bit 0
+ * observed, bit 1 fixed, bits 2..6 the parent's neighbour index (dx + 1) + 3 (dy + 1) +
+ * 9 (dz + 1), 13 for none, bit 7 negative side.  BUFFER_TOO_SMALL when cap is below the
+ * block count. */
+int vbx_esdf_export(vbx_map* map, int32_t* coords, float* d, uint8_t* info, size_t cap, size_t* n_out);
+
 /* Traversal primitive, for verification: for each i < n, the voxels visited between
  * the voxel-space points A_dev[i] and B_dev[i] (dev [n][3] float32), in order,
  * written to out_dev[i][cap][3] (int32), count to counts_dev[i] (may exceed cap;

@@ -15,8 +15,8 @@
  * surface takes its value from the TSDF and is never modified by the waves).
  *  - fixed: an unobserved voxel takes d_T and enters the lower queue; an observed one
  *    takes d_T and enters both the raise and the lower queue;
- *  - not fixed: a voxel that was fixed becomes sign(d_T) d_max and enters the raise
- *    queue; an unobserved voxel becomes sign(d_T) d_max and puts its observed
+ *  - not fixed: a voxel that was fixed, or whose TSDF distance changed sign, becomes
+ *    sign(d_T) d_max and enters the raise queue; an unobserved voxel becomes sign(d_T) d_max and puts its observed
  *    neighbours in the lower queue; an observed voxel that was not fixed is left.
  * Then the raise queue is emptied (a popped voxel that is not fixed returns to
  * sign(d) d_max and loses its parent; each observed neighbour is raised when its
@@ -43,6 +43,10 @@
  *    neighbour is the popped voxel's child when its parent direction points back at
  *    the popped voxel.
  *  - The fixed flag of the ESDF voxel follows |d_T| < gamma at every update.
+ *  - The listing leaves an observed voxel outside the band alone.  One whose TSDF
+ *    distance changed sign (without passing through the band) is treated as a voxel
+ *    that left the band, so that its side follows the TSDF and the voxels that took
+ *    their distance from it on the old side are raised.
  *  - The listing sends a fixed voxel whose distance decreased to the lower queue
  *    only.  That holds for unsigned distances; with signed ones a voxel whose value
  *    decreases moves its negative dependents away from zero, which only a raise
@@ -331,12 +335,14 @@ void orc_esdf_update(orc_esdf* E, size_t n, const int32_t* coords, const double*
                 insert_lower(E, k);
             } else {
                 x->fixed = 1;
+                x->neg = dt < 0.0;       /* a band voxel's side is the sign of its value */
                 x->d = dt;
                 x->parent = 13;
                 fifo_push(&E->raise, k);
                 insert_lower(E, k);
             }
-        } else if (x->fixed) {
+        } else if (x->fixed || (x->observed && (dt < 0.0) != (x->neg != 0))) {
+            /* left the band, or changed side outside it */
             x->fixed = 0;
             x->observed = 1;
             x->neg = dt < 0.0;

@@ -55,6 +55,16 @@ class MapParams(ctypes.Structure):
                 ("alloc_ctx", ctypes.c_void_p)]
 
 
+class EsdfParams(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_float), ("d_max", ctypes.c_float), ("reserved", ctypes.c_uint32 * 6)]
+
+
+class EsdfStats(ctypes.Structure):
+    _fields_ = [("updates", ctypes.c_uint64), ("dirty_blocks", ctypes.c_uint32),
+                ("raise_rounds", ctypes.c_uint32), ("lower_rounds", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("voxels", ctypes.c_uint64)]
+
+
 class Frame(ctypes.Structure):
     _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_uint64), ("width", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32), ("pose", ctypes.c_float * 12)]
@@ -68,7 +78,8 @@ class Stats(ctypes.Structure):
 
 EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_map_destroy",
             "vbx_map_set_stream", "vbx_integrate", "vbx_integrate_batch", "vbx_integrate_frames",
-            "vbx_integrate_frames_noalloc",
+            "vbx_integrate_frames_noalloc", "vbx_write_blocks", "vbx_esdf_enable", "vbx_esdf_update",
+            "vbx_esdf_export",
             "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
             "vbx_map_stats", "vbx_map_interpolate", "vbx_debug_traverse", "vbx_status_string",
@@ -144,6 +155,10 @@ def lib(path: Optional[str] = None):
     L.vbx_map_num_blocks.argtypes = [vp, ctypes.POINTER(sz)]
     L.vbx_export_blocks.argtypes = [vp, vp, vp, sz, ctypes.POINTER(sz)]
     L.vbx_import_blocks.argtypes = [vp, vp, vp, sz]
+    L.vbx_write_blocks.argtypes = [vp, vp, vp, sz]
+    L.vbx_esdf_enable.argtypes = [vp, ctypes.POINTER(EsdfParams)]
+    L.vbx_esdf_update.argtypes = [vp, ctypes.POINTER(EsdfStats)]
+    L.vbx_esdf_export.argtypes = [vp, vp, vp, vp, sz, ctypes.POINTER(sz)]
     L.vbx_last_touches.argtypes = [vp, vp, vp, sz, ctypes.POINTER(sz)]
     L.vbx_map_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.vbx_debug_traverse.argtypes = [vp, vp, i32, vp, i32, vp]
@@ -349,6 +364,39 @@ class Map:
         _check(L.vbx_export_blocks(self._h, coords.ctypes.data, dw.ctypes.data, B, ctypes.byref(n)),
                "vbx_export_blocks")
         return coords, dw
+
+    def write_blocks(self, coords: np.ndarray, dw: np.ndarray):
+        """Writes TSDF blocks (coords [B,3], dw [B,4096,2], D in metres) in place, allocating the
+        missing ones; they count as changed for the next ESDF update."""
+        c = np.ascontiguousarray(coords, np.int32).reshape(-1, 3)
+        d = np.ascontiguousarray(dw, np.float32).reshape(-1, 4096, 2)
+        _check(lib().vbx_write_blocks(self._h, c.ctypes.data, d.ctypes.data, c.shape[0]),
+               "vbx_write_blocks")
+
+    # -- ESDF layer (Sec. V-A) ------------------------------------------------
+    def esdf_enable(self, gamma: float, d_max: float):
+        p = EsdfParams()
+        p.gamma, p.d_max = gamma, d_max
+        _check(lib().vbx_esdf_enable(self._h, ctypes.byref(p)), "vbx_esdf_enable")
+
+    def esdf_update(self) -> dict:
+        st = EsdfStats()
+        _check(lib().vbx_esdf_update(self._h, ctypes.byref(st)), "vbx_esdf_update")
+        return {n: int(getattr(st, n)) for n, _ in EsdfStats._fields_ if n != "reserved"}
+
+    def esdf_export(self):
+        """(coords int32 [B,3] ascending, d float32 [B,4096] signed metres, info uint8 [B,4096]:
+        bit 0 observed, bit 1 fixed, bits 2..6 parent neighbour index, bit 7 negative side)."""
+        L = lib()
+        n = ctypes.c_size_t()
+        _check(L.vbx_esdf_export(self._h, None, None, None, 0, ctypes.byref(n)), "vbx_esdf_export")
+        B = int(n.value)
+        coords = np.zeros((B, 3), np.int32)
+        d = np.zeros((B, 4096), np.float32)
+        info = np.zeros((B, 4096), np.uint8)
+        _check(L.vbx_esdf_export(self._h, coords.ctypes.data, d.ctypes.data, info.ctypes.data, B,
+                                 ctypes.byref(n)), "vbx_esdf_export")
+        return coords, d, info
 
     def import_blocks(self, coords: np.ndarray, dw: np.ndarray):
         c = np.ascontiguousarray(coords, np.int32).reshape(-1, 3)

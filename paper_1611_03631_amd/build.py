@@ -11,7 +11,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libvbx.so")
-SOURCES = [os.path.join(CSRC, "vbx_kernels.hip"), os.path.join(CSRC, "vbx_api.hip")]
+SOURCES = [os.path.join(CSRC, "vbx_kernels.hip"), os.path.join(CSRC, "vbx_esdf.hip"),
+           os.path.join(CSRC, "vbx_api.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

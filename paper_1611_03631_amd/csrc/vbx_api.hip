@@ -96,6 +96,19 @@ struct Profiler {
 
 enum { ST_POINTS, ST_GROUPS, ST_CROSS, ST_RESOLVE, ST_COMMIT, ST_BINS, ST_SCAN, ST_SCATTER, ST_UPDATE, ST_FINISH };
 
+// A map's ESDF layer (host side).  The voxel words cover the pool slots [0, vox_blocks), grown
+// with the map; the dirty flags cover the whole pool.
+struct Esdf {
+    vbx_esdf_params P;
+    u64* vox = nullptr;          // map memory: [vox_blocks * 4096]
+    size_t vox_blocks = 0;
+    u32* dirty = nullptr;        // map memory: [dirty_cap]
+    u32 dirty_cap = 0;
+    DevBuf rstamp, lstamp, list, nbr, slot_key, raise0, raise1, lower0, lower1, cnt;
+    u32 tag = 0;                 // last frontier tag handed out (tags only grow)
+    vbx_esdf_stats stats = {};
+};
+
 struct vbx_map {
     vbx_map_params P;
     Profiler prof;
@@ -114,6 +127,7 @@ struct vbx_map {
     Scratch* touch_src = nullptr; // scratch holding this map's last touches
     int touch_idx = 0;
     int update_variant = 6;       // index into kUpdateVariants (whole block, 1024 threads)
+    Esdf* esdf = nullptr;         // ESDF layer, when enabled
 };
 
 // A captured call: the kernel sequence of one integration call over fixed maps and frame
@@ -227,6 +241,7 @@ MapDesc make_desc(const vbx_map* m, int map_id, int job0, int njobs) {
     d.capacity = m->capacity;
     d.pool = m->pool;
     d.st = m->st;
+    d.dirty = m->esdf ? m->esdf->dirty : nullptr;
     return d;
 }
 
@@ -935,6 +950,90 @@ void host_insert(std::vector<u64>& keys, std::vector<int>& slots, u64 key, int s
     slots[h] = slot;
 }
 
+// One block of host values (dw [4096][2]: D metres, W) in the map's pool format.
+void encode_block(const vbx_map* m, const float* dw, unsigned char* out) {
+    for (int l = 0; l < 4096; ++l) {
+        const float D = dw[2 * l];
+        const float W = dw[2 * l + 1];
+        if (m->P.storage == VBX_F32) {
+            float* v = (float*)out + 2 * l;
+            v[0] = D;
+            v[1] = W;
+        } else {
+            const float dn = D / m->P.trunc;
+            const uint32_t dc = m->P.storage == VBX_F16 ? (uint32_t)__half_as_ushort(__float2half_rn(dn))
+                                                        : (uint32_t)s16_encode(dn);
+            const uint32_t wc = __half_as_ushort(__float2half_rn(W));
+            ((uint32_t*)out)[l] = dc | (wc << 16);
+        }
+    }
+}
+
+// ---- ESDF layer (host side) ------------------------------------------------------------
+
+// Grows the layer's voxel words to cover `blocks` pool slots (content kept, new words zero:
+// unobserved).
+int esdf_grow_vox(vbx_map* m, size_t blocks) {
+    Esdf* e = m->esdf;
+    if (blocks <= e->vox_blocks) return VBX_OK;
+    u64* nv = nullptr;
+    if (map_alloc(m, (void**)&nv, blocks * 4096 * sizeof(u64)) != VBX_OK) return VBX_ERR_OUT_OF_MEMORY;
+    if (e->vox_blocks)
+        VBX_TRY(hipMemcpyAsync(nv, e->vox, e->vox_blocks * 4096 * sizeof(u64), hipMemcpyDeviceToDevice, m->stream));
+    const size_t fresh = (blocks - e->vox_blocks) * 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(fresh)), dim3(256), 0, m->stream, nv + e->vox_blocks * 4096, 0ull,
+                       fresh);
+    VBX_TRY(hipStreamSynchronize(m->stream));
+    map_free(m, e->vox);
+    e->vox = nv;
+    e->vox_blocks = blocks;
+    return VBX_OK;
+}
+
+// Grows the dirty flags to the pool capacity (flags kept, new ones clear).
+int esdf_grow_dirty(vbx_map* m) {
+    Esdf* e = m->esdf;
+    if (m->capacity <= e->dirty_cap) return VBX_OK;
+    u32* nd = nullptr;
+    if (map_alloc(m, (void**)&nd, (size_t)m->capacity * sizeof(u32)) != VBX_OK) return VBX_ERR_OUT_OF_MEMORY;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(m->capacity)), dim3(256), 0, m->stream, nd, 0u, (size_t)m->capacity);
+    if (e->dirty_cap)
+        VBX_TRY(hipMemcpyAsync(nd, e->dirty, (size_t)e->dirty_cap * sizeof(u32), hipMemcpyDeviceToDevice, m->stream));
+    VBX_TRY(hipStreamSynchronize(m->stream));
+    map_free(m, e->dirty);
+    e->dirty = nd;
+    e->dirty_cap = m->capacity;
+    return VBX_OK;
+}
+
+// Every voxel unobserved and the first `mark` pool slots dirty (after the map was cleared or
+// replaced).
+void esdf_reset(vbx_map* m, size_t mark) {
+    Esdf* e = m->esdf;
+    if (!e) return;
+    if (e->vox_blocks)
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(e->vox_blocks * 4096)), dim3(256), 0, m->stream, e->vox, 0ull,
+                           e->vox_blocks * 4096);
+    if (e->dirty_cap)
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(e->dirty_cap)), dim3(256), 0, m->stream, e->dirty, 0u,
+                           (size_t)e->dirty_cap);
+    if (mark)
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(mark)), dim3(256), 0, m->stream, e->dirty, 1u, mark);
+}
+
+void esdf_free(vbx_map* m) {
+    Esdf* e = m->esdf;
+    if (!e) return;
+    map_free(m, e->vox);
+    map_free(m, e->dirty);
+    DevBuf* bufs[] = {&e->rstamp, &e->lstamp, &e->list, &e->nbr, &e->slot_key, &e->raise0, &e->raise1,
+                      &e->lower0, &e->lower1, &e->cnt};
+    for (DevBuf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    delete e;
+    m->esdf = nullptr;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1204,6 +1303,7 @@ void vbx_map_destroy(vbx_map* m) {
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : m->prof.spare) (void)hipEventDestroy(e);
+    esdf_free(m);
     free_storage(m);
     map_free(m, m->st);
     free_scratch(m->scratch);
@@ -1365,6 +1465,7 @@ int vbx_map_reserve(vbx_map* m, uint32_t block_capacity) {
     map_free(m, old_slots);
     map_free(m, old_pool);
     m->P.block_capacity = block_capacity;
+    if (m->esdf && (rc = esdf_grow_dirty(m)) != VBX_OK) return rc;
     if (s.error == VBX_ERR_POOL_FULL) {
         s.error = 0;
         VBX_TRY(hipMemcpy(m->st, &s, sizeof s, hipMemcpyHostToDevice));
@@ -1443,21 +1544,7 @@ int vbx_import_blocks(vbx_map* m, const int32_t* coords, const float* dw, size_t
         const int lim = kVoxLimit / 16;
         if (bx < -lim || bx >= lim || by < -lim || by >= lim || bz < -lim || bz >= lim) return VBX_ERR_INVALID_ARG;
         host_insert(keys, slots, pack_block(bx, by, bz), (int)b);
-        for (int l = 0; l < 4096; ++l) {
-            const float D = dw[2 * (b * 4096 + l)];
-            const float W = dw[2 * (b * 4096 + l) + 1];
-            if (m->P.storage == VBX_F32) {
-                float* v = (float*)pool.data() + 2 * (b * 4096 + l);
-                v[0] = D;
-                v[1] = W;
-            } else {
-                const float dn = D / m->P.trunc;
-                const uint32_t d = m->P.storage == VBX_F16 ? (uint32_t)__half_as_ushort(__float2half_rn(dn))
-                                                           : (uint32_t)s16_encode(dn);
-                const uint32_t w = __half_as_ushort(__float2half_rn(W));
-                ((uint32_t*)pool.data())[b * 4096 + l] = d | (w << 16);
-            }
-        }
+        encode_block(m, dw + 2 * b * 4096, pool.data() + b * 4096 * m->voxel_bytes);
     }
     VBX_TRY(hipMemcpy(m->hkeys, keys.data(), sizeof(u64) * m->hcap, hipMemcpyHostToDevice));
     VBX_TRY(hipMemcpy(m->hslots, slots.data(), sizeof(int) * m->hcap, hipMemcpyHostToDevice));
@@ -1466,6 +1553,7 @@ int vbx_import_blocks(vbx_map* m, const int32_t* coords, const float* dw, size_t
     s.new_count = 0;
     s.error = 0;
     VBX_TRY(hipMemcpy(m->st, &s, sizeof s, hipMemcpyHostToDevice));
+    esdf_reset(m, n);      // new slots: the ESDF starts over from every imported block
     return VBX_OK;
 }
 
@@ -1560,7 +1648,223 @@ int vbx_map_clear(vbx_map* m) {
     if (!m) return VBX_ERR_INVALID_ARG;
     hipLaunchKernelGGL(k_map_clear, dim3(grid_for(m->hcap)), dim3(256), 0, m->stream, m->hkeys, (size_t)m->hcap,
                        (u32*)m->st, (u32)(sizeof(MapState) / 4));
+    esdf_reset(m, 0);
     VBX_TRY(hipGetLastError());
+    return VBX_OK;
+}
+
+int vbx_write_blocks(vbx_map* m, const int32_t* coords, const float* dw, size_t n) {
+    if (!m || (n > 0 && (!coords || !dw))) return VBX_ERR_INVALID_ARG;
+    if (n == 0) return VBX_OK;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    std::vector<u64> keys(m->hcap);
+    std::vector<int> slots(m->hcap);
+    VBX_TRY(hipMemcpy(keys.data(), m->hkeys, sizeof(u64) * m->hcap, hipMemcpyDeviceToHost));
+    VBX_TRY(hipMemcpy(slots.data(), m->hslots, sizeof(int) * m->hcap, hipMemcpyDeviceToHost));
+    // the slot of every block: the one it holds, or the next free one
+    std::vector<int> where(n);
+    u32 count = s.block_count;
+    const int lim = kVoxLimit / 16;
+    for (size_t b = 0; b < n; ++b) {
+        const int bx = coords[3 * b], by = coords[3 * b + 1], bz = coords[3 * b + 2];
+        if (bx < -lim || bx >= lim || by < -lim || by >= lim || bz < -lim || bz >= lim) return VBX_ERR_INVALID_ARG;
+        const u64 key = pack_block(bx, by, bz);
+        const u32 mask = m->hcap - 1;
+        u32 h = (u32)mix64(key) & mask;
+        while (keys[h] != kEmpty && keys[h] != key) h = (h + 1) & mask;
+        if (keys[h] == key) {
+            where[b] = slots[h];
+        } else {
+            if (count >= m->capacity) return VBX_ERR_POOL_FULL;    // nothing written yet
+            keys[h] = key;
+            slots[h] = (int)count;
+            where[b] = (int)count++;
+        }
+    }
+    std::vector<unsigned char> block(4096 * m->voxel_bytes);
+    const u32 one = 1u;
+    for (size_t b = 0; b < n; ++b) {
+        encode_block(m, dw + 2 * b * 4096, block.data());
+        VBX_TRY(hipMemcpy((char*)m->pool + (size_t)where[b] * 4096 * m->voxel_bytes, block.data(), block.size(),
+                          hipMemcpyHostToDevice));
+        if (m->esdf) VBX_TRY(hipMemcpy(m->esdf->dirty + where[b], &one, sizeof one, hipMemcpyHostToDevice));
+    }
+    VBX_TRY(hipMemcpy(m->hkeys, keys.data(), sizeof(u64) * m->hcap, hipMemcpyHostToDevice));
+    VBX_TRY(hipMemcpy(m->hslots, slots.data(), sizeof(int) * m->hcap, hipMemcpyHostToDevice));
+    s.block_count = count;
+    VBX_TRY(hipMemcpy(m->st, &s, sizeof s, hipMemcpyHostToDevice));
+    return VBX_OK;
+}
+
+int vbx_esdf_enable(vbx_map* m, const vbx_esdf_params* p) {
+    if (!m || !p || m->esdf) return VBX_ERR_INVALID_ARG;
+    if (!(p->gamma > 0.0f) || !std::isfinite(p->d_max) || !(p->d_max >= p->gamma)) return VBX_ERR_INVALID_ARG;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    m->esdf = new (std::nothrow) Esdf();
+    if (!m->esdf) return VBX_ERR_OUT_OF_MEMORY;
+    m->esdf->P = *p;
+    if ((rc = esdf_grow_dirty(m)) != VBX_OK) {
+        esdf_free(m);
+        return rc;
+    }
+    // the blocks the map already holds are new to the layer
+    if (s.block_count)
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(s.block_count)), dim3(256), 0, m->stream, m->esdf->dirty, 1u,
+                           (size_t)s.block_count);
+    VBX_TRY(hipStreamSynchronize(m->stream));
+    return VBX_OK;
+}
+
+int vbx_esdf_update(vbx_map* m, vbx_esdf_stats* out) {
+    if (!m || !m->esdf) return VBX_ERR_INVALID_ARG;
+    Esdf* e = m->esdf;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    if (s.error) return s.error;
+    const u32 nb = s.block_count;
+    e->stats.dirty_blocks = 0;
+    e->stats.raise_rounds = 0;
+    e->stats.lower_rounds = 0;
+    e->stats.updates++;
+    e->stats.voxels = (uint64_t)nb * 4096;
+    if (nb == 0) {
+        if (out) *out = e->stats;
+        return VBX_OK;
+    }
+    hipStream_t st = m->stream;
+    if ((rc = esdf_grow_dirty(m)) != VBX_OK || (rc = esdf_grow_vox(m, nb)) != VBX_OK) return rc;
+    const size_t nv = (size_t)nb * 4096;
+    // stamps: grown buffers start at 0, which no tag takes; old tags are all below the next ones
+    auto grow_zero = [&](DevBuf& b, size_t bytes) -> int {
+        if (b.bytes >= bytes && b.p) return VBX_OK;
+        if (dev_alloc(b, bytes) != VBX_OK) return VBX_ERR_OUT_OF_MEMORY;
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(bytes / 4)), dim3(256), 0, st, (u32*)b.p, 0u, bytes / 4);
+        return VBX_OK;
+    };
+    if (grow_zero(e->rstamp, nv * 4) != VBX_OK || grow_zero(e->lstamp, nv * 4) != VBX_OK ||
+        dev_alloc(e->list, (size_t)nb * 4) != VBX_OK || dev_alloc(e->nbr, (size_t)nb * 27 * 4) != VBX_OK ||
+        dev_alloc(e->slot_key, (size_t)nb * 8) != VBX_OK || dev_alloc(e->raise0, nv * 4) != VBX_OK ||
+        dev_alloc(e->raise1, nv * 4) != VBX_OK || dev_alloc(e->lower0, nv * 4) != VBX_OK ||
+        dev_alloc(e->lower1, nv * 4) != VBX_OK || dev_alloc(e->cnt, kEsdfCounters * 4) != VBX_OK)
+        return VBX_ERR_OUT_OF_MEMORY;
+    EsdfDev E;
+    E.vox = e->vox;
+    E.rstamp = (u32*)e->rstamp.p;
+    E.lstamp = (u32*)e->lstamp.p;
+    E.list = (u32*)e->list.p;
+    E.nbr = (int*)e->nbr.p;
+    E.raise[0] = (u32*)e->raise0.p;
+    E.raise[1] = (u32*)e->raise1.p;
+    E.lower[0] = (u32*)e->lower0.p;
+    E.lower[1] = (u32*)e->lower1.p;
+    E.cnt = (u32*)e->cnt.p;
+    E.fcap = (u32)nv;
+    E.gamma = e->P.gamma;
+    E.d_max = e->P.d_max;
+    const float v = m->P.voxel_size;
+    E.step[0] = 0.0f;
+    E.step[1] = v;
+    E.step[2] = (float)((double)v * std::sqrt(2.0));
+    E.step[3] = (float)((double)v * std::sqrt(3.0));
+    const MapDesc d = make_desc(m, 0, 0, 0);
+    // neighbour blocks of every block (new blocks change their neighbours' tables too)
+    hipLaunchKernelGGL(k_esdf_slot_keys, dim3(grid_for(m->hcap)), dim3(256), 0, st, m->hkeys, m->hslots, m->hcap,
+                       (u64*)e->slot_key.p);
+    hipLaunchKernelGGL(k_esdf_neighbours, dim3(grid_for((size_t)nb * 27)), dim3(256), 0, st, d,
+                       (const u64*)e->slot_key.p, nb, (int*)e->nbr.p);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, E.cnt, 0u, (size_t)kEsdfCounters);
+    hipLaunchKernelGGL(k_esdf_dirty_list, dim3(grid_for(nb)), dim3(256), 0, st, e->dirty, nb, E.list,
+                       E.cnt + kEsdfDirtyCount);
+    const unsigned G = 2048;   // persistent grids: threads stride over the frontier
+    const u32 tag_raise0 = ++e->tag, tag_lower0 = ++e->tag;
+    if (m->P.storage == VBX_F32)
+        hipLaunchKernelGGL(k_esdf_seed<0>, dim3(G), dim3(256), 0, st, d, E, tag_raise0, tag_lower0);
+    else if (m->P.storage == VBX_F16)
+        hipLaunchKernelGGL(k_esdf_seed<1>, dim3(G), dim3(256), 0, st, d, E, tag_raise0, tag_lower0);
+    else
+        hipLaunchKernelGGL(k_esdf_seed<2>, dim3(G), dim3(256), 0, st, d, E, tag_raise0, tag_lower0);
+    VBX_TRY(hipGetLastError());
+    // levels in chunks, the host reading the frontier sizes between chunks; a level whose
+    // frontier is empty returns at once
+    constexpr u32 kChunk = 8;
+    u32 host_cnt[kEsdfCounters];
+    VBX_TRY(hipMemcpyAsync(host_cnt, E.cnt, sizeof host_cnt, hipMemcpyDeviceToHost, st));
+    VBX_TRY(hipStreamSynchronize(st));
+    u32 r = 0;
+    while (host_cnt[kEsdfRaiseCount + r % 3] != 0) {
+        for (u32 k = 0; k < kChunk; ++k, ++r)
+            hipLaunchKernelGGL(k_esdf_raise, dim3(G), dim3(256), 0, st, E, r, ++e->tag, tag_lower0);
+        VBX_TRY(hipMemcpyAsync(host_cnt, E.cnt, sizeof host_cnt, hipMemcpyDeviceToHost, st));
+        VBX_TRY(hipStreamSynchronize(st));
+    }
+    e->stats.dirty_blocks = host_cnt[kEsdfDirtyCount];
+    e->stats.raise_rounds = r;
+    r = 0;
+    while (host_cnt[kEsdfLowerCount + r % 3] != 0) {
+        for (u32 k = 0; k < kChunk; ++k, ++r)
+            hipLaunchKernelGGL(k_esdf_lower, dim3(G), dim3(256), 0, st, E, r, ++e->tag);
+        VBX_TRY(hipMemcpyAsync(host_cnt, E.cnt, sizeof host_cnt, hipMemcpyDeviceToHost, st));
+        VBX_TRY(hipStreamSynchronize(st));
+    }
+    e->stats.lower_rounds = r;
+    VBX_TRY(hipGetLastError());
+    if (out) *out = e->stats;
+    return VBX_OK;
+}
+
+int vbx_esdf_export(vbx_map* m, int32_t* coords, float* d, uint8_t* info, size_t cap, size_t* n_out) {
+    if (!m || !n_out || !m->esdf) return VBX_ERR_INVALID_ARG;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    const size_t nb = s.block_count;
+    if ((coords || d || info) && cap < nb) return VBX_ERR_BUFFER_TOO_SMALL;
+    if (!coords && !d && !info) {
+        *n_out = nb;
+        return VBX_OK;
+    }
+    std::vector<u64> keys(m->hcap);
+    std::vector<int> slots(m->hcap);
+    VBX_TRY(hipMemcpy(keys.data(), m->hkeys, sizeof(u64) * m->hcap, hipMemcpyDeviceToHost));
+    VBX_TRY(hipMemcpy(slots.data(), m->hslots, sizeof(int) * m->hcap, hipMemcpyDeviceToHost));
+    std::vector<std::pair<u64, int>> blocks;
+    for (size_t i = 0; i < keys.size(); ++i)
+        if (keys[i] != kEmpty) blocks.push_back({keys[i], slots[i]});
+    if (blocks.size() != nb) return VBX_ERR_DEVICE;
+    std::sort(blocks.begin(), blocks.end());
+    std::vector<u64> words;
+    const size_t have = std::min(m->esdf->vox_blocks, nb);
+    words.assign(nb * 4096, 0ull);
+    if (have) VBX_TRY(hipMemcpy(words.data(), m->esdf->vox, have * 4096 * sizeof(u64), hipMemcpyDeviceToHost));
+    for (size_t b = 0; b < nb; ++b) {
+        if (coords) {
+            int bx, by, bz;
+            unpack_block(blocks[b].first, bx, by, bz);
+            coords[3 * b] = bx;
+            coords[3 * b + 1] = by;
+            coords[3 * b + 2] = bz;
+        }
+        const size_t slot = (size_t)blocks[b].second;
+        for (int l = 0; l < 4096; ++l) {
+            const u64 w = words[slot * 4096 + l];
+            const u32 low = (u32)w;
+            float mag;
+            const u32 hi = (u32)(w >> 32);
+            std::memcpy(&mag, &hi, 4);
+            const bool obs = (low & kEsdfObserved) != 0;
+            if (d) d[b * 4096 + l] = obs ? ((low & kEsdfNeg) ? -mag : mag) : 0.0f;
+            if (info)
+                info[b * 4096 + l] = obs ? (uint8_t)(1u | ((low & kEsdfFixed) ? 2u : 0u) |
+                                                     ((low & kEsdfParentMask) << 2) | ((low & kEsdfNeg) ? 128u : 0u))
+                                         : (uint8_t)0;
+        }
+    }
+    *n_out = nb;
     return VBX_OK;
 }
 

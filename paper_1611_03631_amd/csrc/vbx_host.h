@@ -70,4 +70,32 @@ __global__ void k_debug_traverse(const float* A, const float* B, int n, int* out
 
 constexpr int kScanChunkHost = 4096;
 
+// ESDF layer (Sec. V-A): one 64-bit word per voxel, |d| in the high half, flags and parent below.
+constexpr u32 kEsdfNeg = 1u << 31, kEsdfObserved = 1u << 30, kEsdfFixed = 1u << 29;
+constexpr u32 kEsdfParentMask = 31u, kEsdfNoParent = 13u;
+enum { kEsdfRaiseCount = 0, kEsdfLowerCount = 3, kEsdfDirtyCount = 6, kEsdfCounters = 8 };
+
+// Device view of a map's ESDF layer for one update.
+struct EsdfDev {
+    u64* vox;        // [blocks * 4096] voxel words
+    u32* rstamp;     // [blocks * 4096] last raise-frontier tag per voxel
+    u32* lstamp;     // [blocks * 4096] last lower-frontier tag per voxel
+    u32* list;       // [blocks] dirty blocks of this update
+    int* nbr;        // [blocks * 27] neighbour block slots (-1: none)
+    u32* raise[2];   // raise frontiers (voxel ids slot << 12 | local)
+    u32* lower[2];   // lower frontiers
+    u32* cnt;        // [kEsdfCounters]
+    u32 fcap;        // frontier capacity (voxels)
+    float gamma, d_max;
+    float step[4];   // step length by squared offset length: 0, v, sqrt(2) v, sqrt(3) v
+};
+
+__global__ void k_esdf_slot_keys(const u64* hkeys, const int* hslots, u32 hcap, u64* slot_key);
+__global__ void k_esdf_neighbours(const MapDesc M, const u64* slot_key, u32 nblocks, int* nbr);
+__global__ void k_esdf_dirty_list(u32* dirty, u32 nblocks, u32* list, u32* count);
+template <int STORAGE>
+__global__ void k_esdf_seed(const MapDesc M, EsdfDev E, u32 tag_raise, u32 tag_lower);
+__global__ void k_esdf_raise(EsdfDev E, u32 r, u32 tag_next, u32 tag_lower);
+__global__ void k_esdf_lower(EsdfDev E, u32 r, u32 tag_next);
+
 }  // namespace vbx

@@ -5,6 +5,7 @@
 // mean are binary32/binary64 operations in a fixed order, so that the voxels a
 // ray visits are reproducible bit-for-bit.
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -45,8 +46,9 @@ struct MapDesc {
     int* hslots;                    //             pool slot per key
     u32 hmask;                      // hash capacity - 1
     u32 capacity;                   // pool capacity in blocks
-    void* pool;                     // [capacity][4096] float2 (F32: D metres, W) or u32 half pairs (F16: D/delta, W)
+    void* pool;                     // [capacity][4096] float2 (F32: D metres, W) or u32 16-bit pairs (D/delta, W)
     struct MapState* st;
+    u32* dirty;                     // [capacity] blocks changed since the ESDF last looked (null: no ESDF)
 };
 
 // Device-resident counters of a map.
@@ -160,6 +162,34 @@ __host__ __device__ inline unsigned short s16_encode(float dn) {
     return (unsigned short)(short)(int)__builtin_rintf(x);
 }
 __host__ __device__ inline float s16_decode(unsigned short c) { return (float)(short)c / 32767.0f; }
+
+// One voxel of a map's pool: D (metres for binary32 storage, D / delta for 16-bit storage)
+// and W.
+template <int STORAGE>
+__device__ inline void load_voxel(const void* pool, size_t idx, float& D, float& W) {
+    if (STORAGE == 0) {
+        const float2 dw = ((const float2*)pool)[idx];
+        D = dw.x; W = dw.y;
+    } else {
+        // 16-bit pairs: D / delta in the low half (binary16, or the fixed-point code), W
+        // (binary16) in the high half
+        const u32 raw = ((const u32*)pool)[idx];
+        D = STORAGE == 1 ? __half2float(__ushort_as_half((unsigned short)(raw & 0xFFFF)))
+                         : s16_decode((unsigned short)(raw & 0xFFFF));
+        W = __half2float(__ushort_as_half((unsigned short)(raw >> 16)));
+    }
+}
+// Pool slot of block key bk in the map's hash (linear probing from mix64), -1 if absent.
+__device__ inline int find_block(const MapDesc& M, u64 bk) {
+    u32 h = (u32)mix64(bk) & M.hmask;
+    for (u32 probe = 0; probe <= M.hmask; ++probe) {
+        const u64 k = M.hkeys[h];
+        if (k == bk) return M.hslots[h];
+        if (k == kEmpty) return -1;
+        h = (h + 1) & M.hmask;
+    }
+    return -1;
+}
 
 // ---------------------------------------------------------------------------
 // Point validity and pose transform (binary32, fixed order)

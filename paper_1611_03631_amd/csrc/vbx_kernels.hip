@@ -1313,20 +1313,6 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ jobs,
 // update: one workgroup per touched block
 // ---------------------------------------------------------------------------
 template <int STORAGE>
-__device__ inline void load_voxel(const void* pool, size_t idx, float& D, float& W) {
-    if (STORAGE == 0) {
-        const float2 dw = ((const float2*)pool)[idx];
-        D = dw.x; W = dw.y;
-    } else {
-        // 16-bit pairs: D / delta in the low half (binary16, or the fixed-point code), W
-        // (binary16) in the high half
-        const u32 raw = ((const u32*)pool)[idx];
-        D = STORAGE == 1 ? __half2float(__ushort_as_half((unsigned short)(raw & 0xFFFF)))
-                         : s16_decode((unsigned short)(raw & 0xFFFF));
-        W = __half2float(__ushort_as_half((unsigned short)(raw >> 16)));
-    }
-}
-template <int STORAGE>
 __device__ inline void store_voxel(void* pool, size_t idx, float D, float W) {
     if (STORAGE == 0) {
         ((float2*)pool)[idx] = make_float2(D, W);
@@ -1710,6 +1696,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
         }
 #pragma unroll
         for (int j = 0; j < VPT; ++j) store_voxel<STORAGE>(pool, vbase + block_local(threadIdx.x + NT * j), D[j], W[j]);
+        if (threadIdx.x == 0 && M.dirty) M.dirty[slot] = 1u;   // the ESDF layer looks at this block again
         {
             // summed over the wave first: one lane adds (an atomic on one address with a
             // different value per lane is otherwise carried out lane by lane)
@@ -1960,18 +1947,6 @@ __global__ __launch_bounds__(256) void k_finish_call(const Job* __restrict__ job
 // trilinear blend of the eight corner distances, along x, then y, then z (binary32).  It is
 // known only where all eight voxels are allocated and observed (W > 0); elsewhere the output is
 // NaN.  One thread per query; corners in the block of the previous corner reuse its lookup.
-
-// Pool slot of block key bk in the map's hash (linear probing from mix64), -1 if absent.
-__device__ inline int find_block(const MapDesc& M, u64 bk) {
-    u32 h = (u32)mix64(bk) & M.hmask;
-    for (u32 probe = 0; probe <= M.hmask; ++probe) {
-        const u64 k = M.hkeys[h];
-        if (k == bk) return M.hslots[h];
-        if (k == kEmpty) return -1;
-        h = (h + 1) & M.hmask;
-    }
-    return -1;
-}
 
 template <int STORAGE>
 __global__ __launch_bounds__(256) void k_interpolate(const MapDesc M, const float* __restrict__ q, u32 n,

@@ -156,7 +156,8 @@ def _random_field(rng, shape, p_fixed=0.06):
 def pin_incremental_equals_batch(lib_path=None, seed=5):
     """Algorithm 1 applied call by call reaches the field a single batch build of the final TSDF
     reaches: voxels arrive in two calls (new free voxels next to fixed ones seen before), then
-    fixed voxels move (up, down, across zero) or leave the band, and free voxels enter it."""
+    fixed voxels move (up, down, across zero) or leave the band, free voxels enter it, and free
+    voxels change side."""
     rng = np.random.default_rng(seed)
     g, dT = _random_field(rng, (12, 12, 12))
     first = rng.random(len(g)) < 0.5
@@ -168,6 +169,8 @@ def pin_incremental_equals_batch(lib_path=None, seed=5):
     dT2[leave] = np.where(g[leave, 2] < 4, -2.0 * V, 2.0 * V)
     enter = ~fixed & (rng.random(len(g)) < 0.03)
     dT2[enter] = rng.uniform(-0.9, 0.9, int(enter.sum())) * GAMMA
+    flip = ~fixed & ~enter & (rng.random(len(g)) < 0.03)       # change side outside the band
+    dT2[flip] = -dT[flip]
     ones = np.ones(len(g))
     for queue in ("fifo", "priority"):
         inc = esdf.OracleESDF(V, GAMMA, DMAX, queue, lib_path=lib_path)
@@ -178,7 +181,7 @@ def pin_incremental_equals_batch(lib_path=None, seed=5):
         a, b = inc.export(), bat.export()
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[2] & 3, b[2] & 3)
         assert np.abs(a[1] - b[1]).max() <= TOL, f"{queue}: two calls differ from one"
-        changed = move | leave | enter
+        changed = move | leave | enter | flip
         inc.update(g[changed], dT2[changed], ones[changed])
         bat2 = esdf.OracleESDF(V, GAMMA, DMAX, queue, lib_path=lib_path)
         bat2.update(g, dT2, ones)

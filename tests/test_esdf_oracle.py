@@ -38,6 +38,8 @@ MUTATIONS = {
         "                x->parent = 13;\n                insert_lower(E, k);"),
     "left_band_not_raised": ("            x->parent = 13;\n            fifo_push(&E->raise, k);\n        } else if",
                              "            x->parent = 13;\n        } else if"),
+    "side_frozen": ("} else if (x->fixed || (x->observed && (dt < 0.0) != (x->neg != 0))) {",
+                    "} else if (x->fixed) {"),
 }
 
 
