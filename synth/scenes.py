@@ -395,3 +395,68 @@ def config4_map(m: int, n_ticks: int = 100, seed: int = SEED_BASE + 3,
                   merge="grouped", storage=storage)
     return Workload(f"c4_map{m}_{w}x{h}", params, poses, _cached(frame), w, h,
                     "one map of the 32-map batched mix")
+
+
+# --------------------------------------------------------------------------
+# The simulated ESDF benchmark: a 10 x 10 x 10 m space with three planes (the ground and two
+# walls), a cube and a sphere, seen by a noiseless 320x240 depth sensor (5 m range) from random
+# six-degree-of-freedom poses in free space at least 1 m from every obstacle.
+# --------------------------------------------------------------------------
+def _esdf_scene(rng):
+    cube = (np.array([2.0, 5.5, 0.0]) + rng.uniform(-0.5, 0.5, 3) * [1, 1, 0],)
+    cube = (cube[0], cube[0] + np.array([2.0, 2.0, 2.0]))
+    sphere = (np.array([6.5, 3.5, 2.5]) + rng.uniform(-0.5, 0.5, 3), 1.25)
+    return cube, sphere
+
+
+def esdf_scene_distance(p, cube, sphere) -> np.ndarray:
+    """Signed distance (metres) from points p [n,3] to the scene's solids: the ground (z < 0), the
+    walls x < 0 and y > 10, the cube and the sphere; positive in free space."""
+    p = np.asarray(p, np.float64)
+    d = p[:, 2].copy()
+    d = np.minimum(d, p[:, 0])
+    d = np.minimum(d, 10.0 - p[:, 1])
+    lo, hi = cube
+    q = np.maximum(lo - p, p - hi)
+    outside = np.sqrt((np.maximum(q, 0.0) ** 2).sum(axis=1))
+    inside = np.minimum(q.max(axis=1), 0.0)
+    d = np.minimum(d, outside + inside)
+    c, r = sphere
+    d = np.minimum(d, np.sqrt(((p - c) ** 2).sum(axis=1)) - r)
+    return d
+
+
+def _random_rotation(rng) -> np.ndarray:
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def esdf_benchmark(n_views: int = 50, width: int = 320, height: int = 240,
+                   seed: int = SEED_BASE + 5):
+    """Returns (poses [n,3,4] float32, frame_fn, distance_fn): noiseless depth frames of the
+    simulated ESDF scene and its ground-truth signed distance at any points."""
+    rng = np.random.default_rng(seed)
+    cube, sphere = _esdf_scene(rng)
+    poses = []
+    while len(poses) < n_views:
+        t = rng.uniform(1.0, 9.0, 3)
+        if esdf_scene_distance(t[None, :], cube, sphere)[0] < 1.0:
+            continue
+        poses.append(make_pose(_random_rotation(rng), t))
+    poses = np.stack(poses)
+    dirs = pinhole_dirs(width, height)
+
+    def hit(o, d):
+        t = _hit_room_inside(o, d, np.array([0.0, -1e6, 0.0]), np.array([1e6, 10.0, 1e6]))
+        t = np.minimum(t, _hit_boxes(o, d, [cube]))
+        return np.minimum(t, _hit_spheres(o, d, [sphere]))
+
+    def frame(k):
+        frng = np.random.default_rng([seed, 7919, k])
+        return _depth_frame(poses[k], dirs, hit, lambda z: 0.0 * z, frng, 0.0)
+
+    return poses, frame, lambda p: esdf_scene_distance(p, cube, sphere)
