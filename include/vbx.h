@@ -70,7 +70,12 @@ typedef enum { VBX_F32 = 0, VBX_F16 = 1, VBX_S16 = 2 } vbx_storage;
 typedef enum { VBX_DIST_EQ1 = 0, VBX_DIST_ALONG_RAY = 1 } vbx_dist;
 
 enum {
-    VBX_FLAG_KEEP_TOUCHES = 1u   /* record the touched voxels and ray counts of the last call */
+    VBX_FLAG_KEEP_TOUCHES = 1u,  /* record the touched voxels and ray counts of the last call */
+    /* Raycasting updates every voxel from the sensor origin to trunc behind the point (the
+     * raycasting of Sec. IV-B, which carves the free space in front of the surface), instead of
+     * the truncation band [r - trunc, r + trunc] alone.  Needs (max_range + trunc) / voxel_size
+     * <= 1024 (VBX_ERR_LIMIT otherwise). */
+    VBX_FLAG_FULL_RAY = 2u
 };
 
 /* Limits */

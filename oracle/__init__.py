@@ -39,7 +39,7 @@ class _Params(ctypes.Structure):
                 ("w_max", ctypes.c_float), ("max_range", ctypes.c_float),
                 ("z_min", ctypes.c_float), ("weighting", ctypes.c_int),
                 ("merge", ctypes.c_int), ("fp16", ctypes.c_int), ("dist", ctypes.c_int),
-                ("world64", ctypes.c_int)]
+                ("world64", ctypes.c_int), ("full_ray", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -119,15 +119,16 @@ class OracleMap:
     def __init__(self, voxel_size: float, trunc: float, weighting: str = "const",
                  merge: str = "simple", w_max: float = 1e4, max_range: float = 5.0,
                  z_min: float = 0.1, storage: str = "f32", dist: str = "eq1",
-                 world64: bool = False, lib_path: Optional[str] = None):
+                 world64: bool = False, full_ray: bool = False, lib_path: Optional[str] = None):
         """world64: measure distances from the binary64 transform of each sensor point (and a
         group's exact binary64 mean) instead of the binary32 ray end point."""
         self.lib = load(lib_path)
         self.params = dict(voxel_size=voxel_size, trunc=trunc, weighting=weighting,
                            merge=merge, w_max=w_max, max_range=max_range, z_min=z_min,
-                           storage=storage, dist=dist, world64=world64)
+                           storage=storage, dist=dist, world64=world64, full_ray=full_ray)
         p = _Params(voxel_size, trunc, w_max, max_range, z_min, WEIGHTING[weighting],
-                    MERGE[merge], STORAGE[storage], DIST[dist], 1 if world64 else 0)
+                    MERGE[merge], STORAGE[storage], DIST[dist], 1 if world64 else 0,
+                    1 if full_ray else 0)
         self._h = self.lib.orc_create(ctypes.byref(p))
 
     def close(self):

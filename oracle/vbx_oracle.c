@@ -35,7 +35,9 @@
  *    (p - x).(p - s), sign(0) = 0.  A flag selects the projective distance
  *    along the ray instead.
  *  - Raycasting updates the truncation band only: the segment of the ray from
- *    max(r - delta, 0) to r + delta, r = |p - s|.
+ *    max(r - delta, 0) to r + delta, r = |p - s|.  With full_ray set it updates the
+ *    whole ray, from the sensor origin to delta behind the point (the raycasting of
+ *    Sec. IV-B: "from the center to truncation distance delta behind the point").
  *  - Ray traversal is the Amanatides-Woo grid walk with a fixed step count;
  *    when two axes cross a voxel face at the same parameter the lowest axis
  *    (x, then y, then z) steps first.
@@ -75,6 +77,7 @@ typedef struct {
                           and W to binary16 after every frame (16-bit fixed-point distance) */
     int dist;          /* 0: Eq. (1); 1: projective distance along the ray */
     int world64;       /* 1: distances from the binary64 world point (see the header) */
+    int full_ray;      /* 1: a ray updates every voxel from the sensor to delta behind its point */
 } orc_params;
 
 typedef struct {
@@ -366,7 +369,7 @@ static void cast_ray(orc_map* m, const orc_ray* ray, const float s32[3], const d
     for (int k = 0; k < 3; ++k) e[k] = ray->p32[k] - s32[k];
     float r = sqrtf((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
     if (r == 0.0f) { st->out_of_bounds++; return; }
-    float t0 = r - delta;
+    float t0 = P->full_ray ? 0.0f : r - delta;
     if (t0 < 0.0f) t0 = 0.0f;
     float t1 = r + delta;
     for (int k = 0; k < 3; ++k) {
@@ -530,7 +533,8 @@ int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], 
 
     /* 3. raycast the truncation band of every ray */
     m->n_touch = 0;
-    int bufcap = 3 * ((int)ceilf(2.0f * P->trunc / v) + 4) + 8;
+    const float walk = P->full_ray ? P->max_range + P->trunc : 2.0f * P->trunc;
+    int bufcap = 3 * ((int)ceilf(walk / v) + 4) + 8;
     int32_t* buf = (int32_t*)malloc((size_t)bufcap * 3 * sizeof(int32_t));
     for (size_t i = 0; i < nr; ++i) cast_ray(m, &rays[i], s32, s64, &st, buf, bufcap);
 

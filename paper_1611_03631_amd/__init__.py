@@ -27,6 +27,7 @@ MERGE_NONE, MERGE_GROUPED = 0, 1
 F32, F16, S16 = 0, 1, 2
 DIST_EQ1, DIST_ALONG_RAY = 0, 1
 FLAG_KEEP_TOUCHES = 1
+FLAG_FULL_RAY = 2
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "block pool full",
           -4: "buffer too small", -5: "device error", -6: "limit exceeded"}
@@ -230,7 +231,7 @@ _DIST = {"eq1": DIST_EQ1, "ray": DIST_ALONG_RAY}
 def map_params(voxel_size: float, trunc: float, weighting: str = "const", merge: str = "simple",
                storage: str = "f32", w_max: float = 1e4, max_range: float = 5.0, z_min: float = 0.1,
                dist: str = "eq1", block_capacity: int = 65536, keep_touches: bool = False,
-               stream_handle: int = 0) -> MapParams:
+               stream_handle: int = 0, full_ray: bool = False) -> MapParams:
     p = MapParams()
     lib().vbx_default_params(ctypes.byref(p))
     p.voxel_size, p.trunc, p.w_max = voxel_size, trunc, w_max
@@ -238,7 +239,7 @@ def map_params(voxel_size: float, trunc: float, weighting: str = "const", merge:
     p.weighting, p.merge = _WEIGHTING[weighting], _MERGE[merge]
     p.storage, p.dist = _STORAGE[storage], _DIST[dist]
     p.block_capacity = block_capacity
-    p.flags = FLAG_KEEP_TOUCHES if keep_touches else 0
+    p.flags = (FLAG_KEEP_TOUCHES if keep_touches else 0) | (FLAG_FULL_RAY if full_ray else 0)
     p.stream = stream_handle
     return p
 
@@ -250,7 +251,7 @@ class Map:
                  merge: str = "simple", storage: str = "f32", w_max: float = 1e4,
                  max_range: float = 5.0, z_min: float = 0.1, dist: str = "eq1",
                  block_capacity: int = 65536, keep_touches: bool = False, stream=None,
-                 allocator=None):
+                 allocator=None, full_ray: bool = False):
         """allocator: optional (alloc, free) pair of callables, alloc(nbytes) -> device address
         (0 when it cannot) and free(address), used for the map's hash table, block pool and
         device state instead of hipMalloc / hipFree."""
@@ -258,7 +259,7 @@ class Map:
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
         p = map_params(voxel_size, trunc, weighting, merge, storage, w_max, max_range, z_min, dist,
-                       block_capacity, keep_touches, s.cuda_stream)
+                       block_capacity, keep_touches, s.cuda_stream, full_ray)
         self._hooks = None
         if allocator is not None:
             a_py, f_py = allocator
@@ -272,7 +273,7 @@ class Map:
         self._owned = True
         self.params = dict(voxel_size=voxel_size, trunc=trunc, weighting=weighting, merge=merge,
                            storage=storage, w_max=w_max, max_range=max_range, z_min=z_min,
-                           dist=dist, block_capacity=block_capacity)
+                           dist=dist, block_capacity=block_capacity, full_ray=full_ray)
 
     @classmethod
     def _borrowed(cls, handle, params: dict, owner):

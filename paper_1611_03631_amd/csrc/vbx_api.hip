@@ -186,13 +186,20 @@ int sum_bits(const vbx_map_params& P) {
     return 38 - c;
 }
 
+// Length of a ray's walk in voxels: the truncation band, or the whole ray up to trunc behind a
+// point at the maximum range.
+double walk_voxels(const vbx_map_params& P) {
+    const double len = (P.flags & VBX_FLAG_FULL_RAY) ? (double)P.max_range + (double)P.trunc : 2.0 * (double)P.trunc;
+    return len / (double)P.voxel_size;
+}
+
 int max_blocks_per_ray(const vbx_map_params& P) {
-    const double len = 2.0 * (double)P.trunc / (double)P.voxel_size + 2.0;   // band, voxel units
+    const double len = walk_voxels(P) + 2.0;
     return 1 + 3 * ((int)std::floor(len / 16.0) + 1);
 }
 
 int max_voxels_per_ray(const vbx_map_params& P) {
-    return 3 * ((int)std::ceil(2.0 * (double)P.trunc / (double)P.voxel_size) + 2) + 1;
+    return 3 * ((int)std::ceil(walk_voxels(P)) + 2) + 1;
 }
 
 int validate_params(const vbx_map_params& P) {
@@ -209,6 +216,7 @@ int validate_params(const vbx_map_params& P) {
     if ((P.alloc == nullptr) != (P.free == nullptr)) return VBX_ERR_INVALID_ARG;
     if (P.block_capacity == 0 || P.block_capacity > (1u << 29)) return VBX_ERR_INVALID_ARG;
     if (2.0 * P.trunc / P.voxel_size > 28.0) return VBX_ERR_LIMIT;   // band of <= 28 voxels
+    if ((P.flags & VBX_FLAG_FULL_RAY) && walk_voxels(P) > 1024.0) return VBX_ERR_LIMIT;
     return VBX_OK;
 }
 
@@ -242,6 +250,8 @@ MapDesc make_desc(const vbx_map* m, int map_id, int job0, int njobs) {
     d.pool = m->pool;
     d.st = m->st;
     d.dirty = m->esdf ? m->esdf->dirty : nullptr;
+    d.full_ray = (P.flags & VBX_FLAG_FULL_RAY) ? 1 : 0;
+    d.max_steps = max_voxels_per_ray(P) + 1;
     return d;
 }
 

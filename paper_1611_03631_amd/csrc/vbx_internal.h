@@ -31,7 +31,7 @@ constexpr int kTileSimple = 1024;      // points per workgroup, per-point raycas
 constexpr int kTileGroupedW = 32;      // 2-D tile of an organised cloud (grouped)
 constexpr int kTileGroupedH = 16;
 constexpr int kTileGrouped = kTileGroupedW * kTileGroupedH;  // 512 points
-constexpr int kMaxStepsPerRay = 96;    // guard only; real bands need 3*(2*delta/v + 2) + 1
+constexpr int kMaxStepsPerRay = 96;    // guard of the traversal check only (walk_setup_vox)
 
 // Per-map parameters and device pointers for one call (copied to the device per call).
 struct MapDesc {
@@ -49,6 +49,8 @@ struct MapDesc {
     void* pool;                     // [capacity][4096] float2 (F32: D metres, W) or u32 16-bit pairs (D/delta, W)
     struct MapState* st;
     u32* dirty;                     // [capacity] blocks changed since the ESDF last looked (null: no ESDF)
+    int full_ray;                   // 1: rays start at the sensor, else at max(r - delta, 0)
+    int max_steps;                  // guard of a ray walk: at least the longest walk's steps
 };
 
 // Device-resident counters of a map.
@@ -234,7 +236,7 @@ __device__ inline bool walk_setup(const MapDesc& M, const float p[3], const floa
     for (int k = 0; k < 3; ++k) e[k] = p[k] - s[k];
     r = __builtin_sqrtf((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
     if (r == 0.0f) return false;
-    float t0 = r - M.delta;
+    float t0 = M.full_ray ? 0.0f : r - M.delta;
     if (t0 < 0.0f) t0 = 0.0f;
     float t1 = r + M.delta;
     float A[3], B[3];

@@ -981,13 +981,21 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
             // phase 1: the blocks the band enters, entered in the workgroup's LDS set
             if (ok) {
                 u64 cur = kEmpty;
-                for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
+                const bool full = Mp->full_ray != 0;
+                for (int guard = 0; guard < Mp->max_steps; ++guard) {
                     const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
                     if (bk != cur) {
                         cur = bk;
-                        const u32 h = lds_set_insert(s_key, mapbits | bk);
-                        if (nc < 4) held0 |= (u64)h << (16 * nc);
-                        else if (nc < kCrossHeld) held1 |= (u64)h << (16 * (nc - 4));
+                        if (full) {
+                            // a whole ray crosses up to MB blocks, more than the LDS set and
+                            // registers hold: each crossing enters the call's block set at once
+                            const u32 h = tset_insert<true>(tkeys, tmask, mapbits | bk, tlist, tlist_cap, cs);
+                            if (nc < MB) cross[(size_t)i * MB + nc] = h;
+                        } else {
+                            const u32 h = lds_set_insert(s_key, mapbits | bk);
+                            if (nc < 4) held0 |= (u64)h << (16 * nc);
+                            else if (nc < kCrossHeld) held1 |= (u64)h << (16 * (nc - 4));
+                        }
                         nc++;
                     }
                     if (w.left == 0) break;
@@ -1004,12 +1012,14 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
         __syncthreads();
         // phase 3: crossing c of ray slot i goes to cross[i * MB + c]
         if (i < nrays) {
-            if (nc > MB || nc > kCrossHeld) {   // cannot happen: MB bounds the band
+            const bool full = live && Mp->full_ray != 0;
+            if (nc > MB || (!full && nc > kCrossHeld)) {   // cannot happen: MB bounds the walk
                 cs->error = -4;
                 nc = 0;
             }
-            for (u32 c = 0; c < nc; ++c)
-                cross[(size_t)i * MB + c] = s_h[(u32)((c < 4 ? held0 : held1) >> (16 * (c & 3))) & 0xFFFFu];
+            if (!full)
+                for (u32 c = 0; c < nc; ++c)
+                    cross[(size_t)i * MB + c] = s_h[(u32)((c < 4 ? held0 : held1) >> (16 * (c & 3))) & 0xFFFFu];
             ncross[i] = (unsigned char)nc;
         }
         // out-of-bounds rays per frame (rare); rays were counted when created
@@ -1528,7 +1538,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                             if (miss) continue;
                         }
                         bool inside = false;
-                        for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
+                        for (int guard = 0; guard < M.max_steps; ++guard) {
                             const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
                             if ((u32)lx < (u32)RX && (u32)ly < (u32)RY && (u32)lz < (u32)RZ) {
                                 inside = true;
@@ -1641,7 +1651,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                             if (miss) continue;
                         }
                         bool inside = false;
-                        for (int guard = 0; guard < kMaxStepsPerRay; ++guard) {
+                        for (int guard = 0; guard < M.max_steps; ++guard) {
                             const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
                             if ((u32)lx < (u32)RX && (u32)ly < (u32)RY && (u32)lz < (u32)RZ) {
                                 inside = true;

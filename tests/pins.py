@@ -155,13 +155,14 @@ def _axis_pose(axis, sign):
     return T
 
 
-def head_on_expectation(Z, axis, sign, weighting, frames, pose):
+def head_on_expectation(Z, axis, sign, weighting, frames, pose, full_ray=False):
     """Touched voxels, D and W after `frames` identical frames of one ray along the sensor
-    z axis hitting a plane at depth Z (Eqs. 1-5 evaluated on the axis)."""
+    z axis hitting a plane at depth Z (Eqs. 1-5 evaluated on the axis).  full_ray: the ray
+    updates every voxel from the sensor on, not only the truncation band."""
     s = pose[:, 3].astype(np.float64)
     p = s.copy()
     p[axis] += sign * Z
-    lo_t, hi_t = max(Z - DELTA, 0.0), Z + DELTA
+    lo_t, hi_t = (0.0 if full_ray else max(Z - DELTA, 0.0)), Z + DELTA
     a, b = s[axis] + sign * lo_t, s[axis] + sign * hi_t
     ga, gb = math.floor(a / V), math.floor(b / V)
     cols = range(min(ga, gb), max(ga, gb) + 1)
@@ -220,6 +221,37 @@ def pin_head_on_plane(lib_path=None):
             assert abs(got[g][1] - W) <= 1e-12 * max(1.0, W), f"W at {g}: {got[g][1]} vs {W}"
         blocks = {tuple(int(x) // 16 if int(x) >= 0 else -((-int(x) + 15) // 16) for x in g) for g in exp}
         assert {tuple(map(int, c)) for c in coords} == blocks, "allocated blocks"
+        m.close()
+
+
+def pin_full_ray_head_on(lib_path=None):
+    """Raycasting over the whole ray (Sec. IV-B: every voxel from the sensor to delta behind the
+    point): on the head-on axis the touched column runs from the sensor's voxel to delta behind
+    the plane; the free space in front of the band holds D = +delta (the clamped distance) and
+    the full weight of every frame."""
+    for axis, sign, weighting, Z, frames in [(0, 1, "const", 1.3125, 2), (2, -1, "quad", 2.0625, 3),
+                                             (1, 1, "quad", 0.25, 1)]:
+        pose = _axis_pose(axis, sign)
+        m = oracle.OracleMap(V, DELTA, weighting=weighting, merge="simple", w_max=1e30,
+                             max_range=10.0, z_min=0.1, full_ray=True, lib_path=lib_path)
+        pt = np.array([[0.0, 0.0, Z]], np.float32)
+        for _ in range(frames):
+            st = m.integrate(pt, pose)
+        exp = head_on_expectation(Z, axis, sign, weighting, frames, pose, full_ray=True)
+        band = head_on_expectation(Z, axis, sign, weighting, frames, pose)
+        assert len(exp) > len(band) or Z <= DELTA
+        tc, tn = m.last_touches()
+        assert {tuple(map(int, c)) for c in tc} == set(exp), "touched column"
+        assert np.all(tn == 1) and st["touches"] == len(exp)
+        got, _ = _export_dict(m)
+        free = 0
+        for g, (dc, W) in exp.items():
+            if W == 0:
+                assert g not in got
+                continue
+            assert abs(got[g][0] - dc) <= 1e-12 and abs(got[g][1] - W) <= 1e-12 * max(1.0, W), g
+            free += dc == DELTA
+        assert free >= int((Z - DELTA) / V) - 1, "free space in front of the band"
         m.close()
 
 
@@ -709,7 +741,7 @@ def pin_permutation(lib_path=None, seed=9):
         a.close(); b.close()
 
 
-ALL_PINS = [pin_dda_dyadic, pin_dda_random, pin_head_on_plane, pin_dropoff_values,
+ALL_PINS = [pin_dda_dyadic, pin_dda_random, pin_head_on_plane, pin_full_ray_head_on, pin_dropoff_values,
             pin_along_ray_off_axis, pin_binary16_sequence, pin_s16_sequence, pin_ramp_diagnostic,
             pin_weight_sums, pin_group_mean, pin_merged_singletons, pin_identical_points,
             pin_running_average, pin_validity, pin_round_half, pin_permutation]

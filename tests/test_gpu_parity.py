@@ -258,3 +258,47 @@ def test_repeat_runs_bit_identical(vbx):
         assert g.sync() == 0
         outs.append(g.export())
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+# ---------------------------------------------------------------------------
+# raycasting over the whole ray (Sec. IV-B): every voxel from the sensor to delta behind
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("weighting,merge", [("const", "simple"), ("quad", "grouped")])
+def test_full_ray_room(vbx, weighting, merge):
+    """The whole ray: rays cross up to 22 blocks (voxel 0.05 m, range 5 m), the free space in
+    front of every surface is carved; touches bit-exact, the map within the parity bar."""
+    import synth
+    poses, frame = synth.room_sequence(320, 240, 3, seed=synth.SEED_BASE + 900)
+    params = dict(voxel_size=0.05, trunc=0.15, max_range=5.0, weighting=weighting, merge=merge,
+                  full_ray=True, block_capacity=16384)
+    frames = [(frame(k), poses[k], 320) for k in range(3)]
+    log(f"full ray 320x240 x3 {weighting} {merge}")
+    g, o = run_both(vbx, params, frames)      # frame by frame: the last touches are the last frame's
+    compare_touches(g.last_touches(), o.last_touches())
+    res = compare_export(g.export(), o.export(), params)
+    band = gpu_map(vbx, dict(params, full_ray=False))
+    band.integrate_frames([(dev(f[0]), f[1], f[2]) for f in frames])
+    assert band.sync() == 0
+    nb_band, nb_full = band.export()[0].shape[0], res["blocks"]
+    assert nb_full > nb_band, "the whole ray allocates the free space's blocks too"
+    log(f"  ok: {res}; blocks {nb_full} (band only: {nb_band})")
+
+
+def test_full_ray_lidar(vbx):
+    """LiDAR sweeps over the whole ray: walks of up to 303 voxels (range 60 m, voxel 0.2 m)."""
+    import synth
+    w = synth.config3(n_sweeps=2, n_az=512)
+    params = dict(w.params, full_ray=True, block_capacity=16384)
+    frames = [(w.frame(k), w.poses[k]) for k in range(2)]
+    log("full ray lidar 64x512 x2")
+    g, o = run_both(vbx, params, frames)
+    compare_touches(g.last_touches(), o.last_touches())
+    res = compare_export(g.export(), o.export(), params)
+    log(f"  ok: {res}")
+
+
+def test_full_ray_limit(vbx):
+    """A whole-ray walk longer than 1024 voxels is refused when the map is made."""
+    with pytest.raises(vbx.VbxError) as e:
+        gpu_map(vbx, dict(voxel_size=0.02, trunc=0.06, max_range=30.0, full_ray=True))
+    assert e.value.status == -6

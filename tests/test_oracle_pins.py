@@ -61,9 +61,13 @@ MUTATIONS = {
     "ramp_counts_behind_band": ("if (P->weighting == 1 && d > -d64 && d <= -eps) vx->ramp += ray->wgt;",
                                 "if (P->weighting == 1 && d <= -eps) vx->ramp += ray->wgt;"),
     "ramp_counts_dropped_weight": ("vx->ramp += ray->wgt;", "vx->ramp += w;"),
+    # the whole-ray update (Sec. IV-B)
+    "full_ray_ignored": ("float t0 = P->full_ray ? 0.0f : r - delta;", "float t0 = r - delta;"),
+    "full_ray_stops_at_point": ("float t1 = r + delta;\n    for (int k = 0; k < 3; ++k) {\n        float u = e[k] / r;",
+                                "float t1 = P->full_ray ? r : r + delta;\n    for (int k = 0; k < 3; ++k) {\n        float u = e[k] / r;"),
 }
 
-FAST_FIRST = [pins.pin_head_on_plane, pins.pin_dropoff_values, pins.pin_running_average,
+FAST_FIRST = [pins.pin_head_on_plane, pins.pin_full_ray_head_on, pins.pin_dropoff_values, pins.pin_running_average,
               pins.pin_along_ray_off_axis, pins.pin_binary16_sequence, pins.pin_s16_sequence,
               pins.pin_ramp_diagnostic,
               pins.pin_validity, pins.pin_identical_points, pins.pin_merged_singletons,
