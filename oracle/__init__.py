@@ -69,6 +69,10 @@ def load(path: Optional[str] = None):
                                   ctypes.c_void_p, P(_Stats)]
     lib.orc_num_blocks.restype = ctypes.c_size_t
     lib.orc_num_blocks.argtypes = [ctypes.c_void_p]
+    lib.orc_integrate_projective.restype = ctypes.c_int
+    lib.orc_integrate_projective.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                             ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                             P(_Stats)]
     lib.orc_export.restype = ctypes.c_size_t
     lib.orc_export.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_size_t]
     lib.orc_export_ramp.restype = ctypes.c_size_t
@@ -147,6 +151,20 @@ class OracleMap:
         ps = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
         st = _Stats()
         self.lib.orc_integrate(self._h, _ptr(pts), pts.shape[0], _ptr(ps), ctypes.byref(st))
+        return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
+
+    def integrate_projective(self, points: np.ndarray, pose: np.ndarray, width: int,
+                             intrinsics) -> dict:
+        """Projection mapping of one organised frame (Sec. IV-B): points [H*W, 3] in the sensor
+        frame, intrinsics (fx, fy, cx, cy) mapping camera points to pixel coordinates."""
+        pts = np.ascontiguousarray(points, dtype=np.float32).reshape(-1, 3)
+        ps = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
+        intr = np.ascontiguousarray(intrinsics, dtype=np.float32).reshape(4)
+        st = _Stats()
+        rc = self.lib.orc_integrate_projective(self._h, _ptr(pts), pts.shape[0], int(width), _ptr(ps),
+                                               _ptr(intr), ctypes.byref(st))
+        if rc != 0:
+            raise ValueError("projection mapping needs an organised frame (n a multiple of width)")
         return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
 
     def num_blocks(self) -> int:

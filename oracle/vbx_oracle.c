@@ -359,17 +359,23 @@ static double dropoff(double d, double eps, double delta) {
     return 0.0;
 }
 
-/* Casts one ray through the truncation band and accumulates its observations. */
-static void cast_ray(orc_map* m, const orc_ray* ray, const float s32[3], const double s64[3],
-                     orc_stats* st, int32_t* buf, int bufcap) {
-    const orc_params* P = &m->P;
-    const float v = P->voxel_size, delta = P->trunc, iv = 1.0f / v;
-    /* segment of the ray inside the band, binary32 */
-    float e[3], A[3], B[3];
-    for (int k = 0; k < 3; ++k) e[k] = ray->p32[k] - s32[k];
+/* G2: the world point of a sensor point (binary32, fixed order). */
+static void transform_point(const float pose[12], float x, float y, float z, float q[3]) {
+    for (int k = 0; k < 3; ++k)
+        q[k] = ((pose[4 * k] * x + pose[4 * k + 1] * y) + pose[4 * k + 2] * z) + pose[4 * k + 3];
+}
+
+/* G3-G4: the segment of the ray s -> p that a ray updates (the truncation band, or with
+   whole = 1 the ray from the sensor on), in voxel units A -> B; e = p - s and r = |e|.
+   Returns 0 when r = 0 or an end lies outside the voxel range. */
+static int ray_segment(const orc_params* P, int whole, const float p[3], const float s32[3], float e[3],
+                       float* r_out, float A[3], float B[3]) {
+    const float delta = P->trunc, iv = 1.0f / P->voxel_size;
+    for (int k = 0; k < 3; ++k) e[k] = p[k] - s32[k];
     float r = sqrtf((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
-    if (r == 0.0f) { st->out_of_bounds++; return; }
-    float t0 = P->full_ray ? 0.0f : r - delta;
+    *r_out = r;
+    if (r == 0.0f) return 0;
+    float t0 = whole ? 0.0f : r - delta;
     if (t0 < 0.0f) t0 = 0.0f;
     float t1 = r + delta;
     for (int k = 0; k < 3; ++k) {
@@ -379,11 +385,33 @@ static void cast_ray(orc_map* m, const orc_ray* ray, const float s32[3], const d
         A[k] = a * iv;
         B[k] = b * iv;
         if (!(A[k] >= -(float)ORC_VOX_LIMIT && A[k] < (float)ORC_VOX_LIMIT &&
-              B[k] >= -(float)ORC_VOX_LIMIT && B[k] < (float)ORC_VOX_LIMIT)) {
-            st->out_of_bounds++;
-            return;
-        }
+              B[k] >= -(float)ORC_VOX_LIMIT && B[k] < (float)ORC_VOX_LIMIT)) return 0;
     }
+    return 1;
+}
+
+/* V5: the distance merged into D, clamped to +-delta. */
+static double clamp_distance(double d, double d64) { return d < -d64 ? -d64 : (d > d64 ? d64 : d); }
+
+/* V6/V8: one frame's update of a voxel by Eqs. (3)-(4), then the storage rounding. */
+static void fold_voxel(const orc_params* P, orc_voxel* vx, double sw, double swd) {
+    const double wmax = (double)P->w_max;
+    vx->D = (vx->W * vx->D + swd) / (vx->W + sw);
+    vx->W = vx->W + sw < wmax ? vx->W + sw : wmax;
+    if (P->fp16) {
+        vx->D = P->fp16 == 2 ? orc_round_s16(vx->D) : orc_round_half(vx->D);
+        vx->W = orc_round_half(vx->W);
+    }
+}
+
+/* Casts one ray through the truncation band and accumulates its observations. */
+static void cast_ray(orc_map* m, const orc_ray* ray, const float s32[3], const double s64[3],
+                     orc_stats* st, int32_t* buf, int bufcap) {
+    const orc_params* P = &m->P;
+    const float v = P->voxel_size, delta = P->trunc;
+    /* segment of the ray the update covers, binary32 */
+    float e[3], A[3], B[3], r;
+    if (!ray_segment(P, P->full_ray, ray->p32, s32, e, &r, A, B)) { st->out_of_bounds++; return; }
     st->rays++;
     int cnt = orc_dda(A, B, buf, bufcap);
     if (cnt > bufcap) cnt = bufcap; /* cannot happen: bufcap covers the longest band */
@@ -419,7 +447,7 @@ static void cast_ray(orc_map* m, const orc_ray* ray, const float s32[3], const d
         }
         double w = ray->wgt;
         if (P->weighting == 1) w *= dropoff(d, eps, d64);
-        double dc = d < -d64 ? -d64 : (d > d64 ? d64 : d);
+        double dc = clamp_distance(d, d64);
         int created;
         orc_voxel* vx = (orc_voxel*)table_get(&m->vox, pack3(g[0], g[1], g[2]), 1, &created);
         if (vx->stamp != m->frame + 1) {
@@ -465,11 +493,10 @@ int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], 
         if (!(rho2 > 0.0f && rho2 <= rmax2)) { st.invalid++; continue; }
         if (P->weighting == 1 && !(z >= P->z_min)) { st.invalid++; continue; }
         float q[3];
-        for (int k = 0; k < 3; ++k) {
-            q[k] = ((pose[4 * k] * x + pose[4 * k + 1] * y) + pose[4 * k + 2] * z) + pose[4 * k + 3];
+        transform_point(pose, x, y, z, q);
+        for (int k = 0; k < 3; ++k)
             p64[3 * nv + k] = (((double)pose[4 * k] * x + (double)pose[4 * k + 1] * y) +
                                (double)pose[4 * k + 2] * z) + (double)pose[4 * k + 3];
-        }
         int inside = 1;
         for (int k = 0; k < 3; ++k) {
             float f = q[k] * iv;
@@ -539,7 +566,6 @@ int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], 
     for (size_t i = 0; i < nr; ++i) cast_ray(m, &rays[i], s32, s64, &st, buf, bufcap);
 
     /* 4. Eqs. (3)-(4) once per touched voxel; allocate the blocks of touched voxels */
-    const double wmax = (double)P->w_max;
     for (size_t t = 0; t < m->n_touch; ++t) {
         uint64_t key = m->touch_keys[t];
         orc_voxel* vx = (orc_voxel*)table_get(&m->vox, key, 0, NULL);
@@ -549,20 +575,138 @@ int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], 
         table_get(&m->blocks, pack3(block_of(g[0]), block_of(g[1]), block_of(g[2])), 1, &created);
         st.new_blocks += (uint64_t)created;
         m->touch_n[t] = vx->n;
-        if (vx->sw > 0.0) {
-            vx->D = (vx->W * vx->D + vx->swd) / (vx->W + vx->sw);
-            vx->W = vx->W + vx->sw < wmax ? vx->W + vx->sw : wmax;
-            if (P->fp16) {
-                vx->D = P->fp16 == 2 ? orc_round_s16(vx->D) : orc_round_half(vx->D);
-                vx->W = orc_round_half(vx->W);
-            }
-        }
+        if (vx->sw > 0.0) fold_voxel(P, vx, vx->sw, vx->swd);
     }
     st.voxels = m->n_touch;
     m->frame++;
     m->last = st;
     if (out) *out = st;
     free(buf); free(rays); free(p32); free(p64); free(w32); free(w64); free(valid);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Projection mapping (Sec. IV-B)                                      */
+/* ------------------------------------------------------------------ */
+/*
+ * Integrates one organised frame by projection mapping: instead of casting rays, every voxel
+ * of the frame's blocks is projected into the depth image and takes its distance from the
+ * depth the image holds at that pixel.
+ *  - The blocks: those the truncation bands of the frame's valid points cross (the blocks
+ *    raycasting would allocate; every point casts its band, no grouping).
+ *  - Geometry (binary32, fixed order, no FMA): the voxel centre x = RN32((g + 1/2) v), its
+ *    camera coordinates c_k = ((R_0k e_0 + R_1k e_1) + R_2k e_2) with e = x - t; the pixel
+ *    (floor(fx (c_0 / c_2) + cx), floor(fy (c_1 / c_2) + cy)); the voxel is observed when
+ *    c_2 > 0, the pixel lies in the image, its point is valid (the validity test of the
+ *    point path) and the binary32 distance z_pixel - c_2 exceeds -delta.
+ *  - Values (binary64): d = z_pixel - z, z the binary64 depth of the exact voxel centre; the
+ *    weight of Eq. (2), or of Eq. (5) with the pixel's depth; D and W by Eqs. (3)-(4) with the
+ *    distance clamped to +-delta (one observation per voxel and frame).
+ * Reading: the paper names the distance "between the voxel center and the depth value in the
+ * image"; it is taken along the optical axis (depth minus depth), as in projective TSDF fusion.
+ * Readings of the rest: the image pixel (i, j) holds point i + W j of the organised cloud; the
+ * intrinsics map a camera point to pixel coordinates u = fx x / z + cx, v = fy y / z + cy.
+ */
+int orc_integrate_projective(orc_map* m, const float* pts, size_t n, uint32_t width, const float pose[12],
+                             const float intr[4], orc_stats* out) {
+    const orc_params* P = &m->P;
+    orc_stats st;
+    memset(&st, 0, sizeof st);
+    st.points = n;
+    if (width == 0 || n % width != 0) return -1;
+    const uint32_t height = (uint32_t)(n / width);
+    const float v = P->voxel_size, iv = 1.0f / v, delta = P->trunc;
+    const float rmax2 = P->max_range * P->max_range;
+    const float s32[3] = {pose[3], pose[7], pose[11]};
+
+    /* validity of every pixel's point, and the blocks their bands cross */
+    uint8_t* ok = (uint8_t*)calloc(n + 1, 1);
+    orc_table blocks_now;
+    table_init(&blocks_now, 1);
+    int bufcap = 3 * ((int)ceilf(2.0f * delta / v) + 4) + 8;
+    int32_t* buf = (int32_t*)malloc((size_t)bufcap * 3 * sizeof(int32_t));
+    for (size_t i = 0; i < n; ++i) {
+        float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+        if (!(isfinite(x) && isfinite(y) && isfinite(z))) { st.invalid++; continue; }
+        float rho2 = (x * x + y * y) + z * z;
+        if (!(rho2 > 0.0f && rho2 <= rmax2)) { st.invalid++; continue; }
+        if (P->weighting == 1 && !(z >= P->z_min)) { st.invalid++; continue; }
+        float q[3];
+        int inside = 1;
+        transform_point(pose, x, y, z, q);
+        for (int k = 0; k < 3; ++k) {
+            float f = q[k] * iv;
+            if (!(f >= -(float)ORC_VOX_LIMIT && f < (float)ORC_VOX_LIMIT)) inside = 0;
+        }
+        if (!inside) { st.out_of_bounds++; continue; }
+        ok[i] = 1;
+        st.valid++;
+        /* the band segment, binary32, as raycasting takes it */
+        float e[3], A[3], B[3], r;
+        if (!ray_segment(P, 0, q, s32, e, &r, A, B)) { st.out_of_bounds++; continue; }
+        st.rays++;
+        int cnt = orc_dda(A, B, buf, bufcap);
+        if (cnt > bufcap) cnt = bufcap;
+        for (int c = 0; c < cnt; ++c) {
+            const int32_t* g = buf + 3 * c;
+            int created;
+            table_get(&blocks_now, pack3(block_of(g[0]), block_of(g[1]), block_of(g[2])), 1, &created);
+        }
+    }
+    free(buf);
+
+    /* every voxel of those blocks, projected */
+    const float fx = intr[0], fy = intr[1], cx = intr[2], cy = intr[3];
+    double R64[9], t64[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) R64[3 * r + c] = (double)pose[4 * r + c];
+        t64[r] = (double)pose[4 * r + 3];
+    }
+    const double v64 = (double)v, d64 = (double)delta, eps = v64;
+    m->n_touch = 0;
+    for (size_t bi = 0; bi < blocks_now.cap; ++bi) {
+        if (!blocks_now.keys[bi]) continue;
+        int32_t bc[3];
+        unpack3(blocks_now.keys[bi] - 1, &bc[0], &bc[1], &bc[2]);
+        int created;
+        table_get(&m->blocks, blocks_now.keys[bi] - 1, 1, &created);
+        st.new_blocks += (uint64_t)created;
+        for (int l = 0; l < 4096; ++l) {
+            const int32_t g[3] = {16 * bc[0] + (l & 15), 16 * bc[1] + ((l >> 4) & 15), 16 * bc[2] + (l >> 8)};
+            float e[3], cam[3];
+            for (int k = 0; k < 3; ++k) e[k] = ((float)g[k] + 0.5f) * v - s32[k];
+            for (int k = 0; k < 3; ++k) cam[k] = (pose[k] * e[0] + pose[4 + k] * e[1]) + pose[8 + k] * e[2];
+            if (!(cam[2] > 0.0f)) continue;
+            const float uf = fx * (cam[0] / cam[2]) + cx;
+            const float vf = fy * (cam[1] / cam[2]) + cy;
+            if (!(uf >= 0.0f && uf < (float)width && vf >= 0.0f && vf < (float)height)) continue;
+            const size_t pix = (size_t)floorf(uf) + (size_t)width * (size_t)floorf(vf);
+            if (!ok[pix]) continue;
+            const float zm = pts[3 * pix + 2];
+            if (!(zm - cam[2] > -delta)) continue;
+            /* values, binary64: depth of the exact centre */
+            double z = 0.0;
+            for (int k = 0; k < 3; ++k) z += R64[3 * k + 2] * (((double)g[k] + 0.5) * v64 - t64[k]);
+            const double d = (double)zm - z;
+            double w = P->weighting == 1 ? 1.0 / ((double)zm * (double)zm) : 1.0;
+            const double wgt = w;
+            if (P->weighting == 1) w *= dropoff(d, eps, d64);
+            const double dc = clamp_distance(d, d64);
+            orc_voxel* vx = (orc_voxel*)table_get(&m->vox, pack3(g[0], g[1], g[2]), 1, &created);
+            add_touch(m, pack3(g[0], g[1], g[2]));
+            m->touch_n[m->n_touch - 1] = 1;
+            vx->mass += wgt;
+            if (P->weighting == 1 && d > -d64 && d <= -eps) vx->ramp += wgt;
+            st.touches++;
+            if (w > 0.0) fold_voxel(P, vx, w, w * (dc / d64));
+        }
+    }
+    st.voxels = m->n_touch;
+    m->frame++;
+    m->last = st;
+    if (out) *out = st;
+    table_free(&blocks_now);
+    free(ok);
     return 0;
 }
 

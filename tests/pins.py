@@ -255,6 +255,75 @@ def pin_full_ray_head_on(lib_path=None):
         m.close()
 
 
+def _stair_frame(Z, W=16, H=16, f=8.0):
+    """An organised frame whose pixel (i, j) sees depth z_ij = Z + ((i + 2 j) mod 5) / 32 along
+    ((i + 1/2 - W/2) / f, (j + 1/2 - H/2) / f, 1) (exact in binary32 for dyadic Z): a depth that
+    changes from pixel to pixel, so that the pixel a voxel projects to matters."""
+    i, j = np.meshgrid(np.arange(W), np.arange(H))
+    z = Z + ((i.ravel() + 2 * j.ravel()) % 5) / 32.0
+    d = np.stack([(i.ravel() + 0.5 - W / 2) / f, (j.ravel() + 0.5 - H / 2) / f, np.ones(W * H)], axis=1)
+    return (d * z[:, None]).astype(np.float32), (f, f, W / 2, H / 2)
+
+
+def pin_projective_plane(lib_path=None):
+    """Projection mapping (Sec. IV-B) of a depth image seen head-on, worked in exact arithmetic:
+    the blocks are the ones raycasting allocates for the same frame; every voxel of them that
+    projects into the image (camera point c = R^T (x - t), pixel (floor(f c_x / c_z + W/2),
+    floor(f c_y / c_z + H/2))) with a depth difference z_pixel - c_z above -delta takes
+    D = clamp(z_pixel - c_z, +-delta) and the frame's weight (1, or 1/z_pixel^2 with the Eq. (5)
+    drop-off); the rest is untouched.  Two frames: W doubles, D stays."""
+    for axis, sign, weighting, Z, frames in [(0, 1, "const", 1.0, 2), (2, 1, "quad", 1.25, 1),
+                                             (1, -1, "const", 0.75, 1)]:
+        pose = _axis_pose(axis, sign)
+        pts, intr = _stair_frame(Z)
+        zpix = [Fr(float(z)) for z in pts[:, 2]]
+        m = oracle.OracleMap(V, DELTA, weighting=weighting, merge="simple", w_max=1e30,
+                             max_range=10.0, z_min=0.1, lib_path=lib_path)
+        ray = oracle.OracleMap(V, DELTA, weighting=weighting, merge="simple", w_max=1e30,
+                               max_range=10.0, z_min=0.1, lib_path=lib_path)
+        for _ in range(frames):
+            st = m.integrate_projective(pts, pose, 16, intr)
+        ray.integrate(pts, pose)
+        coords = m.export()[0]
+        assert np.array_equal(coords, ray.export()[0]), "blocks: the ones raycasting allocates"
+        R = [[Fr(float(pose[r, c])) for c in range(3)] for r in range(3)]
+        t = [Fr(float(pose[r, 3])) for r in range(3)]
+        got, _ = _export_dict(m)
+        seen = 0
+        for b in coords.tolist():
+            for l in range(4096):
+                g = (16 * b[0] + (l & 15), 16 * b[1] + ((l >> 4) & 15), 16 * b[2] + (l >> 8))
+                e = [(Fr(g[k]) + Fr(1, 2)) * Fr(V) - t[k] for k in range(3)]
+                c = [sum(R[r][k] * e[r] for r in range(3)) for k in range(3)]
+                hit = c[2] > 0
+                if hit:
+                    u = Fr(intr[0]) * c[0] / c[2] + Fr(intr[2])
+                    vv = Fr(intr[1]) * c[1] / c[2] + Fr(intr[3])
+                    hit = 0 <= u < 16 and 0 <= vv < 16
+                if hit:
+                    zp = zpix[math.floor(u) + 16 * math.floor(vv)]
+                    hit = zp - c[2] > -Fr(DELTA)
+                if not hit:
+                    assert g not in got, f"{g} updated outside the image or behind the band"
+                    continue
+                d = zp - c[2]
+                dc = max(-Fr(DELTA), min(Fr(DELTA), d))
+                w = Fr(1)
+                if weighting == "quad":
+                    fd = 1 if d > -Fr(V) else ((d + Fr(DELTA)) / (Fr(DELTA) - Fr(V)) if d > -Fr(DELTA) else 0)
+                    w = Fr(1) / (zp * zp) * fd
+                if w == 0:
+                    assert g not in got
+                    continue
+                seen += 1
+                assert g in got, f"{g} not updated"
+                assert abs(got[g][0] - float(dc)) <= 1e-12, f"D at {g}: {got[g][0]} vs {float(dc)}"
+                assert abs(got[g][1] - float(frames * w)) <= 1e-12 * float(frames * w), f"W at {g}"
+        assert seen == len(got) and seen > 100
+        assert st["touches"] >= seen
+        m.close(); ray.close()
+
+
 def pin_dropoff_values(lib_path=None):
     """Eq. (5) at the distances where it changes form: d > -eps full weight, d = -(eps+delta)/2
     half weight, d <= -delta zero weight (W stays 0 while the block is still allocated)."""
@@ -741,7 +810,8 @@ def pin_permutation(lib_path=None, seed=9):
         a.close(); b.close()
 
 
-ALL_PINS = [pin_dda_dyadic, pin_dda_random, pin_head_on_plane, pin_full_ray_head_on, pin_dropoff_values,
+ALL_PINS = [pin_dda_dyadic, pin_dda_random, pin_head_on_plane, pin_full_ray_head_on, pin_projective_plane,
+            pin_dropoff_values,
             pin_along_ray_off_axis, pin_binary16_sequence, pin_s16_sequence, pin_ramp_diagnostic,
             pin_weight_sums, pin_group_mean, pin_merged_singletons, pin_identical_points,
             pin_running_average, pin_validity, pin_round_half, pin_permutation]

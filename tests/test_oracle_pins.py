@@ -22,16 +22,15 @@ MUTATIONS = {
     "tie_to_highest_axis": ("if (axis < 0 || tM[k] < tM[axis]) axis = k;",
                             "if (axis < 0 || tM[k] <= tM[axis]) axis = k;"),
     "dropoff_slope": ("return (d + delta) / (delta - eps);", "return (d + delta) / delta;"),
-    "no_weight_cap": ("vx->W = vx->W + vx->sw < wmax ? vx->W + vx->sw : wmax;",
-                      "vx->W = vx->W + vx->sw;"),
-    "merge_drops_old_weight": ("vx->D = (vx->W * vx->D + vx->swd) / (vx->W + vx->sw);",
-                               "vx->D = (vx->D + vx->swd) / (vx->W + vx->sw);"),
+    "no_weight_cap": ("vx->W = vx->W + sw < wmax ? vx->W + sw : wmax;", "vx->W = vx->W + sw;"),
+    "merge_drops_old_weight": ("vx->D = (vx->W * vx->D + swd) / (vx->W + sw);",
+                               "vx->D = (vx->D + swd) / (vx->W + sw);"),
     "rotation_transposed": ("q[k] = ((pose[4 * k] * x + pose[4 * k + 1] * y) + pose[4 * k + 2] * z) + pose[4 * k + 3];",
                             "q[k] = ((pose[k] * x + pose[4 + k] * y) + pose[8 + k] * z) + pose[4 * k + 3];"),
     "group_mean_unweighted": ("uint64_t om = wbits > 0 ? (uint64_t)rintf(ldexpf(w32[i], wbits)) : 1u;",
                               "uint64_t om = 1u;"),
     "no_band_behind_surface": ("float t1 = r + delta;", "float t1 = r;"),
-    "no_distance_clamp": ("double dc = d < -d64 ? -d64 : (d > d64 ? d64 : d);", "double dc = d;"),
+    "no_distance_clamp": ("return d < -d64 ? -d64 : (d > d64 ? d64 : d);", "return d;"),
     "corner_not_centre": ("double x = ((double)g[k] + 0.5) * v64;\n                double f = ray->p64[k] - x;",
                           "double x = ((double)g[k]) * v64;\n                double f = ray->p64[k] - x;"),
     "weight_one_over_z": ("w64[nv] = P->weighting == 1 ? 1.0 / ((double)z * (double)z) : 1.0;",
@@ -45,12 +44,12 @@ MUTATIONS = {
     "binary16_rounds_metres": (": orc_round_half(vx->D);",
                                ": orc_round_half(vx->D * (double)P->trunc) / (double)P->trunc;"),
     "binary16_rounds_w_before_cap": (
-        "vx->W = vx->W + vx->sw < wmax ? vx->W + vx->sw : wmax;\n            if (P->fp16) {\n"
-        "                vx->D = P->fp16 == 2 ? orc_round_s16(vx->D) : orc_round_half(vx->D);\n"
-        "                vx->W = orc_round_half(vx->W);\n            }",
-        "vx->W = P->fp16 ? orc_round_half(vx->W + vx->sw) : vx->W + vx->sw;\n"
-        "            if (vx->W > wmax) vx->W = wmax;\n"
-        "            if (P->fp16) vx->D = P->fp16 == 2 ? orc_round_s16(vx->D) : orc_round_half(vx->D);"),
+        "vx->W = vx->W + sw < wmax ? vx->W + sw : wmax;\n    if (P->fp16) {\n"
+        "        vx->D = P->fp16 == 2 ? orc_round_s16(vx->D) : orc_round_half(vx->D);\n"
+        "        vx->W = orc_round_half(vx->W);\n    }",
+        "vx->W = P->fp16 ? orc_round_half(vx->W + sw) : vx->W + sw;\n"
+        "    if (vx->W > wmax) vx->W = wmax;\n"
+        "    if (P->fp16) vx->D = P->fp16 == 2 ? orc_round_s16(vx->D) : orc_round_half(vx->D);"),
     # the 16-bit fixed-point distance: D / delta in steps of 1/32767, to nearest
     "s16_rounds_metres": ("? orc_round_s16(vx->D) :",
                           "? orc_round_s16(vx->D * (double)P->trunc) / (double)P->trunc :"),
@@ -62,12 +61,21 @@ MUTATIONS = {
                                 "if (P->weighting == 1 && d <= -eps) vx->ramp += ray->wgt;"),
     "ramp_counts_dropped_weight": ("vx->ramp += ray->wgt;", "vx->ramp += w;"),
     # the whole-ray update (Sec. IV-B)
-    "full_ray_ignored": ("float t0 = P->full_ray ? 0.0f : r - delta;", "float t0 = r - delta;"),
+    "full_ray_ignored": ("float t0 = whole ? 0.0f : r - delta;", "float t0 = r - delta;"),
+    # projection mapping (Sec. IV-B)
+    "projective_pixel_rounded": ("const size_t pix = (size_t)floorf(uf) + (size_t)width * (size_t)floorf(vf);",
+                                 "const size_t pix = (size_t)rintf(uf) + (size_t)width * (size_t)rintf(vf);"),
+    "projective_distance_sign": ("const double d = (double)zm - z;", "const double d = z - (double)zm;"),
+    "projective_rotation_not_transposed": (
+        "cam[k] = (pose[k] * e[0] + pose[4 + k] * e[1]) + pose[8 + k] * e[2];",
+        "cam[k] = (pose[4 * k] * e[0] + pose[4 * k + 1] * e[1]) + pose[4 * k + 2] * e[2];"),
+    "projective_band_too_wide": ("if (!(zm - cam[2] > -delta)) continue;", "if (!(zm - cam[2] > -2.0f * delta)) continue;"),
     "full_ray_stops_at_point": ("float t1 = r + delta;\n    for (int k = 0; k < 3; ++k) {\n        float u = e[k] / r;",
-                                "float t1 = P->full_ray ? r : r + delta;\n    for (int k = 0; k < 3; ++k) {\n        float u = e[k] / r;"),
+                                "float t1 = whole ? r : r + delta;\n    for (int k = 0; k < 3; ++k) {\n        float u = e[k] / r;"),
 }
 
-FAST_FIRST = [pins.pin_head_on_plane, pins.pin_full_ray_head_on, pins.pin_dropoff_values, pins.pin_running_average,
+FAST_FIRST = [pins.pin_head_on_plane, pins.pin_full_ray_head_on, pins.pin_projective_plane, pins.pin_dropoff_values,
+              pins.pin_running_average,
               pins.pin_along_ray_off_axis, pins.pin_binary16_sequence, pins.pin_s16_sequence,
               pins.pin_ramp_diagnostic,
               pins.pin_validity, pins.pin_identical_points, pins.pin_merged_singletons,
