@@ -172,6 +172,19 @@ int vbx_integrate_batch(vbx_map* map, const float* const* points_dev, const size
 /* As vbx_integrate_batch, with per-frame organisation hints. */
 int vbx_integrate_frames(vbx_map* map, const vbx_frame* frames, int F);
 
+/* Integrates F organised depth frames in order by projection mapping (Sec. IV-B) instead of
+ * raycasting: every voxel of the blocks the frames' truncation bands cross is projected into the
+ * depth image and takes its distance from the depth the image holds there.  frames: host [F],
+ * each with width > 0 and n a multiple of it (pixel (i, j) is point i + width j); intrinsics:
+ * host [4] = fx, fy, cx, cy, mapping a camera point (x, y, z) to pixel coordinates
+ * (fx x / z + cx, fy y / z + cy), pixel (floor(u), floor(v)).  A voxel is observed when its centre
+ * lies in front of the camera, projects into the image onto a valid point, and the depth
+ * difference d = z_pixel - z_voxel (along the optical axis) exceeds -trunc; it is then updated by
+ * Eqs. (3)-(4) with d clamped to +-trunc and the weight of Eq. (2), or of Eq. (5) with the
+ * pixel's depth.  One observation per voxel and frame.  The map's merge mode does not apply.
+ * INVALID_ARG for unorganised frames or intrinsics that are not finite with fx, fy > 0. */
+int vbx_integrate_projective(vbx_map* map, const vbx_frame* frames, int F, const float intrinsics[4]);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid allocation): vbx_integrate_frames into one map, with the call's
  * scratch memory (rays, partial groups, sort bins, block set, tables, counters) taken from a

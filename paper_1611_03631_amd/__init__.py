@@ -79,7 +79,7 @@ class Stats(ctypes.Structure):
 
 EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_map_destroy",
             "vbx_map_set_stream", "vbx_integrate", "vbx_integrate_batch", "vbx_integrate_frames",
-            "vbx_integrate_frames_noalloc", "vbx_write_blocks", "vbx_esdf_enable", "vbx_esdf_update",
+            "vbx_integrate_frames_noalloc", "vbx_integrate_projective", "vbx_write_blocks", "vbx_esdf_enable", "vbx_esdf_update",
             "vbx_esdf_export",
             "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
@@ -148,6 +148,7 @@ def lib(path: Optional[str] = None):
     L.vbx_integrate_batch.argtypes = [vp, vp, vp, f32p, i32]
     L.vbx_integrate_frames.argtypes = [vp, ctypes.POINTER(Frame), i32]
     L.vbx_integrate_frames_noalloc.argtypes = [vp, ctypes.POINTER(Frame), i32]
+    L.vbx_integrate_projective.argtypes = [vp, ctypes.POINTER(Frame), i32, vp]
     L.vbx_map_interpolate.argtypes = [vp, vp, sz, vp]
     L.vbx_integrate_multi.argtypes = [vp, ctypes.POINTER(Frame), i32]
     L.vbx_map_sync.argtypes = [vp]
@@ -328,6 +329,14 @@ class Map:
         arr = make_frames(frames)
         _check(lib().vbx_integrate_frames_noalloc(self._h, arr, len(frames)),
                "vbx_integrate_frames_noalloc")
+
+    def integrate_projective(self, frames: Sequence[Tuple], intrinsics):
+        """Projection mapping (Sec. IV-B) of organised frames [(points, pose, width)] with pinhole
+        intrinsics (fx, fy, cx, cy)."""
+        arr = make_frames(frames)
+        K = np.ascontiguousarray(np.asarray(intrinsics, dtype=np.float32).reshape(4))
+        _check(lib().vbx_integrate_projective(self._h, arr, len(frames), K.ctypes.data),
+               "vbx_integrate_projective")
 
     def integrate_batch(self, points_list, poses):
         F = len(points_list)

@@ -323,6 +323,8 @@ struct CallPlan {
     int storage = 0;
     bool keep_touches = false;
     u32 tiles_per_job = 0;      // every job has this many tiles and there is one map (else 0)
+    bool projective = false;    // projection mapping instead of raycasting the voxels
+    Intrinsics K = {};          // its camera intrinsics
 };
 
 // Element counts of a call's scratch buffers (host upper bounds: nothing is read back mid-call).
@@ -341,6 +343,8 @@ int scratch_sizes(const CallPlan& plan, int njobs, int nmaps, size_t sum_capacit
     if (z.bins_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
     z.nparts = (z.bins_cap + kScanChunkHost - 1) / kScanChunkHost;
     z.touch_cap = plan.keep_touches ? std::min<size_t>(z.ray_cap * (size_t)plan.max_vox, (size_t)1 << 26) : 0;
+    if (plan.keep_touches && plan.projective)   // every voxel of every block of the call
+        z.touch_cap = std::min<size_t>(z.tlist_cap * 4096, (size_t)1 << 26);
     z.tables_bytes = (size_t)nmaps * sizeof(MapDesc) + (size_t)njobs * sizeof(Job);
     return VBX_OK;
 }
@@ -644,7 +648,7 @@ struct Prepared {
 // Validates the frames of a call over `maps` (frames[i] belongs to maps[owner[i]]; frames of one
 // map are in call order) and numbers the tiles of every frame over the whole call.
 int prepare_call(const std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
-                 const std::vector<int>& owner, Prepared& out) {
+                 const std::vector<int>& owner, Prepared& out, const Intrinsics* projective = nullptr) {
     vbx_map* lead = maps[0];
     const int M = (int)maps.size();
     const int F = (int)frames.size();
@@ -666,6 +670,12 @@ int prepare_call(const std::vector<vbx_map*>& maps, const std::vector<vbx_frame>
         out.sum_capacity += maps[m]->capacity;
     }
     plan.grouped = lead->P.merge == VBX_MERGE_GROUPED;
+    if (projective) {
+        // the blocks come from every point's band (no grouping); the voxels are projected
+        plan.grouped = false;
+        plan.projective = true;
+        plan.K = *projective;
+    }
 
     std::vector<Job>& jobs = out.jobs;
     std::vector<MapDesc>& descs = out.descs;
@@ -865,6 +875,27 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     StageTimer tm(prof_map, st, ST_COMMIT);
     hipLaunchKernelGGL(k_commit, dim3(GT), dim3(256), 0, st, d_maps, (const u64*)s->t_key.p, (int*)s->t_slot.p, cs);
     }
+    if (plan.projective) {
+        {
+        StageTimer tm(prof_map, st, ST_BINS);
+        // which frames' bands cross which blocks: the crossing counts per (block, frame)
+        hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, d_jobs, (const u32*)s->cross.p,
+                           (const unsigned char*)s->ncross.p, MB, (const u32*)s->tval.p, (const u32*)rays_job,
+                           (u32*)s->bins.p, JM, cs, ray_cap);
+        }
+        if (plan.keep_touches) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->touch_count, 0u);
+        StageTimer tm(prof_map, st, ST_UPDATE);
+        const unsigned GP = 2048;   // persistent: workgroups stride over the call's blocks
+#define VBX_PROJ(S)                                                                                           \
+        hipLaunchKernelGGL(k_project<S>, dim3(GP), dim3(256), 0, st, d_jobs, d_maps, (const u64*)s->t_key.p,   \
+                           (const int*)s->t_slot.p, (u32*)s->bins.p, JM, plan.K, (u64*)s->touch_key.p,          \
+                           (u32*)s->touch_n.p,                                                                 \
+                           (u32)s->touch_cap, plan.keep_touches ? 1 : 0, jst, cs)
+        if (plan.storage == VBX_F32) VBX_PROJ(0);
+        else if (plan.storage == VBX_F16) VBX_PROJ(1);
+        else VBX_PROJ(2);
+#undef VBX_PROJ
+    } else {
     {
     StageTimer tm(prof_map, st, ST_BINS);
     hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, d_jobs, (const u32*)s->cross.p,
@@ -893,6 +924,7 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
                   (u64*)s->touch_key.p, (u32*)s->touch_n.p, (u32)s->touch_cap, plan.keep_touches ? 1 : 0,
                   jst, cs);
     }
+    }
     {
     StageTimer tm(prof_map, st, ST_FINISH);
     // one workgroup per map, and few for the block-set cleanup: every workgroup adds to one
@@ -918,10 +950,11 @@ void note_touches(Scratch* s, const std::vector<vbx_map*>& maps, const CallPlan&
 // One integration call over `maps` (distinct maps) with frames[i] belonging to
 // maps[owner[i]]; frames of one map are in call order.  Runs on stream `st` with scratch `s`.
 int run_call_on(Scratch* s, hipStream_t st, std::vector<vbx_map*>& maps, const std::vector<vbx_frame>& frames,
-                const std::vector<int>& owner, int update_variant, vbx_map* timer) {
+                const std::vector<int>& owner, int update_variant, vbx_map* timer,
+                const Intrinsics* projective = nullptr) {
     if (frames.empty()) return VBX_OK;
     Prepared pr;
-    int rc = prepare_call(maps, frames, owner, pr);
+    int rc = prepare_call(maps, frames, owner, pr, projective);
     if (rc != VBX_OK) return rc;
     const int J = (int)pr.jobs.size(), M = (int)maps.size();
     if ((rc = ensure_scratch(s, st, pr.plan, J, M, pr.sum_capacity)) != VBX_OK) return rc;
@@ -1364,6 +1397,21 @@ int vbx_integrate_frames_noalloc(vbx_map* m, const vbx_frame* frames, int F) {
     if ((rc = launch_call(s, st, pr.plan, J, 1, m->update_variant, nullptr)) != VBX_OK) return rc;
     m->touch_src = nullptr;   // no touch records for this call
     return VBX_OK;
+}
+
+int vbx_integrate_projective(vbx_map* m, const vbx_frame* frames, int F, const float intrinsics[4]) {
+    if (!m || F < 0 || (F > 0 && (!frames || !intrinsics))) return VBX_ERR_INVALID_ARG;
+    if (F == 0) return VBX_OK;
+    Intrinsics K{intrinsics[0], intrinsics[1], intrinsics[2], intrinsics[3]};
+    if (!(K.fx > 0.0f) || !(K.fy > 0.0f) || !std::isfinite(K.fx) || !std::isfinite(K.fy) || !std::isfinite(K.cx) ||
+        !std::isfinite(K.cy))
+        return VBX_ERR_INVALID_ARG;
+    for (int i = 0; i < F; ++i)
+        if (frames[i].width == 0 || frames[i].n % frames[i].width != 0) return VBX_ERR_INVALID_ARG;
+    std::vector<vbx_map*> maps{m};
+    std::vector<vbx_frame> fr(frames, frames + F);
+    std::vector<int> owner(F, 0);
+    return run_call_on(m->scratch, m->stream, maps, fr, owner, m->update_variant, m, &K);
 }
 
 int vbx_integrate(vbx_map* m, const float* points_dev, size_t n, const float pose[12]) {

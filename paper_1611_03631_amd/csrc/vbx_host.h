@@ -65,6 +65,16 @@ __global__ void k_finish_call(const Job* jobs, const MapDesc* maps, int nmaps, J
                               u32 tkey_cap, const u32* tlist, u32 tlist_cap, CallState* cs);
 template <int STORAGE>
 __global__ void k_interpolate(const MapDesc M, const float* q, u32 n, float* out);
+
+// Pinhole intrinsics of projection mapping: pixel coordinates u = fx x / z + cx, v = fy y / z + cy.
+struct Intrinsics {
+    float fx, fy, cx, cy;
+};
+template <int STORAGE>
+__global__ void k_project(const Job* jobs, const MapDesc* maps, const u64* t_key, const int* t_slot, u32* bins,
+                          u32 JM, Intrinsics K,
+                          u64* touch_key, u32* touch_n, u32 touch_cap, int keep_touches, JobStat* jst,
+                          CallState* cs);
 __global__ void k_debug_traverse(const float* A, const float* B, int n, int* out, int cap,
                                  int* counts);
 

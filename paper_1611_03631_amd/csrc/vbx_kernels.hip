@@ -1949,6 +1949,135 @@ __global__ __launch_bounds__(256) void k_finish_call(const Job* __restrict__ job
 }
 
 // ---------------------------------------------------------------------------
+// projection mapping (Sec. IV-B): voxels projected into the depth image
+// ---------------------------------------------------------------------------
+// One workgroup per block of the call's block set (the blocks the frames' truncation bands
+// cross), each thread holding 16 voxels in registers and folding, in order, the call's frames of
+// its map whose bands cross this block (bins[t * JM + frame] > 0: the crossing counts, cleared
+// here for the next call), so that a call of several frames equals one call per frame: the voxel centre goes to camera coordinates and to a pixel (binary32, fixed order,
+// no contraction: the same decisions as the point path's), the pixel's point must be valid, and
+// a depth difference above -delta updates the voxel by Eqs. (3)-(4) with the weight of Eq. (2)
+// or (5).  One observation per voxel and frame: no sums, no atomics.
+template <int STORAGE>
+__global__ __launch_bounds__(256) void k_project(const Job* __restrict__ jobs, const MapDesc* __restrict__ maps,
+                                                 const u64* __restrict__ t_key, const int* __restrict__ t_slot,
+                                                 u32* __restrict__ bins, u32 JM,
+                                                 Intrinsics K, u64* __restrict__ touch_key,
+                                                 u32* __restrict__ touch_n, u32 touch_cap, int keep_touches,
+                                                 JobStat* __restrict__ jst, CallState* __restrict__ cs) {
+    constexpr int VPT = 16;
+    __shared__ u32 lds8[4];
+    __shared__ u32 s_tbase;
+    const u32 nt = cs->error ? 0u : cs->t_count;
+    for (u32 t = blockIdx.x; t < nt; t += gridDim.x) {
+        const u64 tk = t_key[t];
+        const MapDesc M = maps[(u32)(tk >> 45)];
+        if (M.st->error != 0) continue;
+        int bx, by, bz;
+        unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
+        const int ts = t_slot[t];
+        const bool is_new = (ts & 0x40000000) != 0;
+        const size_t slot = (size_t)(ts & 0x3FFFFFFF);
+        float D[VPT], W[VPT];
+        u32 nobs[VPT];
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+            nobs[j] = 0;
+            if (is_new) { D[j] = 0.0f; W[j] = 0.0f; }
+            else load_voxel<STORAGE>(M.pool, slot * 4096 + threadIdx.x + 256 * j, D[j], W[j]);
+        }
+        u32 updates = 0;
+        for (int f = 0; f < M.njobs; ++f) {
+            const u32 nb = bins[(size_t)t * JM + (u32)f];
+            __syncthreads();                       // every thread has read the count
+            if (threadIdx.x == 0 && nb) bins[(size_t)t * JM + (u32)f] = 0u;
+            if (!nb) continue;                     // this frame's bands do not cross the block
+            const Job& J = jobs[M.job0 + f];
+            const u32 width = J.width, height = J.width ? J.n / J.width : 0u;
+            const float s0 = J.pose[3], s1 = J.pose[7], s2 = J.pose[11];
+#pragma unroll 4
+            for (int j = 0; j < VPT; ++j) {
+                const u32 l = threadIdx.x + 256u * (u32)j;
+                const int g0 = 16 * bx + (int)(l & 15), g1 = 16 * by + (int)((l >> 4) & 15), g2 = 16 * bz + (int)(l >> 8);
+                const float e0 = ((float)g0 + 0.5f) * M.v - s0;
+                const float e1 = ((float)g1 + 0.5f) * M.v - s1;
+                const float e2 = ((float)g2 + 0.5f) * M.v - s2;
+                const float c0 = (J.pose[0] * e0 + J.pose[4] * e1) + J.pose[8] * e2;
+                const float c1 = (J.pose[1] * e0 + J.pose[5] * e1) + J.pose[9] * e2;
+                const float c2 = (J.pose[2] * e0 + J.pose[6] * e1) + J.pose[10] * e2;
+                if (!(c2 > 0.0f)) continue;
+                const float uf = K.fx * (c0 / c2) + K.cx;
+                const float vf = K.fy * (c1 / c2) + K.cy;
+                if (!(uf >= 0.0f && uf < (float)width && vf >= 0.0f && vf < (float)height)) continue;
+                const size_t pix = (size_t)__builtin_floorf(uf) + (size_t)width * (size_t)__builtin_floorf(vf);
+                const float* pp = J.pts + 3 * pix;
+                const float x = pp[0], y = pp[1], z = pp[2];
+                float q[3];
+                if (classify_point(M, J.pose, x, y, z, q) != 1) continue;
+                const float d = z - c2;
+                if (!(d > -M.delta)) continue;
+                float w = M.weighting == 1 ? 1.0f / (z * z) : 1.0f;
+                if (M.weighting == 1) {
+                    const float ramp = (d + M.delta) * M.ramp;
+                    w = w * (d > -M.eps ? 1.0f : ramp);
+                }
+                nobs[j] += 1;
+                updates += 1;
+                if (!(w > 0.0f)) continue;
+                float dc = d > M.delta ? M.delta : d;
+                if (STORAGE != 0) dc = dc * M.inv_delta;
+                float Dn = (W[j] * D[j] + w * dc) / (W[j] + w);
+                float Wn = W[j] + w;
+                if (Wn > M.w_max) Wn = M.w_max;
+                round_to_storage<STORAGE>(Dn, Wn);
+                D[j] = Dn;
+                W[j] = Wn;
+            }
+        }
+        u32 cells = 0;
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+            store_voxel<STORAGE>(M.pool, slot * 4096 + threadIdx.x + 256 * j, D[j], W[j]);
+            cells += nobs[j] ? 1u : 0u;
+        }
+        if (threadIdx.x == 0 && M.dirty) M.dirty[slot] = 1u;
+        const u32 wu = wave_sum(updates), wc = wave_sum(cells);
+        if (lane_id() == 0 && wu) {
+            atomicAdd(&jst[M.job0].touches, (u64)wu);
+            atomicAdd(&jst[M.job0].voxels, (u64)wu);
+            atomicAdd(&jst[M.job0].cells, (u64)wc);
+        }
+        if (keep_touches) {
+            u32 tot;
+            const u32 incl = block_scan<256>(cells, lds8, &tot);
+            if (threadIdx.x == 0) s_tbase = atomicAdd(&cs->touch_count, tot);
+            __syncthreads();
+            u32 pos = s_tbase + incl - cells;
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                if (nobs[j]) {
+                    const u32 l = threadIdx.x + 256u * (u32)j;
+                    if (pos < touch_cap) {
+                        touch_key[pos] = ((u64)M.map_id << 57) |
+                                         voxel_key_of(16 * bx + (int)(l & 15), 16 * by + (int)((l >> 4) & 15),
+                                                      16 * bz + (int)(l >> 8));
+                        touch_n[pos] = nobs[j];
+                    }
+                    pos++;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+template __global__ void k_project<0>(const Job*, const MapDesc*, const u64*, const int*, u32*, u32, Intrinsics,
+                                      u64*, u32*, u32, int, JobStat*, CallState*);
+template __global__ void k_project<1>(const Job*, const MapDesc*, const u64*, const int*, u32*, u32, Intrinsics,
+                                      u64*, u32*, u32, int, JobStat*, CallState*);
+template __global__ void k_project<2>(const Job*, const MapDesc*, const u64*, const int*, u32*, u32, Intrinsics,
+                                      u64*, u32*, u32, int, JobStat*, CallState*);
+
+// ---------------------------------------------------------------------------
 // query: trilinear interpolation of the distance field (the accuracy evaluation, Sec. VI-A)
 // ---------------------------------------------------------------------------
 // Voxel (i, j, k) holds the field at its centre ((i, j, k) + 1/2) v.  A query point q takes the

@@ -75,6 +75,8 @@ def distance_error(params: dict) -> float:
     the band visits.  Twice that is the stated bound."""
     v = float(np.float32(params["voxel_size"]))
     delta = float(np.float32(params["trunc"]))
+    if "dist_err" in params:        # a path whose distance error has another bound (stated there)
+        return float(params["dist_err"])
     return 8.0 * 2.0 ** -24 * (delta + v)
 
 
