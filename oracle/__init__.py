@@ -39,7 +39,7 @@ class _Params(ctypes.Structure):
                 ("w_max", ctypes.c_float), ("max_range", ctypes.c_float),
                 ("z_min", ctypes.c_float), ("weighting", ctypes.c_int),
                 ("merge", ctypes.c_int), ("fp16", ctypes.c_int), ("dist", ctypes.c_int),
-                ("world64", ctypes.c_int), ("full_ray", ctypes.c_int)]
+                ("world64", ctypes.c_int), ("full_ray", ctypes.c_int), ("color", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -69,6 +69,11 @@ def load(path: Optional[str] = None):
                                   ctypes.c_void_p, P(_Stats)]
     lib.orc_num_blocks.restype = ctypes.c_size_t
     lib.orc_num_blocks.argtypes = [ctypes.c_void_p]
+    lib.orc_integrate_color.restype = ctypes.c_int
+    lib.orc_integrate_color.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p, P(_Stats)]
+    lib.orc_export_color.restype = ctypes.c_size_t
+    lib.orc_export_color.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     lib.orc_integrate_projective.restype = ctypes.c_int
     lib.orc_integrate_projective.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                              ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
@@ -123,16 +128,17 @@ class OracleMap:
     def __init__(self, voxel_size: float, trunc: float, weighting: str = "const",
                  merge: str = "simple", w_max: float = 1e4, max_range: float = 5.0,
                  z_min: float = 0.1, storage: str = "f32", dist: str = "eq1",
-                 world64: bool = False, full_ray: bool = False, lib_path: Optional[str] = None):
+                 world64: bool = False, full_ray: bool = False, color: bool = False,
+                 lib_path: Optional[str] = None):
         """world64: measure distances from the binary64 transform of each sensor point (and a
         group's exact binary64 mean) instead of the binary32 ray end point."""
         self.lib = load(lib_path)
         self.params = dict(voxel_size=voxel_size, trunc=trunc, weighting=weighting,
                            merge=merge, w_max=w_max, max_range=max_range, z_min=z_min,
-                           storage=storage, dist=dist, world64=world64, full_ray=full_ray)
+                           storage=storage, dist=dist, world64=world64, full_ray=full_ray, color=color)
         p = _Params(voxel_size, trunc, w_max, max_range, z_min, WEIGHTING[weighting],
                     MERGE[merge], STORAGE[storage], DIST[dist], 1 if world64 else 0,
-                    1 if full_ray else 0)
+                    1 if full_ray else 0, 1 if color else 0)
         self._h = self.lib.orc_create(ctypes.byref(p))
 
     def close(self):
@@ -146,11 +152,17 @@ class OracleMap:
         except Exception:
             pass
 
-    def integrate(self, points: np.ndarray, pose: np.ndarray) -> dict:
+    def integrate(self, points: np.ndarray, pose: np.ndarray, colors: Optional[np.ndarray] = None) -> dict:
+        """colors: uint32 [n] RGBA8 (red in the low byte) for a colour map."""
         pts = np.ascontiguousarray(points, dtype=np.float32).reshape(-1, 3)
         ps = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
         st = _Stats()
-        self.lib.orc_integrate(self._h, _ptr(pts), pts.shape[0], _ptr(ps), ctypes.byref(st))
+        if colors is not None:
+            col = np.ascontiguousarray(colors, dtype=np.uint32).reshape(-1)
+            assert col.shape[0] == pts.shape[0]
+            self.lib.orc_integrate_color(self._h, _ptr(pts), _ptr(col), pts.shape[0], _ptr(ps), ctypes.byref(st))
+        else:
+            self.lib.orc_integrate(self._h, _ptr(pts), pts.shape[0], _ptr(ps), ctypes.byref(st))
         return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
 
     def integrate_projective(self, points: np.ndarray, pose: np.ndarray, width: int,
@@ -185,6 +197,13 @@ class OracleMap:
         if with_mass:
             self.lib.orc_export_ramp(self._h, _ptr(R), nb)
         return coords, D, W, M, R
+
+    def export_colors(self) -> np.ndarray:
+        """Packed RGB8 colours [B, 4096] (red in the low byte), in export()'s block order."""
+        nb = self.num_blocks()
+        rgb = np.zeros((nb, 4096), np.uint32)
+        self.lib.orc_export_color(self._h, _ptr(rgb), nb)
+        return rgb
 
     def last_touches(self):
         """Voxels touched by the last frame: (coords int32 [T,3], ray counts uint32 [T])."""

@@ -78,6 +78,7 @@ typedef struct {
     int dist;          /* 0: Eq. (1); 1: projective distance along the ray */
     int world64;       /* 1: distances from the binary64 world point (see the header) */
     int full_ray;      /* 1: a ray updates every voxel from the sensor to delta behind its point */
+    int color;         /* 1: points carry colours; each voxel keeps the weighted mean colour */
 } orc_params;
 
 typedef struct {
@@ -94,6 +95,8 @@ typedef struct {
     double ramp;            /* sum of the weights of rays seen on the Eq. (5) ramp (-delta < d <= -eps):
                                a diagnostic for comparisons, never part of D or W */
     double sw, swd;         /* this frame's sums */
+    double C[3];            /* colour (0..255 per channel, an integer after every frame) */
+    double swc[3];          /* this frame's sums of weight * ray colour */
     uint32_t n;             /* this frame's ray count */
     uint32_t stamp;         /* frame in which sw, swd, n were last reset */
 } orc_voxel;
@@ -280,6 +283,7 @@ typedef struct {
     float p32[3];     /* ray end point used for traversal and the sign of Eq. (1) */
     double p64[3];    /* ray end point used for distance values (binary64) */
     double wgt;       /* 1 or 1/z^2 for a point; the summed point weights for a group */
+    double col[3];    /* the point's colour, or the group's weighted mean colour (integers) */
 } orc_ray;
 
 static int weight_scale_bits(const orc_params* P) {
@@ -290,6 +294,12 @@ static int weight_scale_bits(const orc_params* P) {
     int c = 0;
     while (ldexpf(1.0f, c) < wmax) ++c;
     return 32 - c;
+}
+
+/* A point's integer weight in a group's exact means: Omega = rint(w 2^s), or 1 under constant
+   weighting. */
+static uint64_t group_weight(int wbits, float w) {
+    return wbits > 0 ? (uint64_t)rintf(ldexpf(w, wbits)) : 1u;
 }
 
 /*
@@ -310,7 +320,7 @@ void orc_group_mean(const float* p32, const float* w32, int n, float v, int wbit
     uint64_t so = 0;
     unsigned __int128 sq[3] = {0, 0, 0};
     for (int i = 0; i < n; ++i) {
-        uint64_t om = wbits > 0 ? (uint64_t)rintf(ldexpf(w32[i], wbits)) : 1u;
+        uint64_t om = group_weight(wbits, w32[i]);
         so += om;
         for (int k = 0; k < 3; ++k) {
             float f = p32[3 * i + k] * iv;
@@ -393,9 +403,18 @@ static int ray_segment(const orc_params* P, int whole, const float p[3], const f
 /* V5: the distance merged into D, clamped to +-delta. */
 static double clamp_distance(double d, double d64) { return d < -d64 ? -d64 : (d > d64 ? d64 : d); }
 
-/* V6/V8: one frame's update of a voxel by Eqs. (3)-(4), then the storage rounding. */
-static void fold_voxel(const orc_params* P, orc_voxel* vx, double sw, double swd) {
+/* Colour of a voxel: the running mean of its rays' colours with the weights of Eq. (3), blended
+   with the weight W the voxel held before the frame, stored as an integer per channel (8-bit
+   colour), rounded to nearest, ties to even. */
+static void fold_color(orc_voxel* vx, double sw, const double swc[3]) {
+    for (int k = 0; k < 3; ++k) vx->C[k] = nearbyint((vx->W * vx->C[k] + swc[k]) / (vx->W + sw));
+}
+
+/* V6/V8: one frame's update of a voxel by Eqs. (3)-(4), then the storage rounding; swc (NULL:
+   colour unchanged) the frame's colour sums of a colour map. */
+static void fold_voxel(const orc_params* P, orc_voxel* vx, double sw, double swd, const double* swc) {
     const double wmax = (double)P->w_max;
+    if (P->color && swc) fold_color(vx, sw, swc);
     vx->D = (vx->W * vx->D + swd) / (vx->W + sw);
     vx->W = vx->W + sw < wmax ? vx->W + sw : wmax;
     if (P->fp16) {
@@ -453,10 +472,12 @@ static void cast_ray(orc_map* m, const orc_ray* ray, const float s32[3], const d
         if (vx->stamp != m->frame + 1) {
             vx->stamp = m->frame + 1;
             vx->sw = 0.0; vx->swd = 0.0; vx->n = 0;
+            vx->swc[0] = vx->swc[1] = vx->swc[2] = 0.0;
             add_touch(m, pack3(g[0], g[1], g[2]));
         }
         vx->sw += w;
         vx->swd += w * (dc / d64);
+        for (int k = 0; k < 3; ++k) vx->swc[k] += w * ray->col[k];
         vx->n += 1;
         vx->mass += ray->wgt;
         if (P->weighting == 1 && d > -d64 && d <= -eps) vx->ramp += ray->wgt;
@@ -464,11 +485,29 @@ static void cast_ray(orc_map* m, const orc_ray* ray, const float s32[3], const d
     }
 }
 
+/* Exact mean colour of a group: round(sum Omega c / sum Omega) per channel, to nearest with ties
+   to even, in integer arithmetic. */
+static double group_color_channel(unsigned __int128 num, uint64_t den) {
+    const unsigned __int128 q = num / den, r = num - q * den;
+    unsigned __int128 c = q;
+    if (2 * r > (unsigned __int128)den || (2 * r == (unsigned __int128)den && (q & 1))) c = q + 1;
+    return (double)(uint64_t)c;
+}
+
 /*
  * Integrates one frame: points[n][3] in the sensor frame (NaN marks an invalid
- * point), pose[12] = row-major 3x4 T_world_sensor.  Returns 0.
+ * point), pose[12] = row-major 3x4 T_world_sensor, colors[n] (RGBA8, red in the low byte;
+ * NULL: black) for a colour map.  Returns 0.
  */
+int orc_integrate_color(orc_map* m, const float* pts, const uint32_t* colors, size_t n, const float pose[12],
+                        orc_stats* out);
+
 int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], orc_stats* out) {
+    return orc_integrate_color(m, pts, NULL, n, pose, out);
+}
+
+int orc_integrate_color(orc_map* m, const float* pts, const uint32_t* colors, size_t n, const float pose[12],
+                        orc_stats* out) {
     const orc_params* P = &m->P;
     orc_stats st;
     memset(&st, 0, sizeof st);
@@ -521,6 +560,8 @@ int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], 
                 rays[nr].p64[k] = P->world64 ? p64[3 * i + k] : (double)p32[3 * i + k];
             }
             rays[nr].wgt = w64[i];
+            for (int k = 0; k < 3; ++k)
+                rays[nr].col[k] = colors ? (double)((colors[valid[i]] >> (8 * k)) & 255u) : 0.0;
             nr++;
         }
     } else {
@@ -547,6 +588,17 @@ int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], 
                 for (int k = 0; k < 3; ++k) sp[k] += w64[i] * p64[3 * i + k];
             }
             orc_group_mean(gp, gw, cnt, v, wbits, rays[nr].p32);
+            /* the group's colour: its points' colours weighted as in the mean position */
+            unsigned __int128 cs[3] = {0, 0, 0};
+            uint64_t cso = 0;
+            for (size_t j = lo; j < hi; ++j) {
+                const uint32_t i = ki[j].idx;
+                const uint64_t om = group_weight(wbits, w32[i]);
+                const uint32_t c = colors ? colors[valid[i]] : 0u;
+                cso += om;
+                for (int k = 0; k < 3; ++k) cs[k] += (unsigned __int128)om * ((c >> (8 * k)) & 255u);
+            }
+            for (int k = 0; k < 3; ++k) rays[nr].col[k] = group_color_channel(cs[k], cso);
             for (int k = 0; k < 3; ++k) {
                 if (P->world64) rays[nr].p64[k] = cnt == 1 ? p64[3 * ki[lo].idx + k] : sp[k] / sw;
                 else rays[nr].p64[k] = (double)rays[nr].p32[k];
@@ -575,7 +627,7 @@ int orc_integrate(orc_map* m, const float* pts, size_t n, const float pose[12], 
         table_get(&m->blocks, pack3(block_of(g[0]), block_of(g[1]), block_of(g[2])), 1, &created);
         st.new_blocks += (uint64_t)created;
         m->touch_n[t] = vx->n;
-        if (vx->sw > 0.0) fold_voxel(P, vx, vx->sw, vx->swd);
+        if (vx->sw > 0.0) fold_voxel(P, vx, vx->sw, vx->swd, vx->swc);
     }
     st.voxels = m->n_touch;
     m->frame++;
@@ -698,7 +750,7 @@ int orc_integrate_projective(orc_map* m, const float* pts, size_t n, uint32_t wi
             vx->mass += wgt;
             if (P->weighting == 1 && d > -d64 && d <= -eps) vx->ramp += wgt;
             st.touches++;
-            if (w > 0.0) fold_voxel(P, vx, w, w * (dc / d64));
+            if (w > 0.0) fold_voxel(P, vx, w, w * (dc / d64), NULL);   /* colour: raycasting only */
         }
     }
     st.voxels = m->n_touch;
@@ -769,6 +821,31 @@ size_t orc_export_ramp(const orc_map* m, double* ramp, size_t cap) {
             int32_t g0 = 16 * bc[0] + (l & 15), g1 = 16 * bc[1] + ((l >> 4) & 15), g2 = 16 * bc[2] + (l >> 8);
             const orc_voxel* vx = (const orc_voxel*)table_get((orc_table*)&m->vox, pack3(g0, g1, g2), 0, NULL);
             ramp[b * 4096 + (size_t)l] = vx ? vx->ramp : 0.0;
+        }
+    }
+    free(keys);
+    return nb;
+}
+
+/* Colours of every voxel in orc_export's order, packed RGB8 (red in the low byte; 0 where the
+   voxel was never observed).  Returns the number of blocks. */
+size_t orc_export_color(const orc_map* m, uint32_t* rgb, size_t cap) {
+    size_t nb = m->blocks.size;
+    uint64_t* keys = (uint64_t*)malloc((nb + 1) * sizeof(uint64_t));
+    size_t j = 0;
+    for (size_t i = 0; i < m->blocks.cap; ++i)
+        if (m->blocks.keys[i]) keys[j++] = m->blocks.keys[i] - 1;
+    qsort(keys, nb, sizeof(uint64_t), cmp_u64);
+    for (size_t b = 0; b < nb && b < cap; ++b) {
+        int32_t bc[3];
+        unpack3(keys[b], &bc[0], &bc[1], &bc[2]);
+        for (int l = 0; l < 4096; ++l) {
+            int32_t g0 = 16 * bc[0] + (l & 15), g1 = 16 * bc[1] + ((l >> 4) & 15), g2 = 16 * bc[2] + (l >> 8);
+            const orc_voxel* vx = (const orc_voxel*)table_get((orc_table*)&m->vox, pack3(g0, g1, g2), 0, NULL);
+            uint32_t c = 0;
+            if (vx)
+                for (int k = 0; k < 3; ++k) c |= (uint32_t)vx->C[k] << (8 * k);
+            rgb[b * 4096 + (size_t)l] = c;
         }
     }
     free(keys);

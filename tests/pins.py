@@ -324,6 +324,68 @@ def pin_projective_plane(lib_path=None):
         m.close(); ray.close()
 
 
+def _rgb(r, g, b):
+    return np.uint32(r | (g << 8) | (b << 16))
+
+
+def _round_half_even(x: Fr) -> int:
+    return round(x)          # Python rounds fractions half to even
+
+
+def pin_color_sequence(lib_path=None):
+    """Colour (Sec. IV-B): each voxel keeps the running mean of its rays' colours with the
+    weights of Eq. (3), blended with the weight it held before the frame and stored as 8-bit
+    channels (nearest, ties to even).  One ray per frame on the head-on axis, the same depth
+    every frame (so each voxel's weight is the same every frame and cancels): C_1 = c_1,
+    C_(k+1) = round((k C_k + c_(k+1)) / (k + 1)); 15.5 rounds to 16 and 16.5 to 16."""
+    cols = [(10, 200, 7), (21, 100, 8), (23, 0, 255), (2, 33, 254)]
+    for weighting in ("const", "quad"):
+        pose = _axis_pose(2, 1)
+        m = oracle.OracleMap(V, DELTA, weighting=weighting, merge="simple", w_max=1e30,
+                             max_range=10.0, color=True, lib_path=lib_path)
+        C = None
+        for k, c in enumerate(cols):
+            m.integrate(np.array([[0.0, 0.0, 1.3125]], np.float32), pose, colors=np.array([_rgb(*c)]))
+            C = list(c) if C is None else [_round_half_even((k * Fr(C[i]) + c[i]) / (k + 1)) for i in range(3)]
+            if k == 1:
+                assert C[0] == 16, "15.5 rounds to the even 16"
+            if k == 2:
+                assert C[0] == 18
+        exp = head_on_expectation(1.3125, 2, 1, weighting, len(cols), pose)
+        coords = m.export()[0]
+        rgb = m.export_colors()
+        got = {}
+        for b in range(coords.shape[0]):
+            for l in range(4096):
+                g = (16 * coords[b, 0] + (l & 15), 16 * coords[b, 1] + ((l >> 4) & 15), 16 * coords[b, 2] + (l >> 8))
+                got[g] = int(rgb[b, l])
+        want = int(_rgb(*C))
+        for g, (_, W) in exp.items():
+            assert got[g] == (want if W > 0 else 0), f"colour at {g}: {got[g]:06x} vs {want:06x}"
+        m.close()
+
+
+def pin_color_group_mean(lib_path=None):
+    """Grouped raycasting takes the weighted mean of the points' colours in a voxel (Sec. IV-B),
+    rounded to 8 bits (nearest, ties to even): points at one depth (equal weights) in one voxel;
+    every voxel the group's ray updates first takes exactly that colour."""
+    pose = _axis_pose(2, 1)
+    xs = np.array([-0.0625, -0.03125, 0.0, 0.03125], np.float32)   # one voxel (v = 0.125)
+    for weighting, cols, mean in [("const", [(10, 0, 1), (23, 4, 1)], (16, 2, 1)),
+                                  ("quad", [(10, 9, 0), (23, 9, 0), (12, 9, 255), (100, 9, 255)], (36, 9, 128)),
+                                  ("const", [(1, 2, 3)], (1, 2, 3))]:
+        m = oracle.OracleMap(V, DELTA, weighting=weighting, merge="grouped", w_max=1e30,
+                             max_range=10.0, color=True, lib_path=lib_path)
+        n = len(cols)
+        pts = np.stack([xs[:n], np.zeros(n, np.float32), np.full(n, 1.3125, np.float32)], axis=1)
+        st = m.integrate(pts, pose, colors=np.array([_rgb(*c) for c in cols]))
+        assert st["rays"] == 1
+        rgb = m.export_colors()
+        W = m.export()[2]
+        assert np.all(rgb[W > 0] == _rgb(*mean)) and np.all(rgb[W == 0] == 0)
+        m.close()
+
+
 def pin_dropoff_values(lib_path=None):
     """Eq. (5) at the distances where it changes form: d > -eps full weight, d = -(eps+delta)/2
     half weight, d <= -delta zero weight (W stays 0 while the block is still allocated)."""
@@ -811,7 +873,7 @@ def pin_permutation(lib_path=None, seed=9):
 
 
 ALL_PINS = [pin_dda_dyadic, pin_dda_random, pin_head_on_plane, pin_full_ray_head_on, pin_projective_plane,
-            pin_dropoff_values,
+            pin_color_sequence, pin_color_group_mean, pin_dropoff_values,
             pin_along_ray_off_axis, pin_binary16_sequence, pin_s16_sequence, pin_ramp_diagnostic,
             pin_weight_sums, pin_group_mean, pin_merged_singletons, pin_identical_points,
             pin_running_average, pin_validity, pin_round_half, pin_permutation]

@@ -27,8 +27,7 @@ MUTATIONS = {
                                "vx->D = (vx->D + swd) / (vx->W + sw);"),
     "rotation_transposed": ("q[k] = ((pose[4 * k] * x + pose[4 * k + 1] * y) + pose[4 * k + 2] * z) + pose[4 * k + 3];",
                             "q[k] = ((pose[k] * x + pose[4 + k] * y) + pose[8 + k] * z) + pose[4 * k + 3];"),
-    "group_mean_unweighted": ("uint64_t om = wbits > 0 ? (uint64_t)rintf(ldexpf(w32[i], wbits)) : 1u;",
-                              "uint64_t om = 1u;"),
+    "group_mean_unweighted": ("return wbits > 0 ? (uint64_t)rintf(ldexpf(w, wbits)) : 1u;", "return 1u;"),
     "no_band_behind_surface": ("float t1 = r + delta;", "float t1 = r;"),
     "no_distance_clamp": ("return d < -d64 ? -d64 : (d > d64 ? d64 : d);", "return d;"),
     "corner_not_centre": ("double x = ((double)g[k] + 0.5) * v64;\n                double f = ray->p64[k] - x;",
@@ -62,6 +61,15 @@ MUTATIONS = {
     "ramp_counts_dropped_weight": ("vx->ramp += ray->wgt;", "vx->ramp += w;"),
     # the whole-ray update (Sec. IV-B)
     "full_ray_ignored": ("float t0 = whole ? 0.0f : r - delta;", "float t0 = r - delta;"),
+    # colour (Sec. IV-B): running mean with the old weight, 8-bit storage, grouped mean colour
+    "color_drops_old_weight": ("nearbyint((vx->W * vx->C[k] + swc[k]) / (vx->W + sw))",
+                               "nearbyint((vx->C[k] + swc[k]) / (1.0 + sw))"),
+    "color_truncates": ("nearbyint((vx->W * vx->C[k] + swc[k]) / (vx->W + sw))",
+                        "floor((vx->W * vx->C[k] + swc[k]) / (vx->W + sw))"),
+    "group_color_ties_up": ("if (2 * r > (unsigned __int128)den || (2 * r == (unsigned __int128)den && (q & 1))) c = q + 1;",
+                            "if (2 * r >= (unsigned __int128)den) c = q + 1;"),
+    "group_color_first_point": ("for (int k = 0; k < 3; ++k) rays[nr].col[k] = group_color_channel(cs[k], cso);",
+                                "for (int k = 0; k < 3; ++k) rays[nr].col[k] = (double)(((colors ? colors[valid[ki[lo].idx]] : 0u) >> (8 * k)) & 255u);"),
     # projection mapping (Sec. IV-B)
     "projective_pixel_rounded": ("const size_t pix = (size_t)floorf(uf) + (size_t)width * (size_t)floorf(vf);",
                                  "const size_t pix = (size_t)rintf(uf) + (size_t)width * (size_t)rintf(vf);"),
@@ -75,7 +83,7 @@ MUTATIONS = {
 }
 
 FAST_FIRST = [pins.pin_head_on_plane, pins.pin_full_ray_head_on, pins.pin_projective_plane, pins.pin_dropoff_values,
-              pins.pin_running_average,
+              pins.pin_running_average, pins.pin_color_sequence, pins.pin_color_group_mean,
               pins.pin_along_ray_off_axis, pins.pin_binary16_sequence, pins.pin_s16_sequence,
               pins.pin_ramp_diagnostic,
               pins.pin_validity, pins.pin_identical_points, pins.pin_merged_singletons,
