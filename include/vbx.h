@@ -75,7 +75,17 @@ enum {
      * raycasting of Sec. IV-B, which carves the free space in front of the surface), instead of
      * the truncation band [r - trunc, r + trunc] alone.  Needs (max_range + trunc) / voxel_size
      * <= 1024 (VBX_ERR_LIMIT otherwise). */
-    VBX_FLAG_FULL_RAY = 2u
+    VBX_FLAG_FULL_RAY = 2u,
+    /* The map keeps a colour per voxel (Sec. IV-B: each grouped ray carries the mean colour of
+     * its points), 4 more bytes per voxel.  Raycasting frames of such a map must carry colours
+     * (vbx_frame.colors).  Per voxel and frame, with w_i the observation weights of the frame's
+     * rays through the voxel and c_i their colours, and W the voxel's weight before the frame:
+     *   C <- round((W C + sum w_i c_i) / (W + sum w_i))  per 8-bit channel (nearest, ties even).
+     * A grouped ray's colour is round(sum Omega c / sum Omega) over its points (Omega the
+     * points' fixed-point weights of the group mean), computed in integers.  Projection mapping
+     * leaves colours unchanged.  New voxels and imported blocks start black; blocks that
+     * vbx_write_blocks overwrites in place keep their colours. */
+    VBX_FLAG_COLOR = 4u
 };
 
 /* Limits */
@@ -117,6 +127,8 @@ typedef struct {
                             Only a locality hint for grouping: results do not depend on it. */
     uint32_t reserved;
     float pose[12];      /* row-major 3x4 T_world_sensor; the sensor origin is its last column */
+    const uint32_t* colors; /* dev [n] RGBA8 per point, red in the low byte (alpha unused), for maps
+                               with VBX_FLAG_COLOR; NULL otherwise (ignored by other maps) */
 } vbx_frame;
 
 typedef struct {
@@ -262,6 +274,12 @@ int vbx_export_blocks(vbx_map* map, int32_t* coords, float* dw, size_t cap, size
  * host [n][4096][2], D in metres) — the inverse of vbx_export_blocks (checkpoint / resume).  Values
  * are rounded to the map's storage type.  Synchronises. */
 int vbx_import_blocks(vbx_map* map, const int32_t* coords, const float* dw, size_t n);
+
+/* Exports the voxel colours of a VBX_FLAG_COLOR map (Sec. IV-B), in vbx_export_blocks' block order
+ * (synchronises): coords host [cap][3] block indices or NULL; colors host [cap][4096] packed RGB8
+ * (red in the low byte, top byte 0; voxel l of a block is (l & 15, (l >> 4) & 15, l >> 8)) or
+ * NULL.  VBX_ERR_INVALID_ARG for a map without colour; VBX_ERR_BUFFER_TOO_SMALL as above. */
+int vbx_export_colors(vbx_map* map, int32_t* coords, uint32_t* colors, size_t cap, size_t* n_out);
 
 /* Touched voxels of the last integration call (requires VBX_FLAG_KEEP_TOUCHES):
  * coords host [cap][3] voxel indices and counts host [cap] (rays that visited the

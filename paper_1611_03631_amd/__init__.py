@@ -28,6 +28,7 @@ F32, F16, S16 = 0, 1, 2
 DIST_EQ1, DIST_ALONG_RAY = 0, 1
 FLAG_KEEP_TOUCHES = 1
 FLAG_FULL_RAY = 2
+FLAG_COLOR = 4
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "block pool full",
           -4: "buffer too small", -5: "device error", -6: "limit exceeded"}
@@ -68,7 +69,7 @@ class EsdfStats(ctypes.Structure):
 
 class Frame(ctypes.Structure):
     _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_uint64), ("width", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("pose", ctypes.c_float * 12)]
+                ("reserved", ctypes.c_uint32), ("pose", ctypes.c_float * 12), ("colors", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -80,7 +81,7 @@ class Stats(ctypes.Structure):
 EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_map_destroy",
             "vbx_map_set_stream", "vbx_integrate", "vbx_integrate_batch", "vbx_integrate_frames",
             "vbx_integrate_frames_noalloc", "vbx_integrate_projective", "vbx_write_blocks", "vbx_esdf_enable", "vbx_esdf_update",
-            "vbx_esdf_export",
+            "vbx_esdf_export", "vbx_export_colors",
             "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
             "vbx_map_stats", "vbx_map_interpolate", "vbx_debug_traverse", "vbx_status_string",
@@ -161,6 +162,7 @@ def lib(path: Optional[str] = None):
     L.vbx_esdf_enable.argtypes = [vp, ctypes.POINTER(EsdfParams)]
     L.vbx_esdf_update.argtypes = [vp, ctypes.POINTER(EsdfStats)]
     L.vbx_esdf_export.argtypes = [vp, vp, vp, vp, sz, ctypes.POINTER(sz)]
+    L.vbx_export_colors.argtypes = [vp, vp, vp, sz, ctypes.POINTER(sz)]
     L.vbx_last_touches.argtypes = [vp, vp, vp, sz, ctypes.POINTER(sz)]
     L.vbx_map_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.vbx_debug_traverse.argtypes = [vp, vp, i32, vp, i32, vp]
@@ -232,7 +234,7 @@ _DIST = {"eq1": DIST_EQ1, "ray": DIST_ALONG_RAY}
 def map_params(voxel_size: float, trunc: float, weighting: str = "const", merge: str = "simple",
                storage: str = "f32", w_max: float = 1e4, max_range: float = 5.0, z_min: float = 0.1,
                dist: str = "eq1", block_capacity: int = 65536, keep_touches: bool = False,
-               stream_handle: int = 0, full_ray: bool = False) -> MapParams:
+               stream_handle: int = 0, full_ray: bool = False, color: bool = False) -> MapParams:
     p = MapParams()
     lib().vbx_default_params(ctypes.byref(p))
     p.voxel_size, p.trunc, p.w_max = voxel_size, trunc, w_max
@@ -240,7 +242,8 @@ def map_params(voxel_size: float, trunc: float, weighting: str = "const", merge:
     p.weighting, p.merge = _WEIGHTING[weighting], _MERGE[merge]
     p.storage, p.dist = _STORAGE[storage], _DIST[dist]
     p.block_capacity = block_capacity
-    p.flags = (FLAG_KEEP_TOUCHES if keep_touches else 0) | (FLAG_FULL_RAY if full_ray else 0)
+    p.flags = ((FLAG_KEEP_TOUCHES if keep_touches else 0) | (FLAG_FULL_RAY if full_ray else 0) |
+               (FLAG_COLOR if color else 0))
     p.stream = stream_handle
     return p
 
@@ -252,15 +255,16 @@ class Map:
                  merge: str = "simple", storage: str = "f32", w_max: float = 1e4,
                  max_range: float = 5.0, z_min: float = 0.1, dist: str = "eq1",
                  block_capacity: int = 65536, keep_touches: bool = False, stream=None,
-                 allocator=None, full_ray: bool = False):
+                 allocator=None, full_ray: bool = False, color: bool = False):
         """allocator: optional (alloc, free) pair of callables, alloc(nbytes) -> device address
         (0 when it cannot) and free(address), used for the map's hash table, block pool and
-        device state instead of hipMalloc / hipFree."""
+        device state instead of hipMalloc / hipFree.  color: the map keeps a colour per voxel
+        and raycasting frames carry one per point (the fourth element of a frame tuple)."""
         L = lib()
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
         p = map_params(voxel_size, trunc, weighting, merge, storage, w_max, max_range, z_min, dist,
-                       block_capacity, keep_touches, s.cuda_stream, full_ray)
+                       block_capacity, keep_touches, s.cuda_stream, full_ray, color)
         self._hooks = None
         if allocator is not None:
             a_py, f_py = allocator
@@ -274,7 +278,7 @@ class Map:
         self._owned = True
         self.params = dict(voxel_size=voxel_size, trunc=trunc, weighting=weighting, merge=merge,
                            storage=storage, w_max=w_max, max_range=max_range, z_min=z_min,
-                           dist=dist, block_capacity=block_capacity, full_ray=full_ray)
+                           dist=dist, block_capacity=block_capacity, full_ray=full_ray, color=color)
 
     @classmethod
     def _borrowed(cls, handle, params: dict, owner):
@@ -319,7 +323,9 @@ class Map:
         return out
 
     def integrate_frames(self, frames: Sequence[Tuple]):
-        """frames: sequence of (points tensor [N,3], pose [3,4]) or (points, pose, width)."""
+        """frames: sequence of (points tensor [N,3], pose [3,4]), (points, pose, width) or
+        (points, pose, width, colors) with colors a device int32 / uint32 tensor [N] of RGBA8
+        (red in the low byte)."""
         arr = make_frames(frames)
         _check(lib().vbx_integrate_frames(self._h, arr, len(frames)), "vbx_integrate_frames")
 
@@ -374,6 +380,18 @@ class Map:
         _check(L.vbx_export_blocks(self._h, coords.ctypes.data, dw.ctypes.data, B, ctypes.byref(n)),
                "vbx_export_blocks")
         return coords, dw
+
+    def export_colors(self):
+        """(coords int32 [B,3] ascending, packed RGB8 uint32 [B,4096]) of a colour map."""
+        L = lib()
+        n = ctypes.c_size_t()
+        _check(L.vbx_export_colors(self._h, None, None, 0, ctypes.byref(n)), "vbx_export_colors")
+        B = int(n.value)
+        coords = np.zeros((B, 3), np.int32)
+        rgb = np.zeros((B, 4096), np.uint32)
+        _check(L.vbx_export_colors(self._h, coords.ctypes.data, rgb.ctypes.data, B, ctypes.byref(n)),
+               "vbx_export_colors")
+        return coords, rgb
 
     def write_blocks(self, coords: np.ndarray, dw: np.ndarray):
         """Writes TSDF blocks (coords [B,3], dw [B,4096,2], D in metres) in place, allocating the
@@ -486,11 +504,16 @@ def make_frames(frames) -> ctypes.Array:
     arr = (Frame * len(frames))()
     for i, f in enumerate(frames):
         pts, pose = f[0], f[1]
-        width = int(f[2]) if len(f) > 2 else 0
+        width = int(f[2]) if len(f) > 2 and f[2] is not None else 0
         ptr, n = _dev_points(pts)
         arr[i].points = ptr
         arr[i].n = n
         arr[i].width = width
+        if len(f) > 3 and f[3] is not None:
+            col = f[3]
+            if not (col.is_cuda and col.is_contiguous() and col.element_size() == 4 and col.numel() == n):
+                raise ValueError("colors: a contiguous device tensor of 4-byte words, one per point")
+            arr[i].colors = col.data_ptr() if n else None
         pz = _pose12(pose)
         for k in range(12):
             arr[i].pose[k] = float(pz[k])

@@ -60,6 +60,7 @@ struct Stage {
 struct Scratch {
     DevBuf rays_p, rays_job, cross, ncross, sorted, tkeys, tval, tlist, t_key, t_slot, order, bins, off,
         partial, parts, parts_sorted, tile_parts, chunk_first, touch_key, touch_n, tables, jst, cs;
+    DevBuf rays_c, sorted_c, parts_c, parts_sorted_c;   // colour calls: the colours beside the rays
     size_t ray_cap = 0, cross_cap = 0, tkey_cap = 0, tlist_cap = 0, bins_cap = 0, nparts = 0,
            touch_cap = 0;
     Stage stage[4];
@@ -119,6 +120,7 @@ struct vbx_map {
     int* hslots = nullptr;        // device
     u32 hcap = 0;
     void* pool = nullptr;         // device
+    u32* color = nullptr;         // device, VBX_FLAG_COLOR: [capacity][4096] packed RGB8
     u32 capacity = 0;
     size_t voxel_bytes = 8;
     int wbits = 0;
@@ -252,6 +254,7 @@ MapDesc make_desc(const vbx_map* m, int map_id, int job0, int njobs) {
     d.dirty = m->esdf ? m->esdf->dirty : nullptr;
     d.full_ray = (P.flags & VBX_FLAG_FULL_RAY) ? 1 : 0;
     d.max_steps = max_voxels_per_ray(P) + 1;
+    d.color = m->color;
     return d;
 }
 
@@ -283,6 +286,13 @@ int alloc_storage(vbx_map* m, u32 capacity) {
     if (map_alloc(m, (void**)&m->hslots, sizeof(int) * m->hcap) != VBX_OK) return VBX_ERR_OUT_OF_MEMORY;
     if (map_alloc(m, &m->pool, (size_t)capacity * 4096 * m->voxel_bytes) != VBX_OK)
         return VBX_ERR_OUT_OF_MEMORY;
+    if (m->P.flags & VBX_FLAG_COLOR) {
+        if (map_alloc(m, (void**)&m->color, (size_t)capacity * 4096 * sizeof(u32)) != VBX_OK)
+            return VBX_ERR_OUT_OF_MEMORY;
+        // a slot's colour starts black: only the colour kernel writes it afterwards
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((size_t)capacity * 4096, 8192)), dim3(256), 0, m->stream,
+                           m->color, 0u, (size_t)capacity * 4096);
+    }
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(m->hcap)), dim3(256), 0, m->stream, m->hkeys, kEmpty,
                        (size_t)m->hcap);
     return hipGetLastError() == hipSuccess ? VBX_OK : VBX_ERR_DEVICE;
@@ -292,9 +302,18 @@ void free_storage(vbx_map* m) {
     map_free(m, m->hkeys);
     map_free(m, m->hslots);
     map_free(m, m->pool);
+    map_free(m, m->color);
     m->hkeys = nullptr;
     m->hslots = nullptr;
     m->pool = nullptr;
+    m->color = nullptr;
+}
+
+// Colour maps: every slot back to black (after the map's blocks were replaced or dropped).
+void clear_colors(vbx_map* m) {
+    if (!m->color) return;
+    const size_t n = (size_t)m->capacity * 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 8192)), dim3(256), 0, m->stream, m->color, 0u, n);
 }
 
 void free_scratch(Scratch* s) {
@@ -302,7 +321,8 @@ void free_scratch(Scratch* s) {
     DevBuf* bufs[] = {&s->rays_p, &s->rays_job, &s->cross, &s->ncross, &s->sorted, &s->tkeys,
                       &s->tval, &s->tlist, &s->t_key, &s->t_slot, &s->order, &s->bins, &s->off, &s->partial,
                       &s->parts, &s->parts_sorted, &s->tile_parts, &s->chunk_first, &s->touch_key, &s->touch_n,
-                      &s->tables, &s->jst, &s->cs};
+                      &s->tables, &s->jst, &s->cs, &s->rays_c, &s->sorted_c, &s->parts_c,
+                      &s->parts_sorted_c};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (Stage& st : s->stage) {
@@ -325,6 +345,7 @@ struct CallPlan {
     u32 tiles_per_job = 0;      // every job has this many tiles and there is one map (else 0)
     bool projective = false;    // projection mapping instead of raycasting the voxels
     Intrinsics K = {};          // its camera intrinsics
+    bool color = false;         // a map of the call keeps colour: the rays carry colours
 };
 
 // Element counts of a call's scratch buffers (host upper bounds: nothing is read back mid-call).
@@ -372,6 +393,14 @@ void for_each_scratch(Scratch* s, const CallPlan& plan, const ScratchSizes& z, i
         f(s->parts_sorted, z.ray_cap * sizeof(Partial));
         f(s->tile_parts, std::max<size_t>(plan.tiles, 1) * sizeof(u32));
         f(s->chunk_first, (z.ray_cap / kMergeSpan + 2) * sizeof(u32));
+    }
+    if (plan.color) {
+        f(s->rays_c, z.ray_cap * sizeof(u32));
+        f(s->sorted_c, z.cross_cap * sizeof(u32));
+        if (plan.grouped) {
+            f(s->parts_c, z.ray_cap * sizeof(PartialColor));
+            f(s->parts_sorted_c, z.ray_cap * sizeof(PartialColor));
+        }
     }
     if (plan.keep_touches) {
         f(s->touch_key, z.touch_cap * sizeof(u64));
@@ -442,6 +471,14 @@ int ensure_scratch(Scratch* s, hipStream_t st, const CallPlan& plan, int njobs, 
         GROW(s->tile_parts, std::max<size_t>(plan.tiles, 1) * sizeof(u32));
         GROW(s->chunk_first, (ray_cap / kMergeSpan + 2) * sizeof(u32));
     }
+    if (plan.color) {
+        GROW(s->rays_c, ray_cap * sizeof(u32));
+        GROW(s->sorted_c, cross_cap * sizeof(u32));
+        if (plan.grouped) {
+            GROW(s->parts_c, ray_cap * sizeof(PartialColor));
+            GROW(s->parts_sorted_c, ray_cap * sizeof(PartialColor));
+        }
+    }
     if (plan.keep_touches) {
         GROW(s->touch_key, touch_cap * sizeof(u64));
         GROW(s->touch_n, touch_cap * sizeof(u32));
@@ -472,7 +509,7 @@ int group_merge_grid() {
         int dev = 0, cus = 256, per = 1;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_group_merge), 256, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_group_merge<false>), 256, 0) !=
                 hipSuccess || per < 1)
             per = 1;
         grid = cus * per;
@@ -667,6 +704,7 @@ int prepare_call(const std::vector<vbx_map*>& maps, const std::vector<vbx_frame>
         plan.max_blocks = std::max(plan.max_blocks, max_blocks_per_ray(P));
         plan.max_vox = std::max(plan.max_vox, max_voxels_per_ray(P));
         plan.keep_touches = plan.keep_touches || (P.flags & VBX_FLAG_KEEP_TOUCHES);
+        plan.color = plan.color || (!projective && (P.flags & VBX_FLAG_COLOR));
         out.sum_capacity += maps[m]->capacity;
     }
     plan.grouped = lead->P.merge == VBX_MERGE_GROUPED;
@@ -693,7 +731,11 @@ int prepare_call(const std::vector<vbx_map*>& maps, const std::vector<vbx_frame>
             if (fr.width > 0 && fr.n % fr.width != 0) return VBX_ERR_INVALID_ARG;
             for (int q = 0; q < 12; ++q)
                 if (!std::isfinite(fr.pose[q])) return VBX_ERR_INVALID_ARG;
+            // a colour map's raycasting frames carry a colour per point
+            if (plan.color && (maps[m]->P.flags & VBX_FLAG_COLOR) && fr.n > 0 && !fr.colors)
+                return VBX_ERR_INVALID_ARG;
             j.pts = fr.points;
+            j.colors = plan.color ? fr.colors : nullptr;
             j.n = (u32)fr.n;
             j.width = fr.width;
             j.map = (u32)m;
@@ -813,6 +855,10 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     JobStat* jst = (JobStat*)s->jst.p;
     float4* rays_p = (float4*)s->rays_p.p;
     u32* rays_job = (u32*)s->rays_job.p;
+    u32* rays_c = plan.color ? (u32*)s->rays_c.p : nullptr;
+    u32* sorted_c = plan.color ? (u32*)s->sorted_c.p : nullptr;
+    const PartialColor* parts_c = plan.color ? (const PartialColor*)s->parts_c.p : nullptr;
+    PartialColor* parts_sorted_c = plan.color ? (PartialColor*)s->parts_sorted_c.p : nullptr;
     const u32 ray_cap = (u32)s->ray_cap;
     const u32 total_tiles = plan.tiles;
 
@@ -832,11 +878,17 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
         StageTimer tm(prof_map, st, ST_POINTS);
         if (!plan.grouped) {
             hipLaunchKernelGGL(k_points_simple, dim3(total_tiles), dim3(256), 0, st, d_jobs, J, d_maps, rays_p,
-                               rays_job, jst, cs);
-        } else {
-            hipLaunchKernelGGL(k_points_grouped, dim3(total_tiles), dim3(256), 0, st, d_jobs, J, d_maps,
+                               rays_job, rays_c, jst, cs);
+        } else if (!plan.color) {
+            hipLaunchKernelGGL(k_points_grouped<false>, dim3(total_tiles), dim3(256), 0, st, d_jobs, J, d_maps,
                                (u64*)s->tkeys.p, (u32)(s->tkey_cap - 1), (u32*)s->tlist.p, (u32)s->tlist_cap,
-                               (Partial*)s->parts.p, (u32*)s->tile_parts.p, plan.tiles_per_job, jst, cs);
+                               (Partial*)s->parts.p, (PartialColor*)nullptr, (u32*)s->tile_parts.p,
+                               plan.tiles_per_job, jst, cs);
+        } else {
+            hipLaunchKernelGGL(k_points_grouped<true>, dim3(total_tiles), dim3(256), 0, st, d_jobs, J, d_maps,
+                               (u64*)s->tkeys.p, (u32)(s->tkey_cap - 1), (u32*)s->tlist.p, (u32)s->tlist_cap,
+                               (Partial*)s->parts.p, (PartialColor*)s->parts_c.p, (u32*)s->tile_parts.p,
+                               plan.tiles_per_job, jst, cs);
         }
     }
     if (plan.grouped && total_tiles > 0) {
@@ -852,11 +904,18 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
         scan_bins(JMS, (u32*)s->chunk_first.p);
         hipLaunchKernelGGL(k_gscatter, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
                            (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p,
-                           (const u32*)s->off.p, JM, tpw, (Partial*)s->parts_sorted.p, (const CallState*)cs);
-        hipLaunchKernelGGL(k_group_merge, dim3(group_merge_grid()), dim3(256), 0, st, d_jobs, d_maps,
-                           (const u64*)s->tkeys.p, (const u32*)s->tlist.p, (const u32*)s->off.p,
-                           (const u32*)s->chunk_first.p, (const Partial*)s->parts_sorted.p, JMS, rays_p,
-                           rays_job, jst, cs);
+                           (const u32*)s->off.p, JM, tpw, (Partial*)s->parts_sorted.p, parts_c, parts_sorted_c,
+                           (const CallState*)cs);
+        if (!plan.color)
+            hipLaunchKernelGGL(k_group_merge<false>, dim3(group_merge_grid()), dim3(256), 0, st, d_jobs, d_maps,
+                               (const u64*)s->tkeys.p, (const u32*)s->tlist.p, (const u32*)s->off.p,
+                               (const u32*)s->chunk_first.p, (const Partial*)s->parts_sorted.p, JMS,
+                               (const PartialColor*)nullptr, rays_p, rays_job, (u32*)nullptr, jst, cs);
+        else
+            hipLaunchKernelGGL(k_group_merge<true>, dim3(group_merge_grid()), dim3(256), 0, st, d_jobs, d_maps,
+                               (const u64*)s->tkeys.p, (const u32*)s->tlist.p, (const u32*)s->off.p,
+                               (const u32*)s->chunk_first.p, (const Partial*)s->parts_sorted.p, JMS,
+                               (const PartialColor*)parts_sorted_c, rays_p, rays_job, rays_c, jst, cs);
     }
     const unsigned G = grid_for(plan.ray_slots, 2048);
     const u32 MB = (u32)plan.max_blocks;
@@ -910,14 +969,26 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     StageTimer tm(prof_map, st, ST_SCATTER);
     hipLaunchKernelGGL(k_scatter, dim3(G), dim3(256), 0, st, d_jobs, (const u32*)s->cross.p,
                        (const unsigned char*)s->ncross.p, MB, (const u32*)s->tval.p, (const u32*)rays_job,
-                       (u32*)s->bins.p, (const u32*)s->off.p, JM, (const float4*)rays_p, (float4*)s->sorted.p, cs,
-                       ray_cap);
+                       (u32*)s->bins.p, (const u32*)s->off.p, JM, (const float4*)rays_p, (float4*)s->sorted.p,
+                       (const u32*)rays_c, sorted_c, cs, ray_cap);
     }
     if (plan.keep_touches) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, &cs->touch_count, 0u);
     {
     StageTimer tm(prof_map, st, ST_UPDATE);
     hipLaunchKernelGGL(k_order_blocks, dim3(1), dim3(1024), 0, st, (const u32*)s->off.p, JM, (u32*)s->order.p,
                        (const CallState*)cs);
+    if (plan.color) {
+        // colours fold with the weights from before the call's frames: ahead of the update
+        const unsigned GC = 1024;   // persistent: workgroups take half blocks from a counter
+#define VBX_COLOR(S)                                                                                          \
+        hipLaunchKernelGGL(k_color<S>, dim3(GC), dim3(256), 0, st, d_jobs, d_maps, (const u64*)s->t_key.p,     \
+                           (const int*)s->t_slot.p, (const u32*)s->off.p, (const float4*)s->sorted.p,          \
+                           (const u32*)sorted_c, JM, cs)
+        if (plan.storage == VBX_F32) VBX_COLOR(0);
+        else if (plan.storage == VBX_F16) VBX_COLOR(1);
+        else VBX_COLOR(2);
+#undef VBX_COLOR
+    }
     launch_update(plan.storage, update_variant, st, d_jobs, d_maps, (const u64*)s->t_key.p,
                   (const int*)s->t_slot.p, (const u32*)s->off.p, (const u32*)s->order.p,
                   (const float4*)s->sorted.p, JM,
@@ -1496,22 +1567,28 @@ int vbx_map_reserve(vbx_map* m, uint32_t block_capacity) {
     u64* old_keys = m->hkeys;
     int* old_slots = m->hslots;
     void* old_pool = m->pool;
+    u32* old_color = m->color;
     const u32 old_cap = m->capacity;
     m->hkeys = nullptr;
     m->hslots = nullptr;
     m->pool = nullptr;
+    m->color = nullptr;
     rc = alloc_storage(m, block_capacity);
     if (rc != VBX_OK) {
         free_storage(m);
         m->hkeys = old_keys;
         m->hslots = old_slots;
         m->pool = old_pool;
+        m->color = old_color;
         m->capacity = old_cap;
         m->hcap = (u32)okeys.size();
         return rc;
     }
     VBX_TRY(hipMemcpyAsync(m->pool, old_pool, (size_t)s.block_count * 4096 * m->voxel_bytes,
                            hipMemcpyDeviceToDevice, m->stream));
+    if (old_color)
+        VBX_TRY(hipMemcpyAsync(m->color, old_color, (size_t)s.block_count * 4096 * sizeof(u32),
+                               hipMemcpyDeviceToDevice, m->stream));
     std::vector<u64> nkeys(m->hcap, kEmpty);
     std::vector<int> nslots(m->hcap, 0);
     for (size_t i = 0; i < okeys.size(); ++i)
@@ -1522,6 +1599,7 @@ int vbx_map_reserve(vbx_map* m, uint32_t block_capacity) {
     map_free(m, old_keys);
     map_free(m, old_slots);
     map_free(m, old_pool);
+    map_free(m, old_color);
     m->P.block_capacity = block_capacity;
     if (m->esdf && (rc = esdf_grow_dirty(m)) != VBX_OK) return rc;
     if (s.error == VBX_ERR_POOL_FULL) {
@@ -1588,6 +1666,48 @@ int vbx_export_blocks(vbx_map* m, int32_t* coords, float* dw, size_t cap, size_t
     return VBX_OK;
 }
 
+int vbx_export_colors(vbx_map* m, int32_t* coords, uint32_t* colors, size_t cap, size_t* n_out) {
+    if (!m || !n_out) return VBX_ERR_INVALID_ARG;
+    if (!m->color) return VBX_ERR_INVALID_ARG;
+    MapState s;
+    int rc = read_state(m, &s);
+    if (rc != VBX_OK) return rc;
+    const size_t nb = s.block_count;
+    if (!coords && !colors) {
+        *n_out = nb;
+        return VBX_OK;
+    }
+    if (cap < nb) return VBX_ERR_BUFFER_TOO_SMALL;
+    std::vector<u64> keys(m->hcap);
+    std::vector<int> slots(m->hcap);
+    VBX_TRY(hipMemcpy(keys.data(), m->hkeys, sizeof(u64) * m->hcap, hipMemcpyDeviceToHost));
+    VBX_TRY(hipMemcpy(slots.data(), m->hslots, sizeof(int) * m->hcap, hipMemcpyDeviceToHost));
+    std::vector<std::pair<u64, int>> blocks;
+    blocks.reserve(nb);
+    for (size_t i = 0; i < keys.size(); ++i)
+        if (keys[i] != kEmpty) blocks.push_back({keys[i], slots[i]});
+    if (blocks.size() != nb) return VBX_ERR_DEVICE;
+    std::sort(blocks.begin(), blocks.end());
+    std::vector<u32> pool;
+    if (colors) {
+        pool.resize(nb * 4096);
+        if (nb) VBX_TRY(hipMemcpy(pool.data(), m->color, pool.size() * sizeof(u32), hipMemcpyDeviceToHost));
+    }
+    for (size_t b = 0; b < nb; ++b) {
+        if (coords) {
+            int bx, by, bz;
+            unpack_block(blocks[b].first, bx, by, bz);
+            coords[3 * b] = bx;
+            coords[3 * b + 1] = by;
+            coords[3 * b + 2] = bz;
+        }
+        if (colors)
+            std::memcpy(colors + b * 4096, pool.data() + (size_t)blocks[b].second * 4096, 4096 * sizeof(u32));
+    }
+    *n_out = nb;
+    return VBX_OK;
+}
+
 int vbx_import_blocks(vbx_map* m, const int32_t* coords, const float* dw, size_t n) {
     if (!m || (n > 0 && (!coords || !dw))) return VBX_ERR_INVALID_ARG;
     if (n > m->capacity) return VBX_ERR_POOL_FULL;
@@ -1612,6 +1732,7 @@ int vbx_import_blocks(vbx_map* m, const int32_t* coords, const float* dw, size_t
     s.error = 0;
     VBX_TRY(hipMemcpy(m->st, &s, sizeof s, hipMemcpyHostToDevice));
     esdf_reset(m, n);      // new slots: the ESDF starts over from every imported block
+    clear_colors(m);
     return VBX_OK;
 }
 
@@ -1707,6 +1828,7 @@ int vbx_map_clear(vbx_map* m) {
     hipLaunchKernelGGL(k_map_clear, dim3(grid_for(m->hcap)), dim3(256), 0, m->stream, m->hkeys, (size_t)m->hcap,
                        (u32*)m->st, (u32)(sizeof(MapState) / 4));
     esdf_reset(m, 0);
+    clear_colors(m);
     VBX_TRY(hipGetLastError());
     return VBX_OK;
 }

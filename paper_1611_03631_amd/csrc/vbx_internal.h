@@ -51,6 +51,7 @@ struct MapDesc {
     u32* dirty;                     // [capacity] blocks changed since the ESDF last looked (null: no ESDF)
     int full_ray;                   // 1: rays start at the sensor, else at max(r - delta, 0)
     int max_steps;                  // guard of a ray walk: at least the longest walk's steps
+    u32* color;                     // [capacity][4096] packed RGB8 per voxel (null: no colour)
 };
 
 // Device-resident counters of a map.
@@ -71,6 +72,7 @@ struct Job {
     u32 tile0;        // first tile of this job in the current launch
     u32 ntiles;
     float pose[12];
+    const u32* colors;   // [n] RGBA8 per point (red in the low byte), or null
 };
 
 // Counters of one call (device).
@@ -83,6 +85,7 @@ struct CallState {
     u32 work_merge;    // persistent work counter of the group merge kernel
     u32 scan_done;     // workgroups of the current scan that have written their sum
     u32 finish_done;   // workgroups of the call's last kernel that are done
+    u32 work_color;    // persistent work counter of the colour kernel
 };
 
 // Partial group of one tile (40 bytes): exact integer sums of the tile's points in one voxel.
@@ -96,6 +99,12 @@ struct Partial {
     u32 lj;        // local voxel index (12 bits) | frame-in-map index << 12
 };
 static_assert(sizeof(Partial) == 40, "partial group record");
+
+// Colour sums of a partial group (colour calls, stored at the partial's index): per channel
+// the sum of fixed-point point weight * 8-bit channel value.
+struct PartialColor {
+    u64 sc[3];
+};
 constexpr u64 kSoMask = (1ull << 48) - 1;
 __host__ __device__ inline u64 partial_so_n(u64 so, u32 n) { return so | ((u64)(n - 1u) << 48); }
 __host__ __device__ inline u64 partial_so(u64 so_n) { return so_n & kSoMask; }

@@ -274,6 +274,7 @@ __global__ __launch_bounds__(256) void k_points_simple(const Job* __restrict__ j
                                                        const MapDesc* __restrict__ maps,
                                                        float4* __restrict__ rays_p,
                                                        u32* __restrict__ rays_job,
+                                                       u32* __restrict__ rays_c,
                                                        JobStat* __restrict__ jst,
                                                        CallState* __restrict__ cs) {
     __shared__ u32 s_cnt[3];   // valid, invalid, out of bounds
@@ -299,6 +300,7 @@ __global__ __launch_bounds__(256) void k_points_simple(const Job* __restrict__ j
                 // per-point weight: Eq. (2) 1, or the 1/z^2 factor of Eq. (5)
                 const float wgt = M.weighting == 1 ? 1.0f / (z * z) : 1.0f;
                 rays_p[slot] = make_float4(q[0], q[1], q[2], wgt);
+                if (rays_c) rays_c[slot] = J.colors ? J.colors[i] : 0u;   // the ray's colour
                 job = (u32)jid;
             }
         }
@@ -396,15 +398,21 @@ __device__ inline u32 tset_insert(u64* tkeys, u32 tmask, u64 key, u32* tlist, u3
 constexpr int kTileHash = 256;     // voxel table slots per tile (one per thread)
 constexpr int kTileBlocks = 128;   // distinct-block table slots per tile
 
+// COLOR: the points carry colours; each partial group also sums Omega * colour per channel
+// (parts_c, at the partial's index), for the group's exact mean colour.
+template <bool COLOR>
 __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ jobs, int njobs,
                                                         const MapDesc* __restrict__ maps,
                                                         u64* __restrict__ tkeys, u32 tmask,
                                                         u32* __restrict__ tlist, u32 tlist_cap,
                                                         Partial* __restrict__ parts,
+                                                        PartialColor* __restrict__ parts_c,
                                                         u32* __restrict__ tile_parts, u32 tiles_per_job,
                                                         JobStat* __restrict__ jst,
                                                         CallState* __restrict__ cs) {
     static_assert(kTileHash == 256, "one voxel slot per thread");
+    constexpr int CS = COLOR ? kTileHash : 1;
+    __shared__ u64 s_sc[3][CS];             // colour sums (colour calls)
     __shared__ u64 s_key[kTileHash];
     __shared__ u64 s_so[kTileHash];
     __shared__ u64 s_sq[3][kTileHash];
@@ -421,6 +429,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     const MapDesc M = maps[tiles_per_job ? 0u : J.map];
     s_key[threadIdx.x] = kEmpty; s_so[threadIdx.x] = 0;
     s_sq[0][threadIdx.x] = 0; s_sq[1][threadIdx.x] = 0; s_sq[2][threadIdx.x] = 0; s_n[threadIdx.x] = 0;
+    if (COLOR) { s_sc[0][threadIdx.x] = 0; s_sc[1][threadIdx.x] = 0; s_sc[2][threadIdx.x] = 0; }
     if (threadIdx.x < kTileBlocks) s_bkey[threadIdx.x] = kEmpty;
     if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -430,6 +439,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
     const u64 mapbits = (u64)M.map_id << 45;
     const u32 jm12 = J.jm << 12;
     Partial* const tparts = parts + (size_t)blockIdx.x * kTileGrouped;
+    PartialColor* const tparts_c = COLOR ? parts_c + (size_t)blockIdx.x * kTileGrouped : nullptr;
     u32 n_valid = 0, n_inv = 0, n_oob = 0;   // per wave (from ballots)
     // both points of this thread are loaded before either is processed; a lane past the end
     // of the frame loads its first point (a frame with a tile has one) and ignores it
@@ -458,6 +468,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         // this lane's contribution; a lane without a valid point gets a key no point has
         u64 key = kEmpty - 1 - (u64)lane;
         u64 so = 0, sq0 = 0, sq1 = 0, sq2 = 0;
+        u64 sc0 = 0, sc1 = 0, sc2 = 0;   // Omega * colour (colour calls)
         float pw[3] = {0.f, 0.f, 0.f};
         int c = -1;
         if (in) c = classify_point(M, J.pose, px[j], py[j], pz[j], pw);
@@ -471,6 +482,12 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
             sq0 = om * Q[0];
             sq1 = om * Q[1];
             sq2 = om * Q[2];
+            if (COLOR) {
+                const u32 col = J.colors ? J.colors[ii[j]] : 0u;
+                sc0 = om * (col & 255u);
+                sc1 = om * ((col >> 8) & 255u);
+                sc2 = om * ((col >> 16) & 255u);
+            }
         }
         n_valid += (u32)__popcll(__ballot(c == 1));
         n_inv += (u32)__popcll(__ballot(c == 0));
@@ -494,6 +511,10 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
             if (runpos >= N) {                                                                 \
                 so += a_so; sq0 += a0; sq1 += a1; sq2 += a2;                                   \
             }                                                                                  \
+            if (COLOR) {                                                                       \
+                const u64 c0 = row_shr64<N>(sc0), c1 = row_shr64<N>(sc1), c2 = row_shr64<N>(sc2); \
+                if (runpos >= N) { sc0 += c0; sc1 += c1; sc2 += c2; }                          \
+            }                                                                                  \
         }
         VBX_SEG_STEP(1) VBX_SEG_STEP(2) VBX_SEG_STEP(4) VBX_SEG_STEP(8)
 #undef VBX_SEG_STEP
@@ -514,6 +535,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                 atomicAdd(&s_sq[1][h], sq1);
                 atomicAdd(&s_sq[2][h], sq2);
                 atomicAdd(&s_n[h], cnt);
+                if (COLOR) { atomicAdd(&s_sc[0][h], sc0); atomicAdd(&s_sc[1][h], sc1); atomicAdd(&s_sc[2][h], sc2); }
                 // read only when the group has a single point: then it is this one
                 s_pt[0][h] = pw[0]; s_pt[1][h] = pw[1]; s_pt[2][h] = pw[2];
             } else {
@@ -532,7 +554,9 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                 }
                 P.h = tset_insert<false>(tkeys, tmask, mapbits | (key >> 12), tlist, tlist_cap, cs);
                 P.lj = jm12 | (u32)(key & 4095u);
-                tparts[kTileGrouped - 1 - atomicAdd(&s_cnt[3], 1u)] = P;
+                const u32 idx = kTileGrouped - 1 - atomicAdd(&s_cnt[3], 1u);
+                tparts[idx] = P;
+                if (COLOR) tparts_c[idx] = PartialColor{{sc0, sc1, sc2}};
             }
         }
     }
@@ -588,6 +612,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         P.h = direct ? hdirect : s_bh[bh];
         P.lj = jm12 | (u32)(skey & 4095u);
         tparts[incl - 1] = P;
+        if (COLOR) tparts_c[incl - 1] = PartialColor{{s_sc[0][k], s_sc[1][k], s_sc[2][k]}};
     }
     if (threadIdx.x == 0) {
         if (s_cnt[0]) atomicAdd(&jst[jid].valid, (u64)s_cnt[0]);
@@ -595,6 +620,11 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         if (s_cnt[2]) atomicAdd(&jst[jid].oob_pts, (u64)s_cnt[2]);
     }
 }
+
+template __global__ void k_points_grouped<false>(const Job*, int, const MapDesc*, u64*, u32, u32*, u32, Partial*,
+                                                 PartialColor*, u32*, u32, JobStat*, CallState*);
+template __global__ void k_points_grouped<true>(const Job*, int, const MapDesc*, u64*, u32, u32*, u32, Partial*,
+                                                PartialColor*, u32*, u32, JobStat*, CallState*);
 
 // Dense index of every block-set entry listed so far (its list position).
 __global__ __launch_bounds__(256) void k_densify(const u32* __restrict__ tlist, u32 tlist_cap,
@@ -668,6 +698,8 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
                                                   const u32* __restrict__ tval,
                                                   u32* __restrict__ bins, const u32* __restrict__ off,
                                                   u32 JM, u32 tpw, Partial* __restrict__ sorted,
+                                                  const PartialColor* __restrict__ parts_c,
+                                                  PartialColor* __restrict__ sorted_c,
                                                   const CallState* __restrict__ cs) {
     if (cs->error) return;
     const u32 tile0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * tpw;
@@ -687,6 +719,10 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
         wave_claim_by_keys<2>(bins, off, a, k, pos);
         if (a[0]) sorted[pos[0]] = P0;
         if (a[1]) sorted[pos[1]] = P1;
+        if (parts_c) {
+            if (a[0]) sorted_c[pos[0]] = parts_c[tp.record(r0)];
+            if (a[1]) sorted_c[pos[1]] = parts_c[tp.record(r1)];
+        }
     }
 }
 
@@ -750,6 +786,20 @@ __device__ inline void merge_partial(const Partial& P, u32 v, u64* m_so, u64 (*m
     atomicAdd(&m_n[v], n);
 }
 
+// The mean colour of a group, per channel round(sc / so) to nearest with ties to even, in
+// integer arithmetic (the same rounding as the position mean's: no binary floating point).
+__device__ inline u32 group_color(const u64 sc[3], u64 so) {
+    u32 c = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const u64 q = sc[k] / so, r = sc[k] - q * so;
+        const u64 v = q + ((2 * r > so || (2 * r == so && (q & 1))) ? 1u : 0u);
+        c |= (u32)(v > 255u ? 255u : v) << (8 * k);
+    }
+    return c;
+}
+
+template <bool COLOR>
 __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ jobs,
                                                      const MapDesc* __restrict__ maps,
                                                      const u64* __restrict__ tkeys,
@@ -757,10 +807,14 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                                                      const u32* __restrict__ off,
                                                      const u32* __restrict__ chunk_first,
                                                      const Partial* __restrict__ sorted, u32 JMS,
+                                                     const PartialColor* __restrict__ sorted_c,
                                                      float4* __restrict__ rays_p,
                                                      u32* __restrict__ rays_job,
+                                                     u32* __restrict__ rays_c,
                                                      JobStat* __restrict__ jst,
                                                      CallState* __restrict__ cs) {
+    constexpr int CV = COLOR ? kMergeVox : 1;
+    __shared__ u64 m_sc[3][CV];        // colour sums (colour calls)
     __shared__ u32 m_key[kMergeVox];   // hash: (bin in batch << 12 | local) + 1, 0 = free
     __shared__ u64 m_so[kMergeVox];
     __shared__ u64 m_sq[3][kMergeVox];
@@ -774,6 +828,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
     for (int i = threadIdx.x; i < kMergeVox; i += 256) {
         m_key[i] = 0; m_so[i] = 0; m_sq[0][i] = 0; m_sq[1][i] = 0; m_sq[2][i] = 0;
         m_hi[0][i] = 0; m_hi[1][i] = 0; m_hi[2][i] = 0; m_n[i] = 0;
+        if (COLOR) { m_sc[0][i] = 0; m_sc[1][i] = 0; m_sc[2][i] = 0; }
     }
     const u32 nb = cs->error ? 0u : cs->t_count * JMS;
     const u32 total = nb ? off[nb] : 0u;
@@ -819,10 +874,14 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
                 for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
                     const Partial& P = sorted[e];
-                    merge_partial(P, P.lj & (u32)(kMergeVox - 1), m_so, m_sq, m_hi, m_n, m_p);
+                    const u32 vv = P.lj & (u32)(kMergeVox - 1);
+                    merge_partial(P, vv, m_so, m_sq, m_hi, m_n, m_p);
+                    if (COLOR)
+                        for (int k = 0; k < 3; ++k) atomicAdd(&m_sc[k][vv], sorted_c[e].sc[k]);
                 }
                 __syncthreads();
                 float4 ray[kMergePerThread];
+                u32 rcol[kMergePerThread];
                 bool has[kMergePerThread];
                 u32 nmine = 0;
 #pragma unroll
@@ -836,6 +895,12 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                     const u32 hw[3] = {m_hi[0][v], m_hi[1][v], m_hi[2][v]};
                     const float p1[3] = {m_p[0][v], m_p[1][v], m_p[2][v]};
                     group_ray(M, bx, by, bz, qd * (u32)kMergeVox + (u32)v, n, m_so[v], sq, hw, p1, ray[r]);
+                    rcol[r] = 0u;
+                    if (COLOR) {
+                        const u64 sc[3] = {m_sc[0][v], m_sc[1][v], m_sc[2][v]};
+                        rcol[r] = group_color(sc, m_so[v]);
+                        m_sc[0][v] = 0; m_sc[1][v] = 0; m_sc[2][v] = 0;
+                    }
                     nmine++;
                     m_so[v] = 0; m_sq[0][v] = 0; m_sq[1][v] = 0; m_sq[2][v] = 0;
                     m_hi[0][v] = 0; m_hi[1][v] = 0; m_hi[2][v] = 0; m_n[v] = 0;
@@ -848,6 +913,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                     if (!has[r]) continue;
                     rays_p[pos] = ray[r];
                     rays_job[pos] = (u32)jid;
+                    if (COLOR) rays_c[pos] = rcol[r];
                     pos++;
                 }
                 for (u32 e = lo + nrays + threadIdx.x; e < hi; e += 256) rays_job[e] = kNoRay;
@@ -876,6 +942,8 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                     h = (h + 1) & (kMergeVox - 1);
                 }
                 merge_partial(P, h, m_so, m_sq, m_hi, m_n, m_p);
+                if (COLOR)
+                    for (int k = 0; k < 3; ++k) atomicAdd(&m_sc[k][h], sorted_c[e].sc[k]);
             }
             __syncthreads();
             for (int h = threadIdx.x; h < kMergeVox; h += 256) {
@@ -897,6 +965,11 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 const u32 pos = s_off[bi] + atomicAdd(&s_nr[bi], 1u);
                 rays_p[pos] = ray;
                 rays_job[pos] = (u32)jid;
+                if (COLOR) {
+                    const u64 sc[3] = {m_sc[0][h], m_sc[1][h], m_sc[2][h]};
+                    rays_c[pos] = group_color(sc, m_so[h]);
+                    m_sc[0][h] = 0; m_sc[1][h] = 0; m_sc[2][h] = 0;
+                }
                 m_key[h] = 0; m_so[h] = 0; m_sq[0][h] = 0; m_sq[1][h] = 0; m_sq[2][h] = 0;
                 m_hi[0][h] = 0; m_hi[1][h] = 0; m_hi[2][h] = 0; m_n[h] = 0;
             }
@@ -917,6 +990,12 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
         }
     }
 }
+template __global__ void k_group_merge<false>(const Job*, const MapDesc*, const u64*, const u32*, const u32*,
+                                              const u32*, const Partial*, u32, const PartialColor*, float4*, u32*,
+                                              u32*, JobStat*, CallState*);
+template __global__ void k_group_merge<true>(const Job*, const MapDesc*, const u64*, const u32*, const u32*,
+                                             const u32*, const Partial*, u32, const PartialColor*, float4*, u32*,
+                                             u32*, JobStat*, CallState*);
 
 // ---------------------------------------------------------------------------
 // cross: walk the band of each ray, record (block, ray) crossings
@@ -1295,17 +1374,20 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ jobs,
                                                  u32* __restrict__ bins, const u32* __restrict__ off,
                                                  u32 JM, const float4* __restrict__ rays_p,
                                                  float4* __restrict__ sorted,
+                                                 const u32* __restrict__ rays_c, u32* __restrict__ sorted_c,
                                                  CallState* __restrict__ cs, u32 ray_cap) {
     const u32 nr = cs->error ? 0u : (cs->ray_count < ray_cap ? cs->ray_count : ray_cap);
     for (u32 base = blockIdx.x * 256u; base < nr; base += gridDim.x * 256u) {
         const u32 i = base + threadIdx.x;
         u32 nc = 0, jm = 0;
         float4 rp = make_float4(0.f, 0.f, 0.f, 0.f);
+        u32 col = 0;
         if (i < nr) {
             nc = ncross[i];
             if (nc) {
                 jm = jobs[rays_job[i]].jm;
                 rp = rays_p[i];
+                if (rays_c) col = rays_c[i];
             }
         }
         for (u32 c = 0; c < MB; ++c) {
@@ -1315,6 +1397,7 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ jobs,
             // lanes sharing a bin take consecutive positions reserved by one atomic
             const u32 pos = wave_claim_by_key(bins, off, act, b);
             if (act) sorted[pos] = rp;
+            if (act && sorted_c) sorted_c[pos] = col;
         }
     }
 }
@@ -1844,6 +1927,148 @@ template __global__ void k_update<2, 16, 16, 8, 512>(const Job*, const MapDesc*,
                                                         int, JobStat*, CallState*);
 
 // ---------------------------------------------------------------------------
+// colour (Sec. IV-B): per voxel and frame, the frame's weighted mean ray colour is folded into
+// the stored colour with the voxel's weight from before the frame,
+//   C <- round((W C + sum_i w_i c_i) / (W + sum_i w_i))   per channel (to nearest, ties to even).
+// Runs before the update kernel (which then changes W) and replays its walks, observations and
+// weight recurrence exactly (same fixed-point weight sums, same binary32 W, same storage
+// rounding), over half blocks of 16 x 16 x 8 voxels.  Only colour is written.
+// ---------------------------------------------------------------------------
+template <int STORAGE>
+__global__ __launch_bounds__(256) void k_color(const Job* __restrict__ jobs,
+                                               const MapDesc* __restrict__ maps,
+                                               const u64* __restrict__ t_key,
+                                               const int* __restrict__ t_slot,
+                                               const u32* __restrict__ off,
+                                               const float4* __restrict__ sorted,
+                                               const u32* __restrict__ sorted_c, u32 JM,
+                                               CallState* __restrict__ cs) {
+    constexpr int RX = 16, RY = 16, RZ = 8, NT = 256;
+    constexpr int VOX = RX * RY * RZ, VPT = VOX / NT, NREG = 4096 / VOX;
+    __shared__ u64 a_w[VOX];      // fixed-point weight sums of the frame (scale 2^kw)
+    __shared__ u64 a_c[3][VOX];   // fixed-point weight * channel sums (scale 2^(kw - 8))
+    __shared__ u32 s_off[kOffWindow + 1];
+    __shared__ u32 s_t;
+    for (int i = threadIdx.x; i < VOX; i += NT) {
+        a_w[i] = 0; a_c[0][i] = 0; a_c[1][i] = 0; a_c[2][i] = 0;
+    }
+    const u32 nt = cs->error ? 0u : cs->t_count * (u32)NREG;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = atomicAdd(&cs->work_color, 1u);
+        __syncthreads();
+        const u32 u = s_t;
+        if (u >= nt) break;
+        const u32 t = u / (u32)NREG;
+        const int qz = (int)(u % (u32)NREG);
+        const u64 tk = t_key[t];
+        const MapDesc M = maps[(u32)(tk >> 45)];
+        if (M.color == nullptr || M.st->error != 0) { __syncthreads(); continue; }
+        int bx, by, bz;
+        unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
+        const int ts = t_slot[t];
+        const bool is_new = (ts & 0x40000000) != 0;
+        const size_t slot = (size_t)(ts & 0x3FFFFFFF);
+        const size_t vbase = slot * 4096 + (size_t)(256 * (qz * RZ));   // the region is contiguous
+        float W[VPT];
+        u32 C[VPT];
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+            const size_t idx = vbase + (size_t)(threadIdx.x + NT * j);
+            if (is_new) { W[j] = 0.0f; C[j] = 0u; }
+            else {
+                float Dj;
+                load_voxel<STORAGE>(M.pool, idx, Dj, W[j]);
+                C[j] = M.color[idx];
+            }
+        }
+        const int ox = 16 * bx, oy = 16 * by, oz = 16 * bz + qz * RZ;
+        const float cscale = M.wscale * (1.0f / 256.0f);
+        const double inv_w = (double)M.inv_wscale, inv_c = (double)M.inv_wscale * 256.0;
+        for (int w0 = 0; w0 < M.njobs; w0 += kOffWindow) {
+            const int wn = M.njobs - w0 < kOffWindow ? M.njobs - w0 : kOffWindow;
+            for (int k = threadIdx.x; k <= wn; k += NT) s_off[k] = off[t * JM + (u32)(w0 + k)];
+            __syncthreads();
+            for (int jm = 0; jm < wn; ++jm) {
+                const u32 lo = s_off[jm], hi = s_off[jm + 1];
+                if (lo == hi) continue;                       // same in every thread
+                const Job& J = jobs[M.job0 + w0 + jm];
+                const float s[3] = {J.pose[3], J.pose[7], J.pose[11]};
+                for (u32 e = lo + threadIdx.x; e < hi; e += NT) {
+                    const float4 rp = sorted[e];
+                    const u32 col = sorted_c[e];
+                    const float p[3] = {rp.x, rp.y, rp.z};
+                    float ev[3], r;
+                    Walk w;
+                    walk_setup(M, p, s, ev, r, w);
+                    // every walk index lies between its end voxels: skip bands that miss the region
+                    {
+                        const int g_end = w.g[2] + w.step[2] * w.n[2];
+                        const int glo = w.g[2] < g_end ? w.g[2] : g_end;
+                        const int ghi = w.g[2] < g_end ? g_end : w.g[2];
+                        if (ghi < oz || glo >= oz + RZ) continue;
+                    }
+                    const float cf[3] = {(float)(col & 255u), (float)((col >> 8) & 255u), (float)((col >> 16) & 255u)};
+                    bool inside = false;
+                    for (int guard = 0; guard < M.max_steps; ++guard) {
+                        const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
+                        if ((u32)lx < (u32)RX && (u32)ly < (u32)RY && (u32)lz < (u32)RZ) {
+                            inside = true;
+                            const Obs o = observe(M, p, ev, r, rp.w, w.g[0], w.g[1], w.g[2]);
+                            const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
+                            // the weight sum exactly as the update kernel forms it
+                            atomicAdd(&a_w[l], (u64)__builtin_rintf(o.w * M.wscale));
+#pragma unroll
+                            for (int k = 0; k < 3; ++k)
+                                atomicAdd(&a_c[k][l], (u64)__builtin_rintf(o.w * cf[k] * cscale));
+                        } else if (inside) {
+                            break;   // the walk is monotone per axis: it never re-enters the region
+                        }
+                        if (w.left == 0) break;
+                        walk_step(w);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) {
+                    const int l = threadIdx.x + NT * j;
+                    const u64 sw_fx = a_w[l];
+                    if (!sw_fx) continue;
+                    // colour with the weight before the frame (binary64: the quotient is rounded
+                    // once, then to the nearest integer)
+                    const double sw = (double)sw_fx * inv_w, Wd = (double)W[j];
+                    u32 cn = 0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const double ck = (double)((C[j] >> (8 * k)) & 255u);
+                        double q = __builtin_rint((Wd * ck + (double)a_c[k][l] * inv_c) / (Wd + sw));
+                        q = q < 0.0 ? 0.0 : (q > 255.0 ? 255.0 : q);
+                        cn |= (u32)q << (8 * k);
+                    }
+                    C[j] = cn;
+                    // Eq. (4) as the update kernel takes it: binary32, capped, rounded to storage
+                    float Wn = W[j] + (float)sw_fx * M.inv_wscale;
+                    if (Wn > M.w_max) Wn = M.w_max;
+                    if (STORAGE != 0) Wn = __half2float(__float2half_rn(Wn));
+                    W[j] = Wn;
+                    a_w[l] = 0; a_c[0][l] = 0; a_c[1][l] = 0; a_c[2][l] = 0;
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) M.color[vbase + (size_t)(threadIdx.x + NT * j)] = C[j];
+        __syncthreads();
+    }
+}
+
+template __global__ void k_color<0>(const Job*, const MapDesc*, const u64*, const int*, const u32*, const float4*,
+                                    const u32*, u32, CallState*);
+template __global__ void k_color<1>(const Job*, const MapDesc*, const u64*, const int*, const u32*, const float4*,
+                                    const u32*, u32, CallState*);
+template __global__ void k_color<2>(const Job*, const MapDesc*, const u64*, const int*, const u32*, const float4*,
+                                    const u32*, u32, CallState*);
+
+// ---------------------------------------------------------------------------
 // finish: commit block counts, fold statistics, clean per-call tables
 // ---------------------------------------------------------------------------
 // The call's last kernel, in one launch: workgroups [0, nmaps) fold each map's statistics,
@@ -1942,6 +2167,7 @@ __global__ __launch_bounds__(256) void k_finish_call(const Job* __restrict__ job
         cs->t_count = 0;
         cs->work_next = 0;
         cs->work_merge = 0;
+        cs->work_color = 0;
         cs->scan_done = 0;
         cs->error = 0;
         cs->finish_done = 0;

@@ -460,3 +460,26 @@ def esdf_benchmark(n_views: int = 50, width: int = 320, height: int = 240,
         return _depth_frame(poses[k], dirs, hit, lambda z: 0.0 * z, frng, 0.0)
 
     return poses, frame, lambda p: esdf_scene_distance(p, cube, sphere)
+
+
+# --------------------------------------------------------------------------
+# Point colours (a textured scene for the colour layer)
+# --------------------------------------------------------------------------
+def point_colors(points: np.ndarray, pose: np.ndarray, seed: int, k: int = 0,
+                 cell: float = 0.3, noise: float = 8.0) -> np.ndarray:
+    """RGBA8 colours (red in the low byte, alpha 255) of sensor-frame points seen from `pose`:
+    a checker texture of 0.3 m world cells, each cell a seeded palette colour, plus per-point
+    sensor noise (normal, sigma `noise` per channel, frame k's own draw), rounded and clipped to
+    [0, 255].  Invalid (NaN) points get 0.  Elementwise arithmetic only."""
+    p = np.asarray(points, np.float64).reshape(-1, 3)
+    T = np.asarray(pose, np.float64).reshape(3, 4)
+    w = [T[r, 0] * p[:, 0] + T[r, 1] * p[:, 1] + T[r, 2] * p[:, 2] + T[r, 3] for r in range(3)]
+    ok = np.isfinite(w[0]) & np.isfinite(w[1]) & np.isfinite(w[2])
+    cx = [np.floor(np.where(ok, x, 0.0) / cell).astype(np.int64) for x in w]
+    h = (cx[0] * 73856093) ^ (cx[1] * 19349663) ^ (cx[2] * 83492791) ^ int(seed % (1 << 30))
+    h = h & 0xFFFFFF
+    base = np.stack([(h >> (8 * c)) & 255 for c in range(3)], axis=1).astype(np.float64)
+    rng = np.random.default_rng([seed, 7919, k])
+    val = np.clip(np.rint(base + rng.normal(0.0, noise, size=base.shape)), 0, 255).astype(np.uint32)
+    out = val[:, 0] | (val[:, 1] << 8) | (val[:, 2] << 16) | np.uint32(255 << 24)
+    return np.where(ok, out, np.uint32(0)).astype(np.uint32)

@@ -30,7 +30,7 @@ def oracle_map(params: dict, **over):
                             merge=p.get("merge", "simple"), w_max=p.get("w_max", 1e4),
                             max_range=p.get("max_range", 5.0), z_min=p.get("z_min", 0.1),
                             storage=p.get("storage", "f32"), dist=p.get("dist", "eq1"),
-                            full_ray=p.get("full_ray", False))
+                            full_ray=p.get("full_ray", False), color=p.get("color", False))
 
 
 def gpu_map(vbx, params: dict, **over):
@@ -41,7 +41,8 @@ def gpu_map(vbx, params: dict, **over):
                    w_max=p.get("w_max", 1e4), max_range=p.get("max_range", 5.0),
                    z_min=p.get("z_min", 0.1), dist=p.get("dist", "eq1"),
                    block_capacity=p.get("block_capacity", 4096),
-                   keep_touches=p.get("keep_touches", True), full_ray=p.get("full_ray", False))
+                   keep_touches=p.get("keep_touches", True), full_ray=p.get("full_ray", False),
+                   color=p.get("color", False))
 
 
 def touches_dict(coords, counts):

@@ -41,6 +41,22 @@ def test_binding_lists_every_declared_symbol():
     assert sorted(vbx.EXPORTED) == declared_functions()
 
 
+def test_binding_declares_argument_types_of_every_entry_point(libpath):
+    """ctypes passes undeclared integer arguments as 32-bit ints: a pointer argument would be
+    truncated.  Every declared function that takes arguments has its argument types set."""
+    import paper_1611_03631_amd as vbx
+    L = vbx.lib()
+    src = open(os.path.join(ROOT, "include", "vbx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    missing = []
+    for name in declared_functions():
+        m = re.search(name + r"\s*\(([^)]*)\)", src)
+        takes_args = m is not None and m.group(1).strip() not in ("", "void")
+        if takes_args and getattr(L, name).argtypes is None:
+            missing.append(name)
+    assert not missing, f"no argtypes: {missing}"
+
+
 def test_status_strings_without_gpu(libpath):
     lib = ctypes.CDLL(libpath)
     lib.vbx_status_string.restype = ctypes.c_char_p
