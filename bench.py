@@ -324,6 +324,66 @@ def bench_c2(args, np, torch, vbx, synth):
             raise RuntimeError("device status after the compared forms")
         plain.close()
 
+    # ------------------------------------------- the other integration forms on the same frames
+    variants = {}
+    if not args.no_forms:
+        def variant(tag, fn_make, reps=5):
+            vm, run = fn_make()
+            ms = timed(run, reps)
+            if vm.sync() != 0:
+                raise RuntimeError(f"device status after the {tag} form")
+            vs = vm.stats()
+            variants[tag] = {"ms_per_step": round(ms, 4), "points_per_s": round(F * N / (ms / 1e3), 1),
+                             "blocks": vs["blocks"], "touches": vs["touches"]}
+            vm.close()
+
+        def make_map(**kw):
+            return vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"],
+                           storage="f32", max_range=P["max_range"], stream=stream, **kw)
+
+        def projective():      # projection mapping (Sec. IV-B) of the same frames
+            vm = make_map(block_capacity=16384)
+            K = np.array([100.0 * w.width / 160.0, 100.0 * w.width / 160.0, w.width / 2.0, w.height / 2.0],
+                         np.float32)
+            arr = vbx.make_frames(batch)
+
+            def run():
+                L.vbx_map_clear(vm.handle)
+                rc = L.vbx_integrate_projective(vm.handle, arr, F, K.ctypes.data)
+                if rc != 0:
+                    raise vbx.VbxError(rc, "vbx_integrate_projective")
+            return vm, run
+        variant("projective_f32", projective)
+
+        def full_ray():        # raycasting from the sensor (free space carved), grouped
+            vm = make_map(block_capacity=65536, full_ray=True)
+            vm.set_tuning(**m.tuning())
+            arr = vbx.make_frames(batch)
+
+            def run():
+                L.vbx_map_clear(vm.handle)
+                rc = L.vbx_integrate_frames(vm.handle, arr, F)
+                if rc != 0:
+                    raise vbx.VbxError(rc, "vbx_integrate_frames")
+            return vm, run
+        variant("full_ray_grouped_f32", full_ray, reps=3)
+
+        cols = [torch.from_numpy(synth.point_colors(frames[k], w.poses[k], synth.SEED_BASE + 1, k).view(np.int32)).cuda()
+                for k in range(F)]
+
+        def color():           # colour fused with the distances (Sec. IV-B), grouped
+            vm = make_map(block_capacity=16384, color=True)
+            vm.set_tuning(**m.tuning())
+            arr = vbx.make_frames([(dev[k], w.poses[k], w.width, cols[k]) for k in range(F)])
+
+            def run():
+                L.vbx_map_clear(vm.handle)
+                rc = L.vbx_integrate_frames(vm.handle, arr, F)
+                if rc != 0:
+                    raise vbx.VbxError(rc, "vbx_integrate_frames")
+            return vm, run
+        variant("color_grouped_f32", color)
+
     # ---------------------------------------------------------------- CPU oracle sample
     cpu = None
     accuracy = None
@@ -365,6 +425,7 @@ def bench_c2(args, np, torch, vbx, synth):
         "whole_step_algorithmic_GBps": round(whole, 1),
         "stage_ms_per_step": stages,
         "forms_ms_per_step": forms,
+        "other_forms": variants,
         "error_vs_binary64_oracle": accuracy,
         "wall_s": round(wall_s, 3),
         "repeat_bit_identical": True,
@@ -988,17 +1049,25 @@ def bench_esdf(args, np, torch, vbx, synth):
     for vs in (0.05, 0.10, 0.20):
         vv = float(np.float32(vs))
         trunc = 4.0 * vs
-        g = vbx.Map(vs, trunc, weighting="quad", merge="grouped", storage="f32", max_range=5.0,
-                    block_capacity=65536, stream=stream)
-        g.integrate_frames([(sdev[k], poses[k], 320) for k in range(len(poses))])
-        if g.sync() != 0:
-            raise RuntimeError("device status after the simulated sequence")
-        c, dw = g.export()
-        g.close()
+        def tsdf(dist):
+            g = vbx.Map(vs, trunc, weighting="quad", merge="grouped", storage="f32", max_range=5.0,
+                        block_capacity=65536, stream=stream, dist=dist)
+            g.integrate_frames([(sdev[k], poses[k], 320) for k in range(len(poses))])
+            if g.sync() != 0:
+                raise RuntimeError("device status after the simulated sequence")
+            out = g.export()
+            g.close()
+            return out
+        c, dw = tsdf("eq1")
+        # the same TSDF with the distance along the ray (the projective distance of Sec. I)
+        c_ray, dw_ray = tsdf("ray")
+        assert np.array_equal(c_ray, c)
         from_voxel = (16 * c[:, None, :] + np.stack([np.arange(4096) & 15, (np.arange(4096) >> 4) & 15,
                                                      np.arange(4096) >> 8], axis=1)[None]).reshape(-1, 3)
         gt = dist_fn((from_voxel + 0.5) * vv).reshape(c.shape[0], 4096)
-        variants = {"band_1v": (dw, vv), "band_half_trunc": (dw, float(np.float32(trunc / 2.0)))}
+        variants = {"band_1v": (dw, vv), "band_half_trunc": (dw, float(np.float32(trunc / 2.0))),
+                    "band_1v_along_ray": (dw_ray, vv),
+                    "band_half_trunc_along_ray": (dw_ray, float(np.float32(trunc / 2.0)))}
         occ = dw.copy()
         neg = occ[:, :, 0] < 0
         occ[:, :, 0] = np.where(neg, 0.0, np.maximum(occ[:, :, 0], np.float32(1e-3 * vv)))
@@ -1021,7 +1090,9 @@ def bench_esdf(args, np, torch, vbx, synth):
             err = (ed.astype(np.float64) - gt)[sel]
             res[name] = {"voxels": int(sel.sum()), "mean_abs_m": round(float(np.mean(np.abs(err))), 5),
                          "rms_m": round(float(np.sqrt(np.mean(err ** 2))), 5),
-                         "mean_signed_m": round(float(np.mean(err)), 5), "update_ms": round(ms, 3)}
+                         "mean_signed_m": round(float(np.mean(err)), 5),
+                         "p95_abs_m": round(float(np.percentile(np.abs(err), 95)), 5) if err.size else None,
+                         "fixed": int(((ei & 2) > 0).sum()), "update_ms": round(ms, 3)}
         accuracy[f"v{vs:g}"] = res
 
     return {
@@ -1056,6 +1127,123 @@ def bench_esdf(args, np, torch, vbx, synth):
     }
 
 
+# ------------------------------------------------------------------------------------------
+# rocprofv3 summaries (host only): the tables under profiles/ are written by this function
+# ------------------------------------------------------------------------------------------
+def _short_kernel(name: str) -> str:
+    """A kernel's name without its argument list (template arguments kept)."""
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def summarize_profiles(args):
+    """Writes a markdown summary of rocprofv3 output to args.summary_out:
+    * the kernel-trace statistics of every `*_kernel_stats.csv` under args.summary_stats;
+    * for every directory of args.summary_pmc, the per-dispatch counters of its
+      `*_counter_collection.csv`, averaged per kernel; the dispatches of the plain copy kernel
+      give the HBM scaling factors (copy bytes / FETCH_SIZE and / WRITE_SIZE), applied to every
+      kernel's FETCH_SIZE and WRITE_SIZE.
+    args.summary_cmd lists the commands that produced the files, quoted in the summary."""
+    import csv
+    import glob
+    lines = [f"# {args.summary_title}", ""]
+    lines += ["Commands (from the repository root on one MI355X, TMPDIR=/tmp):", ""]
+    lines += [f"    {c}" for c in args.summary_cmd] + [""]
+    lines += [f"Kernel sources: sha {kernel_source_sha()} (bench.py kernel_source_sha).", ""]
+    for d in args.summary_stats or []:
+        for f in sorted(glob.glob(os.path.join(d, "**", "*_kernel_stats.csv"), recursive=True)):
+            rows = list(csv.DictReader(open(f)))
+            lines += ["## Kernel durations (kernel trace)", "",
+                      "| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+            for r in rows:
+                lines.append(f"| {_short_kernel(r['Name'])} | {r['Calls']} | "
+                             f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['AverageNs']) / 1e3:.2f} | "
+                             f"{float(r['Percentage']):.2f} |")
+            lines.append("")
+    per = {}        # kernel -> counter -> [values per dispatch]
+    for d in args.summary_pmc or []:
+        for f in sorted(glob.glob(os.path.join(d, "**", "*_counter_collection.csv"), recursive=True)):
+            acc = {}
+            for r in csv.DictReader(open(f)):
+                key = (_short_kernel(r["Kernel_Name"]), r["Dispatch_Id"], r["Counter_Name"])
+                acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])   # summed over the row's dimensions
+            for (k, _, c), v in acc.items():
+                per.setdefault(k, {}).setdefault(c, []).append(v)
+    if per:
+        counters = sorted({c for k in per.values() for c in k})
+        copy = next((k for k in per if "copyBuffer" in k or "elementwise_kernel" in k), None)
+        scale = {}
+        if copy and args.summary_copy_bytes:
+            for c in ("FETCH_SIZE", "WRITE_SIZE"):
+                if c in per[copy]:
+                    vals = sorted(per[copy][c])
+                    scale[c] = args.summary_copy_bytes / (vals[-1] * 1024.0)   # the largest copy dispatch
+        lines += ["## Counters per dispatch (averaged over the kernel's dispatches)", ""]
+        if scale:
+            lines += ["HBM scaling from the largest dispatch of the plain copy kernel "
+                      f"(`{copy}`, {args.summary_copy_bytes / 2 ** 30:.0f} GiB read and written): "
+                      + ", ".join(f"bytes = {c} KiB x 1024 x {v:.3f}" for c, v in scale.items()), ""]
+        head = "| kernel | dispatches | " + " | ".join(counters) + (" | HBM MB (scaled) |" if scale else " |")
+        lines += [head, "|---|---:|" + "---:|" * (len(counters) + (1 if scale else 0))]
+        for k in sorted(per, key=lambda k: -max((sum(v) / len(v)) for v in per[k].values())):
+            n = max(len(v) for v in per[k].values())
+            avg = {c: (sum(per[k][c]) / len(per[k][c]) if c in per[k] else None) for c in counters}
+            cells = [f"{avg[c]:.4g}" if avg[c] is not None else "" for c in counters]
+            hbm = ""
+            if scale:
+                mb = sum(avg[c] * 1024.0 * scale[c] for c in scale if avg.get(c) is not None) / 1e6
+                hbm = f" {mb:.2f} |"
+            lines.append(f"| {k} | {n} | " + " | ".join(cells) + " |" + hbm)
+        lines.append("")
+        if "SQ_INSTS_VALU" in counters and "SQ_WAVES" in counters:
+            lines += ["Derived: VALU instructions per wave, and the share of the wave cycles spent "
+                      "issuing VALU instructions (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES; both count "
+                      "per wave, in quad-cycles on this hardware):", "",
+                      "| kernel | VALU / wave | LDS / wave | VALU-active / wave cycles | busy-wait / wave cycles |",
+                      "|---|---:|---:|---:|---:|"]
+            for k in per:
+                a = {c: sum(per[k][c]) / len(per[k][c]) for c in per[k]}
+                if not a.get("SQ_WAVES"):
+                    continue
+                r1 = a.get("SQ_INSTS_VALU", 0) / a["SQ_WAVES"]
+                r2 = a.get("SQ_INSTS_LDS", 0) / a["SQ_WAVES"]
+                wc = a.get("SQ_WAVE_CYCLES")
+                r3 = f"{a['SQ_ACTIVE_INST_VALU'] / wc:.3f}" if wc and "SQ_ACTIVE_INST_VALU" in a else ""
+                r4 = f"{a['SQ_WAIT_INST_ANY'] / wc:.3f}" if wc and "SQ_WAIT_INST_ANY" in a else ""
+                lines.append(f"| {k} | {r1:.1f} | {r2:.1f} | {r3} | {r4} |")
+            lines.append("")
+    with open(args.summary_out, "w") as fh:
+        fh.write("\n".join(lines))
+    # per-stage HBM bytes that the benchmark reads back as roofline.traffic
+    for spec in args.summary_traffic or []:
+        stage, sub = spec.split(":", 1)
+        k = next((k for k in per if sub in k), None)
+        if k is None or len(scale) != 2:
+            raise SystemExit(f"no counters of a kernel matching {sub!r}, or no copy calibration")
+        avg = {c: sum(per[k][c]) / len(per[k][c]) for c in scale}
+        hbm = int(round(sum(avg[c] * 1024.0 * scale[c] for c in scale)))
+        tun = ""
+        if stage == "update":
+            tun = "update_tuning = " + args.summary_update_tuning + "\n"
+        text = (f"# HBM bytes per launch of the {stage} stage kernel ({k}) on {args.summary_workload},\n"
+                f"# " + " + ".join(f"{c} x {scale[c]:.3f}" for c in scale) + " (KiB x 1024), from:\n"
+                + "".join(f"#   {c}\n" for c in args.summary_cmd if "FETCH_SIZE" in c or "WRITE_SIZE" in c)
+                + "# valid only for this workload" + (", this update variant (split, threads, columns)"
+                                                      if stage == "update" else "")
+                + " and the kernel sources with this sha (bench.py kernel_source_sha)\n"
+                f"workload = {args.summary_workload}\n{tun}source_sha = {kernel_source_sha()}\n"
+                f"hbm_bytes_per_launch = {hbm}\n")
+        with open(os.path.join(ROOT, "profiles", f"traffic_{stage}.txt"), "w") as fh:
+            fh.write(text)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -1075,7 +1263,23 @@ def main():
                     help="keep the default launch tuning instead of timing the candidates first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--summarize", action="store_true",
+                    help="host only: write a markdown summary of rocprofv3 output (no GPU work)")
+    ap.add_argument("--summary-title", default="Kernel statistics")
+    ap.add_argument("--summary-stats", nargs="*", help="directories holding *_kernel_stats.csv")
+    ap.add_argument("--summary-pmc", nargs="*", help="directories holding *_counter_collection.csv")
+    ap.add_argument("--summary-cmd", action="append", default=[], help="a command that produced the files")
+    ap.add_argument("--summary-copy-bytes", type=float, default=float(1 << 30),
+                    help="bytes the calibration copy reads (and writes)")
+    ap.add_argument("--summary-out", default="profile_summary.md")
+    ap.add_argument("--summary-traffic", nargs="*",
+                    help="stage:kernel-substring pairs whose HBM bytes go to profiles/traffic_<stage>.txt")
+    ap.add_argument("--summary-workload", default="c2_room_640x480x100")
+    ap.add_argument("--summary-update-tuning", default="1,1024,0")
     args = ap.parse_args()
+    if args.summarize:
+        summarize_profiles(args)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the integrator runs on a single MI355X "
