@@ -127,7 +127,8 @@ def oracle_sample(w_list, budget_s, keep=False, keep_first=None):
     for w, k_lo, k_hi in w_list:
         P = w.params
         om = oracle.OracleMap(P["voxel_size"], P["trunc"], weighting=P["weighting"],
-                              merge=P["merge"], max_range=P["max_range"], storage="f32")
+                              merge=P["merge"], max_range=P["max_range"], storage="f32",
+                              full_ray=P.get("full_ray", False))
         finished = True
         for k in range(k_lo, k_hi):
             if secs >= budget_s:
@@ -621,9 +622,16 @@ C3_INITIAL_CAPACITY = 256   # blocks: the streamed sweeps grow the pool several 
 
 def bench_c3(args, np, torch, vbx, synth):
     """50 LiDAR sweeps along a street: batched into one call, and streamed sweep by sweep from
-    a small pool that the host grows (vbx_map_reserve) whenever it fills."""
+    a small pool that the host grows (vbx_map_reserve) whenever it fills.  With --full-ray every
+    ray is walked from the sensor to the truncation distance behind its point (the free space is
+    carved too), and the map grows to tens of thousands of blocks."""
     S = 50
     w = synth.config3(n_sweeps=S)
+    if args.full_ray:
+        w.params = dict(w.params, full_ray=True)
+    if args.voxel:
+        # a finer map of the same street: truncation three voxels, as in the other workloads
+        w.params = dict(w.params, voxel_size=args.voxel, trunc=3.0 * args.voxel)
     t0 = time.time()
     with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
         frames = list(ex.map(w.frame, range(S)))
@@ -636,9 +644,10 @@ def bench_c3(args, np, torch, vbx, synth):
     batch = [(dev[k], w.poses[k], w.width) for k in range(S)]
     L = vbx.lib()
 
+    full = bool(P.get("full_ray", False))
     # streamed: one call per sweep, pool doubled by the host when a sweep finds it full
     m = vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"], storage="f32",
-                max_range=P["max_range"], block_capacity=C3_INITIAL_CAPACITY, stream=stream)
+                max_range=P["max_range"], block_capacity=C3_INITIAL_CAPACITY, stream=stream, full_ray=full)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -662,13 +671,14 @@ def bench_c3(args, np, torch, vbx, synth):
     stream_wall = time.perf_counter() - t_wall
     stream_ms = e0.elapsed_time(e1)
     st_stream = m.stats()
+    hash_stream = m.hash_stats()
     ref = m.export()
     cap = m.params["block_capacity"]
     m.close()
 
     # batched: the whole sequence in one call into a pool of the final size
     b = vbx.Map(P["voxel_size"], P["trunc"], weighting=P["weighting"], merge=P["merge"], storage="f32",
-                max_range=P["max_range"], block_capacity=cap, stream=stream)
+                max_range=P["max_range"], block_capacity=cap, stream=stream, full_ray=full)
     arr = vbx.make_frames(batch)
 
     def step():
@@ -702,6 +712,7 @@ def bench_c3(args, np, torch, vbx, synth):
     prof = b.profile_read(reset=True)
     b.profile(False)
     st = b.stats()
+    hstats = b.hash_stats()
     tuning = b.tuning()
     b.close()
     algo = {"points": 12.0 * S * N + 48.0 * S,
@@ -726,12 +737,16 @@ def bench_c3(args, np, torch, vbx, synth):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {S} sweeps of a 64x2048 LiDAR along a street, voxel 0.20 m, "
-                               "truncation 0.60 m, range 60 m, constant weight, per-point raycasting, f32",
-                   "sweeps": S, "points_per_sweep": N},
+        "config": {"workload": f"{w.name}: {S} sweeps of a 64x2048 LiDAR along a street, "
+                               f"voxel {P['voxel_size']:g} m, truncation {P['trunc']:g} m, range 60 m, "
+                               "constant weight, per-point raycasting"
+                               + (" of the whole ray from the sensor" if full else " of the truncation band")
+                               + ", f32",
+                   "sweeps": S, "points_per_sweep": N, "full_ray": full, "voxel_size": P["voxel_size"]},
         "voxel_updates_per_s": round(st["touches"] / (ms / 1e3), 1),
         "blocks": st["blocks"],
         "blocks_allocated_per_s": round(st["new_blocks"] / (ms / 1e3), 1),
+        "block_hash": {"batched": hstats, "streamed": hash_stream},
         "streamed": {"ms_total": round(stream_ms, 3), "wall_s": round(stream_wall, 3),
                      "rehashes": rehash, "initial_capacity": C3_INITIAL_CAPACITY, "final_capacity": cap,
                      "points_per_s": round(S * N / (stream_ms / 1e3), 1),
@@ -1261,6 +1276,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch tuning instead of timing the candidates first")
+    ap.add_argument("--voxel", type=float, default=None,
+                    help="c3: voxel size (metres) instead of the workload's 0.20 m; truncation 3 voxels")
+    ap.add_argument("--full-ray", action="store_true",
+                    help="c3: walk every ray from the sensor (free space carved; the map grows far larger)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--summarize", action="store_true",

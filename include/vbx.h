@@ -290,6 +290,20 @@ int vbx_last_touches(vbx_map* map, int32_t* coords, uint32_t* counts, size_t cap
 /* Cumulative statistics of the map (synchronises). */
 int vbx_map_stats(vbx_map* map, vbx_stats* out);
 
+/* Occupancy of the map's block hash (Sec. III: blocks are indexed by position through a hash
+ * table; here open addressing with linear probing from a 64-bit mix of the block key).  slots:
+ * table size (twice the pool capacity, rounded up to a power of two, so the pool fills first and
+ * there is no separate hash-full status); blocks: keys held; mean_probe / max_probe: slots a
+ * lookup of a held block reads, from its home slot to its own (1: found at home).  Synchronises. */
+typedef struct {
+    uint64_t slots;
+    uint64_t blocks;
+    double mean_probe;
+    uint32_t max_probe;
+    uint32_t reserved;
+} vbx_hash_stats;
+int vbx_map_hash_stats(vbx_map* map, vbx_hash_stats* out);
+
 /* Distance at query points by trilinear interpolation of the map (the accuracy evaluation of
  * Sec. VI-A: ground-truth surface points are looked up in the field, and the interpolated
  * distance is their error).  points_dev: device [n][3] float32, world frame (metres);

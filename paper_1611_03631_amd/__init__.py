@@ -72,6 +72,11 @@ class Frame(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("pose", ctypes.c_float * 12), ("colors", ctypes.c_void_p)]
 
 
+class HashStats(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint64), ("blocks", ctypes.c_uint64), ("mean_probe", ctypes.c_double),
+                ("max_probe", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("points", "valid", "invalid", "out_of_bounds", "rays", "touches", "voxels",
@@ -81,7 +86,7 @@ class Stats(ctypes.Structure):
 EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_map_destroy",
             "vbx_map_set_stream", "vbx_integrate", "vbx_integrate_batch", "vbx_integrate_frames",
             "vbx_integrate_frames_noalloc", "vbx_integrate_projective", "vbx_write_blocks", "vbx_esdf_enable", "vbx_esdf_update",
-            "vbx_esdf_export", "vbx_export_colors",
+            "vbx_esdf_export", "vbx_export_colors", "vbx_map_hash_stats",
             "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
             "vbx_map_stats", "vbx_map_interpolate", "vbx_debug_traverse", "vbx_status_string",
@@ -165,6 +170,7 @@ def lib(path: Optional[str] = None):
     L.vbx_export_colors.argtypes = [vp, vp, vp, sz, ctypes.POINTER(sz)]
     L.vbx_last_touches.argtypes = [vp, vp, vp, sz, ctypes.POINTER(sz)]
     L.vbx_map_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.vbx_map_hash_stats.argtypes = [vp, ctypes.POINTER(HashStats)]
     L.vbx_debug_traverse.argtypes = [vp, vp, i32, vp, i32, vp]
     L.vbx_status_string.argtypes = [i32]
     L.vbx_status_string.restype = ctypes.c_char_p
@@ -493,6 +499,13 @@ class Map:
                "vbx_map_autotune")
         return {"best": {"update_split": int(best.update_split), "update_threads": int(best.update_threads),
                          "update_columns": int(best.update_columns)}, "ms": list(ms)}
+
+    def hash_stats(self) -> dict:
+        """Block-hash occupancy: slots, blocks, mean and maximum lookup probe length."""
+        h = HashStats()
+        _check(lib().vbx_map_hash_stats(self._h, ctypes.byref(h)), "vbx_map_hash_stats")
+        return {"slots": int(h.slots), "blocks": int(h.blocks), "mean_probe": float(h.mean_probe),
+                "max_probe": int(h.max_probe)}
 
     def stats(self) -> dict:
         s = Stats()

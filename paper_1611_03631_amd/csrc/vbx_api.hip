@@ -1777,6 +1777,29 @@ int vbx_last_touches(vbx_map* m, int32_t* coords, uint32_t* counts, size_t cap, 
     return VBX_OK;
 }
 
+int vbx_map_hash_stats(vbx_map* m, vbx_hash_stats* out) {
+    if (!m || !out) return VBX_ERR_INVALID_ARG;
+    VBX_TRY(hipStreamSynchronize(m->stream));
+    std::vector<u64> keys(m->hcap);
+    VBX_TRY(hipMemcpy(keys.data(), m->hkeys, sizeof(u64) * m->hcap, hipMemcpyDeviceToHost));
+    const u32 mask = m->hcap - 1;
+    uint64_t n = 0, sum = 0;
+    uint32_t mx = 0;
+    for (u32 i = 0; i < m->hcap; ++i) {
+        if (keys[i] == kEmpty) continue;
+        const u32 probe = ((i - ((u32)mix64(keys[i]) & mask)) & mask) + 1u;
+        ++n;
+        sum += probe;
+        mx = probe > mx ? probe : mx;
+    }
+    out->slots = m->hcap;
+    out->blocks = n;
+    out->mean_probe = n ? (double)sum / (double)n : 0.0;
+    out->max_probe = mx;
+    out->reserved = 0;
+    return VBX_OK;
+}
+
 int vbx_map_stats(vbx_map* m, vbx_stats* out) {
     if (!m || !out) return VBX_ERR_INVALID_ARG;
     MapState s;

@@ -1,5 +1,6 @@
 """Full-size workloads in the launch configuration the benchmark times, against the oracle:
-the 50-sweep LiDAR street in one call, and the 32-map tick replayed from a captured graph.
+the 50-sweep LiDAR street in one call (and at 0.05 m voxels, grown past 10^4 blocks), and the
+32-map tick replayed from a captured graph.
 Also the size limits of a call, which must be refused before anything runs."""
 from concurrent.futures import ThreadPoolExecutor
 
@@ -45,6 +46,37 @@ def test_lidar_street_50_sweeps_one_call(vbx):
     log(f"  ok: {res}")
     st = g.stats()
     assert st["points"] == 50 * 64 * 2048 and st["blocks"] == res["blocks"]
+
+
+def test_lidar_street_fine_voxels_grown_past_ten_thousand_blocks(vbx):
+    """The street at 0.05 m voxels: the map grows past 10^4 blocks, sweep by sweep from a pool of
+    256 blocks that the host doubles whenever a sweep finds it full (the sweep is then integrated
+    again into the grown pool), and the final map equals the oracle's (block set bit-exact,
+    constant weights bit-exact, D within the bar).  The block hash stays shallow."""
+    import synth
+    w = synth.config3(n_sweeps=50, cache=False)
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        frames = list(ex.map(w.frame, range(50)))
+    P = dict(w.params, voxel_size=0.05, trunc=0.15)
+    d = dev(np.stack(frames))
+    g = gpu_map(vbx, dict(P, block_capacity=256, keep_touches=False))
+    cap, grown = 256, 0
+    for k in range(50):
+        g.integrate_frames([(d[k], w.poses[k], 2048)])
+        while g.sync() == vbx.ERR_POOL_FULL:      # the map is as it was before the sweep
+            cap *= 2
+            g.reserve(cap)
+            grown += 1
+            g.integrate_frames([(d[k], w.poses[k], 2048)])
+    h = g.hash_stats()
+    log(f"c3 at 0.05 m: {h}, pool grown {grown} times to {cap} blocks")
+    assert h["blocks"] > 10000 and h["blocks"] == g.num_blocks() and h["slots"] >= 2 * cap
+    assert 1.0 <= h["mean_probe"] < 2.0 and h["max_probe"] < 64
+    o = oracle_map(P)
+    for k in range(50):
+        o.integrate(frames[k], w.poses[k])
+    res = compare_export(g.export(), o.export(), P)
+    log(f"  ok: {res}")
 
 
 def test_lidar_street_grouped(vbx):
