@@ -39,11 +39,22 @@ __device__ inline int esdf_neighbour(const EsdfDev& E, u32 slot, u32 l, int n) {
 }
 
 // Appends voxel v to a frontier once per tag: the stamp of v takes the tag, and only the thread
-// that changed it appends.
+// that changed it appends.  The appending lanes of a wave reserve their positions with one
+// atomic (a frontier counter is shared by the whole grid, and single-address atomics are
+// carried out one after another).
 __device__ inline void esdf_push(u32* list, u32* count, u32* stamp, u32 tag, u32 v, u32 cap) {
-    if (atomicExch(&stamp[v], tag) == tag) return;
-    const u32 i = atomicAdd(count, 1u);
-    if (i < cap) list[i] = v;
+    const bool app = atomicExch(&stamp[v], tag) != tag;
+    const u64 m = __ballot(app);                        // over the lanes that reached this call
+    if (m == 0ull) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    u32 base = 0;
+    if (lane == leader) base = atomicAdd(count, (u32)__popcll(m));
+    base = (u32)__shfl((int)base, leader);
+    if (app) {
+        const u32 i = base + (u32)__popcll(m & ((1ull << lane) - 1ull));
+        if (i < cap) list[i] = v;
+    }
 }
 
 }  // namespace
