@@ -773,7 +773,7 @@ def bench_c5(args, np, torch, vbx, synth):
     K = 8                                   # distinct frames per robot, cycled
     seed = synth.SEED_BASE + 5
     rng = np.random.default_rng(seed)
-    rates = rng.uniform(5.0, 30.0, size=R)
+    rates = rng.uniform(5.0, 30.0, size=R) * args.load
     trace = []
     for i in range(R):
         t = rng.exponential(1.0 / rates[i])
@@ -897,10 +897,11 @@ def bench_c5(args, np, torch, vbx, synth):
         "vs_baseline": None,
         "dtype": "f16-storage/f32",
         "data": "synthetic",
-        "config": {"workload": f"c5_served: {R} robots, Poisson U(5,30) Hz each, {args.duration:g} s "
+        "config": {"workload": f"c5_served: {R} robots, Poisson U(5,30) Hz each"
+                               + (f" x {args.load:g}" if args.load != 1.0 else "") + f", {args.duration:g} s "
                                "open-loop trace in real time; 160x120 / 320x240 / 640x480 depth and "
                                "64x2048 LiDAR at voxel 0.02 / 0.05 / 0.10 / 0.20 m; f16; 200 GB budget",
-                   "robots": R, "requests": len(trace), "duration_s": args.duration},
+                   "robots": R, "requests": len(trace), "duration_s": args.duration, "load": args.load},
         "latency_ms": {"p50": round(st["p50_ms"], 4), "p99": round(st["p99_ms"], 4),
                        "max": round(st["max_ms"], 4), "mean": round(st["mean_ms"], 4)},
         "offered_points_per_s": round(offered_pts / args.duration, 1),
@@ -1266,6 +1267,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="c2: skip timing the plain per-frame f32 and batched f16 forms")
     ap.add_argument("--duration", type=float, default=10.0, help="c5: trace length in seconds")
+    ap.add_argument("--load", type=float, default=1.0,
+                    help="c5: multiplies every robot's request rate (1: the workload's 5-30 Hz)")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (c2, c3: 10; c4: 100 ticks)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=100, help="c2: frames of the sequence")
