@@ -84,7 +84,9 @@ enum {
      * A grouped ray's colour is round(sum Omega c / sum Omega) over its points (Omega the
      * points' fixed-point weights of the group mean), computed in integers.  Projection mapping
      * leaves colours unchanged.  New voxels and imported blocks start black; blocks that
-     * vbx_write_blocks overwrites in place keep their colours. */
+     * vbx_write_blocks overwrites in place keep their colours.  Calls with a colour map walk one
+     * frame per step over block regions (the colour sums need the room of a second frame);
+     * results do not depend on it. */
     VBX_FLAG_COLOR = 4u
 };
 

@@ -534,7 +534,7 @@ unsigned sort_resident_waves() {
 }
 
 // Persistent grid of an update-kernel variant: one workgroup per slot the chip can hold.
-template <int STORAGE, int RX, int RY, int RZ, int NT>
+template <int STORAGE, int RX, int RY, int RZ, int NT, bool COLOR = false>
 int update_grid() {
     static int grid = 0;
     static std::once_flag once;
@@ -543,7 +543,7 @@ int update_grid() {
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per, reinterpret_cast<const void*>(&k_update<STORAGE, RX, RY, RZ, NT>), NT, 0) != hipSuccess ||
+                &per, reinterpret_cast<const void*>(&k_update<STORAGE, RX, RY, RZ, NT, COLOR>), NT, 0) != hipSuccess ||
             per < 1)
             per = 1;
         grid = cus * per;
@@ -551,13 +551,14 @@ int update_grid() {
     return grid > 0 ? grid : 256;
 }
 
-template <int STORAGE, int RX, int RY, int RZ, int NT>
+template <int STORAGE, int RX, int RY, int RZ, int NT, bool COLOR = false>
 void launch_update_t(hipStream_t st, const Job* jobs, const MapDesc* maps, const u64* t_key,
-                     const int* t_slot, const u32* off, const u32* order, const float4* sorted, u32 JM,
-                     u64* touch_key, u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
-    hipLaunchKernelGGL((k_update<STORAGE, RX, RY, RZ, NT>), dim3(update_grid<STORAGE, RX, RY, RZ, NT>()), dim3(NT),
-                       0, st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, touch_n, touch_cap,
-                       keep, jst, cs);
+                     const int* t_slot, const u32* off, const u32* order, const float4* sorted,
+                     const u32* sorted_c, u32 JM, u64* touch_key, u32* touch_n, u32 touch_cap, int keep,
+                     JobStat* jst, CallState* cs) {
+    hipLaunchKernelGGL((k_update<STORAGE, RX, RY, RZ, NT, COLOR>),
+                       dim3(update_grid<STORAGE, RX, RY, RZ, NT, COLOR>()), dim3(NT), 0, st, jobs, maps, t_key,
+                       t_slot, off, order, sorted, sorted_c, JM, touch_key, touch_n, touch_cap, keep, jst, cs);
 }
 
 // Update-kernel variants: how a block is cut into regions, and the workgroup size.  Larger
@@ -578,7 +579,7 @@ void launch_update_s(int variant, hipStream_t st, const Job* jobs, const MapDesc
                      const int* t_slot, const u32* off, const u32* order, const float4* sorted, u32 JM,
                      u64* touch_key, u32* touch_n, u32 touch_cap, int keep, JobStat* jst, CallState* cs) {
 #define VBX_UPD(X, Y, Z, T)                                                                        \
-    launch_update_t<STORAGE, X, Y, Z, T>(st, jobs, maps, t_key, t_slot, off, order, sorted, JM, touch_key, \
+    launch_update_t<STORAGE, X, Y, Z, T>(st, jobs, maps, t_key, t_slot, off, order, sorted, nullptr, JM, touch_key, \
                                          touch_n, touch_cap, keep, jst, cs)
     switch (variant) {
         case 0: VBX_UPD(16, 16, 16, 256); break;
@@ -602,6 +603,8 @@ void warm_update_grids() {
     (void)update_grid<STORAGE, 8, 8, 16, 256>();   (void)update_grid<STORAGE, 4, 8, 16, 256>();
     (void)update_grid<STORAGE, 16, 16, 16, 1024>(); (void)update_grid<STORAGE, 16, 16, 8, 1024>();
     (void)update_grid<STORAGE, 16, 16, 4, 1024>();  (void)update_grid<STORAGE, 16, 16, 8, 512>();
+    (void)update_grid<STORAGE, 16, 16, 8, 512, true>(); (void)update_grid<STORAGE, 16, 16, 8, 256, true>();
+    (void)update_grid<STORAGE, 16, 16, 4, 256, true>();
 }
 
 void launch_update(int storage, int variant, hipStream_t st, const Job* jobs, const MapDesc* maps,
@@ -977,23 +980,34 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     StageTimer tm(prof_map, st, ST_UPDATE);
     hipLaunchKernelGGL(k_order_blocks, dim3(1), dim3(1024), 0, st, (const u32*)s->off.p, JM, (u32*)s->order.p,
                        (const CallState*)cs);
-    if (plan.color) {
-        // colours fold with the weights from before the call's frames: ahead of the update
-        const unsigned GC = 1024;   // persistent: workgroups take half blocks from a counter
-#define VBX_COLOR(S)                                                                                          \
-        hipLaunchKernelGGL(k_color<S>, dim3(GC), dim3(256), 0, st, d_jobs, d_maps, (const u64*)s->t_key.p,     \
-                           (const int*)s->t_slot.p, (const u32*)s->off.p, (const float4*)s->sorted.p,          \
-                           (const u32*)sorted_c, JM, cs)
-        if (plan.storage == VBX_F32) VBX_COLOR(0);
-        else if (plan.storage == VBX_F16) VBX_COLOR(1);
-        else VBX_COLOR(2);
-#undef VBX_COLOR
+    if (!plan.color) {
+        launch_update(plan.storage, update_variant, st, d_jobs, d_maps, (const u64*)s->t_key.p,
+                      (const int*)s->t_slot.p, (const u32*)s->off.p, (const u32*)s->order.p,
+                      (const float4*)s->sorted.p, JM,
+                      (u64*)s->touch_key.p, (u32*)s->touch_n.p, (u32)s->touch_cap, plan.keep_touches ? 1 : 0,
+                      jst, cs);
+    } else {
+        // colour calls: z-slab regions, one frame per step, the colour sums beside the others.
+        // The candidates whose sums fit the LDS: quarter blocks of 256 threads (the default;
+        // 0.56 ms on the 100-frame room against 0.66 for half blocks of 512 threads and 0.87 for
+        // half blocks of 256), chosen by the (2, 0, 256) and (2, 0, 512) tunings otherwise.
+#define VBX_UPD_COLOR(S, Z, T)                                                                               \
+        launch_update_t<S, 16, 16, Z, T, true>(st, d_jobs, d_maps, (const u64*)s->t_key.p,                    \
+                                               (const int*)s->t_slot.p, (const u32*)s->off.p,                  \
+                                               (const u32*)s->order.p, (const float4*)s->sorted.p,             \
+                                               (const u32*)sorted_c, JM, (u64*)s->touch_key.p,                 \
+                                               (u32*)s->touch_n.p, (u32)s->touch_cap,                          \
+                                               plan.keep_touches ? 1 : 0, jst, cs)
+#define VBX_UPD_COLOR_S(S)                                                                                   \
+        if (update_variant == 1) VBX_UPD_COLOR(S, 8, 256);                                                    \
+        else if (update_variant == 9) VBX_UPD_COLOR(S, 8, 512);                                               \
+        else VBX_UPD_COLOR(S, 4, 256)
+        if (plan.storage == VBX_F32) { VBX_UPD_COLOR_S(0); }
+        else if (plan.storage == VBX_F16) { VBX_UPD_COLOR_S(1); }
+        else { VBX_UPD_COLOR_S(2); }
+#undef VBX_UPD_COLOR_S
+#undef VBX_UPD_COLOR
     }
-    launch_update(plan.storage, update_variant, st, d_jobs, d_maps, (const u64*)s->t_key.p,
-                  (const int*)s->t_slot.p, (const u32*)s->off.p, (const u32*)s->order.p,
-                  (const float4*)s->sorted.p, JM,
-                  (u64*)s->touch_key.p, (u32*)s->touch_n.p, (u32)s->touch_cap, plan.keep_touches ? 1 : 0,
-                  jst, cs);
     }
     }
     {

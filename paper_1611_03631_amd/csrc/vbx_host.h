@@ -60,13 +60,11 @@ __global__ void k_scatter(const Job* jobs, const u32* cross, const unsigned char
                           u32 MB, const u32* tval, const u32* rays_job, u32* bins,
                           const u32* off, u32 JM, const float4* rays_p, float4* sorted,
                           const u32* rays_c, u32* sorted_c, CallState* cs, u32 ray_cap);
-template <int STORAGE, int RX, int RY, int RZ, int NT>
+template <int STORAGE, int RX, int RY, int RZ, int NT, bool COLOR>
 __global__ void k_update(const Job* jobs, const MapDesc* maps, const u64* t_key, const int* t_slot,
-                         const u32* off, const u32* order, const float4* sorted, u32 JM, u64* touch_key,
-                         u32* touch_n, u32 touch_cap, int keep_touches, JobStat* jst, CallState* cs);
-template <int STORAGE>
-__global__ void k_color(const Job* jobs, const MapDesc* maps, const u64* t_key, const int* t_slot,
-                        const u32* off, const float4* sorted, const u32* sorted_c, u32 JM, CallState* cs);
+                         const u32* off, const u32* order, const float4* sorted, const u32* sorted_c, u32 JM,
+                         u64* touch_key, u32* touch_n, u32 touch_cap, int keep_touches, JobStat* jst,
+                         CallState* cs);
 __global__ void k_order_blocks(const u32* off, u32 JM, u32* order, const CallState* cs);
 __global__ void k_finish_call(const Job* jobs, const MapDesc* maps, int nmaps, JobStat* jst, u64* tkeys,
                               u32 tkey_cap, const u32* tlist, u32 tlist_cap, CallState* cs);

@@ -85,7 +85,6 @@ struct CallState {
     u32 work_merge;    // persistent work counter of the group merge kernel
     u32 scan_done;     // workgroups of the current scan that have written their sum
     u32 finish_done;   // workgroups of the call's last kernel that are done
-    u32 work_color;    // persistent work counter of the colour kernel
 };
 
 // Partial group of one tile (40 bytes): exact integer sums of the tile's points in one voxel.

@@ -1463,14 +1463,20 @@ __global__ __launch_bounds__(1024) void k_order_blocks(const u32* __restrict__ o
 // voxels) and replay the same rays, each ray walked in full but observed only inside the
 // region, so a block's frames run in parallel across NREG workgroups with 1/NREG of the LDS
 // each.  z-slabs divide the rays of walls, x/y columns those of floors and walls alike.
-template <int STORAGE, int RX, int RY, int RZ, int NT>
+//
+// COLOR (maps that keep colour, one frame per step): each voxel also sums weight * channel of
+// the frame's rays (scale 2^(kw - 8)) and, before Eq. (4) changes W, folds the frame's mean ray
+// colour into its colour with the weight from before the frame (Sec. IV-B):
+//   C <- round((W C + sum w c) / (W + sum w)),  binary64 quotient, rounded to even.
+template <int STORAGE, int RX, int RY, int RZ, int NT, bool COLOR>
 __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                                 const MapDesc* __restrict__ maps,
                                                 const u64* __restrict__ t_key,
                                                 const int* __restrict__ t_slot,
                                                 const u32* __restrict__ off,
                                                 const u32* __restrict__ order,
-                                                const float4* __restrict__ sorted, u32 JM,
+                                                const float4* __restrict__ sorted,
+                                                const u32* __restrict__ sorted_c, u32 JM,
                                                 u64* __restrict__ touch_key,
                                                 u32* __restrict__ touch_n, u32 touch_cap,
                                                 int keep_touches,
@@ -1489,6 +1495,8 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
     // has fewer than 2^16 rays in the block; a frame with more is walked alone.  Smaller
     // workgroups walk one frame at a time.
     constexpr int K = NT == 1024 ? 2 : 1;
+    static_assert(!COLOR || K == 1, "colour sums are kept for one frame per step");
+    __shared__ u64 a_sc[3][COLOR ? VOX : 1];   // colour maps: weight * channel sums of the frame
     __shared__ u64 a_w[K][VOX];   // sum of fixed-point weights, per frame of the step
     __shared__ u64 a_d[K][VOX];   // sum of fixed-point weight * distance/delta (two's complement)
     __shared__ u32 a_c[VOX];      // rays over the call (see above)
@@ -1502,6 +1510,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
         a_c[i] = 0;
 #pragma unroll
         for (int h = 0; h < K; ++h) { a_w[h][i] = 0; a_d[h][i] = 0; }
+        if (COLOR) { a_sc[0][i] = 0; a_sc[1][i] = 0; a_sc[2][i] = 0; }
     }
     const u32 nt = cs->error ? 0u : cs->t_count * (u32)NREG;
     for (;;) {
@@ -1528,9 +1537,13 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
         auto block_local = [](int i) { return (i % RX) + 16 * ((i / RX) % RY) + 256 * (i / (RX * RY)); };
         float D[VPT], W[VPT];
         u32 ntot[VPT], last[VPT];
+        u32 C[COLOR ? VPT : 1];
+        // a map without colour can share a colour call with maps that keep it
+        const bool has_color = COLOR && M.color != nullptr;
 #pragma unroll
         for (int j = 0; j < VPT; ++j) {
             ntot[j] = 0;
+            if (COLOR) C[j] = (is_new || !has_color) ? 0u : M.color[vbase + block_local(threadIdx.x + NT * j)];
             if constexpr (K == 2) {   // one frame at a time leaves the counts cleared by its folds
                 last[j] = 0;
                 a_c[threadIdx.x + NT * j] = 0;
@@ -1689,10 +1702,11 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                 int jm = 0;
                 while (jm < wn && s_off[jm] == s_off[jm + 1]) ++jm;
                 float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+                u32 nxc = 0;                       // colour maps: the ray's colour, loaded with it
                 float nxs[3] = {0.f, 0.f, 0.f};   // that frame's sensor origin, also loaded ahead
                 if (jm < wn) {
                     const u32 e = s_off[jm] + threadIdx.x;
-                    if (e < s_off[jm + 1]) nxt = sorted[e];
+                    if (e < s_off[jm + 1]) { nxt = sorted[e]; if (COLOR) nxc = sorted_c[e]; }
                     const Job& Jn = jobs[M.job0 + w0 + jm];
                     nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
                 }
@@ -1700,22 +1714,27 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                     int jn = jm + 1;
                     while (jn < wn && s_off[jn] == s_off[jn + 1]) ++jn;
                     const float4 cur = nxt;
+                    const u32 curc = nxc;
                     const float s[3] = {nxs[0], nxs[1], nxs[2]};
                     const u32 lo = s_off[jm], hi = s_off[jm + 1];
                     if (jn < wn) {
                         const u32 e = s_off[jn] + threadIdx.x;
-                        if (e < s_off[jn + 1]) nxt = sorted[e];
+                        if (e < s_off[jn + 1]) { nxt = sorted[e]; if (COLOR) nxc = sorted_c[e]; }
                         const Job& Jn = jobs[M.job0 + w0 + jn];
                         nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
                     }
                     float4 rp = cur;
+                    u32 rc = curc;
                     for (u32 e = lo + threadIdx.x; e < hi; e += NT) {
                         // the next ray's load is in flight while this one is walked
                         float4 rn = make_float4(0.f, 0.f, 0.f, 0.f);
-                        if (e + NT < hi) rn = sorted[e + NT];
+                        u32 rnc = 0;
+                        if (e + NT < hi) { rn = sorted[e + NT]; if (COLOR) rnc = sorted_c[e + NT]; }
                         const float p[3] = {rp.x, rp.y, rp.z};
                         const float wgt = rp.w;
+                        const float cf[3] = {(float)(rc & 255u), (float)((rc >> 8) & 255u), (float)((rc >> 16) & 255u)};
                         rp = rn;
+                        rc = rnc;
                         float ev[3], r;
                         Walk w;
                         walk_setup(M, p, s, ev, r, w);
@@ -1747,6 +1766,12 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                 atomicAdd(&a_w[0][l], fw);
                                 atomicAdd(&a_d[0][l], (u64)fd);
                                 atomicAdd(&a_c[l], 1u);
+                                if (COLOR) {
+                                    const float cscale = M.wscale * (1.0f / 256.0f);
+#pragma unroll
+                                    for (int k = 0; k < 3; ++k)
+                                        atomicAdd(&a_sc[k][l], (u64)__builtin_rintf(o.w * cf[k] * cscale));
+                                }
                             } else if (inside) {
                                 break;   // the walk is monotone per axis: it never re-enters the region
                             }
@@ -1762,6 +1787,21 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                         const u32 c = a_c[l];
                         if (c) {
                             const u64 sw_fx = a_w[0][l];
+                            if (has_color && sw_fx) {
+                                // colour first, with the weight from before the frame
+                                const double swd64 = (double)sw_fx * (double)M.inv_wscale, Wd = (double)W[j];
+                                const double inv_c = (double)M.inv_wscale * 256.0;
+                                u32 cn = 0;
+#pragma unroll
+                                for (int k = 0; k < 3; ++k) {
+                                    const double ck = (double)((C[j] >> (8 * k)) & 255u);
+                                    double q = __builtin_rint((Wd * ck + (double)a_sc[k][l] * inv_c) / (Wd + swd64));
+                                    q = q < 0.0 ? 0.0 : (q > 255.0 ? 255.0 : q);
+                                    cn |= (u32)q << (8 * k);
+                                }
+                                C[j] = cn;
+                            }
+                            if (COLOR) { a_sc[0][l] = 0; a_sc[1][l] = 0; a_sc[2][l] = 0; }
                             if (sw_fx) {
                                 const float sw = (float)sw_fx * M.inv_wscale;
                                 // sums are in units of delta; binary32 storage keeps D in metres,
@@ -1789,6 +1829,9 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
         }
 #pragma unroll
         for (int j = 0; j < VPT; ++j) store_voxel<STORAGE>(pool, vbase + block_local(threadIdx.x + NT * j), D[j], W[j]);
+        if (has_color)
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) M.color[vbase + block_local(threadIdx.x + NT * j)] = C[j];
         if (threadIdx.x == 0 && M.dirty) M.dirty[slot] = 1u;   // the ESDF layer looks at this block again
         {
             // summed over the wave first: one lane adds (an atomic on one address with a
@@ -1835,238 +1878,124 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
     }
 }
 
-template __global__ void k_update<0, 16, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<0, 16, 16, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<0, 16, 16, 8, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<0, 16, 16, 8, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<0, 16, 16, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<0, 16, 16, 4, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<0, 8, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<0, 8, 16, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<0, 8, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<0, 8, 8, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<0, 4, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<0, 4, 8, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<0, 16, 16, 16, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<0, 16, 16, 16, 1024, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<0, 16, 16, 8, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<0, 16, 16, 8, 1024, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<0, 16, 16, 4, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<0, 16, 16, 4, 1024, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<0, 16, 16, 8, 512>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<0, 16, 16, 8, 512, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<1, 16, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<1, 16, 16, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<1, 16, 16, 8, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<1, 16, 16, 8, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<1, 16, 16, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<1, 16, 16, 4, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<1, 8, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<1, 8, 16, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<1, 8, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<1, 8, 8, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<1, 4, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<1, 4, 8, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<1, 16, 16, 16, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<1, 16, 16, 16, 1024, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<1, 16, 16, 8, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<1, 16, 16, 8, 1024, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<1, 16, 16, 4, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<1, 16, 16, 4, 1024, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<1, 16, 16, 8, 512>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<1, 16, 16, 8, 512, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<2, 16, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<2, 16, 16, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<2, 16, 16, 8, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<2, 16, 16, 8, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<2, 16, 16, 4, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<2, 16, 16, 4, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<2, 8, 16, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<2, 8, 16, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<2, 8, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<2, 8, 8, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<2, 4, 8, 16, 256>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<2, 4, 8, 16, 256, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<2, 16, 16, 16, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<2, 16, 16, 16, 1024, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<2, 16, 16, 8, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<2, 16, 16, 8, 1024, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<2, 16, 16, 4, 1024>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<2, 16, 16, 4, 1024, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
-template __global__ void k_update<2, 16, 16, 8, 512>(const Job*, const MapDesc*, const u64*, const int*,
-                                                        const u32*, const u32*, const float4*, u32, u64*, u32*, u32,
+template __global__ void k_update<2, 16, 16, 8, 512, false>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*, u32*, u32,
                                                         int, JobStat*, CallState*);
+template __global__ void k_update<0, 16, 16, 8, 512, true>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*,
+                                                        u32*, u32, int, JobStat*, CallState*);
+template __global__ void k_update<1, 16, 16, 8, 512, true>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*,
+                                                        u32*, u32, int, JobStat*, CallState*);
+template __global__ void k_update<2, 16, 16, 8, 512, true>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*,
+                                                        u32*, u32, int, JobStat*, CallState*);
+template __global__ void k_update<0, 16, 16, 8, 256, true>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*,
+                                                        u32*, u32, int, JobStat*, CallState*);
+template __global__ void k_update<0, 16, 16, 4, 256, true>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*,
+                                                        u32*, u32, int, JobStat*, CallState*);
+template __global__ void k_update<1, 16, 16, 8, 256, true>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*,
+                                                        u32*, u32, int, JobStat*, CallState*);
+template __global__ void k_update<1, 16, 16, 4, 256, true>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*,
+                                                        u32*, u32, int, JobStat*, CallState*);
+template __global__ void k_update<2, 16, 16, 8, 256, true>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*,
+                                                        u32*, u32, int, JobStat*, CallState*);
+template __global__ void k_update<2, 16, 16, 4, 256, true>(const Job*, const MapDesc*, const u64*, const int*,
+                                                        const u32*, const u32*, const float4*, const u32*, u32, u64*,
+                                                        u32*, u32, int, JobStat*, CallState*);
 
-// ---------------------------------------------------------------------------
-// colour (Sec. IV-B): per voxel and frame, the frame's weighted mean ray colour is folded into
-// the stored colour with the voxel's weight from before the frame,
-//   C <- round((W C + sum_i w_i c_i) / (W + sum_i w_i))   per channel (to nearest, ties to even).
-// Runs before the update kernel (which then changes W) and replays its walks, observations and
-// weight recurrence exactly (same fixed-point weight sums, same binary32 W, same storage
-// rounding), over half blocks of 16 x 16 x 8 voxels.  Only colour is written.
-// ---------------------------------------------------------------------------
-template <int STORAGE>
-__global__ __launch_bounds__(256) void k_color(const Job* __restrict__ jobs,
-                                               const MapDesc* __restrict__ maps,
-                                               const u64* __restrict__ t_key,
-                                               const int* __restrict__ t_slot,
-                                               const u32* __restrict__ off,
-                                               const float4* __restrict__ sorted,
-                                               const u32* __restrict__ sorted_c, u32 JM,
-                                               CallState* __restrict__ cs) {
-    constexpr int RX = 16, RY = 16, RZ = 8, NT = 256;
-    constexpr int VOX = RX * RY * RZ, VPT = VOX / NT, NREG = 4096 / VOX;
-    __shared__ u64 a_w[VOX];      // fixed-point weight sums of the frame (scale 2^kw)
-    __shared__ u64 a_c[3][VOX];   // fixed-point weight * channel sums (scale 2^(kw - 8))
-    __shared__ u32 s_off[kOffWindow + 1];
-    __shared__ u32 s_t;
-    for (int i = threadIdx.x; i < VOX; i += NT) {
-        a_w[i] = 0; a_c[0][i] = 0; a_c[1][i] = 0; a_c[2][i] = 0;
-    }
-    const u32 nt = cs->error ? 0u : cs->t_count * (u32)NREG;
-    for (;;) {
-        if (threadIdx.x == 0) s_t = atomicAdd(&cs->work_color, 1u);
-        __syncthreads();
-        const u32 u = s_t;
-        if (u >= nt) break;
-        const u32 t = u / (u32)NREG;
-        const int qz = (int)(u % (u32)NREG);
-        const u64 tk = t_key[t];
-        const MapDesc M = maps[(u32)(tk >> 45)];
-        if (M.color == nullptr || M.st->error != 0) { __syncthreads(); continue; }
-        int bx, by, bz;
-        unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
-        const int ts = t_slot[t];
-        const bool is_new = (ts & 0x40000000) != 0;
-        const size_t slot = (size_t)(ts & 0x3FFFFFFF);
-        const size_t vbase = slot * 4096 + (size_t)(256 * (qz * RZ));   // the region is contiguous
-        float W[VPT];
-        u32 C[VPT];
-#pragma unroll
-        for (int j = 0; j < VPT; ++j) {
-            const size_t idx = vbase + (size_t)(threadIdx.x + NT * j);
-            if (is_new) { W[j] = 0.0f; C[j] = 0u; }
-            else {
-                float Dj;
-                load_voxel<STORAGE>(M.pool, idx, Dj, W[j]);
-                C[j] = M.color[idx];
-            }
-        }
-        const int ox = 16 * bx, oy = 16 * by, oz = 16 * bz + qz * RZ;
-        const float cscale = M.wscale * (1.0f / 256.0f);
-        const double inv_w = (double)M.inv_wscale, inv_c = (double)M.inv_wscale * 256.0;
-        for (int w0 = 0; w0 < M.njobs; w0 += kOffWindow) {
-            const int wn = M.njobs - w0 < kOffWindow ? M.njobs - w0 : kOffWindow;
-            for (int k = threadIdx.x; k <= wn; k += NT) s_off[k] = off[t * JM + (u32)(w0 + k)];
-            __syncthreads();
-            for (int jm = 0; jm < wn; ++jm) {
-                const u32 lo = s_off[jm], hi = s_off[jm + 1];
-                if (lo == hi) continue;                       // same in every thread
-                const Job& J = jobs[M.job0 + w0 + jm];
-                const float s[3] = {J.pose[3], J.pose[7], J.pose[11]};
-                for (u32 e = lo + threadIdx.x; e < hi; e += NT) {
-                    const float4 rp = sorted[e];
-                    const u32 col = sorted_c[e];
-                    const float p[3] = {rp.x, rp.y, rp.z};
-                    float ev[3], r;
-                    Walk w;
-                    walk_setup(M, p, s, ev, r, w);
-                    // every walk index lies between its end voxels: skip bands that miss the region
-                    {
-                        const int g_end = w.g[2] + w.step[2] * w.n[2];
-                        const int glo = w.g[2] < g_end ? w.g[2] : g_end;
-                        const int ghi = w.g[2] < g_end ? g_end : w.g[2];
-                        if (ghi < oz || glo >= oz + RZ) continue;
-                    }
-                    const float cf[3] = {(float)(col & 255u), (float)((col >> 8) & 255u), (float)((col >> 16) & 255u)};
-                    bool inside = false;
-                    for (int guard = 0; guard < M.max_steps; ++guard) {
-                        const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
-                        if ((u32)lx < (u32)RX && (u32)ly < (u32)RY && (u32)lz < (u32)RZ) {
-                            inside = true;
-                            const Obs o = observe(M, p, ev, r, rp.w, w.g[0], w.g[1], w.g[2]);
-                            const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
-                            // the weight sum exactly as the update kernel forms it
-                            atomicAdd(&a_w[l], (u64)__builtin_rintf(o.w * M.wscale));
-#pragma unroll
-                            for (int k = 0; k < 3; ++k)
-                                atomicAdd(&a_c[k][l], (u64)__builtin_rintf(o.w * cf[k] * cscale));
-                        } else if (inside) {
-                            break;   // the walk is monotone per axis: it never re-enters the region
-                        }
-                        if (w.left == 0) break;
-                        walk_step(w);
-                    }
-                }
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < VPT; ++j) {
-                    const int l = threadIdx.x + NT * j;
-                    const u64 sw_fx = a_w[l];
-                    if (!sw_fx) continue;
-                    // colour with the weight before the frame (binary64: the quotient is rounded
-                    // once, then to the nearest integer)
-                    const double sw = (double)sw_fx * inv_w, Wd = (double)W[j];
-                    u32 cn = 0;
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const double ck = (double)((C[j] >> (8 * k)) & 255u);
-                        double q = __builtin_rint((Wd * ck + (double)a_c[k][l] * inv_c) / (Wd + sw));
-                        q = q < 0.0 ? 0.0 : (q > 255.0 ? 255.0 : q);
-                        cn |= (u32)q << (8 * k);
-                    }
-                    C[j] = cn;
-                    // Eq. (4) as the update kernel takes it: binary32, capped, rounded to storage
-                    float Wn = W[j] + (float)sw_fx * M.inv_wscale;
-                    if (Wn > M.w_max) Wn = M.w_max;
-                    if (STORAGE != 0) Wn = __half2float(__float2half_rn(Wn));
-                    W[j] = Wn;
-                    a_w[l] = 0; a_c[0][l] = 0; a_c[1][l] = 0; a_c[2][l] = 0;
-                }
-                __syncthreads();
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < VPT; ++j) M.color[vbase + (size_t)(threadIdx.x + NT * j)] = C[j];
-        __syncthreads();
-    }
-}
-
-template __global__ void k_color<0>(const Job*, const MapDesc*, const u64*, const int*, const u32*, const float4*,
-                                    const u32*, u32, CallState*);
-template __global__ void k_color<1>(const Job*, const MapDesc*, const u64*, const int*, const u32*, const float4*,
-                                    const u32*, u32, CallState*);
-template __global__ void k_color<2>(const Job*, const MapDesc*, const u64*, const int*, const u32*, const float4*,
-                                    const u32*, u32, CallState*);
 
 // ---------------------------------------------------------------------------
 // finish: commit block counts, fold statistics, clean per-call tables
@@ -2167,7 +2096,6 @@ __global__ __launch_bounds__(256) void k_finish_call(const Job* __restrict__ job
         cs->t_count = 0;
         cs->work_next = 0;
         cs->work_merge = 0;
-        cs->work_color = 0;
         cs->scan_done = 0;
         cs->error = 0;
         cs->finish_done = 0;

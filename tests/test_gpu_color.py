@@ -154,3 +154,21 @@ def test_color_requires_point_colours(vbx):
     plain = gpu_map(vbx, P)
     with pytest.raises(vbx.VbxError):
         plain.export_colors()
+
+
+@pytest.mark.parametrize("tuning", [(2, 256, 0), (2, 512, 0)])
+def test_color_update_candidates_agree(vbx, tuning):
+    """The colour update's launch candidates (half or quarter blocks) give the same map and
+    colours as the default one."""
+    P = dict(voxel_size=0.05, trunc=0.15, weighting="quad", merge="grouped", storage="f32",
+             max_range=5.0, color=True, keep_touches=False)
+    dev = _dev(_frames(5, seed_off=904))
+    a = gpu_map(vbx, P)
+    a.integrate_frames(dev)
+    b = gpu_map(vbx, P)
+    b.set_tuning(*tuning)
+    b.integrate_frames(dev)
+    assert a.sync() == 0 and b.sync() == 0
+    ea, eb = a.export(), b.export()
+    assert np.array_equal(ea[0], eb[0]) and np.array_equal(ea[1], eb[1])
+    assert np.array_equal(a.export_colors()[1], b.export_colors()[1])
