@@ -289,7 +289,7 @@ int alloc_storage(vbx_map* m, u32 capacity) {
     if (m->P.flags & VBX_FLAG_COLOR) {
         if (map_alloc(m, (void**)&m->color, (size_t)capacity * 4096 * sizeof(u32)) != VBX_OK)
             return VBX_ERR_OUT_OF_MEMORY;
-        // a slot's colour starts black: only the colour kernel writes it afterwards
+        // a slot's colour starts black: only the update of a colour call writes it afterwards
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((size_t)capacity * 4096, 8192)), dim3(256), 0, m->stream,
                            m->color, 0u, (size_t)capacity * 4096);
     }
