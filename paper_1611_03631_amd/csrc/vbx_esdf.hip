@@ -129,12 +129,20 @@ __global__ void k_esdf_seed(const MapDesc M, EsdfDev E, u32 tag_raise, u32 tag_l
             E.vox[v] = esdf_word(E.d_max, side | kEsdfObserved | kEsdfNoParent);
             esdf_push(E.raise[0], &E.cnt[kEsdfRaiseCount], E.rstamp, tag_raise, v, E.fcap);
         } else if (!observed) {
-            // a new voxel outside the band: d_max on its side; its neighbours pass it distances
+            // a new voxel outside the band: d_max on its side; its neighbours pass it distances.
+            // Only a neighbour that holds a distance below d_max (or is fixed) can pass one: a
+            // neighbour at d_max, or unobserved, offers nothing; one that changes in this update
+            // enters the waves through its own seed.
             E.vox[v] = esdf_word(E.d_max, side | kEsdfObserved | kEsdfNoParent);
             for (int n = 0; n < 27; ++n) {
                 if (n == 13) continue;
                 const int u = esdf_neighbour(E, slot, l, n);
-                if (u >= 0) esdf_push(E.lower[0], &E.cnt[kEsdfLowerCount], E.lstamp, tag_lower, (u32)u, E.fcap);
+                if (u < 0) continue;
+                const u64 wu = E.vox[u];
+                const u32 lu = (u32)wu;
+                if (!(lu & kEsdfObserved)) continue;
+                if (!(lu & kEsdfFixed) && !(esdf_mag(wu) < E.d_max)) continue;
+                esdf_push(E.lower[0], &E.cnt[kEsdfLowerCount], E.lstamp, tag_lower, (u32)u, E.fcap);
             }
         }
     }
@@ -161,11 +169,12 @@ __global__ void k_esdf_raise(EsdfDev E, u32 r, u32 tag_next, u32 tag_lower) {
             if (n == 13) continue;
             const int u = esdf_neighbour(E, slot, l, n);
             if (u < 0) continue;
-            const u32 lu = (u32)E.vox[u];
+            const u64 wu = E.vox[u];
+            const u32 lu = (u32)wu;
             if (!(lu & kEsdfObserved)) continue;
             if (!(lu & kEsdfFixed) && (lu & kEsdfParentMask) == (u32)(26 - n))
                 esdf_push(out, n_out, E.rstamp, tag_next, (u32)u, E.fcap);
-            else
+            else if ((lu & kEsdfFixed) || esdf_mag(wu) < E.d_max)   // one at d_max offers nothing
                 esdf_push(E.lower[0], &E.cnt[kEsdfLowerCount], E.lstamp, tag_lower, (u32)u, E.fcap);
         }
     }
