@@ -107,6 +107,7 @@ struct Esdf {
     u32 dirty_cap = 0;
     DevBuf rstamp, lstamp, list, nbr, slot_key, raise0, raise1, lower0, lower1, cnt;
     u32 tag = 0;                 // last frontier tag handed out (tags only grow)
+    u32 nbr_blocks = 0;          // blocks the neighbour tables were built for (0: rebuild)
     vbx_esdf_stats stats = {};
 };
 
@@ -1139,6 +1140,7 @@ int esdf_grow_dirty(vbx_map* m) {
 void esdf_reset(vbx_map* m, size_t mark) {
     Esdf* e = m->esdf;
     if (!e) return;
+    e->nbr_blocks = 0;   // the blocks were dropped or replaced
     if (e->vox_blocks)
         hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(e->vox_blocks * 4096)), dim3(256), 0, m->stream, e->vox, 0ull,
                            e->vox_blocks * 4096);
@@ -1989,11 +1991,15 @@ int vbx_esdf_update(vbx_map* m, vbx_esdf_stats* out) {
     E.step[2] = (float)((double)v * std::sqrt(2.0));
     E.step[3] = (float)((double)v * std::sqrt(3.0));
     const MapDesc d = make_desc(m, 0, 0, 0);
-    // neighbour blocks of every block (new blocks change their neighbours' tables too)
-    hipLaunchKernelGGL(k_esdf_slot_keys, dim3(grid_for(m->hcap)), dim3(256), 0, st, m->hkeys, m->hslots, m->hcap,
-                       (u64*)e->slot_key.p);
-    hipLaunchKernelGGL(k_esdf_neighbours, dim3(grid_for((size_t)nb * 27)), dim3(256), 0, st, d,
-                       (const u64*)e->slot_key.p, nb, (int*)e->nbr.p);
+    // neighbour blocks of every block, rebuilt when blocks were added (new blocks change their
+    // neighbours' tables too); blocks only come and go together with a reset otherwise
+    if (e->nbr_blocks != nb) {
+        hipLaunchKernelGGL(k_esdf_slot_keys, dim3(grid_for(m->hcap)), dim3(256), 0, st, m->hkeys, m->hslots,
+                           m->hcap, (u64*)e->slot_key.p);
+        hipLaunchKernelGGL(k_esdf_neighbours, dim3(grid_for((size_t)nb * 27)), dim3(256), 0, st, d,
+                           (const u64*)e->slot_key.p, nb, (int*)e->nbr.p);
+        e->nbr_blocks = nb;
+    }
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, E.cnt, 0u, (size_t)kEsdfCounters);
     hipLaunchKernelGGL(k_esdf_dirty_list, dim3(grid_for(nb)), dim3(256), 0, st, e->dirty, nb, E.list,
                        E.cnt + kEsdfDirtyCount);
