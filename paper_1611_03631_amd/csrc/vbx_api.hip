@@ -231,6 +231,10 @@ MapDesc make_desc(const vbx_map* m, int map_id, int job0, int njobs) {
     d.iv = 1.0f / P.voxel_size;
     d.delta = P.trunc;
     d.inv_delta = 1.0f / P.trunc;
+    {
+        const float e = d.delta * d.inv_delta;   // binary32, as the kernels form d / delta
+        d.e_max = e < 1.0f ? e : 1.0f;
+    }
     d.eps = P.voxel_size;
     d.ramp = 1.0f / (P.trunc - P.voxel_size);
     d.w_max = P.w_max;

@@ -37,7 +37,8 @@ constexpr int kMaxStepsPerRay = 96;    // guard of the traversal check only (wal
 struct MapDesc {
     float v, iv, delta, inv_delta;  // voxel size, 1/v (binary32), truncation, 1/delta
     float eps, ramp, w_max, rmax2;  // Eq. (5) epsilon = v, 1/(delta-eps), W_max, max_range^2
-    float z_min, wscale, inv_wscale, pad0;  // weight fixed-point scale 2^kw and 2^-kw
+    float z_min, wscale, inv_wscale;  // weight fixed-point scale 2^kw and 2^-kw
+    float e_max;                    // min(fl(delta * (1/delta)), 1): bound of a clamped d / delta
     int weighting, merge, storage, dist;
     int wbits;                      // grouped-mean weight bits (0: unit weights)
     int njobs, job0;                // this map's frames in the call: jobs [job0, job0+njobs)
@@ -350,8 +351,8 @@ __device__ inline Obs observe(const MapDesc& M, const float p[3], const float e[
     float d;
     if (M.dist == 0) {
         const float dot = (f0 * e[0] + f1 * e[1]) + f2 * e[2];
-        // correctly rounded square root of the exact-centre offset
-        const float mag = __builtin_sqrtf((h0 * h0 + h1 * h1) + h2 * h2);
+        // the hardware square root (within 1 ulp of the exact root) of the exact-centre offset
+        const float mag = __builtin_amdgcn_sqrtf((h0 * h0 + h1 * h1) + h2 * h2);
         d = dot > 0.0f ? mag : (dot < 0.0f ? -mag : 0.0f);
     } else {
         // the projective distance is continuous in the offset: no binary32 sign decision
@@ -364,11 +365,30 @@ __device__ inline Obs observe(const MapDesc& M, const float p[3], const float e[
         fdrop = d > -M.eps ? 1.0f : (d > -M.delta ? ramp : 0.0f);
     }
     o.w = wgt * fdrop;
-    float dc = d < -M.delta ? -M.delta : (d > M.delta ? M.delta : d);
-    o.e = dc * M.inv_delta;
-    if (o.e > 1.0f) o.e = 1.0f;
-    if (o.e < -1.0f) o.e = -1.0f;
+    // d clamped to [-delta, delta], over delta, clamped to [-1, 1]: the rounded product is
+    // monotone in d and equals e_max at d = delta, so one clamp of d / delta gives the same value
+    o.e = __builtin_amdgcn_fmed3f(d * M.inv_delta, -M.e_max, M.e_max);
     return o;
+}
+
+// rint(x) (ties to even) as a two's-complement 64-bit integer, for |x| < 2^51: binary64 holds x
+// exactly, and adding 1.5 * 2^52 rounds it to an integer, held in the low mantissa bits.
+__device__ inline u64 rint_fixed51(float x) {
+    const u64 b = (u64)__double_as_longlong((double)x + 6755399441055744.0);
+    return ((u64)((u32)(b >> 32) - 0x43380000u) << 32) | (u64)(u32)b;
+}
+
+// The fixed-point terms of one observation, rint(w 2^kw) and rint(w e 2^kw).  A wave whose
+// weights all lie below 2^51 in fixed point (every ray of fewer than 2^(51 - kw) points'
+// weight) takes the short binary64 form; otherwise the general 64-bit conversion.
+__device__ inline void fixed_terms(float xw, float xd, u64& fw, u64& fd) {
+    if (__builtin_expect(__ballot(!(xw < 0x1p51f)) == 0ull, 1)) {
+        fw = rint_fixed51(xw);
+        fd = rint_fixed51(xd);
+    } else {
+        fw = (u64)__builtin_rintf(xw);
+        fd = (u64)(i64)__builtin_rintf(xd);
+    }
 }
 
 }  // namespace vbx

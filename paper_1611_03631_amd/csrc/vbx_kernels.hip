@@ -1640,12 +1640,12 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                 inside = true;
                                 const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
                                 const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
-                                const u64 fw = (u64)__builtin_rintf(o.w * M.wscale);
-                                const i64 fd = (i64)__builtin_rintf(o.w * o.e * M.wscale);
+                                u64 fw, fd;
+                                fixed_terms(o.w * M.wscale, o.w * o.e * M.wscale, fw, fd);
                                 // issued unconditionally: a wave issues an LDS atomic once for
                                 // all its lanes, and adding zero is harmless
                                 atomicAdd(&sw_buf[l], fw);
-                                atomicAdd(&sd_buf[l], (u64)fd);
+                                atomicAdd(&sd_buf[l], fd);
                                 atomicAdd(&a_c[l], S.cadd);
                             } else if (inside) {
                                 break;   // the walk is monotone per axis: it never re-enters the region
@@ -1759,12 +1759,12 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                 inside = true;
                                 const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
                                 const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
-                                const u64 fw = (u64)__builtin_rintf(o.w * M.wscale);
-                                const i64 fd = (i64)__builtin_rintf(o.w * o.e * M.wscale);
+                                u64 fw, fd;
+                                fixed_terms(o.w * M.wscale, o.w * o.e * M.wscale, fw, fd);
                                 // issued unconditionally: a wave issues an LDS atomic once for
                                 // all its lanes, and adding zero is harmless
                                 atomicAdd(&a_w[0][l], fw);
-                                atomicAdd(&a_d[0][l], (u64)fd);
+                                atomicAdd(&a_d[0][l], fd);
                                 atomicAdd(&a_c[l], 1u);
                                 if (COLOR) {
                                     const float cscale = M.wscale * (1.0f / 256.0f);

@@ -71,9 +71,9 @@ def _ulp_half(x: np.ndarray) -> np.ndarray:
 def distance_error(params: dict) -> float:
     """Bound e on the difference between the kernel's binary32 Eq. (1) distance and the exact one
     from the same ray end point: each offset p_k - (g_k + 1/2) v is formed from the exact centre
-    with two roundings (2u relative, u = 2^-24), the squared norm adds three more and the square
-    root halves the total and adds one: 4u |p - x| in all, with |p - x| <= delta + v for a voxel
-    the band visits.  Twice that is the stated bound."""
+    with two roundings (2u relative, u = 2^-24), the squared norm adds three more, the square
+    root halves the total and the hardware root (within one ulp) adds two: 5.5u |p - x| in all,
+    with |p - x| <= delta + v for a voxel the band visits.  The stated bound rounds that up to 8u."""
     v = float(np.float32(params["voxel_size"]))
     delta = float(np.float32(params["trunc"]))
     if "dist_err" in params:        # a path whose distance error has another bound (stated there)
