@@ -380,6 +380,14 @@ int vbx_esdf_export(vbx_map* map, int32_t* coords, float* d, uint8_t* info, size
 int vbx_debug_traverse(const float* A_dev, const float* B_dev, int n, int32_t* out_dev,
                        int cap, int32_t* counts_dev);
 
+/* The 16^3 blocks of the same traversals, in order, as the integration finds them: from the
+ * traversal's block-changing steps alone (Sec. III: a ray is integrated into the blocks its
+ * truncation band passes through).  Block indices (voxel index >> 4) to out_dev[i][cap][3]
+ * (int32), block count to counts_dev[i] (may exceed cap; -1 for a segment outside the voxel
+ * range).  Runs on the null stream and synchronises. */
+int vbx_debug_traverse_blocks(const float* A_dev, const float* B_dev, int n, int32_t* out_dev,
+                              int cap, int32_t* counts_dev);
+
 /* Removes every block and restarts the statistics (stream-ordered, asynchronous).  The
  * pool keeps its capacity; the next call allocates blocks from the start again. */
 int vbx_map_clear(vbx_map* map);

@@ -89,7 +89,8 @@ EXPORTED = ["vbx_default_params", "vbx_map_create", "vbx_map_create_ex", "vbx_ma
             "vbx_esdf_export", "vbx_export_colors", "vbx_map_hash_stats",
             "vbx_integrate_multi", "vbx_map_sync", "vbx_map_clear_error", "vbx_map_reserve",
             "vbx_map_num_blocks", "vbx_export_blocks", "vbx_import_blocks", "vbx_last_touches",
-            "vbx_map_stats", "vbx_map_interpolate", "vbx_debug_traverse", "vbx_status_string",
+            "vbx_map_stats", "vbx_map_interpolate", "vbx_debug_traverse", "vbx_debug_traverse_blocks",
+            "vbx_status_string",
             "vbx_map_clear",
             "vbx_map_profile", "vbx_map_profile_read", "vbx_map_profile_stages", "vbx_profile_stage_name",
             "vbx_map_get_tuning", "vbx_map_set_tuning", "vbx_map_autotune",
@@ -172,6 +173,7 @@ def lib(path: Optional[str] = None):
     L.vbx_map_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.vbx_map_hash_stats.argtypes = [vp, ctypes.POINTER(HashStats)]
     L.vbx_debug_traverse.argtypes = [vp, vp, i32, vp, i32, vp]
+    L.vbx_debug_traverse_blocks.argtypes = [vp, vp, i32, vp, i32, vp]
     L.vbx_status_string.argtypes = [i32]
     L.vbx_status_string.restype = ctypes.c_char_p
     L.vbx_map_clear.argtypes = [vp]
@@ -673,4 +675,15 @@ def debug_traverse(A: torch.Tensor, B: torch.Tensor, cap: int = 128):
     counts = torch.zeros(n, dtype=torch.int32, device=A.device)
     _check(lib().vbx_debug_traverse(A.data_ptr(), B.data_ptr(), n, out.data_ptr(), cap,
                                     counts.data_ptr()), "vbx_debug_traverse")
+    return out, counts
+
+
+def debug_traverse_blocks(A: torch.Tensor, B: torch.Tensor, cap: int = 128):
+    """Blocks (voxel index >> 4) passed through from A[i] to B[i] (voxel units, device float32
+    [n,3]), found as the integration finds them."""
+    n = A.shape[0]
+    out = torch.zeros((n, cap, 3), dtype=torch.int32, device=A.device)
+    counts = torch.zeros(n, dtype=torch.int32, device=A.device)
+    _check(lib().vbx_debug_traverse_blocks(A.data_ptr(), B.data_ptr(), n, out.data_ptr(), cap,
+                                           counts.data_ptr()), "vbx_debug_traverse_blocks")
     return out, counts

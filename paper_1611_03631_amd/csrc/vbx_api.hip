@@ -522,6 +522,24 @@ int group_merge_grid() {
     return grid > 0 ? grid : 256;
 }
 
+// Workgroups of the crossing kernel that the chip holds at once (its LDS block set allows
+// fewer per CU than the thread limit): a persistent grid of that many, since a larger grid
+// runs its last workgroups in a second, mostly idle round.
+unsigned cross_grid() {
+    static unsigned grid = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0, cus = 256, per = 1;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_cross), 256, 0) !=
+                hipSuccess || per < 1)
+            per = 1;
+        grid = (unsigned)cus * (unsigned)per;
+    });
+    return grid > 0 ? grid : 256u;
+}
+
 // Waves of the partial-group sort kernels that the chip holds at once.
 unsigned sort_resident_waves() {
     static unsigned waves = 0;
@@ -844,6 +862,7 @@ NoAllocDevice g_noalloc[kNoAllocDevices];
 void warm_launch_shapes() {
     (void)group_merge_grid();
     (void)sort_resident_waves();
+    (void)cross_grid();
     warm_update_grids<0>();
     warm_update_grids<1>();
     warm_update_grids<2>();
@@ -926,10 +945,11 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
                                (const PartialColor*)parts_sorted_c, rays_p, rays_job, rays_c, jst, cs);
     }
     const unsigned G = grid_for(plan.ray_slots, 2048);
+    const unsigned GC = std::min(G, cross_grid());
     const u32 MB = (u32)plan.max_blocks;
     {
     StageTimer tm(prof_map, st, ST_CROSS);
-    hipLaunchKernelGGL(k_cross, dim3(G), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
+    hipLaunchKernelGGL(k_cross, dim3(GC), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
                        (const u32*)rays_job, (u64*)s->tkeys.p, (u32)(s->tkey_cap - 1), (u32*)s->tlist.p,
                        (u32)s->tlist_cap, (u32*)s->cross.p, (unsigned char*)s->ncross.p, MB, jst, cs, ray_cap);
     }
@@ -1860,6 +1880,18 @@ int vbx_debug_traverse(const float* A_dev, const float* B_dev, int n, int32_t* o
         return VBX_ERR_INVALID_ARG;
     if (n == 0) return VBX_OK;
     hipLaunchKernelGGL(k_debug_traverse, dim3((n + 255) / 256), dim3(256), 0, nullptr, A_dev, B_dev, n,
+                       (int*)out_dev, cap, (int*)counts_dev);
+    VBX_TRY(hipGetLastError());
+    VBX_TRY(hipStreamSynchronize(nullptr));
+    return VBX_OK;
+}
+
+int vbx_debug_traverse_blocks(const float* A_dev, const float* B_dev, int n, int32_t* out_dev, int cap,
+                              int32_t* counts_dev) {
+    if (n < 0 || cap < 0 || (n > 0 && (!A_dev || !B_dev || !counts_dev || (cap > 0 && !out_dev))))
+        return VBX_ERR_INVALID_ARG;
+    if (n == 0) return VBX_OK;
+    hipLaunchKernelGGL(k_debug_traverse_blocks, dim3((n + 255) / 256), dim3(256), 0, nullptr, A_dev, B_dev, n,
                        (int*)out_dev, cap, (int*)counts_dev);
     VBX_TRY(hipGetLastError());
     VBX_TRY(hipStreamSynchronize(nullptr));

@@ -82,6 +82,8 @@ __global__ void k_project(const Job* jobs, const MapDesc* maps, const u64* t_key
                           CallState* cs);
 __global__ void k_debug_traverse(const float* A, const float* B, int n, int* out, int cap,
                                  int* counts);
+__global__ void k_debug_traverse_blocks(const float* A, const float* B, int n, int* out, int cap,
+                                 int* counts);
 
 constexpr int kScanChunkHost = 4096;
 

@@ -11,6 +11,8 @@
 #include <cstring>
 #include <stdint.h>
 
+#include "vbx_walk.h"
+
 #pragma clang fp contract(off)
 
 namespace vbx {
@@ -229,14 +231,6 @@ __device__ inline int classify_point(const MapDesc& M, const float* pose, float 
 // ---------------------------------------------------------------------------
 // Ray set-up and traversal of the truncation band (binary32, fixed order)
 // ---------------------------------------------------------------------------
-struct Walk {
-    int g[3];        // current voxel
-    int n[3];        // steps left per axis
-    int step[3];
-    float tM[3], tD[3];
-    int left;        // total steps left
-};
-
 // Segment of the ray s->p inside the band [max(r - delta, 0), r + delta]; returns
 // false (out of bounds) when r == 0 or an end lies outside the voxel range.
 __device__ inline bool walk_setup(const MapDesc& M, const float p[3], const float s[3],
@@ -280,51 +274,6 @@ __device__ inline bool walk_setup(const MapDesc& M, const float p[3], const floa
         w.left += w.n[k];
     }
     return true;
-}
-
-// Traversal from voxel-space end points directly (verification entry point).
-__device__ inline void walk_setup_vox(const float A[3], const float B[3], Walk& w) {
-    w.left = 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        int ga = (int)__builtin_floorf(A[k]);
-        int gb = (int)__builtin_floorf(B[k]);
-        w.g[k] = ga;
-        w.n[k] = gb > ga ? gb - ga : ga - gb;
-        w.step[k] = gb > ga ? 1 : (gb < ga ? -1 : 0);
-        w.tM[k] = __builtin_inff();
-        w.tD[k] = __builtin_inff();
-        if (w.n[k] > 0) {
-            float delta = B[k] - A[k];
-            float bound = (float)(ga + (w.step[k] > 0 ? 1 : 0));
-            w.tD[k] = 1.0f / __builtin_fabsf(delta);
-            w.tM[k] = (bound - A[k]) / delta;
-        }
-        w.left += w.n[k];
-    }
-}
-
-// One step: among axes with steps left, the smallest crossing parameter; ties go
-// to the lowest axis.
-// (Constant indices only, so the walk state stays in registers.)
-__device__ inline void walk_step(Walk& w) {
-    // the axis with steps left whose next boundary comes first (ties: the lowest axis), chosen
-    // with selects rather than branches, so that the lanes of a wave never diverge here
-    const bool c0 = w.n[0] > 0, c1 = w.n[1] > 0, c2 = w.n[2] > 0;
-    const bool t1 = c1 && (!c0 || w.tM[1] < w.tM[0]);
-    const float best = t1 ? w.tM[1] : w.tM[0];
-    const bool t2 = c2 && ((!c0 && !t1) || w.tM[2] < best);
-    // an axis is always found: the caller only steps while w.left > 0
-    const int axis = t2 ? 2 : (t1 ? 1 : 0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const bool s = axis == k;
-        const float next = w.tM[k] + w.tD[k];
-        w.g[k] += s ? w.step[k] : 0;
-        w.n[k] -= s ? 1 : 0;
-        w.tM[k] = s ? next : w.tM[k];
-    }
-    w.left -= 1;
 }
 
 // ---------------------------------------------------------------------------

@@ -1000,18 +1000,28 @@ template __global__ void k_group_merge<true>(const Job*, const MapDesc*, const u
 // ---------------------------------------------------------------------------
 // cross: walk the band of each ray, record (block, ray) crossings
 // ---------------------------------------------------------------------------
-// Per workgroup of 256 rays, in three phases separated by barriers:
-//  1. walk every ray, count its block crossings and enter the block keys in an LDS set;
-//  2. insert each distinct block of the workgroup once into the per-call block set;
-//  3. walk again and write the crossings at a range reserved with one global atomic.
-constexpr int kCrossSlots = 2048;   // LDS block-key set (at most 256 rays x 7 blocks)
+// A workgroup takes a contiguous range of ray slots, 256 at a time, in three phases separated
+// by barriers:
+//  1. find the blocks of every ray's band and enter their keys in the workgroup's LDS set;
+//  2. enter each key new to the set in the per-call block set (global);
+//  3. write ray i's crossings (block-set slots) to cross[i * MB + c].
+// The LDS set is kept from one batch of rays to the next, so a block that consecutive rays
+// share (they come sorted by block, or in sensor order) enters the global set once per
+// workgroup rather than once per batch.
+constexpr int kCrossSlots = 2048;   // LDS block-key set
+constexpr int kCrossBatchKeys = 256 * 7;   // keys one batch can add (256 rays x 7 blocks)
+constexpr u32 kCrossPending = 0xFFFFFFFEu; // an LDS set entry not yet in the global set
 
-__device__ inline u32 lds_set_insert(u64* keys, u64 key) {
+// Enters key in the LDS set; returns its slot, with *added when this call put it there.
+__device__ inline u32 lds_set_insert(u64* keys, u64 key, bool* added) {
     static_assert(kCrossSlots == 2048, "slot hash bits");
     u32 h = lds_slot<11>(key);
     for (;;) {
         const u64 old = atomicCAS(&keys[h], kEmpty, key);
-        if (old == kEmpty || old == key) return h;
+        if (old == kEmpty || old == key) {
+            *added = old == kEmpty;
+            return h;
+        }
         h = (h + 1) & (kCrossSlots - 1);
     }
 }
@@ -1030,64 +1040,93 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                                                u32 MB, JobStat* __restrict__ jst,
                                                CallState* __restrict__ cs, u32 ray_cap) {
     __shared__ u64 s_key[kCrossSlots];
-    __shared__ u32 s_h[kCrossSlots];
+    __shared__ u32 s_h[kCrossSlots];   // global block-set slot of each key (kCrossPending: not yet)
+    __shared__ u32 s_fill;             // keys in the LDS set
     const u32 nrays = cs->ray_count < ray_cap ? cs->ray_count : ray_cap;
-    for (u32 base = blockIdx.x * 256u; base < nrays; base += gridDim.x * 256u) {
-        for (int i = threadIdx.x; i < kCrossSlots; i += 256) s_key[i] = kEmpty;
-        __syncthreads();
-        const u32 i = base + threadIdx.x;
-        bool ok = false, live = false;
-        u32 jid = 0;
-        float p[3] = {0.f, 0.f, 0.f}, s[3] = {0.f, 0.f, 0.f};
+    const u32 nbatch = (nrays + 255u) / 256u;
+    const u32 per = (nbatch + gridDim.x - 1u) / gridDim.x;
+    const u32 bt0 = blockIdx.x * per;
+    const u32 bt1 = bt0 + per < nbatch ? bt0 + per : nbatch;
+    for (int k = threadIdx.x; k < kCrossSlots; k += 256) s_key[k] = kEmpty;
+    if (threadIdx.x == 0) s_fill = 0;
+    __syncthreads();
+    // the first batch's ray slots; each batch loads the next one's while it works
+    u32 nxt_job = kNoRay;
+    float4 nxt_p = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (bt0 < bt1 && bt0 * 256u + threadIdx.x < nrays) {
+        nxt_job = rays_job[bt0 * 256u + threadIdx.x];
+        nxt_p = rays_p[bt0 * 256u + threadIdx.x];   // an empty slot's point is loaded and ignored
+    }
+    for (u32 bt = bt0; bt < bt1; ++bt) {
+        // a batch adds at most kCrossBatchKeys keys: the set is emptied before it could overflow
+        // (s_fill is read by every thread before the barrier, and changed only after it)
+        if (s_fill > (u32)(kCrossSlots - kCrossBatchKeys)) {
+            __syncthreads();
+            for (int k = threadIdx.x; k < kCrossSlots; k += 256) s_key[k] = kEmpty;
+            if (threadIdx.x == 0) s_fill = 0;
+            __syncthreads();
+        }
+        const u32 i = bt * 256u + threadIdx.x;
+        bool ok = false;
+        const u32 jid = nxt_job;
+        const bool live = i < nrays && jid != kNoRay;
+        const float4 rp = nxt_p;
+        nxt_job = kNoRay;
+        if (bt + 1u < bt1 && i + 256u < nrays) {
+            nxt_job = rays_job[i + 256u];
+            nxt_p = rays_p[i + 256u];
+        }
+        float p[3] = {rp.x, rp.y, rp.z}, s[3] = {0.f, 0.f, 0.f};
         u64 mapbits = 0;
         u64 held0 = 0, held1 = 0;   // LDS set slots of the crossed blocks, in crossing order
-        u32 nc = 0;
+        u32 nc = 0, added = 0;
         const MapDesc* Mp = maps;
-        if (i < nrays) {
-            jid = rays_job[i];
-            live = jid != kNoRay;
-        }
         if (live) {
             const Job& J = jobs[jid];
             Mp = &maps[J.map];
-            const float4 rp = rays_p[i];
-            p[0] = rp.x; p[1] = rp.y; p[2] = rp.z;
             s[0] = J.pose[3]; s[1] = J.pose[7]; s[2] = J.pose[11];
             mapbits = (u64)Mp->map_id << 45;
             float e[3], r;
             Walk w;
             ok = walk_setup(*Mp, p, s, e, r, w);
-            // phase 1: the blocks the band enters, entered in the workgroup's LDS set
+            // phase 1: the blocks the band enters, in walk order.  They follow from the walk's
+            // block-changing steps alone (every 16th step of an axis), with the crossing
+            // parameters of the voxel walk, which is not stepped here.
             if (ok) {
-                u64 cur = kEmpty;
                 const bool full = Mp->full_ray != 0;
-                for (int guard = 0; guard < Mp->max_steps; ++guard) {
-                    const u64 bk = block_key_of(w.g[0], w.g[1], w.g[2]);
-                    if (bk != cur) {
-                        cur = bk;
-                        if (full) {
-                            // a whole ray crosses up to MB blocks, more than the LDS set and
-                            // registers hold: each crossing enters the call's block set at once
-                            const u32 h = tset_insert<true>(tkeys, tmask, mapbits | bk, tlist, tlist_cap, cs);
-                            if (nc < MB) cross[(size_t)i * MB + nc] = h;
-                        } else {
-                            const u32 h = lds_set_insert(s_key, mapbits | bk);
-                            if (nc < 4) held0 |= (u64)h << (16 * nc);
-                            else if (nc < kCrossHeld) held1 |= (u64)h << (16 * (nc - 4));
+                BlockWalk bw;
+                block_walk_init(w, bw);
+                for (int guard = 0, axis = 0; axis >= 0 && guard <= Mp->max_steps;
+                     ++guard, axis = block_walk_next(bw)) {
+                    const u64 bk = pack_block(bw.b[0], bw.b[1], bw.b[2]);
+                    if (full) {
+                        // a whole ray crosses up to MB blocks, more than the LDS set and
+                        // registers hold: each crossing enters the call's block set at once
+                        const u32 h = tset_insert<true>(tkeys, tmask, mapbits | bk, tlist, tlist_cap, cs);
+                        if (nc < MB) cross[(size_t)i * MB + nc] = h;
+                    } else {
+                        bool fresh;
+                        const u32 h = lds_set_insert(s_key, mapbits | bk, &fresh);
+                        if (fresh) {
+                            s_h[h] = kCrossPending;
+                            added++;
                         }
-                        nc++;
+                        if (nc < 4) held0 |= (u64)h << (16 * nc);
+                        else if (nc < kCrossHeld) held1 |= (u64)h << (16 * (nc - 4));
                     }
-                    if (w.left == 0) break;
-                    walk_step(w);
+                    nc++;
                 }
             }
         }
-        __syncthreads();
-        // phase 2: each distinct block of the workgroup enters the per-call block set once
-        for (int k = threadIdx.x; k < kCrossSlots; k += 256) {
-            const u64 key = s_key[k];
-            if (key != kEmpty) s_h[k] = tset_insert<true>(tkeys, tmask, key, tlist, tlist_cap, cs);
+        {
+            const u32 wa = wave_sum(added);
+            if (lane_id() == 0 && wa) atomicAdd(&s_fill, wa);
         }
+        __syncthreads();
+        // phase 2: each block new to the LDS set enters the per-call block set
+        for (int k = threadIdx.x; k < kCrossSlots; k += 256)
+            if (s_h[k] == kCrossPending && s_key[k] != kEmpty)
+                s_h[k] = tset_insert<true>(tkeys, tmask, s_key[k], tlist, tlist_cap, cs);
         __syncthreads();
         // phase 3: crossing c of ray slot i goes to cross[i * MB + c]
         if (i < nrays) {
@@ -2320,6 +2359,37 @@ __global__ void k_debug_traverse(const float* __restrict__ A, const float* __res
         c++;
         if (w.left == 0) break;
         walk_step(w);
+    }
+    counts[i] = c;
+}
+
+// The blocks of the same traversals, from the block-changing steps alone (as the crossing
+// kernel finds them): out[i][c] = block indices, counts[i] = the number of blocks.
+__global__ void k_debug_traverse_blocks(const float* __restrict__ A, const float* __restrict__ B, int n,
+                                        int* __restrict__ out, int cap, int* __restrict__ counts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float a[3] = {A[3 * i], A[3 * i + 1], A[3 * i + 2]};
+    const float b[3] = {B[3 * i], B[3 * i + 1], B[3 * i + 2]};
+    for (int k = 0; k < 3; ++k) {
+        if (!(a[k] >= -(float)kVoxLimit && a[k] < (float)kVoxLimit && b[k] >= -(float)kVoxLimit &&
+              b[k] < (float)kVoxLimit)) {
+            counts[i] = -1;   // outside the addressable voxel range
+            return;
+        }
+    }
+    Walk w;
+    walk_setup_vox(a, b, w);
+    BlockWalk bw;
+    block_walk_init(w, bw);
+    int c = 0;
+    for (int axis = 0; axis >= 0; axis = block_walk_next(bw)) {
+        if (c < cap) {
+            out[(size_t)i * cap * 3 + 3 * c] = bw.b[0];
+            out[(size_t)i * cap * 3 + 3 * c + 1] = bw.b[1];
+            out[(size_t)i * cap * 3 + 3 * c + 2] = bw.b[2];
+        }
+        c++;
     }
     counts[i] = c;
 }

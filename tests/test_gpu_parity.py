@@ -60,6 +60,38 @@ def test_traversal_bit_exact(vbx):
         assert np.array_equal(out[i, :counts[i]], ref), i
 
 
+def test_traversal_blocks_bit_exact(vbx):
+    """The blocks the crossing kernel's block walk finds (from the block-changing steps alone)
+    are the distinct blocks of the oracle's voxel traversal, in order: random band-length and
+    long segments, and dyadic ones with exact ties at block faces, edges and corners."""
+    import oracle
+    rng = np.random.default_rng(22)
+    A = rng.uniform(-200, 200, size=(3000, 3)).astype(np.float32)
+    B = (A + rng.uniform(-40, 40, size=(3000, 3))).astype(np.float32)
+    Al = rng.uniform(-200, 200, size=(300, 3)).astype(np.float32)
+    Bl = (Al + rng.uniform(-300, 300, size=(300, 3))).astype(np.float32)
+    Ad = (16.0 * rng.integers(-4, 4, size=(3000, 3)) + rng.integers(-8, 8, size=(3000, 3)) / 4.0).astype(np.float32)
+    Bd = (Ad + rng.integers(-48, 48, size=(3000, 3)) / 2.0).astype(np.float32)
+    C = (16.0 * rng.integers(-4, 4, size=(1000, 3))).astype(np.float32)
+    D = (rng.integers(-48, 48, size=(1000, 3)) / 8.0).astype(np.float32)
+    A = np.concatenate([A, Al, Ad, C - D])
+    B = np.concatenate([B, Bl, Bd, C + D])
+    log(f"traversal blocks: {A.shape[0]} segments")
+    out, counts = vbx.debug_traverse_blocks(dev(A), dev(B), cap=128)
+    out, counts = out.cpu().numpy(), counts.cpu().numpy()
+    multi = 0
+    for i in range(A.shape[0]):
+        vox = oracle.dda(A[i], B[i])
+        blk = vox >> 4
+        keep = np.ones(blk.shape[0], bool)
+        keep[1:] = np.any(blk[1:] != blk[:-1], axis=1)
+        ref = blk[keep]
+        multi += ref.shape[0] > 1
+        assert counts[i] == ref.shape[0], i
+        assert np.array_equal(out[i, :counts[i]], ref), i
+    log(f"  ok: {multi} segments cross blocks")
+
+
 # ---------------------------------------------------------------------------
 # single frames, every mode
 # ---------------------------------------------------------------------------
