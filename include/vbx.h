@@ -395,7 +395,8 @@ int vbx_map_clear(vbx_map* map);
 /* Per-stage timing of integration calls.  While enabled, every call records HIP events on
  * the map's stream around each pipeline stage (points, groups, cross, resolve, commit,
  * bins, scan, scatter, update, finish); vbx_map_profile_read synchronises and returns the
- * summed milliseconds and launch counts per stage since the last reset. */
+ * summed milliseconds and launch counts per stage since the last reset.  "bins" is timed for
+ * projection mapping only: raycasting counts its crossings inside the cross stage. */
 #define VBX_PROFILE_STAGES 10
 typedef struct {
     double ms[VBX_PROFILE_STAGES];

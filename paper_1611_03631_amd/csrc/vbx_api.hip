@@ -60,9 +60,10 @@ struct Stage {
 struct Scratch {
     DevBuf rays_p, rays_job, cross, ncross, sorted, tkeys, tval, tlist, t_key, t_slot, order, bins, off,
         partial, parts, parts_sorted, tile_parts, chunk_first, touch_key, touch_n, tables, jst, cs;
+    DevBuf hbins;   // crossing counts by (block-set slot, frame), kept zero between calls
     DevBuf rays_c, sorted_c, parts_c, parts_sorted_c;   // colour calls: the colours beside the rays
     size_t ray_cap = 0, cross_cap = 0, tkey_cap = 0, tlist_cap = 0, bins_cap = 0, nparts = 0,
-           touch_cap = 0;
+           touch_cap = 0, hbins_cap = 0;
     Stage stage[4];
     int stage_i = 0;
     // host copy of the maps of the last call (for vbx_last_touches)
@@ -355,7 +356,7 @@ struct CallPlan {
 
 // Element counts of a call's scratch buffers (host upper bounds: nothing is read back mid-call).
 struct ScratchSizes {
-    size_t ray_cap, cross_cap, tlist_cap, tkey_cap, bins_cap, nparts, touch_cap, tables_bytes;
+    size_t ray_cap, cross_cap, tlist_cap, tkey_cap, bins_cap, hbins_cap, nparts, touch_cap, tables_bytes;
 };
 
 int scratch_sizes(const CallPlan& plan, int njobs, int nmaps, size_t sum_capacity, ScratchSizes& z) {
@@ -367,6 +368,10 @@ int scratch_sizes(const CallPlan& plan, int njobs, int nmaps, size_t sum_capacit
     // grouped calls sort partial groups into kGroupSubBins bins per (block, frame)
     z.bins_cap = z.tlist_cap * (size_t)plan.JM * (plan.grouped ? (size_t)kGroupSubBins : 1u);
     if (z.bins_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
+    // the crossing kernel counts crossings by (block-set slot, frame) before blocks have dense
+    // indices; the scan moves the counts to dense order
+    z.hbins_cap = z.tkey_cap * (size_t)plan.JM;
+    if (z.hbins_cap > 0xFFFFFFF0ull) return VBX_ERR_LIMIT;
     z.nparts = (z.bins_cap + kScanChunkHost - 1) / kScanChunkHost;
     z.touch_cap = plan.keep_touches ? std::min<size_t>(z.ray_cap * (size_t)plan.max_vox, (size_t)1 << 26) : 0;
     if (plan.keep_touches && plan.projective)   // every voxel of every block of the call
@@ -390,6 +395,7 @@ void for_each_scratch(Scratch* s, const CallPlan& plan, const ScratchSizes& z, i
     f(s->t_slot, z.tlist_cap * sizeof(int));
     f(s->order, z.tlist_cap * sizeof(u32));
     f(s->bins, (z.bins_cap + 1) * sizeof(u32));
+    f(s->hbins, z.hbins_cap * sizeof(u32));
     f(s->off, (z.bins_cap + 1) * sizeof(u32));
     f(s->partial, (z.nparts + 1) * sizeof(u32));
     if (plan.grouped) {
@@ -421,6 +427,7 @@ void note_scratch_sizes(Scratch* s, const ScratchSizes& z) {
     s->cross_cap = z.cross_cap;
     s->tlist_cap = z.tlist_cap;
     s->bins_cap = z.bins_cap;
+    s->hbins_cap = z.hbins_cap;
     s->nparts = z.nparts;
     s->tkey_cap = z.tkey_cap;
     s->touch_cap = z.touch_cap;
@@ -467,6 +474,11 @@ int ensure_scratch(Scratch* s, hipStream_t st, const CallPlan& plan, int njobs, 
     if (r == 1)
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(bins_cap + 1)), dim3(256), 0, st, (u32*)s->bins.p, 0u,
                            bins_cap + 1);
+    if ((r = grow(s->hbins, z.hbins_cap * sizeof(u32))) < 0) return VBX_ERR_OUT_OF_MEMORY;
+    if (r == 1)
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(s->hbins.bytes / 4)), dim3(256), 0, st, (u32*)s->hbins.p, 0u,
+                           s->hbins.bytes / 4);
+    s->hbins_cap = z.hbins_cap;
     GROW(s->off, (bins_cap + 1) * sizeof(u32));
     GROW(s->partial, (nparts + 1) * sizeof(u32));
     if (plan.grouped) {
@@ -672,6 +684,8 @@ int clear_carved(Scratch* s, hipStream_t st, int njobs) {
                        s->tkey_cap);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(s->bins_cap + 1)), dim3(256), 0, st, (u32*)s->bins.p, 0u,
                        s->bins_cap + 1);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(s->hbins_cap)), dim3(256), 0, st, (u32*)s->hbins.p, 0u,
+                       s->hbins_cap);
     const size_t jst_words = (size_t)njobs * sizeof(JobStat) / 8;
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(jst_words)), dim3(256), 0, st, (u64*)s->jst.p, 0ull, jst_words);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, (u32*)s->cs.p, 0u, sizeof(CallState) / 4);
@@ -893,9 +907,10 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     const unsigned GT = grid_for(s->tlist_cap, 1024);
     const unsigned NP = (unsigned)std::max<size_t>(s->nparts, 1);
     // exclusive scan of the t_count * per_block bin counts
-    auto scan_bins = [&](u32 per_block, u32* chunk_first) {
-        hipLaunchKernelGGL(k_scan_sums, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, per_block,
-                           (u32*)s->partial.p, (u32*)s->off.p, cs);
+    auto scan_bins = [&](u32 per_block, u32* chunk_first, u32* hsrc) {
+        hipLaunchKernelGGL(k_scan_sums, dim3(NP), dim3(256), 0, st, (u32*)s->bins.p, per_block,
+                           (u32*)s->partial.p, (u32*)s->off.p, cs, hsrc, (const u32*)s->tlist.p,
+                           (u32)s->tlist_cap);
         hipLaunchKernelGGL(k_scan_final, dim3(NP), dim3(256), 0, st, (const u32*)s->bins.p, (const u32*)s->partial.p,
                            (u32*)s->off.p, per_block, chunk_first, (const CallState*)cs);
     };
@@ -928,7 +943,7 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
         hipLaunchKernelGGL(k_gbin_count, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
                            (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p, JM,
                            tpw, (const CallState*)cs);
-        scan_bins(JMS, (u32*)s->chunk_first.p);
+        scan_bins(JMS, (u32*)s->chunk_first.p, nullptr);
         hipLaunchKernelGGL(k_gscatter, dim3(GW), dim3(256), 0, st, (const Partial*)s->parts.p,
                            (const u32*)s->tile_parts.p, total_tiles, (const u32*)s->tval.p, (u32*)s->bins.p,
                            (const u32*)s->off.p, JM, tpw, (Partial*)s->parts_sorted.p, parts_c, parts_sorted_c,
@@ -949,9 +964,12 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
     const u32 MB = (u32)plan.max_blocks;
     {
     StageTimer tm(prof_map, st, ST_CROSS);
+    // raycasting calls count their crossings here (by block-set slot and frame); projection
+    // mapping counts them in its own pass
     hipLaunchKernelGGL(k_cross, dim3(GC), dim3(256), 0, st, d_jobs, d_maps, (const float4*)rays_p,
                        (const u32*)rays_job, (u64*)s->tkeys.p, (u32)(s->tkey_cap - 1), (u32*)s->tlist.p,
-                       (u32)s->tlist_cap, (u32*)s->cross.p, (unsigned char*)s->ncross.p, MB, jst, cs, ray_cap);
+                       (u32)s->tlist_cap, (u32*)s->cross.p, (unsigned char*)s->ncross.p, MB,
+                       plan.projective ? (u32*)nullptr : (u32*)s->hbins.p, JM, jst, cs, ray_cap);
     }
     {
     StageTimer tm(prof_map, st, ST_RESOLVE);
@@ -984,14 +1002,9 @@ int launch_call(Scratch* s, hipStream_t st, const CallPlan& plan, int J, int M, 
 #undef VBX_PROJ
     } else {
     {
-    StageTimer tm(prof_map, st, ST_BINS);
-    hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, d_jobs, (const u32*)s->cross.p,
-                       (const unsigned char*)s->ncross.p, MB, (const u32*)s->tval.p, (const u32*)rays_job,
-                       (u32*)s->bins.p, JM, cs, ray_cap);
-    }
-    {
+    // the counts by (block, frame), gathered from the crossing kernel's counts by block-set slot
     StageTimer tm(prof_map, st, ST_SCAN);
-    scan_bins(JM, nullptr);
+    scan_bins(JM, nullptr, (u32*)s->hbins.p);
     }
     {
     StageTimer tm(prof_map, st, ST_SCATTER);

@@ -45,15 +45,16 @@ __global__ void k_group_merge(const Job* jobs, const MapDesc* maps, const u64* t
                               u32* rays_job, u32* rays_c, JobStat* jst, CallState* cs);
 __global__ void k_cross(const Job* jobs, const MapDesc* maps, const float4* rays_p,
                         const u32* rays_job, u64* tkeys, u32 tmask, u32* tlist, u32 tlist_cap,
-                        u32* cross, unsigned char* ncross, u32 MB, JobStat* jst, CallState* cs,
-                        u32 ray_cap);
+                        u32* cross, unsigned char* ncross, u32 MB, u32* hbins, u32 JM, JobStat* jst,
+                        CallState* cs, u32 ray_cap);
 __global__ void k_resolve(const MapDesc* maps, const u64* tkeys, u32* tval, const u32* tlist,
                           u64* t_key, int* t_slot, CallState* cs);
 __global__ void k_commit(const MapDesc* maps, const u64* t_key, int* t_slot, CallState* cs);
 __global__ void k_bin_count(const Job* jobs, const u32* cross, const unsigned char* ncross,
                             u32 MB, const u32* tval, const u32* rays_job, u32* bins, u32 JM,
                             CallState* cs, u32 ray_cap);
-__global__ void k_scan_sums(const u32* bins, u32 JM, u32* partial, u32* off, CallState* cs);
+__global__ void k_scan_sums(u32* bins, u32 JM, u32* partial, u32* off, CallState* cs, u32* hsrc,
+                            const u32* tlist, u32 tlist_cap);
 __global__ void k_scan_final(const u32* bins, const u32* partial, u32* off, u32 JM, u32* chunk_first,
                              const CallState* cs);
 __global__ void k_scatter(const Job* jobs, const u32* cross, const unsigned char* ncross,

@@ -1037,7 +1037,8 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                                                u64* __restrict__ tkeys, u32 tmask,
                                                u32* __restrict__ tlist, u32 tlist_cap,
                                                u32* __restrict__ cross, unsigned char* __restrict__ ncross,
-                                               u32 MB, JobStat* __restrict__ jst,
+                                               u32 MB, u32* __restrict__ hbins, u32 JM,
+                                               JobStat* __restrict__ jst,
                                                CallState* __restrict__ cs, u32 ray_cap) {
     __shared__ u64 s_key[kCrossSlots];
     __shared__ u32 s_h[kCrossSlots];   // global block-set slot of each key (kCrossPending: not yet)
@@ -1079,11 +1080,12 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
         float p[3] = {rp.x, rp.y, rp.z}, s[3] = {0.f, 0.f, 0.f};
         u64 mapbits = 0;
         u64 held0 = 0, held1 = 0;   // LDS set slots of the crossed blocks, in crossing order
-        u32 nc = 0, added = 0;
+        u32 nc = 0, added = 0, jm = 0;
         const MapDesc* Mp = maps;
         if (live) {
             const Job& J = jobs[jid];
             Mp = &maps[J.map];
+            jm = J.jm;
             s[0] = J.pose[3]; s[1] = J.pose[7]; s[2] = J.pose[11];
             mapbits = (u64)Mp->map_id << 45;
             float e[3], r;
@@ -1104,6 +1106,8 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                         // registers hold: each crossing enters the call's block set at once
                         const u32 h = tset_insert<true>(tkeys, tmask, mapbits | bk, tlist, tlist_cap, cs);
                         if (nc < MB) cross[(size_t)i * MB + nc] = h;
+                        // (a failed insert is an error of the call and is not counted)
+                        if (hbins) wave_count_by_key(hbins, nc < MB && h != 0xFFFFFFFFu, h * JM + jm);
                     } else {
                         bool fresh;
                         const u32 h = lds_set_insert(s_key, mapbits | bk, &fresh);
@@ -1128,17 +1132,30 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
             if (s_h[k] == kCrossPending && s_key[k] != kEmpty)
                 s_h[k] = tset_insert<true>(tkeys, tmask, s_key[k], tlist, tlist_cap, cs);
         __syncthreads();
-        // phase 3: crossing c of ray slot i goes to cross[i * MB + c]
+        // phase 3: crossing c of ray slot i goes to cross[i * MB + c], and (raycasting calls)
+        // counts towards its (block-set slot, frame) bin
+        u32 nband = 0;   // band crossings, whose slots are held in registers
         if (i < nrays) {
             const bool full = live && Mp->full_ray != 0;
             if (nc > MB || (!full && nc > kCrossHeld)) {   // cannot happen: MB bounds the walk
                 cs->error = -4;
                 nc = 0;
             }
-            if (!full)
+            if (!full) {
+                nband = nc;
                 for (u32 c = 0; c < nc; ++c)
                     cross[(size_t)i * MB + c] = s_h[(u32)((c < 4 ? held0 : held1) >> (16 * (c & 3))) & 0xFFFFu];
+            }
             ncross[i] = (unsigned char)nc;
+        }
+        if (hbins) {
+            for (u32 c = 0; c < kCrossHeld; ++c) {
+                if (__ballot(c < nband) == 0ull) break;
+                const u32 h = c < nband ? s_h[(u32)((c < 4 ? held0 : held1) >> (16 * (c & 3))) & 0xFFFFu]
+                                        : 0xFFFFFFFFu;
+                const bool act = h != 0xFFFFFFFFu;   // a failed insert is an error of the call
+                wave_count_by_key(hbins, act, act ? h * JM + jm : 0u);
+            }
         }
         // out-of-bounds rays per frame (rare); rays were counted when created
         const bool oob = live && !ok;
@@ -1316,11 +1333,31 @@ constexpr int kScanChunk = 4096;
 // workgroups of chunks that hold bins take part.  The last of them to finish (counted in
 // cs->scan_done, which it then clears for the next scan) turns the sums into exclusive chunk
 // offsets and writes the total at off[n]: no workgroup waits for another.
-__global__ __launch_bounds__(256) void k_scan_sums(const u32* __restrict__ bins, u32 JM,
+//
+// hsrc (raycasting calls): the counts were made by block-set slot, hsrc[h * JM + frame]; they
+// are moved to bins[t * JM + frame] for the dense block order t (h = tlist[t]) and cleared, so
+// that hsrc is zero again for the next call, whatever the state of this one.
+__global__ __launch_bounds__(256) void k_scan_sums(u32* __restrict__ bins, u32 JM,
                                                    u32* __restrict__ partial, u32* __restrict__ off,
-                                                   CallState* __restrict__ cs) {
+                                                   CallState* __restrict__ cs, u32* __restrict__ hsrc,
+                                                   const u32* __restrict__ tlist, u32 tlist_cap) {
     __shared__ u32 lds8[4];
     __shared__ bool s_last;
+    if (hsrc) {
+        const u32 tc = cs->t_count < tlist_cap ? cs->t_count : tlist_cap;   // listed blocks
+        const u32 ng = tc * JM;
+        const u32 gb = blockIdx.x * (u32)kScanChunk;
+        for (int j = 0; j < 16; ++j) {
+            const u32 i = gb + threadIdx.x * 16u + j;
+            if (i < ng) {
+                const u32 t = i / JM;
+                const size_t src = (size_t)tlist[t] * JM + (i - t * JM);
+                const u32 c = hsrc[src];
+                if (c) hsrc[src] = 0u;
+                bins[i] = c;
+            }
+        }
+    }
     const u32 n = cs->error ? 0u : cs->t_count * JM;
     const u32 nparts = gridDim.x;
     const u32 used_all = (n + kScanChunk - 1) / kScanChunk;
