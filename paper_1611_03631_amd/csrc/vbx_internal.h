@@ -212,20 +212,19 @@ __device__ inline int find_block(const MapDesc& M, u64 bk) {
 // and the world point's voxel index inside the addressable range.
 __device__ inline int classify_point(const MapDesc& M, const float* pose, float x, float y,
                                      float z, float q[3]) {
-    // 0 = invalid, 1 = valid, 2 = out of bounds
-    if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z))) return 0;
-    float rho2 = (x * x + y * y) + z * z;
-    if (!(rho2 > 0.0f && rho2 <= M.rmax2)) return 0;
-    if (M.weighting == 1 && !(z >= M.z_min)) return 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        q[k] = ((pose[4 * k] * x + pose[4 * k + 1] * y) + pose[4 * k + 2] * z) + pose[4 * k + 3];
+    // 0 = invalid, 1 = valid, 2 = out of bounds.  Straight-line: every test is evaluated and
+    // the class selected at the end.  A non-finite coordinate makes rho2 infinite or NaN, which
+    // fails rho2 <= rmax2, so the range test also rejects it.
+    const float rho2 = (x * x + y * y) + z * z;
+    const bool ok = rho2 > 0.0f && rho2 <= M.rmax2 && (M.weighting != 1 || z >= M.z_min);
+    bool inb = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        float f = q[k] * M.iv;
-        if (!(f >= -(float)kVoxLimit && f < (float)kVoxLimit)) return 2;
+        q[k] = ((pose[4 * k] * x + pose[4 * k + 1] * y) + pose[4 * k + 2] * z) + pose[4 * k + 3];
+        const float f = q[k] * M.iv;
+        inb = inb && f >= -(float)kVoxLimit && f < (float)kVoxLimit;
     }
-    return 1;
+    return ok ? (inb ? 1 : 2) : 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -336,7 +336,7 @@ __device__ inline void group_terms(const MapDesc& M, const float q[3], float z, 
         float f = q[k] * M.iv;
         float fl = __builtin_floorf(f);
         g[k] = (int)fl;
-        float fr = f - (float)g[k];
+        float fr = f - fl;   // fl is an integer below 2^18 in magnitude: exactly (float)g[k]
         float qs = __builtin_rintf(__builtin_ldexpf(fr, 20));
         u32 Qk = (u32)qs;
         Q[k] = Qk > (1u << 20) - 1 ? (1u << 20) - 1 : Qk;
