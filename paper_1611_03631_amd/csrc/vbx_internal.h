@@ -85,7 +85,6 @@ struct CallState {
     u32 work_next;     // persistent work counter of the update kernel
     u32 touch_count;
     int error;         // call-wide error (scratch overflow)
-    u32 work_merge;    // persistent work counter of the group merge kernel
     u32 scan_done;     // workgroups of the current scan that have written their sum
     u32 finish_done;   // workgroups of the call's last kernel that are done
 };

@@ -2171,7 +2171,6 @@ __global__ __launch_bounds__(256) void k_finish_call(const Job* __restrict__ job
         cs->ray_count = 0;
         cs->t_count = 0;
         cs->work_next = 0;
-        cs->work_merge = 0;
         cs->scan_done = 0;
         cs->error = 0;
         cs->finish_done = 0;
