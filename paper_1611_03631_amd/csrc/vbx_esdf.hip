@@ -153,6 +153,18 @@ __global__ void k_esdf_seed(const MapDesc M, EsdfDev E, u32 tag_raise, u32 tag_l
 // every other observed neighbour joins the lower wave's first frontier.  Counters rotate over
 // three words: this round reads cnt[r % 3], appends to cnt[(r + 1) % 3] and clears the one the
 // next round appends to.
+//
+// A small frontier is spread over more lanes: each frontier voxel gets L lanes (L a power of
+// two up to 32, as many as let the grid take every voxel at once), lane j of a voxel handling
+// neighbours j, j + L, ... .  A round then waits for about 27 / L neighbour loads in a row
+// rather than 26; a large frontier keeps one lane per voxel, as the grid is full anyway.
+__device__ inline u32 esdf_lanes(u64 nv) {
+    const u64 T = (u64)gridDim.x * blockDim.x;
+    u32 L = 32;
+    while (L > 1 && nv * L > T) L >>= 1;
+    return L;
+}
+
 __global__ void k_esdf_raise(EsdfDev E, u32 r, u32 tag_next, u32 tag_lower) {
     const u32 n_in = E.cnt[kEsdfRaiseCount + r % 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) E.cnt[kEsdfRaiseCount + (r + 2) % 3] = 0;
@@ -160,13 +172,17 @@ __global__ void k_esdf_raise(EsdfDev E, u32 r, u32 tag_next, u32 tag_lower) {
     const u32* in = E.raise[r & 1];
     u32* out = E.raise[(r + 1) & 1];
     u32* n_out = &E.cnt[kEsdfRaiseCount + (r + 1) % 3];
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n_in && i < E.fcap; i += gridDim.x * blockDim.x) {
-        const u32 v = in[i];
+    const u64 nv = n_in < E.fcap ? n_in : E.fcap;
+    const u32 L = esdf_lanes(nv);
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < nv * L; i += (u64)gridDim.x * blockDim.x) {
+        const u32 v = in[i / L];
         const u32 slot = v >> 12, l = v & 4095u;
-        const u32 low = (u32)E.vox[v];
-        if (!(low & kEsdfFixed)) E.vox[v] = esdf_word(E.d_max, (low & ~kEsdfParentMask) | kEsdfNoParent);
-        for (int n = 0; n < 27; ++n) {
-            if (n == 13) continue;
+        for (int n = (int)(i % L); n < 27; n += (int)L) {
+            if (n == 13) {   // the voxel itself: its reset
+                const u32 low = (u32)E.vox[v];
+                if (!(low & kEsdfFixed)) E.vox[v] = esdf_word(E.d_max, (low & ~kEsdfParentMask) | kEsdfNoParent);
+                continue;
+            }
             const int u = esdf_neighbour(E, slot, l, n);
             if (u < 0) continue;
             const u64 wu = E.vox[u];
@@ -191,15 +207,17 @@ __global__ void k_esdf_lower(EsdfDev E, u32 r, u32 tag_next) {
     const u32* in = E.lower[r & 1];
     u32* out = E.lower[(r + 1) & 1];
     u32* n_out = &E.cnt[kEsdfLowerCount + (r + 1) % 3];
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n_in && i < E.fcap; i += gridDim.x * blockDim.x) {
-        const u32 v = in[i];
+    const u64 nv = n_in < E.fcap ? n_in : E.fcap;
+    const u32 L = esdf_lanes(nv);   // lanes per frontier voxel, as in the raise
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < nv * L; i += (u64)gridDim.x * blockDim.x) {
+        const u32 v = in[i / L];
         const u32 slot = v >> 12, l = v & 4095u;
         const u64 wv = E.vox[v];
         const u32 lv = (u32)wv;
         if (!(lv & kEsdfObserved)) continue;
         const float dv = (lv & kEsdfNeg) ? -esdf_mag(wv) : esdf_mag(wv);
         const bool vfixed = (lv & kEsdfFixed) != 0;
-        for (int n = 0; n < 27; ++n) {
+        for (int n = (int)(i % L); n < 27; n += (int)L) {
             if (n == 13) continue;
             const int u = esdf_neighbour(E, slot, l, n);
             if (u < 0) continue;
