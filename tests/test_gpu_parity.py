@@ -248,6 +248,31 @@ def test_ragged_sizes(vbx, n, merge):
     compare_export(g.export(), o.export(), params)
 
 
+@pytest.mark.parametrize("merge", ["simple", "grouped"])
+def test_scattered_points_many_blocks_per_batch(vbx, merge):
+    """420 000 points scattered through a 25 m cube (about 4 000 blocks of 1.6 m): consecutive
+    rays end in different blocks, so each batch of 256 rays in the crossing kernel brings a few
+    hundred blocks to its workgroup's LDS block set, and with more batches than workgroups the
+    set fills and is emptied between batches.  Block set, touches and values against the
+    oracle."""
+    rng = np.random.default_rng(31)
+    n = 420000
+    pts = np.empty((n, 3), np.float32)
+    pts[:, 0] = rng.uniform(-12.5, 12.5, n)
+    pts[:, 1] = rng.uniform(-12.5, 12.5, n)
+    pts[:, 2] = rng.uniform(0.5, 25.5, n)
+    pose = np.eye(3, 4, dtype=np.float32)
+    pose[:, 3] = [0.05, -0.02, 0.01]
+    params = dict(voxel_size=0.1, trunc=0.3, weighting="quad", merge=merge, max_range=40.0,
+                  block_capacity=16384, keep_touches=True)
+    log(f"scattered points: {n}, {merge}")
+    g, o = run_both(vbx, params, [(pts, pose)])
+    nt = compare_touches(g.last_touches(), o.last_touches())
+    res = compare_export(g.export(), o.export(), params, quiet=True)
+    assert g.num_blocks() > 3000
+    log(f"  ok: {g.num_blocks()} blocks, {nt} touched voxels, {res}")
+
+
 def test_organised_hint_does_not_change_result(vbx):
     import synth
     poses, frame = synth.room_sequence(160, 120, 2, seed=synth.SEED_BASE + 12)
