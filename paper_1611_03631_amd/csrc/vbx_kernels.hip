@@ -1300,7 +1300,8 @@ __global__ __launch_bounds__(256) void k_commit(const MapDesc* __restrict__ maps
 }
 
 // ---------------------------------------------------------------------------
-// bins: counting sort of crossings by (block, frame)
+// bins: counting sort of crossings by (block, frame).  Projection mapping counts its crossings
+// here; raycasting counts them in the crossing kernel (by block-set slot, gathered by the scan).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bin_count(const Job* __restrict__ jobs,
                                                    const u32* __restrict__ cross,
