@@ -268,6 +268,15 @@ def bench_c2(args, np, torch, vbx, synth):
     }
     roofline = stage_roofline(prof, algo, args.steps, w.name, m.tuning())
     whole = (algo["points"] + algo["update"]) / (ms_per_step / 1e3) / 1e9
+    # the whole call: algorithmic bytes, and the HBM bytes the counters measured over all its
+    # kernels (when taken on these sources, this workload and this update variant)
+    call_traffic = read_traffic("call", kernel_source_sha(), w.name, m.tuning())
+    whole_call = {"algorithmic_GBps": round(whole, 1), "algorithmic_frac": round(whole / HBM_PEAK_GBS, 4),
+                  "measured_bytes_per_step": call_traffic,
+                  "measured_GBps": None if call_traffic is None else round(call_traffic / (ms_per_step / 1e3) / 1e9, 1),
+                  "measured_frac": None if call_traffic is None
+                  else round(call_traffic / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "peak_GBps": HBM_PEAK_GBS}
     stages = {k: round(v[0] / BREAKDOWN_STEPS, 4) for k, v in prof_all.items()}
 
     # ---------------------------------------------------------------- forms compared on this GPU
@@ -424,6 +433,7 @@ def bench_c2(args, np, torch, vbx, synth):
         "rays_per_step": st["rays"],
         "blocks": st["blocks"],
         "whole_step_algorithmic_GBps": round(whole, 1),
+        "whole_call_hbm": whole_call,
         "stage_ms_per_step": stages,
         "forms_ms_per_step": forms,
         "other_forms": variants,
@@ -1235,8 +1245,42 @@ def summarize_profiles(args):
                 r4 = f"{a['SQ_WAIT_INST_ANY'] / wc:.3f}" if wc and "SQ_WAIT_INST_ANY" in a else ""
                 lines.append(f"| {k} | {r1:.1f} | {r2:.1f} | {r3} | {r4} |")
             lines.append("")
+    # HBM bytes of a whole call: every kernel of the library that runs at least once per call,
+    # its average bytes per dispatch times its dispatches, over the calls (the dispatches of the
+    # kernel named by --summary-call-kernel, which runs once per call)
+    call_bytes = None
+    if args.summary_call_kernel and per and len(scale) == 2:
+        ck = next((k for k in per if args.summary_call_kernel in k), None)
+        if ck is None:
+            raise SystemExit(f"no counters of a kernel matching {args.summary_call_kernel!r}")
+        n_calls = len(per[ck]["FETCH_SIZE"])
+        rows = []
+        for k in per:
+            if "vbx::" not in k or any(c not in per[k] for c in scale):
+                continue
+            n = len(per[k]["FETCH_SIZE"])
+            if n < n_calls:
+                continue   # set-up work outside the calls' common path
+            tot = sum(sum(per[k][c]) * 1024.0 * scale[c] for c in scale)
+            rows.append((k, n / n_calls, tot / n_calls))
+        call_bytes = int(round(sum(r[2] for r in rows)))
+        lines += [f"## HBM bytes per call ({n_calls} calls, kernels dispatched at least once per call)", "",
+                  "| kernel | dispatches per call | HBM MB per call |", "|---|---:|---:|"]
+        for k, dpc, b in sorted(rows, key=lambda r: -r[2]):
+            lines.append(f"| {k} | {dpc:.0f} | {b / 1e6:.2f} |")
+        lines += [f"| **whole call** | | **{call_bytes / 1e6:.2f}** |", ""]
     with open(args.summary_out, "w") as fh:
         fh.write("\n".join(lines))
+    if call_bytes is not None:
+        text = (f"# HBM bytes per call (every kernel of the call, summed) on {args.summary_workload},\n"
+                f"# " + " + ".join(f"{c} x {scale[c]:.3f}" for c in scale) + " (KiB x 1024), from:\n"
+                + "".join(f"#   {c}\n" for c in args.summary_cmd if "FETCH_SIZE" in c or "WRITE_SIZE" in c)
+                + "# valid only for this workload, this update variant (split, threads, columns) and the\n"
+                "# kernel sources with this sha (bench.py kernel_source_sha)\n"
+                f"workload = {args.summary_workload}\nupdate_tuning = {args.summary_update_tuning}\n"
+                f"source_sha = {kernel_source_sha()}\nhbm_bytes_per_launch = {call_bytes}\n")
+        with open(os.path.join(ROOT, "profiles", "traffic_call.txt"), "w") as fh:
+            fh.write(text)
     # per-stage HBM bytes that the benchmark reads back as roofline.traffic
     for spec in args.summary_traffic or []:
         stage, sub = spec.split(":", 1)
@@ -1296,6 +1340,9 @@ def main():
     ap.add_argument("--summary-out", default="profile_summary.md")
     ap.add_argument("--summary-traffic", nargs="*",
                     help="stage:kernel-substring pairs whose HBM bytes go to profiles/traffic_<stage>.txt")
+    ap.add_argument("--summary-call-kernel", default=None,
+                    help="a kernel that runs once per call: the whole call's HBM bytes go to "
+                         "profiles/traffic_call.txt")
     ap.add_argument("--summary-workload", default="c2_room_640x480x100")
     ap.add_argument("--summary-update-tuning", default="1,1024,0")
     args = ap.parse_args()
