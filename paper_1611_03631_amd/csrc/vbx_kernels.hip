@@ -328,9 +328,10 @@ __global__ __launch_bounds__(256) void k_points_simple(const Job* __restrict__ j
 // ---------------------------------------------------------------------------
 // Fixed-point terms of one point for the exact group mean:
 //   Q_k = min(rint(q_k 2^20), 2^20 - 1) with q_k = f_k - floor(f_k), f_k = p_k / v (binary32),
-//   Omega = rint(w 2^wbits) (w = 1/z^2) or 1.
+//   Omega = rint(w 2^wbits) (w = 1/z^2) or 1, returned as the (integral) binary32 value; it
+//   is at most 2^32 (w <= 2^(32 - wbits)).
 __device__ inline void group_terms(const MapDesc& M, const float q[3], float z, int g[3], u32 Q[3],
-                                   u64& om) {
+                                   float& om) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         float f = q[k] * M.iv;
@@ -343,9 +344,9 @@ __device__ inline void group_terms(const MapDesc& M, const float q[3], float z, 
     }
     if (M.wbits > 0) {
         float w = 1.0f / (z * z);
-        om = (u64)__builtin_rintf(__builtin_ldexpf(w, M.wbits));
+        om = __builtin_rintf(__builtin_ldexpf(w, M.wbits));
     } else {
-        om = 1;
+        om = 1.0f;
     }
 }
 
@@ -475,13 +476,24 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         if (c == 1) {
             int g[3];
             u32 Q[3];
-            u64 om;
-            group_terms(M, pw, pz[j], g, Q, om);
+            float omf;
+            group_terms(M, pw, pz[j], g, Q, omf);
             key = voxel_key_of(g[0], g[1], g[2]);
+            u64 om;
+            if (__builtin_expect(__ballot(omf >= 0x1p32f) == 0ull, 1)) {
+                // every Omega of the wave is below 2^32: 32 x 32-bit products
+                const u32 o32 = (u32)omf;
+                om = o32;
+                sq0 = (u64)o32 * Q[0];
+                sq1 = (u64)o32 * Q[1];
+                sq2 = (u64)o32 * Q[2];
+            } else {
+                om = (u64)omf;
+                sq0 = om * Q[0];
+                sq1 = om * Q[1];
+                sq2 = om * Q[2];
+            }
             so = om;
-            sq0 = om * Q[0];
-            sq1 = om * Q[1];
-            sq2 = om * Q[2];
             if (COLOR) {
                 const u32 col = J.colors ? J.colors[ii[j]] : 0u;
                 sc0 = om * (col & 255u);
@@ -497,15 +509,17 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
         // only the last lane of a run enters the tile's table.  A run holds valid points only
         // (every other lane has a key of its own); its first lane is a head, found by ballot,
         // and at the step of shift N a lane adds the partial sum N lanes below when that lane
-        // lies in its run (its position in the run is at least N).
-        // cross-lane reads run with every lane active (never inside a short-circuit condition)
+        // lies in its run (its position in the run is at least N); a step that no lane of the
+        // wave needs (every run shorter than N + 1) is skipped.
+        // cross-lane reads run with every lane active (never inside a short-circuit condition;
+        // the skip is wave-uniform)
         const u64 prev_key = row_shr64<1>(key);
         const bool head0 = r16 == 0 || prev_key != key;
         const u64 heads = __ballot(head0);
         const u64 upto = heads & ((2ull << lane) - 1ull);     // heads at or below this lane
         const u32 runpos = (u32)lane - (u32)(63 - __clzll((long long)upto));
 #define VBX_SEG_STEP(N)                                                                        \
-        {                                                                                      \
+        if (__ballot(runpos >= N) != 0ull) {                                                   \
             const u64 a_so = row_shr64<N>(so), a0 = row_shr64<N>(sq0), a1 = row_shr64<N>(sq1),  \
                       a2 = row_shr64<N>(sq2);                                                  \
             if (runpos >= N) {                                                                 \
@@ -546,7 +560,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
                 if (cnt == 1) {
                     int g1[3];
                     u32 Q1[3];
-                    u64 om1;
+                    float om1;
                     group_terms(M, pw, 1.0f, g1, Q1, om1);
                     pack_single(pw, Q1, P.sq);
                 } else {
@@ -603,7 +617,7 @@ __global__ __launch_bounds__(256) void k_points_grouped(const Job* __restrict__ 
             const float p1[3] = {s_pt[0][k], s_pt[1][k], s_pt[2][k]};
             int g1[3];
             u32 Q1[3];
-            u64 om1;
+            float om1;
             group_terms(M, p1, 1.0f, g1, Q1, om1);
             pack_single(p1, Q1, P.sq);
         } else {
@@ -834,100 +848,159 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
     const u32 total = nb ? off[nb] : 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) cs->ray_count = total;
     const u32 nchunks = (total + kMergeSpan - 1) / kMergeSpan;
+    // The workgroup takes chunks blockIdx.x, blockIdx.x + gridDim.x, ...; each iteration below
+    // merges one batch (or one large bin) of its current chunk.  The next batch's bin offsets,
+    // block keys and first partials are loaded while the current one is merged, so that their
+    // latency overlaps the merge instead of preceding it.
+    // (c, b, be): chunk, first bin of the batch, end of the chunk's bins; a chunk that owns no
+    // bin (a large bin started in an earlier chunk) is passed over.
+    auto seek = [&](u32& c_, u32& b_, u32& be_) {
+        for (; c_ < nchunks; c_ += gridDim.x) {
+            b_ = chunk_first[c_];
+            be_ = c_ + 1 < nchunks ? chunk_first[c_ + 1] : nb;
+            if (b_ < be_) return;
+        }
+    };
+    // loads of the batch at (b_, be_), in two steps (the second needs the first's values):
+    // this thread's bins k = threadIdx.x and k + 256 (offsets, then block keys through the
+    // block list), and the batch's partials at positions threadIdx.x and threadIdx.x + 256
+    u32 nx_off[2] = {0u, 0u}, nx_tl[2] = {0u, 0u}, nx_p0 = 0u;
+    u64 nx_tk[2] = {0ull, 0ull};
+    Partial nx_P[2] = {};
+    auto load_offsets = [&](u32 b_, u32 be_) {
+        const u32 wn_ = be_ - b_ < (u32)kMergeBatch ? be_ - b_ : (u32)kMergeBatch;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const u32 k = threadIdx.x + 256u * (u32)q;
+            if (k <= wn_) nx_off[q] = off[b_ + k];
+            if (k < wn_) nx_tl[q] = tlist[(b_ + k) / JMS];
+        }
+        nx_p0 = off[b_];   // the batch's first partial (the same address in every thread)
+    };
+    auto load_rest = [&](u32 b_, u32 be_) {
+        const u32 wn_ = be_ - b_ < (u32)kMergeBatch ? be_ - b_ : (u32)kMergeBatch;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const u32 k = threadIdx.x + 256u * (u32)q;
+            if (k < wn_) nx_tk[q] = tkeys[nx_tl[q]];
+            const u32 e = nx_p0 + threadIdx.x + 256u * (u32)q;
+            if (e < total) nx_P[q] = sorted[e];
+        }
+    };
+    u32 c = blockIdx.x, b = 0, be = 0;
+    seek(c, b, be);
+    if (c < nchunks) {
+        load_offsets(b, be);
+        load_rest(b, be);
+    }
     __syncthreads();
-    for (u32 c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const u32 bs = chunk_first[c];
-        const u32 be = c + 1 < nchunks ? chunk_first[c + 1] : nb;
-        // bins [bs, be) in batches; a batch is a run of bins with at most kMergeBatch partials
-        u32 b = bs;
-        while (b < be) {
-            // stage the offsets of up to kMergeBatch bins
-            // (and their blocks' keys, loaded alongside rather than after them)
-            const u32 wn = be - b < (u32)kMergeBatch ? be - b : (u32)kMergeBatch;
-            for (u32 k = threadIdx.x; k <= wn; k += 256) {
-                s_off[k] = off[b + k];
-                if (k < wn) s_tk[k] = tkeys[tlist[(b + k) / JMS]];
+    while (c < nchunks) {
+        // stage the offsets and block keys of up to kMergeBatch bins
+        const u32 wn = be - b < (u32)kMergeBatch ? be - b : (u32)kMergeBatch;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const u32 k = threadIdx.x + 256u * (u32)q;
+            if (k <= wn) s_off[k] = nx_off[q];
+            if (k < wn) s_tk[k] = nx_tk[q];
+        }
+        const Partial cur_P[2] = {nx_P[0], nx_P[1]};
+        // the partial at position e, the it-th of this thread (the first two were loaded ahead)
+        auto partial_at = [&](u32 e, u32 it) {
+            Partial P;
+            if (it == 0u) P = cur_P[0];
+            else if (it == 1u) P = cur_P[1];
+            else P = sorted[e];
+            return P;
+        };
+        __syncthreads();
+        const u32 base = s_off[0];
+        // bins [b, b + nbat) hold at most kMergeBatch partials: nbat is the largest n <= wn
+        // with s_off[n] - base <= kMergeBatch (offsets are non-decreasing)
+        u32 nbat = 0;
+        {
+            u32 lo_n = 0, hi_n = wn;
+            while (lo_n < hi_n) {
+                const u32 mid = (lo_n + hi_n + 1) >> 1;
+                if (s_off[mid] - base <= (u32)kMergeBatch) lo_n = mid; else hi_n = mid - 1;
             }
+            nbat = lo_n;
+        }
+        // the next batch: the bins after this one in the chunk, else the next chunk's
+        u32 c_n = c, b_n = b + (nbat ? nbat : 1u), be_n = be;
+        if (b_n >= be_n) {
+            c_n += gridDim.x;
+            seek(c_n, b_n, be_n);
+        }
+        const bool more = c_n < nchunks;
+        if (nbat == 0) {
+            // ---- a bin too large for one hash pass: its at most kMergeVox voxels (one
+            // eighth of the block) over a dense table
+            const u32 lo = s_off[0], hi = s_off[1];
+            const u32 t = b / JMS, rb = b - t * JMS;
+            const u32 jm = rb / (u32)kGroupSubBins, qd = rb % (u32)kGroupSubBins;
+            const u64 tk = s_tk[0];
+            const MapDesc& M = maps[(u32)(tk >> 45)];
+            const int jid = M.job0 + (int)jm;
+            int bx, by, bz;
+            unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
+            u32 it = 0;
+            for (u32 e = lo + threadIdx.x; e < hi; e += 256, ++it) {
+                const Partial P = partial_at(e, it);
+                const u32 vv = P.lj & (u32)(kMergeVox - 1);
+                merge_partial(P, vv, m_so, m_sq, m_hi, m_n, m_p);
+                if (COLOR)
+                    for (int k = 0; k < 3; ++k) atomicAdd(&m_sc[k][vv], sorted_c[e].sc[k]);
+            }
+            if (more) load_offsets(b_n, be_n);
             __syncthreads();
-            const u32 base = s_off[0];
-            // bins [b, b + nbat) hold at most kMergeBatch partials: nbat is the largest n <= wn
-            // with s_off[n] - base <= kMergeBatch (offsets are non-decreasing)
-            u32 nbat = 0;
-            {
-                u32 lo_n = 0, hi_n = wn;
-                while (lo_n < hi_n) {
-                    const u32 mid = (lo_n + hi_n + 1) >> 1;
-                    if (s_off[mid] - base <= (u32)kMergeBatch) lo_n = mid; else hi_n = mid - 1;
-                }
-                nbat = lo_n;
-            }
-            if (nbat == 0) {
-                // ---- a bin too large for one hash pass: its at most kMergeVox voxels (one
-                // eighth of the block) over a dense table
-                const u32 lo = s_off[0], hi = s_off[1];
-                const u32 t = b / JMS, rb = b - t * JMS;
-                const u32 jm = rb / (u32)kGroupSubBins, qd = rb % (u32)kGroupSubBins;
-                const u64 tk = s_tk[0];
-                const MapDesc& M = maps[(u32)(tk >> 45)];
-                const int jid = M.job0 + (int)jm;
-                int bx, by, bz;
-                unpack_block(tk & ((1ull << 45) - 1), bx, by, bz);
-                for (u32 e = lo + threadIdx.x; e < hi; e += 256) {
-                    const Partial& P = sorted[e];
-                    const u32 vv = P.lj & (u32)(kMergeVox - 1);
-                    merge_partial(P, vv, m_so, m_sq, m_hi, m_n, m_p);
-                    if (COLOR)
-                        for (int k = 0; k < 3; ++k) atomicAdd(&m_sc[k][vv], sorted_c[e].sc[k]);
-                }
-                __syncthreads();
-                float4 ray[kMergePerThread];
-                u32 rcol[kMergePerThread];
-                bool has[kMergePerThread];
-                u32 nmine = 0;
+            float4 ray[kMergePerThread];
+            u32 rcol[kMergePerThread];
+            bool has[kMergePerThread];
+            u32 nmine = 0;
 #pragma unroll
-                for (int r = 0; r < kMergePerThread; ++r) {
-                    const int v = threadIdx.x + 256 * r;
-                    const u32 n = m_n[v];
-                    has[r] = n != 0;
-                    ray[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (!n) continue;
-                    const u64 sq[3] = {m_sq[0][v], m_sq[1][v], m_sq[2][v]};
-                    const u32 hw[3] = {m_hi[0][v], m_hi[1][v], m_hi[2][v]};
-                    const float p1[3] = {m_p[0][v], m_p[1][v], m_p[2][v]};
-                    group_ray(M, bx, by, bz, qd * (u32)kMergeVox + (u32)v, n, m_so[v], sq, hw, p1, ray[r]);
-                    rcol[r] = 0u;
-                    if (COLOR) {
-                        const u64 sc[3] = {m_sc[0][v], m_sc[1][v], m_sc[2][v]};
-                        rcol[r] = group_color(sc, m_so[v]);
-                        m_sc[0][v] = 0; m_sc[1][v] = 0; m_sc[2][v] = 0;
-                    }
-                    nmine++;
-                    m_so[v] = 0; m_sq[0][v] = 0; m_sq[1][v] = 0; m_sq[2][v] = 0;
-                    m_hi[0][v] = 0; m_hi[1][v] = 0; m_hi[2][v] = 0; m_n[v] = 0;
+            for (int r = 0; r < kMergePerThread; ++r) {
+                const int v = threadIdx.x + 256 * r;
+                const u32 n = m_n[v];
+                has[r] = n != 0;
+                ray[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (!n) continue;
+                const u64 sq[3] = {m_sq[0][v], m_sq[1][v], m_sq[2][v]};
+                const u32 hw[3] = {m_hi[0][v], m_hi[1][v], m_hi[2][v]};
+                const float p1[3] = {m_p[0][v], m_p[1][v], m_p[2][v]};
+                group_ray(M, bx, by, bz, qd * (u32)kMergeVox + (u32)v, n, m_so[v], sq, hw, p1, ray[r]);
+                rcol[r] = 0u;
+                if (COLOR) {
+                    const u64 sc[3] = {m_sc[0][v], m_sc[1][v], m_sc[2][v]};
+                    rcol[r] = group_color(sc, m_so[v]);
+                    m_sc[0][v] = 0; m_sc[1][v] = 0; m_sc[2][v] = 0;
                 }
-                u32 nrays;
-                const u32 incl = block_scan_256(nmine, lds8, &nrays);
-                u32 pos = lo + incl - nmine;
-#pragma unroll
-                for (int r = 0; r < kMergePerThread; ++r) {
-                    if (!has[r]) continue;
-                    rays_p[pos] = ray[r];
-                    rays_job[pos] = (u32)jid;
-                    if (COLOR) rays_c[pos] = rcol[r];
-                    pos++;
-                }
-                for (u32 e = lo + nrays + threadIdx.x; e < hi; e += 256) rays_job[e] = kNoRay;
-                if (threadIdx.x == 0 && nrays) atomicAdd(&jst[jid].rays, (u64)nrays);
-                __syncthreads();
-                b += 1;
-                continue;
+                nmine++;
+                m_so[v] = 0; m_sq[0][v] = 0; m_sq[1][v] = 0; m_sq[2][v] = 0;
+                m_hi[0][v] = 0; m_hi[1][v] = 0; m_hi[2][v] = 0; m_n[v] = 0;
             }
+            u32 nrays;
+            const u32 incl = block_scan_256(nmine, lds8, &nrays);
+            u32 pos = lo + incl - nmine;
+#pragma unroll
+            for (int r = 0; r < kMergePerThread; ++r) {
+                if (!has[r]) continue;
+                rays_p[pos] = ray[r];
+                rays_job[pos] = (u32)jid;
+                if (COLOR) rays_c[pos] = rcol[r];
+                pos++;
+            }
+            if (more) load_rest(b_n, be_n);
+            for (u32 e = lo + nrays + threadIdx.x; e < hi; e += 256) rays_job[e] = kNoRay;
+            if (threadIdx.x == 0 && nrays) atomicAdd(&jst[jid].rays, (u64)nrays);
+            __syncthreads();
+        } else {
             // ---- hash merge of bins [b, b + nbat)
             const u32 pend = s_off[nbat];
             for (u32 k = threadIdx.x; k < nbat; k += 256) s_nr[k] = 0;
             __syncthreads();
-            for (u32 e = base + threadIdx.x; e < pend; e += 256) {
-                const Partial& P = sorted[e];
+            u32 it = 0;
+            for (u32 e = base + threadIdx.x; e < pend; e += 256, ++it) {
+                const Partial P = partial_at(e, it);
                 // bin of partial e: the last staged bin whose start is <= e
                 u32 lo_i = 0, hi_i = nbat - 1;
                 while (lo_i < hi_i) {
@@ -945,6 +1018,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 if (COLOR)
                     for (int k = 0; k < 3; ++k) atomicAdd(&m_sc[k][h], sorted_c[e].sc[k]);
             }
+            if (more) load_offsets(b_n, be_n);
             __syncthreads();
             for (int h = threadIdx.x; h < kMergeVox; h += 256) {
                 const u32 key = m_key[h];
@@ -973,6 +1047,7 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 m_key[h] = 0; m_so[h] = 0; m_sq[0][h] = 0; m_sq[1][h] = 0; m_sq[2][h] = 0;
                 m_hi[0][h] = 0; m_hi[1][h] = 0; m_hi[2][h] = 0; m_n[h] = 0;
             }
+            if (more) load_rest(b_n, be_n);
             __syncthreads();
             // empty slots of each bin, and per-frame ray counts (one thread per bin)
             for (u32 k = threadIdx.x; k < nbat; k += 256) {
@@ -986,8 +1061,8 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
                 }
             }
             __syncthreads();
-            b += nbat;
         }
+        c = c_n; b = b_n; be = be_n;
     }
 }
 template __global__ void k_group_merge<false>(const Job*, const MapDesc*, const u64*, const u32*, const u32*,
@@ -1505,6 +1580,17 @@ __device__ inline void round_to_storage(float& D, float& W) {
     }
 }
 
+// A fixed-point sum (below 2^62 in magnitude) to binary32: its two 32-bit halves convert to
+// binary64 exactly and one fma joins them (exact below 2^53, else rounded once), then one
+// rounding to binary32 -- within 2^-24 + 2^-53 of the sum relative to it, in a few
+// instructions instead of the integer normalisation of a direct 64-bit conversion.
+__device__ inline float fixed_to_float(u64 x) {
+    return (float)__builtin_fma((double)(u32)(x >> 32), 0x1p32, (double)(u32)x);
+}
+__device__ inline float fixed_to_float(i64 x) {
+    return (float)__builtin_fma((double)(int)(x >> 32), 0x1p32, (double)(u32)(u64)x);
+}
+
 constexpr int kOffWindow = 256;   // frames whose bin offsets are staged in LDS at a time
 
 // Order in which the update takes the call's blocks: heaviest first (log2 buckets of the rays
@@ -1691,7 +1777,9 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                         float4 rn = make_float4(0.f, 0.f, 0.f, 0.f);
                         if (e + S.stride < hi) rn = sorted[e + S.stride];
                         const float p[3] = {rp.x, rp.y, rp.z};
-                        const float wgt = rp.w;
+                        // the ray weight in fixed-point units: scaling by the power of two 2^kw
+                        // here rather than after the products leaves every product unchanged
+                        const float wgt = rp.w * M.wscale;
                         rp = rn;
                         float ev[3], r;
                         Walk w;
@@ -1718,7 +1806,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                 const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
                                 const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
                                 u64 fw, fd;
-                                fixed_terms(o.w * M.wscale, o.w * o.e * M.wscale, fw, fd);
+                                fixed_terms(o.w, o.w * o.e, fw, fd);
                                 // issued unconditionally: a wave issues an LDS atomic once for
                                 // all its lanes, and adding zero is harmless
                                 atomicAdd(&sw_buf[l], fw);
@@ -1745,10 +1833,10 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                             if (!dn[h]) continue;
                             const u64 sw_fx = a_w[h][l];
                             if (sw_fx) {
-                                const float sw = (float)sw_fx * M.inv_wscale;
+                                const float sw = fixed_to_float(sw_fx) * M.inv_wscale;
                                 // sums are in units of delta; binary32 storage keeps D in metres,
                                 // 16-bit storage keeps D / delta
-                                float swd = (float)(i64)a_d[h][l] * M.inv_wscale;
+                                float swd = fixed_to_float((i64)a_d[h][l]) * M.inv_wscale;
                                 if (STORAGE == 0) swd = swd * M.delta;
                                 float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
                                 float Wn = W[j] + sw;
@@ -1808,7 +1896,9 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                         u32 rnc = 0;
                         if (e + NT < hi) { rn = sorted[e + NT]; if (COLOR) rnc = sorted_c[e + NT]; }
                         const float p[3] = {rp.x, rp.y, rp.z};
-                        const float wgt = rp.w;
+                        // the ray weight in fixed-point units: scaling by the power of two 2^kw
+                        // here rather than after the products leaves every product unchanged
+                        const float wgt = rp.w * M.wscale;
                         const float cf[3] = {(float)(rc & 255u), (float)((rc >> 8) & 255u), (float)((rc >> 16) & 255u)};
                         rp = rn;
                         rc = rnc;
@@ -1837,14 +1927,14 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                 const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
                                 const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
                                 u64 fw, fd;
-                                fixed_terms(o.w * M.wscale, o.w * o.e * M.wscale, fw, fd);
+                                fixed_terms(o.w, o.w * o.e, fw, fd);
                                 // issued unconditionally: a wave issues an LDS atomic once for
                                 // all its lanes, and adding zero is harmless
                                 atomicAdd(&a_w[0][l], fw);
                                 atomicAdd(&a_d[0][l], fd);
                                 atomicAdd(&a_c[l], 1u);
                                 if (COLOR) {
-                                    const float cscale = M.wscale * (1.0f / 256.0f);
+                                    const float cscale = 1.0f / 256.0f;   // o.w carries 2^kw
 #pragma unroll
                                     for (int k = 0; k < 3; ++k)
                                         atomicAdd(&a_sc[k][l], (u64)__builtin_rintf(o.w * cf[k] * cscale));
@@ -1880,10 +1970,10 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                             }
                             if (COLOR) { a_sc[0][l] = 0; a_sc[1][l] = 0; a_sc[2][l] = 0; }
                             if (sw_fx) {
-                                const float sw = (float)sw_fx * M.inv_wscale;
+                                const float sw = fixed_to_float(sw_fx) * M.inv_wscale;
                                 // sums are in units of delta; binary32 storage keeps D in metres,
                                 // 16-bit storage keeps D / delta
-                                float swd = (float)(i64)a_d[0][l] * M.inv_wscale;
+                                float swd = fixed_to_float((i64)a_d[0][l]) * M.inv_wscale;
                                 if (STORAGE == 0) swd = swd * M.delta;
                                 float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
                                 float Wn = W[j] + sw;
