@@ -296,7 +296,7 @@ __device__ inline Obs observe(const MapDesc& M, const float p[3], const float e[
     const float h1 = f1 - __builtin_fmaf(c1, M.v, -x1);
     const float h2 = f2 - __builtin_fmaf(c2, M.v, -x2);
     float d;
-    if (M.dist == 0) {
+    if (__builtin_expect(M.dist == 0, 1)) {   // the Eq. (1) distance, the common form
         const float dot = (f0 * e[0] + f1 * e[1]) + f2 * e[2];
         // the hardware square root (within 1 ulp of the exact root) of the exact-centre offset
         const float mag = __builtin_amdgcn_sqrtf((h0 * h0 + h1 * h1) + h2 * h2);

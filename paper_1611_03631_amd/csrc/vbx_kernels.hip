@@ -1801,8 +1801,9 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                         bool inside = false;
                         for (int guard = 0; guard < M.max_steps; ++guard) {
                             const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
-                            if ((u32)lx < (u32)RX && (u32)ly < (u32)RY && (u32)lz < (u32)RZ) {
-                                inside = true;
+                            // (bitwise operators: no branch per test)
+                            const bool in = ((u32)lx < (u32)RX) & ((u32)ly < (u32)RY) & ((u32)lz < (u32)RZ);
+                            if (in) {
                                 const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
                                 const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
                                 u64 fw, fd;
@@ -1812,10 +1813,12 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                 atomicAdd(&sw_buf[l], fw);
                                 atomicAdd(&sd_buf[l], fd);
                                 atomicAdd(&a_c[l], S.cadd);
-                            } else if (inside) {
-                                break;   // the walk is monotone per axis: it never re-enters the region
                             }
-                            if (w.left == 0) break;
+                            // one exit: the walk's last voxel, or the first voxel after the region
+                            // (the walk is monotone per axis: it never re-enters the region)
+                            const bool stop = (inside & !in) | (w.left == 0);
+                            inside |= in;
+                            if (stop) break;
                             walk_step(w);
                         }
                     }
@@ -1922,8 +1925,9 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                         bool inside = false;
                         for (int guard = 0; guard < M.max_steps; ++guard) {
                             const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
-                            if ((u32)lx < (u32)RX && (u32)ly < (u32)RY && (u32)lz < (u32)RZ) {
-                                inside = true;
+                            // (bitwise operators: no branch per test)
+                            const bool in = ((u32)lx < (u32)RX) & ((u32)ly < (u32)RY) & ((u32)lz < (u32)RZ);
+                            if (in) {
                                 const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
                                 const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
                                 u64 fw, fd;
@@ -1939,10 +1943,12 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                     for (int k = 0; k < 3; ++k)
                                         atomicAdd(&a_sc[k][l], (u64)__builtin_rintf(o.w * cf[k] * cscale));
                                 }
-                            } else if (inside) {
-                                break;   // the walk is monotone per axis: it never re-enters the region
                             }
-                            if (w.left == 0) break;
+                            // one exit: the walk's last voxel, or the first voxel after the region
+                            // (the walk is monotone per axis: it never re-enters the region)
+                            const bool stop = (inside & !in) | (w.left == 0);
+                            inside |= in;
+                            if (stop) break;
                             walk_step(w);
                         }
                     }

@@ -51,11 +51,12 @@ VBX_HD inline void walk_setup_vox(const float A[3], const float B[3], Walk& w) {
 // (Constant indices only, so the walk state stays in registers.)
 VBX_HD inline void walk_step(Walk& w) {
     // the axis with steps left whose next boundary comes first (ties: the lowest axis), chosen
-    // with selects rather than branches, so that the lanes of a wave never diverge here
+    // with selects rather than branches (bitwise operators: no short-circuit), so that the lanes
+    // of a wave never diverge here
     const bool c0 = w.n[0] > 0, c1 = w.n[1] > 0, c2 = w.n[2] > 0;
-    const bool t1 = c1 && (!c0 || w.tM[1] < w.tM[0]);
+    const bool t1 = c1 & (!c0 | (w.tM[1] < w.tM[0]));
     const float best = t1 ? w.tM[1] : w.tM[0];
-    const bool t2 = c2 && ((!c0 && !t1) || w.tM[2] < best);
+    const bool t2 = c2 & ((!c0 & !t1) | (w.tM[2] < best));
     // an axis is always found: the caller only steps while w.left > 0
     const int axis = t2 ? 2 : (t1 ? 1 : 0);
 #pragma unroll
