@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <type_traits>
 #include <stdint.h>
 
 #include "vbx_walk.h"
@@ -282,6 +283,8 @@ struct Obs {
     float e;     // clamped distance / delta, in [-1, 1]
 };
 
+// DIST: the distance form (M.dist), fixed by the caller for a whole walk.
+template <int DIST>
 __device__ inline Obs observe(const MapDesc& M, const float p[3], const float e[3], float r,
                               float wgt, int gx, int gy, int gz) {
     // Voxel centre c v, c = g + 1/2 (exact in binary32 for |g| < 2^18).  The rounded product
@@ -296,7 +299,7 @@ __device__ inline Obs observe(const MapDesc& M, const float p[3], const float e[
     const float h1 = f1 - __builtin_fmaf(c1, M.v, -x1);
     const float h2 = f2 - __builtin_fmaf(c2, M.v, -x2);
     float d;
-    if (__builtin_expect(M.dist == 0, 1)) {   // the Eq. (1) distance, the common form
+    if (DIST == 0) {
         const float dot = (f0 * e[0] + f1 * e[1]) + f2 * e[2];
         // the hardware square root (within 1 ulp of the exact root) of the exact-centre offset
         const float mag = __builtin_amdgcn_sqrtf((h0 * h0 + h1 * h1) + h2 * h2);
@@ -329,10 +332,9 @@ __device__ inline u64 rint_fixed51(float x) {
 // weights all lie below 2^51 in fixed point (every ray of fewer than 2^(51 - kw) points'
 // weight) takes the short binary64 form; otherwise the general 64-bit conversion.
 __device__ inline void fixed_terms(float xw, float xd, u64& fw, u64& fd) {
-    if (__builtin_expect(__ballot(!(xw < 0x1p51f)) == 0ull, 1)) {
-        fw = rint_fixed51(xw);
-        fd = rint_fixed51(xd);
-    } else {
+    fw = rint_fixed51(xw);
+    fd = rint_fixed51(xd);
+    if (__builtin_expect(__ballot(!(xw < 0x1p51f)) != 0ull, 0)) {   // rare: the general form
         fw = (u64)__builtin_rintf(xw);
         fd = (u64)(i64)__builtin_rintf(xd);
     }

@@ -1798,29 +1798,35 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                             }
                             if (miss) continue;
                         }
-                        bool inside = false;
-                        for (int guard = 0; guard < M.max_steps; ++guard) {
-                            const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
-                            // (bitwise operators: no branch per test)
-                            const bool in = ((u32)lx < (u32)RX) & ((u32)ly < (u32)RY) & ((u32)lz < (u32)RZ);
-                            if (in) {
-                                const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
-                                const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
-                                u64 fw, fd;
-                                fixed_terms(o.w, o.w * o.e, fw, fd);
-                                // issued unconditionally: a wave issues an LDS atomic once for
-                                // all its lanes, and adding zero is harmless
-                                atomicAdd(&sw_buf[l], fw);
-                                atomicAdd(&sd_buf[l], fd);
-                                atomicAdd(&a_c[l], S.cadd);
+                        // the walk through the region, with the distance form fixed per ray
+                        auto walk_band = [&](auto dist_form) {
+                            constexpr int DIST = decltype(dist_form)::value;
+                            bool inside = false;
+                            for (int guard = 0; guard < M.max_steps; ++guard) {
+                                const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
+                                // (bitwise operators: no branch per test)
+                                const bool in = ((u32)lx < (u32)RX) & ((u32)ly < (u32)RY) & ((u32)lz < (u32)RZ);
+                                if (in) {
+                                    const Obs o = observe<DIST>(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
+                                    const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
+                                    u64 fw, fd;
+                                    fixed_terms(o.w, o.w * o.e, fw, fd);
+                                    // issued unconditionally: a wave issues an LDS atomic once for
+                                    // all its lanes, and adding zero is harmless
+                                    atomicAdd(&sw_buf[l], fw);
+                                    atomicAdd(&sd_buf[l], fd);
+                                    atomicAdd(&a_c[l], S.cadd);
+                                }
+                                // one exit: the walk's last voxel, or the first voxel after the region
+                                // (the walk is monotone per axis: it never re-enters the region)
+                                const bool stop = (inside & !in) | (w.left == 0);
+                                inside |= in;
+                                if (stop) break;
+                                walk_step(w);
                             }
-                            // one exit: the walk's last voxel, or the first voxel after the region
-                            // (the walk is monotone per axis: it never re-enters the region)
-                            const bool stop = (inside & !in) | (w.left == 0);
-                            inside |= in;
-                            if (stop) break;
-                            walk_step(w);
-                        }
+                        };
+                        if (M.dist == 0) walk_band(std::integral_constant<int, 0>{});
+                        else walk_band(std::integral_constant<int, 1>{});
                     }
                     __syncthreads();
                     // Eqs. (3)-(4), once per voxel for each frame of the step, in frame order
@@ -1922,35 +1928,41 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                             }
                             if (miss) continue;
                         }
-                        bool inside = false;
-                        for (int guard = 0; guard < M.max_steps; ++guard) {
-                            const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
-                            // (bitwise operators: no branch per test)
-                            const bool in = ((u32)lx < (u32)RX) & ((u32)ly < (u32)RY) & ((u32)lz < (u32)RZ);
-                            if (in) {
-                                const Obs o = observe(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
-                                const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
-                                u64 fw, fd;
-                                fixed_terms(o.w, o.w * o.e, fw, fd);
-                                // issued unconditionally: a wave issues an LDS atomic once for
-                                // all its lanes, and adding zero is harmless
-                                atomicAdd(&a_w[0][l], fw);
-                                atomicAdd(&a_d[0][l], fd);
-                                atomicAdd(&a_c[l], 1u);
-                                if (COLOR) {
-                                    const float cscale = 1.0f / 256.0f;   // o.w carries 2^kw
-#pragma unroll
-                                    for (int k = 0; k < 3; ++k)
-                                        atomicAdd(&a_sc[k][l], (u64)__builtin_rintf(o.w * cf[k] * cscale));
+                        // the walk through the region, with the distance form fixed per ray
+                        auto walk_band = [&](auto dist_form) {
+                            constexpr int DIST = decltype(dist_form)::value;
+                            bool inside = false;
+                            for (int guard = 0; guard < M.max_steps; ++guard) {
+                                const int lx = w.g[0] - ox, ly = w.g[1] - oy, lz = w.g[2] - oz;
+                                // (bitwise operators: no branch per test)
+                                const bool in = ((u32)lx < (u32)RX) & ((u32)ly < (u32)RY) & ((u32)lz < (u32)RZ);
+                                if (in) {
+                                    const Obs o = observe<DIST>(M, p, ev, r, wgt, w.g[0], w.g[1], w.g[2]);
+                                    const u32 l = (u32)lx + (u32)RX * ((u32)ly + (u32)RY * (u32)lz);
+                                    u64 fw, fd;
+                                    fixed_terms(o.w, o.w * o.e, fw, fd);
+                                    // issued unconditionally: a wave issues an LDS atomic once for
+                                    // all its lanes, and adding zero is harmless
+                                    atomicAdd(&a_w[0][l], fw);
+                                    atomicAdd(&a_d[0][l], fd);
+                                    atomicAdd(&a_c[l], 1u);
+                                    if (COLOR) {
+                                        const float cscale = 1.0f / 256.0f;   // o.w carries 2^kw
+    #pragma unroll
+                                        for (int k = 0; k < 3; ++k)
+                                            atomicAdd(&a_sc[k][l], (u64)__builtin_rintf(o.w * cf[k] * cscale));
+                                    }
                                 }
+                                // one exit: the walk's last voxel, or the first voxel after the region
+                                // (the walk is monotone per axis: it never re-enters the region)
+                                const bool stop = (inside & !in) | (w.left == 0);
+                                inside |= in;
+                                if (stop) break;
+                                walk_step(w);
                             }
-                            // one exit: the walk's last voxel, or the first voxel after the region
-                            // (the walk is monotone per axis: it never re-enters the region)
-                            const bool stop = (inside & !in) | (w.left == 0);
-                            inside |= in;
-                            if (stop) break;
-                            walk_step(w);
-                        }
+                        };
+                        if (M.dist == 0) walk_band(std::integral_constant<int, 0>{});
+                        else walk_band(std::integral_constant<int, 1>{});
                     }
                     __syncthreads();
                     // Eqs. (3)-(4), once per voxel for this frame
