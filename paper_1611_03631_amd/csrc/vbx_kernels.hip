@@ -1117,6 +1117,7 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                                                CallState* __restrict__ cs, u32 ray_cap) {
     __shared__ u64 s_key[kCrossSlots];
     __shared__ u32 s_h[kCrossSlots];   // global block-set slot of each key (kCrossPending: not yet)
+    __shared__ u32 s_pend[kCrossSlots / 32];   // bit per slot: a key new to the set this batch
     __shared__ u32 s_fill;             // keys in the LDS set
     const u32 nrays = cs->ray_count < ray_cap ? cs->ray_count : ray_cap;
     const u32 nbatch = (nrays + 255u) / 256u;
@@ -1124,6 +1125,7 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
     const u32 bt0 = blockIdx.x * per;
     const u32 bt1 = bt0 + per < nbatch ? bt0 + per : nbatch;
     for (int k = threadIdx.x; k < kCrossSlots; k += 256) s_key[k] = kEmpty;
+    for (int k = threadIdx.x; k < kCrossSlots / 32; k += 256) s_pend[k] = 0;
     if (threadIdx.x == 0) s_fill = 0;
     __syncthreads();
     // the first batch's ray slots; each batch loads the next one's while it works
@@ -1188,6 +1190,7 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                         const u32 h = lds_set_insert(s_key, mapbits | bk, &fresh);
                         if (fresh) {
                             s_h[h] = kCrossPending;
+                            atomicOr(&s_pend[h >> 5], 1u << (h & 31u));
                             added++;
                         }
                         if (nc < 4) held0 |= (u64)h << (16 * nc);
@@ -1202,10 +1205,19 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
             if (lane_id() == 0 && wa) atomicAdd(&s_fill, wa);
         }
         __syncthreads();
-        // phase 2: each block new to the LDS set enters the per-call block set
-        for (int k = threadIdx.x; k < kCrossSlots; k += 256)
-            if (s_h[k] == kCrossPending && s_key[k] != kEmpty)
-                s_h[k] = tset_insert<true>(tkeys, tmask, s_key[k], tlist, tlist_cap, cs);
+        // phase 2: each block new to the LDS set enters the per-call block set (the slots
+        // marked in s_pend, a word of 32 per thread; the marks are cleared for the next batch)
+        for (int k = threadIdx.x; k < kCrossSlots / 32; k += 256) {
+            u32 bits = s_pend[k];
+            if (bits) {
+                s_pend[k] = 0;
+                while (bits) {
+                    const u32 slot = (u32)k * 32u + (u32)(__ffs(bits) - 1);
+                    bits &= bits - 1u;
+                    s_h[slot] = tset_insert<true>(tkeys, tmask, s_key[slot], tlist, tlist_cap, cs);
+                }
+            }
+        }
         __syncthreads();
         // phase 3: crossing c of ray slot i goes to cross[i * MB + c], and (raycasting calls)
         // counts towards its (block-set slot, frame) bin
