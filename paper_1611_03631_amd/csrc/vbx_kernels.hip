@@ -1676,11 +1676,32 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
     __shared__ u64 a_d[K][VOX];   // sum of fixed-point weight * distance/delta (two's complement)
     __shared__ u32 a_c[VOX];      // rays over the call (see above)
     __shared__ u32 s_off[kOffWindow + 1];
+    __shared__ unsigned short s_fr[kOffWindow];   // the window's frames with rays, in order
+    __shared__ u32 s_wcnt[kOffWindow / 64];       // their count per wave of the listing
     __shared__ u32 s_t;
     __shared__ u32 s_stat[3];
     __shared__ u32 s_tbase;
     __shared__ u32 lds8[NT / 64];
     static_assert(NT % (64 * K) == 0, "each half of the workgroup is whole waves");
+    static_assert(NT >= kOffWindow, "one thread per frame of a window");
+    // Lists the frames of the staged window (wn of them) that have rays in s_fr, in order;
+    // returns their count (the same in every thread).  Called by every thread.
+    auto list_frames = [&](int wn) -> int {
+        const int j = (int)threadIdx.x, wave = j >> 6, lane = lane_id();
+        const bool has = j < wn && s_off[j + 1] > s_off[j];
+        const u64 bal = __ballot(has);
+        if (wave < kOffWindow / 64 && lane == 0) s_wcnt[wave] = (u32)__popcll(bal);
+        __syncthreads();
+        u32 base = 0, tot = 0;
+#pragma unroll
+        for (int v = 0; v < kOffWindow / 64; ++v) {
+            base += v < wave ? s_wcnt[v] : 0u;
+            tot += s_wcnt[v];
+        }
+        if (has) s_fr[base + (u32)__popcll(bal & ((1ull << lane) - 1ull))] = (unsigned short)j;
+        __syncthreads();
+        return __builtin_amdgcn_readfirstlane((int)tot);
+    };
     for (int i = threadIdx.x; i < VOX; i += NT) {
         a_c[i] = 0;
 #pragma unroll
@@ -1733,27 +1754,27 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                 const int wn = M.njobs - w0 < kOffWindow ? M.njobs - w0 : kOffWindow;
                 for (int k = threadIdx.x; k <= wn; k += NT) s_off[k] = off[t * JM + (u32)(w0 + k)];
                 __syncthreads();
+                const int nfr = list_frames(wn);
                 // Step plan from the window's offsets (the same in every thread): the step's first
-                // frame jm, the next frame with rays jn, whether the two are walked together, and this
-                // thread's frame, position and stride in that frame's rays.
-                auto next_frame = [&](int j) {
-                    while (j < wn && s_off[j] == s_off[j + 1]) ++j;
-                    return j;
-                };
+                // frame jm (the im-th frame with rays), the next frame with rays jn, whether the two
+                // are walked together, and this thread's frame, position and stride in that frame's
+                // rays.
+                auto fr_at = [&](int i) { return i < nfr ? __builtin_amdgcn_readfirstlane((int)s_fr[i]) : wn; };
                 struct Step {
-                    int jm, jn, fr;
+                    int im, jm, jn, fr;
                     bool pair;
                     u32 pos, stride, cadd;
                     int half;
                 };
-                auto plan = [&](int jm) {
+                auto plan = [&](int im) {
                     Step S;
-                    S.jm = jm;
-                    S.jn = jm < wn ? next_frame(jm + 1) : wn;
-                    S.pair = K == 2 && S.jn < wn && s_off[jm + 1] - s_off[jm] < 65536u &&
+                    S.im = im;
+                    S.jm = fr_at(im);
+                    S.jn = S.jm < wn ? fr_at(im + 1) : wn;
+                    S.pair = K == 2 && S.jn < wn && s_off[S.jm + 1] - s_off[S.jm] < 65536u &&
                              s_off[S.jn + 1] - s_off[S.jn] < 65536u;
                     S.half = S.pair && (int)threadIdx.x >= NT / 2 ? 1 : 0;
-                    S.fr = S.half ? S.jn : jm;
+                    S.fr = S.half ? S.jn : S.jm;
                     S.pos = S.half ? threadIdx.x - NT / 2 : threadIdx.x;
                     S.stride = S.pair ? NT / 2 : NT;
                     S.cadd = S.half ? 65536u : 1u;
@@ -1761,7 +1782,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                 };
                 // the first ray and sensor origin of every thread for the next step are loaded while
                 // the current step is processed
-                Step S = plan(next_frame(0));
+                Step S = plan(0);
                 float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
                 float nxs[3] = {0.f, 0.f, 0.f};
                 if (S.jm < wn) {
@@ -1771,7 +1792,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                     nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
                 }
                 while (S.jm < wn) {
-                    const Step Sn = plan(next_frame(S.pair ? S.jn + 1 : S.jn));
+                    const Step Sn = plan(S.pair ? S.im + 2 : S.im + 1);
                     const float4 cur = nxt;
                     const float s[3] = {nxs[0], nxs[1], nxs[2]};
                     const u32 lo = s_off[S.fr], hi = s_off[S.fr + 1];
@@ -1883,10 +1904,11 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                 const int wn = M.njobs - w0 < kOffWindow ? M.njobs - w0 : kOffWindow;
                 for (int k = threadIdx.x; k <= wn; k += NT) s_off[k] = off[t * JM + (u32)(w0 + k)];
                 __syncthreads();
-                // frames of the window in order; the first ray of every thread for the next frame
-                // that has rays is loaded while the current frame is processed
-                int jm = 0;
-                while (jm < wn && s_off[jm] == s_off[jm + 1]) ++jm;
+                const int nfr = list_frames(wn);
+                // frames of the window with rays in order (the im-th is jm); the first ray of every
+                // thread for the next one is loaded while the current frame is processed
+                int im = 0;
+                int jm = nfr > 0 ? __builtin_amdgcn_readfirstlane((int)s_fr[0]) : wn;
                 float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
                 u32 nxc = 0;                       // colour maps: the ray's colour, loaded with it
                 float nxs[3] = {0.f, 0.f, 0.f};   // that frame's sensor origin, also loaded ahead
@@ -1897,8 +1919,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                     nxs[0] = Jn.pose[3]; nxs[1] = Jn.pose[7]; nxs[2] = Jn.pose[11];
                 }
                 while (jm < wn) {
-                    int jn = jm + 1;
-                    while (jn < wn && s_off[jn] == s_off[jn + 1]) ++jn;
+                    const int jn = im + 1 < nfr ? __builtin_amdgcn_readfirstlane((int)s_fr[im + 1]) : wn;
                     const float4 cur = nxt;
                     const u32 curc = nxc;
                     const float s[3] = {nxs[0], nxs[1], nxs[2]};
@@ -2020,6 +2041,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                     }
                     __syncthreads();
                     jm = jn;
+                    ++im;
                 }
                 __syncthreads();
             }
