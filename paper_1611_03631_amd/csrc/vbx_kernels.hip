@@ -1172,20 +1172,26 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
             // block-changing steps alone (every 16th step of an axis), with the crossing
             // parameters of the voxel walk, which is not stepped here.
             if (ok) {
-                const bool full = Mp->full_ray != 0;
                 BlockWalk bw;
                 block_walk_init(w, bw);
-                for (int guard = 0, axis = 0; axis >= 0 && guard <= Mp->max_steps;
-                     ++guard, axis = block_walk_next(bw)) {
-                    const u64 bk = pack_block(bw.b[0], bw.b[1], bw.b[2]);
-                    if (full) {
+                // (the walk's form is uniform across the workgroup's map: two loops, no branch
+                // inside either)
+                if (Mp->full_ray != 0) {
+                    for (int guard = 0, axis = 0; axis >= 0 && guard <= Mp->max_steps;
+                         ++guard, axis = block_walk_next(bw)) {
+                        const u64 bk = pack_block(bw.b[0], bw.b[1], bw.b[2]);
                         // a whole ray crosses up to MB blocks, more than the LDS set and
                         // registers hold: each crossing enters the call's block set at once
                         const u32 h = tset_insert<true>(tkeys, tmask, mapbits | bk, tlist, tlist_cap, cs);
                         if (nc < MB) cross[(size_t)i * MB + nc] = h;
                         // (a failed insert is an error of the call and is not counted)
                         if (hbins) wave_count_by_key(hbins, nc < MB && h != 0xFFFFFFFFu, h * JM + jm);
-                    } else {
+                        nc++;
+                    }
+                } else {
+                    for (int guard = 0, axis = 0; axis >= 0 && guard <= Mp->max_steps;
+                         ++guard, axis = block_walk_next(bw)) {
+                        const u64 bk = pack_block(bw.b[0], bw.b[1], bw.b[2]);
                         bool fresh;
                         const u32 h = lds_set_insert(s_key, mapbits | bk, &fresh);
                         if (fresh) {
@@ -1193,10 +1199,12 @@ __global__ __launch_bounds__(256) void k_cross(const Job* __restrict__ jobs,
                             atomicOr(&s_pend[h >> 5], 1u << (h & 31u));
                             added++;
                         }
-                        if (nc < 4) held0 |= (u64)h << (16 * nc);
-                        else if (nc < kCrossHeld) held1 |= (u64)h << (16 * (nc - 4));
+                        // slot c of the crossing in held0 (c < 4) or held1 (4 <= c < 8)
+                        const u64 sh = (u64)h << (16u * (nc & 3u));
+                        held0 |= nc < 4u ? sh : 0ull;
+                        held1 |= (nc >= 4u && nc < kCrossHeld) ? sh : 0ull;
+                        nc++;
                     }
-                    nc++;
                 }
             }
         }
