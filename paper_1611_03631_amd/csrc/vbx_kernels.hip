@@ -1870,23 +1870,28 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                         else walk_band(std::integral_constant<int, 1>{});
                     }
                     __syncthreads();
-                    // Eqs. (3)-(4), once per voxel for each frame of the step, in frame order
+                    // Eqs. (3)-(4), once per voxel for each frame of the step, in frame order.
+                    // (The counts of all this thread's voxels are read together, and each sum
+                    // pair together: LDS reads in flight at once rather than one after another.)
+                    u32 cnt_all[VPT];
+    #pragma unroll
+                    for (int j = 0; j < VPT; ++j) cnt_all[j] = a_c[threadIdx.x + NT * j];
     #pragma unroll
                     for (int j = 0; j < VPT; ++j) {
                         const int l = threadIdx.x + NT * j;
-                        const u32 c = a_c[l];
+                        const u32 c = cnt_all[j];
                         const u32 d = c - last[j];
                         last[j] = c;
                         const u32 dn[2] = {S.pair ? (d & 0xFFFFu) : d, S.pair ? (d >> 16) : 0u};
     #pragma unroll
                         for (int h = 0; h < K; ++h) {
                             if (!dn[h]) continue;
-                            const u64 sw_fx = a_w[h][l];
+                            const u64 sw_fx = a_w[h][l], sd_fx = a_d[h][l];
                             if (sw_fx) {
                                 const float sw = fixed_to_float(sw_fx) * M.inv_wscale;
                                 // sums are in units of delta; binary32 storage keeps D in metres,
                                 // 16-bit storage keeps D / delta
-                                float swd = fixed_to_float((i64)a_d[h][l]) * M.inv_wscale;
+                                float swd = fixed_to_float((i64)sd_fx) * M.inv_wscale;
                                 if (STORAGE == 0) swd = swd * M.delta;
                                 float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
                                 float Wn = W[j] + sw;
@@ -2006,13 +2011,17 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                         else walk_band(std::integral_constant<int, 1>{});
                     }
                     __syncthreads();
-                    // Eqs. (3)-(4), once per voxel for this frame
+                    // Eqs. (3)-(4), once per voxel for this frame (counts read together, and
+                    // each sum pair together, as above)
+                    u32 cnt_all[VPT];
+    #pragma unroll
+                    for (int j = 0; j < VPT; ++j) cnt_all[j] = a_c[threadIdx.x + NT * j];
     #pragma unroll
                     for (int j = 0; j < VPT; ++j) {
                         const int l = threadIdx.x + NT * j;
-                        const u32 c = a_c[l];
+                        const u32 c = cnt_all[j];
                         if (c) {
-                            const u64 sw_fx = a_w[0][l];
+                            const u64 sw_fx = a_w[0][l], sd_fx = a_d[0][l];
                             if (has_color && sw_fx) {
                                 // colour first, with the weight from before the frame
                                 const double swd64 = (double)sw_fx * (double)M.inv_wscale, Wd = (double)W[j];
@@ -2032,7 +2041,7 @@ __global__ __launch_bounds__(NT) void k_update(const Job* __restrict__ jobs,
                                 const float sw = fixed_to_float(sw_fx) * M.inv_wscale;
                                 // sums are in units of delta; binary32 storage keeps D in metres,
                                 // 16-bit storage keeps D / delta
-                                float swd = fixed_to_float((i64)a_d[0][l]) * M.inv_wscale;
+                                float swd = fixed_to_float((i64)sd_fx) * M.inv_wscale;
                                 if (STORAGE == 0) swd = swd * M.delta;
                                 float Dn = (W[j] * D[j] + swd) / (W[j] + sw);
                                 float Wn = W[j] + sw;
