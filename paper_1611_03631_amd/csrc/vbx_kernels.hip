@@ -791,13 +791,20 @@ __device__ inline void merge_partial(const Partial& P, u32 v, u64* m_so, u64 (*m
         add[2] = so * Q[2];
         m_p[0][v] = p1[0]; m_p[1][v] = p1[1]; m_p[2][v] = p1[2];   // read only if the group stays single
     }
-    atomicAdd(&m_so[v], so);
+    // the three returning adds are issued together, their carries (rare) added afterwards
+    u64 old[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const u64 old = atomicAdd(&m_sq[k][v], add[k]);
-        if (old + add[k] < old) atomicAdd(&m_hi[k][v], 1u);   // carry
-    }
+    for (int k = 0; k < 3; ++k) old[k] = atomicAdd(&m_sq[k][v], add[k]);
+    atomicAdd(&m_so[v], so);
     atomicAdd(&m_n[v], n);
+    bool carry[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) carry[k] = old[k] + add[k] < old[k];
+    if (__builtin_expect(__ballot(carry[0] | carry[1] | carry[2]) != 0ull, 0)) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (carry[k]) atomicAdd(&m_hi[k][v], 1u);
+    }
 }
 
 // The mean colour of a group, per channel round(sc / so) to nearest with ties to even, in
