@@ -890,8 +890,9 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
         for (int q = 0; q < 2; ++q) {
             const u32 k = threadIdx.x + 256u * (u32)q;
             if (k < wn_) nx_tk[q] = tkeys[nx_tl[q]];
+            // (a hash batch holds at most kMergeBatch partials: none is loaded beyond them)
             const u32 e = nx_p0 + threadIdx.x + 256u * (u32)q;
-            if (e < total) nx_P[q] = sorted[e];
+            if (e < total && e < nx_p0 + (u32)kMergeBatch) nx_P[q] = sorted[e];
         }
     };
     u32 c = blockIdx.x, b = 0, be = 0;
@@ -911,11 +912,12 @@ __global__ __launch_bounds__(256) void k_group_merge(const Job* __restrict__ job
             if (k < wn) s_tk[k] = nx_tk[q];
         }
         const Partial cur_P[2] = {nx_P[0], nx_P[1]};
-        // the partial at position e, the it-th of this thread (the first two were loaded ahead)
+        // the partial at position e, the it-th of this thread (loaded ahead when it lies among
+        // the batch's first kMergeBatch partials)
         auto partial_at = [&](u32 e, u32 it) {
             Partial P;
             if (it == 0u) P = cur_P[0];
-            else if (it == 1u) P = cur_P[1];
+            else if (it == 1u && e < s_off[0] + (u32)kMergeBatch) P = cur_P[1];
             else P = sorted[e];
             return P;
         };
