@@ -73,19 +73,22 @@ __device__ inline void wave_group_by_key(bool active, u32 key, u32& leader_of, u
 // key.  The groups are found first (ballots only) and every group's atomic is then issued by
 // one instruction, so a wave waits for one atomic round trip rather than one per key.
 __device__ inline u32 wave_claim_by_key(u32* bins, const u32* off, bool active, u32 key) {
+    const u32 o = off[active ? key : 0u];   // loaded before the reservation, in flight with it
     u32 leader_of, rank, count;
     wave_group_by_key(active, key, leader_of, rank, count);
     u32 old = 0;
     if (count) old = atomicSub(&bins[key], count);   // the leaders, together
     const u32 base = (u32)__shfl((int)old, (int)leader_of);
-    return active ? off[key] + base - 1u - rank : 0u;
+    return active ? o + base - 1u - rank : 0u;
 }
 
 // The same for N keys per lane, all N sets of reservations in flight together.
 template <int N>
 __device__ inline void wave_claim_by_keys(u32* bins, const u32* off, const bool (&act)[N],
                                           const u32 (&key)[N], u32 (&pos)[N]) {
-    u32 lead[N], rank[N], cnt[N], old[N];
+    u32 lead[N], rank[N], cnt[N], old[N], o[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) o[k] = off[act[k] ? key[k] : 0u];   // in flight with the reservations
 #pragma unroll
     for (int k = 0; k < N; ++k) wave_group_by_key(act[k], key[k], lead[k], rank[k], cnt[k]);
 #pragma unroll
@@ -96,7 +99,7 @@ __device__ inline void wave_claim_by_keys(u32* bins, const u32* off, const bool 
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const u32 base = (u32)__shfl((int)old[k], (int)lead[k]);
-        pos[k] = act[k] ? off[key[k]] + base - 1u - rank[k] : 0u;
+        pos[k] = act[k] ? o[k] + base - 1u - rank[k] : 0u;
     }
 }
 
@@ -700,8 +703,10 @@ __global__ __launch_bounds__(256) void k_gbin_count(const Partial* __restrict__ 
         u32 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
         if (a0) { const Partial& P = parts[tp.record(r0)]; h0 = P.h; l0 = P.lj; }
         if (a1) { const Partial& P = parts[tp.record(r1)]; h1 = P.h; l1 = P.lj; }
-        const u32 k0 = a0 ? group_bin(tval[h0], l0, JM) : 0u;
-        const u32 k1 = a1 ? group_bin(tval[h1], l1, JM) : 0u;
+        // both dense indices loaded together (an inactive lane reads entry 0 and ignores it)
+        const u32 t0 = tval[h0], t1 = tval[h1];
+        const u32 k0 = a0 ? group_bin(t0, l0, JM) : 0u;
+        const u32 k1 = a1 ? group_bin(t1, l1, JM) : 0u;
         wave_count_by_key(bins, a0, k0);
         wave_count_by_key(bins, a1, k1);
     }
@@ -727,8 +732,9 @@ __global__ __launch_bounds__(256) void k_gscatter(const Partial* __restrict__ pa
         Partial P0, P1;
         if (a[0]) P0 = parts[tp.record(r0)];
         if (a[1]) P1 = parts[tp.record(r1)];
-        const u32 k[2] = {a[0] ? group_bin(tval[P0.h], P0.lj, JM) : 0u,
-                          a[1] ? group_bin(tval[P1.h], P1.lj, JM) : 0u};
+        // both dense indices loaded together (an inactive lane reads entry 0 and ignores it)
+        const u32 t0 = tval[a[0] ? P0.h : 0u], t1 = tval[a[1] ? P1.h : 0u];
+        const u32 k[2] = {a[0] ? group_bin(t0, P0.lj, JM) : 0u, a[1] ? group_bin(t1, P1.lj, JM) : 0u};
         u32 pos[2];
         wave_claim_by_keys<2>(bins, off, a, k, pos);
         if (a[0]) sorted[pos[0]] = P0;
