@@ -1279,7 +1279,7 @@ def summarize_profiles(args):
                 "# kernel sources with this sha (bench.py kernel_source_sha)\n"
                 f"workload = {args.summary_workload}\nupdate_tuning = {args.summary_update_tuning}\n"
                 f"source_sha = {kernel_source_sha()}\nhbm_bytes_per_launch = {call_bytes}\n")
-        with open(os.path.join(ROOT, "profiles", "traffic_call.txt"), "w") as fh:
+        with open(os.path.join(args.summary_traffic_dir, "traffic_call.txt"), "w") as fh:
             fh.write(text)
     # per-stage HBM bytes that the benchmark reads back as roofline.traffic
     for spec in args.summary_traffic or []:
@@ -1300,7 +1300,7 @@ def summarize_profiles(args):
                 + " and the kernel sources with this sha (bench.py kernel_source_sha)\n"
                 f"workload = {args.summary_workload}\n{tun}source_sha = {kernel_source_sha()}\n"
                 f"hbm_bytes_per_launch = {hbm}\n")
-        with open(os.path.join(ROOT, "profiles", f"traffic_{stage}.txt"), "w") as fh:
+        with open(os.path.join(args.summary_traffic_dir, f"traffic_{stage}.txt"), "w") as fh:
             fh.write(text)
 
 
@@ -1340,6 +1340,8 @@ def main():
     ap.add_argument("--summary-out", default="profile_summary.md")
     ap.add_argument("--summary-traffic", nargs="*",
                     help="stage:kernel-substring pairs whose HBM bytes go to profiles/traffic_<stage>.txt")
+    ap.add_argument("--summary-traffic-dir", default=os.path.join(ROOT, "profiles"),
+                    help="where the traffic_*.txt files go (the benchmark reads them from profiles/)")
     ap.add_argument("--summary-call-kernel", default=None,
                     help="a kernel that runs once per call: the whole call's HBM bytes go to "
                          "profiles/traffic_call.txt")
